@@ -1,0 +1,97 @@
+"""Pins of the oracle's Perona-Malik lagged-diffusivity prior."""
+import numpy as np
+
+from qpat_inputs import kuhn_mesh, make_problem
+from oracle import fem, prior
+from oracle.solve import Direct, pcg
+
+T = 5e-3
+
+
+def geo(n=4):
+    m = kuhn_mesh(n, 40.0)
+    return m, fem.geometry(m.coords, m.tets, m.bfaces)
+
+
+def test_diffusivity_is_derivative_ratio():
+    """c(t) = r'(t)/t with r(t) = (T^2/2) log(1 + (t/T)^2): check r' by central differences."""
+    def r(t):
+        return 0.5 * T * T * np.log1p((t / T) ** 2)
+    t = np.array([1e-4, 3e-3, 5e-3, 0.02, 0.7])
+    d = 1e-7 * t
+    fd = (r(t + d) - r(t - d)) / (2 * d)
+    assert np.allclose(prior.r_prime(t, T), fd, rtol=1e-7)
+    assert np.allclose(prior.diffusivity(t, T), fd / t, rtol=1e-7)
+    assert prior.diffusivity(np.array([0.0]), T)[0] == 1.0
+
+
+def test_M_kernel_and_semidefinite():
+    P = make_problem("T8")
+    g = fem.geometry(P.mesh.coords, P.mesh.tets, P.mesh.bfaces)
+    u = np.log(P.kappa / P.kappa0)
+    M = prior.M_of(g, u, T)
+    one = np.ones(g.N)
+    assert np.abs(M @ one).max() < 1e-13 * np.abs(M).max()
+    assert abs(M - M.T).max() <= 1e-15 * abs(M).max()
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        v = rng.standard_normal(g.N)
+        assert v @ (M @ v) >= 0.0
+    ev = np.linalg.eigvalsh(M.toarray())
+    assert ev[0] > -1e-12 * ev[-1] and ev[1] > 1e-10 * ev[-1]      # Ker M = span{1}
+
+
+def test_constant_u_gives_laplacian():
+    m, g = geo(3)
+    M = prior.M_of(g, np.full(m.N, 0.37), T)
+    S = fem.stiffness(g, np.ones(m.N))
+    assert np.allclose(M.toarray(), S.toarray(), rtol=1e-13, atol=1e-15)
+
+
+def test_linear_u_scales_laplacian():
+    """u = g.x has |grad u| = |g| everywhere, so M = S(1) / (1 + |g|^2 / T^2)."""
+    m, g = geo(3)
+    gvec = np.array([2e-3, -4e-3, 1e-3])
+    M = prior.M_of(g, m.coords @ gvec, T)
+    S = fem.stiffness(g, np.ones(m.N))
+    want = S / (1 + (gvec @ gvec) / T ** 2)
+    assert np.allclose(M.toarray(), want.toarray(), rtol=1e-12, atol=1e-15)
+
+
+def test_M_delta_structure():
+    P = make_problem("T4")
+    g = fem.geometry(P.mesh.coords, P.mesh.tets, P.mesh.bfaces)
+    kt = np.log(P.kappa / P.kappa0)
+    mt = np.log(P.mu / P.mu0)
+    N = g.N
+    Md = prior.M_delta(g, kt, mt, T, b_over_a=2.5, delta=1e-6).toarray()
+    Mk = prior.M_of(g, kt, T).toarray()
+    Mm = prior.M_of(g, mt, T).toarray()
+    assert np.allclose(Md[:N, :N], Mk + 1e-6 * np.eye(N), rtol=1e-14, atol=1e-20)
+    assert np.allclose(Md[N:, N:], 2.5 * Mm + 1e-6 * np.eye(N), rtol=1e-14, atol=1e-20)
+    assert np.all(Md[:N, N:] == 0) and np.all(Md[N:, :N] == 0)
+    # the constant vectors are eigenvectors with eigenvalue delta
+    e = np.concatenate([np.ones(N), np.zeros(N)])
+    assert np.allclose(Md @ e, 1e-6 * e, atol=1e-15)
+
+
+def test_M_delta_solve_direct_vs_pcg():
+    P = make_problem("T8")
+    g = fem.geometry(P.mesh.coords, P.mesh.tets, P.mesh.bfaces)
+    kt = np.log(P.kappa / P.kappa0)
+    mt = np.log(P.mu / P.mu0)
+    Md = prior.M_delta(g, kt, mt)
+    rng = np.random.default_rng(1)
+    p = rng.standard_normal(2 * g.N)
+    xd = Direct(Md)(p)
+    info = {}
+    xc = pcg(Md, p, rtol=1e-10, info=info)
+    assert info["relres"] <= 1e-10
+    assert np.linalg.norm(Md @ xd - p) <= 1e-9 * np.linalg.norm(p)   # eps ||M|| ||x||
+    # ||dx|| / ||x|| <= cond(M_delta) rtol in the worst case; cond ~ ||M|| / delta
+    # is ~1e8 here, but the error along the delta-eigenvector 1 is tiny because
+    # its component is fixed by the mean: 1.(M_delta x) = delta 1.x per block
+    assert np.linalg.norm(xc - xd) <= 1e-8 * np.linalg.norm(xd)
+    N = g.N
+    assert abs(1e-6 * xd[:N].sum() - p[:N].sum()) <= 1e-9 * np.abs(p[:N]).sum()
+    assert abs(1e-6 * xd[N:].sum() - p[N:].sum()) <= 1e-9 * np.abs(p[N:]).sum()
