@@ -1,0 +1,184 @@
+/*
+ * qpat.h -- C ABI of libqpat, the MI355X (gfx950) implementation of the
+ * matrix-free Jacobian / priorconditioned-LSQR path of
+ *
+ *   A. Hannukainen, N. Hyvonen, H. Majander, T. Tarvainen, "Efficient
+ *   inclusion of total variation type priors in quantitative photoacoustic
+ *   tomography" (SIAM J. Imaging Sci. 2016; arXiv:1512.02796).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array arguments are caller-owned, contiguous DEVICE pointers (for
+ *   example a torch tensor's data_ptr() on the GPU the context was created
+ *   on). The library never frees them and keeps none of them after the call
+ *   returns, except `beta_out` of qpat_lsqr_init (see there).
+ * - Floating-point arrays are IEEE double (FP64) unless stated otherwise;
+ *   index arrays are int32, zero-based.
+ * - "[n][m]" means row-major with m fastest.
+ * - All device work is enqueued on the HIP stream given to qpat_setup_mesh.
+ *   Calls that return host-visible numbers (qpat_info, resnorm_out, status of
+ *   iterative solves) synchronise that stream before returning.
+ * - Errors never throw across the ABI. Every entry point returns a
+ *   qpat_status; qpat_last_error() returns the message of the last failure.
+ * - A context is not thread-safe; calls on one context must be serialised.
+ *
+ * Units: lengths in mm, kappa in mm, mu in 1/mm (Sec. 5).
+ */
+#ifndef QPAT_H
+#define QPAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qpat_ctx qpat_ctx;
+
+typedef enum {
+    QPAT_OK = 0,
+    QPAT_ERR_ARG = 1,        /* null pointer, bad size, non-finite or non-positive input   */
+    QPAT_ERR_MESH = 2,       /* index out of range, degenerate tetrahedron, row too long    */
+    QPAT_ERR_NOCONV = 3,     /* a PCG solve hit pcg_maxit; outputs hold the last iterate   */
+    QPAT_ERR_BREAKDOWN = 4,  /* LSQR: p.r <= 0 or non-finite inside a step                  */
+    QPAT_ERR_DEVICE = 5,     /* a HIP runtime call failed                                   */
+    QPAT_ERR_OOM = 6,        /* device allocation failed                                    */
+    QPAT_ERR_STATE = 7       /* call order violated (e.g. qpat_jvp before qpat_forward)     */
+} qpat_status;
+
+typedef struct {
+    int32_t precision;      /* 0: FP64 throughout. 1: mixed -- FP32 operator, FP32 Jacobi and
+                               FP32 PCG vectors, FP64 dot products, FP64 true-residual
+                               recomputation (reliable updates) and FP64 iterate.            */
+    int32_t max_rhs_block;  /* right-hand sides per block PCG (1, 2, 4, 8 or 16). 1 solves the
+                               illuminations one after another ("plain").                    */
+    double  pcg_rtol;       /* K solves stop when ||b - K x||_2 <= pcg_rtol ||b||_2 (true
+                               residual, FP64).                                                */
+    int32_t pcg_maxit;      /* iteration cap per solve -> QPAT_ERR_NOCONV.                    */
+    double  prior_rtol;     /* same rule for M_delta solves.                                  */
+    int32_t prior_deflate;  /* 1: the constant vector of each block (the delta-eigenvector of
+                               M_delta) is solved exactly and PCG runs on its complement.    */
+    int32_t lsqr_reorth;    /* 1: full reorthogonalisation of both bidiagonalisation bases.
+                               0: plain Paige-Saunders recurrences.                           */
+    int32_t lsqr_max_steps; /* capacity of the stored bases when lsqr_reorth = 1.             */
+    double  ru_delta;       /* mixed precision: recompute the FP64 residual whenever the
+                               recursive one fell by this factor since the last recompute.   */
+} qpat_opts;
+
+typedef struct {
+    int32_t n_solves;       /* linear systems solved by the call                               */
+    int32_t iters_max;      /* largest PCG iteration count among them                          */
+    int64_t iters_sum;      /* total PCG iterations                                            */
+    int32_t updates;        /* FP64 true-residual recomputations                              */
+    double  relres_max;     /* largest final true relative residual                           */
+} qpat_info;
+
+/* Fill *opts with the defaults: FP64, block 16, rtol 1e-10, maxit 20000,
+ * prior_rtol 1e-10, deflation on, reorthogonalisation on with 64 steps,
+ * ru_delta 1e-3. */
+void qpat_default_opts(qpat_opts* opts);
+
+/* Create a context for a tetrahedral P1 mesh (Sec. 3: piecewise linear
+ * basis on a tetrahedral partition; Sec. 5 / Appendix: the FEM system).
+ *   N, coords  : nodes, [N][3] FP64 (device).
+ *   E, tets    : tetrahedra, [E][4] int32 (device). Either orientation.
+ *   F_b, bfaces: boundary triangles, [F_b][3] int32 (device); they carry the
+ *                Robin term and the sources.
+ *   opts       : NULL for the defaults.
+ *   hip_stream : hipStream_t used for all work of this context (NULL = default).
+ * Builds on the device: tetrahedron volumes and barycentric gradients,
+ * node->element adjacency, the sparsity pattern of K (sorted rows, sliced-ELL
+ * layout of 64-row slices) and boundary-triangle areas.
+ * Errors: QPAT_ERR_ARG (N < 4, E < 1, null), QPAT_ERR_MESH (index out of
+ * range, zero-volume tetrahedron, a row with more than 64 entries). */
+qpat_status qpat_setup_mesh(qpat_ctx** ctx, int64_t N, const double* coords,
+                            int64_t E, const int32_t* tets,
+                            int64_t F_b, const int32_t* bfaces,
+                            const qpat_opts* opts, void* hip_stream);
+
+qpat_status qpat_set_opts(qpat_ctx* ctx, const qpat_opts* opts);
+qpat_status qpat_get_opts(const qpat_ctx* ctx, qpat_opts* opts);
+
+/* Boundary photon fluxes Phi^(k), k < n_ill (Sec. 2 eq. (2.1); several
+ * illuminations: Sec. 4, paragraph after Algorithm 1). phi_src is
+ * [n_ill][F_b][3] FP64 (device): Phi at the three vertices of each boundary
+ * triangle, linear in between. Computes the load vectors
+ * f_k = 2 int Phi_k v dS (Appendix, weak form). 1 <= n_ill <= 64. */
+qpat_status qpat_set_sources(qpat_ctx* ctx, int32_t n_ill, const double* phi_src);
+
+/* Linearisation point and forward map (Sec. 2 eqs. (2.1)-(2.2); Appendix).
+ * kappa, mu: nodal [N] (device), > 0. Assembles K(kappa, mu) = S(kappa) +
+ * Mass(mu) + B/2 with kappa, mu entering as P1 interpolants, solves
+ * K phi_k = f_k for every illumination and keeps phi inside the context.
+ * phi_out, h_out: [n_ill][N] (device) or NULL; h = mu * phi (nodal product).
+ * info: host struct or NULL. */
+qpat_status qpat_forward(qpat_ctx* ctx, const double* kappa, const double* mu,
+                         double* phi_out, double* h_out, qpat_info* info);
+
+/* Same as qpat_forward at kappa = kappa0 exp(kt), mu = mu0 exp(mt), with
+ * beta = [kt; mt] of length 2N (device) (Sec. 3 eq. (3.1)). */
+qpat_status qpat_forward_log(qpat_ctx* ctx, double kappa0, double mu0, const double* beta,
+                             double* phi_out, double* h_out, qpat_info* info);
+
+/* J s at the last forward point, J the Jacobian of beta -> h w.r.t. the
+ * log-parameters (Appendix, formula for J s):
+ *   J s = diag(mu) K^{-1} (G1 diag(kappa) s1 + G2 diag(mu) s2) + diag(phi) diag(mu) s2,
+ * with G1, G2 applied element by element, never formed.
+ * s: [2N] = [s_kt; s_mt] (device). out: [n_ill][N] (device). */
+qpat_status qpat_jvp(qpat_ctx* ctx, const double* s, double* out, qpat_info* info);
+
+/* J^T t (Appendix, formula for the transpose): t [n_ill][N] (device),
+ * out [2N] (device). */
+qpat_status qpat_vjp(qpat_ctx* ctx, const double* t, double* out, qpat_info* info);
+
+/* Lagged-diffusivity Perona-Malik prior (Sec. 3 eq. (3.7); Sec. 4 eqs. (4.3),
+ * (4.5), (4.8)): c_T = 1 / (1 + |grad u_T|^2 / T^2) per tetrahedron,
+ * M(u) = FEM matrix of -div(c_u grad), M_delta = blockdiag(M(kt),
+ * b_over_a M(mt)) + delta I. kt, mt: [N] (device). T, delta > 0. */
+qpat_status qpat_prior_setup(qpat_ctx* ctx, const double* kt, const double* mt,
+                             double T, double b_over_a, double delta);
+
+/* y = M_delta x; x, y: [2N] (device). */
+qpat_status qpat_prior_apply(qpat_ctx* ctx, const double* x, double* y);
+
+/* r = M_delta^{-1} p by PCG (prior_rtol); p, r: [2N] (device). */
+qpat_status qpat_prior_solve(qpat_ctx* ctx, const double* p, double* r, qpat_info* info);
+
+/* Whitened nonlinear misfit ||W (chi - h)||_2 at the last forward point
+ * (Algorithm 1, step 4). chi, w: [n_ill][N] (device), w = Gamma^{-1/2} as a
+ * diagonal. The result is written to *out (host). */
+qpat_status qpat_misfit(qpat_ctx* ctx, const double* chi, const double* w, double* out);
+
+/* Initial guess of Algorithm 1 (preamble; several illuminations: Sec. 4 and
+ * Sec. 5): call after qpat_forward at the homogeneous (kappa0, mu0).
+ * beta_out[0:N] = 0, beta_out[N:2N] = log(mean_k(chi_k / phi_k) / mu0), the
+ * ratio clamped below at 1e-12 mu0. chi: [n_ill][N]; beta_out: [2N] (device). */
+qpat_status qpat_init_guess(qpat_ctx* ctx, const double* chi, double mu0, double* beta_out);
+
+/* Start priorconditioned LSQR (Sec. 4 eq. (4.10); Algorithm 1 steps 1 and 3)
+ * at the last forward point with the last prior:
+ *   A = W J, yt = W (chi - h + J beta_lin), iterate x = 0.
+ * chi, w: [n_ill][N]; beta_lin: [2N] or NULL (then yt = W (chi - h)).
+ * beta_out: [2N] device buffer that receives the iterate x (= beta, already
+ * mapped back by L^{-1}); it stays registered and is updated in place by each
+ * qpat_lsqr_step until the next qpat_lsqr_init or qpat_destroy. */
+qpat_status qpat_lsqr_init(qpat_ctx* ctx, const double* chi, const double* w,
+                           const double* beta_lin, double* beta_out, qpat_info* info);
+
+/* One LSQR step: one J v, one J^T u, one M_delta^{-1}, scalar recurrences in
+ * FP64 on the device. *resnorm_out (host) = |phibar| = ||A x - yt|| in exact
+ * arithmetic. A lucky breakdown (beta or alpha = 0) returns QPAT_OK and
+ * freezes the iterate. */
+qpat_status qpat_lsqr_step(qpat_ctx* ctx, double* resnorm_out, qpat_info* info);
+
+/* Steps taken since qpat_lsqr_init. */
+int32_t qpat_lsqr_steps(const qpat_ctx* ctx);
+
+const char* qpat_last_error(const qpat_ctx* ctx);
+const char* qpat_version(void);
+void qpat_destroy(qpat_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QPAT_H */

@@ -1,0 +1,410 @@
+// C ABI of libqpat: argument checks, context state, allocation, and the
+// layout changes between the caller's [n_ill][N] arrays and the interleaved
+// [N][n_pad] arrays used inside the library.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <algorithm>
+
+#include "qpat_internal.h"
+
+namespace qpat {
+
+qpat_status fail(qpat_ctx* c, qpat_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return st;
+}
+
+qpat_status hip_check(qpat_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return QPAT_OK;
+    return fail(c, e == hipErrorOutOfMemory ? QPAT_ERR_OOM : QPAT_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+qpat_status dfree(qpat_ctx* c, void* p) {
+    if (!p) return QPAT_OK;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    QPAT_HIP(c, hipFree(p));
+    return QPAT_OK;
+}
+
+namespace {
+
+__global__ void k_from_interleaved(int64_t N, int n_ill, int n_pad, const double* __restrict__ src,
+                                   const double* __restrict__ mu, double* __restrict__ dst) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * n_ill) return;
+    const int64_t k = t / N, row = t % N;
+    double v = src[row * n_pad + k];
+    if (mu) v *= mu[row];
+    dst[t] = v;
+}
+
+__global__ void k_copy_d(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+bool pow2_block(int b) { return b == 1 || b == 2 || b == 4 || b == 8 || b == 16; }
+
+qpat_status check_opts(qpat_ctx* c, const qpat_opts* o) {
+    if (o->precision != 0 && o->precision != 1) return fail(c, QPAT_ERR_ARG, "precision must be 0 or 1");
+    if (!pow2_block(o->max_rhs_block)) return fail(c, QPAT_ERR_ARG, "max_rhs_block must be 1, 2, 4, 8 or 16");
+    if (!(o->pcg_rtol > 0.0) || !(o->prior_rtol > 0.0)) return fail(c, QPAT_ERR_ARG, "tolerances must be > 0");
+    if (o->pcg_maxit < 1) return fail(c, QPAT_ERR_ARG, "pcg_maxit must be >= 1");
+    if (o->lsqr_max_steps < 1) return fail(c, QPAT_ERR_ARG, "lsqr_max_steps must be >= 1");
+    if (!(o->ru_delta > 0.0 && o->ru_delta < 1.0)) return fail(c, QPAT_ERR_ARG, "ru_delta must be in (0, 1)");
+    return QPAT_OK;
+}
+
+void fill_info(qpat_info* info, const SolveStats& s) {
+    if (!info) return;
+    info->n_solves = s.n_solves;
+    info->iters_max = s.iters_max;
+    info->iters_sum = s.iters_sum;
+    info->updates = s.updates;
+    info->relres_max = s.relres_max;
+}
+
+qpat_status finish(qpat_ctx* c, const SolveStats& s, qpat_info* info) {
+    fill_info(info, s);
+    if (s.noconv)
+        return fail(c, QPAT_ERR_NOCONV, "PCG did not reach the tolerance within pcg_maxit (relres %.3e)",
+                    s.relres_max);
+    return QPAT_OK;
+}
+
+qpat_status alloc_core(qpat_ctx* c) {
+    const int64_t N = c->N, L = c->sell.len;
+    QPAT_TRY(dalloc(c, &c->kappa, N));
+    QPAT_TRY(dalloc(c, &c->mu, N));
+    QPAT_TRY(dalloc(c, &c->K64, L));
+    QPAT_TRY(dalloc(c, &c->K32, L));
+    QPAT_TRY(dalloc(c, &c->Kdinv64, N));
+    QPAT_TRY(dalloc(c, &c->Kdinv32, N));
+    QPAT_TRY(dalloc(c, &c->M64, 2 * L));
+    QPAT_TRY(dalloc(c, &c->M32, 2 * L));
+    QPAT_TRY(dalloc(c, &c->Mdinv64, 2 * N));
+    QPAT_TRY(dalloc(c, &c->Mdinv32, 2 * N));
+    const int64_t V = N * kMaxRhs;  // >= 2N
+    QPAT_TRY(dalloc(c, &c->x64, V));
+    QPAT_TRY(dalloc(c, &c->b64, V));
+    double* t = nullptr;
+    QPAT_TRY(dalloc(c, &t, V)); c->xl = t;
+    QPAT_TRY(dalloc(c, &t, V)); c->rl = t;
+    QPAT_TRY(dalloc(c, &t, V)); c->pa = t;
+    QPAT_TRY(dalloc(c, &t, V)); c->pb = t;
+    QPAT_TRY(dalloc(c, &t, V)); c->ql = t;
+    QPAT_TRY(dalloc(c, &c->scal, kMaxSys));
+    QPAT_TRY(dalloc(c, &c->shared, 1));
+    QPAT_HIP(c, hipMemsetAsync(c->shared, 0, sizeof(PcgShared), c->stream));
+    QPAT_TRY(dalloc(c, &c->partials, (size_t)5 * kMaxSys * 1024));
+    QPAT_TRY(dalloc(c, &c->acc1, N));
+    QPAT_TRY(dalloc(c, &c->acc2, N));
+    QPAT_TRY(dalloc(c, &c->red_partials, 1024));
+    QPAT_TRY(dalloc(c, &c->red_out, 64));
+    QPAT_TRY(dalloc(c, &c->red_counter, 16));
+    QPAT_HIP(c, hipMemsetAsync(c->red_counter, 0, 16 * sizeof(uint32_t), c->stream));
+    QPAT_TRY(dalloc(c, &c->ls, 1));
+    QPAT_HIP(c, hipMemsetAsync(c->ls, 0, sizeof(LsqrScal), c->stream));
+    QPAT_TRY(dalloc(c, &c->lv, 2 * N));
+    QPAT_TRY(dalloc(c, &c->lwh, 2 * N));
+    QPAT_TRY(dalloc(c, &c->lwd, 2 * N));
+    QPAT_TRY(dalloc(c, &c->lp, 2 * N));
+    QPAT_TRY(dalloc(c, &c->lr, 2 * N));
+    QPAT_HIP(c, hipHostMalloc((void**)&c->scal_host, sizeof(PcgScal) * kMaxSys, hipHostMallocDefault));
+    QPAT_HIP(c, hipHostMalloc((void**)&c->ls_host, sizeof(LsqrScal), hipHostMallocDefault));
+    QPAT_HIP(c, hipHostMalloc((void**)&c->red_host, sizeof(double) * 64, hipHostMallocDefault));
+    std::memset(c->ls_host, 0, sizeof(LsqrScal));
+    return QPAT_OK;
+}
+
+qpat_status alloc_bases(qpat_ctx* c) {
+    const int cap = c->opts.lsqr_max_steps + 1;
+    if (c->basis_cap == cap && c->U) return QPAT_OK;
+    QPAT_TRY(dfree(c, c->U));
+    QPAT_TRY(dfree(c, c->V));
+    QPAT_TRY(dfree(c, c->WH));
+    QPAT_TRY(dfree(c, c->coef));
+    c->U = c->V = c->WH = c->coef = nullptr;
+    c->basis_cap = 0;
+    QPAT_TRY(dalloc(c, &c->U, (size_t)cap * c->N * c->n_pad));
+    QPAT_TRY(dalloc(c, &c->V, (size_t)cap * 2 * c->N));
+    QPAT_TRY(dalloc(c, &c->WH, (size_t)cap * 2 * c->N));
+    QPAT_TRY(dalloc(c, &c->coef, cap));
+    c->basis_cap = cap;
+    return QPAT_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+}  // namespace qpat
+
+using namespace qpat;
+
+extern "C" {
+
+void qpat_default_opts(qpat_opts* o) {
+    if (!o) return;
+    o->precision = 0;
+    o->max_rhs_block = 16;
+    o->pcg_rtol = 1e-10;
+    o->pcg_maxit = 20000;
+    o->prior_rtol = 1e-10;
+    o->prior_deflate = 1;
+    o->lsqr_reorth = 1;
+    o->lsqr_max_steps = 64;
+    o->ru_delta = 1e-3;
+}
+
+const char* qpat_version(void) { return "qpat 0.1 (gfx950)"; }
+
+qpat_status qpat_setup_mesh(qpat_ctx** out, int64_t N, const double* coords, int64_t E, const int32_t* tets,
+                            int64_t F_b, const int32_t* bfaces, const qpat_opts* opts, void* hip_stream) {
+    if (!out) return QPAT_ERR_ARG;
+    *out = nullptr;
+    qpat_ctx* c = new (std::nothrow) qpat_ctx();
+    if (!c) return QPAT_ERR_OOM;
+    *out = c;
+    if (!coords || !tets || N < 4 || E < 1 || F_b < 0 || (F_b > 0 && !bfaces))
+        return fail(c, QPAT_ERR_ARG, "setup_mesh: bad sizes or null pointers");
+    qpat_default_opts(&c->opts);
+    if (opts) {
+        QPAT_TRY(check_opts(c, opts));
+        c->opts = *opts;
+    }
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    QPAT_HIP(c, hipGetDevice(&c->device));
+    c->N = N;
+    c->E = E;
+    c->Fb = F_b;
+    QPAT_TRY(mesh_build(c, coords, tets, bfaces));
+    QPAT_TRY(alloc_core(c));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return QPAT_OK;
+}
+
+qpat_status qpat_set_opts(qpat_ctx* c, const qpat_opts* o) {
+    if (!c || !o) return QPAT_ERR_ARG;
+    QPAT_TRY(check_opts(c, o));
+    c->opts = *o;
+    return QPAT_OK;
+}
+
+qpat_status qpat_get_opts(const qpat_ctx* c, qpat_opts* o) {
+    if (!c || !o) return QPAT_ERR_ARG;
+    *o = c->opts;
+    return QPAT_OK;
+}
+
+qpat_status qpat_set_sources(qpat_ctx* c, int32_t n_ill, const double* phi_src) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (n_ill < 1 || n_ill > 64 || (!phi_src && c->Fb > 0))
+        return fail(c, QPAT_ERR_ARG, "set_sources: need 1 <= n_ill <= 64 and a source array");
+    int n_pad = 1;
+    while (n_pad < n_ill && n_pad < kMaxRhs) n_pad <<= 1;
+    if (n_ill > kMaxRhs) n_pad = ((n_ill + kMaxRhs - 1) / kMaxRhs) * kMaxRhs;
+    if (n_pad != c->n_pad) {
+        for (double** p : {&c->f, &c->phi, &c->dvec, &c->lu, &c->lq, &c->lw}) {
+            QPAT_TRY(dfree(c, *p));
+            *p = nullptr;
+        }
+        QPAT_TRY(dfree(c, c->U));
+        QPAT_TRY(dfree(c, c->V));
+        QPAT_TRY(dfree(c, c->WH));
+        QPAT_TRY(dfree(c, c->coef));
+        c->U = c->V = c->WH = c->coef = nullptr;
+        c->basis_cap = 0;
+        const int64_t nd = c->N * n_pad;
+        for (double** p : {&c->f, &c->phi, &c->dvec, &c->lu, &c->lq, &c->lw}) QPAT_TRY(dalloc(c, p, nd));
+    }
+    c->n_ill = n_ill;
+    c->n_pad = n_pad;
+    c->have_forward = false;
+    c->lsqr_ready = false;
+    QPAT_TRY(assemble_load(c, phi_src));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return QPAT_OK;
+}
+
+static qpat_status forward_common(qpat_ctx* c, double* phi_out, double* h_out, qpat_info* info) {
+    QPAT_TRY(assemble_K(c));
+    SolveStats st;
+    c->have_forward = false;
+    c->lsqr_ready = false;
+    QPAT_TRY(forward_solve(c, &st));
+    const int64_t n = c->N * c->n_ill;
+    const dim3 g(grid_for(n, kThreads, 1 << 30)), b(kThreads);
+    if (phi_out) hipLaunchKernelGGL(k_from_interleaved, g, b, 0, c->stream, c->N, c->n_ill, c->n_pad, c->phi, nullptr, phi_out);
+    if (h_out) hipLaunchKernelGGL(k_from_interleaved, g, b, 0, c->stream, c->N, c->n_ill, c->n_pad, c->phi, c->mu, h_out);
+    QPAT_HIP(c, hipGetLastError());
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    qpat_status s = finish(c, st, info);
+    if (s == QPAT_OK) c->have_forward = true;
+    return s;
+}
+
+qpat_status qpat_forward(qpat_ctx* c, const double* kappa, const double* mu, double* phi_out, double* h_out,
+                         qpat_info* info) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!kappa || !mu) return fail(c, QPAT_ERR_ARG, "forward: null kappa or mu");
+    if (c->n_ill == 0) return fail(c, QPAT_ERR_STATE, "forward: call qpat_set_sources first");
+    bool ok1 = false, ok2 = false;
+    QPAT_TRY(check_positive(c, kappa, c->N, &ok1));
+    QPAT_TRY(check_positive(c, mu, c->N, &ok2));
+    if (!ok1 || !ok2) return fail(c, QPAT_ERR_ARG, "forward: kappa and mu must be finite and > 0");
+    const dim3 gr(grid_for(c->N, kThreads, 1 << 30)), b(kThreads);
+    hipLaunchKernelGGL(k_copy_d, gr, b, 0, c->stream, c->N, kappa, c->kappa);
+    hipLaunchKernelGGL(k_copy_d, gr, b, 0, c->stream, c->N, mu, c->mu);
+    return forward_common(c, phi_out, h_out, info);
+}
+
+qpat_status qpat_forward_log(qpat_ctx* c, double kappa0, double mu0, const double* beta, double* phi_out,
+                             double* h_out, qpat_info* info) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!beta || !(kappa0 > 0.0) || !(mu0 > 0.0)) return fail(c, QPAT_ERR_ARG, "forward_log: bad arguments");
+    if (c->n_ill == 0) return fail(c, QPAT_ERR_STATE, "forward_log: call qpat_set_sources first");
+    QPAT_TRY(exp_params(c, kappa0, mu0, beta));
+    bool ok1 = false, ok2 = false;
+    QPAT_TRY(check_positive(c, c->kappa, c->N, &ok1));
+    QPAT_TRY(check_positive(c, c->mu, c->N, &ok2));
+    if (!ok1 || !ok2) return fail(c, QPAT_ERR_ARG, "forward_log: exp(beta) not finite and positive");
+    return forward_common(c, phi_out, h_out, info);
+}
+
+qpat_status qpat_jvp(qpat_ctx* c, const double* s, double* out, qpat_info* info) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!s || !out) return fail(c, QPAT_ERR_ARG, "jvp: null pointer");
+    if (!c->have_forward) return fail(c, QPAT_ERR_STATE, "jvp: call qpat_forward first");
+    SolveStats st;
+    QPAT_TRY(jvp_core(c, s, 0, out, &st));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return finish(c, st, info);
+}
+
+qpat_status qpat_vjp(qpat_ctx* c, const double* t, double* out, qpat_info* info) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!t || !out) return fail(c, QPAT_ERR_ARG, "vjp: null pointer");
+    if (!c->have_forward) return fail(c, QPAT_ERR_STATE, "vjp: call qpat_forward first");
+    SolveStats st;
+    QPAT_TRY(vjp_core(c, t, 0, out, &st));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return finish(c, st, info);
+}
+
+qpat_status qpat_prior_setup(qpat_ctx* c, const double* kt, const double* mt, double T, double b_over_a,
+                             double delta) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!kt || !mt || !(T > 0.0) || !(b_over_a > 0.0) || !(delta > 0.0))
+        return fail(c, QPAT_ERR_ARG, "prior_setup: need kt, mt and T, b_over_a, delta > 0");
+    QPAT_TRY(assemble_prior(c, kt, mt, T, b_over_a, delta));
+    c->delta = delta;
+    c->have_prior = true;
+    c->lsqr_ready = false;
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return QPAT_OK;
+}
+
+qpat_status qpat_prior_apply(qpat_ctx* c, const double* x, double* y) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!x || !y) return fail(c, QPAT_ERR_ARG, "prior_apply: null pointer");
+    if (!c->have_prior) return fail(c, QPAT_ERR_STATE, "prior_apply: call qpat_prior_setup first");
+    QPAT_TRY(prior_apply_core(c, x, y));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return QPAT_OK;
+}
+
+qpat_status qpat_prior_solve(qpat_ctx* c, const double* p, double* r, qpat_info* info) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!p || !r) return fail(c, QPAT_ERR_ARG, "prior_solve: null pointer");
+    if (!c->have_prior) return fail(c, QPAT_ERR_STATE, "prior_solve: call qpat_prior_setup first");
+    SolveStats st;
+    QPAT_TRY(prior_solve_core(c, p, r, &st));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return finish(c, st, info);
+}
+
+qpat_status qpat_misfit(qpat_ctx* c, const double* chi, const double* w, double* out) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!chi || !w || !out) return fail(c, QPAT_ERR_ARG, "misfit: null pointer");
+    if (!c->have_forward) return fail(c, QPAT_ERR_STATE, "misfit: call qpat_forward first");
+    return misfit_core(c, chi, w, out);
+}
+
+qpat_status qpat_init_guess(qpat_ctx* c, const double* chi, double mu0, double* beta_out) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!chi || !beta_out || !(mu0 > 0.0)) return fail(c, QPAT_ERR_ARG, "init_guess: bad arguments");
+    if (!c->have_forward) return fail(c, QPAT_ERR_STATE, "init_guess: call qpat_forward first");
+    QPAT_TRY(init_guess_core(c, chi, mu0, beta_out));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return QPAT_OK;
+}
+
+qpat_status qpat_lsqr_init(qpat_ctx* c, const double* chi, const double* w, const double* beta_lin,
+                           double* beta_out, qpat_info* info) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!chi || !w || !beta_out) return fail(c, QPAT_ERR_ARG, "lsqr_init: null pointer");
+    if (!c->have_forward || !c->have_prior)
+        return fail(c, QPAT_ERR_STATE, "lsqr_init: needs qpat_forward and qpat_prior_setup");
+    c->lsqr_ready = false;
+    if (c->opts.lsqr_reorth) QPAT_TRY(alloc_bases(c));
+    c->lx = beta_out;
+    QPAT_TRY(lsqr_init_core(c, chi, w, beta_lin));
+    c->lsqr_ready = true;
+    fill_info(info, SolveStats());
+    return QPAT_OK;
+}
+
+qpat_status qpat_lsqr_step(qpat_ctx* c, double* resnorm_out, qpat_info* info) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!c->lsqr_ready) return fail(c, QPAT_ERR_STATE, "lsqr_step: call qpat_lsqr_init first");
+    SolveStats st;
+    QPAT_TRY(lsqr_step_core(c, &st));
+    if (resnorm_out) *resnorm_out = std::fabs(c->ls_host->phibar);
+    return finish(c, st, info);
+}
+
+int32_t qpat_lsqr_steps(const qpat_ctx* c) { return c && c->ls_host ? c->ls_host->steps : 0; }
+
+const char* qpat_last_error(const qpat_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void qpat_destroy(qpat_ctx* c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->scal_host) (void)hipHostFree(c->scal_host);
+    if (c->ls_host) (void)hipHostFree(c->ls_host);
+    if (c->red_host) (void)hipHostFree(c->red_host);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+// Forward solve and the matrix-free Jacobian products J s, J^T t.
+//
+// Appendix: K J^phi = [G(1), G(2)] with G(1)_ij = -int phi_j grad(phi).grad(phi_i),
+// G(2)_ij = -int phi_j phi phi_i, and
+//   J s   = diag(mu) K^{-1} (G(1) diag(kappa) s1 + G(2) diag(mu) s2) + diag(phi) diag(mu) s2
+//   J^T t = [diag(kappa) G(1)^T K^{-1} diag(mu) t ; diag(mu) (G(2) K^{-1} diag(mu) t + diag(phi) t)].
+// G is never formed. K is linear in the nodal coefficients, so for P1 fields
+//   G(1) u1 + G(2) u2 = -(S(u1) + Mass(u2)) phi            (same element loop as K)
+//   (G(1)^T z)_j      = -sum_{T at j} |T|/4 grad(phi_T).grad(z_T)
+//   G(2) z            = -Mass(phi) z
+// with S(u)_ab = mean_T(u) |T| grad(l_a).grad(l_b) and
+// Mass(u)_ab = |T| (1 + d_ab) (sum_T u + u_a + u_b) / 120.
+// Data-space vectors inside the library are interleaved [N][n_pad]; the
+// illuminations are solved in blocks of B right-hand sides.
+#include "qpat_internal.h"
+
+namespace qpat {
+namespace {
+
+struct Geo4 {
+    double vol;
+    double g[4][3];
+};
+
+__device__ __forceinline__ void load_geo4(const double* __restrict__ geo, int32_t e, Geo4& G) {
+    const double* p = geo + (int64_t)kTetGeo * e;
+    G.vol = p[0];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        G.g[1][d] = p[1 + d];
+        G.g[2][d] = p[4 + d];
+        G.g[3][d] = p[7 + d];
+        G.g[0][d] = -(G.g[1][d] + G.g[2][d] + G.g[3][d]);
+    }
+}
+
+// b[row][k] = -(S(u1) + Mass(u2)) phi_{col0+k}, u1 = kappa s1, u2 = mu s2
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_gfwd(int64_t N, const int32_t* __restrict__ tets,
+                                                  const double* __restrict__ geo, const int32_t* __restrict__ n2t_ptr,
+                                                  const int32_t* __restrict__ n2t, const double* __restrict__ kappa,
+                                                  const double* __restrict__ mu, const double* __restrict__ s,
+                                                  const double* __restrict__ phi, int n_pad, int col0,
+                                                  double* __restrict__ b) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * B) return;
+    const int64_t row = t / B;
+    const int k = static_cast<int>(t % B);
+    const int kk = col0 + k;
+    double acc = 0.0;
+    for (int32_t q = n2t_ptr[row]; q < n2t_ptr[row + 1]; ++q) {
+        const int32_t e = n2t[q] >> 2, a = n2t[q] & 3;
+        Geo4 G;
+        load_geo4(geo, e, G);
+        double u1 = 0.0, u2[4], ph[4], s2 = 0.0;
+        double gp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int32_t v = tets[4 * e + c];
+            u1 += kappa[v] * s[v];
+            u2[c] = mu[v] * s[N + v];
+            s2 += u2[c];
+            ph[c] = phi[(int64_t)v * n_pad + kk];
+            gp[0] += ph[c] * G.g[c][0];
+            gp[1] += ph[c] * G.g[c][1];
+            gp[2] += ph[c] * G.g[c][2];
+        }
+        u1 *= 0.25;
+        const double stiff = u1 * G.vol * (G.g[a][0] * gp[0] + G.g[a][1] * gp[1] + G.g[a][2] * gp[2]);
+        double mass = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) mass += (c == a ? 2.0 : 1.0) * (s2 + u2[a] + u2[c]) * ph[c];
+        acc -= stiff + G.vol * (1.0 / 120.0) * mass;
+    }
+    b[t] = acc;
+}
+
+// a1[row] (+)= -sum_k sum_T |T|/4 grad(phi_k).grad(z_k)
+// a2[row] (+)= sum_k [ -(Mass(phi_k) z_k)_row + phi_k,row t_k,row ]
+// tmode 0: t external [n_ill][N]; tmode 1: t = W u interleaved [N][n_pad]
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_gadj(int64_t N, const int32_t* __restrict__ tets,
+                                                  const double* __restrict__ geo, const int32_t* __restrict__ n2t_ptr,
+                                                  const int32_t* __restrict__ n2t, const double* __restrict__ phi,
+                                                  int n_pad, int n_ill, int col0, const double* __restrict__ z,
+                                                  int tmode, const double* __restrict__ t_ext,
+                                                  const double* __restrict__ W, const double* __restrict__ U,
+                                                  int first, double* __restrict__ a1, double* __restrict__ a2) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool valid = t < N * B;
+    const int64_t row = valid ? t / B : 0;
+    const int k = static_cast<int>(t % B);
+    const int kk = col0 + k;
+    double acc1 = 0.0, acc2 = 0.0;
+    if (valid) {
+        for (int32_t q = n2t_ptr[row]; q < n2t_ptr[row + 1]; ++q) {
+            const int32_t e = n2t[q] >> 2, a = n2t[q] & 3;
+            Geo4 G;
+            load_geo4(geo, e, G);
+            double ph[4], zz[4], sp = 0.0;
+            double gp[3] = {0.0, 0.0, 0.0}, gz[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int32_t v = tets[4 * e + c];
+                ph[c] = phi[(int64_t)v * n_pad + kk];
+                zz[c] = z[(int64_t)v * B + k];
+                sp += ph[c];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    gp[d] += ph[c] * G.g[c][d];
+                    gz[d] += zz[c] * G.g[c][d];
+                }
+            }
+            acc1 -= 0.25 * G.vol * (gp[0] * gz[0] + gp[1] * gz[1] + gp[2] * gz[2]);
+            double mass = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) mass += (c == a ? 2.0 : 1.0) * (sp + ph[a] + ph[c]) * zz[c];
+            acc2 -= G.vol * (1.0 / 120.0) * mass;
+        }
+        double tv = 0.0;
+        if (kk < n_ill) {
+            if (tmode == 0) tv = t_ext[(int64_t)kk * N + row];
+            else tv = W[row * n_pad + kk] * U[row * n_pad + kk];
+        }
+        acc2 += phi[row * n_pad + kk] * tv;
+    }
+#pragma unroll
+    for (int off = B >> 1; off >= 1; off >>= 1) {
+        acc1 += __shfl_xor(acc1, off);
+        acc2 += __shfl_xor(acc2, off);
+    }
+    if (valid && k == 0) {
+        if (first) {
+            a1[row] = acc1;
+            a2[row] = acc2;
+        } else {
+            a1[row] += acc1;
+            a2[row] += acc2;
+        }
+    }
+}
+
+// solver block <- columns col0..col0+B-1 of an interleaved data array
+template <int B>
+__global__ void k_pack(int64_t N, const double* __restrict__ src, int n_pad, int col0, double* __restrict__ dst) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * B) return;
+    dst[t] = src[(t / B) * n_pad + col0 + (t % B)];
+}
+
+template <int B>
+__global__ void k_unpack(int64_t N, const double* __restrict__ src, int n_pad, int col0, double* __restrict__ dst) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * B) return;
+    dst[(t / B) * n_pad + col0 + (t % B)] = src[t];
+}
+
+// adjoint right-hand side b = mu t (tmode 0: external t; 1: t = W u interleaved)
+template <int B>
+__global__ void k_adj_rhs(int64_t N, const double* __restrict__ mu, int n_pad, int n_ill, int col0, int tmode,
+                          const double* __restrict__ t_ext, const double* __restrict__ W,
+                          const double* __restrict__ U, double* __restrict__ b) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * B) return;
+    const int64_t row = t / B;
+    const int kk = col0 + static_cast<int>(t % B);
+    double tv = 0.0;
+    if (kk < n_ill) {
+        if (tmode == 0) tv = t_ext[(int64_t)kk * N + row];
+        else tv = W[row * n_pad + kk] * U[row * n_pad + kk];
+    }
+    b[t] = mu[row] * tv;
+}
+
+// J s output: y = mu w + phi mu s2.
+// mode 0: out [n_ill][N]; mode 1: q = W y - alpha u (interleaved); mode 2: out interleaved y
+template <int B>
+__global__ void k_jvp_out(int64_t N, const double* __restrict__ mu, const double* __restrict__ phi,
+                          const double* __restrict__ s, const double* __restrict__ w, int n_pad, int n_ill, int col0,
+                          int mode, double* __restrict__ out, const double* __restrict__ W,
+                          const double* __restrict__ U, const LsqrScal* __restrict__ ls) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * B) return;
+    const int64_t row = t / B;
+    const int kk = col0 + static_cast<int>(t % B);
+    const int64_t di = row * n_pad + kk;
+    const double y = mu[row] * (w[t] + phi[di] * s[N + row]);
+    if (mode == 0) {
+        if (kk < n_ill) out[(int64_t)kk * N + row] = y;
+    } else if (mode == 1) {
+        out[di] = (kk < n_ill ? W[di] * y : 0.0) - ls->alpha * U[di];
+    } else {
+        out[di] = kk < n_ill ? y : 0.0;
+    }
+}
+
+// J^T t output: out = [kappa a1 ; mu a2] (- beta what when sub)
+__global__ void k_vjp_out(int64_t N, const double* __restrict__ kappa, const double* __restrict__ mu,
+                          const double* __restrict__ a1, const double* __restrict__ a2, double* __restrict__ out,
+                          int sub, const double* __restrict__ wh, const LsqrScal* __restrict__ ls) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double o1 = kappa[i] * a1[i], o2 = mu[i] * a2[i];
+    if (sub) {
+        const double b = ls->beta;
+        o1 -= b * wh[i];
+        o2 -= b * wh[N + i];
+    }
+    out[i] = o1;
+    out[N + i] = o2;
+}
+
+int block_size(const qpat_ctx* c) {
+    int B = c->opts.max_rhs_block;
+    return B < c->n_pad ? B : c->n_pad;
+}
+
+#define QPAT_DISPATCH_B(B, CALL)                                  \
+    switch (B) {                                                  \
+        case 1: { constexpr int BB = 1; CALL; } break;            \
+        case 2: { constexpr int BB = 2; CALL; } break;            \
+        case 4: { constexpr int BB = 4; CALL; } break;            \
+        case 8: { constexpr int BB = 8; CALL; } break;            \
+        case 16: { constexpr int BB = 16; CALL; } break;          \
+        default: return fail(c, QPAT_ERR_ARG, "bad block size"); \
+    }
+
+}  // namespace
+
+qpat_status forward_solve(qpat_ctx* c, SolveStats* st) {
+    const int B = block_size(c);
+    const dim3 g(grid_for(c->N * B, kThreads, 1 << 30)), blk(kThreads);
+    for (int col0 = 0; col0 < c->n_pad; col0 += B) {
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_pack<BB>, g, blk, 0, c->stream, c->N, c->f, c->n_pad, col0, c->b64));
+        QPAT_TRY(pcg_solve(c, Op::K, B, st));
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_unpack<BB>, g, blk, 0, c->stream, c->N, c->x64, c->n_pad, col0, c->phi));
+    }
+    QPAT_HIP(c, hipGetLastError());
+    return QPAT_OK;
+}
+
+qpat_status jvp_core(qpat_ctx* c, const double* s, int mode, double* out, SolveStats* st) {
+    const int B = block_size(c);
+    const dim3 g(grid_for(c->N * B, kThreads, 1 << 30)), blk(kThreads);
+    for (int col0 = 0; col0 < c->n_pad; col0 += B) {
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gfwd<BB>, g, blk, 0, c->stream, c->N, c->tets, c->geo, c->n2t_ptr,
+                                              c->n2t, c->kappa, c->mu, s, c->phi, c->n_pad, col0, c->b64));
+        QPAT_TRY(pcg_solve(c, Op::K, B, st));
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_jvp_out<BB>, g, blk, 0, c->stream, c->N, c->mu, c->phi, s, c->x64,
+                                              c->n_pad, c->n_ill, col0, mode, out, c->lw, c->lu, c->ls));
+    }
+    QPAT_HIP(c, hipGetLastError());
+    return QPAT_OK;
+}
+
+// mode 0: t external [n_ill][N], out = J^T t
+// mode 1: t = W u (c->lw, c->lu), out = J^T t
+// mode 2: as 1, out = J^T t - beta what
+qpat_status vjp_core(qpat_ctx* c, const double* t, int mode, double* out, SolveStats* st) {
+    const int B = block_size(c);
+    const dim3 g(grid_for(c->N * B, kThreads, 1 << 30)), blk(kThreads);
+    const int tmode = mode == 0 ? 0 : 1;
+    for (int col0 = 0; col0 < c->n_pad; col0 += B) {
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_adj_rhs<BB>, g, blk, 0, c->stream, c->N, c->mu, c->n_pad, c->n_ill,
+                                              col0, tmode, t, c->lw, c->lu, c->b64));
+        QPAT_TRY(pcg_solve(c, Op::K, B, st));
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gadj<BB>, g, blk, 0, c->stream, c->N, c->tets, c->geo, c->n2t_ptr,
+                                              c->n2t, c->phi, c->n_pad, c->n_ill, col0, c->x64, tmode, t, c->lw,
+                                              c->lu, col0 == 0 ? 1 : 0, c->acc1, c->acc2));
+    }
+    hipLaunchKernelGGL(k_vjp_out, dim3(grid_for(c->N, kThreads, 1 << 30)), blk, 0, c->stream, c->N, c->kappa, c->mu,
+                       c->acc1, c->acc2, out, mode == 2 ? 1 : 0, c->lwh, c->ls);
+    QPAT_HIP(c, hipGetLastError());
+    return QPAT_OK;
+}
+
+}  // namespace qpat

@@ -1,0 +1,688 @@
+// Block Jacobi-PCG on the sliced-ELL operator, B independent right-hand sides
+// interleaved [N][B] per system, nsys systems sharing one pattern.
+//
+// Every K^{-1} (Appendix: "operate with the inverse of the FEM system
+// matrix") and every M_delta^{-1} (Sec. 4, one per LSQR round) of the path
+// goes through this engine. Stopping rule: ||b - A x||_2 <= rtol ||b||_2 on
+// the FP64 true residual.
+//
+// One iteration is two kernels:
+//   dir_spmv : p <- D^{-1} r - c + beta p (recomputed on the fly for every
+//              gathered neighbour, p ping-pongs between two buffers),
+//              q = A p, partial p.q; the last block to finish reduces the
+//              partials in fixed order and sets alpha = r.z / p.q.
+//   update   : x += alpha p, r -= alpha q, partial r.D^{-1}r and r.r (and
+//              the deflation sums); the last block sets beta and flags.
+// All scalars stay on the device; the host reads them once per chunk of
+// iterations to schedule FP64 true-residual recomputations (reliable updates
+// in mixed precision, confirmation of convergence in both modes).
+// Deflation (prior only): M_delta has the exact eigenpair (delta, 1) per
+// block; the mean of the solution is mean(b)/delta and PCG runs on the
+// complement of the constants with the projected preconditioner
+// z = D^{-1} r - mean(D^{-1} r).
+#include <cmath>
+
+#include "qpat_internal.h"
+
+namespace qpat {
+namespace {
+
+template <typename T>
+struct PcgArgs {
+    Sell s;
+    int64_t N;
+    int32_t nsys;
+    int32_t gs;          // blocks per system (multiple of 8)
+    int32_t rpb;         // rows per block (multiple of 64)
+    const T* vals;       // [nsys][len]
+    const T* dinv;       // [nsys][N]
+    const double* vals64;
+    const double* dinv64;
+    T* r;                // [nsys][N][B]
+    T* pa;
+    T* pb;
+    T* q;
+    T* x;                // low-precision iterate (FP64 mode: x64 itself)
+    double* x64;
+    double* b64;
+    PcgScal* sc;
+    PcgShared* sh;
+    double* partials;
+    double rtol2;
+    int32_t maxit;
+    uint32_t mask;       // lanes of a true-residual recomputation
+    double inv_delta;
+};
+
+__device__ __forceinline__ double ld_acq(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// XCD-aware block -> row-range map: consecutive hardware blocks go to
+// different XCDs, so give each XCD a contiguous band of rows.
+__device__ __forceinline__ void block_rows(int32_t gs, int32_t rpb, int64_t N, int32_t& sys, int64_t& r0,
+                                           int64_t& r1) {
+    int32_t bx = blockIdx.x;
+    sys = bx / gs;
+    int32_t local = bx % gs;
+    int32_t lb = (local & 7) * (gs >> 3) + (local >> 3);
+    r0 = (int64_t)lb * rpb;
+    r1 = r0 + rpb;
+    if (r1 > N) r1 = N;
+}
+
+// sum over threads with equal (tid % B); result valid in threads tid < B
+template <int B>
+__device__ __forceinline__ double block_sum(double v, double* sm) {
+#pragma unroll
+    for (int off = 32; off >= B; off >>= 1) v += __shfl_xor(v, off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < B) sm[wave * B + lane] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < B) t = sm[threadIdx.x] + sm[B + threadIdx.x] + sm[2 * B + threadIdx.x] + sm[3 * B + threadIdx.x];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ bool arrive_last(PcgShared* sh, uint32_t nblocks) {
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t prev = atomicAdd(&sh->counter, 1u);
+        last = prev == nblocks - 1;
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+// out[v] = sum_b partials[v * gs + b], deterministic order; out in shared memory
+__device__ void reduce_partials(const double* partials, int nv, int gs, double* out) {
+    int tpv = 64;
+    while (tpv * nv > kThreads && tpv > 1) tpv >>= 1;
+    const int vpp = kThreads / tpv;
+    for (int v0 = 0; v0 < nv; v0 += vpp) {
+        const int v = v0 + threadIdx.x / tpv;
+        const int sub = threadIdx.x % tpv;
+        double s = 0.0;
+        if (v < nv)
+            for (int b = sub; b < gs; b += tpv) s += ld_acq(partials + (int64_t)v * gs + b);
+        for (int off = tpv >> 1; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+        if (sub == 0 && v < nv) out[v] = s;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void write_partial(double* partials, int v, int gs, double val) {
+    const int32_t local = blockIdx.x % gs;
+    partials[(int64_t)v * gs + local] = val;
+}
+
+__device__ void count_active(PcgScal* sc, PcgShared* sh, int S) {
+    if (threadIdx.x == 0) {
+        int n = 0;
+        for (int i = 0; i < S; ++i) n += sc[i].active;
+        sh->n_active = n;
+    }
+}
+
+// ---------------------------------------------------------------- iteration
+template <typename T, int B, bool DEFL>
+__global__ __launch_bounds__(kThreads) void k_dir_spmv(PcgArgs<T> a) {
+    __shared__ double sm[4 * kMaxRhs];
+    __shared__ double tot[kMaxSys];
+    if (a.sh->n_active == 0) return;
+    int32_t sys;
+    int64_t r0, r1;
+    block_rows(a.gs, a.rpb, a.N, sys, r0, r1);
+    const int k = threadIdx.x % B;
+    const int sidx = sys * B + k;
+    const int par = a.sh->parity;
+    const T* __restrict__ pold = par ? a.pb : a.pa;
+    T* __restrict__ pnew = par ? a.pa : a.pb;
+    const PcgScal scl = a.sc[sidx];
+    const bool act = scl.active != 0;
+    const T beta = static_cast<T>(scl.beta);
+    const T cc = DEFL ? static_cast<T>(scl.c) : T(0);
+    const T* __restrict__ vals = a.vals + (int64_t)sys * a.s.len;
+    const T* __restrict__ dinv = a.dinv + (int64_t)sys * a.N;
+    const T* __restrict__ r = a.r + (int64_t)sys * a.N * B;
+    const T* __restrict__ po = pold + (int64_t)sys * a.N * B;
+    T* __restrict__ pn = pnew + (int64_t)sys * a.N * B;
+    T* __restrict__ q = a.q + (int64_t)sys * a.N * B;
+    const int32_t* __restrict__ cols = a.s.cols;
+    double acc = 0.0;
+    for (int64_t row = r0 + threadIdx.x / B; row < r1; row += kThreads / B) {
+        const int64_t idx = row * B + k;
+        if (act) {
+            const T pi = dinv[row] * r[idx] - cc + beta * po[idx];
+            const int32_t base = a.s.slice_ptr[row / kSlice] + static_cast<int32_t>(row % kSlice);
+            const int32_t n = a.s.rowlen[row];
+            T sum = T(0);
+            for (int32_t j = 0; j < n; ++j) {
+                const int32_t col = cols[base + j * kSlice];
+                const T av = vals[base + j * kSlice];
+                const int64_t jdx = (int64_t)col * B + k;
+                const T pj = dinv[col] * r[jdx] - cc + beta * po[jdx];
+                sum += av * pj;
+            }
+            pn[idx] = pi;
+            q[idx] = sum;
+            acc += static_cast<double>(pi) * static_cast<double>(sum);
+        } else {
+            pn[idx] = po[idx];
+        }
+    }
+    double bs = block_sum<B>(acc, sm);
+    if (threadIdx.x < B) write_partial(a.partials, sys * B + threadIdx.x, a.gs, bs);
+    const int S = a.nsys * B;
+    if (!arrive_last(a.sh, gridDim.x)) return;
+    reduce_partials(a.partials, S, a.gs, tot);
+    if (threadIdx.x < S) {
+        PcgScal& c = a.sc[threadIdx.x];
+        if (c.active) {
+            c.pq = tot[threadIdx.x];
+            c.alpha = c.pq != 0.0 ? c.rz / c.pq : 0.0;
+        } else {
+            c.alpha = 0.0;
+        }
+    }
+    if (threadIdx.x == 0) {
+        a.sh->parity = par ^ 1;
+        a.sh->counter = 0u;
+    }
+}
+
+template <typename T, int B, bool DEFL>
+__global__ __launch_bounds__(kThreads) void k_update(PcgArgs<T> a) {
+    __shared__ double sm[4 * kMaxRhs];
+    __shared__ double tot[4 * kMaxSys];
+    if (a.sh->n_active == 0) return;
+    int32_t sys;
+    int64_t r0, r1;
+    block_rows(a.gs, a.rpb, a.N, sys, r0, r1);
+    const int k = threadIdx.x % B;
+    const int sidx = sys * B + k;
+    const int par = a.sh->parity;
+    const T* __restrict__ p = (par ? a.pb : a.pa) + (int64_t)sys * a.N * B;
+    const PcgScal scl = a.sc[sidx];
+    const bool act = scl.active != 0;
+    const T alpha = static_cast<T>(scl.alpha);
+    const T* __restrict__ dinv = a.dinv + (int64_t)sys * a.N;
+    T* __restrict__ r = a.r + (int64_t)sys * a.N * B;
+    T* __restrict__ x = a.x + (int64_t)sys * a.N * B;
+    const T* __restrict__ q = a.q + (int64_t)sys * a.N * B;
+    double rz = 0.0, rr = 0.0, z1 = 0.0, r1s = 0.0;
+    if (act) {
+        for (int64_t row = r0 + threadIdx.x / B; row < r1; row += kThreads / B) {
+            const int64_t idx = row * B + k;
+            const T xi = x[idx] + alpha * p[idx];
+            const T ri = r[idx] - alpha * q[idx];
+            x[idx] = xi;
+            r[idx] = ri;
+            const T zi = dinv[row] * ri;
+            rz += static_cast<double>(ri) * static_cast<double>(zi);
+            rr += static_cast<double>(ri) * static_cast<double>(ri);
+            if (DEFL) {
+                z1 += static_cast<double>(zi);
+                r1s += static_cast<double>(ri);
+            }
+        }
+    }
+    constexpr int Q = DEFL ? 4 : 2;
+    const int S = a.nsys * B;
+    double v0 = block_sum<B>(rz, sm);
+    double v1 = block_sum<B>(rr, sm);
+    double v2 = 0.0, v3 = 0.0;
+    if (DEFL) {
+        v2 = block_sum<B>(z1, sm);
+        v3 = block_sum<B>(r1s, sm);
+    }
+    if (threadIdx.x < B) {
+        const int v = sys * B + threadIdx.x;
+        write_partial(a.partials, v, a.gs, v0);
+        write_partial(a.partials, S + v, a.gs, v1);
+        if (DEFL) {
+            write_partial(a.partials, 2 * S + v, a.gs, v2);
+            write_partial(a.partials, 3 * S + v, a.gs, v3);
+        }
+    }
+    if (!arrive_last(a.sh, gridDim.x)) return;
+    reduce_partials(a.partials, Q * S, a.gs, tot);
+    if (threadIdx.x < S) {
+        PcgScal& c = a.sc[threadIdx.x];
+        if (c.active) {
+            double rzn = tot[threadIdx.x];
+            const double rrn = tot[S + threadIdx.x];
+            double cn = 0.0;
+            if (DEFL) {
+                cn = tot[2 * S + threadIdx.x] / static_cast<double>(a.N);
+                rzn -= cn * tot[3 * S + threadIdx.x];
+            }
+            c.beta = c.rz != 0.0 ? rzn / c.rz : 0.0;
+            c.rz_prev = c.rz;
+            c.rz = rzn;
+            c.c = cn;
+            c.rr = rrn;
+            c.iters += 1;
+            if (rrn <= a.rtol2 * c.bnorm2 || !(rrn == rrn)) {
+                c.active = 0;
+                c.pending = 1;
+            } else if (c.iters >= a.maxit) {
+                c.active = 0;
+            }
+        }
+    }
+    __syncthreads();
+    count_active(a.sc, a.sh, S);
+    if (threadIdx.x == 0) a.sh->counter = 0u;
+}
+
+// ------------------------------------------------------- true residual (FP64)
+// mixed precision: fold the low-precision iterate into x64 first
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void k_fold(PcgArgs<T> a) {
+    int32_t sys;
+    int64_t r0, r1;
+    block_rows(a.gs, a.rpb, a.N, sys, r0, r1);
+    const int k = threadIdx.x % B;
+    if (!((a.mask >> (sys * B + k)) & 1u)) return;
+    T* __restrict__ x = a.x + (int64_t)sys * a.N * B;
+    double* __restrict__ x64 = a.x64 + (int64_t)sys * a.N * B;
+    for (int64_t row = r0 + threadIdx.x / B; row < r1; row += kThreads / B) {
+        const int64_t idx = row * B + k;
+        x64[idx] += static_cast<double>(x[idx]);
+        x[idx] = T(0);
+    }
+}
+
+// r = b - A64 x64 for the masked lanes; replaces the recursive residual and
+// decides convergence on it. With init = true (all lanes, x64 = 0 assumed when
+// has_x0 is false) it also sets up the run.
+template <typename T, int B, bool DEFL>
+__global__ __launch_bounds__(kThreads) void k_true_residual(PcgArgs<T> a, int init, int has_x0) {
+    __shared__ double sm[4 * kMaxRhs];
+    __shared__ double tot[5 * kMaxSys];
+    int32_t sys;
+    int64_t r0, r1;
+    block_rows(a.gs, a.rpb, a.N, sys, r0, r1);
+    const int k = threadIdx.x % B;
+    const int sidx = sys * B + k;
+    const bool on = (a.mask >> sidx) & 1u;
+    const double* __restrict__ vals = a.vals64 + (int64_t)sys * a.s.len;
+    const T* __restrict__ dinv = a.dinv + (int64_t)sys * a.N;
+    const double* __restrict__ b = a.b64 + (int64_t)sys * a.N * B;
+    const double* __restrict__ x64 = a.x64 + (int64_t)sys * a.N * B;
+    T* __restrict__ r = a.r + (int64_t)sys * a.N * B;
+    T* __restrict__ pa = a.pa + (int64_t)sys * a.N * B;
+    T* __restrict__ xl = a.x + (int64_t)sys * a.N * B;
+    const int32_t* __restrict__ cols = a.s.cols;
+    double rr = 0.0, rz = 0.0, z1 = 0.0, r1s = 0.0, bb = 0.0;
+    if (on) {
+        for (int64_t row = r0 + threadIdx.x / B; row < r1; row += kThreads / B) {
+            const int64_t idx = row * B + k;
+            double res = b[idx];
+            if (init) bb += res * res;
+            if (!init || has_x0) {
+                const int32_t base = a.s.slice_ptr[row / kSlice] + static_cast<int32_t>(row % kSlice);
+                const int32_t n = a.s.rowlen[row];
+                double sum = 0.0;
+                for (int32_t j = 0; j < n; ++j) {
+                    const int32_t col = cols[base + j * kSlice];
+                    sum += vals[base + j * kSlice] * x64[(int64_t)col * B + k];
+                }
+                res -= sum;
+            }
+            const T rl = static_cast<T>(res);
+            r[idx] = rl;
+            if (init) {
+                pa[idx] = T(0);
+                if ((void*)xl != (void*)x64) xl[idx] = T(0);
+            }
+            const T zi = dinv[row] * rl;
+            rr += res * res;
+            rz += static_cast<double>(rl) * static_cast<double>(zi);
+            if (DEFL) {
+                z1 += static_cast<double>(zi);
+                r1s += static_cast<double>(rl);
+            }
+        }
+    }
+    const int S = a.nsys * B;
+    double v0 = block_sum<B>(rr, sm);
+    double v1 = block_sum<B>(rz, sm);
+    double v2 = block_sum<B>(z1, sm);
+    double v3 = block_sum<B>(r1s, sm);
+    double v4 = block_sum<B>(bb, sm);
+    if (threadIdx.x < B) {
+        const int v = sys * B + threadIdx.x;
+        write_partial(a.partials, v, a.gs, v0);
+        write_partial(a.partials, S + v, a.gs, v1);
+        write_partial(a.partials, 2 * S + v, a.gs, v2);
+        write_partial(a.partials, 3 * S + v, a.gs, v3);
+        write_partial(a.partials, 4 * S + v, a.gs, v4);
+    }
+    if (!arrive_last(a.sh, gridDim.x)) return;
+    reduce_partials(a.partials, 5 * S, a.gs, tot);
+    if (threadIdx.x < S && ((a.mask >> threadIdx.x) & 1u)) {
+        PcgScal& c = a.sc[threadIdx.x];
+        const double rrt = tot[threadIdx.x];
+        double rzn = tot[S + threadIdx.x];
+        double cn = 0.0;
+        if (DEFL) {
+            cn = tot[2 * S + threadIdx.x] / static_cast<double>(a.N);
+            rzn -= cn * tot[3 * S + threadIdx.x];
+        }
+        if (init) {
+            // bnorm2 of the deflated run is set by the mean kernel (norm of the
+            // unprojected right-hand side)
+            if (!DEFL) c.bnorm2 = tot[4 * S + threadIdx.x];
+            c.iters = 0;
+            c.updates = 0;
+            c.beta = 0.0;
+            c.rz_prev = rzn;
+            c.rz = rzn;
+        } else {
+            c.beta = c.rz_prev != 0.0 ? rzn / c.rz_prev : 0.0;
+            c.rz = rzn;
+            c.updates += 1;
+        }
+        c.c = cn;
+        c.rr = rrt;
+        c.truerr = rrt;
+        c.rlast2 = rrt;
+        c.pending = 0;
+        if (rrt <= a.rtol2 * c.bnorm2) {
+            c.done = 1;
+            c.active = 0;
+        } else if (c.iters >= a.maxit) {
+            c.done = 0;
+            c.active = 0;
+        } else {
+            c.done = 0;
+            c.active = 1;
+        }
+    }
+    __syncthreads();
+    count_active(a.sc, a.sh, S);
+    if (threadIdx.x == 0) {
+        if (init) a.sh->parity = 0;
+        a.sh->counter = 0u;
+    }
+}
+
+// deflation: mean of each block of b, b <- b - mean, sc.mean = mean / delta,
+// sc.bnorm2 = ||b||^2 before projection. B = 1, one block per system.
+__global__ __launch_bounds__(kThreads) void k_deflate_rhs(double* b64, int64_t N, PcgScal* sc, double inv_delta) {
+    __shared__ double sm[4];
+    const int sys = blockIdx.x;
+    double* b = b64 + (int64_t)sys * N;
+    double s = 0.0, s2 = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += kThreads) {
+        s += b[i];
+        s2 += b[i] * b[i];
+    }
+    s = block_sum<1>(s, sm);
+    s2 = block_sum<1>(s2, sm);
+    __shared__ double mean;
+    if (threadIdx.x == 0) {
+        mean = s / static_cast<double>(N);
+        sc[sys].mean = mean * inv_delta;
+        sc[sys].bnorm2 = s2;
+        sc[sys].done = 0;
+        sc[sys].active = 0;
+        sc[sys].pending = 0;
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < N; i += kThreads) b[i] -= mean;
+}
+
+// stop lanes whose true residual no longer improves (attainable accuracy reached)
+__global__ void k_deactivate(PcgScal* sc, int S, PcgShared* sh, uint32_t mask) {
+    if (threadIdx.x != 0) return;
+    int n = 0;
+    for (int i = 0; i < S; ++i) {
+        if ((mask >> i) & 1u) sc[i].active = 0;
+        n += sc[i].active;
+    }
+    sh->n_active = n;
+}
+
+__global__ void k_reset_scal(PcgScal* sc, int S, PcgShared* sh) {
+    int i = threadIdx.x;
+    if (i < S) {
+        sc[i].done = 0;
+        sc[i].active = 0;
+        sc[i].pending = 0;
+        sc[i].iters = 0;
+        sc[i].updates = 0;
+        sc[i].mean = 0.0;
+    }
+    if (i == 0) {
+        sh->counter = 0u;
+        sh->parity = 0;
+        sh->n_active = 0;
+    }
+}
+
+// y = A64 x + shift x for nsys systems, B right-hand sides
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_spmv64(const Sell s, int64_t N, const double* __restrict__ vals,
+                                                    const double* __restrict__ x, double* __restrict__ y,
+                                                    double shift) {
+    const int sys = blockIdx.y;
+    const int k = threadIdx.x % B;
+    const double* V = vals + (int64_t)sys * s.len;
+    const double* X = x + (int64_t)sys * N * B;
+    double* Y = y + (int64_t)sys * N * B;
+    for (int64_t row = blockIdx.x * (int64_t)(kThreads / B) + threadIdx.x / B; row < N;
+         row += (int64_t)gridDim.x * (kThreads / B)) {
+        const int32_t base = s.slice_ptr[row / kSlice] + static_cast<int32_t>(row % kSlice);
+        const int32_t n = s.rowlen[row];
+        double sum = 0.0;
+        for (int32_t j = 0; j < n; ++j) sum += V[base + j * kSlice] * X[(int64_t)s.cols[base + j * kSlice] * B + k];
+        Y[row * B + k] = sum + shift * X[row * B + k];
+    }
+}
+
+// ---------------------------------------------------------------- host side
+template <typename T, int B, bool DEFL>
+struct Runner {
+    static qpat_status run(qpat_ctx* c, Op op, PcgArgs<T>& a, double rtol, SolveStats* st) {
+        const int S = a.nsys * B;
+        const dim3 grid(a.gs * a.nsys), blk(kThreads);
+        hipStream_t sm = c->stream;
+        hipLaunchKernelGGL(k_reset_scal, dim3(1), dim3(64), 0, sm, a.sc, S, a.sh);
+        if (DEFL) hipLaunchKernelGGL(k_deflate_rhs, dim3(a.nsys), blk, 0, sm, a.b64, a.N, a.sc, a.inv_delta);
+        QPAT_HIP(c, hipMemsetAsync(a.x64, 0, sizeof(double) * a.N * B * a.nsys, sm));
+        a.mask = (S >= 32) ? 0xffffffffu : ((1u << S) - 1u);
+        hipLaunchKernelGGL((k_true_residual<T, B, DEFL>), grid, blk, 0, sm, a, 1, 0);
+        QPAT_HIP(c, hipGetLastError());
+        PcgScal* hs = c->scal_host;
+        auto fetch = [&]() -> qpat_status {
+            QPAT_HIP(c, hipMemcpyAsync(hs, a.sc, sizeof(PcgScal) * S, hipMemcpyDeviceToHost, sm));
+            QPAT_HIP(c, hipStreamSynchronize(sm));
+            return QPAT_OK;
+        };
+        QPAT_TRY(fetch());
+        const bool mixed = !std::is_same<T, double>::value;
+        const double ru2 = c->opts.ru_delta * c->opts.ru_delta;
+        int chunk = 16;
+        std::vector<double> best_true(S, INFINITY);
+        std::vector<int> stalls(S, 0);
+        std::vector<double> rr_prev(S);
+        for (int i = 0; i < S; ++i) rr_prev[i] = hs[i].rr;
+        for (;;) {
+            bool any_active = false;
+            for (int i = 0; i < S; ++i) any_active |= hs[i].active != 0;
+            if (!any_active) break;
+            for (int it = 0; it < chunk; ++it) {
+                hipLaunchKernelGGL((k_dir_spmv<T, B, DEFL>), grid, blk, 0, sm, a);
+                hipLaunchKernelGGL((k_update<T, B, DEFL>), grid, blk, 0, sm, a);
+            }
+            QPAT_HIP(c, hipGetLastError());
+            QPAT_TRY(fetch());
+            uint32_t mask = 0;
+            for (int i = 0; i < S; ++i) {
+                if (hs[i].pending) mask |= 1u << i;
+                else if (mixed && hs[i].active && hs[i].rr <= ru2 * hs[i].rlast2) mask |= 1u << i;
+            }
+            if (mask) {
+                const uint32_t confirm = mask & [&] {
+                    uint32_t m = 0;
+                    for (int i = 0; i < S; ++i)
+                        if (hs[i].pending) m |= 1u << i;
+                    return m;
+                }();
+                a.mask = mask;
+                if (mixed) hipLaunchKernelGGL((k_fold<T, B>), grid, blk, 0, sm, a);
+                hipLaunchKernelGGL((k_true_residual<T, B, DEFL>), grid, blk, 0, sm, a, 0, 0);
+                QPAT_HIP(c, hipGetLastError());
+                QPAT_TRY(fetch());
+                // a confirmation that failed without halving the best true residual
+                // counts as a stall; three stalls end the lane (QPAT_ERR_NOCONV)
+                uint32_t stop = 0;
+                for (int i = 0; i < S; ++i) {
+                    if (!((confirm >> i) & 1u) || hs[i].done) continue;
+                    if (hs[i].truerr < 0.25 * best_true[i]) {
+                        best_true[i] = hs[i].truerr;
+                        stalls[i] = 0;
+                    } else if (++stalls[i] >= 3) {
+                        stop |= 1u << i;
+                    }
+                }
+                if (stop) {
+                    hipLaunchKernelGGL(k_deactivate, dim3(1), dim3(64), 0, sm, a.sc, S, a.sh, stop);
+                    QPAT_TRY(fetch());
+                }
+            }
+            // next chunk: predicted iterations to the nearest target of the slowest lane
+            int need = 4;
+            for (int i = 0; i < S; ++i) {
+                if (!hs[i].active) continue;
+                double target = rtol * rtol * hs[i].bnorm2;
+                if (mixed) target = std::max(target, ru2 * hs[i].rlast2);
+                double rate = (rr_prev[i] > 0 && hs[i].rr > 0 && hs[i].rr < rr_prev[i])
+                                  ? std::log(hs[i].rr / rr_prev[i]) / chunk : 0.0;
+                int pred = rate < 0 ? static_cast<int>(std::log(target / hs[i].rr) / rate) + 1 : 64;
+                need = std::max(need, pred);
+            }
+            chunk = std::min(std::max(need, 4), 256);
+            for (int i = 0; i < S; ++i) rr_prev[i] = hs[i].rr;
+        }
+        if (mixed) {
+            // fold anything left (lanes stopped at maxit)
+            uint32_t mask = 0;
+            for (int i = 0; i < S; ++i)
+                if (!hs[i].done) mask |= 1u << i;
+            if (mask) {
+                a.mask = mask;
+                hipLaunchKernelGGL((k_fold<T, B>), grid, blk, 0, sm, a);
+            }
+        }
+        for (int i = 0; i < S; ++i) {
+            st->n_solves += 1;
+            st->iters_max = std::max(st->iters_max, hs[i].iters);
+            st->iters_sum += hs[i].iters;
+            st->updates += hs[i].updates;
+            double rel = hs[i].bnorm2 > 0 ? std::sqrt(hs[i].truerr / hs[i].bnorm2) : 0.0;
+            st->relres_max = std::max(st->relres_max, rel);
+            if (!hs[i].done) st->noconv = true;
+        }
+        return QPAT_OK;
+    }
+};
+
+template <typename T, bool DEFL>
+qpat_status dispatch_B(qpat_ctx* c, Op op, int B, PcgArgs<T>& a, double rtol, SolveStats* st) {
+    switch (B) {
+        case 1: return Runner<T, 1, DEFL>::run(c, op, a, rtol, st);
+        case 2: return Runner<T, 2, DEFL>::run(c, op, a, rtol, st);
+        case 4: return Runner<T, 4, DEFL>::run(c, op, a, rtol, st);
+        case 8: return Runner<T, 8, DEFL>::run(c, op, a, rtol, st);
+        case 16: return Runner<T, 16, DEFL>::run(c, op, a, rtol, st);
+        default: return fail(c, QPAT_ERR_ARG, "block size %d not supported", B);
+    }
+}
+
+template <typename T>
+PcgArgs<T> make_args(qpat_ctx* c, Op op, int B) {
+    PcgArgs<T> a{};
+    a.s = c->sell;
+    a.N = c->N;
+    a.nsys = op == Op::Prior ? 2 : 1;
+    // blocks per system: about 4 per CU over the device, multiple of 8
+    const int64_t rows_per_pass = kThreads / B;
+    int64_t want = (c->N + rows_per_pass - 1) / rows_per_pass;
+    int64_t cap = op == Op::Prior ? 512 : 1024;
+    int64_t gs = std::min(want, cap);
+    gs = ((gs + 7) / 8) * 8;
+    int64_t rpb = (c->N + gs - 1) / gs;
+    rpb = ((rpb + kSlice - 1) / kSlice) * kSlice;
+    a.gs = static_cast<int32_t>(gs);
+    a.rpb = static_cast<int32_t>(rpb);
+    const bool is64 = std::is_same<T, double>::value;
+    if (op == Op::K) {
+        a.vals = is64 ? reinterpret_cast<const T*>(c->K64) : reinterpret_cast<const T*>(c->K32);
+        a.dinv = is64 ? reinterpret_cast<const T*>(c->Kdinv64) : reinterpret_cast<const T*>(c->Kdinv32);
+        a.vals64 = c->K64;
+        a.dinv64 = c->Kdinv64;
+    } else {
+        a.vals = is64 ? reinterpret_cast<const T*>(c->M64) : reinterpret_cast<const T*>(c->M32);
+        a.dinv = is64 ? reinterpret_cast<const T*>(c->Mdinv64) : reinterpret_cast<const T*>(c->Mdinv32);
+        a.vals64 = c->M64;
+        a.dinv64 = c->Mdinv64;
+    }
+    a.r = static_cast<T*>(c->rl);
+    a.pa = static_cast<T*>(c->pa);
+    a.pb = static_cast<T*>(c->pb);
+    a.q = static_cast<T*>(c->ql);
+    a.x = is64 ? reinterpret_cast<T*>(c->x64) : static_cast<T*>(c->xl);
+    a.x64 = c->x64;
+    a.b64 = c->b64;
+    a.sc = c->scal;
+    a.sh = c->shared;
+    a.partials = c->partials;
+    a.inv_delta = c->delta > 0 ? 1.0 / c->delta : 0.0;
+    return a;
+}
+
+}  // namespace
+
+qpat_status pcg_solve(qpat_ctx* c, Op op, int B, SolveStats* st) {
+    const bool mixed = c->opts.precision == 1 && op == Op::K;
+    const bool defl = op == Op::Prior && c->opts.prior_deflate;
+    const double rtol = op == Op::K ? c->opts.pcg_rtol : c->opts.prior_rtol;
+    if (op == Op::Prior) B = 1;
+    if (mixed) {
+        PcgArgs<float> a = make_args<float>(c, op, B);
+        a.rtol2 = rtol * rtol;
+        a.maxit = c->opts.pcg_maxit;
+        return dispatch_B<float, false>(c, op, B, a, rtol, st);
+    }
+    PcgArgs<double> a = make_args<double>(c, op, B);
+    a.rtol2 = rtol * rtol;
+    a.maxit = c->opts.pcg_maxit;
+    if (defl) return Runner<double, 1, true>::run(c, op, a, rtol, st);
+    return dispatch_B<double, false>(c, op, B, a, rtol, st);
+}
+
+qpat_status spmv64(qpat_ctx* c, Op op, int B, const double* x, double* y, double shift) {
+    const int nsys = op == Op::Prior ? 2 : 1;
+    const double* vals = op == Op::K ? c->K64 : c->M64;
+    const dim3 grid(grid_for(c->N, kThreads / B, 4096), nsys), blk(kThreads);
+    switch (B) {
+        case 1: hipLaunchKernelGGL(k_spmv64<1>, grid, blk, 0, c->stream, c->sell, c->N, vals, x, y, shift); break;
+        case 2: hipLaunchKernelGGL(k_spmv64<2>, grid, blk, 0, c->stream, c->sell, c->N, vals, x, y, shift); break;
+        case 4: hipLaunchKernelGGL(k_spmv64<4>, grid, blk, 0, c->stream, c->sell, c->N, vals, x, y, shift); break;
+        case 8: hipLaunchKernelGGL(k_spmv64<8>, grid, blk, 0, c->stream, c->sell, c->N, vals, x, y, shift); break;
+        case 16: hipLaunchKernelGGL(k_spmv64<16>, grid, blk, 0, c->stream, c->sell, c->N, vals, x, y, shift); break;
+        default: return fail(c, QPAT_ERR_ARG, "block size %d not supported", B);
+    }
+    QPAT_HIP(c, hipGetLastError());
+    return QPAT_OK;
+}
+
+}  // namespace qpat

@@ -1,0 +1,255 @@
+// Internal definitions of libqpat (HIP, gfx950). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/qpat.h"
+
+namespace qpat {
+
+constexpr int kThreads = 256;        // threads per block of every streaming kernel
+constexpr int kSlice = 64;           // rows per sliced-ELL slice (one wavefront)
+constexpr int kMaxRow = 64;          // longest admissible matrix row
+constexpr int kMaxRhs = 16;          // right-hand sides per block solve
+constexpr int kMaxSys = 32;          // systems x right-hand sides tracked by one PCG run
+constexpr int kTetGeo = 12;          // doubles per tetrahedron: |T|, grad l1, grad l2, grad l3, pad
+
+struct Error {
+    qpat_status st;
+    std::string msg;
+};
+
+// Sliced ELL of the node-node pattern: slice s covers rows [64 s, 64 s + 64);
+// entry k of row i sits at slice_ptr[s] + k * 64 + (i % 64). Padding entries
+// have col = i and value 0. Columns are sorted within a row.
+struct Sell {
+    int64_t N = 0;
+    int32_t nslices = 0;
+    int64_t len = 0;             // total padded entries
+    int32_t max_width = 0;
+    int32_t* slice_ptr = nullptr;  // [nslices+1]
+    int32_t* slice_w = nullptr;    // [nslices]
+    int32_t* rowlen = nullptr;     // [N]
+    int32_t* cols = nullptr;       // [len]
+    int32_t* diag = nullptr;       // [N] position k of the diagonal in row i
+};
+
+// Per (system, right-hand side) scalars of one PCG run; FP64.
+struct PcgScal {
+    double rz;        // r . z (current)
+    double rz_prev;   // r . z before the last update
+    double pq;        // p . K p
+    double alpha;
+    double beta;
+    double c;         // deflation: mean of D^{-1} r
+    double rr;        // ||r||^2 (recursive)
+    double bnorm2;    // ||b||^2
+    double rlast2;    // ||r||^2 at the last true-residual recomputation
+    double truerr;    // ||b - K x||^2 at the last recomputation
+    double mean;      // deflation: mean(b) / delta
+    int32_t active;   // 1 while iterating
+    int32_t pending;  // 1: recursive residual converged, awaiting a true-residual check
+    int32_t done;     // 1: converged on the true residual
+    int32_t iters;
+    int32_t updates;
+    int32_t pad;
+};
+
+struct PcgShared {       // device-side counters shared by the kernels of one run
+    int32_t n_active;
+    int32_t parity;      // which p buffer is current
+    uint32_t counter;    // last-block-done counter
+    int32_t pad;
+};
+
+struct LsqrScal {
+    double alpha, beta, rhobar, phibar, rho, phi, theta, c, s;
+    double beta1;
+    int32_t done;        // lucky breakdown / zero rhs
+    int32_t breakdown;   // p.r <= 0 or non-finite
+    int32_t steps;
+    int32_t rotated;     // 1 when the last step applied a plane rotation
+};
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace qpat
+
+struct qpat_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    qpat_opts opts{};
+    std::string err;
+
+    // mesh
+    int64_t N = 0, E = 0, Fb = 0;
+    int32_t* tets = nullptr;       // [E][4]
+    double* geo = nullptr;         // [E][kTetGeo]
+    int32_t* bfaces = nullptr;     // [Fb][3]
+    double* barea = nullptr;       // [Fb]
+    int32_t* n2t_ptr = nullptr;    // [N+1]
+    int32_t* n2t = nullptr;        // [4E], entry = e*4 + a
+    int32_t* n2f_ptr = nullptr;    // [N+1]
+    int32_t* n2f = nullptr;        // [3Fb], entry = f*3 + a
+    qpat::Sell sell;
+
+    // linearisation point and operator
+    double* kappa = nullptr;       // [N]
+    double* mu = nullptr;          // [N]
+    double* K64 = nullptr;         // [sell.len]
+    float* K32 = nullptr;
+    double* Kdinv64 = nullptr;     // [N]
+    float* Kdinv32 = nullptr;
+    bool have_forward = false;
+
+    // prior
+    double* M64 = nullptr;         // [2][sell.len]
+    float* M32 = nullptr;
+    double* Mdinv64 = nullptr;     // [2][N]  1/(diag + delta)
+    float* Mdinv32 = nullptr;
+    double delta = 0.0;
+    bool have_prior = false;
+
+    // illuminations; data-space vectors are interleaved [N][n_pad]
+    int32_t n_ill = 0, n_pad = 0;
+    double* f = nullptr;           // [N][n_pad]
+    double* phi = nullptr;         // [N][n_pad]
+
+    // PCG workspace, sized for N x kMaxRhs entries per vector
+    double* x64 = nullptr;
+    double* r64 = nullptr;
+    double* b64 = nullptr;
+    void* xl = nullptr;            // low-precision iterate (mixed)
+    void* rl = nullptr;
+    void* pa = nullptr;
+    void* pb = nullptr;
+    void* ql = nullptr;
+    qpat::PcgScal* scal = nullptr; // [kMaxSys]
+    qpat::PcgShared* shared = nullptr;
+    double* partials = nullptr;    // [4][kMaxSys][max blocks]
+    int32_t pcg_blocks = 0;        // blocks per system
+    qpat::PcgScal* scal_host = nullptr;  // pinned mirror
+
+    // Jacobian accumulators
+    double* acc1 = nullptr;        // [N]
+    double* acc2 = nullptr;        // [N]
+    double* dvec = nullptr;        // [N][n_pad] scratch in data space
+
+    // LSQR
+    bool lsqr_ready = false;
+    double* lu = nullptr;          // [N][n_pad]
+    double* lq = nullptr;          // [N][n_pad]
+    double* lw = nullptr;          // W, [N][n_pad]
+    double* lv = nullptr;          // [2N]
+    double* lwh = nullptr;         // [2N]
+    double* lwd = nullptr;         // w direction [2N]
+    double* lp = nullptr;          // [2N]
+    double* lr = nullptr;          // [2N]
+    double* lx = nullptr;          // caller's beta_out
+    double* U = nullptr;           // [max_steps+1][N*n_pad]
+    double* V = nullptr;           // [max_steps+1][2N]
+    double* WH = nullptr;          // [max_steps+1][2N]
+    int32_t basis_cap = 0;
+    int32_t nbasis = 0;
+    bool reorth_on = false;        // reorthogonalisation state fixed at qpat_lsqr_init
+    double* coef = nullptr;        // [max_steps+1] Gram-Schmidt coefficients
+    qpat::LsqrScal* ls = nullptr;
+    qpat::LsqrScal* ls_host = nullptr;
+
+    // reductions
+    double* red_partials = nullptr;  // [kMaxRed]
+    double* red_out = nullptr;       // [64]
+    uint32_t* red_counter = nullptr;
+    double* red_host = nullptr;      // pinned [64]
+
+    int32_t* dev_flag = nullptr;     // error flag written by validation kernels
+
+    std::vector<void*> allocs;
+};
+
+namespace qpat {
+
+// ---- allocation / error helpers (api.hip)
+qpat_status fail(qpat_ctx* c, qpat_status st, const char* fmt, ...);
+qpat_status hip_check(qpat_ctx* c, hipError_t e, const char* what);
+template <typename T>
+qpat_status dalloc(qpat_ctx* c, T** p, size_t n) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, n * sizeof(T) > 0 ? n * sizeof(T) : 16);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, QPAT_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", n * sizeof(T), hipGetErrorString(e));
+    }
+    c->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return QPAT_OK;
+}
+qpat_status dfree(qpat_ctx* c, void* p);
+
+#define QPAT_TRY(expr)                    \
+    do {                                  \
+        qpat_status _s = (expr);          \
+        if (_s != QPAT_OK) return _s;     \
+    } while (0)
+#define QPAT_HIP(c, expr) QPAT_TRY(::qpat::hip_check((c), (expr), #expr))
+
+inline int grid_for(int64_t items, int per_block, int cap) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<int>(g);
+}
+
+// ---- mesh.hip
+qpat_status mesh_build(qpat_ctx* c, const double* coords, const int32_t* tets_in,
+                       const int32_t* bfaces_in);
+
+// ---- assemble.hip
+qpat_status assemble_K(qpat_ctx* c);
+qpat_status assemble_prior(qpat_ctx* c, const double* kt, const double* mt, double T,
+                           double b_over_a, double delta);
+qpat_status assemble_load(qpat_ctx* c, const double* phi_src);
+qpat_status exp_params(qpat_ctx* c, double kappa0, double mu0, const double* beta);
+qpat_status check_positive(qpat_ctx* c, const double* a, int64_t n, bool* ok);
+
+// ---- pcg.hip
+// Which operator a solve uses.
+enum class Op { K, Prior };
+struct SolveStats {
+    int32_t n_solves = 0, iters_max = 0, updates = 0;
+    int64_t iters_sum = 0;
+    double relres_max = 0.0;
+    bool noconv = false;
+};
+// Solve op * x = b for B right-hand sides (interleaved [N][B], b in c->b64,
+// result in c->x64). For Op::Prior, nsys = 2 systems with B = 1 ([2][N]).
+qpat_status pcg_solve(qpat_ctx* c, Op op, int B, SolveStats* st);
+qpat_status spmv64(qpat_ctx* c, Op op, int B, const double* x, double* y, double shift);
+
+// ---- jacobian.hip
+qpat_status forward_solve(qpat_ctx* c, SolveStats* st);
+// J s: s [2N]; mode 0 -> out [n_ill][N]; mode 1 (LSQR) -> q = W (J s) - alpha u
+qpat_status jvp_core(qpat_ctx* c, const double* s, int mode, double* out, SolveStats* st);
+// J^T t: mode 0 -> t [n_ill][N]; mode 1 (LSQR) -> t = W u (interleaved), out = J^T t - beta what
+qpat_status vjp_core(qpat_ctx* c, const double* t, int mode, double* out, SolveStats* st);
+
+// ---- lsqr.hip
+qpat_status dot(qpat_ctx* c, const double* a, const double* b, int64_t n, double* dev_out);
+qpat_status lsqr_init_core(qpat_ctx* c, const double* chi, const double* w, const double* beta_lin);
+qpat_status lsqr_step_core(qpat_ctx* c, SolveStats* st);
+qpat_status misfit_core(qpat_ctx* c, const double* chi, const double* w, double* out);
+qpat_status init_guess_core(qpat_ctx* c, const double* chi, double mu0, double* beta_out);
+qpat_status prior_apply_core(qpat_ctx* c, const double* x, double* y);
+qpat_status prior_solve_core(qpat_ctx* c, const double* p, double* r, SolveStats* st);
+
+}  // namespace qpat

@@ -1,0 +1,58 @@
+"""Helpers shared by the GPU tests: move a seeded problem onto the device and
+build the oracle's view of the same problem."""
+import numpy as np
+import pytest
+import torch
+
+from qpat_inputs import make_problem, noise_draws
+from oracle import fem
+from oracle.jacobian import Linearisation
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+class GpuProblem:
+    def __init__(self, name, opts=None, **over):
+        from paper_1512_02796_amd import qpat
+        self.P = make_problem(name, **over)
+        m = self.P.mesh
+        self.N, self.n_ill = m.N, self.P.n_ill
+        self.ctx = qpat.Context(dev(m.coords), dev(m.tets, torch.int32), dev(m.bfaces, torch.int32), opts=opts)
+        self.ctx.set_sources(dev(self.P.phi_src))
+        self.kappa = dev(self.P.kappa)
+        self.mu = dev(self.P.mu)
+
+    def forward(self):
+        phi = torch.empty(self.n_ill * self.N, dtype=torch.float64, device="cuda")
+        h = torch.empty_like(phi)
+        info = self.ctx.forward(self.kappa, self.mu, phi, h)
+        return phi.view(self.n_ill, self.N), h.view(self.n_ill, self.N), info
+
+
+def oracle_of(P):
+    g = fem.geometry(P.mesh.coords, P.mesh.tets, P.mesh.bfaces)
+    return g, Linearisation(g, P.kappa, P.mu, P.phi_src)
+
+
+def data_of(P, lin):
+    """chi and W of the seeded data model (noise sigma_rel |h| xi, W = 1/(sigma_rel |h|))."""
+    sig = P.cfg["noise"]
+    xi = noise_draws(P.cfg["id"], P.n_ill, P.mesh.N)
+    chi = lin.h + sig * np.abs(lin.h) * xi
+    W = 1.0 / (sig * np.abs(lin.h))
+    return chi, W
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
