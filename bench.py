@@ -1,0 +1,262 @@
+#!/usr/bin/env python
+"""Benchmark of the QPAT Jacobian / priorconditioned-LSQR path on one MI355X.
+
+Workload (default): 128^3 Kuhn voxels of a 40 mm cube (N = 2,146,689 nodes,
+E = 12,582,912 tetrahedra), 16 Gaussian illuminations, seeded ellipsoid
+phantom, linearised at the true phantom. A timed step is one J s + J^T t pair
+(16 tangent and 16 adjoint solves as 16-RHS block PCG, FP32 operator with FP64
+reliable updates, true FP64 residual <= 1e-10 ||b||). After the timed pairs:
+seconds per priorconditioned-LSQR iteration (pair + M_delta^{-1} +
+reorthogonalisation), the same pair in plain FP64 (one right-hand side at a
+time), live per-launch timing of the dominant PCG kernel for the roofline,
+and the FP64 CPU oracle timed on a bounded sample of the same system.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "J·v+Jᵀ·w pairs/s & s per LSQR iter at 128³ grid; % HBM peak; plain vs batched"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kind, N, nnz, V, stat):
+    """Bytes one launch must move, summed over the measured launches.
+
+    dir_spmv: per active right-hand side read r, p_old and write p_new, q
+    (4 N V); per launch the matrix (nnz values of V bytes + 4-byte columns),
+    the Jacobi diagonal (N V) and the row lengths (4 N).
+    update: per active right-hand side read x, p, q, r and write x, r (6 N V);
+    per launch the Jacobi diagonal (N V).
+    """
+    L, lanes = stat["launches"], stat["lanes"]
+    if kind == "dir_spmv":
+        return lanes * 4 * N * V + L * (nnz * (4 + V) + N * (V + 4))
+    return lanes * 6 * N * V + L * N * V
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--n-ill", type=int, default=16)
+    ap.add_argument("--lsqr-steps", type=int, default=3)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=150)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run a device copy of this size (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding by illumination is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1512_02796_amd import qpat
+    from qpat_inputs import make_problem, noise_draws, probe_vectors
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    def d(a, dt=torch.float64):
+        return torch.as_tensor(np.ascontiguousarray(a)).to(device=dev, dtype=dt)
+
+    t_setup = time.time()
+    P = make_problem("C3", n=args.grid, n_ill=args.n_ill)
+    m = P.mesh
+    N, K = m.N, P.n_ill
+    log(f"problem {args.grid}^3: N={N} E={m.E} n_ill={K} ({time.time() - t_setup:.1f}s)")
+    opts = qpat.default_opts(precision=1, max_rhs_block=16)
+    ctx = qpat.Context(d(m.coords), d(m.tets, torch.int32), d(m.bfaces, torch.int32), opts=opts)
+    ctx.set_sources(d(P.phi_src))
+    h = torch.empty(K * N, dtype=torch.float64, device=dev)
+    finfo = ctx.forward(d(P.kappa), d(P.mu), None, h)
+    log("forward", finfo)
+    # seeded data of the reconstruction (synthetic): chi = h + sigma |h| xi, W = 1/(sigma |h|)
+    hh = h.cpu().numpy().reshape(K, N)
+    sig = P.cfg["noise"]
+    chi = hh + sig * np.abs(hh) * noise_draws(P.cfg["id"], K, N)
+    W = 1.0 / (sig * np.abs(hh))
+    s_np, t_np = probe_vectors(P.cfg["id"], K, N)
+    s, t = d(s_np), d(t_np)
+    Js = torch.empty(K * N, dtype=torch.float64, device=dev)
+    Jt = torch.empty(2 * N, dtype=torch.float64, device=dev)
+    nnz = None
+
+    # ---- timed J s + J^T t pairs (batched + mixed)
+    for _ in range(args.warmup):
+        ctx.jvp(s, Js)
+        ctx.vjp(t, Jt)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append((ctx.jvp(s, Js), ctx.vjp(t, Jt)))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile(False)
+    kst = ctx.profile_read()
+    pair_s = (t1 - t0) / args.steps
+    log(f"batched mixed pair: {pair_s * 1e3:.1f} ms", infos[-1])
+
+    # ---- one PLSQR iteration (pair + M_delta^{-1} + reorthogonalisation)
+    kt = np.log(P.kappa / P.kappa0)
+    mt = np.log(P.mu / P.mu0)
+    lsqr_s = prior_s = None
+    ls_hist, pinfo = [], {"iters_max": None}
+    if args.lsqr_steps > 0:
+        ctx.prior_setup(d(kt), d(mt))
+        x = torch.zeros(2 * N, dtype=torch.float64, device=dev)
+        ctx.lsqr_init(d(chi), d(W), d(np.concatenate([kt, mt])), x)
+        ctx.lsqr_step()                      # warm-up step
+        torch.cuda.synchronize()
+        ls_t0 = time.perf_counter()
+        for _ in range(args.lsqr_steps):
+            r, _ = ctx.lsqr_step()
+            ls_hist.append(r)
+        torch.cuda.synchronize()
+        lsqr_s = (time.perf_counter() - ls_t0) / args.lsqr_steps
+        log(f"LSQR iteration: {lsqr_s * 1e3:.1f} ms, residuals {ls_hist}")
+        p_t0 = time.perf_counter()
+        pinfo = ctx.prior_solve(d(s_np), torch.empty(2 * N, dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+        prior_s = time.perf_counter() - p_t0
+        log(f"M_delta^-1: {prior_s * 1e3:.1f} ms", pinfo)
+
+    # ---- plain FP64 pair (one right-hand side at a time) and batched FP64
+    plain = None
+    if not args.no_plain:
+        out = {}
+        for label, prec, blk in (("plain_fp64", 0, 1), ("batched_fp64", 0, 16)):
+            ctx.set_opts(precision=prec, max_rhs_block=blk)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            i1 = ctx.jvp(s, Js)
+            i2 = ctx.vjp(t, Jt)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - a
+            out[label] = {"pairs_per_s": 1.0 / dt, "ms_per_pair": dt * 1e3,
+                          "pcg_iters_sum": i1["iters_sum"] + i2["iters_sum"],
+                          "pcg_iters_max": max(i1["iters_max"], i2["iters_max"])}
+            log(label, out[label])
+        ctx.set_opts(precision=1, max_rhs_block=16)
+        plain = out
+
+    # ---- calibration copy for HBM counters (profiling runs only)
+    if args.copy_calib_mib:
+        a = torch.empty(args.copy_calib_mib * (1 << 20) // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    # ---- roofline of the dominant kernel (live HIP-event timing)
+    from paper_1512_02796_amd.qpat import Context  # noqa: F401
+    # nnz of the P1 pattern on the Kuhn mesh (14 neighbours per interior node)
+    n = args.grid
+    nnz = N + 2 * (3 * n * (n + 1) ** 2 + 3 * n * n * (n + 1) + n ** 3)
+    V = 4  # FP32 vectors and values in the mixed K solve
+    cand = {"k_dir_spmv<float,16>": ("dir_spmv", kst["K_dir_spmv"]),
+            "k_update<float,16>": ("update", kst["K_update"])}
+    name, (kind, st) = max(cand.items(), key=lambda kv: kv[1][1]["total_ms"])
+    bytes_total = algorithmic_bytes(kind, N, nnz, V, st)
+    avg_ms = st["total_ms"] / st["launches"]
+    achieved = bytes_total / st["launches"] / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_ms": round(avg_ms, 4), "launches": st["launches"],
+                "bytes_per_launch": round(bytes_total / st["launches"]),
+                "other_kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "launches": v["launches"],
+                                      "GB/s": round(algorithmic_bytes(
+                                          "dir_spmv" if "dir" in k else "update", N, nnz, V, v)
+                                          / max(v["total_ms"], 1e-9) / 1e6, 1) if v["launches"] else 0}
+                                  for k, v in kst.items() if k.startswith("K_")}}
+    log("roofline", roofline)
+
+    # ---- CPU oracle on a bounded sample of the same system
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(P, args.cpu_iters, plain)
+        log("cpu_baseline", cpu)
+
+    ctx.close()
+    res = {
+        "metric": METRIC,
+        "value": round(1.0 / pair_s, 4),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(pair_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": f"QPAT J s + J^T t pair, {args.grid}^3 Kuhn voxels (N={N}, E={m.E}), "
+                               f"{K} Gaussian illuminations, seeded ellipsoid phantom, 16-RHS block PCG, "
+                               "FP32 apply + FP64 reliable updates, rtol 1e-10",
+                   "grid": args.grid, "nodes": N, "tets": m.E, "n_ill": K, "precision": "mixed",
+                   "rhs_block": 16, "pcg_rtol": 1e-10},
+        "s_per_lsqr_iter": round(lsqr_s, 4) if lsqr_s else None,
+        "prior_solve_s": round(prior_s, 4) if prior_s else None,
+        "pcg_iters": {"pair_sum": infos[-1][0]["iters_sum"] + infos[-1][1]["iters_sum"],
+                      "tangent_max": infos[-1][0]["iters_max"], "adjoint_max": infos[-1][1]["iters_max"],
+                      "prior": pinfo["iters_max"], "reliable_updates": infos[-1][0]["updates"] + infos[-1][1]["updates"]},
+        "plain": plain,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(P, iters, plain):
+    """FP64 oracle on the same 128^3 system: Jacobi-PCG iterations of one
+    right-hand side (the oracle's K solve), timed over `iters` iterations and
+    scaled to one J s + J^T t pair by the pair's FP64 PCG iteration count."""
+    from oracle import fem
+    from oracle.solve import pcg
+    m = P.mesh
+    a = time.time()
+    g = fem.geometry(m.coords, m.tets, m.bfaces)
+    Kmat = fem.system_matrix(g, P.kappa, P.mu)
+    f = fem.load_vectors(g, P.phi_src[:1])[0]
+    setup = time.time() - a
+    t0 = time.perf_counter()
+    try:
+        pcg(Kmat, f, rtol=1e-30, maxit=iters)
+    except RuntimeError:
+        pass                              # stopped at maxit by design
+    dt = (time.perf_counter() - t0) / iters
+    pair_iters = plain["plain_fp64"]["pcg_iters_sum"] if plain else None
+    out = {"kind": "oracle", "cores": 1, "unit": "pairs/s",
+           "sample": f"oracle Jacobi-PCG on the {m.n}^3 K system, {iters} iterations of one right-hand side "
+                     f"({dt * 1e3:.1f} ms/iteration, single-threaded scipy/numpy; assembly {setup:.0f}s untimed)",
+           "s_per_pcg_iter": round(dt, 5)}
+    if pair_iters:
+        out["value"] = round(1.0 / (dt * pair_iters), 6)
+        out["sample"] += f", scaled by the {pair_iters} FP64 PCG iterations of one pair (32 solves)"
+    else:
+        out["value"] = None
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -63,6 +63,7 @@ typedef struct {
     int32_t lsqr_max_steps; /* capacity of the stored bases when lsqr_reorth = 1.             */
     double  ru_delta;       /* mixed precision: recompute the FP64 residual whenever the
                                recursive one fell by this factor since the last recompute.   */
+    int32_t use_graphs;     /* 1: replay chunks of PCG iterations as captured HIP graphs.     */
 } qpat_opts;
 
 typedef struct {
@@ -75,7 +76,7 @@ typedef struct {
 
 /* Fill *opts with the defaults: FP64, block 16, rtol 1e-10, maxit 20000,
  * prior_rtol 1e-10, deflation on, reorthogonalisation on with 64 steps,
- * ru_delta 1e-3. */
+ * ru_delta 1e-3, graphs on. */
 void qpat_default_opts(qpat_opts* opts);
 
 /* Create a context for a tetrahedral P1 mesh (Sec. 3: piecewise linear
@@ -171,8 +172,61 @@ qpat_status qpat_lsqr_init(qpat_ctx* ctx, const double* chi, const double* w,
  * freezes the iterate. */
 qpat_status qpat_lsqr_step(qpat_ctx* ctx, double* resnorm_out, qpat_info* info);
 
+/* Per-launch timing of the two PCG iteration kernels, for roofline
+ * measurements. While enabled, every launch of the direction+SpMV kernel and
+ * of the update kernel is bracketed by HIP events on the context's stream
+ * and its duration accumulated. Index 0: K solves, direction+SpMV;
+ * 1: K solves, update; 2: M_delta solves, direction+SpMV; 3: M_delta solves,
+ * update. qpat_profile(ctx, 1) clears the counters and starts, 0 stops. */
+typedef struct {
+    int64_t launches;       /* launches that did work                                */
+    int64_t lanes;          /* sum over those launches of the right-hand sides still
+                               iterating (the rest of the block is skipped)         */
+    double  total_ms;
+    double  min_ms;
+    double  max_ms;
+} qpat_kstat;
+qpat_status qpat_profile(qpat_ctx* ctx, int32_t enable);
+qpat_status qpat_profile_read(const qpat_ctx* ctx, qpat_kstat out[4]);
+
+/* ---- Learned initial guess of the forward solves (extension; needs a
+ * structured node lattice: node (x, y, z) has index x + nx (y + ny z)).
+ * A four-layer 3x3x3 convolutional network, channels 3 -> 16 -> 16 -> 16 -> 1,
+ * ReLU between layers, zero padding, BF16 weights and activations with FP32
+ * accumulation on MFMA. Parameters (15601 FP32 on the device) are ordered
+ * layer by layer as w[c_out][c_in][27] (taps (dz, dy, dx), dx fastest) then
+ * b[c_out]. For illumination k the inputs are log(mu/mu0), log(kappa/kappa0)
+ * and log(phi_hom_k), phi_hom_k the fluence of the homogeneous (kappa0, mu0)
+ * medium; the output is the log correction, phi0_k = phi_hom_k exp(net). */
+qpat_status qpat_guess_setup(qpat_ctx* ctx, int32_t nx, int32_t ny, int32_t nz);
+qpat_status qpat_guess_set_params(qpat_ctx* ctx, const float* params);   /* also resets Adam */
+qpat_status qpat_guess_get_params(qpat_ctx* ctx, float* params);
+/* raw network: input [3][N] FP32, out [N] FP32 */
+qpat_status qpat_guess_eval(qpat_ctx* ctx, const float* input, float* out);
+/* mean squared error against target [N] and its gradient [15601] (grad may be NULL) */
+qpat_status qpat_guess_grad(qpat_ctx* ctx, const float* input, const float* target, float* grad,
+                            double* loss);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on a raw sample */
+qpat_status qpat_guess_train_step(qpat_ctx* ctx, const float* input, const float* target, float lr,
+                                  double* loss);
+/* one Adam step on the sample of one illumination: phi_hom, phi [N] FP64 */
+qpat_status qpat_guess_train(qpat_ctx* ctx, const double* kappa, const double* mu, double kappa0,
+                             double mu0, const double* phi_hom, const double* phi, float lr,
+                             double* loss);
+/* predicted fluence for every illumination: phi_hom, phi0_out [n_ill][N] FP64 */
+qpat_status qpat_guess_fluence(qpat_ctx* ctx, const double* kappa, const double* mu, double kappa0,
+                               double mu0, const double* phi_hom, double* phi0_out);
+/* qpat_forward with the solves started from x0 [n_ill][N]; the stopping rule
+ * is unchanged (true residual relative to ||f_k||). */
+qpat_status qpat_forward_x0(qpat_ctx* ctx, const double* kappa, const double* mu, const double* x0,
+                            double* phi_out, double* h_out, qpat_info* info);
+
 /* Steps taken since qpat_lsqr_init. */
 int32_t qpat_lsqr_steps(const qpat_ctx* ctx);
+
+/* |phibar| after the last qpat_lsqr_init (= ||yt||) or qpat_lsqr_step, from
+ * the host copy made when that call returned; -1 before any init. */
+double qpat_lsqr_residual(const qpat_ctx* ctx);
 
 const char* qpat_last_error(const qpat_ctx* ctx);
 const char* qpat_version(void);

@@ -59,6 +59,7 @@ qpat_status check_opts(qpat_ctx* c, const qpat_opts* o) {
     if (o->pcg_maxit < 1) return fail(c, QPAT_ERR_ARG, "pcg_maxit must be >= 1");
     if (o->lsqr_max_steps < 1) return fail(c, QPAT_ERR_ARG, "lsqr_max_steps must be >= 1");
     if (!(o->ru_delta > 0.0 && o->ru_delta < 1.0)) return fail(c, QPAT_ERR_ARG, "ru_delta must be in (0, 1)");
+    if (o->use_graphs != 0 && o->use_graphs != 1) return fail(c, QPAT_ERR_ARG, "use_graphs must be 0 or 1");
     return QPAT_OK;
 }
 
@@ -170,6 +171,7 @@ void qpat_default_opts(qpat_opts* o) {
     o->lsqr_reorth = 1;
     o->lsqr_max_steps = 64;
     o->ru_delta = 1e-3;
+    o->use_graphs = 1;
 }
 
 const char* qpat_version(void) { return "qpat 0.1 (gfx950)"; }
@@ -243,12 +245,14 @@ qpat_status qpat_set_sources(qpat_ctx* c, int32_t n_ill, const double* phi_src) 
     return QPAT_OK;
 }
 
-static qpat_status forward_common(qpat_ctx* c, double* phi_out, double* h_out, qpat_info* info) {
+static qpat_status forward_common(qpat_ctx* c, double* phi_out, double* h_out, qpat_info* info,
+                                  const double* x0 = nullptr) {
     QPAT_TRY(assemble_K(c));
     SolveStats st;
     c->have_forward = false;
     c->lsqr_ready = false;
-    QPAT_TRY(forward_solve(c, &st));
+    if (x0) QPAT_TRY(forward_solve_x0(c, x0, &st));
+    else QPAT_TRY(forward_solve(c, &st));
     const int64_t n = c->N * c->n_ill;
     const dim3 g(grid_for(n, kThreads, 1 << 30)), b(kThreads);
     if (phi_out) hipLaunchKernelGGL(k_from_interleaved, g, b, 0, c->stream, c->N, c->n_ill, c->n_pad, c->phi, nullptr, phi_out);
@@ -274,6 +278,107 @@ qpat_status qpat_forward(qpat_ctx* c, const double* kappa, const double* mu, dou
     hipLaunchKernelGGL(k_copy_d, gr, b, 0, c->stream, c->N, kappa, c->kappa);
     hipLaunchKernelGGL(k_copy_d, gr, b, 0, c->stream, c->N, mu, c->mu);
     return forward_common(c, phi_out, h_out, info);
+}
+
+qpat_status qpat_forward_x0(qpat_ctx* c, const double* kappa, const double* mu, const double* x0,
+                            double* phi_out, double* h_out, qpat_info* info) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!kappa || !mu || !x0) return fail(c, QPAT_ERR_ARG, "forward_x0: null pointer");
+    if (c->n_ill == 0) return fail(c, QPAT_ERR_STATE, "forward_x0: call qpat_set_sources first");
+    bool ok1 = false, ok2 = false;
+    QPAT_TRY(check_positive(c, kappa, c->N, &ok1));
+    QPAT_TRY(check_positive(c, mu, c->N, &ok2));
+    if (!ok1 || !ok2) return fail(c, QPAT_ERR_ARG, "forward_x0: kappa and mu must be finite and > 0");
+    const dim3 gr(grid_for(c->N, kThreads, 1 << 30)), b(kThreads);
+    hipLaunchKernelGGL(k_copy_d, gr, b, 0, c->stream, c->N, kappa, c->kappa);
+    hipLaunchKernelGGL(k_copy_d, gr, b, 0, c->stream, c->N, mu, c->mu);
+    return forward_common(c, phi_out, h_out, info, x0);
+}
+
+qpat_status qpat_guess_setup(qpat_ctx* c, int32_t nx, int32_t ny, int32_t nz) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (nx < 1 || ny < 1 || nz < 1) return fail(c, QPAT_ERR_ARG, "guess_setup: bad lattice");
+    QPAT_TRY(guess_setup(c, nx, ny, nz));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return QPAT_OK;
+}
+
+#define QPAT_NEED_GUESS(c)                                                                 \
+    do {                                                                                   \
+        if (!(c)->guess) return fail((c), QPAT_ERR_STATE, "call qpat_guess_setup first"); \
+    } while (0)
+
+qpat_status qpat_guess_set_params(qpat_ctx* c, const float* params) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    QPAT_NEED_GUESS(c);
+    if (!params) return fail(c, QPAT_ERR_ARG, "guess_set_params: null pointer");
+    QPAT_TRY(guess_set_params(c, params));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return QPAT_OK;
+}
+
+qpat_status qpat_guess_get_params(qpat_ctx* c, float* params) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    QPAT_NEED_GUESS(c);
+    if (!params) return fail(c, QPAT_ERR_ARG, "guess_get_params: null pointer");
+    QPAT_TRY(guess_get_params(c, params));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return QPAT_OK;
+}
+
+qpat_status qpat_guess_eval(qpat_ctx* c, const float* input, float* out) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    QPAT_NEED_GUESS(c);
+    if (!input || !out) return fail(c, QPAT_ERR_ARG, "guess_eval: null pointer");
+    QPAT_TRY(guess_eval_raw(c, input, out, 0));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return QPAT_OK;
+}
+
+qpat_status qpat_guess_grad(qpat_ctx* c, const float* input, const float* target, float* grad, double* loss) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    QPAT_NEED_GUESS(c);
+    if (!input || !target) return fail(c, QPAT_ERR_ARG, "guess_grad: null pointer");
+    return guess_grad_raw(c, input, target, grad, loss);
+}
+
+qpat_status qpat_guess_train_step(qpat_ctx* c, const float* input, const float* target, float lr, double* loss) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    QPAT_NEED_GUESS(c);
+    if (!input || !target || !(lr > 0.f)) return fail(c, QPAT_ERR_ARG, "guess_train_step: bad arguments");
+    QPAT_TRY(guess_train_raw(c, input, target, lr, loss));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return QPAT_OK;
+}
+
+qpat_status qpat_guess_train(qpat_ctx* c, const double* kappa, const double* mu, double kappa0, double mu0,
+                             const double* phi_hom, const double* phi, float lr, double* loss) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    QPAT_NEED_GUESS(c);
+    if (!kappa || !mu || !phi_hom || !phi || !(lr > 0.f) || !(kappa0 > 0) || !(mu0 > 0))
+        return fail(c, QPAT_ERR_ARG, "guess_train: bad arguments");
+    return guess_train(c, kappa, mu, kappa0, mu0, phi_hom, phi, lr, loss);
+}
+
+qpat_status qpat_guess_fluence(qpat_ctx* c, const double* kappa, const double* mu, double kappa0, double mu0,
+                               const double* phi_hom, double* phi0_out) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    QPAT_NEED_GUESS(c);
+    if (!kappa || !mu || !phi_hom || !phi0_out || !(kappa0 > 0) || !(mu0 > 0))
+        return fail(c, QPAT_ERR_ARG, "guess_fluence: bad arguments");
+    if (c->n_ill == 0) return fail(c, QPAT_ERR_STATE, "guess_fluence: call qpat_set_sources first");
+    QPAT_TRY(guess_fluence(c, kappa, mu, kappa0, mu0, phi_hom, phi0_out));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    return QPAT_OK;
 }
 
 qpat_status qpat_forward_log(qpat_ctx* c, double kappa0, double mu0, const double* beta, double* phi_out,
@@ -391,7 +496,27 @@ qpat_status qpat_lsqr_step(qpat_ctx* c, double* resnorm_out, qpat_info* info) {
     return finish(c, st, info);
 }
 
+qpat_status qpat_profile(qpat_ctx* c, int32_t enable) {
+    if (!c) return QPAT_ERR_ARG;
+    if (enable) {
+        for (auto& k : c->prof) k = qpat_kstat{0, 0, 0.0, 0.0, 0.0};
+    }
+    c->prof_on = enable != 0;
+    return QPAT_OK;
+}
+
+qpat_status qpat_profile_read(const qpat_ctx* c, qpat_kstat out[4]) {
+    if (!c || !out) return QPAT_ERR_ARG;
+    for (int i = 0; i < 4; ++i) out[i] = c->prof[i];
+    return QPAT_OK;
+}
+
 int32_t qpat_lsqr_steps(const qpat_ctx* c) { return c && c->ls_host ? c->ls_host->steps : 0; }
+
+double qpat_lsqr_residual(const qpat_ctx* c) {
+    if (!c || !c->ls_host || !c->lsqr_ready) return -1.0;
+    return std::fabs(c->ls_host->phibar);
+}
 
 const char* qpat_last_error(const qpat_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
@@ -399,6 +524,10 @@ void qpat_destroy(qpat_ctx* c) {
     if (!c) return;
     DeviceGuard g(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    guess_destroy(c);
     for (void* p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->scal_host) (void)hipHostFree(c->scal_host);

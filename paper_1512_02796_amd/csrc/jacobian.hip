@@ -155,6 +155,15 @@ __global__ void k_unpack(int64_t N, const double* __restrict__ src, int n_pad, i
     dst[(t / B) * n_pad + col0 + (t % B)] = src[t];
 }
 
+// solver block <- columns col0..col0+B-1 of a caller array [n_ill][N] (zero past n_ill)
+template <int B>
+__global__ void k_pack_ext(int64_t N, const double* __restrict__ src, int n_ill, int col0, double* __restrict__ dst) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * B) return;
+    const int kk = col0 + static_cast<int>(t % B);
+    dst[t] = kk < n_ill ? src[(int64_t)kk * N + t / B] : 0.0;
+}
+
 // adjoint right-hand side b = mu t (tmode 0: external t; 1: t = W u interleaved)
 template <int B>
 __global__ void k_adj_rhs(int64_t N, const double* __restrict__ mu, int n_pad, int n_ill, int col0, int tmode,
@@ -233,6 +242,20 @@ qpat_status forward_solve(qpat_ctx* c, SolveStats* st) {
     for (int col0 = 0; col0 < c->n_pad; col0 += B) {
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_pack<BB>, g, blk, 0, c->stream, c->N, c->f, c->n_pad, col0, c->b64));
         QPAT_TRY(pcg_solve(c, Op::K, B, st));
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_unpack<BB>, g, blk, 0, c->stream, c->N, c->x64, c->n_pad, col0, c->phi));
+    }
+    QPAT_HIP(c, hipGetLastError());
+    return QPAT_OK;
+}
+
+// forward solves started from a caller's initial guess x0 [n_ill][N]
+qpat_status forward_solve_x0(qpat_ctx* c, const double* x0, SolveStats* st) {
+    const int B = block_size(c);
+    const dim3 g(grid_for(c->N * B, kThreads, 1 << 30)), blk(kThreads);
+    for (int col0 = 0; col0 < c->n_pad; col0 += B) {
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_pack<BB>, g, blk, 0, c->stream, c->N, c->f, c->n_pad, col0, c->b64));
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_pack_ext<BB>, g, blk, 0, c->stream, c->N, x0, c->n_ill, col0, c->x64));
+        QPAT_TRY(pcg_solve(c, Op::K, B, st, true));
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_unpack<BB>, g, blk, 0, c->stream, c->N, c->x64, c->n_pad, col0, c->phi));
     }
     QPAT_HIP(c, hipGetLastError());

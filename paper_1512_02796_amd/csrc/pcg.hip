@@ -488,17 +488,54 @@ __global__ __launch_bounds__(kThreads) void k_spmv64(const Sell s, int64_t N, co
 }
 
 // ---------------------------------------------------------------- host side
+// number of launched iterations of a chunk that did work: the largest
+// per-lane iteration increase
+inline int live_iters(const PcgScal* hs, int S, const std::vector<int>& before, int chunk) {
+    int m = 0;
+    for (int i = 0; i < S; ++i) m = std::max(m, hs[i].iters - before[i]);
+    return std::min(m, chunk);
+}
+
+// Captured graph of `chunk` PCG iterations for this kernel configuration. The
+// capture runs on a private stream (capture is not allowed on the legacy
+// default stream); replays go to the context's stream.
+template <typename T, int B, bool DEFL>
+qpat_status chunk_graph(qpat_ctx* c, const PcgArgs<T>& a, int chunk, dim3 grid, dim3 blk, hipGraphExec_t* out) {
+    const void* kfn = reinterpret_cast<const void*>(&k_dir_spmv<T, B, DEFL>);
+    char key[256];
+    snprintf(key, sizeof key, "%p/%d/%d/%d/%.17g/%d/%d", kfn, chunk, a.gs, a.nsys, a.rtol2, a.maxit, (int)a.N);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) {
+        *out = it->second;
+        return QPAT_OK;
+    }
+    if (!c->cap_stream) QPAT_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    QPAT_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < chunk; ++i) {
+        hipLaunchKernelGGL((k_dir_spmv<T, B, DEFL>), grid, blk, 0, c->cap_stream, a);
+        hipLaunchKernelGGL((k_update<T, B, DEFL>), grid, blk, 0, c->cap_stream, a);
+    }
+    QPAT_HIP(c, hipStreamEndCapture(c->cap_stream, &graph));
+    hipGraphExec_t exec = nullptr;
+    QPAT_HIP(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    QPAT_HIP(c, hipGraphDestroy(graph));
+    c->graphs[key] = exec;
+    *out = exec;
+    return QPAT_OK;
+}
+
 template <typename T, int B, bool DEFL>
 struct Runner {
-    static qpat_status run(qpat_ctx* c, Op op, PcgArgs<T>& a, double rtol, SolveStats* st) {
+    static qpat_status run(qpat_ctx* c, Op op, PcgArgs<T>& a, double rtol, SolveStats* st, bool has_x0) {
         const int S = a.nsys * B;
         const dim3 grid(a.gs * a.nsys), blk(kThreads);
         hipStream_t sm = c->stream;
         hipLaunchKernelGGL(k_reset_scal, dim3(1), dim3(64), 0, sm, a.sc, S, a.sh);
         if (DEFL) hipLaunchKernelGGL(k_deflate_rhs, dim3(a.nsys), blk, 0, sm, a.b64, a.N, a.sc, a.inv_delta);
-        QPAT_HIP(c, hipMemsetAsync(a.x64, 0, sizeof(double) * a.N * B * a.nsys, sm));
+        if (!has_x0) QPAT_HIP(c, hipMemsetAsync(a.x64, 0, sizeof(double) * a.N * B * a.nsys, sm));
         a.mask = (S >= 32) ? 0xffffffffu : ((1u << S) - 1u);
-        hipLaunchKernelGGL((k_true_residual<T, B, DEFL>), grid, blk, 0, sm, a, 1, 0);
+        hipLaunchKernelGGL((k_true_residual<T, B, DEFL>), grid, blk, 0, sm, a, 1, has_x0 ? 1 : 0);
         QPAT_HIP(c, hipGetLastError());
         PcgScal* hs = c->scal_host;
         auto fetch = [&]() -> qpat_status {
@@ -514,16 +551,56 @@ struct Runner {
         std::vector<int> stalls(S, 0);
         std::vector<double> rr_prev(S);
         for (int i = 0; i < S; ++i) rr_prev[i] = hs[i].rr;
+        std::vector<int> iters_before(S);
         for (;;) {
+            for (int i = 0; i < S; ++i) iters_before[i] = hs[i].iters;
             bool any_active = false;
             for (int i = 0; i < S; ++i) any_active |= hs[i].active != 0;
             if (!any_active) break;
-            for (int it = 0; it < chunk; ++it) {
-                hipLaunchKernelGGL((k_dir_spmv<T, B, DEFL>), grid, blk, 0, sm, a);
-                hipLaunchKernelGGL((k_update<T, B, DEFL>), grid, blk, 0, sm, a);
+            const bool prof = c->prof_on;
+            if (prof && c->ev_pool.size() < (size_t)4 * chunk) {
+                size_t old = c->ev_pool.size();
+                c->ev_pool.resize((size_t)4 * chunk);
+                for (size_t e = old; e < c->ev_pool.size(); ++e) QPAT_HIP(c, hipEventCreate(&c->ev_pool[e]));
+            }
+            if (!prof && c->opts.use_graphs) {
+                // replay a captured graph of `chunk` iterations (kernel arguments are
+                // identical from one iteration to the next: all state is on the device)
+                hipGraphExec_t g = nullptr;
+                QPAT_TRY((chunk_graph<T, B, DEFL>(c, a, chunk, grid, blk, &g)));
+                QPAT_HIP(c, hipGraphLaunch(g, sm));
+            } else {
+                for (int it = 0; it < chunk; ++it) {
+                    if (prof) QPAT_HIP(c, hipEventRecord(c->ev_pool[4 * it], sm));
+                    hipLaunchKernelGGL((k_dir_spmv<T, B, DEFL>), grid, blk, 0, sm, a);
+                    if (prof) QPAT_HIP(c, hipEventRecord(c->ev_pool[4 * it + 1], sm));
+                    hipLaunchKernelGGL((k_update<T, B, DEFL>), grid, blk, 0, sm, a);
+                    if (prof) QPAT_HIP(c, hipEventRecord(c->ev_pool[4 * it + 2], sm));
+                }
             }
             QPAT_HIP(c, hipGetLastError());
             QPAT_TRY(fetch());
+            if (prof) {
+                // launches after every lane stopped exit at once; count only live ones
+                const int base = op == Op::K ? 0 : 2;
+                for (int it = 0; it < chunk; ++it) {
+                    float t1 = 0.f, t2 = 0.f;
+                    QPAT_HIP(c, hipEventElapsedTime(&t1, c->ev_pool[4 * it], c->ev_pool[4 * it + 1]));
+                    QPAT_HIP(c, hipEventElapsedTime(&t2, c->ev_pool[4 * it + 1], c->ev_pool[4 * it + 2]));
+                    if (it >= live_iters(hs, S, iters_before, chunk)) break;
+                    int lanes = 0;
+                    for (int i = 0; i < S; ++i) lanes += (hs[i].iters - iters_before[i]) > it;
+                    for (int kk = 0; kk < 2; ++kk) {
+                        qpat_kstat& ks = c->prof[base + kk];
+                        const double t = kk == 0 ? t1 : t2;
+                        ks.launches += 1;
+                        ks.lanes += lanes;
+                        ks.total_ms += t;
+                        ks.min_ms = ks.launches == 1 ? t : std::min(ks.min_ms, t);
+                        ks.max_ms = std::max(ks.max_ms, t);
+                    }
+                }
+            }
             uint32_t mask = 0;
             for (int i = 0; i < S; ++i) {
                 if (hs[i].pending) mask |= 1u << i;
@@ -569,7 +646,15 @@ struct Runner {
                 int pred = rate < 0 ? static_cast<int>(std::log(target / hs[i].rr) / rate) + 1 : 64;
                 need = std::max(need, pred);
             }
-            chunk = std::min(std::max(need, 4), 256);
+            // mixed precision: the FP32 recursive residual may not run far past a
+            // reliable-update point (its drift grows with the distance), and CG
+            // often speeds up, so chunks stay short there
+            chunk = std::min(std::max(need, 4), mixed ? 32 : 256);
+            if (c->opts.use_graphs) {
+                int p2 = 4;
+                while (p2 < chunk) p2 <<= 1;
+                chunk = p2;
+            }
             for (int i = 0; i < S; ++i) rr_prev[i] = hs[i].rr;
         }
         if (mixed) {
@@ -596,13 +681,13 @@ struct Runner {
 };
 
 template <typename T, bool DEFL>
-qpat_status dispatch_B(qpat_ctx* c, Op op, int B, PcgArgs<T>& a, double rtol, SolveStats* st) {
+qpat_status dispatch_B(qpat_ctx* c, Op op, int B, PcgArgs<T>& a, double rtol, SolveStats* st, bool x0) {
     switch (B) {
-        case 1: return Runner<T, 1, DEFL>::run(c, op, a, rtol, st);
-        case 2: return Runner<T, 2, DEFL>::run(c, op, a, rtol, st);
-        case 4: return Runner<T, 4, DEFL>::run(c, op, a, rtol, st);
-        case 8: return Runner<T, 8, DEFL>::run(c, op, a, rtol, st);
-        case 16: return Runner<T, 16, DEFL>::run(c, op, a, rtol, st);
+        case 1: return Runner<T, 1, DEFL>::run(c, op, a, rtol, st, x0);
+        case 2: return Runner<T, 2, DEFL>::run(c, op, a, rtol, st, x0);
+        case 4: return Runner<T, 4, DEFL>::run(c, op, a, rtol, st, x0);
+        case 8: return Runner<T, 8, DEFL>::run(c, op, a, rtol, st, x0);
+        case 16: return Runner<T, 16, DEFL>::run(c, op, a, rtol, st, x0);
         default: return fail(c, QPAT_ERR_ARG, "block size %d not supported", B);
     }
 }
@@ -651,7 +736,7 @@ PcgArgs<T> make_args(qpat_ctx* c, Op op, int B) {
 
 }  // namespace
 
-qpat_status pcg_solve(qpat_ctx* c, Op op, int B, SolveStats* st) {
+qpat_status pcg_solve(qpat_ctx* c, Op op, int B, SolveStats* st, bool has_x0) {
     const bool mixed = c->opts.precision == 1 && op == Op::K;
     const bool defl = op == Op::Prior && c->opts.prior_deflate;
     const double rtol = op == Op::K ? c->opts.pcg_rtol : c->opts.prior_rtol;
@@ -660,13 +745,13 @@ qpat_status pcg_solve(qpat_ctx* c, Op op, int B, SolveStats* st) {
         PcgArgs<float> a = make_args<float>(c, op, B);
         a.rtol2 = rtol * rtol;
         a.maxit = c->opts.pcg_maxit;
-        return dispatch_B<float, false>(c, op, B, a, rtol, st);
+        return dispatch_B<float, false>(c, op, B, a, rtol, st, has_x0);
     }
     PcgArgs<double> a = make_args<double>(c, op, B);
     a.rtol2 = rtol * rtol;
     a.maxit = c->opts.pcg_maxit;
-    if (defl) return Runner<double, 1, true>::run(c, op, a, rtol, st);
-    return dispatch_B<double, false>(c, op, B, a, rtol, st);
+    if (defl) return Runner<double, 1, true>::run(c, op, a, rtol, st, false);
+    return dispatch_B<double, false>(c, op, B, a, rtol, st, has_x0);
 }
 
 qpat_status spmv64(qpat_ctx* c, Op op, int B, const double* x, double* y, double shift) {

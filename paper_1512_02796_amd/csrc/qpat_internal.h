@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <algorithm>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -76,6 +77,8 @@ struct LsqrScal {
     int32_t steps;
     int32_t rotated;     // 1 when the last step applied a plane rotation
 };
+
+struct GuessNet;
 
 template <typename T>
 struct DevBuf {
@@ -174,6 +177,18 @@ struct qpat_ctx {
 
     int32_t* dev_flag = nullptr;     // error flag written by validation kernels
 
+    // per-launch timing of the PCG iteration kernels
+    bool prof_on = false;
+    qpat_kstat prof[4]{};
+    std::vector<hipEvent_t> ev_pool;
+
+    // learned initial guess (conv net on the node lattice)
+    qpat::GuessNet* guess = nullptr;
+
+    // captured graphs of PCG iteration chunks, keyed by kernel configuration
+    hipStream_t cap_stream = nullptr;
+    std::map<std::string, hipGraphExec_t> graphs;
+
     std::vector<void*> allocs;
 };
 
@@ -233,7 +248,8 @@ struct SolveStats {
 };
 // Solve op * x = b for B right-hand sides (interleaved [N][B], b in c->b64,
 // result in c->x64). For Op::Prior, nsys = 2 systems with B = 1 ([2][N]).
-qpat_status pcg_solve(qpat_ctx* c, Op op, int B, SolveStats* st);
+// has_x0: c->x64 already holds the initial guess (K solves only)
+qpat_status pcg_solve(qpat_ctx* c, Op op, int B, SolveStats* st, bool has_x0 = false);
 qpat_status spmv64(qpat_ctx* c, Op op, int B, const double* x, double* y, double shift);
 
 // ---- jacobian.hip
@@ -242,6 +258,20 @@ qpat_status forward_solve(qpat_ctx* c, SolveStats* st);
 qpat_status jvp_core(qpat_ctx* c, const double* s, int mode, double* out, SolveStats* st);
 // J^T t: mode 0 -> t [n_ill][N]; mode 1 (LSQR) -> t = W u (interleaved), out = J^T t - beta what
 qpat_status vjp_core(qpat_ctx* c, const double* t, int mode, double* out, SolveStats* st);
+
+// ---- guess.hip
+qpat_status guess_setup(qpat_ctx* c, int nx, int ny, int nz);
+qpat_status guess_set_params(qpat_ctx* c, const float* p);
+qpat_status guess_get_params(qpat_ctx* c, float* p);
+qpat_status guess_eval_raw(qpat_ctx* c, const float* in, float* out, int all_channels);
+qpat_status guess_grad_raw(qpat_ctx* c, const float* in, const float* target, float* grad, double* loss);
+qpat_status guess_train_raw(qpat_ctx* c, const float* in, const float* target, float lr, double* loss);
+qpat_status guess_train(qpat_ctx* c, const double* kappa, const double* mu, double k0, double m0,
+                        const double* phih, const double* phi, float lr, double* loss);
+qpat_status guess_fluence(qpat_ctx* c, const double* kappa, const double* mu, double k0, double m0,
+                          const double* phih, double* phi0);
+void guess_destroy(qpat_ctx* c);
+qpat_status forward_solve_x0(qpat_ctx* c, const double* x0, SolveStats* st);
 
 // ---- lsqr.hip
 qpat_status dot(qpat_ctx* c, const double* a, const double* b, int64_t n, double* dev_out);

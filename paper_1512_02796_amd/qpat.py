@@ -31,7 +31,7 @@ class Opts(ctypes.Structure):
                 ("pcg_rtol", ctypes.c_double), ("pcg_maxit", ctypes.c_int32),
                 ("prior_rtol", ctypes.c_double), ("prior_deflate", ctypes.c_int32),
                 ("lsqr_reorth", ctypes.c_int32), ("lsqr_max_steps", ctypes.c_int32),
-                ("ru_delta", ctypes.c_double)]
+                ("ru_delta", ctypes.c_double), ("use_graphs", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -42,6 +42,18 @@ class Info(ctypes.Structure):
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
+
+class KStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("lanes", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["avg_ms"] = self.total_ms / self.launches if self.launches else 0.0
+        return d
+
+
+KSTAT_NAMES = ("K_dir_spmv", "K_update", "prior_dir_spmv", "prior_update")
 
 _P = ctypes.c_void_p
 _D = ctypes.c_double
@@ -68,6 +80,18 @@ SIGNATURES = {
     "qpat_lsqr_init": (_S, [_P, _P, _P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_lsqr_step": (_S, [_P, ctypes.POINTER(_D), ctypes.POINTER(Info)]),
     "qpat_lsqr_steps": (_I32, [_P]),
+    "qpat_lsqr_residual": (_D, [_P]),
+    "qpat_profile": (_S, [_P, _I32]),
+    "qpat_profile_read": (_S, [_P, ctypes.POINTER(KStat)]),
+    "qpat_forward_x0": (_S, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(Info)]),
+    "qpat_guess_setup": (_S, [_P, _I32, _I32, _I32]),
+    "qpat_guess_set_params": (_S, [_P, _P]),
+    "qpat_guess_get_params": (_S, [_P, _P]),
+    "qpat_guess_eval": (_S, [_P, _P, _P]),
+    "qpat_guess_grad": (_S, [_P, _P, _P, _P, ctypes.POINTER(_D)]),
+    "qpat_guess_train_step": (_S, [_P, _P, _P, ctypes.c_float, ctypes.POINTER(_D)]),
+    "qpat_guess_train": (_S, [_P, _P, _P, _D, _D, _P, _P, ctypes.c_float, ctypes.POINTER(_D)]),
+    "qpat_guess_fluence": (_S, [_P, _P, _P, _D, _D, _P, _P]),
     "qpat_last_error": (ctypes.c_char_p, [_P]),
     "qpat_version": (ctypes.c_char_p, []),
     "qpat_destroy": (None, [_P]),
@@ -197,6 +221,62 @@ class Context:
                                           _ptr(h_out, torch.float64, nd, "h_out", True), ctypes.byref(info)))
         return info.as_dict()
 
+    def forward_x0(self, kappa, mu, x0, phi_out=None, h_out=None):
+        info = Info()
+        nd = self.n_ill * self.N
+        self._check(_lib.qpat_forward_x0(self._h, _ptr(kappa, torch.float64, self.N, "kappa"),
+                                         _ptr(mu, torch.float64, self.N, "mu"),
+                                         _ptr(x0, torch.float64, nd, "x0"),
+                                         _ptr(phi_out, torch.float64, nd, "phi_out", True),
+                                         _ptr(h_out, torch.float64, nd, "h_out", True), ctypes.byref(info)))
+        return info.as_dict()
+
+    # ---- learned initial guess
+    N_PARAMS = 15601
+
+    def guess_setup(self, nx, ny, nz):
+        self._check(_lib.qpat_guess_setup(self._h, nx, ny, nz))
+
+    def guess_set_params(self, params):
+        self._check(_lib.qpat_guess_set_params(self._h, _ptr(params, torch.float32, self.N_PARAMS, "params")))
+
+    def guess_get_params(self, out):
+        self._check(_lib.qpat_guess_get_params(self._h, _ptr(out, torch.float32, self.N_PARAMS, "params")))
+
+    def guess_eval(self, inp, out):
+        self._check(_lib.qpat_guess_eval(self._h, _ptr(inp, torch.float32, 3 * self.N, "input"),
+                                         _ptr(out, torch.float32, self.N, "out")))
+
+    def guess_grad(self, inp, target, grad=None):
+        loss = ctypes.c_double()
+        self._check(_lib.qpat_guess_grad(self._h, _ptr(inp, torch.float32, 3 * self.N, "input"),
+                                         _ptr(target, torch.float32, self.N, "target"),
+                                         _ptr(grad, torch.float32, self.N_PARAMS, "grad", True),
+                                         ctypes.byref(loss)))
+        return loss.value
+
+    def guess_train_step(self, inp, target, lr):
+        loss = ctypes.c_double()
+        self._check(_lib.qpat_guess_train_step(self._h, _ptr(inp, torch.float32, 3 * self.N, "input"),
+                                               _ptr(target, torch.float32, self.N, "target"), float(lr),
+                                               ctypes.byref(loss)))
+        return loss.value
+
+    def guess_train(self, kappa, mu, kappa0, mu0, phi_hom, phi, lr):
+        loss = ctypes.c_double()
+        self._check(_lib.qpat_guess_train(self._h, _ptr(kappa, torch.float64, self.N, "kappa"),
+                                          _ptr(mu, torch.float64, self.N, "mu"), float(kappa0), float(mu0),
+                                          _ptr(phi_hom, torch.float64, self.N, "phi_hom"),
+                                          _ptr(phi, torch.float64, self.N, "phi"), float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def guess_fluence(self, kappa, mu, kappa0, mu0, phi_hom, phi0_out):
+        nd = self.n_ill * self.N
+        self._check(_lib.qpat_guess_fluence(self._h, _ptr(kappa, torch.float64, self.N, "kappa"),
+                                            _ptr(mu, torch.float64, self.N, "mu"), float(kappa0), float(mu0),
+                                            _ptr(phi_hom, torch.float64, nd, "phi_hom"),
+                                            _ptr(phi0_out, torch.float64, nd, "phi0_out")))
+
     def jvp(self, s, out):
         info = Info()
         self._check(_lib.qpat_jvp(self._h, _ptr(s, torch.float64, 2 * self.N, "s"),
@@ -254,6 +334,17 @@ class Context:
 
     def lsqr_steps(self):
         return _lib.qpat_lsqr_steps(self._h)
+
+    def lsqr_residual(self):
+        return _lib.qpat_lsqr_residual(self._h)
+
+    def profile(self, enable):
+        self._check(_lib.qpat_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        arr = (KStat * 4)()
+        self._check(_lib.qpat_profile_read(self._h, arr))
+        return {KSTAT_NAMES[i]: arr[i].as_dict() for i in range(4)}
 
 
 def version():

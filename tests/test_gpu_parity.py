@@ -100,16 +100,26 @@ def test_prior_apply_and_solve(deflate, rtol):
     # the delta-eigenvector carries |x| ~ mean/delta; the oracle's LU is itself
     # accurate to eps cond ~ 1e-9 here, so compare at 1e-8
     assert rel(host(r), ref) <= 1e-8, info
+    # the residual measured with the oracle's own matrix carries its rounding
+    # times |r| ~ mean/delta: a floor of about eps ||M|| |r| / |x| ~ 3e-11 here
     res = np.linalg.norm(Md @ host(r) - x) / np.linalg.norm(x)
-    assert res <= 2 * rtol
+    assert res <= max(2 * rtol, 1e-10)
 
 
-def test_lsqr_matches_oracle():
+@pytest.mark.parametrize("whiten,hist_tol,x_tol", [("const", 1e-10, 1e-8), ("noise", 1e-6, 1e-4)])
+def test_lsqr_matches_oracle(whiten, hist_tol, x_tol):
+    """8 PLSQR steps from the same chi and W. With a constant W the history
+    matches to 1e-10. With W = 1/(sigma |h|) (the data model) the pointwise
+    relative error of h at nodes of tiny fluence -- which the solves bound
+    only in norm (rtol 1e-12) -- is amplified by W, so the right-hand sides of
+    the two sides differ at about 1e-7 and the comparison is at 1e-6."""
     G = GpuProblem("T8", opts())
     phi, h, _ = G.forward()
     P = G.P
     g, lin = oracle_of(P)
     chi, W = data_of(P, lin)
+    if whiten == "const":
+        W = np.full_like(W, 1.0 / (P.cfg["noise"] * np.abs(lin.h).mean()))
     kt = np.log(P.kappa / P.kappa0)
     mt = np.log(P.mu / P.mu0)
     beta_lin = np.concatenate([kt, mt])
@@ -117,7 +127,7 @@ def test_lsqr_matches_oracle():
     x = torch.zeros(2 * G.N, dtype=torch.float64, device="cuda")
     G.ctx.lsqr_init(dev(chi), dev(W), dev(beta_lin), x)
     steps = 8
-    hist = []
+    hist = [G.ctx.lsqr_residual()]
     for _ in range(steps):
         res, _ = G.ctx.lsqr_step()
         hist.append(res)
@@ -129,9 +139,10 @@ def test_lsqr_matches_oracle():
     it = PLSQR(lambda v: (W * lin.jvp(v)).ravel(), lambda u: lin.vjp(W * u.reshape(n_ill, N)), solve, yt)
     for _ in range(steps):
         it.step()
-    ref_hist = np.array(it.history[1:])
-    assert np.all(np.abs(np.array(hist) - ref_hist) <= 1e-8 * ref_hist), (hist, ref_hist)
-    assert rel(host(x), it.x) <= 1e-6
+    ref_hist = np.array(it.history)
+    assert np.all(np.abs(np.array(hist) - ref_hist) <= hist_tol * ref_hist), (hist, ref_hist)
+    assert rel(host(x), it.x) <= x_tol
+    assert G.ctx.lsqr_steps() == steps
 
 
 def test_block_sizes_agree_and_deterministic():
@@ -162,12 +173,15 @@ def test_error_paths():
         qpat.Context(dev(flat), dev(m.tets, torch.int32), dev(m.bfaces, torch.int32))
     assert e.value.status == qpat.QPAT_ERR_MESH
     ctx = qpat.Context(dev(m.coords), dev(m.tets, torch.int32), dev(m.bfaces, torch.int32))
+    ctx.set_sources(dev(np.ones((1, m.F_b, 3))))
     s = torch.zeros(2 * m.N, dtype=torch.float64, device="cuda")
     out = torch.zeros(m.N, dtype=torch.float64, device="cuda")
-    with pytest.raises(qpat.QpatError) as e:
+    with pytest.raises(qpat.QpatError) as e:       # J before any forward solve
         ctx.jvp(s, out)
     assert e.value.status == qpat.QPAT_ERR_STATE
-    ctx.set_sources(dev(np.ones((1, m.F_b, 3))))
+    with pytest.raises(qpat.QpatError) as e:       # prior solve before prior setup
+        ctx.prior_solve(s, torch.zeros_like(s))
+    assert e.value.status == qpat.QPAT_ERR_STATE
     kap = torch.full((m.N,), 0.3, dtype=torch.float64, device="cuda")
     mu = torch.full((m.N,), -0.01, dtype=torch.float64, device="cuda")
     with pytest.raises(qpat.QpatError) as e:
@@ -178,3 +192,18 @@ def test_error_paths():
     with pytest.raises(qpat.QpatError) as e:
         ctx.forward(kap, mu)
     assert e.value.status == qpat.QPAT_ERR_NOCONV
+
+
+def test_graph_replays_match_eager():
+    """Chunks of PCG iterations replayed as captured HIP graphs give the eager
+    launches' result bit for bit, replay after replay, with eager work between."""
+    G = GpuProblem("T12", opts(use_graphs=0))
+    a, _, _ = G.forward()
+    a = host(a).copy()
+    for _ in range(3):
+        G.ctx.set_opts(use_graphs=1)
+        b, _, _ = G.forward()
+        assert np.array_equal(a, host(b))
+        G.ctx.set_opts(use_graphs=0)
+        c, _, _ = G.forward()
+        assert np.array_equal(a, host(c))
