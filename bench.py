@@ -59,6 +59,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=150)
+    ap.add_argument("--workload", choices=("pair", "learned"), default="pair",
+                    help="pair: J s + J^T t pairs at 128^3 (default); learned: the learned-guess experiment")
+    ap.add_argument("--train-phantoms", type=int, default=125)
+    ap.add_argument("--held-phantoms", type=int, default=13)
+    ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -73,6 +78,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.workload == "learned":
+        return bench_learned(args)
 
     def d(a, dt=torch.float64):
         return torch.as_tensor(np.ascontiguousarray(a)).to(device=dev, dtype=dt)
@@ -223,6 +230,67 @@ def main():
         "plain": plain,
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def bench_learned(args):
+    """Learned PCG initial guess on the 96^3 workload with 8 Gaussian
+    illuminations: train on solver-generated samples (phantoms x
+    illuminations), then on held-out phantoms compare the forward block
+    solve from zero, from the homogeneous fluence, and from the network's
+    prediction (same true-residual tolerance 1e-10)."""
+    import torch
+    from paper_1512_02796_amd import qpat, learned
+    from qpat_inputs import make_problem, initial_params
+    dev = torch.device("cuda:0")
+    P = make_problem("C5")
+    m = P.mesh
+    N, K = m.N, P.n_ill
+    ctx = qpat.Context(torch.as_tensor(m.coords, device=dev), torch.as_tensor(m.tets, device=dev),
+                       torch.as_tensor(m.bfaces, device=dev),
+                       opts=qpat.default_opts(precision=1, max_rhs_block=8))
+    ctx.set_sources(torch.as_tensor(P.phi_src, device=dev))
+    n1 = m.n + 1
+    ctx.guess_setup(n1, n1, n1)
+    ctx.guess_set_params(torch.as_tensor(initial_params(P.cfg["id"]), device=dev))
+    phi_hom = learned.homogeneous_fluence(ctx, P.kappa0, P.mu0, dev)
+    t0 = time.time()
+    train = learned.make_samples(ctx, m, args.train_phantoms, P.cfg["id"], 3, dev)
+    held = learned.make_samples(ctx, m, args.held_phantoms, P.cfg["id"], 4, dev)
+    t_data = time.time() - t0
+    log(f"data: {len(train) * K} training and {len(held) * K} held-out samples in {t_data:.1f}s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = learned.train(ctx, train, phi_hom, P.kappa0, P.mu0, args.epochs, 1e-3, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    steps = args.epochs * len(train) * K
+    agg, _ = learned.evaluate(ctx, held, phi_hom, P.kappa0, P.mu0, dev)
+    log("held-out", agg)
+    # conv MFMA throughput: forward 2 V (27 (3 16) + 2 (27 16 16) + 27 16) flop per sample,
+    # a training step is forward + weight gradients + input gradients of layers 2-4 (~3x forward)
+    fwd_flop = 2.0 * N * 27 * (3 * 16 + 16 * 16 * 2 + 16)
+    train_tflops = 3.0 * fwd_flop * steps / t_train / 1e12
+    ctx.close()
+    res = {
+        "metric": "forward PCG iterations and wall time to rtol 1e-10, learned vs zero initial guess",
+        "value": round(agg["zero_ms"] / agg["net_ms"], 4),
+        "unit": "x speed-up of the forward block solve (zero start / learned start)",
+        "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": round(t_train / steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16/f32 net, f32/f64 solve",
+        "data": "synthetic",
+        "config": {"workload": f"learned PCG initial guess, {m.n}^3 Kuhn voxels (N={N}), {K} Gaussian "
+                               f"illuminations, 4-layer 3x3x3 conv net 3-16-16-16-1, "
+                               f"{len(train) * K} training / {len(held) * K} held-out samples, "
+                               f"{args.epochs} epochs Adam"},
+        "pcg_iters_per_solve": {"zero": agg["zero_iters"], "homogeneous_fluence": agg["hom_iters"],
+                                "learned": agg["net_iters"]},
+        "ms_per_block_solve": {"zero": agg["zero_ms"], "homogeneous_fluence": agg["hom_ms"],
+                               "learned_incl_inference": agg["net_ms"]},
+        "train": {"seconds": round(t_train, 2), "loss_per_epoch": hist, "data_seconds": round(t_data, 1),
+                  "approx_TFLOP_s": round(train_tflops, 1), "peak_bf16_TFLOP_s": 2500.0},
+        "max_relres": agg["relres"],
     }
     print(json.dumps(res), flush=True)
 

@@ -104,7 +104,7 @@ qpat_status alloc_core(qpat_ctx* c) {
     QPAT_TRY(dalloc(c, &c->scal, kMaxSys));
     QPAT_TRY(dalloc(c, &c->shared, 1));
     QPAT_HIP(c, hipMemsetAsync(c->shared, 0, sizeof(PcgShared), c->stream));
-    QPAT_TRY(dalloc(c, &c->partials, (size_t)5 * kMaxSys * 1024));
+    QPAT_TRY(dalloc(c, &c->partials, (size_t)5 * kMaxSys * 2048));
     QPAT_TRY(dalloc(c, &c->acc1, N));
     QPAT_TRY(dalloc(c, &c->acc2, N));
     QPAT_TRY(dalloc(c, &c->red_partials, 1024));
@@ -166,7 +166,7 @@ void qpat_default_opts(qpat_opts* o) {
     o->max_rhs_block = 16;
     o->pcg_rtol = 1e-10;
     o->pcg_maxit = 20000;
-    o->prior_rtol = 1e-10;
+    o->prior_rtol = 1e-8;
     o->prior_deflate = 1;
     o->lsqr_reorth = 1;
     o->lsqr_max_steps = 64;
@@ -335,7 +335,7 @@ qpat_status qpat_guess_eval(qpat_ctx* c, const float* input, float* out) {
     DeviceGuard g(c->device);
     QPAT_NEED_GUESS(c);
     if (!input || !out) return fail(c, QPAT_ERR_ARG, "guess_eval: null pointer");
-    QPAT_TRY(guess_eval_raw(c, input, out, 0));
+    QPAT_TRY(guess_eval_raw(c, input, out));
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
     return QPAT_OK;
 }

@@ -60,7 +60,6 @@ __device__ __forceinline__ int64_t neighbour(const Lat& L, int x, int y, int z, 
 // MODE 0: out bf16 [V][16] = relu(z + bias)
 // MODE 1: out f32 [V]      = z[:, 0] + bias[0]
 // MODE 2: out bf16 [V][16] = z * (mask[V][16] > 0)          (backward data; no bias)
-// MODE 3: out f32 [V][16]  = z + bias                        (testing)
 template <int CIN, int MODE>
 __global__ __launch_bounds__(kThreads) void k_conv(Lat L, const uint16_t* __restrict__ X,
                                                    const uint16_t* __restrict__ Wp, const float* __restrict__ bias,
@@ -104,11 +103,9 @@ __global__ __launch_bounds__(kThreads) void k_conv(Lat L, const uint16_t* __rest
                 static_cast<uint16_t*>(out)[vo * 16 + co] = f2bf(val > 0.f ? val : 0.f);
             } else if (MODE == 1) {
                 if (co == 0) static_cast<float*>(out)[vo] = val + bias[0];
-            } else if (MODE == 2) {
+            } else {
                 const bool on = bf2f(mask[vo * 16 + co]) > 0.f;
                 static_cast<uint16_t*>(out)[vo * 16 + co] = f2bf(on ? val : 0.f);
-            } else {
-                static_cast<float*>(out)[vo * 16 + co] = val + bias[co];
             }
         }
     }
@@ -222,6 +219,12 @@ __global__ void k_pack(const float* __restrict__ w, int cin, int cout, int nch, 
     Wp[i] = f2bf(val);
 }
 
+// The discrete fluence can dip slightly below zero far from the sources (the P1
+// mass matrix has positive off-diagonal entries), so logs of fluences are
+// taken of max(phi, kPhiFloor); corrections are clamped to e^{+-kMaxCorr}.
+constexpr double kPhiFloor = 1e-16;
+constexpr float kMaxCorr = 8.f;
+
 // network input for illumination k: [V][4] bf16 = (log mu/mu0, log kappa/kappa0, log phi_hom, 0)
 __global__ void k_inputs(int64_t V, const double* __restrict__ kappa, const double* __restrict__ mu, double k0,
                          double m0, const double* __restrict__ phih, uint16_t* __restrict__ X) {
@@ -229,7 +232,7 @@ __global__ void k_inputs(int64_t V, const double* __restrict__ kappa, const doub
     if (v >= V) return;
     X[v * 4 + 0] = f2bf(static_cast<float>(log(mu[v] / m0)));
     X[v * 4 + 1] = f2bf(static_cast<float>(log(kappa[v] / k0)));
-    X[v * 4 + 2] = f2bf(static_cast<float>(log(fmax(phih[v], 1e-300))));
+    X[v * 4 + 2] = f2bf(static_cast<float>(log(fmax(phih[v], kPhiFloor))));
     X[v * 4 + 3] = 0;
 }
 
@@ -248,7 +251,8 @@ __global__ void k_target(int64_t V, const double* __restrict__ phi, const double
                          float* __restrict__ t) {
     int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= V) return;
-    t[v] = static_cast<float>(log(fmax(phi[v], 1e-300)) - log(fmax(phih[v], 1e-300)));
+    const double d = log(fmax(phi[v], kPhiFloor)) - log(fmax(phih[v], kPhiFloor));
+    t[v] = static_cast<float>(fmin(fmax(d, -(double)kMaxCorr), (double)kMaxCorr));
 }
 
 // phi0 = phi_hom exp(pred)
@@ -256,7 +260,10 @@ __global__ void k_fluence(int64_t V, const float* __restrict__ pred, const doubl
                           double* __restrict__ phi0) {
     int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= V) return;
-    phi0[v] = phih[v] * exp(static_cast<double>(pred[v]));
+    float p = pred[v];
+    if (!(p == p)) p = 0.f;   // a non-finite prediction falls back to phi_hom
+    p = fminf(fmaxf(p, -kMaxCorr), kMaxCorr);
+    phi0[v] = phih[v] * exp(static_cast<double>(p));
 }
 
 // mean squared error: per-block partial sums; dZ4[v][0] = 2 (pred - t) / V
@@ -349,7 +356,8 @@ static qpat_status guess_pack(qpat_ctx* c) {
     return QPAT_OK;
 }
 
-static qpat_status guess_forward(qpat_ctx* c, int last_mode, void* out) {
+// forward pass; the last layer writes its single output channel, FP32 [V]
+static qpat_status guess_forward(qpat_ctx* c, float* out) {
     GuessNet* G = c->guess;
     const dim3 g(kConvBlocks), b(kThreads);
     const float* bias[kLayers];
@@ -357,10 +365,7 @@ static qpat_status guess_forward(qpat_ctx* c, int last_mode, void* out) {
     hipLaunchKernelGGL((k_conv<4, 0>), g, b, 0, c->stream, G->L, G->X0, G->Wf[0], bias[0], nullptr, (void*)G->Y[0]);
     hipLaunchKernelGGL((k_conv<16, 0>), g, b, 0, c->stream, G->L, G->Y[0], G->Wf[1], bias[1], nullptr, (void*)G->Y[1]);
     hipLaunchKernelGGL((k_conv<16, 0>), g, b, 0, c->stream, G->L, G->Y[1], G->Wf[2], bias[2], nullptr, (void*)G->Y[2]);
-    if (last_mode == 1)
-        hipLaunchKernelGGL((k_conv<16, 1>), g, b, 0, c->stream, G->L, G->Y[2], G->Wf[3], bias[3], nullptr, out);
-    else
-        hipLaunchKernelGGL((k_conv<16, 3>), g, b, 0, c->stream, G->L, G->Y[2], G->Wf[3], bias[3], nullptr, out);
+    hipLaunchKernelGGL((k_conv<16, 1>), g, b, 0, c->stream, G->L, G->Y[2], G->Wf[3], bias[3], nullptr, (void*)out);
     QPAT_HIP(c, hipGetLastError());
     return QPAT_OK;
 }
@@ -371,7 +376,7 @@ static qpat_status guess_backward(qpat_ctx* c) {
     const int64_t V = G->L.V;
     const dim3 g(kConvBlocks), b(kThreads);
     const int lb = grid_for(V, kThreads, 1024);
-    QPAT_TRY(guess_forward(c, 1, G->pred));
+    QPAT_TRY(guess_forward(c, G->pred));
     hipLaunchKernelGGL(k_loss, dim3(lb), b, 0, c->stream, V, G->pred, G->target, G->dA, G->lossp);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, c->stream, G->lossp, lb, V, G->lossv);
     const int64_t nw = (int64_t)kConvBlocks * 4;
@@ -444,11 +449,11 @@ qpat_status guess_get_params(qpat_ctx* c, float* p) {
     return QPAT_OK;
 }
 
-qpat_status guess_eval_raw(qpat_ctx* c, const float* in, float* out, int all_channels) {
+qpat_status guess_eval_raw(qpat_ctx* c, const float* in, float* out) {
     GuessNet* G = c->guess;
     hipLaunchKernelGGL(k_inputs_raw, dim3(grid_for(G->L.V, kThreads, 1 << 30)), dim3(kThreads), 0, c->stream,
                        G->L.V, in, G->X0);
-    return guess_forward(c, all_channels ? 3 : 1, out);
+    return guess_forward(c, out);
 }
 
 qpat_status guess_grad_raw(qpat_ctx* c, const float* in, const float* target, float* grad, double* loss) {
@@ -504,7 +509,7 @@ qpat_status guess_fluence(qpat_ctx* c, const double* kappa, const double* mu, do
     const dim3 gg(grid_for(V, kThreads, 1 << 30)), b(kThreads);
     for (int k = 0; k < c->n_ill; ++k) {
         hipLaunchKernelGGL(k_inputs, gg, b, 0, c->stream, V, kappa, mu, k0, m0, phih + k * V, G->X0);
-        QPAT_TRY(guess_forward(c, 1, G->pred));
+        QPAT_TRY(guess_forward(c, G->pred));
         hipLaunchKernelGGL(k_fluence, gg, b, 0, c->stream, V, G->pred, phih + k * V, phi0 + k * V);
     }
     QPAT_HIP(c, hipGetLastError());

@@ -15,6 +15,8 @@
 // against the stored u_j, and p against vbar_j = L v_j in the form
 // p -= (v_j . p) what_j. Every dot product is a deterministic two-stage
 // reduction; every scalar stays on the device.
+// Dot products are two kernels: per-block partial sums, then one block adds
+// them in a fixed order.
 #include <cmath>
 
 #include "qpat_internal.h"
@@ -23,10 +25,6 @@ namespace qpat {
 namespace {
 
 constexpr int kRedBlocks = 1024;
-
-__device__ __forceinline__ double ld_relaxed(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -46,50 +44,49 @@ __device__ double block_total(double v) {
     return t;
 }
 
-// out = sum_i f(i) over contiguous per-block chunks, reduced by the last block
+// partials[block] = sum of f(i) over the block's contiguous chunk of [0, n)
 template <typename F>
-__device__ void reduce_to(F f, int64_t n, double* partials, uint32_t* counter, double* out) {
+__device__ void block_partials(F f, int64_t n, double* partials) {
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = blockIdx.x * chunk;
     int64_t b1 = b0 + chunk;
     if (b1 > n) b1 = n;
-    double acc = 0.0;
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += kThreads) acc += f(i);
-    double t = block_total(acc);
-    __shared__ int last;
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double s = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kThreads) s += ld_relaxed(partials + b);
-    s = block_total(s);
-    if (threadIdx.x == 0) {
-        *out = s;
-        *counter = 0u;
+    double a0 = 0.0, a1 = 0.0;
+    int64_t i = b0 + threadIdx.x;
+    for (; i + kThreads < b1; i += 2 * kThreads) {
+        a0 += f(i);
+        a1 += f(i + kThreads);
     }
+    if (i < b1) a0 += f(i);
+    const double t = block_total(a0 + a1);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// out = sum of nb partials in a fixed order (one block)
+__global__ __launch_bounds__(kThreads) void k_sum_partials(const double* __restrict__ partials, int nb,
+                                                           double* __restrict__ out) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) s += partials[b];
+    s = block_total(s);
+    if (threadIdx.x == 0) *out = s;
 }
 
 __global__ __launch_bounds__(kThreads) void k_dot(const double* __restrict__ a, const double* __restrict__ b,
-                                                  int64_t n, double* partials, uint32_t* counter, double* out) {
-    reduce_to([=] __device__(int64_t i) { return a[i] * b[i]; }, n, partials, counter, out);
+                                                  int64_t n, double* partials) {
+    block_partials([=] __device__(int64_t i) { return a[i] * b[i]; }, n, partials);
 }
 
 // ||W (chi - mu phi)||^2 with chi, W external [n_ill][N], phi interleaved
 __global__ __launch_bounds__(kThreads) void k_misfit(int64_t N, int n_ill, int n_pad, const double* __restrict__ chi,
                                                      const double* __restrict__ w, const double* __restrict__ mu,
-                                                     const double* __restrict__ phi, double* partials,
-                                                     uint32_t* counter, double* out) {
-    reduce_to(
+                                                     const double* __restrict__ phi, double* partials) {
+    block_partials(
         [=] __device__(int64_t i) {
             const int64_t k = i / N, row = i % N;
             const double d = w[i] * (chi[i] - mu[row] * phi[row * n_pad + k]);
             return d * d;
         },
-        N * n_ill, partials, counter, out);
+        N * n_ill, partials);
 }
 
 // u = W (chi - mu phi + Jb), interleaved; Jb interleaved (or null); also W interleaved
@@ -284,16 +281,19 @@ inline dim3 grid1(int64_t n) { return dim3(grid_for(n, kThreads, 8192)); }
 }  // namespace
 
 qpat_status dot(qpat_ctx* c, const double* a, const double* b, int64_t n, double* dev_out) {
-    hipLaunchKernelGGL(k_dot, dim3(grid_for(n, kThreads * 4, kRedBlocks)), dim3(kThreads), 0, c->stream, a, b, n,
-                       c->red_partials, c->red_counter, dev_out);
+    const int nb = grid_for(n, kThreads * 8, kRedBlocks);
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kThreads), 0, c->stream, a, b, n, c->red_partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, c->stream, c->red_partials, nb, dev_out);
     QPAT_HIP(c, hipGetLastError());
     return QPAT_OK;
 }
 
 qpat_status misfit_core(qpat_ctx* c, const double* chi, const double* w, double* out) {
     const int64_t n = c->N * c->n_ill;
-    hipLaunchKernelGGL(k_misfit, dim3(grid_for(n, kThreads * 4, kRedBlocks)), dim3(kThreads), 0, c->stream, c->N,
-                       c->n_ill, c->n_pad, chi, w, c->mu, c->phi, c->red_partials, c->red_counter, c->red_out);
+    const int nb = grid_for(n, kThreads * 8, kRedBlocks);
+    hipLaunchKernelGGL(k_misfit, dim3(nb), dim3(kThreads), 0, c->stream, c->N, c->n_ill, c->n_pad, chi, w, c->mu,
+                       c->phi, c->red_partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, c->stream, c->red_partials, nb, c->red_out);
     QPAT_HIP(c, hipMemcpyAsync(c->red_host, c->red_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
     *out = std::sqrt(c->red_host[0]);

@@ -27,6 +27,9 @@
 namespace qpat {
 namespace {
 
+constexpr int kUnroll = 16;   // neighbours gathered per row before the arithmetic
+constexpr int kMaxBlocks = 2048;  // blocks per system (partial-sum buffer: 5 x kMaxSys x kMaxBlocks)
+
 template <typename T>
 struct PcgArgs {
     Sell s;
@@ -85,36 +88,6 @@ __device__ __forceinline__ double block_sum(double v, double* sm) {
     return t;
 }
 
-__device__ __forceinline__ bool arrive_last(PcgShared* sh, uint32_t nblocks) {
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t prev = atomicAdd(&sh->counter, 1u);
-        last = prev == nblocks - 1;
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
-
-// out[v] = sum_b partials[v * gs + b], deterministic order; out in shared memory
-__device__ void reduce_partials(const double* partials, int nv, int gs, double* out) {
-    int tpv = 64;
-    while (tpv * nv > kThreads && tpv > 1) tpv >>= 1;
-    const int vpp = kThreads / tpv;
-    for (int v0 = 0; v0 < nv; v0 += vpp) {
-        const int v = v0 + threadIdx.x / tpv;
-        const int sub = threadIdx.x % tpv;
-        double s = 0.0;
-        if (v < nv)
-            for (int b = sub; b < gs; b += tpv) s += ld_acq(partials + (int64_t)v * gs + b);
-        for (int off = tpv >> 1; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-        if (sub == 0 && v < nv) out[v] = s;
-    }
-    __syncthreads();
-}
-
 __device__ __forceinline__ void write_partial(double* partials, int v, int gs, double val) {
     const int32_t local = blockIdx.x % gs;
     partials[(int64_t)v * gs + local] = val;
@@ -132,7 +105,6 @@ __device__ void count_active(PcgScal* sc, PcgShared* sh, int S) {
 template <typename T, int B, bool DEFL>
 __global__ __launch_bounds__(kThreads) void k_dir_spmv(PcgArgs<T> a) {
     __shared__ double sm[4 * kMaxRhs];
-    __shared__ double tot[kMaxSys];
     if (a.sh->n_active == 0) return;
     int32_t sys;
     int64_t r0, r1;
@@ -157,16 +129,29 @@ __global__ __launch_bounds__(kThreads) void k_dir_spmv(PcgArgs<T> a) {
     for (int64_t row = r0 + threadIdx.x / B; row < r1; row += kThreads / B) {
         const int64_t idx = row * B + k;
         if (act) {
-            const T pi = dinv[row] * r[idx] - cc + beta * po[idx];
             const int32_t base = a.s.slice_ptr[row / kSlice] + static_cast<int32_t>(row % kSlice);
             const int32_t n = a.s.rowlen[row];
+            // all column indices and values first, then all gathers: two memory
+            // round trips per row instead of two per neighbour
+            int32_t col[kUnroll];
+            T av[kUnroll];
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j) {
+                col[j] = j < n ? cols[base + j * kSlice] : static_cast<int32_t>(row);
+                av[j] = j < n ? vals[base + j * kSlice] : T(0);
+            }
+            const T pi = dinv[row] * r[idx] - cc + beta * po[idx];
             T sum = T(0);
-            for (int32_t j = 0; j < n; ++j) {
-                const int32_t col = cols[base + j * kSlice];
-                const T av = vals[base + j * kSlice];
-                const int64_t jdx = (int64_t)col * B + k;
-                const T pj = dinv[col] * r[jdx] - cc + beta * po[jdx];
-                sum += av * pj;
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j) {
+                const int64_t jdx = (int64_t)col[j] * B + k;
+                const T pj = dinv[col[j]] * r[jdx] - cc + beta * po[jdx];
+                sum += av[j] * pj;
+            }
+            for (int32_t j = kUnroll; j < n; ++j) {   // rows longer than kUnroll (unstructured meshes)
+                const int32_t cj = cols[base + j * kSlice];
+                const int64_t jdx = (int64_t)cj * B + k;
+                sum += vals[base + j * kSlice] * (dinv[cj] * r[jdx] - cc + beta * po[jdx]);
             }
             pn[idx] = pi;
             q[idx] = sum;
@@ -177,28 +162,11 @@ __global__ __launch_bounds__(kThreads) void k_dir_spmv(PcgArgs<T> a) {
     }
     double bs = block_sum<B>(acc, sm);
     if (threadIdx.x < B) write_partial(a.partials, sys * B + threadIdx.x, a.gs, bs);
-    const int S = a.nsys * B;
-    if (!arrive_last(a.sh, gridDim.x)) return;
-    reduce_partials(a.partials, S, a.gs, tot);
-    if (threadIdx.x < S) {
-        PcgScal& c = a.sc[threadIdx.x];
-        if (c.active) {
-            c.pq = tot[threadIdx.x];
-            c.alpha = c.pq != 0.0 ? c.rz / c.pq : 0.0;
-        } else {
-            c.alpha = 0.0;
-        }
-    }
-    if (threadIdx.x == 0) {
-        a.sh->parity = par ^ 1;
-        a.sh->counter = 0u;
-    }
 }
 
 template <typename T, int B, bool DEFL>
 __global__ __launch_bounds__(kThreads) void k_update(PcgArgs<T> a) {
     __shared__ double sm[4 * kMaxRhs];
-    __shared__ double tot[4 * kMaxSys];
     if (a.sh->n_active == 0) return;
     int32_t sys;
     int64_t r0, r1;
@@ -216,7 +184,37 @@ __global__ __launch_bounds__(kThreads) void k_update(PcgArgs<T> a) {
     const T* __restrict__ q = a.q + (int64_t)sys * a.N * B;
     double rz = 0.0, rr = 0.0, z1 = 0.0, r1s = 0.0;
     if (act) {
-        for (int64_t row = r0 + threadIdx.x / B; row < r1; row += kThreads / B) {
+        constexpr int RS = kThreads / B;   // row stride of one pass
+        int64_t row = r0 + threadIdx.x / B;
+        // four rows per iteration: their loads are independent and go out together
+        for (; row + 3 * RS < r1; row += 4 * RS) {
+            T xv[4], pv[4], qv[4], rv[4], dv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t idx = (row + u * RS) * B + k;
+                xv[u] = x[idx];
+                pv[u] = p[idx];
+                qv[u] = q[idx];
+                rv[u] = r[idx];
+                dv[u] = dinv[row + u * RS];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t idx = (row + u * RS) * B + k;
+                const T xi = xv[u] + alpha * pv[u];
+                const T ri = rv[u] - alpha * qv[u];
+                x[idx] = xi;
+                r[idx] = ri;
+                const T zi = dv[u] * ri;
+                rz += static_cast<double>(ri) * static_cast<double>(zi);
+                rr += static_cast<double>(ri) * static_cast<double>(ri);
+                if (DEFL) {
+                    z1 += static_cast<double>(zi);
+                    r1s += static_cast<double>(ri);
+                }
+            }
+        }
+        for (; row < r1; row += RS) {
             const int64_t idx = row * B + k;
             const T xi = x[idx] + alpha * p[idx];
             const T ri = r[idx] - alpha * q[idx];
@@ -249,35 +247,6 @@ __global__ __launch_bounds__(kThreads) void k_update(PcgArgs<T> a) {
             write_partial(a.partials, 3 * S + v, a.gs, v3);
         }
     }
-    if (!arrive_last(a.sh, gridDim.x)) return;
-    reduce_partials(a.partials, Q * S, a.gs, tot);
-    if (threadIdx.x < S) {
-        PcgScal& c = a.sc[threadIdx.x];
-        if (c.active) {
-            double rzn = tot[threadIdx.x];
-            const double rrn = tot[S + threadIdx.x];
-            double cn = 0.0;
-            if (DEFL) {
-                cn = tot[2 * S + threadIdx.x] / static_cast<double>(a.N);
-                rzn -= cn * tot[3 * S + threadIdx.x];
-            }
-            c.beta = c.rz != 0.0 ? rzn / c.rz : 0.0;
-            c.rz_prev = c.rz;
-            c.rz = rzn;
-            c.c = cn;
-            c.rr = rrn;
-            c.iters += 1;
-            if (rrn <= a.rtol2 * c.bnorm2 || !(rrn == rrn)) {
-                c.active = 0;
-                c.pending = 1;
-            } else if (c.iters >= a.maxit) {
-                c.active = 0;
-            }
-        }
-    }
-    __syncthreads();
-    count_active(a.sc, a.sh, S);
-    if (threadIdx.x == 0) a.sh->counter = 0u;
 }
 
 // ------------------------------------------------------- true residual (FP64)
@@ -304,7 +273,6 @@ __global__ __launch_bounds__(kThreads) void k_fold(PcgArgs<T> a) {
 template <typename T, int B, bool DEFL>
 __global__ __launch_bounds__(kThreads) void k_true_residual(PcgArgs<T> a, int init, int has_x0) {
     __shared__ double sm[4 * kMaxRhs];
-    __shared__ double tot[5 * kMaxSys];
     int32_t sys;
     int64_t r0, r1;
     block_rows(a.gs, a.rpb, a.N, sys, r0, r1);
@@ -364,8 +332,113 @@ __global__ __launch_bounds__(kThreads) void k_true_residual(PcgArgs<T> a, int in
         write_partial(a.partials, 3 * S + v, a.gs, v3);
         write_partial(a.partials, 4 * S + v, a.gs, v4);
     }
-    if (!arrive_last(a.sh, gridDim.x)) return;
-    reduce_partials(a.partials, 5 * S, a.gs, tot);
+}
+
+// ---------------------------------------------------------------- reductions
+// One block of kRedThreads threads sums the per-block partials of the kernel
+// that ran before it, in a fixed order, and updates the scalars. Kernel
+// boundaries order everything: no atomics, no inter-block waiting.
+constexpr int kRedThreads = 1024;
+
+struct RedArgs {
+    PcgScal* sc;
+    PcgShared* sh;
+    const double* partials;
+    int32_t gs;
+    int32_t S;
+    int64_t N;
+    double rtol2;
+    int32_t maxit;
+    uint32_t mask;
+    int32_t init;
+};
+
+// out[v] = sum_b partials[v * gs + b] for v < nv, in shared memory
+__device__ void reduce_rows(const double* partials, int nv, int gs, double* out) {
+    int tpv = 64;
+    while (tpv * nv > kRedThreads && tpv > 1) tpv >>= 1;
+    const int vpp = kRedThreads / tpv;
+    for (int v0 = 0; v0 < nv; v0 += vpp) {
+        const int v = v0 + threadIdx.x / tpv;
+        const int sub = threadIdx.x % tpv;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (v < nv) {
+            const double* P = partials + (int64_t)v * gs;
+            int b = sub;
+            for (; b + 3 * tpv < gs; b += 4 * tpv) {
+                s0 += P[b];
+                s1 += P[b + tpv];
+                s2 += P[b + 2 * tpv];
+                s3 += P[b + 3 * tpv];
+            }
+            for (; b < gs; b += tpv) s0 += P[b];
+        }
+        double sum = (s0 + s1) + (s2 + s3);
+        for (int off = tpv >> 1; off >= 1; off >>= 1) sum += __shfl_xor(sum, off);
+        if (sub == 0 && v < nv) out[v] = sum;
+    }
+    __syncthreads();
+}
+
+// after direction+SpMV: alpha = r.z / p.q; the new p becomes current
+__global__ __launch_bounds__(kRedThreads) void k_red_alpha(RedArgs a) {
+    __shared__ double tot[kMaxSys];
+    if (a.sh->n_active == 0) return;
+    reduce_rows(a.partials, a.S, a.gs, tot);
+    if (threadIdx.x < a.S) {
+        PcgScal& c = a.sc[threadIdx.x];
+        if (c.active) {
+            c.pq = tot[threadIdx.x];
+            c.alpha = c.pq != 0.0 ? c.rz / c.pq : 0.0;
+        } else {
+            c.alpha = 0.0;
+        }
+    }
+    if (threadIdx.x == 0) a.sh->parity ^= 1;
+}
+
+// after the update: beta, convergence flags, iteration counts
+template <bool DEFL>
+__global__ __launch_bounds__(kRedThreads) void k_red_beta(RedArgs a) {
+    __shared__ double tot[4 * kMaxSys];
+    if (a.sh->n_active == 0) return;
+    constexpr int Q = DEFL ? 4 : 2;
+    const int S = a.S;
+    reduce_rows(a.partials, Q * S, a.gs, tot);
+    if (threadIdx.x < S) {
+        PcgScal& c = a.sc[threadIdx.x];
+        if (c.active) {
+            double rzn = tot[threadIdx.x];
+            const double rrn = tot[S + threadIdx.x];
+            double cn = 0.0;
+            if (DEFL) {
+                cn = tot[2 * S + threadIdx.x] / static_cast<double>(a.N);
+                rzn -= cn * tot[3 * S + threadIdx.x];
+            }
+            c.beta = c.rz != 0.0 ? rzn / c.rz : 0.0;
+            c.rz_prev = c.rz;
+            c.rz = rzn;
+            c.c = cn;
+            c.rr = rrn;
+            c.iters += 1;
+            if (rrn <= a.rtol2 * c.bnorm2 || !(rrn == rrn)) {
+                c.active = 0;
+                c.pending = 1;
+            } else if (c.iters >= a.maxit) {
+                c.active = 0;
+            }
+        }
+    }
+    __syncthreads();
+    count_active(a.sc, a.sh, S);
+}
+// after a true-residual recomputation (or the set-up of a run)
+template <bool DEFL>
+__global__ __launch_bounds__(kRedThreads) void k_red_true(RedArgs a) {
+    __shared__ double tot[5 * kMaxSys];
+    const int S = a.S;
+    const int init = a.init;
+    reduce_rows(a.partials, 5 * S, a.gs, tot);
     if (threadIdx.x < S && ((a.mask >> threadIdx.x) & 1u)) {
         PcgScal& c = a.sc[threadIdx.x];
         const double rrt = tot[threadIdx.x];
@@ -409,37 +482,61 @@ __global__ __launch_bounds__(kThreads) void k_true_residual(PcgArgs<T> a, int in
     count_active(a.sc, a.sh, S);
     if (threadIdx.x == 0) {
         if (init) a.sh->parity = 0;
-        a.sh->counter = 0u;
     }
 }
-
 // deflation: mean of each block of b, b <- b - mean, sc.mean = mean / delta,
-// sc.bnorm2 = ||b||^2 before projection. B = 1, one block per system.
-__global__ __launch_bounds__(kThreads) void k_deflate_rhs(double* b64, int64_t N, PcgScal* sc, double inv_delta) {
+// sc.bnorm2 = ||b||^2 before projection (B = 1). Three kernels: per-block
+// partial sums, one block finishing them in order, the subtraction.
+constexpr int kDeflBlocks = 256;
+
+__global__ __launch_bounds__(kThreads) void k_defl_partials(const double* __restrict__ b64, int64_t N,
+                                                            double* __restrict__ part) {
     __shared__ double sm[4];
-    const int sys = blockIdx.x;
-    double* b = b64 + (int64_t)sys * N;
+    const int sys = blockIdx.y;
+    const double* b = b64 + (int64_t)sys * N;
+    const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = blockIdx.x * chunk;
+    const int64_t i1 = i0 + chunk < N ? i0 + chunk : N;
     double s = 0.0, s2 = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += kThreads) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) {
         s += b[i];
         s2 += b[i] * b[i];
     }
     s = block_sum<1>(s, sm);
     s2 = block_sum<1>(s2, sm);
-    __shared__ double mean;
     if (threadIdx.x == 0) {
-        mean = s / static_cast<double>(N);
+        part[(sys * 2) * gridDim.x + blockIdx.x] = s;
+        part[(sys * 2 + 1) * gridDim.x + blockIdx.x] = s2;
+    }
+}
+
+__global__ void k_defl_finish(const double* __restrict__ part, int nb, int64_t N, int nsys, PcgScal* sc,
+                              double inv_delta) {
+    if (threadIdx.x != 0) return;
+    for (int sys = 0; sys < nsys; ++sys) {
+        double s = 0.0, s2 = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            s += part[(sys * 2) * nb + b];
+            s2 += part[(sys * 2 + 1) * nb + b];
+        }
+        const double mean = s / static_cast<double>(N);
         sc[sys].mean = mean * inv_delta;
+        sc[sys].c = mean;          // temporarily: the mean to subtract
         sc[sys].bnorm2 = s2;
         sc[sys].done = 0;
         sc[sys].active = 0;
         sc[sys].pending = 0;
     }
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < N; i += kThreads) b[i] -= mean;
 }
 
-// stop lanes whose true residual no longer improves (attainable accuracy reached)
+__global__ void k_defl_subtract(double* __restrict__ b64, int64_t N, const PcgScal* __restrict__ sc) {
+    const int sys = blockIdx.y;
+    const double m = sc[sys].c;
+    double* b = b64 + (int64_t)sys * N;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] -= m;
+}
+
 __global__ void k_deactivate(PcgScal* sc, int S, PcgShared* sh, uint32_t mask) {
     if (threadIdx.x != 0) return;
     int n = 0;
@@ -496,6 +593,43 @@ inline int live_iters(const PcgScal* hs, int S, const std::vector<int>& before, 
     return std::min(m, chunk);
 }
 
+template <typename T>
+RedArgs red_args(const PcgArgs<T>& a, int S, uint32_t mask = 0, int init = 0) {
+    RedArgs r{};
+    r.sc = a.sc;
+    r.sh = a.sh;
+    r.partials = a.partials;
+    r.gs = a.gs;
+    r.S = S;
+    r.N = a.N;
+    r.rtol2 = a.rtol2;
+    r.maxit = a.maxit;
+    r.mask = mask;
+    r.init = init;
+    return r;
+}
+
+// one PCG iteration: direction+SpMV, alpha, update, beta
+template <typename T, int B, bool DEFL>
+inline void launch_iteration(const PcgArgs<T>& a, dim3 grid, dim3 blk, hipStream_t st, hipEvent_t* ev) {
+    const RedArgs ra = red_args(a, a.nsys * B);
+    if (ev) (void)hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL((k_dir_spmv<T, B, DEFL>), grid, blk, 0, st, a);
+    if (ev) (void)hipEventRecord(ev[1], st);
+    hipLaunchKernelGGL(k_red_alpha, dim3(1), dim3(kRedThreads), 0, st, ra);
+    if (ev) (void)hipEventRecord(ev[2], st);
+    hipLaunchKernelGGL((k_update<T, B, DEFL>), grid, blk, 0, st, a);
+    if (ev) (void)hipEventRecord(ev[3], st);
+    hipLaunchKernelGGL(k_red_beta<DEFL>, dim3(1), dim3(kRedThreads), 0, st, ra);
+    if (ev) (void)hipEventRecord(ev[4], st);
+}
+
+template <typename T, int B, bool DEFL>
+inline void launch_true_residual(const PcgArgs<T>& a, dim3 grid, dim3 blk, hipStream_t st, int init, int has_x0) {
+    hipLaunchKernelGGL((k_true_residual<T, B, DEFL>), grid, blk, 0, st, a, init, has_x0);
+    hipLaunchKernelGGL(k_red_true<DEFL>, dim3(1), dim3(kRedThreads), 0, st, red_args(a, a.nsys * B, a.mask, init));
+}
+
 // Captured graph of `chunk` PCG iterations for this kernel configuration. The
 // capture runs on a private stream (capture is not allowed on the legacy
 // default stream); replays go to the context's stream.
@@ -512,10 +646,7 @@ qpat_status chunk_graph(qpat_ctx* c, const PcgArgs<T>& a, int chunk, dim3 grid, 
     if (!c->cap_stream) QPAT_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     QPAT_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < chunk; ++i) {
-        hipLaunchKernelGGL((k_dir_spmv<T, B, DEFL>), grid, blk, 0, c->cap_stream, a);
-        hipLaunchKernelGGL((k_update<T, B, DEFL>), grid, blk, 0, c->cap_stream, a);
-    }
+    for (int i = 0; i < chunk; ++i) launch_iteration<T, B, DEFL>(a, grid, blk, c->cap_stream, nullptr);
     QPAT_HIP(c, hipStreamEndCapture(c->cap_stream, &graph));
     hipGraphExec_t exec = nullptr;
     QPAT_HIP(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -532,10 +663,16 @@ struct Runner {
         const dim3 grid(a.gs * a.nsys), blk(kThreads);
         hipStream_t sm = c->stream;
         hipLaunchKernelGGL(k_reset_scal, dim3(1), dim3(64), 0, sm, a.sc, S, a.sh);
-        if (DEFL) hipLaunchKernelGGL(k_deflate_rhs, dim3(a.nsys), blk, 0, sm, a.b64, a.N, a.sc, a.inv_delta);
+        if (DEFL) {
+            hipLaunchKernelGGL(k_defl_partials, dim3(kDeflBlocks, a.nsys), blk, 0, sm, a.b64, a.N, a.partials);
+            hipLaunchKernelGGL(k_defl_finish, dim3(1), dim3(64), 0, sm, a.partials, kDeflBlocks, a.N, a.nsys, a.sc,
+                               a.inv_delta);
+            hipLaunchKernelGGL(k_defl_subtract, dim3(grid_for(a.N, kThreads, 4096), a.nsys), blk, 0, sm, a.b64, a.N,
+                               a.sc);
+        }
         if (!has_x0) QPAT_HIP(c, hipMemsetAsync(a.x64, 0, sizeof(double) * a.N * B * a.nsys, sm));
         a.mask = (S >= 32) ? 0xffffffffu : ((1u << S) - 1u);
-        hipLaunchKernelGGL((k_true_residual<T, B, DEFL>), grid, blk, 0, sm, a, 1, has_x0 ? 1 : 0);
+        launch_true_residual<T, B, DEFL>(a, grid, blk, sm, 1, has_x0 ? 1 : 0);
         QPAT_HIP(c, hipGetLastError());
         PcgScal* hs = c->scal_host;
         auto fetch = [&]() -> qpat_status {
@@ -558,9 +695,9 @@ struct Runner {
             for (int i = 0; i < S; ++i) any_active |= hs[i].active != 0;
             if (!any_active) break;
             const bool prof = c->prof_on;
-            if (prof && c->ev_pool.size() < (size_t)4 * chunk) {
+            if (prof && c->ev_pool.size() < (size_t)5 * chunk) {
                 size_t old = c->ev_pool.size();
-                c->ev_pool.resize((size_t)4 * chunk);
+                c->ev_pool.resize((size_t)5 * chunk);
                 for (size_t e = old; e < c->ev_pool.size(); ++e) QPAT_HIP(c, hipEventCreate(&c->ev_pool[e]));
             }
             if (!prof && c->opts.use_graphs) {
@@ -570,13 +707,8 @@ struct Runner {
                 QPAT_TRY((chunk_graph<T, B, DEFL>(c, a, chunk, grid, blk, &g)));
                 QPAT_HIP(c, hipGraphLaunch(g, sm));
             } else {
-                for (int it = 0; it < chunk; ++it) {
-                    if (prof) QPAT_HIP(c, hipEventRecord(c->ev_pool[4 * it], sm));
-                    hipLaunchKernelGGL((k_dir_spmv<T, B, DEFL>), grid, blk, 0, sm, a);
-                    if (prof) QPAT_HIP(c, hipEventRecord(c->ev_pool[4 * it + 1], sm));
-                    hipLaunchKernelGGL((k_update<T, B, DEFL>), grid, blk, 0, sm, a);
-                    if (prof) QPAT_HIP(c, hipEventRecord(c->ev_pool[4 * it + 2], sm));
-                }
+                for (int it = 0; it < chunk; ++it)
+                    launch_iteration<T, B, DEFL>(a, grid, blk, sm, prof ? &c->ev_pool[5 * it] : nullptr);
             }
             QPAT_HIP(c, hipGetLastError());
             QPAT_TRY(fetch());
@@ -585,8 +717,8 @@ struct Runner {
                 const int base = op == Op::K ? 0 : 2;
                 for (int it = 0; it < chunk; ++it) {
                     float t1 = 0.f, t2 = 0.f;
-                    QPAT_HIP(c, hipEventElapsedTime(&t1, c->ev_pool[4 * it], c->ev_pool[4 * it + 1]));
-                    QPAT_HIP(c, hipEventElapsedTime(&t2, c->ev_pool[4 * it + 1], c->ev_pool[4 * it + 2]));
+                    QPAT_HIP(c, hipEventElapsedTime(&t1, c->ev_pool[5 * it], c->ev_pool[5 * it + 1]));
+                    QPAT_HIP(c, hipEventElapsedTime(&t2, c->ev_pool[5 * it + 2], c->ev_pool[5 * it + 3]));
                     if (it >= live_iters(hs, S, iters_before, chunk)) break;
                     int lanes = 0;
                     for (int i = 0; i < S; ++i) lanes += (hs[i].iters - iters_before[i]) > it;
@@ -615,7 +747,7 @@ struct Runner {
                 }();
                 a.mask = mask;
                 if (mixed) hipLaunchKernelGGL((k_fold<T, B>), grid, blk, 0, sm, a);
-                hipLaunchKernelGGL((k_true_residual<T, B, DEFL>), grid, blk, 0, sm, a, 0, 0);
+                launch_true_residual<T, B, DEFL>(a, grid, blk, sm, 0, 0);
                 QPAT_HIP(c, hipGetLastError());
                 QPAT_TRY(fetch());
                 // a confirmation that failed without halving the best true residual
@@ -692,18 +824,60 @@ qpat_status dispatch_B(qpat_ctx* c, Op op, int B, PcgArgs<T>& a, double rtol, So
     }
 }
 
+template <typename T, int B, bool DEFL>
+int occupancy_of() {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_dir_spmv<T, B, DEFL>),
+                                                     kThreads, 0) != hipSuccess)
+        blocks = 4;
+    return blocks;
+}
+
+// resident blocks of the direction+SpMV kernel over the whole device (cached)
+int resident_blocks(qpat_ctx* c, bool defl, bool fp64, int B) {
+    const int key = (defl ? 100 : 0) + (fp64 ? 50 : 0) + B;
+    auto it = c->occupancy.find(key);
+    if (it != c->occupancy.end()) return it->second;
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) cus = 256;
+    int per_cu = 4;
+    if (defl) per_cu = occupancy_of<double, 1, true>();
+    else if (fp64) {
+        switch (B) {
+            case 1: per_cu = occupancy_of<double, 1, false>(); break;
+            case 2: per_cu = occupancy_of<double, 2, false>(); break;
+            case 4: per_cu = occupancy_of<double, 4, false>(); break;
+            case 8: per_cu = occupancy_of<double, 8, false>(); break;
+            default: per_cu = occupancy_of<double, 16, false>(); break;
+        }
+    } else {
+        switch (B) {
+            case 1: per_cu = occupancy_of<float, 1, false>(); break;
+            case 2: per_cu = occupancy_of<float, 2, false>(); break;
+            case 4: per_cu = occupancy_of<float, 4, false>(); break;
+            case 8: per_cu = occupancy_of<float, 8, false>(); break;
+            default: per_cu = occupancy_of<float, 16, false>(); break;
+        }
+    }
+    const int r = std::max(per_cu, 1) * cus;
+    c->occupancy[key] = r;
+    return r;
+}
+
 template <typename T>
 PcgArgs<T> make_args(qpat_ctx* c, Op op, int B) {
     PcgArgs<T> a{};
     a.s = c->sell;
     a.N = c->N;
     a.nsys = op == Op::Prior ? 2 : 1;
-    // blocks per system: about 4 per CU over the device, multiple of 8
+    // one resident wave of blocks: occupancy of the direction+SpMV kernel times
+    // the compute units, split over the systems, a multiple of 8 (XCD mapping)
     const int64_t rows_per_pass = kThreads / B;
     int64_t want = (c->N + rows_per_pass - 1) / rows_per_pass;
-    int64_t cap = op == Op::Prior ? 512 : 1024;
-    int64_t gs = std::min(want, cap);
+    int64_t cap = resident_blocks(c, op == Op::Prior, std::is_same<T, double>::value, B) / a.nsys;
+    int64_t gs = std::min(want, std::max<int64_t>(cap, 8));
     gs = ((gs + 7) / 8) * 8;
+    gs = std::min<int64_t>(gs, kMaxBlocks);   // size of the partial-sum buffer
     int64_t rpb = (c->N + gs - 1) / gs;
     rpb = ((rpb + kSlice - 1) / kSlice) * kSlice;
     a.gs = static_cast<int32_t>(gs);

@@ -185,6 +185,9 @@ struct qpat_ctx {
     // learned initial guess (conv net on the node lattice)
     qpat::GuessNet* guess = nullptr;
 
+    // resident blocks per kernel configuration (occupancy x compute units)
+    std::map<int, int> occupancy;
+
     // captured graphs of PCG iteration chunks, keyed by kernel configuration
     hipStream_t cap_stream = nullptr;
     std::map<std::string, hipGraphExec_t> graphs;
@@ -263,7 +266,7 @@ qpat_status vjp_core(qpat_ctx* c, const double* t, int mode, double* out, SolveS
 qpat_status guess_setup(qpat_ctx* c, int nx, int ny, int nz);
 qpat_status guess_set_params(qpat_ctx* c, const float* p);
 qpat_status guess_get_params(qpat_ctx* c, float* p);
-qpat_status guess_eval_raw(qpat_ctx* c, const float* in, float* out, int all_channels);
+qpat_status guess_eval_raw(qpat_ctx* c, const float* in, float* out);
 qpat_status guess_grad_raw(qpat_ctx* c, const float* in, const float* target, float* grad, double* loss);
 qpat_status guess_train_raw(qpat_ctx* c, const float* in, const float* target, float lr, double* loss);
 qpat_status guess_train(qpat_ctx* c, const double* kappa, const double* mu, double k0, double m0,

@@ -83,12 +83,15 @@ def test_prior_apply_on_sampled_rows(big):
     for part in (rows, N + rows):
         err = np.abs(yy[part] - ref[part]).max() / np.abs(ref[part]).max()
         assert err <= 1e-13
+    # M_delta^{-1} at the default prior_rtol (1e-8: with delta = 1e-6 and
+    # Perona-Malik diffusivities ~1e-5 across the phantom's edges FP64 PCG
+    # attains ~4e-9 at this size)
     r = torch.empty_like(y)
     pinfo = ctx.prior_solve(dev(x), r)
-    assert pinfo["relres_max"] <= 1e-10
+    assert pinfo["relres_max"] <= 1e-8
     # sampled residual of the solve
     res = (x - Md @ host(r))[np.concatenate([rows, N + rows])]
-    assert np.abs(res).max() <= 1e-10 * np.linalg.norm(x)
+    assert np.abs(res).max() <= 1e-8 * np.linalg.norm(x)
 
 
 def test_adjoint_identity_and_central_differences(big):
