@@ -66,6 +66,11 @@ typedef struct {
     double  ru_delta;       /* mixed precision: recompute the FP64 residual whenever the
                                recursive one fell by this factor since the last recompute.   */
     int32_t use_graphs;     /* 1: replay chunks of PCG iterations as captured HIP graphs.     */
+    int32_t operator_format;/* 1: on meshes whose node numbering is a lattice (x fastest, every
+                               matrix neighbour at most one lattice step away per axis, e.g.
+                               the Kuhn voxel meshes of Sec. 5) the PCG products use the
+                               stencil form (diagonal + upper offsets, LDS-tiled).
+                               0: sliced ELL on every mesh. Same results up to rounding.     */
 } qpat_opts;
 
 typedef struct {
@@ -78,7 +83,7 @@ typedef struct {
 
 /* Fill *opts with the defaults: FP64, block 16, rtol 1e-10, maxit 20000,
  * prior_rtol 1e-8, deflation on, reorthogonalisation on with 64 steps,
- * ru_delta 1e-3, graphs on. */
+ * ru_delta 1e-3, graphs on, stencil form on lattice meshes. */
 void qpat_default_opts(qpat_opts* opts);
 
 /* Create a context for a tetrahedral P1 mesh (Sec. 3: piecewise linear
@@ -190,6 +195,12 @@ typedef struct {
 } qpat_kstat;
 qpat_status qpat_profile(qpat_ctx* ctx, int32_t enable);
 qpat_status qpat_profile_read(const qpat_ctx* ctx, qpat_kstat out[4]);
+
+/* Storage of the PCG operators. out[0] = 1 when the node numbering was
+ * recognised as a lattice (the stencil form exists), out[1..3] = nx, ny, nz,
+ * out[4] = stored stencil arrays per operator (diagonal + upper offsets),
+ * out[5] = padded sliced-ELL entries. out: 6 int64 (host). */
+qpat_status qpat_operator_layout(const qpat_ctx* ctx, int64_t out[6]);
 
 /* ---- Learned initial guess of the forward solves (extension; needs a
  * structured node lattice: node (x, y, z) has index x + nx (y + ny z)).

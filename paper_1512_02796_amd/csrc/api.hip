@@ -60,6 +60,8 @@ qpat_status check_opts(qpat_ctx* c, const qpat_opts* o) {
     if (o->lsqr_max_steps < 1) return fail(c, QPAT_ERR_ARG, "lsqr_max_steps must be >= 1");
     if (!(o->ru_delta > 0.0 && o->ru_delta < 1.0)) return fail(c, QPAT_ERR_ARG, "ru_delta must be in (0, 1)");
     if (o->use_graphs != 0 && o->use_graphs != 1) return fail(c, QPAT_ERR_ARG, "use_graphs must be 0 or 1");
+    if (o->operator_format != 0 && o->operator_format != 1)
+        return fail(c, QPAT_ERR_ARG, "operator_format must be 0 or 1");
     return QPAT_OK;
 }
 
@@ -172,6 +174,7 @@ void qpat_default_opts(qpat_opts* o) {
     o->lsqr_max_steps = 64;
     o->ru_delta = 1e-3;
     o->use_graphs = 1;
+    o->operator_format = 1;
 }
 
 const char* qpat_version(void) { return "qpat 0.1 (gfx950)"; }
@@ -197,6 +200,7 @@ qpat_status qpat_setup_mesh(qpat_ctx** out, int64_t N, const double* coords, int
     c->Fb = F_b;
     QPAT_TRY(mesh_build(c, coords, tets, bfaces));
     QPAT_TRY(alloc_core(c));
+    QPAT_TRY(lattice_setup(c, coords));
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
     return QPAT_OK;
 }
@@ -248,6 +252,7 @@ qpat_status qpat_set_sources(qpat_ctx* c, int32_t n_ill, const double* phi_src) 
 static qpat_status forward_common(qpat_ctx* c, double* phi_out, double* h_out, qpat_info* info,
                                   const double* x0 = nullptr) {
     QPAT_TRY(assemble_K(c));
+    QPAT_TRY(lattice_convert(c, Op::K));
     SolveStats st;
     c->have_forward = false;
     c->lsqr_ready = false;
@@ -424,6 +429,7 @@ qpat_status qpat_prior_setup(qpat_ctx* c, const double* kt, const double* mt, do
     if (!kt || !mt || !(T > 0.0) || !(b_over_a > 0.0) || !(delta > 0.0))
         return fail(c, QPAT_ERR_ARG, "prior_setup: need kt, mt and T, b_over_a, delta > 0");
     QPAT_TRY(assemble_prior(c, kt, mt, T, b_over_a, delta));
+    QPAT_TRY(lattice_convert(c, Op::Prior));
     c->delta = delta;
     c->have_prior = true;
     c->lsqr_ready = false;
@@ -508,6 +514,17 @@ qpat_status qpat_profile(qpat_ctx* c, int32_t enable) {
 qpat_status qpat_profile_read(const qpat_ctx* c, qpat_kstat out[4]) {
     if (!c || !out) return QPAT_ERR_ARG;
     for (int i = 0; i < 4; ++i) out[i] = c->prof[i];
+    return QPAT_OK;
+}
+
+qpat_status qpat_operator_layout(const qpat_ctx* c, int64_t out[6]) {
+    if (!c || !out) return QPAT_ERR_ARG;
+    out[0] = c->lat.on ? 1 : 0;
+    out[1] = c->lat.nx;
+    out[2] = c->lat.ny;
+    out[3] = c->lat.nz;
+    out[4] = c->lat.on ? c->lat.m + 1 : 0;
+    out[5] = c->sell.len;
     return QPAT_OK;
 }
 

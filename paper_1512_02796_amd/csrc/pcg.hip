@@ -57,6 +57,21 @@ struct PcgArgs {
     double inv_delta;
 };
 
+// Tiling of the stencil direction+SpMV kernel (lattice meshes). A work item
+// is a tile of tx x ty lattice columns over a chunk of zc planes; a block
+// sweeps the chunk plane by plane with the direction vector of three planes
+// (plus a one-node halo) in LDS.
+template <typename T>
+struct StArgs {
+    bool on;
+    int32_t nx, ny, nz, m;
+    const int4* tab;     // [m] upper offsets: dx, dy, dz, dx + nx (dy + ny dz)
+    const T* U;          // [nsys][m+1][N]
+    int32_t tx, ty, hx, hy;
+    int32_t tiles_x, tiles_y, zc, items;
+    size_t lds;
+};
+
 __device__ __forceinline__ double ld_acq(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -162,6 +177,255 @@ __global__ __launch_bounds__(kThreads) void k_dir_spmv(PcgArgs<T> a) {
     }
     double bs = block_sum<B>(acc, sm);
     if (threadIdx.x < B) write_partial(a.partials, sys * B + threadIdx.x, a.gs, bs);
+}
+
+// Direction + SpMV on the lattice form. Same arithmetic as k_dir_spmv: the
+// direction p = D^{-1} r - c + beta p_old is formed once per node (and halo
+// node) as its plane enters a three-plane ring in LDS, then every output node
+// of the middle plane gathers its neighbours from LDS:
+//   q_i = U_0[i] p_i + sum_j ( U_j[i] p_{i+u_j} + U_j[i-u_j] p_{i-u_j} ).
+// With NPU > 0 the stored diagonals of planes z-1 and z are staged in LDS as
+// well (coalesced loads; B >= 8 right-hand sides share every value), else
+// they are read from global memory per node. The loads of plane z+2 are in
+// flight during the arithmetic of plane z. Element offsets are 32-bit (the
+// lattice form is only enabled when N (m+1) and N B fit).
+constexpr int kStThreads = 512;
+
+// Raw buffer access with 32-bit byte offsets: one vector register per
+// address, and offsets at or past the resource's size read 0 / are dropped
+// (the hardware range check), which handles halo and tile edges.
+constexpr uint32_t kOut = 0x80000000u;   // an offset past every resource used here
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), static_cast<short>(0), static_cast<int>(bytes),
+                                             0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t b, uint32_t off) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(b, off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(b, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t b, uint32_t off, T v) {
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b, off, 0, 0);
+    else
+    {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b, off, 0, 0);
+    }
+}
+
+template <int B, int NT>
+__device__ __forceinline__ double block_sum_n(double v, double* sm) {
+#pragma unroll
+    for (int off = 32; off >= B; off >>= 1) v += __shfl_xor(v, off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < B) sm[wave * B + lane] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < B)
+        for (int w = 0; w < NT / 64; ++w) t += sm[w * B + threadIdx.x];
+    __syncthreads();
+    return t;
+}
+
+template <typename T, int B, bool DEFL, int NPF, int NPU>
+__global__ __launch_bounds__(kStThreads) void k_dir_stencil(PcgArgs<T> a, StArgs<T> g) {
+    constexpr bool STAGE = NPU > 0;
+    constexpr int NU = NPU > 0 ? NPU : 1;
+    constexpr int NT = kStThreads;
+    constexpr int RS = NPF * NT;   // ring slot stride (>= halo nodes x B); the tail is padding
+    constexpr int US = NU * NT;    // staged-diagonal slot stride (>= (m+1) x halo nodes)
+    constexpr uint32_t SZ = sizeof(T);
+    extern __shared__ __align__(16) unsigned char st_smem[];
+    __shared__ double sm[(NT / 64) * kMaxRhs];
+    if (a.sh->n_active == 0) return;
+    const int32_t sys = blockIdx.x / a.gs, local = blockIdx.x % a.gs;
+    const int tid = threadIdx.x;
+    const int k = tid % B;
+    const int par = a.sh->parity;
+    const PcgScal scl = a.sc[sys * B + k];
+    const bool act = scl.active != 0;
+    const T beta = static_cast<T>(scl.beta);
+    const T cc = DEFL ? static_cast<T>(scl.c) : T(0);
+    const int64_t N = a.N;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, m = g.m;
+    const int hx = g.hx, hn = g.hx * g.hy, tx = g.tx, ty = g.ty;
+    const int64_t nxy = (int64_t)nx * ny;
+    const uint32_t pv = static_cast<uint32_t>(nxy) * B * SZ;           // bytes of one plane of a vector
+    const uint32_t pu = static_cast<uint32_t>(m * N + nxy) * SZ;        // plane of U_0 .. U_m
+    const T* __restrict__ dinv = a.dinv + (int64_t)sys * N;
+    const T* __restrict__ r = a.r + (int64_t)sys * N * B;
+    const T* __restrict__ po = (par ? a.pb : a.pa) + (int64_t)sys * N * B;
+    T* __restrict__ pn = (par ? a.pa : a.pb) + (int64_t)sys * N * B;
+    T* __restrict__ q = a.q + (int64_t)sys * N * B;
+    const T* __restrict__ U = g.U + (int64_t)sys * (m + 1) * N;
+    T* ring = reinterpret_cast<T*>(st_smem);          // [3][RS]: [halo node][B]
+    T* ust = ring + 3 * RS;                           // [2][US]: [m+1][halo node]
+    // a plane's buffer resource; planes outside the lattice have no records,
+    // so their loads return 0 and their stores are dropped
+    auto plane = [&](const T* base, int pl, int64_t stride, uint32_t bytes) {
+        const bool in = pl >= 0 && pl < nz;
+        return rsrc(base + (in ? pl * stride : 0), in ? bytes : 0u);
+    };
+
+    // LDS position of output slot u, fixed for the launch (slots past the tile
+    // point at a valid interior position; their results are not stored)
+    int32_t oc0[NPF];
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+        const int nl = (tid + u * NT) / B;
+        oc0[u] = nl < tx * ty ? (nl / tx + 1) * hx + nl % tx + 1 : hx + 1;
+    }
+
+    // byte offset of an output node's U_0 entry from its vector-element offset
+    auto node_bytes = [&](uint32_t o) { return o == kOut ? kOut : (o - k * SZ) / B; };
+
+    T rr[NPF], pp[NPF], dd[NPF], uu[NU];
+    bool fz = false;
+    double acc = 0.0;
+
+    const int32_t xcd = local & 7, slot = local >> 3, per = a.gs >> 3;
+    const int32_t wx = (g.items + 7) / 8;
+    const int32_t it_end = min(g.items, (xcd + 1) * wx);
+    const int32_t tiles = g.tiles_x * g.tiles_y;
+    for (int32_t item = xcd * wx + slot; item < it_end; item += per) {
+        const int32_t ch = item / tiles, t2 = item % tiles;
+        const int32_t x0 = (t2 % g.tiles_x) * tx, y0 = (t2 / g.tiles_x) * ty;
+        const int32_t zb = ch * g.zc, ze = min(zb + g.zc, nz);
+        // byte offsets inside a plane of this tile's slots (kOut: outside the
+        // lattice or the tile -- past every resource's records)
+        uint32_t fo[NPF], fd[NPF], oo[NPF], uo[NU];
+        int32_t oxy[NPF];
+#pragma unroll
+        for (int u = 0; u < NPF; ++u) {
+            const int nl = (tid + u * NT) / B;
+            const int gx = x0 - 1 + nl % hx, gy = y0 - 1 + nl / hx;
+            const bool fin = nl < hn && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            fo[u] = fin ? (static_cast<uint32_t>(gy * nx + gx) * B + k) * SZ : kOut;
+            fd[u] = fin ? static_cast<uint32_t>(gy * nx + gx) * SZ : kOut;
+            const int ox = x0 + nl % tx, oy = y0 + nl / tx;
+            const bool oin = nl < tx * ty && ox < nx && oy < ny;
+            oo[u] = oin ? (static_cast<uint32_t>(oy * nx + ox) * B + k) * SZ : kOut;
+            oxy[u] = oin ? (oy << 16) | ox : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int e = tid + u * NT, nl = e % hn;
+            const int gx = x0 - 1 + nl % hx, gy = y0 - 1 + nl / hx;
+            uo[u] = (STAGE && e < (m + 1) * hn && gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+                        ? static_cast<uint32_t>((e / hn) * N + gy * nx + gx) * SZ
+                        : kOut;
+        }
+
+        auto fetch = [&](int pl) {
+            fz = pl >= 0 && pl < nz;
+            const auto br = plane(r, pl, nxy * B, pv), bp = plane(po, pl, nxy * B, pv);
+            const auto bd = plane(dinv, pl, nxy, pv / B);
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) {
+                rr[u] = bload<T>(br, fo[u]);
+                pp[u] = bload<T>(bp, fo[u]);
+                dd[u] = bload<T>(bd, fd[u]);
+            }
+        };
+        auto store = [&](int sl) {
+            T* R = ring + sl * RS;
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) {
+                const T v = dd[u] * rr[u] - cc + beta * pp[u];
+                R[tid + u * NT] = (!DEFL || (fz && fo[u] != kOut)) ? v : T(0);
+            }
+        };
+        auto fetch_u = [&](int pl) {
+            const auto bu = plane(U, pl, nxy, pu);
+#pragma unroll
+            for (int u = 0; u < NU; ++u) uu[u] = bload<T>(bu, uo[u]);
+        };
+        auto store_u = [&](int sl) {
+            T* S = ust + sl * US;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) S[tid + u * NT] = uu[u];
+        };
+
+        if (STAGE) {
+            fetch_u(zb - 1);
+            store_u(0);
+        }
+        fetch(zb - 1);
+        store(0);
+        fetch(zb);
+        store(1);
+        if (STAGE) fetch_u(zb);
+        fetch(zb + 1);
+        for (int z = zb; z < ze; ++z) {
+            const int sz = (z - zb + 1) % 3, sp = (sz + 1) % 3, sl = (sz + 2) % 3;
+            const int us = (z - zb + 1) & 1;
+            store(sp);
+            if (STAGE) store_u(us);
+            __syncthreads();
+            if (z + 1 < ze) {
+                if (STAGE) fetch_u(z + 1);
+                fetch(z + 2);
+            }
+            const auto bpn = plane(pn, z, nxy * B, pv), bq = plane(q, z, nxy * B, pv);
+            if (act) {
+                const T* Rz = ring + sz * RS;
+                const auto bu = plane(U, z, nxy, pu), bul = plane(U, z - 1, nxy, pu);
+                T sum[NPF], pc[NPF];
+#pragma unroll
+                for (int u = 0; u < NPF; ++u) {
+                    pc[u] = Rz[oc0[u] * B + k];
+                    sum[u] = (STAGE ? ust[us * US + oc0[u]] : bload<T>(bu, node_bytes(oo[u]))) * pc[u];
+                }
+#pragma unroll 1
+                for (int j = 0; j < m; ++j) {
+                    const int4 t = g.tab[j];          // dx, dy, dz, dx + nx (dy + ny dz)
+                    const int d = t.y * hx + t.x;
+                    const T* Ru = ring + (t.z ? sp : sz) * RS;
+                    const T* Rl = ring + (t.z ? sl : sz) * RS;
+                    const T* Sc = ust + us * US + (j + 1) * hn;
+                    const T* Sl = ust + (t.z ? us ^ 1 : us) * US + (j + 1) * hn;
+                    // U_j of the output node, and of its lower partner (plane z - dz)
+                    const uint32_t jo = static_cast<uint32_t>((j + 1) * N) * SZ;
+                    const int32_t lw = (t.z ? (int32_t)nxy : 0) - t.w;
+#pragma unroll
+                    for (int u = 0; u < NPF; ++u) {
+                        const int c0 = oc0[u];
+                        T uj, ul;
+                        if (STAGE) {
+                            uj = Sc[c0];
+                            ul = Sl[c0 - d];
+                        } else {
+                            const uint32_t on = node_bytes(oo[u]);
+                            uj = bload<T>(bu, on == kOut ? kOut : jo + on);
+                            const int lx = (oxy[u] & 0xffff) - t.x, ly = (oxy[u] >> 16) - t.y;
+                            const bool in = oxy[u] >= 0 && lx >= 0 && lx < nx && ly >= 0 && ly < ny;
+                            ul = bload<T>(t.z ? bul : bu,
+                                          in ? jo + on + static_cast<uint32_t>(lw * (int32_t)SZ) : kOut);
+                        }
+                        sum[u] += uj * Ru[(c0 + d) * B + k] + ul * Rl[(c0 - d) * B + k];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < NPF; ++u) {
+                    bstore<T>(bpn, oo[u], pc[u]);
+                    bstore<T>(bq, oo[u], sum[u]);
+                    acc += oo[u] != kOut ? static_cast<double>(pc[u]) * static_cast<double>(sum[u]) : 0.0;
+                }
+            } else {
+                const auto bo = plane(po, z, nxy * B, pv);
+#pragma unroll
+                for (int u = 0; u < NPF; ++u) bstore<T>(bpn, oo[u], bload<T>(bo, oo[u]));
+            }
+            __syncthreads();
+        }
+    }
+    const double bs = block_sum_n<B, NT>(acc, sm);
+    if (tid < B) write_partial(a.partials, sys * B + tid, a.gs, bs);
 }
 
 template <typename T, int B, bool DEFL>
@@ -609,12 +873,32 @@ RedArgs red_args(const PcgArgs<T>& a, int S, uint32_t mask = 0, int init = 0) {
     return r;
 }
 
+// Per-thread register budgets of the stencil kernel: NPF halo-plane elements
+// (and output elements) per thread, NPU staged diagonal values per thread
+// (0: diagonals read from global memory), TX0 the preferred tile width.
+template <typename T, int B>
+struct StTile {
+    static constexpr int NPF = B == 1 ? 2 : ((B == 16 && sizeof(T) == 4) ? 6 : 4);
+    static constexpr int NPU = sizeof(T) == 4 ? (B == 16 ? 3 : (B == 8 ? 4 : 0)) : 0;
+    static constexpr int TX0 = B >= 8 ? 16 : (B == 4 ? 32 : 64);
+};
+
+template <typename T, int B, bool DEFL>
+const void* stencil_kernel() {
+    return reinterpret_cast<const void*>(&k_dir_stencil<T, B, DEFL, StTile<T, B>::NPF, StTile<T, B>::NPU>);
+}
+
 // one PCG iteration: direction+SpMV, alpha, update, beta
 template <typename T, int B, bool DEFL>
-inline void launch_iteration(const PcgArgs<T>& a, dim3 grid, dim3 blk, hipStream_t st, hipEvent_t* ev) {
+inline void launch_iteration(const PcgArgs<T>& a, const StArgs<T>& g, dim3 grid, dim3 blk, hipStream_t st,
+                             hipEvent_t* ev) {
     const RedArgs ra = red_args(a, a.nsys * B);
     if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL((k_dir_spmv<T, B, DEFL>), grid, blk, 0, st, a);
+    if (g.on)
+        hipLaunchKernelGGL((k_dir_stencil<T, B, DEFL, StTile<T, B>::NPF, StTile<T, B>::NPU>), grid,
+                           dim3(kStThreads), g.lds, st, a, g);
+    else
+        hipLaunchKernelGGL((k_dir_spmv<T, B, DEFL>), grid, blk, 0, st, a);
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(k_red_alpha, dim3(1), dim3(kRedThreads), 0, st, ra);
     if (ev) (void)hipEventRecord(ev[2], st);
@@ -634,10 +918,12 @@ inline void launch_true_residual(const PcgArgs<T>& a, dim3 grid, dim3 blk, hipSt
 // capture runs on a private stream (capture is not allowed on the legacy
 // default stream); replays go to the context's stream.
 template <typename T, int B, bool DEFL>
-qpat_status chunk_graph(qpat_ctx* c, const PcgArgs<T>& a, int chunk, dim3 grid, dim3 blk, hipGraphExec_t* out) {
-    const void* kfn = reinterpret_cast<const void*>(&k_dir_spmv<T, B, DEFL>);
+qpat_status chunk_graph(qpat_ctx* c, const PcgArgs<T>& a, const StArgs<T>& g, int chunk, dim3 grid, dim3 blk,
+                        hipGraphExec_t* out) {
+    const void* kfn = g.on ? stencil_kernel<T, B, DEFL>() : reinterpret_cast<const void*>(&k_dir_spmv<T, B, DEFL>);
     char key[256];
-    snprintf(key, sizeof key, "%p/%d/%d/%d/%.17g/%d/%d", kfn, chunk, a.gs, a.nsys, a.rtol2, a.maxit, (int)a.N);
+    snprintf(key, sizeof key, "%p/%d/%d/%d/%.17g/%d/%d/%p/%d/%d/%d/%d", kfn, chunk, a.gs, a.nsys, a.rtol2, a.maxit,
+             (int)a.N, (const void*)g.U, g.tx, g.ty, g.zc, g.items);
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
         *out = it->second;
@@ -646,7 +932,7 @@ qpat_status chunk_graph(qpat_ctx* c, const PcgArgs<T>& a, int chunk, dim3 grid, 
     if (!c->cap_stream) QPAT_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     QPAT_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < chunk; ++i) launch_iteration<T, B, DEFL>(a, grid, blk, c->cap_stream, nullptr);
+    for (int i = 0; i < chunk; ++i) launch_iteration<T, B, DEFL>(a, g, grid, blk, c->cap_stream, nullptr);
     QPAT_HIP(c, hipStreamEndCapture(c->cap_stream, &graph));
     hipGraphExec_t exec = nullptr;
     QPAT_HIP(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -656,11 +942,97 @@ qpat_status chunk_graph(qpat_ctx* c, const PcgArgs<T>& a, int chunk, dim3 grid, 
     return QPAT_OK;
 }
 
+// Tiling of the stencil kernel for this launch (g->on = false keeps the
+// sliced-ELL kernel): the largest tile that fits the register and LDS
+// budgets, then the number of z chunks that best balances the work items
+// over the blocks resident per XCD.
+template <typename T, int B, bool DEFL>
+qpat_status make_st(qpat_ctx* c, Op op, const PcgArgs<T>& a, StArgs<T>* out) {
+    StArgs<T> g{};
+    g.on = false;
+    *out = g;
+    const Lattice& L = c->lat;
+    if (!L.on || c->opts.operator_format != 1) return QPAT_OK;
+    using TL = StTile<T, B>;
+    constexpr bool stage = TL::NPU > 0;
+    const int64_t sz = sizeof(T);
+    // 32-bit byte offsets below kOut: every array the kernel addresses under 2 GiB
+    if ((int64_t)(L.m + 1) * c->N * sz >= (int64_t(1) << 31) || c->N * B * sz >= (int64_t(1) << 31)) return QPAT_OK;
+    int64_t hn_max = (int64_t)TL::NPF * kStThreads / B;
+    if (stage) hn_max = std::min<int64_t>(hn_max, (int64_t)TL::NPU * kStThreads / (L.m + 1));
+    int64_t tiles_x = (L.nx + TL::TX0 - 1) / TL::TX0;
+    int64_t tx = (L.nx + tiles_x - 1) / tiles_x;
+    if (tx + 2 > hn_max / 3) tx = hn_max / 3 - 2;
+    if (tx < 1) return QPAT_OK;
+    tiles_x = (L.nx + tx - 1) / tx;
+    tx = (L.nx + tiles_x - 1) / tiles_x;
+    int64_t ty = std::min<int64_t>(hn_max / (tx + 2) - 2, L.ny);
+    if (ty < 1) return QPAT_OK;
+    const int64_t tiles_y = (L.ny + ty - 1) / ty;
+    ty = (L.ny + tiles_y - 1) / tiles_y;
+    g.nx = L.nx;
+    g.ny = L.ny;
+    g.nz = L.nz;
+    g.m = L.m;
+    g.tab = reinterpret_cast<const int4*>(c->lat_tab);
+    g.tx = static_cast<int32_t>(tx);
+    g.ty = static_cast<int32_t>(ty);
+    g.hx = g.tx + 2;
+    g.hy = g.ty + 2;
+    g.tiles_x = static_cast<int32_t>(tiles_x);
+    g.tiles_y = static_cast<int32_t>(tiles_y);
+    g.lds = static_cast<size_t>((3 * TL::NPF + (stage ? 2 * TL::NPU : 0)) * kStThreads * sz);
+    static_assert((3 * TL::NPF + (stage ? 2 * TL::NPU : 0)) * kStThreads * sizeof(T) <= 63 * 1024,
+                  "stencil LDS budget");
+    char key[96];
+    snprintf(key, sizeof key, "st/%p/%zu", stencil_kernel<T, B, DEFL>(), g.lds);
+    int occ = 0;
+    auto it = c->st_occ.find(key);
+    if (it != c->st_occ.end()) {
+        occ = it->second;
+    } else {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, stencil_kernel<T, B, DEFL>(), kStThreads, g.lds) !=
+            hipSuccess)
+            occ = 1;
+        c->st_occ[key] = occ;
+    }
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) cus = 256;
+    const int64_t slots = (int64_t)std::max(occ, 1) * std::max(cus / 8, 1);
+    const int64_t conc = std::min<int64_t>(slots, (int64_t)(a.gs / 8) * a.nsys);
+    const int64_t tiles = tiles_x * tiles_y;
+    int64_t best = -1, best_zc = L.nz;
+    for (int64_t nch = 1; nch <= L.nz; ++nch) {
+        const int64_t zc = (L.nz + nch - 1) / nch;
+        const int64_t items = tiles * ((L.nz + zc - 1) / zc);
+        const int64_t wx = (items + 7) / 8;
+        const int64_t cost = ((wx * a.nsys + conc - 1) / conc) * (zc + 2);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_zc = zc;
+        }
+    }
+    g.zc = static_cast<int32_t>(best_zc);
+    g.items = static_cast<int32_t>(tiles * ((L.nz + best_zc - 1) / best_zc));
+    const bool is64 = std::is_same<T, double>::value;
+    if (op == Op::K)
+        g.U = is64 ? reinterpret_cast<const T*>(c->KU64) : reinterpret_cast<const T*>(c->KU32);
+    else if (is64)
+        g.U = reinterpret_cast<const T*>(c->MU64);
+    else
+        return QPAT_OK;
+    g.on = true;
+    *out = g;
+    return QPAT_OK;
+}
+
 template <typename T, int B, bool DEFL>
 struct Runner {
     static qpat_status run(qpat_ctx* c, Op op, PcgArgs<T>& a, double rtol, SolveStats* st, bool has_x0) {
         const int S = a.nsys * B;
         const dim3 grid(a.gs * a.nsys), blk(kThreads);
+        StArgs<T> g{};
+        QPAT_TRY((make_st<T, B, DEFL>(c, op, a, &g)));
         hipStream_t sm = c->stream;
         hipLaunchKernelGGL(k_reset_scal, dim3(1), dim3(64), 0, sm, a.sc, S, a.sh);
         if (DEFL) {
@@ -703,12 +1075,12 @@ struct Runner {
             if (!prof && c->opts.use_graphs) {
                 // replay a captured graph of `chunk` iterations (kernel arguments are
                 // identical from one iteration to the next: all state is on the device)
-                hipGraphExec_t g = nullptr;
-                QPAT_TRY((chunk_graph<T, B, DEFL>(c, a, chunk, grid, blk, &g)));
-                QPAT_HIP(c, hipGraphLaunch(g, sm));
+                hipGraphExec_t gx = nullptr;
+                QPAT_TRY((chunk_graph<T, B, DEFL>(c, a, g, chunk, grid, blk, &gx)));
+                QPAT_HIP(c, hipGraphLaunch(gx, sm));
             } else {
                 for (int it = 0; it < chunk; ++it)
-                    launch_iteration<T, B, DEFL>(a, grid, blk, sm, prof ? &c->ev_pool[5 * it] : nullptr);
+                    launch_iteration<T, B, DEFL>(a, g, grid, blk, sm, prof ? &c->ev_pool[5 * it] : nullptr);
             }
             QPAT_HIP(c, hipGetLastError());
             QPAT_TRY(fetch());

@@ -78,6 +78,23 @@ struct LsqrScal {
     int32_t rotated;     // 1 when the last step applied a plane rotation
 };
 
+// Lattice (stencil) form of the node-node pattern. When node i sits at
+// lattice position (i % nx, (i / nx) % ny, i / (nx ny)) and every matrix
+// neighbour differs by at most one step along each axis, a symmetric operator
+// is stored as its diagonal plus the m "upper" offsets u_1..u_m (dz > 0, or
+// dz = 0 and dy > 0, or dz = dy = 0 and dx > 0): U_j[i] = A(i, i + u_j), zero
+// where that entry is not in the pattern. Row i then reads
+//   A(i, i - u_j) = A(i - u_j, i) = U_j[i - u_j]
+// from the partner row. Arrays are [m + 1][N] per system, U_0 the diagonal.
+constexpr int kMaxUpper = 13;
+struct Lattice {
+    bool on = false;
+    int32_t nx = 0, ny = 0, nz = 0;
+    int32_t m = 0;
+    int8_t dx[kMaxUpper]{}, dy[kMaxUpper]{}, dz[kMaxUpper]{};
+    int8_t code[27]{};     // (dx+1) + 3 (dy+1) + 9 (dz+1) -> 0 diagonal, j >= 1 upper offset j, -1 otherwise
+};
+
 struct GuessNet;
 
 template <typename T>
@@ -105,6 +122,8 @@ struct qpat_ctx {
     int32_t* n2f_ptr = nullptr;    // [N+1]
     int32_t* n2f = nullptr;        // [3Fb], entry = f*3 + a
     qpat::Sell sell;
+    qpat::Lattice lat;             // stencil form, when the numbering is a lattice
+    int32_t* lat_tab = nullptr;    // [kMaxUpper][4]: dx, dy, dz, dx + nx (dy + ny dz)
 
     // linearisation point and operator
     double* kappa = nullptr;       // [N]
@@ -113,6 +132,8 @@ struct qpat_ctx {
     float* K32 = nullptr;
     double* Kdinv64 = nullptr;     // [N]
     float* Kdinv32 = nullptr;
+    double* KU64 = nullptr;        // lattice form of K, [m+1][N]
+    float* KU32 = nullptr;
     bool have_forward = false;
 
     // prior
@@ -120,6 +141,7 @@ struct qpat_ctx {
     float* M32 = nullptr;
     double* Mdinv64 = nullptr;     // [2][N]  1/(diag + delta)
     float* Mdinv32 = nullptr;
+    double* MU64 = nullptr;        // lattice form, [2][m+1][N]
     double delta = 0.0;
     bool have_prior = false;
 
@@ -187,6 +209,7 @@ struct qpat_ctx {
 
     // resident blocks per kernel configuration (occupancy x compute units)
     std::map<int, int> occupancy;
+    std::map<std::string, int> st_occ;   // stencil kernel, keyed by kernel and LDS size
 
     // captured graphs of PCG iteration chunks, keyed by kernel configuration
     hipStream_t cap_stream = nullptr;
@@ -243,6 +266,12 @@ qpat_status check_positive(qpat_ctx* c, const double* a, int64_t n, bool* ok);
 // ---- pcg.hip
 // Which operator a solve uses.
 enum class Op { K, Prior };
+
+// ---- lattice.hip
+// Detects the lattice numbering after mesh_build; allocates the stencil arrays.
+qpat_status lattice_setup(qpat_ctx* c, const double* coords);
+// Copies the assembled sliced-ELL operator into its stencil arrays.
+qpat_status lattice_convert(qpat_ctx* c, Op op);
 struct SolveStats {
     int32_t n_solves = 0, iters_max = 0, updates = 0;
     int64_t iters_sum = 0;

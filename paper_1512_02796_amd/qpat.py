@@ -31,7 +31,8 @@ class Opts(ctypes.Structure):
                 ("pcg_rtol", ctypes.c_double), ("pcg_maxit", ctypes.c_int32),
                 ("prior_rtol", ctypes.c_double), ("prior_deflate", ctypes.c_int32),
                 ("lsqr_reorth", ctypes.c_int32), ("lsqr_max_steps", ctypes.c_int32),
-                ("ru_delta", ctypes.c_double), ("use_graphs", ctypes.c_int32)]
+                ("ru_delta", ctypes.c_double), ("use_graphs", ctypes.c_int32),
+                ("operator_format", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -83,6 +84,7 @@ SIGNATURES = {
     "qpat_lsqr_residual": (_D, [_P]),
     "qpat_profile": (_S, [_P, _I32]),
     "qpat_profile_read": (_S, [_P, ctypes.POINTER(KStat)]),
+    "qpat_operator_layout": (_S, [_P, ctypes.POINTER(_I64)]),
     "qpat_forward_x0": (_S, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_guess_setup": (_S, [_P, _I32, _I32, _I32]),
     "qpat_guess_set_params": (_S, [_P, _P]),
@@ -345,6 +347,12 @@ class Context:
         arr = (KStat * 4)()
         self._check(_lib.qpat_profile_read(self._h, arr))
         return {KSTAT_NAMES[i]: arr[i].as_dict() for i in range(4)}
+
+    def operator_layout(self):
+        arr = (_I64 * 6)()
+        self._check(_lib.qpat_operator_layout(self._h, arr))
+        return {"lattice": bool(arr[0]), "nx": arr[1], "ny": arr[2], "nz": arr[3], "stencil_arrays": arr[4],
+                "sell_len": arr[5]}
 
 
 def version():

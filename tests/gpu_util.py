@@ -33,6 +33,11 @@ class GpuProblem:
         self.kappa = dev(self.P.kappa)
         self.mu = dev(self.P.mu)
 
+    @staticmethod
+    def opts(**kw):
+        from paper_1512_02796_amd import qpat
+        return qpat.default_opts(**kw)
+
     def forward(self):
         phi = torch.empty(self.n_ill * self.N, dtype=torch.float64, device="cuda")
         h = torch.empty_like(phi)

@@ -1,0 +1,144 @@
+"""The lattice (stencil) form of the PCG operators against the sliced-ELL form
+and the FP64 oracle.
+
+On a node numbering that is a lattice the library applies K and M_delta in
+the stencil form (diagonal + upper offsets, LDS-tiled); operator_format = 0
+forces the sliced-ELL kernels. Both solve the same systems to the same true
+residual, so their solutions agree to the solver tolerance. Boxes with
+unequal sides and odd sizes put ragged tiles on every face of the tiling.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import GpuProblem, oracle_of, dev, host, rel, need_gpu
+from oracle import fem
+from oracle.jacobian import Linearisation
+
+pytestmark = pytest.mark.gpu
+
+_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def kuhn_box(nx, ny, nz, h=1.0):
+    """Kuhn mesh of nx x ny x nz voxels of side h, nodes numbered x fastest;
+    boundary triangles are the tetrahedron faces that occur once."""
+    mx, my, mz = nx + 1, ny + 1, nz + 1
+    zz, yy, xx = np.meshgrid(np.arange(mz), np.arange(my), np.arange(mx), indexing="ij")
+    coords = h * np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1).astype(np.float64)
+    step = np.array([1, mx, mx * my])
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    v0 = (ii + mx * (jj + my * kk)).ravel()
+    tets = np.empty((v0.size, 6, 4), dtype=np.int64)
+    for p, (a, b, _) in enumerate(_PERMS):
+        tets[:, p, 0] = v0
+        tets[:, p, 1] = v0 + step[a]
+        tets[:, p, 2] = v0 + step[a] + step[b]
+        tets[:, p, 3] = v0 + step.sum()
+    tets = tets.reshape(-1, 4)
+    faces = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]], tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]])
+    key = np.sort(faces, axis=1)
+    _, idx, cnt = np.unique(key, axis=0, return_index=True, return_counts=True)
+    bfaces = faces[idx[cnt == 1]]
+    return coords, tets.astype(np.int32), bfaces.astype(np.int32)
+
+
+def box_problem(nx, ny, nz, n_ill, seed):
+    coords, tets, bfaces = kuhn_box(nx, ny, nz)
+    rng = np.random.default_rng(seed)
+    N = coords.shape[0]
+    kappa = 0.3 * np.exp(0.3 * rng.standard_normal(N))
+    mu = 0.02 * np.exp(0.3 * rng.standard_normal(N))
+    src = rng.uniform(0.0, 1.0, size=(n_ill, bfaces.shape[0], 3))
+    return coords, tets, bfaces, kappa, mu, src
+
+
+def solve(coords, tets, bfaces, kappa, mu, src, **o):
+    from paper_1512_02796_amd import qpat
+    ctx = qpat.Context(dev(coords), dev(tets, torch.int32), dev(bfaces, torch.int32),
+                       opts=qpat.default_opts(**o))
+    ctx.set_sources(dev(src))
+    phi = torch.empty(src.shape[0] * coords.shape[0], dtype=torch.float64, device="cuda")
+    info = ctx.forward(dev(kappa), dev(mu), phi)
+    return ctx, host(phi).reshape(src.shape[0], -1), info
+
+
+def test_layout_of_kuhn_cube():
+    G = GpuProblem("T8")
+    lay = G.ctx.operator_layout()
+    assert lay["lattice"] and (lay["nx"], lay["ny"], lay["nz"]) == (9, 9, 9)
+    assert lay["stencil_arrays"] == 8          # diagonal + 7 upper Kuhn offsets
+    assert lay["sell_len"] >= 15 * 9 ** 3 - 9 ** 3
+
+
+@pytest.mark.parametrize("dims", [(13, 7, 5), (5, 11, 17), (30, 3, 9)])
+@pytest.mark.parametrize("block,precision", [(1, 0), (2, 0), (4, 0), (8, 0), (16, 0), (4, 1), (8, 1), (16, 1)])
+def test_stencil_matches_oracle_on_boxes(dims, block, precision):
+    n_ill = 16
+    coords, tets, bfaces, kappa, mu, src = box_problem(*dims, n_ill, seed=sum(dims))
+    g = fem.geometry(coords, tets, bfaces)
+    lin = Linearisation(g, kappa, mu, src)
+    ctx, phi, info = solve(coords, tets, bfaces, kappa, mu, src, max_rhs_block=block, precision=precision,
+                           pcg_rtol=1e-12)
+    lay = ctx.operator_layout()
+    assert lay["lattice"] and (lay["nx"], lay["ny"], lay["nz"]) == tuple(d + 1 for d in dims)
+    tol = 1e-10 if precision == 0 else 1e-6
+    assert rel(phi, lin.phi) <= tol, info
+    assert info["relres_max"] <= 1e-12
+
+
+@pytest.mark.parametrize("block,precision", [(1, 0), (16, 0), (16, 1), (8, 1)])
+def test_stencil_and_sell_agree(block, precision):
+    G1 = GpuProblem("T24", GpuProblem.opts(max_rhs_block=block, precision=precision, pcg_rtol=1e-12))
+    G0 = GpuProblem("T24", GpuProblem.opts(max_rhs_block=block, precision=precision, pcg_rtol=1e-12,
+                                           operator_format=0))
+    phi1, _, i1 = G1.forward()
+    phi0, _, i0 = G0.forward()
+    tol = 1e-10 if precision == 0 else 1e-6
+    assert rel(host(phi1), host(phi0)) <= tol
+    # the same Krylov iteration up to rounding: iteration counts close (FP32
+    # rounding moves the reliable-update points of the mixed solves)
+    slack = max(3, i0["iters_max"] // 50) if precision == 0 else max(5, i0["iters_max"] // 5)
+    assert abs(i1["iters_max"] - i0["iters_max"]) <= slack, (i1, i0)
+
+
+@pytest.mark.parametrize("deflate", [1, 0])
+def test_prior_solve_stencil_and_sell_agree(deflate):
+    from qpat_inputs import make_problem
+    P = make_problem("T24")
+    kt = np.log(P.kappa / P.kappa0)
+    mt = np.log(P.mu / P.mu0)
+    rng = np.random.default_rng(7)
+    p = rng.standard_normal(2 * P.mesh.N)
+    # without deflation the delta-eigenvector limits the attainable residual
+    # (about 1e-10 here), hence the looser stopping rule
+    rtol = 1e-11 if deflate else 1e-9
+    outs = []
+    for fmt in (1, 0):
+        G = GpuProblem("T24", GpuProblem.opts(operator_format=fmt, prior_deflate=deflate, prior_rtol=rtol))
+        G.ctx.prior_setup(dev(kt), dev(mt))
+        out = torch.empty(2 * P.mesh.N, dtype=torch.float64, device="cuda")
+        info = G.ctx.prior_solve(dev(p), out)
+        assert info["relres_max"] <= rtol
+        outs.append(host(out))
+    assert rel(outs[0], outs[1]) <= (1e-8 if deflate else 1e-6)
+
+
+def test_permuted_numbering_uses_sell_and_matches():
+    """A shuffled node numbering is not a lattice: the sliced-ELL path runs
+    and the fluence is the same field, renumbered."""
+    G = GpuProblem("T8", GpuProblem.opts(pcg_rtol=1e-12))
+    phi, _, _ = G.forward()
+    m = G.P.mesh
+    perm = np.random.default_rng(3).permutation(m.N)       # new id of old node i
+    inv = np.argsort(perm)
+    coords = m.coords[inv]
+    ctx, phi_p, info = solve(coords, perm[m.tets].astype(np.int32), perm[m.bfaces].astype(np.int32),
+                             G.P.kappa[inv], G.P.mu[inv], G.P.phi_src, pcg_rtol=1e-12)
+    assert not ctx.operator_layout()["lattice"]
+    assert rel(phi_p[:, perm], host(phi)) <= 1e-10
