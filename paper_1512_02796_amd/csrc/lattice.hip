@@ -69,13 +69,13 @@ __global__ void k_offsets(Sell s, int64_t N, int32_t nx, int32_t ny, uint32_t* o
     }
 }
 
-// U[sys][code[offset]][i] = A_sys(i, col) for the diagonal and upper entries of row i
+// U[sys][i][code[offset]] = A_sys(i, col) for the diagonal and upper entries of row i
 __global__ void k_to_lattice(Sell s, int64_t N, Lattice lat, const double* __restrict__ vals, int64_t vals_stride,
                              double* __restrict__ u64, float* __restrict__ u32) {
     const int32_t sys = blockIdx.y;
     const double* __restrict__ v = vals + sys * vals_stride;
     const int64_t nxy = (int64_t)lat.nx * lat.ny;
-    const int64_t ustride = (int64_t)(lat.m + 1) * N;
+    const int64_t M1 = lat.m + 1;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t ix = i % lat.nx, iy = (i / lat.nx) % lat.ny, iz = i / nxy;
         const int32_t base = s.slice_ptr[i / kSlice] + static_cast<int32_t>(i % kSlice);
@@ -86,7 +86,7 @@ __global__ void k_to_lattice(Sell s, int64_t N, Lattice lat, const double* __res
             const int64_t dx = col % lat.nx - ix, dy = (col / lat.nx) % lat.ny - iy, dz = col / nxy - iz;
             const int c = lat.code[(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)];
             if (c < 0) continue;
-            const int64_t at = sys * ustride + (int64_t)c * N + i;
+            const int64_t at = (sys * N + i) * M1 + c;   // [sys][node][m+1]
             if (u64) u64[at] = v[e];
             if (u32) u32[at] = static_cast<float>(v[e]);
         }

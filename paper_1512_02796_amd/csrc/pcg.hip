@@ -64,12 +64,12 @@ struct PcgArgs {
 template <typename T>
 struct StArgs {
     bool on;
+    bool kuhn;           // the Kuhn offsets: the kernel specialised on them
     int32_t nx, ny, nz, m;
     const int4* tab;     // [m] upper offsets: dx, dy, dz, dx + nx (dy + ny dz)
-    const T* U;          // [nsys][m+1][N]
-    int32_t tx, ty, hx, hy;
+    const T* U;          // [nsys][N][m+1]
+    int32_t hx, hy;      // halo'd tile: (hx - 2) x (hy - 2) output columns
     int32_t tiles_x, tiles_y, zc, items;
-    size_t lds;
 };
 
 __device__ __forceinline__ double ld_acq(const double* p) {
@@ -232,13 +232,22 @@ __device__ __forceinline__ double block_sum_n(double v, double* sm) {
     return t;
 }
 
-template <typename T, int B, bool DEFL, int NPF, int NPU>
-__global__ __launch_bounds__(kStThreads) void k_dir_stencil(PcgArgs<T> a, StArgs<T> g) {
-    constexpr bool STAGE = NPU > 0;
-    constexpr int NU = NPU > 0 ? NPU : 1;
+// upper offsets of the Kuhn split along the (1,1,1) diagonal, in the order the
+// lattice setup numbers them (ascending (dx+1) + 3 (dy+1) + 9 (dz+1))
+constexpr int kKuhnM = 7;
+constexpr int kKdx[kKuhnM] = {1, 0, 1, 0, 1, 0, 1};
+constexpr int kKdy[kKuhnM] = {0, 1, 1, 0, 0, 1, 1};
+constexpr int kKdz[kKuhnM] = {0, 0, 0, 1, 1, 1, 1};
+
+// HXC > 0: the Kuhn offsets above and a halo'd tile width of HXC, both known
+// at compile time, so every LDS offset of the gather is an immediate.
+// HXC = 0: any lattice stencil (offsets from g.tab, tile width g.hx).
+template <typename T, int B, bool DEFL, int NPF, int NU, int HXC>
+__global__ __launch_bounds__(kStThreads, 4) void k_dir_stencil(PcgArgs<T> a, StArgs<T> g) {
+    constexpr bool KUHN = HXC > 0;
     constexpr int NT = kStThreads;
     constexpr int RS = NPF * NT;   // ring slot stride (>= halo nodes x B); the tail is padding
-    constexpr int US = NU * NT;    // staged-diagonal slot stride (>= (m+1) x halo nodes)
+    constexpr int US = NU * NT;    // staged-diagonal slot stride (>= halo nodes x (m+1))
     constexpr uint32_t SZ = sizeof(T);
     extern __shared__ __align__(16) unsigned char st_smem[];
     __shared__ double sm[(NT / 64) * kMaxRhs];
@@ -252,19 +261,22 @@ __global__ __launch_bounds__(kStThreads) void k_dir_stencil(PcgArgs<T> a, StArgs
     const T beta = static_cast<T>(scl.beta);
     const T cc = DEFL ? static_cast<T>(scl.c) : T(0);
     const int64_t N = a.N;
-    const int nx = g.nx, ny = g.ny, nz = g.nz, m = g.m;
-    const int hx = g.hx, hn = g.hx * g.hy, tx = g.tx, ty = g.ty;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int m = KUHN ? kKuhnM : g.m;
+    const int M1 = m + 1;
+    const int hx = KUHN ? HXC : g.hx;
+    const int hn = hx * g.hy, tx = hx - 2, ty = g.hy - 2;
     const int64_t nxy = (int64_t)nx * ny;
     const uint32_t pv = static_cast<uint32_t>(nxy) * B * SZ;           // bytes of one plane of a vector
-    const uint32_t pu = static_cast<uint32_t>(m * N + nxy) * SZ;        // plane of U_0 .. U_m
+    const uint32_t pu = static_cast<uint32_t>(nxy) * M1 * SZ;          // one plane of the stencil arrays
     const T* __restrict__ dinv = a.dinv + (int64_t)sys * N;
     const T* __restrict__ r = a.r + (int64_t)sys * N * B;
     const T* __restrict__ po = (par ? a.pb : a.pa) + (int64_t)sys * N * B;
     T* __restrict__ pn = (par ? a.pa : a.pb) + (int64_t)sys * N * B;
     T* __restrict__ q = a.q + (int64_t)sys * N * B;
-    const T* __restrict__ U = g.U + (int64_t)sys * (m + 1) * N;
+    const T* __restrict__ U = g.U + (int64_t)sys * M1 * N;
     T* ring = reinterpret_cast<T*>(st_smem);          // [3][RS]: [halo node][B]
-    T* ust = ring + 3 * RS;                           // [2][US]: [m+1][halo node]
+    T* ust = ring + 3 * RS;                           // [3][US]: [halo node][m+1]
     // a plane's buffer resource; planes outside the lattice have no records,
     // so their loads return 0 and their stores are dropped
     auto plane = [&](const T* base, int pl, int64_t stride, uint32_t bytes) {
@@ -272,17 +284,14 @@ __global__ __launch_bounds__(kStThreads) void k_dir_stencil(PcgArgs<T> a, StArgs
         return rsrc(base + (in ? pl * stride : 0), in ? bytes : 0u);
     };
 
-    // LDS position of output slot u, fixed for the launch (slots past the tile
-    // point at a valid interior position; their results are not stored)
+    // LDS element index of output slot u in a ring slot (slots past the tile
+    // point at an interior position; their results are not stored)
     int32_t oc0[NPF];
 #pragma unroll
     for (int u = 0; u < NPF; ++u) {
         const int nl = (tid + u * NT) / B;
         oc0[u] = nl < tx * ty ? (nl / tx + 1) * hx + nl % tx + 1 : hx + 1;
     }
-
-    // byte offset of an output node's U_0 entry from its vector-element offset
-    auto node_bytes = [&](uint32_t o) { return o == kOut ? kOut : (o - k * SZ) / B; };
 
     T rr[NPF], pp[NPF], dd[NPF], uu[NU];
     bool fz = false;
@@ -298,39 +307,40 @@ __global__ __launch_bounds__(kStThreads) void k_dir_stencil(PcgArgs<T> a, StArgs
         const int32_t zb = ch * g.zc, ze = min(zb + g.zc, nz);
         // byte offsets inside a plane of this tile's slots (kOut: outside the
         // lattice or the tile -- past every resource's records)
-        uint32_t fo[NPF], fd[NPF], oo[NPF], uo[NU];
-        int32_t oxy[NPF];
+        uint32_t fo[NPF], oo[NPF], uo[NU];
 #pragma unroll
         for (int u = 0; u < NPF; ++u) {
             const int nl = (tid + u * NT) / B;
             const int gx = x0 - 1 + nl % hx, gy = y0 - 1 + nl / hx;
             const bool fin = nl < hn && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
             fo[u] = fin ? (static_cast<uint32_t>(gy * nx + gx) * B + k) * SZ : kOut;
-            fd[u] = fin ? static_cast<uint32_t>(gy * nx + gx) * SZ : kOut;
             const int ox = x0 + nl % tx, oy = y0 + nl / tx;
             const bool oin = nl < tx * ty && ox < nx && oy < ny;
             oo[u] = oin ? (static_cast<uint32_t>(oy * nx + ox) * B + k) * SZ : kOut;
-            oxy[u] = oin ? (oy << 16) | ox : -1;
         }
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            const int e = tid + u * NT, nl = e % hn;
+        for (int v = 0; v < NU; ++v) {
+            const int e = tid + v * NT, nl = e / M1;
             const int gx = x0 - 1 + nl % hx, gy = y0 - 1 + nl / hx;
-            uo[u] = (STAGE && e < (m + 1) * hn && gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-                        ? static_cast<uint32_t>((e / hn) * N + gy * nx + gx) * SZ
+            uo[v] = (nl < hn && gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+                        ? (static_cast<uint32_t>(gy * nx + gx) * M1 + e % M1) * SZ
                         : kOut;
         }
 
+        // loads are unconditional (the range check zeroes halo and edge slots),
+        // so they issue back to back without branches
         auto fetch = [&](int pl) {
             fz = pl >= 0 && pl < nz;
             const auto br = plane(r, pl, nxy * B, pv), bp = plane(po, pl, nxy * B, pv);
-            const auto bd = plane(dinv, pl, nxy, pv / B);
+            const auto bd = plane(dinv, pl, nxy, pv / B), bu = plane(U, pl, nxy * M1, pu);
 #pragma unroll
             for (int u = 0; u < NPF; ++u) {
                 rr[u] = bload<T>(br, fo[u]);
                 pp[u] = bload<T>(bp, fo[u]);
-                dd[u] = bload<T>(bd, fd[u]);
+                dd[u] = bload<T>(bd, (fo[u] - k * SZ) / B);   // kOut maps past the plane too
             }
+#pragma unroll
+            for (int v = 0; v < NU; ++v) uu[v] = bload<T>(bu, uo[v]);
         };
         auto store = [&](int sl) {
             T* R = ring + sl * RS;
@@ -339,82 +349,69 @@ __global__ __launch_bounds__(kStThreads) void k_dir_stencil(PcgArgs<T> a, StArgs
                 const T v = dd[u] * rr[u] - cc + beta * pp[u];
                 R[tid + u * NT] = (!DEFL || (fz && fo[u] != kOut)) ? v : T(0);
             }
-        };
-        auto fetch_u = [&](int pl) {
-            const auto bu = plane(U, pl, nxy, pu);
-#pragma unroll
-            for (int u = 0; u < NU; ++u) uu[u] = bload<T>(bu, uo[u]);
-        };
-        auto store_u = [&](int sl) {
             T* S = ust + sl * US;
 #pragma unroll
-            for (int u = 0; u < NU; ++u) S[tid + u * NT] = uu[u];
+            for (int v = 0; v < NU; ++v) S[tid + v * NT] = uu[v];
         };
-
-        if (STAGE) {
-            fetch_u(zb - 1);
-            store_u(0);
-        }
-        fetch(zb - 1);
-        store(0);
-        fetch(zb);
-        store(1);
-        if (STAGE) fetch_u(zb);
-        fetch(zb + 1);
-        for (int z = zb; z < ze; ++z) {
-            const int sz = (z - zb + 1) % 3, sp = (sz + 1) % 3, sl = (sz + 2) % 3;
-            const int us = (z - zb + 1) & 1;
+        // plane z with ring/diagonal slots (z, z+1, z-1) = (SZ0, SP0, SL0)
+        auto step = [&](int z, auto SZ0, auto SP0, auto SL0) {
+            constexpr int sz = decltype(SZ0)::value, sp = decltype(SP0)::value, sl = decltype(SL0)::value;
             store(sp);
-            if (STAGE) store_u(us);
             __syncthreads();
-            if (z + 1 < ze) {
-                if (STAGE) fetch_u(z + 1);
-                fetch(z + 2);
-            }
+            if (z + 1 < ze) fetch(z + 2);
             const auto bpn = plane(pn, z, nxy * B, pv), bq = plane(q, z, nxy * B, pv);
             if (act) {
                 const T* Rz = ring + sz * RS;
-                const auto bu = plane(U, z, nxy, pu), bul = plane(U, z - 1, nxy, pu);
-                T sum[NPF], pc[NPF];
+                const T* Sz = ust + sz * US;
+                const T* Rp = ring + sp * RS;
+                const T* Rm = ring + sl * RS;
+                const T* Sm = ust + sl * US;
+                // q_i = U_0 p_i + sum_j U_j[i] p_{i+u_j} + U_j[i-u_j] p_{i-u_j}
+                auto row = [&](int c0) {
+                    T sum = Sz[c0 * M1] * Rz[c0 * B + k];
+                    auto term = [&](int j, int dx, int dy, int dz) {
+                        const int d = dy * hx + dx;
+                        const T* Ru = dz ? Rp : Rz;
+                        const T* Rl = dz ? Rm : Rz;
+                        const T* Sl = dz ? Sm : Sz;
+                        sum += Sz[c0 * M1 + j] * Ru[(c0 + d) * B + k] + Sl[(c0 - d) * M1 + j] * Rl[(c0 - d) * B + k];
+                    };
+                    if constexpr (KUHN) {
+                        // byte offsets from the tile-corner neighbour (c0 - hx - 1) are all
+                        // non-negative compile-time constants: LDS reads with immediate offsets
+                        const char* rb = reinterpret_cast<const char*>(ring) + ((c0 - HXC - 1) * B + k) * SZ;
+                        const char* ub = reinterpret_cast<const char*>(ust) + (c0 - HXC - 1) * (kKuhnM + 1) * SZ;
+                        constexpr int cc = HXC + 1;
+                        auto R = [&](int sl_, int at) {
+                            return *reinterpret_cast<const T*>(rb + (sl_ * RS + at * B) * SZ);
+                        };
+                        auto S = [&](int sl_, int at, int j) {
+                            return *reinterpret_cast<const T*>(ub + (sl_ * US + at * (kKuhnM + 1) + j) * SZ);
+                        };
+                        sum = S(sz, cc, 0) * R(sz, cc);
 #pragma unroll
-                for (int u = 0; u < NPF; ++u) {
-                    pc[u] = Rz[oc0[u] * B + k];
-                    sum[u] = (STAGE ? ust[us * US + oc0[u]] : bload<T>(bu, node_bytes(oo[u]))) * pc[u];
-                }
-#pragma unroll 1
-                for (int j = 0; j < m; ++j) {
-                    const int4 t = g.tab[j];          // dx, dy, dz, dx + nx (dy + ny dz)
-                    const int d = t.y * hx + t.x;
-                    const T* Ru = ring + (t.z ? sp : sz) * RS;
-                    const T* Rl = ring + (t.z ? sl : sz) * RS;
-                    const T* Sc = ust + us * US + (j + 1) * hn;
-                    const T* Sl = ust + (t.z ? us ^ 1 : us) * US + (j + 1) * hn;
-                    // U_j of the output node, and of its lower partner (plane z - dz)
-                    const uint32_t jo = static_cast<uint32_t>((j + 1) * N) * SZ;
-                    const int32_t lw = (t.z ? (int32_t)nxy : 0) - t.w;
-#pragma unroll
-                    for (int u = 0; u < NPF; ++u) {
-                        const int c0 = oc0[u];
-                        T uj, ul;
-                        if (STAGE) {
-                            uj = Sc[c0];
-                            ul = Sl[c0 - d];
-                        } else {
-                            const uint32_t on = node_bytes(oo[u]);
-                            uj = bload<T>(bu, on == kOut ? kOut : jo + on);
-                            const int lx = (oxy[u] & 0xffff) - t.x, ly = (oxy[u] >> 16) - t.y;
-                            const bool in = oxy[u] >= 0 && lx >= 0 && lx < nx && ly >= 0 && ly < ny;
-                            ul = bload<T>(t.z ? bul : bu,
-                                          in ? jo + on + static_cast<uint32_t>(lw * (int32_t)SZ) : kOut);
+                        for (int j = 0; j < kKuhnM; ++j) {
+                            const int d = kKdy[j] * HXC + kKdx[j];
+                            const int up = kKdz[j] ? sp : sz, lo = kKdz[j] ? sl : sz;
+                            sum += S(sz, cc, j + 1) * R(up, cc + d) + S(lo, cc - d, j + 1) * R(lo, cc - d);
                         }
-                        sum[u] += uj * Ru[(c0 + d) * B + k] + ul * Rl[(c0 - d) * B + k];
+                    } else {
+#pragma unroll 1
+                        for (int j = 0; j < m; ++j) {
+                            const int4 t = g.tab[j];          // dx, dy, dz, dx + nx (dy + ny dz)
+                            term(j + 1, t.x, t.y, t.z);
+                        }
                     }
-                }
+                    return sum;
+                };
 #pragma unroll
                 for (int u = 0; u < NPF; ++u) {
-                    bstore<T>(bpn, oo[u], pc[u]);
-                    bstore<T>(bq, oo[u], sum[u]);
-                    acc += oo[u] != kOut ? static_cast<double>(pc[u]) * static_cast<double>(sum[u]) : 0.0;
+                    if (tid + u * NT >= tx * ty * B) continue;   // whole waves past the tile skip
+                    const T pc = Rz[oc0[u] * B + k];
+                    const T sum = row(oc0[u]);
+                    bstore<T>(bpn, oo[u], pc);
+                    bstore<T>(bq, oo[u], sum);
+                    acc += oo[u] != kOut ? static_cast<double>(pc) * static_cast<double>(sum) : 0.0;
                 }
             } else {
                 const auto bo = plane(po, z, nxy * B, pv);
@@ -422,6 +419,20 @@ __global__ __launch_bounds__(kStThreads) void k_dir_stencil(PcgArgs<T> a, StArgs
                 for (int u = 0; u < NPF; ++u) bstore<T>(bpn, oo[u], bload<T>(bo, oo[u]));
             }
             __syncthreads();
+        };
+
+        fetch(zb - 1);
+        store(0);
+        fetch(zb);
+        store(1);
+        fetch(zb + 1);
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        for (int z = zb; z < ze; z += 3) {   // plane z - zb + 1 lives in slot (z - zb + 1) % 3
+            step(z, I1{}, I2{}, I0{});
+            if (z + 1 < ze) step(z + 1, I2{}, I0{}, I1{});
+            if (z + 2 < ze) step(z + 2, I0{}, I1{}, I2{});
         }
     }
     const double bs = block_sum_n<B, NT>(acc, sm);
@@ -878,14 +889,16 @@ RedArgs red_args(const PcgArgs<T>& a, int S, uint32_t mask = 0, int init = 0) {
 // (0: diagonals read from global memory), TX0 the preferred tile width.
 template <typename T, int B>
 struct StTile {
-    static constexpr int NPF = B == 1 ? 2 : ((B == 16 && sizeof(T) == 4) ? 6 : 4);
-    static constexpr int NPU = sizeof(T) == 4 ? (B == 16 ? 3 : (B == 8 ? 4 : 0)) : 0;
-    static constexpr int TX0 = B >= 8 ? 16 : (B == 4 ? 32 : 64);
+    static constexpr int NPF = B == 16 ? (sizeof(T) == 4 ? 6 : 4) : (B >= 4 ? 4 : (B == 2 ? 2 : 1));
+    static constexpr int NU = B == 16 ? (sizeof(T) == 4 ? 3 : 2) : (B == 8 ? 4 : 8);
+    static constexpr int HX = B >= 16 ? 17 : (B == 8 ? 18 : 34);   // halo'd tile width of the Kuhn kernel
+    static constexpr size_t LDS = (size_t)3 * (NPF + NU) * kStThreads * sizeof(T);
 };
 
-template <typename T, int B, bool DEFL>
+template <typename T, int B, bool DEFL, bool KUHN>
 const void* stencil_kernel() {
-    return reinterpret_cast<const void*>(&k_dir_stencil<T, B, DEFL, StTile<T, B>::NPF, StTile<T, B>::NPU>);
+    using TL = StTile<T, B>;
+    return reinterpret_cast<const void*>(&k_dir_stencil<T, B, DEFL, TL::NPF, TL::NU, KUHN ? TL::HX : 0>);
 }
 
 // one PCG iteration: direction+SpMV, alpha, update, beta
@@ -894,9 +907,13 @@ inline void launch_iteration(const PcgArgs<T>& a, const StArgs<T>& g, dim3 grid,
                              hipEvent_t* ev) {
     const RedArgs ra = red_args(a, a.nsys * B);
     if (ev) (void)hipEventRecord(ev[0], st);
-    if (g.on)
-        hipLaunchKernelGGL((k_dir_stencil<T, B, DEFL, StTile<T, B>::NPF, StTile<T, B>::NPU>), grid,
-                           dim3(kStThreads), g.lds, st, a, g);
+    using TL = StTile<T, B>;
+    if (g.on && g.kuhn)
+        hipLaunchKernelGGL((k_dir_stencil<T, B, DEFL, TL::NPF, TL::NU, TL::HX>), grid, dim3(kStThreads), TL::LDS, st,
+                           a, g);
+    else if (g.on)
+        hipLaunchKernelGGL((k_dir_stencil<T, B, DEFL, TL::NPF, TL::NU, 0>), grid, dim3(kStThreads), TL::LDS, st, a,
+                           g);
     else
         hipLaunchKernelGGL((k_dir_spmv<T, B, DEFL>), grid, blk, 0, st, a);
     if (ev) (void)hipEventRecord(ev[1], st);
@@ -920,10 +937,11 @@ inline void launch_true_residual(const PcgArgs<T>& a, dim3 grid, dim3 blk, hipSt
 template <typename T, int B, bool DEFL>
 qpat_status chunk_graph(qpat_ctx* c, const PcgArgs<T>& a, const StArgs<T>& g, int chunk, dim3 grid, dim3 blk,
                         hipGraphExec_t* out) {
-    const void* kfn = g.on ? stencil_kernel<T, B, DEFL>() : reinterpret_cast<const void*>(&k_dir_spmv<T, B, DEFL>);
+    const void* kfn = !g.on ? reinterpret_cast<const void*>(&k_dir_spmv<T, B, DEFL>)
+                      : g.kuhn ? stencil_kernel<T, B, DEFL, true>() : stencil_kernel<T, B, DEFL, false>();
     char key[256];
     snprintf(key, sizeof key, "%p/%d/%d/%d/%.17g/%d/%d/%p/%d/%d/%d/%d", kfn, chunk, a.gs, a.nsys, a.rtol2, a.maxit,
-             (int)a.N, (const void*)g.U, g.tx, g.ty, g.zc, g.items);
+             (int)a.N, (const void*)g.U, g.hx, g.hy, g.zc, g.items);
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
         *out = it->second;
@@ -954,46 +972,51 @@ qpat_status make_st(qpat_ctx* c, Op op, const PcgArgs<T>& a, StArgs<T>* out) {
     const Lattice& L = c->lat;
     if (!L.on || c->opts.operator_format != 1) return QPAT_OK;
     using TL = StTile<T, B>;
-    constexpr bool stage = TL::NPU > 0;
     const int64_t sz = sizeof(T);
     // 32-bit byte offsets below kOut: every array the kernel addresses under 2 GiB
     if ((int64_t)(L.m + 1) * c->N * sz >= (int64_t(1) << 31) || c->N * B * sz >= (int64_t(1) << 31)) return QPAT_OK;
-    int64_t hn_max = (int64_t)TL::NPF * kStThreads / B;
-    if (stage) hn_max = std::min<int64_t>(hn_max, (int64_t)TL::NPU * kStThreads / (L.m + 1));
-    int64_t tiles_x = (L.nx + TL::TX0 - 1) / TL::TX0;
-    int64_t tx = (L.nx + tiles_x - 1) / tiles_x;
-    if (tx + 2 > hn_max / 3) tx = hn_max / 3 - 2;
-    if (tx < 1) return QPAT_OK;
-    tiles_x = (L.nx + tx - 1) / tx;
-    tx = (L.nx + tiles_x - 1) / tiles_x;
-    int64_t ty = std::min<int64_t>(hn_max / (tx + 2) - 2, L.ny);
+    bool kuhn = L.m == kKuhnM;
+    for (int j = 0; kuhn && j < kKuhnM; ++j)
+        kuhn = L.dx[j] == kKdx[j] && L.dy[j] == kKdy[j] && L.dz[j] == kKdz[j];
+    const int64_t hn_max = std::min<int64_t>((int64_t)TL::NPF * kStThreads / B,
+                                             (int64_t)TL::NU * kStThreads / (L.m + 1));
+    int64_t hx = TL::HX;
+    if (!kuhn) {
+        const int64_t tiles_x = (L.nx + TL::HX - 3) / (TL::HX - 2);
+        hx = (L.nx + tiles_x - 1) / tiles_x + 2;
+    }
+    if (hx > hn_max / 3) {
+        if (kuhn) kuhn = false;
+        hx = hn_max / 3;
+    }
+    if (hx < 3) return QPAT_OK;
+    int64_t ty = std::min<int64_t>(hn_max / hx - 2, L.ny);
     if (ty < 1) return QPAT_OK;
     const int64_t tiles_y = (L.ny + ty - 1) / ty;
     ty = (L.ny + tiles_y - 1) / tiles_y;
+    const int64_t tiles_x = (L.nx + hx - 3) / (hx - 2);
+    g.kuhn = kuhn;
     g.nx = L.nx;
     g.ny = L.ny;
     g.nz = L.nz;
     g.m = L.m;
     g.tab = reinterpret_cast<const int4*>(c->lat_tab);
-    g.tx = static_cast<int32_t>(tx);
-    g.ty = static_cast<int32_t>(ty);
-    g.hx = g.tx + 2;
-    g.hy = g.ty + 2;
+    g.hx = static_cast<int32_t>(hx);
+    g.hy = static_cast<int32_t>(ty + 2);
     g.tiles_x = static_cast<int32_t>(tiles_x);
     g.tiles_y = static_cast<int32_t>(tiles_y);
-    g.lds = static_cast<size_t>((3 * TL::NPF + (stage ? 2 * TL::NPU : 0)) * kStThreads * sz);
-    static_assert((3 * TL::NPF + (stage ? 2 * TL::NPU : 0)) * kStThreads * sizeof(T) <= 63 * 1024,
-                  "stencil LDS budget");
+    static_assert(TL::LDS <= 159 * 1024, "stencil LDS budget");
+    const void* kfn = kuhn ? stencil_kernel<T, B, DEFL, true>() : stencil_kernel<T, B, DEFL, false>();
     char key[96];
-    snprintf(key, sizeof key, "st/%p/%zu", stencil_kernel<T, B, DEFL>(), g.lds);
+    snprintf(key, sizeof key, "st/%p", kfn);
     int occ = 0;
     auto it = c->st_occ.find(key);
     if (it != c->st_occ.end()) {
         occ = it->second;
     } else {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, stencil_kernel<T, B, DEFL>(), kStThreads, g.lds) !=
-            hipSuccess)
-            occ = 1;
+        // dynamic LDS beyond the default per-block limit has to be allowed per kernel
+        QPAT_HIP(c, hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TL::LDS));
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, kStThreads, TL::LDS) != hipSuccess) occ = 1;
         c->st_occ[key] = occ;
     }
     int cus = 256;

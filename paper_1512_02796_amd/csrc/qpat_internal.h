@@ -85,7 +85,8 @@ struct LsqrScal {
 // dz = 0 and dy > 0, or dz = dy = 0 and dx > 0): U_j[i] = A(i, i + u_j), zero
 // where that entry is not in the pattern. Row i then reads
 //   A(i, i - u_j) = A(i - u_j, i) = U_j[i - u_j]
-// from the partner row. Arrays are [m + 1][N] per system, U_0 the diagonal.
+// from the partner row. Arrays are [N][m + 1] per system (the m + 1 values of
+// a node together), U_0 the diagonal.
 constexpr int kMaxUpper = 13;
 struct Lattice {
     bool on = false;
@@ -132,7 +133,7 @@ struct qpat_ctx {
     float* K32 = nullptr;
     double* Kdinv64 = nullptr;     // [N]
     float* Kdinv32 = nullptr;
-    double* KU64 = nullptr;        // lattice form of K, [m+1][N]
+    double* KU64 = nullptr;        // lattice form of K, [N][m+1]
     float* KU32 = nullptr;
     bool have_forward = false;
 
@@ -141,7 +142,7 @@ struct qpat_ctx {
     float* M32 = nullptr;
     double* Mdinv64 = nullptr;     // [2][N]  1/(diag + delta)
     float* Mdinv32 = nullptr;
-    double* MU64 = nullptr;        // lattice form, [2][m+1][N]
+    double* MU64 = nullptr;        // lattice form, [2][N][m+1]
     double delta = 0.0;
     bool have_prior = false;
 
