@@ -33,19 +33,42 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kind, N, nnz, V, stat):
+def algorithmic_bytes(kind, N, layout, V, stat):
     """Bytes one launch must move, summed over the measured launches.
 
     dir_spmv: per active right-hand side read r, p_old and write p_new, q
-    (4 N V); per launch the matrix (nnz values of V bytes + 4-byte columns),
-    the Jacobi diagonal (N V) and the row lengths (4 N).
+    (4 N V); per launch the operator and the Jacobi diagonal (N V). The
+    operator is the stencil form on lattice meshes (N (m+1) values: the
+    diagonal and the m upper offsets) and otherwise the sliced ELL (padded
+    entries of V bytes + 4-byte columns, plus 4-byte row lengths).
     update: per active right-hand side read x, p, q, r and write x, r (6 N V);
     per launch the Jacobi diagonal (N V).
     """
     L, lanes = stat["launches"], stat["lanes"]
     if kind == "dir_spmv":
-        return lanes * 4 * N * V + L * (nnz * (4 + V) + N * (V + 4))
+        if layout["lattice"]:
+            op = N * layout["stencil_arrays"] * V
+        else:
+            op = layout["sell_len"] * (4 + V) + 4 * N
+        return lanes * 4 * N * V + L * (op + N * V)
     return lanes * 6 * N * V + L * N * V
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (profiles/hbm_traffic.json, copy-calibrated), or None when
+    the kernel source has changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    d = rec["per_dispatch_bytes"].get(kernel)
+    return None if d is None else d["fetch"] + d["write"]
 
 
 def main():
@@ -104,7 +127,6 @@ def main():
     s, t = d(s_np), d(t_np)
     Js = torch.empty(K * N, dtype=torch.float64, device=dev)
     Jt = torch.empty(2 * N, dtype=torch.float64, device=dev)
-    nnz = None
 
     # ---- timed J s + J^T t pairs (batched + mixed)
     for _ in range(args.warmup):
@@ -175,26 +197,27 @@ def main():
         torch.cuda.synchronize()
 
     # ---- roofline of the dominant kernel (live HIP-event timing)
-    from paper_1512_02796_amd.qpat import Context  # noqa: F401
-    # nnz of the P1 pattern on the Kuhn mesh (14 neighbours per interior node)
-    n = args.grid
-    nnz = N + 2 * (3 * n * (n + 1) ** 2 + 3 * n * n * (n + 1) + n ** 3)
+    layout = ctx.operator_layout()
     V = 4  # FP32 vectors and values in the mixed K solve
-    cand = {"k_dir_spmv<float,16>": ("dir_spmv", kst["K_dir_spmv"]),
+    dir_name = "k_dir_stencil<float,16>" if layout["lattice"] else "k_dir_spmv<float,16>"
+    cand = {dir_name: ("dir_spmv", kst["K_dir_spmv"]),
             "k_update<float,16>": ("update", kst["K_update"])}
     name, (kind, st) = max(cand.items(), key=lambda kv: kv[1][1]["total_ms"])
-    bytes_total = algorithmic_bytes(kind, N, nnz, V, st)
+    bytes_total = algorithmic_bytes(kind, N, layout, V, st)
     avg_ms = st["total_ms"] / st["launches"]
     achieved = bytes_total / st["launches"] / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_ms": round(avg_ms, 4), "launches": st["launches"],
                 "bytes_per_launch": round(bytes_total / st["launches"]),
+                "operator": "stencil (diagonal + %d upper offsets)" % (layout["stencil_arrays"] - 1)
+                            if layout["lattice"] else "sliced ELL",
                 "other_kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "launches": v["launches"],
                                       "GB/s": round(algorithmic_bytes(
-                                          "dir_spmv" if "dir" in k else "update", N, nnz, V, v)
+                                          "dir_spmv" if "dir" in k else "update", N, layout, V, v)
                                           / max(v["total_ms"], 1e-9) / 1e6, 1) if v["launches"] else 0}
                                   for k, v in kst.items() if k.startswith("K_")}}
+    roofline["traffic"] = measured_traffic(name)
     log("roofline", roofline)
 
     # ---- CPU oracle on a bounded sample of the same system

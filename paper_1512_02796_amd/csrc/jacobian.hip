@@ -34,7 +34,15 @@ __device__ __forceinline__ void load_geo4(const double* __restrict__ geo, int32_
     }
 }
 
-// b[row][k] = -(S(u1) + Mass(u2)) phi_{col0+k}, u1 = kappa s1, u2 = mu s2
+// right-hand sides handled by one thread of the G kernels: the per-tetrahedron
+// geometry and coefficients are loaded once for all of them
+template <int B>
+constexpr int kGroup = B > 8 ? 8 : B;
+
+// b[row][k] = -(S(u1) + Mass(u2)) phi_{col0+k}, u1 = kappa s1, u2 = mu s2.
+// Per tetrahedron at row vertex a the contribution is linear in the vertex
+// values of phi: sum_c w_c phi_c with
+//   w_c = mean(u1) |T| grad(l_a).grad(l_c) + |T| (1 + d_ac) (sum u2 + u2_a + u2_c) / 120.
 template <int B>
 __global__ __launch_bounds__(kThreads) void k_gfwd(int64_t N, const int32_t* __restrict__ tets,
                                                   const double* __restrict__ geo, const int32_t* __restrict__ n2t_ptr,
@@ -42,37 +50,48 @@ __global__ __launch_bounds__(kThreads) void k_gfwd(int64_t N, const int32_t* __r
                                                   const double* __restrict__ mu, const double* __restrict__ s,
                                                   const double* __restrict__ phi, int n_pad, int col0,
                                                   double* __restrict__ b) {
+    constexpr int KG = kGroup<B>, G = B / KG;
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= N * B) return;
-    const int64_t row = t / B;
-    const int k = static_cast<int>(t % B);
-    const int kk = col0 + k;
-    double acc = 0.0;
+    if (t >= N * G) return;
+    const int64_t row = t / G;
+    const int k0 = static_cast<int>(t % G) * KG;
+    double acc[KG];
+#pragma unroll
+    for (int i = 0; i < KG; ++i) acc[i] = 0.0;
     for (int32_t q = n2t_ptr[row]; q < n2t_ptr[row + 1]; ++q) {
         const int32_t e = n2t[q] >> 2, a = n2t[q] & 3;
-        Geo4 G;
-        load_geo4(geo, e, G);
-        double u1 = 0.0, u2[4], ph[4], s2 = 0.0;
-        double gp[3] = {0.0, 0.0, 0.0};
+        Geo4 G4;
+        load_geo4(geo, e, G4);
+        int32_t v[4];
+        double u1 = 0.0, u2[4], s2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const int32_t v = tets[4 * e + c];
-            u1 += kappa[v] * s[v];
-            u2[c] = mu[v] * s[N + v];
+            v[c] = tets[4 * e + c];
+            u1 += kappa[v[c]] * s[v[c]];
+            u2[c] = mu[v[c]] * s[N + v[c]];
             s2 += u2[c];
-            ph[c] = phi[(int64_t)v * n_pad + kk];
-            gp[0] += ph[c] * G.g[c][0];
-            gp[1] += ph[c] * G.g[c][1];
-            gp[2] += ph[c] * G.g[c][2];
         }
         u1 *= 0.25;
-        const double stiff = u1 * G.vol * (G.g[a][0] * gp[0] + G.g[a][1] * gp[1] + G.g[a][2] * gp[2]);
-        double mass = 0.0;
+        double ga[3];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) mass += (c == a ? 2.0 : 1.0) * (s2 + u2[a] + u2[c]) * ph[c];
-        acc -= stiff + G.vol * (1.0 / 120.0) * mass;
+        for (int d = 0; d < 3; ++d) ga[d] = G4.g[a][d];   // runtime vertex: select once
+        double w[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double gg = ga[0] * G4.g[c][0] + ga[1] * G4.g[c][1] + ga[2] * G4.g[c][2];
+            w[c] = u1 * G4.vol * gg + G4.vol * (1.0 / 120.0) * (c == a ? 2.0 : 1.0) * (s2 + u2[a] + u2[c]);
+        }
+#pragma unroll
+        for (int i = 0; i < KG; ++i) {
+            const int kk = col0 + k0 + i;
+            double sum = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sum += w[c] * phi[(int64_t)v[c] * n_pad + kk];
+            acc[i] -= sum;
+        }
     }
-    b[t] = acc;
+#pragma unroll
+    for (int i = 0; i < KG; ++i) b[row * B + k0 + i] = acc[i];
 }
 
 // a1[row] (+)= -sum_k sum_T |T|/4 grad(phi_k).grad(z_k)
@@ -86,50 +105,63 @@ __global__ __launch_bounds__(kThreads) void k_gadj(int64_t N, const int32_t* __r
                                                   int tmode, const double* __restrict__ t_ext,
                                                   const double* __restrict__ W, const double* __restrict__ U,
                                                   int first, double* __restrict__ a1, double* __restrict__ a2) {
+    constexpr int KG = kGroup<B>, G = B / KG;
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool valid = t < N * B;
-    const int64_t row = valid ? t / B : 0;
-    const int k = static_cast<int>(t % B);
-    const int kk = col0 + k;
+    const bool valid = t < N * G;
+    const int64_t row = valid ? t / G : 0;
+    const int k0 = static_cast<int>(t % G) * KG;
     double acc1 = 0.0, acc2 = 0.0;
     if (valid) {
         for (int32_t q = n2t_ptr[row]; q < n2t_ptr[row + 1]; ++q) {
             const int32_t e = n2t[q] >> 2, a = n2t[q] & 3;
-            Geo4 G;
-            load_geo4(geo, e, G);
-            double ph[4], zz[4], sp = 0.0;
-            double gp[3] = {0.0, 0.0, 0.0}, gz[3] = {0.0, 0.0, 0.0};
+            Geo4 G4;
+            load_geo4(geo, e, G4);
+            int32_t v[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int32_t v = tets[4 * e + c];
-                ph[c] = phi[(int64_t)v * n_pad + kk];
-                zz[c] = z[(int64_t)v * B + k];
-                sp += ph[c];
+            for (int c = 0; c < 4; ++c) v[c] = tets[4 * e + c];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    gp[d] += ph[c] * G.g[c][d];
-                    gz[d] += zz[c] * G.g[c][d];
+            for (int i = 0; i < KG; ++i) {
+                const int kk = col0 + k0 + i;
+                double ph[4], zz[4], sp = 0.0;
+                double gp[3] = {0.0, 0.0, 0.0}, gz[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    ph[c] = phi[(int64_t)v[c] * n_pad + kk];
+                    zz[c] = z[(int64_t)v[c] * B + k0 + i];
+                    sp += ph[c];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        gp[d] += ph[c] * G4.g[c][d];
+                        gz[d] += zz[c] * G4.g[c][d];
+                    }
                 }
-            }
-            acc1 -= 0.25 * G.vol * (gp[0] * gz[0] + gp[1] * gz[1] + gp[2] * gz[2]);
-            double mass = 0.0;
+                acc1 -= 0.25 * G4.vol * (gp[0] * gz[0] + gp[1] * gz[1] + gp[2] * gz[2]);
+                double pa = 0.0;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) mass += (c == a ? 2.0 : 1.0) * (sp + ph[a] + ph[c]) * zz[c];
-            acc2 -= G.vol * (1.0 / 120.0) * mass;
+                for (int c = 0; c < 4; ++c) pa = c == a ? ph[c] : pa;
+                double mass = 0.0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) mass += (c == a ? 2.0 : 1.0) * (sp + pa + ph[c]) * zz[c];
+                acc2 -= G4.vol * (1.0 / 120.0) * mass;
+            }
         }
-        double tv = 0.0;
-        if (kk < n_ill) {
-            if (tmode == 0) tv = t_ext[(int64_t)kk * N + row];
-            else tv = W[row * n_pad + kk] * U[row * n_pad + kk];
+#pragma unroll
+        for (int i = 0; i < KG; ++i) {
+            const int kk = col0 + k0 + i;
+            double tv = 0.0;
+            if (kk < n_ill) {
+                if (tmode == 0) tv = t_ext[(int64_t)kk * N + row];
+                else tv = W[row * n_pad + kk] * U[row * n_pad + kk];
+            }
+            acc2 += phi[row * n_pad + kk] * tv;
         }
-        acc2 += phi[row * n_pad + kk] * tv;
     }
 #pragma unroll
-    for (int off = B >> 1; off >= 1; off >>= 1) {
+    for (int off = G >> 1; off >= 1; off >>= 1) {
         acc1 += __shfl_xor(acc1, off);
         acc2 += __shfl_xor(acc2, off);
     }
-    if (valid && k == 0) {
+    if (valid && k0 == 0) {
         if (first) {
             a1[row] = acc1;
             a2[row] = acc2;
@@ -266,8 +298,9 @@ qpat_status jvp_core(qpat_ctx* c, const double* s, int mode, double* out, SolveS
     const int B = block_size(c);
     const dim3 g(grid_for(c->N * B, kThreads, 1 << 30)), blk(kThreads);
     for (int col0 = 0; col0 < c->n_pad; col0 += B) {
-        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gfwd<BB>, g, blk, 0, c->stream, c->N, c->tets, c->geo, c->n2t_ptr,
-                                              c->n2t, c->kappa, c->mu, s, c->phi, c->n_pad, col0, c->b64));
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gfwd<BB>, dim3(grid_for(c->N * (BB / kGroup<BB>), kThreads, 1 << 30)),
+                                              blk, 0, c->stream, c->N, c->tets, c->geo, c->n2t_ptr, c->n2t, c->kappa,
+                                              c->mu, s, c->phi, c->n_pad, col0, c->b64));
         QPAT_TRY(pcg_solve(c, Op::K, B, st));
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_jvp_out<BB>, g, blk, 0, c->stream, c->N, c->mu, c->phi, s, c->x64,
                                               c->n_pad, c->n_ill, col0, mode, out, c->lw, c->lu, c->ls));
@@ -287,9 +320,10 @@ qpat_status vjp_core(qpat_ctx* c, const double* t, int mode, double* out, SolveS
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_adj_rhs<BB>, g, blk, 0, c->stream, c->N, c->mu, c->n_pad, c->n_ill,
                                               col0, tmode, t, c->lw, c->lu, c->b64));
         QPAT_TRY(pcg_solve(c, Op::K, B, st));
-        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gadj<BB>, g, blk, 0, c->stream, c->N, c->tets, c->geo, c->n2t_ptr,
-                                              c->n2t, c->phi, c->n_pad, c->n_ill, col0, c->x64, tmode, t, c->lw,
-                                              c->lu, col0 == 0 ? 1 : 0, c->acc1, c->acc2));
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gadj<BB>, dim3(grid_for(c->N * (BB / kGroup<BB>), kThreads, 1 << 30)),
+                                              blk, 0, c->stream, c->N, c->tets, c->geo, c->n2t_ptr, c->n2t, c->phi,
+                                              c->n_pad, c->n_ill, col0, c->x64, tmode, t, c->lw, c->lu,
+                                              col0 == 0 ? 1 : 0, c->acc1, c->acc2));
     }
     hipLaunchKernelGGL(k_vjp_out, dim3(grid_for(c->N, kThreads, 1 << 30)), blk, 0, c->stream, c->N, c->kappa, c->mu,
                        c->acc1, c->acc2, out, mode == 2 ? 1 : 0, c->lwh, c->ls);

@@ -55,6 +55,10 @@ struct PcgArgs {
     int32_t maxit;
     uint32_t mask;       // lanes of a true-residual recomputation
     double inv_delta;
+    // FP64 stencil form for the true residual (null: sliced ELL)
+    const double* u64;   // [nsys][N][m+1]
+    const int4* tab;     // [m] dx, dy, dz, dx + nx (dy + ny dz)
+    int32_t nx, ny, nz, m;
 };
 
 // Tiling of the stencil direction+SpMV kernel (lattice meshes). A work item
@@ -569,12 +573,30 @@ __global__ __launch_bounds__(kThreads) void k_true_residual(PcgArgs<T> a, int in
             double res = b[idx];
             if (init) bb += res * res;
             if (!init || has_x0) {
-                const int32_t base = a.s.slice_ptr[row / kSlice] + static_cast<int32_t>(row % kSlice);
-                const int32_t n = a.s.rowlen[row];
                 double sum = 0.0;
-                for (int32_t j = 0; j < n; ++j) {
-                    const int32_t col = cols[base + j * kSlice];
-                    sum += vals[base + j * kSlice] * x64[(int64_t)col * B + k];
+                if (a.u64) {
+                    // stencil form: U_0 x_i + sum_j U_j[i] x_{i+u_j} + U_j[i-u_j] x_{i-u_j}
+                    const int M1 = a.m + 1;
+                    const double* __restrict__ U = a.u64 + (int64_t)sys * a.N * M1;
+                    const int32_t i = static_cast<int32_t>(row);
+                    const int32_t ix = i % a.nx, iy = (i / a.nx) % a.ny, iz = i / (a.nx * a.ny);
+                    sum = U[(int64_t)i * M1] * x64[idx];
+                    for (int j = 0; j < a.m; ++j) {
+                        const int4 t = a.tab[j];
+                        const int32_t ux = ix + t.x, uy = iy + t.y, uz = iz + t.z;
+                        if (ux >= 0 && ux < a.nx && uy >= 0 && uy < a.ny && uz < a.nz)
+                            sum += U[(int64_t)i * M1 + j + 1] * x64[(int64_t)(i + t.w) * B + k];
+                        const int32_t lx = ix - t.x, ly = iy - t.y, lz = iz - t.z;
+                        if (lx >= 0 && lx < a.nx && ly >= 0 && ly < a.ny && lz >= 0)
+                            sum += U[(int64_t)(i - t.w) * M1 + j + 1] * x64[(int64_t)(i - t.w) * B + k];
+                    }
+                } else {
+                    const int32_t base = a.s.slice_ptr[row / kSlice] + static_cast<int32_t>(row % kSlice);
+                    const int32_t n = a.s.rowlen[row];
+                    for (int32_t j = 0; j < n; ++j) {
+                        const int32_t col = cols[base + j * kSlice];
+                        sum += vals[base + j * kSlice] * x64[(int64_t)col * B + k];
+                    }
                 }
                 res -= sum;
             }
@@ -1283,11 +1305,13 @@ PcgArgs<T> make_args(qpat_ctx* c, Op op, int B) {
         a.dinv = is64 ? reinterpret_cast<const T*>(c->Kdinv64) : reinterpret_cast<const T*>(c->Kdinv32);
         a.vals64 = c->K64;
         a.dinv64 = c->Kdinv64;
+        a.u64 = c->KU64;
     } else {
         a.vals = is64 ? reinterpret_cast<const T*>(c->M64) : reinterpret_cast<const T*>(c->M32);
         a.dinv = is64 ? reinterpret_cast<const T*>(c->Mdinv64) : reinterpret_cast<const T*>(c->Mdinv32);
         a.vals64 = c->M64;
         a.dinv64 = c->Mdinv64;
+        a.u64 = c->MU64;
     }
     a.r = static_cast<T*>(c->rl);
     a.pa = static_cast<T*>(c->pa);
@@ -1300,6 +1324,15 @@ PcgArgs<T> make_args(qpat_ctx* c, Op op, int B) {
     a.sh = c->shared;
     a.partials = c->partials;
     a.inv_delta = c->delta > 0 ? 1.0 / c->delta : 0.0;
+    if (c->lat.on && c->opts.operator_format == 1) {
+        a.tab = reinterpret_cast<const int4*>(c->lat_tab);
+        a.nx = c->lat.nx;
+        a.ny = c->lat.ny;
+        a.nz = c->lat.nz;
+        a.m = c->lat.m;
+    } else {
+        a.u64 = nullptr;
+    }
     return a;
 }
 
