@@ -71,6 +71,9 @@ typedef struct {
                                the Kuhn voxel meshes of Sec. 5) the PCG products use the
                                stencil form (diagonal + upper offsets, LDS-tiled).
                                0: sliced ELL on every mesh. Same results up to rounding.     */
+    int32_t prior_precond;  /* M_delta solves: 1 = PCG with a geometric multigrid V-cycle
+                               (lattice meshes with the stencil form; otherwise Jacobi),
+                               0 = Jacobi-PCG. Same stopping rule either way.               */
 } qpat_opts;
 
 typedef struct {
@@ -83,7 +86,7 @@ typedef struct {
 
 /* Fill *opts with the defaults: FP64, block 16, rtol 1e-10, maxit 20000,
  * prior_rtol 1e-8, deflation on, reorthogonalisation on with 64 steps,
- * ru_delta 1e-3, graphs on, stencil form on lattice meshes. */
+ * ru_delta 1e-3, graphs on, stencil form on lattice meshes, multigrid for M_delta. */
 void qpat_default_opts(qpat_opts* opts);
 
 /* Create a context for a tetrahedral P1 mesh (Sec. 3: piecewise linear

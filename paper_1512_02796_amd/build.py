@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqpat.so")
-SOURCES = ["mesh.hip", "lattice.hip", "assemble.hip", "pcg.hip", "jacobian.hip", "lsqr.hip", "guess.hip", "api.hip"]
+SOURCES = ["mesh.hip", "lattice.hip", "assemble.hip", "pcg.hip", "jacobian.hip", "lsqr.hip", "mg.hip", "guess.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -62,6 +62,7 @@ qpat_status check_opts(qpat_ctx* c, const qpat_opts* o) {
     if (o->use_graphs != 0 && o->use_graphs != 1) return fail(c, QPAT_ERR_ARG, "use_graphs must be 0 or 1");
     if (o->operator_format != 0 && o->operator_format != 1)
         return fail(c, QPAT_ERR_ARG, "operator_format must be 0 or 1");
+    if (o->prior_precond != 0 && o->prior_precond != 1) return fail(c, QPAT_ERR_ARG, "prior_precond must be 0 or 1");
     return QPAT_OK;
 }
 
@@ -175,6 +176,7 @@ void qpat_default_opts(qpat_opts* o) {
     o->ru_delta = 1e-3;
     o->use_graphs = 1;
     o->operator_format = 1;
+    o->prior_precond = 1;
 }
 
 const char* qpat_version(void) { return "qpat 0.1 (gfx950)"; }
@@ -431,6 +433,7 @@ qpat_status qpat_prior_setup(qpat_ctx* c, const double* kt, const double* mt, do
     QPAT_TRY(assemble_prior(c, kt, mt, T, b_over_a, delta));
     QPAT_TRY(lattice_convert(c, Op::Prior));
     c->delta = delta;
+    QPAT_TRY(mg_setup(c));
     c->have_prior = true;
     c->lsqr_ready = false;
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
@@ -545,6 +548,7 @@ void qpat_destroy(qpat_ctx* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     guess_destroy(c);
+    mg_destroy(c);
     for (void* p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->scal_host) (void)hipHostFree(c->scal_host);

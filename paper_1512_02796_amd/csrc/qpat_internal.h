@@ -97,6 +97,7 @@ struct Lattice {
 };
 
 struct GuessNet;
+struct MgState;
 
 template <typename T>
 struct DevBuf {
@@ -208,6 +209,9 @@ struct qpat_ctx {
     // learned initial guess (conv net on the node lattice)
     qpat::GuessNet* guess = nullptr;
 
+    // multigrid hierarchy of M_delta (lattice meshes)
+    qpat::MgState* mg = nullptr;
+
     // resident blocks per kernel configuration (occupancy x compute units)
     std::map<int, int> occupancy;
     std::map<std::string, int> st_occ;   // stencil kernel, keyed by kernel and LDS size
@@ -305,6 +309,12 @@ qpat_status guess_fluence(qpat_ctx* c, const double* kappa, const double* mu, do
                           const double* phih, double* phi0);
 void guess_destroy(qpat_ctx* c);
 qpat_status forward_solve_x0(qpat_ctx* c, const double* x0, SolveStats* st);
+
+// ---- mg.hip
+bool mg_available(const qpat_ctx* c);
+qpat_status mg_setup(qpat_ctx* c);
+qpat_status mg_solve(qpat_ctx* c, SolveStats* st);
+void mg_destroy(qpat_ctx* c);
 
 // ---- lsqr.hip
 qpat_status dot(qpat_ctx* c, const double* a, const double* b, int64_t n, double* dev_out);

@@ -142,3 +142,47 @@ def test_permuted_numbering_uses_sell_and_matches():
                              G.P.kappa[inv], G.P.mu[inv], G.P.phi_src, pcg_rtol=1e-12)
     assert not ctx.operator_layout()["lattice"]
     assert rel(phi_p[:, perm], host(phi)) <= 1e-10
+
+
+@pytest.mark.parametrize("deflate", [1, 0])
+def test_prior_multigrid_matches_jacobi(deflate):
+    """M_delta^{-1} with the multigrid-preconditioned PCG against Jacobi-PCG:
+    same solution to the solver tolerance, far fewer iterations."""
+    from qpat_inputs import make_problem
+    P = make_problem("T24")
+    kt = np.log(P.kappa / P.kappa0)
+    mt = np.log(P.mu / P.mu0)
+    p = np.random.default_rng(11).standard_normal(2 * P.mesh.N)
+    rtol = 1e-11 if deflate else 1e-9
+    outs, infos = [], []
+    for pre in (1, 0):
+        G = GpuProblem("T24", GpuProblem.opts(prior_precond=pre, prior_deflate=deflate, prior_rtol=rtol))
+        G.ctx.prior_setup(dev(kt), dev(mt))
+        out = torch.empty(2 * P.mesh.N, dtype=torch.float64, device="cuda")
+        infos.append(G.ctx.prior_solve(dev(p), out))
+        assert infos[-1]["relres_max"] <= rtol
+        outs.append(host(out))
+    assert rel(outs[0], outs[1]) <= (1e-8 if deflate else 1e-6)
+    assert infos[0]["iters_max"] * 4 < infos[1]["iters_max"], infos
+
+
+@pytest.mark.parametrize("dims", [(13, 7, 5), (30, 3, 9)])
+def test_prior_multigrid_on_boxes(dims):
+    """Ragged boxes (odd and even sides, a side of 4 nodes) against the oracle's M_delta."""
+    from oracle.prior import Prior
+    coords, tets, bfaces, kappa, mu, src = box_problem(*dims, 1, seed=7 + sum(dims))
+    rng = np.random.default_rng(sum(dims))
+    N = coords.shape[0]
+    kt = 0.5 * rng.standard_normal(N)
+    mt = 0.5 * rng.standard_normal(N)
+    p = rng.standard_normal(2 * N)
+    g = fem.geometry(coords, tets, bfaces)
+    ref = Prior(g, kt, mt).solve(p)
+    from paper_1512_02796_amd import qpat
+    ctx = qpat.Context(dev(coords), dev(tets, torch.int32), dev(bfaces, torch.int32),
+                       opts=qpat.default_opts(prior_rtol=1e-11))
+    ctx.prior_setup(dev(kt), dev(mt))
+    out = torch.empty(2 * N, dtype=torch.float64, device="cuda")
+    info = ctx.prior_solve(dev(p), out)
+    assert info["relres_max"] <= 1e-11
+    assert rel(host(out), ref) <= 1e-7
