@@ -36,20 +36,22 @@ def log(*a):
 def algorithmic_bytes(kind, N, layout, V, stat):
     """Bytes one launch must move, summed over the measured launches.
 
-    dir_spmv: per active right-hand side read r, p_old and write p_new, q
-    (4 N V); per launch the operator and the Jacobi diagonal (N V). The
-    operator is the stencil form on lattice meshes (N (m+1) values: the
-    diagonal and the m upper offsets) and otherwise the sliced ELL (padded
-    entries of V bytes + 4-byte columns, plus 4-byte row lengths).
-    update: per active right-hand side read x, p, q, r and write x, r (6 N V);
-    per launch the Jacobi diagonal (N V).
+    Sliced ELL (any mesh): dir_spmv per active right-hand side reads r,
+    p_old and writes p_new, q (4 N V), per launch the matrix (padded entries
+    of V bytes + 4-byte columns, 4-byte row lengths) and the Jacobi diagonal
+    (N V); update reads x, p, q, r and writes x, r (6 N V) + N V.
+    Stencil form (lattice meshes): the direction kernel also applies the
+    previous iteration's x += alpha p (read x, write x: 6 N V per right-hand
+    side) and reads the operator as N (m+1) values; the update then reads q,
+    r and writes r (3 N V) + N V.
     """
     L, lanes = stat["launches"], stat["lanes"]
+    if layout["lattice"]:
+        if kind == "dir_spmv":
+            return lanes * 6 * N * V + L * (N * layout["stencil_arrays"] * V + N * V)
+        return lanes * 3 * N * V + L * N * V
     if kind == "dir_spmv":
-        if layout["lattice"]:
-            op = N * layout["stencil_arrays"] * V
-        else:
-            op = layout["sell_len"] * (4 + V) + 4 * N
+        op = layout["sell_len"] * (4 + V) + 4 * N
         return lanes * 4 * N * V + L * (op + N * V)
     return lanes * 6 * N * V + L * N * V
 

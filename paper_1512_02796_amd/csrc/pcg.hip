@@ -264,6 +264,7 @@ __global__ __launch_bounds__(kStThreads, 4) void k_dir_stencil(PcgArgs<T> a, StA
     const bool act = scl.active != 0;
     const T beta = static_cast<T>(scl.beta);
     const T cc = DEFL ? static_cast<T>(scl.c) : T(0);
+    const T alpha = static_cast<T>(scl.alpha);   // pending x += alpha p_old of the last iteration
     const int64_t N = a.N;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int m = KUHN ? kKuhnM : g.m;
@@ -278,6 +279,7 @@ __global__ __launch_bounds__(kStThreads, 4) void k_dir_stencil(PcgArgs<T> a, StA
     const T* __restrict__ po = (par ? a.pb : a.pa) + (int64_t)sys * N * B;
     T* __restrict__ pn = (par ? a.pa : a.pb) + (int64_t)sys * N * B;
     T* __restrict__ q = a.q + (int64_t)sys * N * B;
+    T* __restrict__ xv = a.x + (int64_t)sys * N * B;
     const T* __restrict__ U = g.U + (int64_t)sys * M1 * N;
     T* ring = reinterpret_cast<T*>(st_smem);          // [3][RS]: [halo node][B]
     T* ust = ring + 3 * RS;                           // [3][US]: [halo node][m+1]
@@ -364,6 +366,16 @@ __global__ __launch_bounds__(kStThreads, 4) void k_dir_stencil(PcgArgs<T> a, StA
             __syncthreads();
             if (z + 1 < ze) fetch(z + 2);
             const auto bpn = plane(pn, z, nxy * B, pv), bq = plane(q, z, nxy * B, pv);
+            // the deferred iterate update of the output nodes: loads issued here,
+            // in flight during the arithmetic below
+            const auto bx = plane(xv, z, nxy * B, alpha != T(0) ? pv : 0u);
+            const auto bo = plane(po, z, nxy * B, (alpha != T(0) || !act) ? pv : 0u);   // inactive lanes copy p
+            T xo[NPF], pov[NPF];
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) {
+                xo[u] = bload<T>(bx, oo[u]);
+                pov[u] = bload<T>(bo, oo[u]);
+            }
             if (act) {
                 const T* Rz = ring + sz * RS;
                 const T* Sz = ust + sz * US;
@@ -418,10 +430,12 @@ __global__ __launch_bounds__(kStThreads, 4) void k_dir_stencil(PcgArgs<T> a, StA
                     acc += oo[u] != kOut ? static_cast<double>(pc) * static_cast<double>(sum) : 0.0;
                 }
             } else {
-                const auto bo = plane(po, z, nxy * B, pv);
 #pragma unroll
-                for (int u = 0; u < NPF; ++u) bstore<T>(bpn, oo[u], bload<T>(bo, oo[u]));
+                for (int u = 0; u < NPF; ++u) bstore<T>(bpn, oo[u], pov[u]);
             }
+            // with alpha = 0 the resources have no records: nothing is stored
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) bstore<T>(bx, oo[u], xo[u] + alpha * pov[u]);
             __syncthreads();
         };
 
@@ -443,7 +457,9 @@ __global__ __launch_bounds__(kStThreads, 4) void k_dir_stencil(PcgArgs<T> a, StA
     if (tid < B) write_partial(a.partials, sys * B + tid, a.gs, bs);
 }
 
-template <typename T, int B, bool DEFL>
+// XD: the iterate update x += alpha p is deferred to the next direction
+// kernel (which reads p anyway), so this kernel only updates r
+template <typename T, int B, bool DEFL, bool XD>
 __global__ __launch_bounds__(kThreads) void k_update(PcgArgs<T> a) {
     __shared__ double sm[4 * kMaxRhs];
     if (a.sh->n_active == 0) return;
@@ -471,8 +487,10 @@ __global__ __launch_bounds__(kThreads) void k_update(PcgArgs<T> a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t idx = (row + u * RS) * B + k;
-                xv[u] = x[idx];
-                pv[u] = p[idx];
+                if (!XD) {
+                    xv[u] = x[idx];
+                    pv[u] = p[idx];
+                }
                 qv[u] = q[idx];
                 rv[u] = r[idx];
                 dv[u] = dinv[row + u * RS];
@@ -480,9 +498,8 @@ __global__ __launch_bounds__(kThreads) void k_update(PcgArgs<T> a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t idx = (row + u * RS) * B + k;
-                const T xi = xv[u] + alpha * pv[u];
                 const T ri = rv[u] - alpha * qv[u];
-                x[idx] = xi;
+                if (!XD) x[idx] = xv[u] + alpha * pv[u];
                 r[idx] = ri;
                 const T zi = dv[u] * ri;
                 rz += static_cast<double>(ri) * static_cast<double>(zi);
@@ -495,9 +512,8 @@ __global__ __launch_bounds__(kThreads) void k_update(PcgArgs<T> a) {
         }
         for (; row < r1; row += RS) {
             const int64_t idx = row * B + k;
-            const T xi = x[idx] + alpha * p[idx];
             const T ri = r[idx] - alpha * q[idx];
-            x[idx] = xi;
+            if (!XD) x[idx] = x[idx] + alpha * p[idx];
             r[idx] = ri;
             const T zi = dinv[row] * ri;
             rz += static_cast<double>(ri) * static_cast<double>(zi);
@@ -544,6 +560,28 @@ __global__ __launch_bounds__(kThreads) void k_fold(PcgArgs<T> a) {
         x64[idx] += static_cast<double>(x[idx]);
         x[idx] = T(0);
     }
+}
+
+// deferred iterate update: x += alpha p (current direction) for every lane
+// whose last update is still pending; k_alpha_done then clears alpha
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void k_xflush(PcgArgs<T> a) {
+    int32_t sys;
+    int64_t r0, r1;
+    block_rows(a.gs, a.rpb, a.N, sys, r0, r1);
+    const int k = threadIdx.x % B;
+    const T alpha = static_cast<T>(a.sc[sys * B + k].alpha);
+    if (alpha == T(0)) return;
+    const T* __restrict__ p = (a.sh->parity ? a.pb : a.pa) + (int64_t)sys * a.N * B;
+    T* __restrict__ x = a.x + (int64_t)sys * a.N * B;
+    for (int64_t row = r0 + threadIdx.x / B; row < r1; row += kThreads / B) {
+        const int64_t idx = row * B + k;
+        x[idx] += alpha * p[idx];
+    }
+}
+
+__global__ void k_alpha_done(PcgScal* sc, int S) {
+    if (threadIdx.x < S) sc[threadIdx.x].alpha = 0.0;
 }
 
 // r = b - A64 x64 for the masked lanes; replaces the recursive residual and
@@ -853,6 +891,7 @@ __global__ void k_reset_scal(PcgScal* sc, int S, PcgShared* sh) {
         sc[i].iters = 0;
         sc[i].updates = 0;
         sc[i].mean = 0.0;
+        sc[i].alpha = 0.0;
     }
     if (i == 0) {
         sh->counter = 0u;
@@ -941,7 +980,10 @@ inline void launch_iteration(const PcgArgs<T>& a, const StArgs<T>& g, dim3 grid,
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(k_red_alpha, dim3(1), dim3(kRedThreads), 0, st, ra);
     if (ev) (void)hipEventRecord(ev[2], st);
-    hipLaunchKernelGGL((k_update<T, B, DEFL>), grid, blk, 0, st, a);
+    if (g.on)
+        hipLaunchKernelGGL((k_update<T, B, DEFL, true>), grid, blk, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_update<T, B, DEFL, false>), grid, blk, 0, st, a);
     if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL(k_red_beta<DEFL>, dim3(1), dim3(kRedThreads), 0, st, ra);
     if (ev) (void)hipEventRecord(ev[4], st);
@@ -1092,6 +1134,12 @@ struct Runner {
         launch_true_residual<T, B, DEFL>(a, grid, blk, sm, 1, has_x0 ? 1 : 0);
         QPAT_HIP(c, hipGetLastError());
         PcgScal* hs = c->scal_host;
+        // the stencil direction kernel applies x += alpha p one iteration late;
+        // apply what is pending before x is read (fold, true residual, result)
+        auto flush = [&]() {
+            hipLaunchKernelGGL((k_xflush<T, B>), grid, blk, 0, sm, a);
+            hipLaunchKernelGGL(k_alpha_done, dim3(1), dim3(64), 0, sm, a.sc, S);
+        };
         auto fetch = [&]() -> qpat_status {
             QPAT_HIP(c, hipMemcpyAsync(hs, a.sc, sizeof(PcgScal) * S, hipMemcpyDeviceToHost, sm));
             QPAT_HIP(c, hipStreamSynchronize(sm));
@@ -1155,6 +1203,13 @@ struct Runner {
                 if (hs[i].pending) mask |= 1u << i;
                 else if (mixed && hs[i].active && hs[i].rr <= ru2 * hs[i].rlast2) mask |= 1u << i;
             }
+            if (mask && mixed) {
+                // a recomputation is due anyway: take along the lanes within 10x (in
+                // norm) of their own reliable-update point, so the block's lanes stay
+                // in step and share later recomputations (each costs a full FP64 SpMV)
+                for (int i = 0; i < S; ++i)
+                    if (hs[i].active && !hs[i].pending && hs[i].rr <= 100.0 * ru2 * hs[i].rlast2) mask |= 1u << i;
+            }
             if (mask) {
                 const uint32_t confirm = mask & [&] {
                     uint32_t m = 0;
@@ -1163,6 +1218,7 @@ struct Runner {
                     return m;
                 }();
                 a.mask = mask;
+                if (g.on) flush();
                 if (mixed) hipLaunchKernelGGL((k_fold<T, B>), grid, blk, 0, sm, a);
                 launch_true_residual<T, B, DEFL>(a, grid, blk, sm, 0, 0);
                 QPAT_HIP(c, hipGetLastError());
@@ -1206,6 +1262,7 @@ struct Runner {
             }
             for (int i = 0; i < S; ++i) rr_prev[i] = hs[i].rr;
         }
+        if (g.on) flush();
         if (mixed) {
             // fold anything left (lanes stopped at maxit)
             uint32_t mask = 0;
