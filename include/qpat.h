@@ -199,6 +199,30 @@ typedef struct {
 qpat_status qpat_profile(qpat_ctx* ctx, int32_t enable);
 qpat_status qpat_profile_read(const qpat_ctx* ctx, qpat_kstat out[4]);
 
+/* Batched instances (several independent reconstructions, e.g. meshes of
+ * different sizes and illumination counts): run one call on n contexts at
+ * once and return when all have finished. Each context must own a distinct
+ * HIP stream (given at qpat_setup_mesh); the calls run on one host thread per
+ * context, so their kernels and graph replays overlap on the device.
+ *   QPAT_BATCH_FORWARD  : qpat_forward(ctx, in0 = kappa, in1 = mu, phi = NULL, h = out0 or NULL)
+ *   QPAT_BATCH_JVP      : qpat_jvp(ctx, in0 = s, out0)
+ *   QPAT_BATCH_VJP      : qpat_vjp(ctx, in0 = t, out0)
+ *   QPAT_BATCH_PAIR     : qpat_jvp(ctx, in0, out0) then qpat_vjp(ctx, in1, out1)
+ *   QPAT_BATCH_LSQR_STEP: qpat_lsqr_step(ctx, NULL); arrays unused (may be NULL)
+ * ctxs, in0, out0, in1, out1: host arrays of n pointers (the pointers device
+ * arrays as in the single calls); infos: n entries (host) or NULL, the pair's
+ * two calls merged. 1 <= n <= 256. Returns the first failing instance's
+ * status (its message in that context's qpat_last_error), or QPAT_OK. */
+typedef enum {
+    QPAT_BATCH_FORWARD = 0,
+    QPAT_BATCH_JVP = 1,
+    QPAT_BATCH_VJP = 2,
+    QPAT_BATCH_PAIR = 3,
+    QPAT_BATCH_LSQR_STEP = 4
+} qpat_batch_op;
+qpat_status qpat_batch(qpat_ctx* const* ctxs, int32_t n, int32_t op, const double* const* in0, double* const* out0,
+                       const double* const* in1, double* const* out1, qpat_info* infos);
+
 /* Storage of the PCG operators. out[0] = 1 when the node numbering was
  * recognised as a lattice (the stencil form exists), out[1..3] = nx, ny, nz,
  * out[4] = stored stencil arrays per operator (diagonal + upper offsets),

@@ -6,6 +6,8 @@
 #include <cstring>
 #include <algorithm>
 
+#include <thread>
+
 #include "qpat_internal.h"
 
 namespace qpat {
@@ -503,6 +505,56 @@ qpat_status qpat_lsqr_step(qpat_ctx* c, double* resnorm_out, qpat_info* info) {
     QPAT_TRY(lsqr_step_core(c, &st));
     if (resnorm_out) *resnorm_out = std::fabs(c->ls_host->phibar);
     return finish(c, st, info);
+}
+
+qpat_status qpat_batch(qpat_ctx* const* ctxs, int32_t n, int32_t op, const double* const* in0, double* const* out0,
+                       const double* const* in1, double* const* out1, qpat_info* infos) {
+    if (!ctxs || n < 1 || n > 256 || op < QPAT_BATCH_FORWARD || op > QPAT_BATCH_LSQR_STEP) return QPAT_ERR_ARG;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return QPAT_ERR_ARG;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i] || ctxs[j]->stream == ctxs[i]->stream)
+                return fail(ctxs[i], QPAT_ERR_ARG, "batch: contexts %d and %d share a context or a stream", j, i);
+        const bool need0 = op != QPAT_BATCH_LSQR_STEP, need1 = op == QPAT_BATCH_FORWARD || op == QPAT_BATCH_PAIR;
+        if ((need0 && (!in0 || !in0[i])) || (need1 && (!in1 || !in1[i])) ||
+            ((op == QPAT_BATCH_JVP || op == QPAT_BATCH_VJP || op == QPAT_BATCH_PAIR) && (!out0 || !out0[i])) ||
+            (op == QPAT_BATCH_PAIR && (!out1 || !out1[i])))
+            return fail(ctxs[i], QPAT_ERR_ARG, "batch: missing array for instance %d", i);
+    }
+    std::vector<qpat_status> st(n, QPAT_OK);
+    std::vector<qpat_info> inf(n);
+    auto work = [&](int i) {
+        qpat_ctx* c = ctxs[i];
+        qpat_info a{}, b{};
+        switch (op) {
+            case QPAT_BATCH_FORWARD:
+                st[i] = qpat_forward(c, in0[i], in1[i], nullptr, out0 ? out0[i] : nullptr, &a);
+                break;
+            case QPAT_BATCH_JVP: st[i] = qpat_jvp(c, in0[i], out0[i], &a); break;
+            case QPAT_BATCH_VJP: st[i] = qpat_vjp(c, in0[i], out0[i], &a); break;
+            case QPAT_BATCH_PAIR:
+                st[i] = qpat_jvp(c, in0[i], out0[i], &a);
+                if (st[i] == QPAT_OK) st[i] = qpat_vjp(c, in1[i], out1[i], &b);
+                a.n_solves += b.n_solves;
+                a.iters_max = std::max(a.iters_max, b.iters_max);
+                a.iters_sum += b.iters_sum;
+                a.updates += b.updates;
+                a.relres_max = std::max(a.relres_max, b.relres_max);
+                break;
+            default: st[i] = qpat_lsqr_step(c, nullptr, &a); break;
+        }
+        inf[i] = a;
+    };
+    std::vector<std::thread> pool;
+    pool.reserve(n - 1);
+    for (int i = 1; i < n; ++i) pool.emplace_back(work, i);
+    work(0);
+    for (auto& t : pool) t.join();
+    if (infos)
+        for (int i = 0; i < n; ++i) infos[i] = inf[i];
+    for (int i = 0; i < n; ++i)
+        if (st[i] != QPAT_OK) return st[i];
+    return QPAT_OK;
 }
 
 qpat_status qpat_profile(qpat_ctx* c, int32_t enable) {

@@ -85,6 +85,8 @@ SIGNATURES = {
     "qpat_profile": (_S, [_P, _I32]),
     "qpat_profile_read": (_S, [_P, ctypes.POINTER(KStat)]),
     "qpat_operator_layout": (_S, [_P, ctypes.POINTER(_I64)]),
+    "qpat_batch": (_S, [ctypes.POINTER(_P), _I32, _I32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                        ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(Info)]),
     "qpat_forward_x0": (_S, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_guess_setup": (_S, [_P, _I32, _I32, _I32]),
     "qpat_guess_set_params": (_S, [_P, _P]),
@@ -353,6 +355,32 @@ class Context:
         self._check(_lib.qpat_operator_layout(self._h, arr))
         return {"lattice": bool(arr[0]), "nx": arr[1], "ny": arr[2], "nz": arr[3], "stencil_arrays": arr[4],
                 "sell_len": arr[5]}
+
+
+BATCH_OPS = {"forward": 0, "jvp": 1, "vjp": 2, "pair": 3, "lsqr_step": 4}
+
+
+def batch(ctxs, op, in0=None, out0=None, in1=None, out1=None):
+    """One call on several contexts at once (each on its own stream); returns
+    the per-instance info dicts. Arrays are lists with one tensor per context
+    (None where the call takes none)."""
+    n = len(ctxs)
+    hs = (_P * n)(*[c._h.value for c in ctxs])
+
+    def ptrs(lst, what, dtype=torch.float64):
+        if lst is None:
+            return None
+        arr = (_P * n)()
+        for i, t in enumerate(lst):
+            arr[i] = None if t is None else _ptr(t, dtype, name=f"{what}[{i}]").value
+        return arr
+    infos = (Info * n)()
+    st = _lib.qpat_batch(hs, n, BATCH_OPS[op], ptrs(in0, "in0"), ptrs(out0, "out0"), ptrs(in1, "in1"),
+                         ptrs(out1, "out1"), infos)
+    if st != 0:
+        bad = next((c for c in ctxs if c.last_error()), ctxs[0])
+        raise QpatError(st, bad.last_error())
+    return [infos[i].as_dict() for i in range(n)]
 
 
 def version():

@@ -8,18 +8,18 @@ that a user of the method would also have to supply.
 Random streams: ``numpy.random.default_rng([1512, cfg, stream])`` with
 stream 0 = phantom, 1 = noise draws, 2 = test vectors s and t,
 3 = training samples of the learned guess, 4 = held-out samples, 5 = initial
-network weights.
+network weights, 6 = sizes of the batched instances.
 """
 from .mesh import kuhn_mesh, KuhnMesh, FACE_NAMES
 from .phantom import (sphere_phantom, ellipsoid_phantom, background_phantom,
                       kappa_from_optics)
 from .sources import face_sources, gaussian_sources
-from .configs import CONFIGS, config, rng, make_problem, Problem
+from .configs import CONFIGS, config, rng, make_problem, Problem, batch_instances
 from .vectors import probe_vectors, noise_draws
 from .net import initial_params
 
 __all__ = [
     "kuhn_mesh", "KuhnMesh", "FACE_NAMES", "sphere_phantom", "ellipsoid_phantom",
     "background_phantom", "kappa_from_optics", "face_sources", "gaussian_sources",
-    "CONFIGS", "config", "rng", "make_problem", "Problem", "probe_vectors", "noise_draws", "initial_params",
+    "CONFIGS", "config", "rng", "make_problem", "Problem", "batch_instances", "probe_vectors", "noise_draws", "initial_params",
 ]

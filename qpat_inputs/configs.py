@@ -31,6 +31,9 @@ CONFIGS = {
     # batched + mixed: 128^3, 16 Gaussian sources in one block solve
     "C3": dict(id=3, n=128, n_ill=16, source="gauss", phantom="ellipsoids",
                noise=0.02, outer=3, inner=30, precision="mixed"),
+    # batched instances: template of the 32 uneven instances (sizes from batch_instances)
+    "C4": dict(id=4, n=48, n_ill=8, source="gauss", phantom="ellipsoids",
+               noise=0.02, outer=3, inner=30, precision="mixed"),
     # learned initial guess: 96^3, 8 illuminations
     "C5": dict(id=5, n=96, n_ill=8, source="gauss", phantom="ellipsoids",
                noise=0.02, outer=3, inner=30, precision="mixed"),
@@ -46,6 +49,15 @@ CONFIGS = {
 }
 
 METHOD = dict(T=5e-3, delta=1e-6, b_over_a=1.0, m0=10, tau=1e-2, pcg_rtol=1e-10)
+
+
+def batch_instances(count=32, cfg_id=4):
+    """Sizes of the batched-instance workload: n ~ U{24..96} voxels per side,
+    n_ill ~ U{4..12}, drawn from stream 6; instance i uses phantom id 1000 cfg_id + i."""
+    g = rng(cfg_id, 6)
+    n = g.integers(24, 97, size=count)
+    k = g.integers(4, 13, size=count)
+    return [dict(n=int(n[i]), n_ill=int(k[i]), id=1000 * int(cfg_id) + i) for i in range(count)]
 
 
 def config(name, **over):
