@@ -275,17 +275,20 @@ __global__ __launch_bounds__(kMgT) void k_mg_first(SmArgs a, const double* __res
 
 // y = x + w D^{-1} (b - A x)
 template <int KIND>
+// The two systems are swept one after the other by the same blocks (not
+// side by side): each XCD's L2 then holds the band of one system only.
 __global__ __launch_bounds__(kMgT) void k_mg_smooth(SmArgs a, const double* __restrict__ b,
                                                     const double* __restrict__ x, double* __restrict__ y) {
-    const int sys = blockIdx.y;
-    if (!a.sc[sys].active) return;
-    const double w = a.w[sys * a.nlev + a.lev];
-    const int M1 = a.L.m + 1;
-    const int64_t o = sys * a.L.N;
-    const double* U = a.L.U + o * M1;
-    QPAT_MG_ROWS(i, a.L.N) {
-        const double ax = st_apply<KIND>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, x + o, (int32_t)i);
-        y[o + i] = x[o + i] + w * a.dinv[o + i] * (b[o + i] - ax);
+    for (int sys = 0; sys < 2; ++sys) {
+        if (!a.sc[sys].active) continue;
+        const double w = a.w[sys * a.nlev + a.lev];
+        const int M1 = a.L.m + 1;
+        const int64_t o = sys * a.L.N;
+        const double* U = a.L.U + o * M1;
+        QPAT_MG_ROWS(i, a.L.N) {
+            const double ax = st_apply<KIND>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, x + o, (int32_t)i);
+            y[o + i] = x[o + i] + w * a.dinv[o + i] * (b[o + i] - ax);
+        }
     }
 }
 
@@ -293,13 +296,14 @@ __global__ __launch_bounds__(kMgT) void k_mg_smooth(SmArgs a, const double* __re
 template <int KIND>
 __global__ __launch_bounds__(kMgT) void k_mg_resid(SmArgs a, const double* __restrict__ b,
                                                    const double* __restrict__ x, double* __restrict__ r) {
-    const int sys = blockIdx.y;
-    if (!a.sc[sys].active) return;
-    const int M1 = a.L.m + 1;
-    const int64_t o = sys * a.L.N;
-    const double* U = a.L.U + o * M1;
-    QPAT_MG_ROWS(i, a.L.N)
-        r[o + i] = b[o + i] - st_apply<KIND>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, x + o, (int32_t)i);
+    for (int sys = 0; sys < 2; ++sys) {
+        if (!a.sc[sys].active) continue;
+        const int M1 = a.L.m + 1;
+        const int64_t o = sys * a.L.N;
+        const double* U = a.L.U + o * M1;
+        QPAT_MG_ROWS(i, a.L.N)
+            r[o + i] = b[o + i] - st_apply<KIND>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, x + o, (int32_t)i);
+    }
 }
 
 // bc = P^T r
@@ -403,19 +407,20 @@ __global__ __launch_bounds__(kMgT) void k_mgp_dir(PcgMg a) {
 template <int KIND>
 __global__ __launch_bounds__(kMgT) void k_mgp_spmv(PcgMg a) {
     __shared__ double sm[kMgT / 64];
-    const int sys = blockIdx.y;
-    if (!a.sc[sys].active) return;
-    const int M1 = a.L.m + 1;
-    const int64_t o = sys * a.L.N;
-    const double* U = a.L.U + o * M1;
-    double pq = 0.0;
-    QPAT_MG_ROWS(i, a.L.N) {
-        const double v = st_apply<KIND>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, a.p + o, (int32_t)i);
-        a.q[o + i] = v;
-        pq += a.p[o + i] * v;
+    for (int sys = 0; sys < 2; ++sys) {
+        if (!a.sc[sys].active) continue;
+        const int M1 = a.L.m + 1;
+        const int64_t o = sys * a.L.N;
+        const double* U = a.L.U + o * M1;
+        double pq = 0.0;
+        QPAT_MG_ROWS(i, a.L.N) {
+            const double v = st_apply<KIND>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, a.p + o, (int32_t)i);
+            a.q[o + i] = v;
+            pq += a.p[o + i] * v;
+        }
+        pq = bsum(pq, sm);
+        if (threadIdx.x == 0) put(a.parts, sys, 0, pq);
     }
-    pq = bsum(pq, sm);
-    if (threadIdx.x == 0) put(a.parts, sys, 0, pq);
 }
 
 // x += alpha p, r -= alpha q, partial r.r
@@ -557,18 +562,20 @@ __global__ __launch_bounds__(kMgT) void k_mgp_start(PcgMg a, double* __restrict_
 // true residual r = b - A x, partial r.r (restart of a run: r replaces the recursive residual)
 __global__ __launch_bounds__(kMgT) void k_mgp_true(PcgMg a, const double* __restrict__ b) {
     __shared__ double sm[kMgT / 64];
-    const int sys = blockIdx.y;
-    const int M1 = a.L.m + 1;
-    const int64_t o = sys * a.L.N;
-    const double* U = a.L.U + o * M1;
-    double rr = 0.0;
-    QPAT_MG_ROWS(i, a.L.N) {
-        const double ri = b[o + i] - st_row<false>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, a.x + o, (int32_t)i);
-        a.r[o + i] = ri;
-        rr += ri * ri;
+    for (int sys = 0; sys < 2; ++sys) {
+        const int M1 = a.L.m + 1;
+        const int64_t o = sys * a.L.N;
+        const double* U = a.L.U + o * M1;
+        double rr = 0.0;
+        QPAT_MG_ROWS(i, a.L.N) {
+            const double ri =
+                b[o + i] - st_row<false>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, a.x + o, (int32_t)i);
+            a.r[o + i] = ri;
+            rr += ri * ri;
+        }
+        rr = bsum(rr, sm);
+        if (threadIdx.x == 0) put(a.parts, sys, 1, rr);
     }
-    rr = bsum(rr, sm);
-    if (threadIdx.x == 0) put(a.parts, sys, 1, rr);
 }
 
 __global__ void k_mgp_true_fin(PcgMg a, int reopen) {
@@ -600,6 +607,8 @@ inline LvArgs lv_args(const MgLevel& L) {
 
 // a multiple of 8 blocks per system (the XCD row split), at most kMgBlocks
 inline dim3 vgrid(int64_t n) { return dim3((grid_for(n, kMgT, kMgBlocks) + 7) & ~7, 2); }
+// the stencil kernels loop over the two systems themselves
+inline dim3 sgrid(int64_t n) { return dim3(vgrid(n).x, 1); }
 
 #define QPAT_MG_KIND(kind, KERNEL, ...)                                                   \
     switch (kind) {                                                                        \
@@ -669,10 +678,10 @@ double* vcycle(qpat_ctx* c, hipStream_t st, bool launch = true) {
         const SmArgs a = sm(l);
         hipLaunchKernelGGL(k_mg_first, vgrid(L.N), dim3(kMgT), 0, st, a, L.b, xl[l]);
         for (int k = 1; k < kMgNu; ++k) {
-            QPAT_MG_KIND(L.kind, k_mg_smooth, vgrid(L.N), dim3(kMgT), 0, st, a, L.b, xl[l], tl[l]);
+            QPAT_MG_KIND(L.kind, k_mg_smooth, sgrid(L.N), dim3(kMgT), 0, st, a, L.b, xl[l], tl[l]);
             std::swap(xl[l], tl[l]);
         }
-        QPAT_MG_KIND(L.kind, k_mg_resid, vgrid(L.N), dim3(kMgT), 0, st, a, L.b, xl[l], L.r);
+        QPAT_MG_KIND(L.kind, k_mg_resid, sgrid(L.N), dim3(kMgT), 0, st, a, L.b, xl[l], L.r);
         hipLaunchKernelGGL(k_mg_restrict, vgrid(C.N), dim3(kMgT), 0, st, L.nx, L.ny, L.nz, C.nx, C.ny, C.nz, L.r, C.b,
                            M.sc);
     }
@@ -685,7 +694,7 @@ double* vcycle(qpat_ctx* c, hipStream_t st, bool launch = true) {
         hipLaunchKernelGGL(k_mg_prolong, vgrid(L.N), dim3(kMgT), 0, st, L.nx, L.ny, L.nz, C.nx, C.ny, C.nz, xl[l + 1],
                            xl[l], M.sc);
         for (int k = 0; k < kMgNu; ++k) {
-            QPAT_MG_KIND(L.kind, k_mg_smooth, vgrid(L.N), dim3(kMgT), 0, st, a, L.b, xl[l], tl[l]);
+            QPAT_MG_KIND(L.kind, k_mg_smooth, sgrid(L.N), dim3(kMgT), 0, st, a, L.b, xl[l], tl[l]);
             std::swap(xl[l], tl[l]);
         }
     }
@@ -715,7 +724,7 @@ PcgMg pcg_args(qpat_ctx* c) {
 void iteration(qpat_ctx* c, const PcgMg& a, hipStream_t st) {
     const dim3 g = vgrid(a.L.N), one(1, 2);
     hipLaunchKernelGGL(k_mgp_dir, g, dim3(kMgT), 0, st, a);
-    QPAT_MG_KIND(a.L.kind, k_mgp_spmv, g, dim3(kMgT), 0, st, a);
+    QPAT_MG_KIND(a.L.kind, k_mgp_spmv, sgrid(a.L.N), dim3(kMgT), 0, st, a);
     hipLaunchKernelGGL(k_mgp_scalars, one, dim3(kMgT), 0, st, a, 0);
     hipLaunchKernelGGL(k_mgp_update, g, dim3(kMgT), 0, st, a);
     hipLaunchKernelGGL(k_mgp_scalars, one, dim3(kMgT), 0, st, a, 1);
@@ -917,7 +926,7 @@ qpat_status mg_solve(qpat_ctx* c, SolveStats* st) {
             chunk = std::min(chunk * 2, 16);
         }
         // confirm on the true residual; a failed check restarts from the true residual
-        hipLaunchKernelGGL(k_mgp_true, g, dim3(kMgT), 0, sm, a, c->b64);
+        hipLaunchKernelGGL(k_mgp_true, sgrid(c->N), dim3(kMgT), 0, sm, a, c->b64);
         hipLaunchKernelGGL(k_mgp_true_fin, one, dim3(kMgT), 0, sm, a, restart < 3 ? 1 : 0);
         QPAT_HIP(c, hipGetLastError());
         QPAT_TRY(fetch());
