@@ -74,6 +74,10 @@ typedef struct {
     int32_t prior_precond;  /* M_delta solves: 1 = PCG with a geometric multigrid V-cycle
                                (lattice meshes with the stencil form; otherwise Jacobi),
                                0 = Jacobi-PCG. Same stopping rule either way.               */
+    int32_t pcg_precond;    /* K solves: 1 = PCG with a geometric multigrid V-cycle in FP64
+                               (lattice meshes with the stencil form; elsewhere, and with
+                               0, Jacobi-PCG in the arithmetic `precision` selects). Same
+                               stopping rule either way.                                      */
 } qpat_opts;
 
 typedef struct {

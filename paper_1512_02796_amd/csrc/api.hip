@@ -65,6 +65,7 @@ qpat_status check_opts(qpat_ctx* c, const qpat_opts* o) {
     if (o->operator_format != 0 && o->operator_format != 1)
         return fail(c, QPAT_ERR_ARG, "operator_format must be 0 or 1");
     if (o->prior_precond != 0 && o->prior_precond != 1) return fail(c, QPAT_ERR_ARG, "prior_precond must be 0 or 1");
+    if (o->pcg_precond != 0 && o->pcg_precond != 1) return fail(c, QPAT_ERR_ARG, "pcg_precond must be 0 or 1");
     return QPAT_OK;
 }
 
@@ -179,6 +180,7 @@ void qpat_default_opts(qpat_opts* o) {
     o->use_graphs = 1;
     o->operator_format = 1;
     o->prior_precond = 1;
+    o->pcg_precond = 1;
 }
 
 const char* qpat_version(void) { return "qpat 0.1 (gfx950)"; }
@@ -257,6 +259,7 @@ static qpat_status forward_common(qpat_ctx* c, double* phi_out, double* h_out, q
                                   const double* x0 = nullptr) {
     QPAT_TRY(assemble_K(c));
     QPAT_TRY(lattice_convert(c, Op::K));
+    QPAT_TRY(mg_setup(c, Op::K));
     SolveStats st;
     c->have_forward = false;
     c->lsqr_ready = false;
@@ -435,7 +438,7 @@ qpat_status qpat_prior_setup(qpat_ctx* c, const double* kt, const double* mt, do
     QPAT_TRY(assemble_prior(c, kt, mt, T, b_over_a, delta));
     QPAT_TRY(lattice_convert(c, Op::Prior));
     c->delta = delta;
-    QPAT_TRY(mg_setup(c));
+    QPAT_TRY(mg_setup(c, Op::Prior));
     c->have_prior = true;
     c->lsqr_ready = false;
     QPAT_HIP(c, hipStreamSynchronize(c->stream));

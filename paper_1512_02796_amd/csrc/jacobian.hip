@@ -268,12 +268,19 @@ int block_size(const qpat_ctx* c) {
 
 }  // namespace
 
+// K x = b for one block of B right-hand sides: multigrid-preconditioned PCG
+// where its hierarchy is built, Jacobi-PCG otherwise
+static qpat_status k_solve(qpat_ctx* c, int B, SolveStats* st, bool has_x0 = false) {
+    if (mg_ready(c, Op::K)) return mg_solve(c, Op::K, B, st, has_x0);
+    return pcg_solve(c, Op::K, B, st, has_x0);
+}
+
 qpat_status forward_solve(qpat_ctx* c, SolveStats* st) {
     const int B = block_size(c);
     const dim3 g(grid_for(c->N * B, kThreads, 1 << 30)), blk(kThreads);
     for (int col0 = 0; col0 < c->n_pad; col0 += B) {
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_pack<BB>, g, blk, 0, c->stream, c->N, c->f, c->n_pad, col0, c->b64));
-        QPAT_TRY(pcg_solve(c, Op::K, B, st));
+        QPAT_TRY(k_solve(c, B, st));
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_unpack<BB>, g, blk, 0, c->stream, c->N, c->x64, c->n_pad, col0, c->phi));
     }
     QPAT_HIP(c, hipGetLastError());
@@ -287,7 +294,7 @@ qpat_status forward_solve_x0(qpat_ctx* c, const double* x0, SolveStats* st) {
     for (int col0 = 0; col0 < c->n_pad; col0 += B) {
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_pack<BB>, g, blk, 0, c->stream, c->N, c->f, c->n_pad, col0, c->b64));
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_pack_ext<BB>, g, blk, 0, c->stream, c->N, x0, c->n_ill, col0, c->x64));
-        QPAT_TRY(pcg_solve(c, Op::K, B, st, true));
+        QPAT_TRY(k_solve(c, B, st, true));
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_unpack<BB>, g, blk, 0, c->stream, c->N, c->x64, c->n_pad, col0, c->phi));
     }
     QPAT_HIP(c, hipGetLastError());
@@ -301,7 +308,7 @@ qpat_status jvp_core(qpat_ctx* c, const double* s, int mode, double* out, SolveS
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gfwd<BB>, dim3(grid_for(c->N * (BB / kGroup<BB>), kThreads, 1 << 30)),
                                               blk, 0, c->stream, c->N, c->tets, c->geo, c->n2t_ptr, c->n2t, c->kappa,
                                               c->mu, s, c->phi, c->n_pad, col0, c->b64));
-        QPAT_TRY(pcg_solve(c, Op::K, B, st));
+        QPAT_TRY(k_solve(c, B, st));
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_jvp_out<BB>, g, blk, 0, c->stream, c->N, c->mu, c->phi, s, c->x64,
                                               c->n_pad, c->n_ill, col0, mode, out, c->lw, c->lu, c->ls));
     }
@@ -319,7 +326,7 @@ qpat_status vjp_core(qpat_ctx* c, const double* t, int mode, double* out, SolveS
     for (int col0 = 0; col0 < c->n_pad; col0 += B) {
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_adj_rhs<BB>, g, blk, 0, c->stream, c->N, c->mu, c->n_pad, c->n_ill,
                                               col0, tmode, t, c->lw, c->lu, c->b64));
-        QPAT_TRY(pcg_solve(c, Op::K, B, st));
+        QPAT_TRY(k_solve(c, B, st));
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gadj<BB>, dim3(grid_for(c->N * (BB / kGroup<BB>), kThreads, 1 << 30)),
                                               blk, 0, c->stream, c->N, c->tets, c->geo, c->n2t_ptr, c->n2t, c->phi,
                                               c->n_pad, c->n_ill, col0, c->x64, tmode, t, c->lw, c->lu,

@@ -314,8 +314,8 @@ qpat_status prior_apply_core(qpat_ctx* c, const double* x, double* y) {
 qpat_status prior_solve_core(qpat_ctx* c, const double* p, double* r, SolveStats* st) {
     const int64_t n2 = 2 * c->N;
     hipLaunchKernelGGL(k_copy, grid1(n2), dim3(kThreads), 0, c->stream, n2, p, c->b64);
-    if (c->mg && mg_available(c))
-        QPAT_TRY(mg_solve(c, st));
+    if (mg_ready(c, Op::Prior))
+        QPAT_TRY(mg_solve(c, Op::Prior, 1, st));
     else
         QPAT_TRY(pcg_solve(c, Op::Prior, 1, st));
     hipLaunchKernelGGL(k_prior_out, dim3(grid_for(c->N, kThreads, 4096), 2), dim3(kThreads), 0, c->stream, c->N,

@@ -1,21 +1,27 @@
-// Geometric multigrid preconditioner for the M_delta solves on lattice meshes.
+// Geometric multigrid preconditioner for the K and M_delta solves on lattice
+// meshes.
 //
-// Each block of M_delta (Sec. 4 eqs. (4.5), (4.8)) is an SPD FEM matrix on the
-// node lattice. The solve is PCG preconditioned by one symmetric V-cycle:
+// K (the forward and adjoint diffusion operator, Sec. 2 and the Appendix) and
+// each block of M_delta (Sec. 4 eqs. (4.5), (4.8)) are SPD FEM matrices on the
+// node lattice. Their solves are PCG preconditioned by one symmetric V-cycle:
 //   * levels: the lattice and its vertex-centred coarsenings, n -> n/2 + 1 per
 //     axis, down to at most kMgCoarse nodes per axis;
 //   * prolongation P: trilinear interpolation (weights 1, 1/2 per axis),
 //     restriction P^T;
 //   * coarse operators by Galerkin products A_c = P^T A P, stored like the fine
 //     stencil form (diagonal + upper offsets, node-major), 27-point;
-//   * smoother: kMgNu Jacobi sweeps before and after the coarse correction,
-//     weight 4/(3 g) with g >= lambda_max(D^{-1} A) the Gershgorin bound;
+//   * smoother: kMgNu weighted Jacobi sweeps before and after the coarse
+//     correction, weight 4/(3 g) with g >= lambda_max(D^{-1} A) the Gershgorin
+//     bound;
 //   * coarsest level: the explicit inverse (dense, computed on the host).
-// With deflation (the exact eigenpair (delta, 1) of each block) the solve runs
-// on the complement of the constants as the Jacobi-PCG path does: b <- b -
-// mean(b), z <- V(r) - mean(V(r)), and the mean of the solution is mean(b)/delta.
-// The stopping rule is the same: ||b - A x||_2 <= rtol ||b||_2 on the FP64
-// residual, confirmed on the true residual at the end.
+// Vectors hold B right-hand sides interleaved ([sys][N][B]); every lane
+// (system, right-hand side) has its own PCG scalars and stops on its own.
+// With deflation (M_delta: the exact eigenpair (delta, 1) of each block) the
+// solve runs on the complement of the constants as the Jacobi-PCG path does:
+// b <- b - mean(b), z <- V(r) - mean(V(r)), and the mean of the solution is
+// mean(b)/delta. The stopping rule is the same as Jacobi-PCG's:
+// ||b - A x||_2 <= rtol ||b||_2 on the FP64 residual, confirmed on the true
+// residual at the end. Everything is FP64.
 #include <cmath>
 #include <cstring>
 
@@ -30,12 +36,12 @@ struct MgLevel {
     int32_t kind = 0;              // row kernel: 0 generic table, 1 Kuhn offsets, 2 full 27-point
     const int4* tab = nullptr;     // [m]: dx, dy, dz, dx + nx (dy + ny dz)
     int4* tab_own = nullptr;
-    double* U = nullptr;           // [2][N][m+1] (level 0: the context's MU64)
-    double* dinv = nullptr;        // [2][N] 1 / a_ii
-    double* b = nullptr;           // [2][N] (level 0: the PCG residual)
-    double* x = nullptr;           // [2][N]
-    double* t = nullptr;           // [2][N] ping-pong partner of x
-    double* r = nullptr;           // [2][N] residual before restriction
+    double* U = nullptr;           // [nsys][N][m+1] (level 0: the context's stencil arrays)
+    double* dinv = nullptr;        // [nsys][N] 1 / a_ii
+    double* b = nullptr;           // [nsys][N][B] (level 0: the PCG residual)
+    double* x = nullptr;           // [nsys][N][B]
+    double* t = nullptr;           // ping-pong partner of x
+    double* r = nullptr;           // residual before restriction
 };
 
 struct MgScal {
@@ -43,16 +49,25 @@ struct MgScal {
     int32_t active, done, iters, pad;
 };
 
+// Tiling of the finest level for one block size (LDS-tiled kernels)
+struct TileGeo {
+    bool ready = false, on = false;
+    int32_t tiles_x = 0, tiles_y = 0, zc = 0, items = 0;
+};
+
 struct MgState {
+    int32_t nsys = 1;              // 1 (K) or 2 (the blocks of M_delta)
+    int32_t bmax = 1;              // right-hand sides the vectors are sized for
+    bool current = false;          // built from the operator now assembled
     std::vector<MgLevel> lv;
-    double* w = nullptr;           // [2][levels] Jacobi weights
-    double* ainv = nullptr;        // [2][Nc][Nc]
-    double *pr = nullptr, *pp = nullptr, *pq = nullptr;  // PCG r, p, q: [2][N]
-    double* parts = nullptr;       // [2][4][kMgBlocks]
-    uint64_t* gmax = nullptr;      // [2][levels] Gershgorin bounds (bit patterns)
-    MgScal* sc = nullptr;          // [2]
+    double* w = nullptr;           // [nsys][levels] Jacobi weights
+    double* ainv = nullptr;        // [nsys][Nc][Nc]
+    double *pr = nullptr, *pa = nullptr, *pb = nullptr, *pq = nullptr;  // PCG r, p (two), q: [nsys][N][bmax]
+    double* parts = nullptr;       // [lanes][4][kMgBlocks]
+    uint64_t* gmax = nullptr;      // [nsys][levels] Gershgorin bounds (bit patterns)
+    MgScal* sc = nullptr;          // [lanes], lane = sys B + k
     MgScal* sc_host = nullptr;
-    double* zout = nullptr;        // where the V-cycle leaves z
+    std::map<int, TileGeo> tiles;  // by block size
     std::map<std::string, hipGraphExec_t> graphs;
     hipStream_t cap = nullptr;
 };
@@ -61,8 +76,9 @@ namespace {
 
 constexpr int kMgCoarse = 5;      // coarsest lattice: at most this many nodes per axis
 constexpr int kMgNu = 1;          // Jacobi sweeps before and after the coarse correction
-constexpr int kMgBlocks = 512;    // blocks per system of the vector kernels (partial sums)
+constexpr int kMgBlocks = 512;    // blocks of the vector kernels (partial sums)
 constexpr int kMgT = 256;
+constexpr int kMgLanes = 32;      // systems x right-hand sides
 
 __device__ __forceinline__ void coords(int32_t i, int nx, int ny, int& ix, int& iy, int& iz) {
     ix = i % nx;
@@ -71,86 +87,93 @@ __device__ __forceinline__ void coords(int32_t i, int nx, int ny, int& ix, int& 
     iz = q / ny;
 }
 
-// (A x)_i, and sum_j |a_ij| when ABS
-template <bool ABS>
+// (A x)_i of lane k (x interleaved [N][B]), and sum_j |a_ij| when ABS
+template <bool ABS, int B>
 __device__ __forceinline__ double st_row(const double* __restrict__ U, int M1, const int4* __restrict__ tab, int m,
-                                         int nx, int ny, int nz, const double* __restrict__ x, int32_t i) {
+                                         int nx, int ny, int nz, const double* __restrict__ x, int32_t i, int k) {
     int ix, iy, iz;
     coords(i, nx, ny, ix, iy, iz);
-    double s = ABS ? fabs(U[(int64_t)i * M1]) : U[(int64_t)i * M1] * x[i];
+    double s = ABS ? fabs(U[(int64_t)i * M1]) : U[(int64_t)i * M1] * x[(int64_t)i * B + k];
     for (int j = 0; j < m; ++j) {
         const int4 t = tab[j];
         const int ux = ix + t.x, uy = iy + t.y, uz = iz + t.z;
         if (ux >= 0 && ux < nx && uy >= 0 && uy < ny && uz < nz) {
             const double a = U[(int64_t)i * M1 + j + 1];
-            s += ABS ? fabs(a) : a * x[i + t.w];
+            s += ABS ? fabs(a) : a * x[(int64_t)(i + t.w) * B + k];
         }
         const int lx = ix - t.x, ly = iy - t.y, lz = iz - t.z;
         if (lx >= 0 && lx < nx && ly >= 0 && ly < ny && lz >= 0) {
             const double a = U[(int64_t)(i - t.w) * M1 + j + 1];
-            s += ABS ? fabs(a) : a * x[i - t.w];
+            s += ABS ? fabs(a) : a * x[(int64_t)(i - t.w) * B + k];
         }
     }
     return s;
 }
-
-// The same row with compile-time offsets: KIND 1 the Kuhn split (7 upper
-// offsets, the fine level), KIND 2 the full 27-point stencil (13 upper offsets
-// in code order, the Galerkin levels); KIND 0 the generic table. Interior rows
-// skip the lattice-edge tests.
+// The rows with compile-time offsets: KIND 1 the Kuhn split (7 upper offsets,
+// the fine level of a Kuhn mesh), KIND 2 the full 27-point stencil (13 upper
+// offsets in code order, the Galerkin levels); KIND 0 the generic table.
 constexpr int kKx[7] = {1, 0, 1, 0, 1, 0, 1};
 constexpr int kKy[7] = {0, 1, 1, 0, 0, 1, 1};
 constexpr int kKz[7] = {0, 0, 0, 1, 1, 1, 1};
 
-template <int KIND>
-__device__ __forceinline__ double st_apply(const double* __restrict__ U, int M1, const int4* __restrict__ tab, int m,
-                                           int nx, int ny, int nz, const double* __restrict__ x, int32_t i) {
-    if constexpr (KIND == 0) {
-        return st_row<false>(U, M1, tab, m, nx, ny, nz, x, i);
-    } else {
-        constexpr int MM = KIND == 1 ? 7 : 13;
-        int ix, iy, iz;
-        coords(i, nx, ny, ix, iy, iz);
-        const bool inner = ix > 0 && ix < nx - 1 && iy > 0 && iy < ny - 1 && iz > 0 && iz < nz - 1;
-        const double* __restrict__ Ui = U + (int64_t)i * (MM + 1);
-        double s = Ui[0] * x[i];
-#pragma unroll
-        for (int j = 0; j < MM; ++j) {
-            const int code = 14 + j;
-            const int dx = KIND == 1 ? kKx[j] : code % 3 - 1;
-            const int dy = KIND == 1 ? kKy[j] : (code / 3) % 3 - 1;
-            const int dz = KIND == 1 ? kKz[j] : code / 9 - 1;
-            const int32_t lin = dx + nx * (dy + ny * dz);
-            const bool up = inner || (ix + dx >= 0 && ix + dx < nx && iy + dy >= 0 && iy + dy < ny && iz + dz < nz);
-            const bool lo = inner || (ix - dx >= 0 && ix - dx < nx && iy - dy >= 0 && iy - dy < ny && iz - dz >= 0);
-            if (up) s += Ui[j + 1] * x[i + lin];
-            if (lo) s += U[(int64_t)(i - lin) * (MM + 1) + j + 1] * x[i - lin];
-        }
-        return s;
-    }
+// The stencil and V-cycle kernels give each thread V = 2 adjacent right-hand
+// sides of one node (16-byte loads and stores; the row of the operator is read
+// once for both); BV = B / V threads share a node.
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <int B>
+struct Pk {
+    static constexpr int V = B >= 2 ? 2 : 1;
+    static constexpr int BV = B / V;
+};
+template <int V>
+struct VecT {
+    using T = double;
+};
+template <>
+struct VecT<2> {
+    using T = d2v;
+};
+template <int B>
+using TB = typename VecT<Pk<B>::V>::T;
+
+template <typename T>
+__device__ __forceinline__ T vld(const double* p) {
+    return *reinterpret_cast<const T*>(p);
 }
+template <typename T>
+__device__ __forceinline__ void vst(double* p, T v) {
+    *reinterpret_cast<T*>(p) = v;
+}
+__device__ __forceinline__ double comp(double v, int) { return v; }
+__device__ __forceinline__ double comp(d2v v, int c) { return c ? v.y : v.x; }
 
-// XCD-aware row loop for the stencil kernels: block b runs on XCD b mod 8,
-// so each XCD takes a contiguous eighth of the rows and its blocks sweep it
-// together; the partner rows one plane back are then still in that XCD's L2.
-#define QPAT_MG_ROWS(i, N)                                                                      \
-    const int32_t _per = gridDim.x >> 3;                                                       \
-    const int64_t _chunk = ((N) + 7) / 8;                                                      \
-    const int64_t _lo = (blockIdx.x & 7) * _chunk;                                             \
-    const int64_t _hi = _lo + _chunk < (N) ? _lo + _chunk : (N);                               \
-    for (int64_t i = _lo + (int64_t)(blockIdx.x >> 3) * kMgT + threadIdx.x; i < _hi; i += (int64_t)_per * kMgT)
-
-__device__ __forceinline__ double bsum(double v, double* sm) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) sm[wave] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kMgT / 64; ++w) t += sm[w];
-    __syncthreads();
-    return t;
+// Node order of the stencil kernels. The blocks of XCD x (block b runs on XCD
+// b mod 8) take the y-strip [x ny / 8, (x + 1) ny / 8) of every plane (z-slabs
+// when ny < 8) and sweep it plane by plane, x fastest. The strip's planes
+// around the sweep (about 0.3 MB per plane of a 129^2 lattice with 16
+// right-hand sides) then stay in that XCD's 4 MB L2 while the up to 27
+// neighbours of every node are read, so each vector comes from HBM about
+// once. Calls f(ix, iy, iz, node, thread-in-node). The thread-in-node is
+// threadIdx.x mod BV for every element of a thread.
+template <int BV, typename F>
+__device__ __forceinline__ void walk(int32_t nx, int32_t ny, int32_t nz, F&& f) {
+    const int32_t xcd = blockIdx.x & 7;
+    int32_t y0 = 0, ys = ny, z0 = 0, zs = nz;
+    if (ny >= 8) {
+        y0 = xcd * ny / 8;
+        ys = (xcd + 1) * ny / 8 - y0;
+    } else {
+        z0 = xcd * nz / 8;
+        zs = (xcd + 1) * nz / 8 - z0;
+    }
+    const int32_t total = nx * ys * zs * BV;
+    const int32_t step = (gridDim.x >> 3) * kMgT;
+    for (int32_t e = (blockIdx.x >> 3) * kMgT + threadIdx.x; e < total; e += step) {
+        const int32_t v = e % BV, n = e / BV;
+        const int32_t ix = n % nx, q = n / nx;
+        const int32_t iy = y0 + q % ys, iz = z0 + q / ys;
+        f(ix, iy, iz, ix + nx * (iy + ny * iz), v);
+    }
 }
 
 struct LvArgs {
@@ -160,6 +183,98 @@ struct LvArgs {
     int64_t N;
     int32_t kind;         // 0 generic table, 1 Kuhn offsets, 2 full 27-point
 };
+
+// (A x)_i for the thread's V right-hand sides; x points at the thread's
+// first right-hand side of node 0 ([N][B] interleaved). Interior rows skip
+// the lattice-edge tests.
+template <int KIND, int B>
+__device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict__ U, const double* __restrict__ x,
+                                       int32_t ix, int32_t iy, int32_t iz, int32_t i) {
+    using T = TB<B>;
+    if constexpr (KIND == 0) {
+        const int32_t M1 = L.m + 1;
+        T s = U[i * M1] * vld<T>(x + i * B);
+        for (int j = 0; j < L.m; ++j) {
+            const int4 t = L.tab[j];
+            if (ix + t.x >= 0 && ix + t.x < L.nx && iy + t.y >= 0 && iy + t.y < L.ny && iz + t.z < L.nz)
+                s += U[i * M1 + j + 1] * vld<T>(x + (i + t.w) * B);
+            if (ix - t.x >= 0 && ix - t.x < L.nx && iy - t.y >= 0 && iy - t.y < L.ny && iz - t.z >= 0)
+                s += U[(i - t.w) * M1 + j + 1] * vld<T>(x + (i - t.w) * B);
+        }
+        return s;
+    } else {
+        constexpr int MM = KIND == 1 ? 7 : 13;
+        constexpr int M1 = MM + 1;   // even: the row is M1 / 2 16-byte loads
+        double u[M1];
+        const d2v* Ur = reinterpret_cast<const d2v*>(U + i * M1);
+#pragma unroll
+        for (int k = 0; k < M1 / 2; ++k) {
+            const d2v t = Ur[k];
+            u[2 * k] = t.x;
+            u[2 * k + 1] = t.y;
+        }
+        const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
+        T s = u[0] * vld<T>(x + i * B);
+#pragma unroll
+        for (int j = 0; j < MM; ++j) {
+            const int code = 14 + j;
+            const int dx = KIND == 1 ? kKx[j] : code % 3 - 1;
+            const int dy = KIND == 1 ? kKy[j] : (code / 3) % 3 - 1;
+            const int dz = KIND == 1 ? kKz[j] : code / 9 - 1;
+            const int32_t lin = dx + L.nx * (dy + L.ny * dz);
+            const bool up = inner || (ix + dx >= 0 && ix + dx < L.nx && iy + dy >= 0 && iy + dy < L.ny && iz + dz < L.nz);
+            const bool lo = inner || (ix - dx >= 0 && ix - dx < L.nx && iy - dy >= 0 && iy - dy < L.ny && iz - dz >= 0);
+            if (up) s += u[j + 1] * vld<T>(x + (i + lin) * B);
+            if (lo) s += U[(i - lin) * M1 + j + 1] * vld<T>(x + (i - lin) * B);
+        }
+        return s;
+    }
+}
+
+// plain grid-stride loop over n elements (one right-hand side each; the lane
+// of a thread is threadIdx.x mod B)
+#define QPAT_MG_ELEMS(e, n) \
+    for (int64_t e = blockIdx.x * (int64_t)kMgT + threadIdx.x; e < (n); e += (int64_t)gridDim.x * kMgT)
+
+// Sum over the threads with equal threadIdx.x mod G; the result is valid in
+// threads threadIdx.x < G (group threadIdx.x).
+template <int G>
+__device__ __forceinline__ double group_sum(double v, double* sm) {
+#pragma unroll
+    for (int off = 32; off >= G; off >>= 1) v += __shfl_xor(v, off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < G) sm[wave * G + lane] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < G)
+        for (int w = 0; w < kMgT / 64; ++w) t += sm[w * G + threadIdx.x];
+    __syncthreads();
+    return t;
+}
+
+// any of the V right-hand sides of thread-in-node v of system sys still iterating
+template <int B>
+__device__ __forceinline__ bool pair_active(const MgScal* sc, int sys, int v) {
+    bool on = false;
+#pragma unroll
+    for (int c = 0; c < Pk<B>::V; ++c) on = on || sc[sys * B + v * Pk<B>::V + c].active;
+    return on;
+}
+
+// partial sums of the block: parts[lane][slot][block]
+__device__ __forceinline__ void put(double* parts, int lane, int slot, double val) {
+    parts[(lane * 4 + slot) * kMgBlocks + blockIdx.x] = val;
+}
+
+// per-right-hand-side block sums of a V-wide accumulator, written as partials
+template <int B>
+__device__ __forceinline__ void put_sums(double* parts, int sys, int slot, TB<B> acc, double* sm) {
+#pragma unroll
+    for (int c = 0; c < Pk<B>::V; ++c) {
+        const double t = group_sum<Pk<B>::BV>(comp(acc, c), sm);
+        if (threadIdx.x < Pk<B>::BV) put(parts, sys * B + threadIdx.x * Pk<B>::V + c, slot, t);
+    }
+}
 
 // 1 / a_ii and the Gershgorin bound max_i sum_j |a_ij| / a_ii
 __global__ __launch_bounds__(kMgT) void k_mg_diag(LvArgs L, double* __restrict__ dinv, uint64_t* __restrict__ gmax,
@@ -172,7 +287,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_diag(LvArgs L, double* __restrict__
     for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * kMgT) {
         const double d = U[i * M1];
         dinv[sys * L.N + i] = 1.0 / d;
-        const double row = st_row<true>(U, M1, L.tab, L.m, L.nx, L.ny, L.nz, nullptr, static_cast<int32_t>(i));
+        const double row = st_row<true, 1>(U, M1, L.tab, L.m, L.nx, L.ny, L.nz, nullptr, static_cast<int32_t>(i), 0);
         g = fmax(g, row / d);
     }
 #pragma unroll
@@ -231,16 +346,13 @@ __global__ __launch_bounds__(kMgT) void k_mg_rap(LvArgs F, double* __restrict__ 
                 }
                 const int jx = fx + sx, jy = fy + sy, jz = fz + sz;
                 // coarse nodes J with j in their support: per axis one (even) or two (odd)
-                const int x0 = jx >> 1, x1 = (jx + 1) >> 1;
-                const int y0 = jy >> 1, y1 = (jy + 1) >> 1;
-                const int z0 = jz >> 1, z1 = (jz + 1) >> 1;
-                for (int Jz = z0; Jz <= z1; ++Jz) {
+                for (int Jz = jz >> 1; Jz <= (jz + 1) >> 1; ++Jz) {
                     if (Jz >= cz) continue;
                     const double wz = pw(jz - 2 * Jz);
-                    for (int Jy = y0; Jy <= y1; ++Jy) {
+                    for (int Jy = jy >> 1; Jy <= (jy + 1) >> 1; ++Jy) {
                         if (Jy >= cy) continue;
                         const double wy = pw(jy - 2 * Jy);
-                        for (int Jx = x0; Jx <= x1; ++Jx) {
+                        for (int Jx = jx >> 1; Jx <= (jx + 1) >> 1; ++Jx) {
                             if (Jx >= cx) continue;
                             const int code = (Jx - Ix + 1) + 3 * (Jy - Iy + 1) + 9 * (Jz - Iz + 1);
                             if (code < 13) continue;   // lower half: stored at the partner row
@@ -257,234 +369,349 @@ __global__ __launch_bounds__(kMgT) void k_mg_rap(LvArgs F, double* __restrict__ 
 
 struct SmArgs {
     LvArgs L;
-    const double* dinv;
-    const double* w;     // [2][levels]
-    int32_t nlev, lev;
-    const MgScal* sc;
+    const double* dinv;  // [nsys][N]
+    const double* w;     // [nsys][levels]
+    int32_t nlev, lev, nsys;
+    const MgScal* sc;    // [nsys][B]
 };
 
-// x = w D^{-1} b (first sweep from zero)
+// x = w D^{-1} b (the first sweep from zero; on the finest level only at the
+// start of a run, elsewhere the kernel that writes b also writes x)
+template <int B>
 __global__ __launch_bounds__(kMgT) void k_mg_first(SmArgs a, const double* __restrict__ b, double* __restrict__ x) {
-    const int sys = blockIdx.y;
-    if (!a.sc[sys].active) return;
-    const double w = a.w[sys * a.nlev + a.lev];
-    const int64_t o = sys * a.L.N;
-    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < a.L.N; i += (int64_t)gridDim.x * kMgT)
-        x[o + i] = w * a.dinv[o + i] * b[o + i];
+    const int k = threadIdx.x % B;
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        if (!a.sc[sys * B + k].active) continue;
+        const double w = a.w[sys * a.nlev + a.lev];
+        const int64_t o = sys * a.L.N * B;
+        const double* dinv = a.dinv + sys * a.L.N;
+        QPAT_MG_ELEMS(e, a.L.N * B) x[o + e] = w * dinv[e / B] * b[o + e];
+    }
 }
 
-// y = x + w D^{-1} (b - A x)
-template <int KIND>
-// The two systems are swept one after the other by the same blocks (not
-// side by side): each XCD's L2 then holds the band of one system only.
+// y = x + w D^{-1} (b - A x). The systems are swept one after the other by
+// the same blocks. DOTS (the last sweep on the finest level, where b = r and
+// y = z): also the partial sums r.z, sum z and sum r of every right-hand side.
+template <int KIND, int B, bool DOTS>
 __global__ __launch_bounds__(kMgT) void k_mg_smooth(SmArgs a, const double* __restrict__ b,
-                                                    const double* __restrict__ x, double* __restrict__ y) {
-    for (int sys = 0; sys < 2; ++sys) {
-        if (!a.sc[sys].active) continue;
+                                                    const double* __restrict__ x, double* __restrict__ y,
+                                                    double* __restrict__ parts) {
+    using T = TB<B>;
+    constexpr int V = Pk<B>::V;
+    __shared__ double sm[(kMgT / 64) * 16];
+    const int v = threadIdx.x % Pk<B>::BV;
+    const int32_t M1 = a.L.m + 1;
+    for (int sys = 0; sys < a.nsys; ++sys) {
         const double w = a.w[sys * a.nlev + a.lev];
-        const int M1 = a.L.m + 1;
-        const int64_t o = sys * a.L.N;
-        const double* U = a.L.U + o * M1;
-        QPAT_MG_ROWS(i, a.L.N) {
-            const double ax = st_apply<KIND>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, x + o, (int32_t)i);
-            y[o + i] = x[o + i] + w * a.dinv[o + i] * (b[o + i] - ax);
+        const double* U = a.L.U + sys * a.L.N * M1;
+        const double* dinv = a.dinv + sys * a.L.N;
+        const int64_t o = sys * a.L.N * B + v * V;
+        const double* bs = b + o;
+        const double* xs = x + o;
+        double* ys = y + o;
+        T rz = 0.0, z1 = 0.0, r1 = 0.0;
+        if (pair_active<B>(a.sc, sys, v)) {
+            walk<Pk<B>::BV>(a.L.nx, a.L.ny, a.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
+                const T bi = vld<T>(bs + i * B);
+                const T ax = apply<KIND, B>(a.L, U, xs, ix, iy, iz, i);
+                const T yi = vld<T>(xs + i * B) + (w * dinv[i]) * (bi - ax);
+                vst<T>(ys + i * B, yi);
+                if constexpr (DOTS) {
+                    rz += bi * yi;
+                    z1 += yi;
+                    r1 += bi;
+                }
+            });
+        }
+        if constexpr (DOTS) {
+            put_sums<B>(parts, sys, 0, rz, sm);
+            put_sums<B>(parts, sys, 2, z1, sm);
+            put_sums<B>(parts, sys, 3, r1, sm);
         }
     }
 }
 
 // r = b - A x
-template <int KIND>
+template <int KIND, int B>
 __global__ __launch_bounds__(kMgT) void k_mg_resid(SmArgs a, const double* __restrict__ b,
                                                    const double* __restrict__ x, double* __restrict__ r) {
-    for (int sys = 0; sys < 2; ++sys) {
-        if (!a.sc[sys].active) continue;
-        const int M1 = a.L.m + 1;
-        const int64_t o = sys * a.L.N;
-        const double* U = a.L.U + o * M1;
-        QPAT_MG_ROWS(i, a.L.N)
-            r[o + i] = b[o + i] - st_apply<KIND>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, x + o, (int32_t)i);
+    using T = TB<B>;
+    constexpr int V = Pk<B>::V;
+    const int v = threadIdx.x % Pk<B>::BV;
+    const int32_t M1 = a.L.m + 1;
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        if (!pair_active<B>(a.sc, sys, v)) continue;
+        const double* U = a.L.U + sys * a.L.N * M1;
+        const int64_t o = sys * a.L.N * B + v * V;
+        const double* bs = b + o;
+        const double* xs = x + o;
+        double* rs = r + o;
+        walk<Pk<B>::BV>(a.L.nx, a.L.ny, a.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
+            vst<T>(rs + i * B, vld<T>(bs + i * B) - apply<KIND, B>(a.L, U, xs, ix, iy, iz, i));
+        });
     }
 }
 
-// bc = P^T r
-__global__ __launch_bounds__(kMgT) void k_mg_restrict(int nx, int ny, int nz, int cx, int cy, int cz,
+// the two coarse nodes (or one) whose support holds fine node i along an
+// axis: J0 = i / 2 (weight 1 if i is even, 1/2 if odd) and J0 + 1 (1/2 if odd)
+struct Span {
+    int32_t j0, j1;
+    double w0, w1;
+    __device__ __forceinline__ Span(int32_t i, int32_t c) {
+        j0 = i >> 1;
+        const bool odd = i & 1;
+        j1 = min(j0 + (odd ? 1 : 0), c - 1);
+        w0 = odd ? 0.5 : 1.0;
+        w1 = odd ? 0.5 : 0.0;
+    }
+};
+
+// bc = P^T r on the coarse level c, and the first sweep there, xc = w D^{-1} bc.
+// Fine nodes 2 I + {-1, 0, 1} per axis, weights 1/2, 1, 1/2; the ones past
+// the lattice get weight 0 (their loads are clamped inside it).
+template <int B>
+__global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int32_t ny, int32_t nz,
                                                       const double* __restrict__ r, double* __restrict__ bc,
-                                                      const MgScal* __restrict__ sc) {
-    const int sys = blockIdx.y;
-    if (!sc[sys].active) return;
-    const int64_t Nf = (int64_t)nx * ny * nz, Nc = (int64_t)cx * cy * cz;
-    for (int64_t I = blockIdx.x * (int64_t)kMgT + threadIdx.x; I < Nc; I += (int64_t)gridDim.x * kMgT) {
-        int Ix, Iy, Iz;
-        coords((int32_t)I, cx, cy, Ix, Iy, Iz);
-        double s = 0.0;
-        for (int az = -1; az <= 1; ++az) {
-            const int fz = 2 * Iz + az;
-            if (fz < 0 || fz >= nz) continue;
-            for (int ay = -1; ay <= 1; ++ay) {
-                const int fy = 2 * Iy + ay;
-                if (fy < 0 || fy >= ny) continue;
-                for (int ax = -1; ax <= 1; ++ax) {
-                    const int fx = 2 * Ix + ax;
-                    if (fx < 0 || fx >= nx) continue;
-                    s += pw(ax) * pw(ay) * pw(az) * r[sys * Nf + fx + (int64_t)nx * (fy + (int64_t)ny * fz)];
-                }
+                                                      double* __restrict__ xc) {
+    using T = TB<B>;
+    constexpr int V = Pk<B>::V;
+    const int v = threadIdx.x % Pk<B>::BV;
+    const int64_t Nf = (int64_t)nx * ny * nz, Nc = c.L.N;
+    for (int sys = 0; sys < c.nsys; ++sys) {
+        if (!pair_active<B>(c.sc, sys, v)) continue;
+        const double w = c.w[sys * c.nlev + c.lev];
+        const double* dinv = c.dinv + sys * Nc;
+        const double* rs = r + sys * Nf * B + v * V;
+        const int64_t oc = sys * Nc * B + v * V;
+        walk<Pk<B>::BV>(c.L.nx, c.L.ny, c.L.nz, [&](int32_t Ix, int32_t Iy, int32_t Iz, int32_t I, int32_t) {
+            int32_t fx[3], fy[3], fz[3];
+            double wx[3], wy[3], wz[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int32_t gx = 2 * Ix + d - 1, gy = 2 * Iy + d - 1, gz = 2 * Iz + d - 1;
+                const double wd = d == 1 ? 1.0 : 0.5;
+                wx[d] = gx >= 0 && gx < nx ? wd : 0.0;
+                wy[d] = gy >= 0 && gy < ny ? wd : 0.0;
+                wz[d] = gz >= 0 && gz < nz ? wd : 0.0;
+                fx[d] = min(max(gx, 0), nx - 1);
+                fy[d] = min(max(gy, 0), ny - 1);
+                fz[d] = min(max(gz, 0), nz - 1);
             }
-        }
-        bc[sys * Nc + I] = s;
+            T s = 0.0;
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const int32_t row = nx * (fy[dy] + ny * fz[dz]);
+                    const double wyz = wy[dy] * wz[dz];
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) s += (wyz * wx[dx]) * vld<T>(rs + (row + fx[dx]) * B);
+                }
+            vst<T>(bc + oc + I * B, s);
+            vst<T>(xc + oc + I * B, (w * dinv[I]) * s);
+        });
     }
 }
 
-// x += P xc
-__global__ __launch_bounds__(kMgT) void k_mg_prolong(int nx, int ny, int nz, int cx, int cy, int cz,
-                                                     const double* __restrict__ xc, double* __restrict__ x,
-                                                     const MgScal* __restrict__ sc) {
-    const int sys = blockIdx.y;
-    if (!sc[sys].active) return;
-    const int64_t Nf = (int64_t)nx * ny * nz, Nc = (int64_t)cx * cy * cz;
-    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < Nf; i += (int64_t)gridDim.x * kMgT) {
-        int ix, iy, iz;
-        coords((int32_t)i, nx, ny, ix, iy, iz);
-        double s = 0.0;
-        for (int Jz = iz >> 1; Jz <= (iz + 1) >> 1; ++Jz) {
-            if (Jz >= cz) continue;
-            for (int Jy = iy >> 1; Jy <= (iy + 1) >> 1; ++Jy) {
-                if (Jy >= cy) continue;
-                for (int Jx = ix >> 1; Jx <= (ix + 1) >> 1; ++Jx) {
-                    if (Jx >= cx) continue;
-                    s += pw(ix - 2 * Jx) * pw(iy - 2 * Jy) * pw(iz - 2 * Jz) *
-                         xc[sys * Nc + Jx + (int64_t)cx * (Jy + (int64_t)cy * Jz)];
+// x = base + P xc on fine level f (coarse lattice cx, cy, cz). base = x, or
+// with FIRST the first sweep w D^{-1} b, which is then never stored.
+template <int B, bool FIRST>
+__global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32_t cy, int32_t cz,
+                                                     const double* __restrict__ xc, const double* __restrict__ b,
+                                                     double* __restrict__ x) {
+    using T = TB<B>;
+    constexpr int V = Pk<B>::V;
+    const int v = threadIdx.x % Pk<B>::BV;
+    const int64_t Nf = f.L.N, Nc = (int64_t)cx * cy * cz;
+    for (int sys = 0; sys < f.nsys; ++sys) {
+        if (!pair_active<B>(f.sc, sys, v)) continue;
+        const double w = f.w[sys * f.nlev + f.lev];
+        const double* dinv = f.dinv + sys * Nf;
+        const double* xs = xc + sys * Nc * B + v * V;
+        const double* bs = b + sys * Nf * B + v * V;
+        double* xf = x + sys * Nf * B + v * V;
+        walk<Pk<B>::BV>(f.L.nx, f.L.ny, f.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
+            const Span sx(ix, cx), sy(iy, cy), sz(iz, cz);
+            const int32_t jx[2] = {sx.j0, sx.j1}, jy[2] = {sy.j0, sy.j1}, jz[2] = {sz.j0, sz.j1};
+            const double wx[2] = {sx.w0, sx.w1}, wy[2] = {sy.w0, sy.w1}, wz[2] = {sz.w0, sz.w1};
+            T s = FIRST ? (w * dinv[i]) * vld<T>(bs + i * B) : vld<T>(xf + i * B);
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+                for (int b2 = 0; b2 < 2; ++b2) {
+                    const int32_t row = cx * (jy[b2] + cy * jz[c2]);
+                    const double wyz = wy[b2] * wz[c2];
+#pragma unroll
+                    for (int a2 = 0; a2 < 2; ++a2) s += (wyz * wx[a2]) * vld<T>(xs + (row + jx[a2]) * B);
                 }
-            }
-        }
-        x[sys * Nf + i] += s;
+            vst<T>(xf + i * B, s);
+        });
     }
 }
 
 // x = Ainv b on the coarsest level
-__global__ __launch_bounds__(kMgT) void k_mg_dense(int64_t Nc, const double* __restrict__ ainv,
+template <int B>
+__global__ __launch_bounds__(kMgT) void k_mg_dense(int64_t Nc, int nsys, const double* __restrict__ ainv,
                                                    const double* __restrict__ b, double* __restrict__ x,
                                                    const MgScal* __restrict__ sc) {
-    const int sys = blockIdx.y;
-    if (!sc[sys].active) return;
-    const double* A = ainv + sys * Nc * Nc;
-    for (int64_t I = blockIdx.x * (int64_t)kMgT + threadIdx.x; I < Nc; I += (int64_t)gridDim.x * kMgT) {
-        double s = 0.0;
-        for (int64_t J = 0; J < Nc; ++J) s += A[I * Nc + J] * b[sys * Nc + J];
-        x[sys * Nc + I] = s;
+    using T = TB<B>;
+    constexpr int V = Pk<B>::V, BV = Pk<B>::BV;
+    const int v = threadIdx.x % BV;
+    for (int sys = 0; sys < nsys; ++sys) {
+        if (!pair_active<B>(sc, sys, v)) continue;
+        const double* A = ainv + sys * Nc * Nc;
+        const double* bs = b + sys * Nc * B + v * V;
+        QPAT_MG_ELEMS(e, Nc * BV) {
+            const int64_t I = e / BV;
+            T s = 0.0;
+            for (int64_t J = 0; J < Nc; ++J) s += A[I * Nc + J] * vld<T>(bs + J * B);
+            vst<T>(x + sys * Nc * B + v * V + I * B, s);
+        }
     }
 }
 
 // ---------------------------------------------------------------- PCG kernels
+// The direction ping-pongs between two buffers (po: the last iteration's,
+// pn: this one's), so that the fused direction + product kernel can read the
+// old direction in the halo of a tile while other blocks write the new one.
 struct PcgMg {
     LvArgs L;             // the fine operator
-    double* x;            // [2][N] iterate
+    double* x;            // [nsys][N][B] iterate
     double* r;
-    double* p;
+    double* po;
+    double* pn;
     double* q;
     const double* z;
-    double* parts;        // [2][4][kMgBlocks]
-    MgScal* sc;
+    double* parts;        // [lanes][4][kMgBlocks]
+    MgScal* sc;           // [lanes]
     double rtol2;
-    int32_t maxit, deflate;
-    int32_t nb;           // blocks per system of the vector kernels (partials written)
+    int32_t maxit, deflate, nsys;
+    int32_t nb;           // blocks of the kernels that write partials
 };
 
-__device__ __forceinline__ void put(double* parts, int sys, int v, double val) {
-    parts[(sys * 4 + v) * kMgBlocks + blockIdx.x] = val;
+// per-component choice between two V-wide values
+__device__ __forceinline__ double pick(double a, double b, bool c0, bool) { return c0 ? a : b; }
+__device__ __forceinline__ d2v pick(d2v a, d2v b, bool c0, bool c1) {
+    d2v r;
+    r.x = c0 ? a.x : b.x;
+    r.y = c1 ? a.y : b.y;
+    return r;
 }
 
-// p = z - c + beta p
-__global__ __launch_bounds__(kMgT) void k_mgp_dir(PcgMg a) {
-    const int sys = blockIdx.y;
-    const MgScal s = a.sc[sys];
-    if (!s.active) return;
-    const int64_t o = sys * a.L.N;
-    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < a.L.N; i += (int64_t)gridDim.x * kMgT)
-        a.p[o + i] = a.z[o + i] - s.c + s.beta * a.p[o + i];
-}
-
-// q = A p, partial p.q
-template <int KIND>
-__global__ __launch_bounds__(kMgT) void k_mgp_spmv(PcgMg a) {
-    __shared__ double sm[kMgT / 64];
-    for (int sys = 0; sys < 2; ++sys) {
-        if (!a.sc[sys].active) continue;
-        const int M1 = a.L.m + 1;
-        const int64_t o = sys * a.L.N;
-        const double* U = a.L.U + o * M1;
-        double pq = 0.0;
-        QPAT_MG_ROWS(i, a.L.N) {
-            const double v = st_apply<KIND>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, a.p + o, (int32_t)i);
-            a.q[o + i] = v;
-            pq += a.p[o + i] * v;
+// the PCG scalars of thread-in-node v's right-hand sides as V-wide values
+template <int B>
+struct LaneScal {
+    TB<B> alpha, beta, c;
+    bool on0, on1;
+    __device__ __forceinline__ LaneScal(const MgScal* sc, int sys, int v) {
+        const MgScal& s0 = sc[sys * B + v * Pk<B>::V];
+        const MgScal& s1 = sc[sys * B + v * Pk<B>::V + Pk<B>::V - 1];
+        on0 = s0.active != 0;
+        on1 = s1.active != 0;
+        if constexpr (Pk<B>::V == 2) {
+            alpha = d2v{s0.alpha, s1.alpha};
+            beta = d2v{s0.beta, s1.beta};
+            c = d2v{s0.c, s1.c};
+        } else {
+            alpha = s0.alpha;
+            beta = s0.beta;
+            c = s0.c;
         }
-        pq = bsum(pq, sm);
-        if (threadIdx.x == 0) put(a.parts, sys, 0, pq);
+    }
+};
+
+// pn = z - c + beta po (right-hand sides that stopped keep pn)
+template <int B>
+__global__ __launch_bounds__(kMgT) void k_mgp_dir(PcgMg a) {
+    using T = TB<B>;
+    constexpr int V = Pk<B>::V, BV = Pk<B>::BV;
+    const int v = threadIdx.x % BV;
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        const LaneScal<B> s(a.sc, sys, v);
+        if (!s.on0 && !s.on1) continue;
+        const int64_t o = sys * a.L.N * B + v * V;
+        QPAT_MG_ELEMS(e, a.L.N * BV) {
+            const int64_t at = o + (e / BV) * B;
+            const T pn = vld<T>(a.z + at) - s.c + s.beta * vld<T>(a.po + at);
+            vst<T>(a.pn + at, pick(pn, vld<T>(a.pn + at), s.on0, s.on1));
+        }
     }
 }
 
-// x += alpha p, r -= alpha q, partial r.r
+// q = A pn, partial pn.q
+template <int KIND, int B>
+__global__ __launch_bounds__(kMgT) void k_mgp_spmv(PcgMg a) {
+    using T = TB<B>;
+    constexpr int V = Pk<B>::V;
+    __shared__ double sm[(kMgT / 64) * 16];
+    const int v = threadIdx.x % Pk<B>::BV;
+    const int32_t M1 = a.L.m + 1;
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        const double* U = a.L.U + sys * a.L.N * M1;
+        const int64_t o = sys * a.L.N * B + v * V;
+        const double* ps = a.pn + o;
+        double* qs = a.q + o;
+        T pq = 0.0;
+        if (pair_active<B>(a.sc, sys, v)) {
+            walk<Pk<B>::BV>(a.L.nx, a.L.ny, a.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
+                const T qi = apply<KIND, B>(a.L, U, ps, ix, iy, iz, i);
+                vst<T>(qs + i * B, qi);
+                pq += vld<T>(ps + i * B) * qi;
+            });
+        }
+        put_sums<B>(a.parts, sys, 0, pq, sm);
+    }
+}
+
+// x += alpha pn, r -= alpha q (right-hand sides that stopped keep both),
+// partial r.r
+template <int B>
 __global__ __launch_bounds__(kMgT) void k_mgp_update(PcgMg a) {
-    __shared__ double sm[kMgT / 64];
-    const int sys = blockIdx.y;
-    const MgScal s = a.sc[sys];
-    if (!s.active) return;
-    const int64_t o = sys * a.L.N;
-    double rr = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < a.L.N; i += (int64_t)gridDim.x * kMgT) {
-        a.x[o + i] += s.alpha * a.p[o + i];
-        const double ri = a.r[o + i] - s.alpha * a.q[o + i];
-        a.r[o + i] = ri;
-        rr += ri * ri;
-    }
-    rr = bsum(rr, sm);
-    if (threadIdx.x == 0) put(a.parts, sys, 1, rr);
-}
-
-// partial r.z, sum z, sum r (after the V-cycle)
-__global__ __launch_bounds__(kMgT) void k_mgp_dots(PcgMg a) {
-    __shared__ double sm[kMgT / 64];
-    const int sys = blockIdx.y;
-    if (!a.sc[sys].active) return;
-    const int64_t o = sys * a.L.N;
-    double rz = 0.0, z1 = 0.0, r1 = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < a.L.N; i += (int64_t)gridDim.x * kMgT) {
-        rz += a.r[o + i] * a.z[o + i];
-        z1 += a.z[o + i];
-        r1 += a.r[o + i];
-    }
-    rz = bsum(rz, sm);
-    z1 = bsum(z1, sm);
-    r1 = bsum(r1, sm);
-    if (threadIdx.x == 0) {
-        put(a.parts, sys, 0, rz);
-        put(a.parts, sys, 2, z1);
-        put(a.parts, sys, 3, r1);
+    using T = TB<B>;
+    constexpr int V = Pk<B>::V, BV = Pk<B>::BV;
+    __shared__ double sm[(kMgT / 64) * 16];
+    const int v = threadIdx.x % BV;
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        const LaneScal<B> s(a.sc, sys, v);
+        const int64_t o = sys * a.L.N * B + v * V;
+        T rr = 0.0;
+        if (s.on0 || s.on1) {
+            QPAT_MG_ELEMS(e, a.L.N * BV) {
+                const int64_t at = o + (e / BV) * B;
+                const T p = vld<T>(a.pn + at), r = vld<T>(a.r + at), x = vld<T>(a.x + at);
+                const T rn = pick(r - s.alpha * vld<T>(a.q + at), r, s.on0, s.on1);
+                vst<T>(a.x + at, pick(x + s.alpha * p, x, s.on0, s.on1));
+                vst<T>(a.r + at, rn);
+                rr += rn * rn;
+            }
+        }
+        put_sums<B>(a.parts, sys, 1, rr, sm);
     }
 }
 
-__device__ double red(const double* parts, int nb, int sys, int v, double* sm) {
+// deterministic sum of one lane's partials (one block)
+__device__ double red(const double* parts, int nb, int lane, int slot, double* sm) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += parts[(sys * 4 + v) * kMgBlocks + b];
-    return bsum(s, sm);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += parts[(lane * 4 + slot) * kMgBlocks + b];
+    return group_sum<1>(s, sm);
 }
 
-// phase 0: alpha = rz / pq; phase 1: rr, convergence, iteration count;
-// phase 2 (after the V-cycle): c, beta, rz; phase 3: start of a run (r = b,
-// after its V-cycle): c, rz, beta = 0
+// one block per lane (blockIdx.y). phase 0: alpha = rz / pq; phase 1: rr,
+// convergence, iteration count; phase 2 (after the V-cycle): c, beta, rz;
+// phase 3: start of a run (after its first V-cycle): c, rz, beta = 0
 __global__ __launch_bounds__(kMgT) void k_mgp_scalars(PcgMg a, int phase) {
     __shared__ double sm[kMgT / 64];
-    const int sys = blockIdx.y;
-    if (!a.sc[sys].active) return;
-    MgScal& s = a.sc[sys];
+    const int lane = blockIdx.y;
+    if (!a.sc[lane].active) return;
+    MgScal& s = a.sc[lane];
     if (phase == 0) {
-        const double pq = red(a.parts, a.nb, sys, 0, sm);
+        const double pq = red(a.parts, a.nb, lane, 0, sm);
         if (threadIdx.x == 0) {
             s.pq = pq;
             s.alpha = pq != 0.0 ? s.rz / pq : 0.0;
         }
     } else if (phase == 1) {
-        const double rr = red(a.parts, a.nb, sys, 1, sm);
+        const double rr = red(a.parts, a.nb, lane, 1, sm);
         if (threadIdx.x == 0) {
             s.rr = rr;
             s.iters += 1;
@@ -496,9 +723,9 @@ __global__ __launch_bounds__(kMgT) void k_mgp_scalars(PcgMg a, int phase) {
             }
         }
     } else {
-        double rz = red(a.parts, a.nb, sys, 0, sm);
-        const double z1 = red(a.parts, a.nb, sys, 2, sm);
-        const double r1 = red(a.parts, a.nb, sys, 3, sm);
+        double rz = red(a.parts, a.nb, lane, 0, sm);
+        const double z1 = red(a.parts, a.nb, lane, 2, sm);
+        const double r1 = red(a.parts, a.nb, lane, 3, sm);
         if (threadIdx.x == 0) {
             const double c = a.deflate ? z1 / static_cast<double>(a.L.N) : 0.0;
             rz -= c * r1;     // r.(z - c)
@@ -509,31 +736,33 @@ __global__ __launch_bounds__(kMgT) void k_mgp_scalars(PcgMg a, int phase) {
     }
 }
 
-// b <- b - mean(b) per system (deflation), ||b||^2 of the original b
+// partial sums of b and b.b per lane
+template <int B>
 __global__ __launch_bounds__(kMgT) void k_mgp_bstats(PcgMg a, const double* __restrict__ b) {
-    __shared__ double sm[kMgT / 64];
-    const int sys = blockIdx.y;
-    const int64_t o = sys * a.L.N;
-    double s1 = 0.0, s2 = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < a.L.N; i += (int64_t)gridDim.x * kMgT) {
-        s1 += b[o + i];
-        s2 += b[o + i] * b[o + i];
-    }
-    s1 = bsum(s1, sm);
-    s2 = bsum(s2, sm);
-    if (threadIdx.x == 0) {
-        put(a.parts, sys, 2, s1);
-        put(a.parts, sys, 3, s2);
+    __shared__ double sm[(kMgT / 64) * 16];
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        const int64_t o = sys * a.L.N * B;
+        double s1 = 0.0, s2 = 0.0;
+        QPAT_MG_ELEMS(e, a.L.N * B) {
+            s1 += b[o + e];
+            s2 += b[o + e] * b[o + e];
+        }
+        s1 = group_sum<B>(s1, sm);
+        s2 = group_sum<B>(s2, sm);
+        if (threadIdx.x < B) {
+            put(a.parts, sys * B + threadIdx.x, 2, s1);
+            put(a.parts, sys * B + threadIdx.x, 3, s2);
+        }
     }
 }
 
 __global__ __launch_bounds__(kMgT) void k_mgp_init(PcgMg a, double inv_delta) {
     __shared__ double sm[kMgT / 64];
-    const int sys = blockIdx.y;
-    const double s1 = red(a.parts, a.nb, sys, 2, sm);
-    const double s2 = red(a.parts, a.nb, sys, 3, sm);
+    const int lane = blockIdx.y;
+    const double s1 = red(a.parts, a.nb, lane, 2, sm);
+    const double s2 = red(a.parts, a.nb, lane, 3, sm);
     if (threadIdx.x == 0) {
-        MgScal& s = a.sc[sys];
+        MgScal& s = a.sc[lane];
         const double mean = a.deflate ? s1 / static_cast<double>(a.L.N) : 0.0;
         s.c = mean;                       // subtracted from b by k_mgp_start
         s.mean = mean * inv_delta;
@@ -541,54 +770,295 @@ __global__ __launch_bounds__(kMgT) void k_mgp_init(PcgMg a, double inv_delta) {
         s.rz = s.pq = s.alpha = s.beta = 0.0;
         s.rr = s2;
         s.iters = 0;
-        s.done = s2 == 0.0 ? 1 : 0;
+        s.done = s2 == 0.0 ? 1 : 0;       // b = 0: x = 0
         s.active = s2 == 0.0 ? 0 : 1;
     }
 }
 
-// r = b - mean, x = 0, p = 0
-__global__ __launch_bounds__(kMgT) void k_mgp_start(PcgMg a, double* __restrict__ b) {
-    const int sys = blockIdx.y;
-    const double m = a.sc[sys].c;
-    const int64_t o = sys * a.L.N;
-    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < a.L.N; i += (int64_t)gridDim.x * kMgT) {
-        b[o + i] -= m;
-        a.r[o + i] = b[o + i];
-        a.x[o + i] = 0.0;
-        a.p[o + i] = 0.0;
-    }
-}
-
-// true residual r = b - A x, partial r.r (restart of a run: r replaces the recursive residual)
-__global__ __launch_bounds__(kMgT) void k_mgp_true(PcgMg a, const double* __restrict__ b) {
-    __shared__ double sm[kMgT / 64];
-    for (int sys = 0; sys < 2; ++sys) {
-        const int M1 = a.L.m + 1;
-        const int64_t o = sys * a.L.N;
-        const double* U = a.L.U + o * M1;
-        double rr = 0.0;
-        QPAT_MG_ROWS(i, a.L.N) {
-            const double ri =
-                b[o + i] - st_row<false>(U, M1, a.L.tab, a.L.m, a.L.nx, a.L.ny, a.L.nz, a.x + o, (int32_t)i);
-            a.r[o + i] = ri;
-            rr += ri * ri;
+// b -= mean; r = b; po = 0; x = 0 unless a start is given (and b != 0)
+template <int B>
+__global__ __launch_bounds__(kMgT) void k_mgp_start(PcgMg a, double* __restrict__ b, int has_x0) {
+    const int k = threadIdx.x % B;
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        const MgScal& s = a.sc[sys * B + k];
+        const double m = s.c;
+        const bool keep = has_x0 && s.active;
+        const int64_t o = sys * a.L.N * B;
+        QPAT_MG_ELEMS(e, a.L.N * B) {
+            b[o + e] -= m;
+            a.r[o + e] = b[o + e];
+            if (!keep) a.x[o + e] = 0.0;
+            a.po[o + e] = 0.0;
         }
-        rr = bsum(rr, sm);
-        if (threadIdx.x == 0) put(a.parts, sys, 1, rr);
     }
 }
 
-__global__ void k_mgp_true_fin(PcgMg a, int reopen) {
+// true residual r = b - A x, partial r.r (also the start of a run from x0)
+template <int KIND, int B>
+__global__ __launch_bounds__(kMgT) void k_mgp_true(PcgMg a, const double* __restrict__ b) {
+    using T = TB<B>;
+    constexpr int V = Pk<B>::V;
+    __shared__ double sm[(kMgT / 64) * 16];
+    const int v = threadIdx.x % Pk<B>::BV;
+    const int32_t M1 = a.L.m + 1;
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        const double* U = a.L.U + sys * a.L.N * M1;
+        const int64_t o = sys * a.L.N * B + v * V;
+        const double* bs = b + o;
+        const double* xs = a.x + o;
+        double* rs = a.r + o;
+        T rr = 0.0;
+        walk<Pk<B>::BV>(a.L.nx, a.L.ny, a.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
+            const T ri = vld<T>(bs + i * B) - apply<KIND, B>(a.L, U, xs, ix, iy, iz, i);
+            vst<T>(rs + i * B, ri);
+            rr += ri * ri;
+        });
+        put_sums<B>(a.parts, sys, 1, rr, sm);
+    }
+}
+
+__global__ __launch_bounds__(kMgT) void k_mgp_true_fin(PcgMg a, int reopen) {
     __shared__ double sm[kMgT / 64];
-    const int sys = blockIdx.y;
-    const double rr = red(a.parts, a.nb, sys, 1, sm);
+    const int lane = blockIdx.y;
+    const double rr = red(a.parts, a.nb, lane, 1, sm);
     if (threadIdx.x == 0) {
-        MgScal& s = a.sc[sys];
+        MgScal& s = a.sc[lane];
         s.rr = rr;
         const bool ok = rr <= a.rtol2 * s.bnorm2;
         s.done = ok ? 1 : 0;
         s.active = (!ok && reopen && s.iters < a.maxit) ? 1 : 0;
         s.rz = 0.0;   // a reopened run restarts its Krylov space from the true residual
+    }
+}
+
+
+// ------------------------------------------------ LDS-tiled finest-level kernels
+// On the finest level of a Kuhn lattice with B >= 8 right-hand sides (the
+// K solves) the stencil products run 2.5D-tiled: a work item is a tile of
+// (kTHX - 2) x (kTHY - 2) lattice columns over a chunk of planes, and the
+// block sweeps the chunk plane by plane with the input vector of three planes
+// (plus a one-node halo) and the stored operator rows of the same planes in
+// LDS. Every input value then comes from global memory kTHX kTHY /
+// ((kTHX - 2)(kTHY - 2)) times per product (the halo) instead of once per row
+// that uses it, and the gathers are LDS reads with immediate offsets. The
+// work items of one XCD are contiguous bands of tiles. Byte offsets are
+// 32-bit buffer offsets: loads outside the lattice return 0, stores there are
+// dropped.
+constexpr int kTT = 512;                 // threads of the tiled kernels
+constexpr int kTHX = 12, kTHY = 10;      // halo'd tile
+constexpr int kTHN = kTHX * kTHY;
+template <int B>
+struct MgTile {
+    static constexpr int NPF = (kTHN * B + kTT - 1) / kTT;   // input elements per thread and plane
+    static constexpr int NU = (kTHN * 8 + kTT - 1) / kTT;     // operator values per thread and plane
+    static constexpr size_t LDS = (size_t)3 * (NPF + NU) * kTT * sizeof(double);
+};
+enum TileMode { kTDirSpmv = 0, kTResidFirst = 1, kTSmoothDots = 2, kTTrue = 3, kTResid = 4 };
+
+struct TileArgs {
+    int32_t nx, ny, nz;
+    int32_t tiles_x, tiles_y, zc, items;
+    const double* U;      // [N][8] the Kuhn stencil form
+    const double* in;     // the vector staged in LDS (see the modes), [N][B]
+    const double* in2;    // kTDirSpmv: the old direction
+    const double* b;      // right-hand side (kTResid*, kTSmoothDots, kTTrue)
+    const double* dinv;   // [N] (kTResidFirst, kTSmoothDots)
+    const double* w;      // the level's Jacobi weight (kTResidFirst, kTSmoothDots)
+    double* out;
+    double* out2;         // kTDirSpmv: the new direction
+    double* parts;        // partial sums, [lanes][4][kMgBlocks]
+    const MgScal* sc;     // [B]
+};
+
+// kTDirSpmv: the PCG direction and product, p = in - c + beta in2 (in = z,
+//   in2 = the old direction) staged, out2 = p, out = A p, partial p.out.
+// kTResidFirst: the V-cycle's first sweep and residual, x = w D^{-1} in
+//   (in = r) staged, out = b - A x with b = r.
+// kTResid: out = b - A in. kTTrue: the same for every right-hand side,
+//   partial out.out.
+// kTSmoothDots: out = in + w D^{-1} (b - A in), partial b.out, sum out,
+//   sum b (the last finest-level sweep of the V-cycle: b = r, out = z).
+template <int MODE, int B>
+__global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
+    using TL = MgTile<B>;
+    constexpr int NPF = TL::NPF, NU = TL::NU, RS = NPF * kTT, US = NU * kTT;
+    constexpr int TX = kTHX - 2, TY = kTHY - 2, M1 = 8;
+    constexpr uint32_t SZ = sizeof(double);
+    constexpr bool HAS_B = MODE != kTDirSpmv;
+    constexpr bool CENTER_D = MODE == kTSmoothDots;
+    extern __shared__ __align__(16) unsigned char mg_smem[];
+    __shared__ double sm[(kTT / 64) * 16];
+    double* ring = reinterpret_cast<double*>(mg_smem);   // [3][RS]: [halo node][B]
+    double* ust = ring + 3 * RS;                          // [3][US]: [halo node][8]
+    const int tid = threadIdx.x, k = tid % B;
+    const MgScal scl = g.sc[k];
+    const bool act = MODE == kTTrue || scl.active != 0;
+    const double cc_ = MODE == kTDirSpmv ? scl.c : 0.0, beta = MODE == kTDirSpmv ? scl.beta : 0.0;
+    const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
+    const uint32_t nxy = static_cast<uint32_t>(nx) * ny;
+    const uint32_t pv = nxy * B * SZ, pu = nxy * M1 * SZ, pd = nxy * SZ;
+    const double w = (MODE == kTSmoothDots || MODE == kTResidFirst) ? *g.w : 0.0;
+    auto plane = [&](const double* base, int pl, uint32_t stride, uint32_t bytes) {
+        const bool in = pl >= 0 && pl < nz;
+        return rsrc(base + (in ? (int64_t)pl * stride : 0), in ? bytes : 0u);
+    };
+    // LDS node of output slot u (slots past the tile point at an interior node)
+    int32_t oc[NPF];
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+        const int nl = (tid + u * kTT) / B;
+        oc[u] = nl < TX * TY ? (nl / TX + 1) * kTHX + nl % TX + 1 : kTHX + 1;
+    }
+    double fr[NPF], f2[NPF], fu[NU];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+
+    const int32_t xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
+    const int32_t wx = (g.items + 7) / 8;
+    const int32_t it_end = min(g.items, (xcd + 1) * wx);
+    const int32_t tiles = g.tiles_x * g.tiles_y;
+    for (int32_t item = xcd * wx + slot; item < it_end; item += per) {
+        const int32_t ch = item / tiles, t2 = item % tiles;
+        const int32_t x0 = (t2 % g.tiles_x) * TX, y0 = (t2 / g.tiles_x) * TY;
+        const int32_t zb = ch * g.zc, ze = min(zb + g.zc, nz);
+        uint32_t fo[NPF], oo[NPF], od[NPF], uo[NU];
+#pragma unroll
+        for (int u = 0; u < NPF; ++u) {
+            const int nl = (tid + u * kTT) / B;
+            const int gx = x0 - 1 + nl % kTHX, gy = y0 - 1 + nl / kTHX;
+            const bool fin = nl < kTHN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            fo[u] = fin ? (static_cast<uint32_t>(gy * nx + gx) * B + k) * SZ : kOut;
+            const int ox = x0 + nl % TX, oy = y0 + nl / TX;
+            const bool oin = nl < TX * TY && ox < nx && oy < ny;
+            oo[u] = oin ? (static_cast<uint32_t>(oy * nx + ox) * B + k) * SZ : kOut;
+            od[u] = oin ? static_cast<uint32_t>(oy * nx + ox) * SZ : kOut;
+        }
+#pragma unroll
+        for (int v = 0; v < NU; ++v) {
+            const int e = tid + v * kTT, nl = e / M1;
+            const int gx = x0 - 1 + nl % kTHX, gy = y0 - 1 + nl / kTHX;
+            uo[v] = (nl < kTHN && gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+                        ? (static_cast<uint32_t>(gy * nx + gx) * M1 + e % M1) * SZ
+                        : kOut;
+        }
+        auto fetch = [&](int pl) {
+            const auto bi = plane(g.in, pl, nxy * B, pv), bu = plane(g.U, pl, nxy * M1, pu);
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) fr[u] = bload<double>(bi, fo[u]);
+            if constexpr (MODE == kTDirSpmv) {
+                const auto b2 = plane(g.in2, pl, nxy * B, pv);
+#pragma unroll
+                for (int u = 0; u < NPF; ++u) f2[u] = bload<double>(b2, fo[u]);
+            }
+            if constexpr (MODE == kTResidFirst) {
+                const auto bd = plane(g.dinv, pl, nxy, pd);
+#pragma unroll
+                for (int u = 0; u < NPF; ++u) f2[u] = bload<double>(bd, fo[u] == kOut ? kOut : (fo[u] / SZ - k) / B * SZ);
+            }
+#pragma unroll
+            for (int v = 0; v < NU; ++v) fu[v] = bload<double>(bu, uo[v]);
+        };
+        auto store = [&](int sl) {
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) {
+                double val = fr[u];
+                if constexpr (MODE == kTDirSpmv) val = fo[u] != kOut ? fr[u] - cc_ + beta * f2[u] : 0.0;
+                if constexpr (MODE == kTResidFirst) val = w * f2[u] * fr[u];
+                ring[sl * RS + tid + u * kTT] = val;
+            }
+#pragma unroll
+            for (int v = 0; v < NU; ++v) ust[sl * US + tid + v * kTT] = fu[v];
+        };
+        // plane z with slots (z, z+1, z-1) = (SZ0, SP0, SL0)
+        auto step = [&](int z, auto SZ0, auto SP0, auto SL0) {
+            constexpr int sz = decltype(SZ0)::value, sp = decltype(SP0)::value, sl = decltype(SL0)::value;
+            store(sp);
+            __syncthreads();
+            if (z + 1 < ze) fetch(z + 2);
+            // per-node inputs of plane z: loads in flight during the arithmetic
+            double bc[NPF], dc[NPF];
+            if constexpr (HAS_B) {
+                const auto bb = plane(g.b, z, nxy * B, act ? pv : 0u);
+#pragma unroll
+                for (int u = 0; u < NPF; ++u) bc[u] = bload<double>(bb, oo[u]);
+            }
+            if constexpr (CENTER_D) {
+                const auto bd = plane(g.dinv, z, nxy, act ? pd : 0u);
+#pragma unroll
+                for (int u = 0; u < NPF; ++u) dc[u] = bload<double>(bd, od[u]);
+            }
+            const auto bo = plane(g.out, z, nxy * B, act ? pv : 0u);
+            if (act) {
+                const auto bo2 = plane(g.out2, z, nxy * B, MODE == kTDirSpmv ? pv : 0u);
+#pragma unroll
+                for (int u = 0; u < NPF; ++u) {
+                    if (tid + u * kTT >= TX * TY * B) continue;   // whole waves past the tile skip
+                    // offsets from the tile-corner neighbour of the node are
+                    // non-negative compile-time constants
+                    const double* rb = ring + (oc[u] - kTHX - 1) * B + k;
+                    const double* ub = ust + (oc[u] - kTHX - 1) * M1;
+                    constexpr int cc = kTHX + 1;
+                    const double xc = rb[sz * RS + cc * B];
+                    double sum = ub[sz * US + cc * M1] * xc;
+#pragma unroll
+                    for (int j = 0; j < 7; ++j) {
+                        const int d = kKy[j] * kTHX + kKx[j];
+                        const int up = kKz[j] ? sp : sz, lo = kKz[j] ? sl : sz;
+                        sum += ub[sz * US + cc * M1 + j + 1] * rb[up * RS + (cc + d) * B] +
+                               ub[lo * US + (cc - d) * M1 + j + 1] * rb[lo * RS + (cc - d) * B];
+                    }
+                    const bool in = oo[u] != kOut;
+                    double o;
+                    if constexpr (MODE == kTDirSpmv) {
+                        o = sum;
+                        a0 += in ? xc * sum : 0.0;
+                        bstore<double>(bo2, oo[u], xc);
+                    } else if constexpr (MODE == kTSmoothDots) {
+                        o = xc + w * dc[u] * (bc[u] - sum);
+                        a0 += in ? bc[u] * o : 0.0;
+                        a1 += in ? o : 0.0;
+                        a2 += in ? bc[u] : 0.0;
+                    } else {
+                        o = bc[u] - sum;
+                        if constexpr (MODE == kTTrue) a1 += in ? o * o : 0.0;
+                    }
+                    bstore<double>(bo, oo[u], o);
+                }
+            }
+            __syncthreads();
+        };
+        fetch(zb - 1);
+        store(0);
+        fetch(zb);
+        store(1);
+        fetch(zb + 1);
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        for (int z = zb; z < ze; z += 3) {   // plane z - zb + 1 lives in slot (z - zb + 1) % 3
+            step(z, I1{}, I2{}, I0{});
+            if (z + 1 < ze) step(z + 1, I2{}, I0{}, I1{});
+            if (z + 2 < ze) step(z + 2, I0{}, I1{}, I2{});
+        }
+    }
+    auto out_sum = [&](double v, int slot_) {
+#pragma unroll
+        for (int off = 32; off >= B; off >>= 1) v += __shfl_xor(v, off);
+        const int lane = tid & 63, wave = tid >> 6;
+        if (lane < B) sm[wave * B + lane] = v;
+        __syncthreads();
+        if (tid < B) {
+            double t = 0.0;
+            for (int wv = 0; wv < kTT / 64; ++wv) t += sm[wv * B + tid];
+            put(g.parts, tid, slot_, t);
+        }
+        __syncthreads();
+    };
+    if constexpr (MODE == kTDirSpmv) out_sum(a0, 0);
+    if constexpr (MODE == kTTrue) out_sum(a1, 1);
+    if constexpr (MODE == kTSmoothDots) {
+        out_sum(a0, 0);
+        out_sum(a1, 2);
+        out_sum(a2, 3);
     }
 }
 
@@ -605,16 +1075,14 @@ inline LvArgs lv_args(const MgLevel& L) {
     return a;
 }
 
-// a multiple of 8 blocks per system (the XCD row split), at most kMgBlocks
-inline dim3 vgrid(int64_t n) { return dim3((grid_for(n, kMgT, kMgBlocks) + 7) & ~7, 2); }
-// the stencil kernels loop over the two systems themselves
-inline dim3 sgrid(int64_t n) { return dim3(vgrid(n).x, 1); }
+// a multiple of 8 blocks (the XCD row split), at most kMgBlocks
+inline dim3 vgrid(int64_t n) { return dim3((grid_for(n, kMgT, kMgBlocks) + 7) & ~7); }
 
-#define QPAT_MG_KIND(kind, KERNEL, ...)                                                   \
-    switch (kind) {                                                                        \
-        case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                         \
-        case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                         \
-        default: hipLaunchKernelGGL(KERNEL<0>, __VA_ARGS__); break;                        \
+#define QPAT_MG_KIND(kind, B, KERNEL, ...)                                 \
+    switch (kind) {                                                         \
+        case 1: hipLaunchKernelGGL((KERNEL<1, B>), __VA_ARGS__); break;     \
+        case 2: hipLaunchKernelGGL((KERNEL<2, B>), __VA_ARGS__); break;     \
+        default: hipLaunchKernelGGL((KERNEL<0, B>), __VA_ARGS__); break;    \
     }
 
 // Dense inverse of an SPD matrix (Cholesky), in place; false if not positive definite.
@@ -650,11 +1118,103 @@ bool spd_inverse(std::vector<double>& A, int n) {
     return true;
 }
 
-// one V-cycle on both systems: z = V(b_0); returns the buffer that holds z
-// (launch = false: only that buffer, nothing enqueued)
-double* vcycle(qpat_ctx* c, hipStream_t st, bool launch = true) {
-    MgState& M = *c->mg;
+template <int B, bool DOTS>
+void launch_smooth(int kind, dim3 g, hipStream_t st, const SmArgs& a, const double* b, const double* x, double* y,
+                   double* parts) {
+    switch (kind) {
+        case 1: hipLaunchKernelGGL((k_mg_smooth<1, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
+        case 2: hipLaunchKernelGGL((k_mg_smooth<2, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
+        default: hipLaunchKernelGGL((k_mg_smooth<0, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
+    }
+}
+
+// grid of the stencil and V-cycle kernels of a level with n nodes
+template <int B>
+dim3 sgrid(int64_t n) {
+    return vgrid(n * Pk<B>::BV);
+}
+
+template <int MODE, int B>
+void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const double* in, const double* in2,
+                 const double* b, double* out, double* out2) {
+    if constexpr (B >= 8) {   // tile_setup turns the tiling on only there
+        const MgLevel& L = M.lv[0];
+        TileArgs g;
+        g.nx = L.nx;
+        g.ny = L.ny;
+        g.nz = L.nz;
+        g.tiles_x = t.tiles_x;
+        g.tiles_y = t.tiles_y;
+        g.zc = t.zc;
+        g.items = t.items;
+        g.U = L.U;
+        g.in = in;
+        g.in2 = in2;
+        g.b = b;
+        g.dinv = L.dinv;
+        g.w = M.w;   // system 0, level 0
+        g.out = out;
+        g.out2 = out2;
+        g.parts = M.parts;
+        g.sc = M.sc;
+        hipLaunchKernelGGL((k_mg_tile<MODE, B>), sgrid<B>(L.N), dim3(kTT), MgTile<B>::LDS, st, g);
+    }
+}
+
+// The finest-level tiling for block size B: on for the Kuhn stencil of one
+// system with B >= 8 whose plane offsets fit 32 bits; the z-chunk length
+// balances the work items over the blocks resident per XCD.
+template <int B>
+qpat_status tile_setup(qpat_ctx* c, MgState& M) {
+    TileGeo& t = M.tiles[B];
+    if (t.ready) return QPAT_OK;
+    t.ready = true;
+    t.on = false;
+    const MgLevel& L = M.lv[0];
+    if constexpr (B >= 8) {
+        if (M.nsys != 1 || L.kind != 1 || L.N * B * (int64_t)sizeof(double) >= (int64_t(1) << 31)) return QPAT_OK;
+        static_assert(MgTile<B>::LDS <= 159 * 1024, "tiled multigrid LDS budget");
+        const void* fns[5] = {reinterpret_cast<const void*>(&k_mg_tile<kTDirSpmv, B>),
+                              reinterpret_cast<const void*>(&k_mg_tile<kTResidFirst, B>),
+                              reinterpret_cast<const void*>(&k_mg_tile<kTSmoothDots, B>),
+                              reinterpret_cast<const void*>(&k_mg_tile<kTTrue, B>),
+                              reinterpret_cast<const void*>(&k_mg_tile<kTResid, B>)};
+        for (const void* f : fns)   // dynamic LDS beyond the default limit is allowed per kernel
+            QPAT_HIP(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MgTile<B>::LDS));
+        int occ = 1, cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fns[2], kTT, MgTile<B>::LDS) != hipSuccess) occ = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) cus = 256;
+        const int64_t blocks = sgrid<B>(L.N).x;
+        const int64_t conc = std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(occ, 1) * (cus / 8), blocks / 8));
+        const int64_t tx = (L.nx + kTHX - 3) / (kTHX - 2), ty = (L.ny + kTHY - 3) / (kTHY - 2);
+        int64_t best = -1, best_zc = L.nz;
+        for (int64_t nch = 1; nch <= L.nz; ++nch) {
+            const int64_t zc = (L.nz + nch - 1) / nch;
+            const int64_t items = tx * ty * ((L.nz + zc - 1) / zc);
+            const int64_t cost = (((items + 7) / 8 + conc - 1) / conc) * (zc + 2);
+            if (best < 0 || cost < best) {
+                best = cost;
+                best_zc = zc;
+            }
+        }
+        t.tiles_x = static_cast<int32_t>(tx);
+        t.tiles_y = static_cast<int32_t>(ty);
+        t.zc = static_cast<int32_t>(best_zc);
+        t.items = static_cast<int32_t>(tx * ty * ((L.nz + best_zc - 1) / best_zc));
+        t.on = true;
+    }
+    return QPAT_OK;
+}
+
+// One V-cycle on every lane: z = V(r), r = level 0's b. The last sweep also
+// leaves the partial sums r.z, sum z, sum r. On a tiled finest level with one
+// sweep each way the first sweep w D^{-1} r is never stored: the residual
+// kernel stages it and the prolongation recomputes it. Level 0 takes
+// 2 kMgNu - 1 ping-pong sweeps (an odd number), so z ends in level 0's t.
+template <int B>
+void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg) {
     const int nl = static_cast<int>(M.lv.size());
+    const bool fused0 = tg.on && kMgNu == 1;
     std::vector<double*> xl(nl), tl(nl);
     for (int l = 0; l < nl; ++l) {
         xl[l] = M.lv[l].x;
@@ -667,94 +1227,231 @@ double* vcycle(qpat_ctx* c, hipStream_t st, bool launch = true) {
         a.w = M.w;
         a.nlev = nl;
         a.lev = l;
+        a.nsys = M.nsys;
         a.sc = M.sc;
         return a;
     };
-    // level 0 takes 2 kMgNu - 1 ping-pong sweeps (odd): z ends in t
-    if (!launch) return nl > 1 ? tl[0] : xl[0];
     for (int l = 0; l < nl - 1; ++l) {
         const MgLevel& L = M.lv[l];
         const MgLevel& C = M.lv[l + 1];
         const SmArgs a = sm(l);
-        hipLaunchKernelGGL(k_mg_first, vgrid(L.N), dim3(kMgT), 0, st, a, L.b, xl[l]);
+        const dim3 g = sgrid<B>(L.N);
+        if (l == 0 && !fused0) hipLaunchKernelGGL(k_mg_first<B>, vgrid(L.N * B), dim3(kMgT), 0, st, a, L.b, xl[0]);
         for (int k = 1; k < kMgNu; ++k) {
-            QPAT_MG_KIND(L.kind, k_mg_smooth, sgrid(L.N), dim3(kMgT), 0, st, a, L.b, xl[l], tl[l]);
+            launch_smooth<B, false>(L.kind, g, st, a, L.b, xl[l], tl[l], nullptr);
             std::swap(xl[l], tl[l]);
         }
-        QPAT_MG_KIND(L.kind, k_mg_resid, sgrid(L.N), dim3(kMgT), 0, st, a, L.b, xl[l], L.r);
-        hipLaunchKernelGGL(k_mg_restrict, vgrid(C.N), dim3(kMgT), 0, st, L.nx, L.ny, L.nz, C.nx, C.ny, C.nz, L.r, C.b,
-                           M.sc);
+        if (l == 0 && fused0)
+            launch_tile<kTResidFirst, B>(M, tg, st, L.b, nullptr, L.b, L.r, nullptr);
+        else if (l == 0 && tg.on)
+            launch_tile<kTResid, B>(M, tg, st, xl[0], nullptr, L.b, L.r, nullptr);
+        else
+            QPAT_MG_KIND(L.kind, B, k_mg_resid, g, dim3(kMgT), 0, st, a, L.b, xl[l], L.r);
+        hipLaunchKernelGGL(k_mg_restrict<B>, sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny, L.nz, L.r, C.b,
+                           xl[l + 1]);
     }
     const MgLevel& K = M.lv[nl - 1];
-    hipLaunchKernelGGL(k_mg_dense, vgrid(K.N), dim3(kMgT), 0, st, K.N, M.ainv, K.b, xl[nl - 1], M.sc);
+    hipLaunchKernelGGL(k_mg_dense<B>, sgrid<B>(K.N), dim3(kMgT), 0, st, K.N, M.nsys, M.ainv, K.b, xl[nl - 1], M.sc);
     for (int l = nl - 2; l >= 0; --l) {
         const MgLevel& L = M.lv[l];
         const MgLevel& C = M.lv[l + 1];
         const SmArgs a = sm(l);
-        hipLaunchKernelGGL(k_mg_prolong, vgrid(L.N), dim3(kMgT), 0, st, L.nx, L.ny, L.nz, C.nx, C.ny, C.nz, xl[l + 1],
-                           xl[l], M.sc);
+        const dim3 g = sgrid<B>(L.N);
+        if (l == 0 && fused0)
+            hipLaunchKernelGGL((k_mg_prolong<B, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], L.b, xl[0]);
+        else
+            hipLaunchKernelGGL((k_mg_prolong<B, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1], L.b,
+                               xl[l]);
         for (int k = 0; k < kMgNu; ++k) {
-            QPAT_MG_KIND(L.kind, k_mg_smooth, sgrid(L.N), dim3(kMgT), 0, st, a, L.b, xl[l], tl[l]);
+            if (l == 0 && k == kMgNu - 1 && tg.on)
+                launch_tile<kTSmoothDots, B>(M, tg, st, xl[0], nullptr, L.b, tl[0], nullptr);
+            else if (l == 0 && k == kMgNu - 1)
+                launch_smooth<B, true>(L.kind, g, st, a, L.b, xl[l], tl[l], M.parts);
+            else
+                launch_smooth<B, false>(L.kind, g, st, a, L.b, xl[l], tl[l], nullptr);
             std::swap(xl[l], tl[l]);
         }
     }
-    return xl[0];
 }
 
-PcgMg pcg_args(qpat_ctx* c) {
-    MgState& M = *c->mg;
+MgState*& state_of(qpat_ctx* c, Op op) { return op == Op::K ? c->mgk : c->mg; }
+
+template <int B>
+PcgMg pcg_args(qpat_ctx* c, Op op) {
+    const MgState& M = *state_of(c, op);
     PcgMg a;
     a.L = lv_args(M.lv[0]);
     a.x = c->x64;
     a.r = M.pr;
-    a.p = M.pp;
+    a.po = M.pa;
+    a.pn = M.pb;
     a.q = M.pq;
-    a.z = M.zout;
+    a.z = M.lv[0].t;   // where the V-cycle leaves z
     a.parts = M.parts;
     a.sc = M.sc;
-    a.rtol2 = c->opts.prior_rtol * c->opts.prior_rtol;
+    const double rtol = op == Op::K ? c->opts.pcg_rtol : c->opts.prior_rtol;
+    a.rtol2 = rtol * rtol;
     a.maxit = c->opts.pcg_maxit;
-    a.deflate = c->opts.prior_deflate;
-    a.nb = static_cast<int32_t>(vgrid(c->N).x);
+    a.deflate = op == Op::Prior ? c->opts.prior_deflate : 0;
+    a.nsys = M.nsys;
+    a.nb = static_cast<int32_t>(sgrid<B>(c->N).x);
     return a;
 }
 
-// one iteration after the first direction: direction, SpMV, alpha, update,
-// rr, V-cycle, dots, beta
-void iteration(qpat_ctx* c, const PcgMg& a, hipStream_t st) {
-    const dim3 g = vgrid(a.L.N), one(1, 2);
-    hipLaunchKernelGGL(k_mgp_dir, g, dim3(kMgT), 0, st, a);
-    QPAT_MG_KIND(a.L.kind, k_mgp_spmv, sgrid(a.L.N), dim3(kMgT), 0, st, a);
-    hipLaunchKernelGGL(k_mgp_scalars, one, dim3(kMgT), 0, st, a, 0);
-    hipLaunchKernelGGL(k_mgp_update, g, dim3(kMgT), 0, st, a);
-    hipLaunchKernelGGL(k_mgp_scalars, one, dim3(kMgT), 0, st, a, 1);
-    (void)vcycle(c, st);
-    hipLaunchKernelGGL(k_mgp_dots, g, dim3(kMgT), 0, st, a);
-    hipLaunchKernelGGL(k_mgp_scalars, one, dim3(kMgT), 0, st, a, 2);
+// one iteration after the first direction: direction and product, alpha,
+// update, rr, V-cycle (with r.z, sum z, sum r), beta. Iterations alternate
+// the two direction buffers (par); chunks of iterations have even length.
+template <int B>
+void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int par) {
+    if (par) std::swap(a.po, a.pn);
+    const dim3 g = sgrid<B>(a.L.N), lanes(1, a.nsys * B);
+    if (tg.on) {
+        launch_tile<kTDirSpmv, B>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn);
+    } else {
+        hipLaunchKernelGGL(k_mgp_dir<B>, g, dim3(kMgT), 0, st, a);
+        QPAT_MG_KIND(a.L.kind, B, k_mgp_spmv, g, dim3(kMgT), 0, st, a);
+    }
+    hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 0);
+    hipLaunchKernelGGL(k_mgp_update<B>, g, dim3(kMgT), 0, st, a);
+    hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 1);
+    vcycle<B>(M, st, tg);
+    hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 2);
+}
+
+// true residual r = b - A x of every lane, partial r.r
+template <int B>
+void true_residual(const MgState& M, const PcgMg& a, const TileGeo& tg, const double* b, hipStream_t st) {
+    if (tg.on)
+        launch_tile<kTTrue, B>(M, tg, st, a.x, nullptr, b, a.r, nullptr);
+    else
+        QPAT_MG_KIND(a.L.kind, B, k_mgp_true, sgrid<B>(a.L.N), dim3(kMgT), 0, st, a, b);
+}
+
+template <int B>
+qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
+    MgState& M = *state_of(c, op);
+    hipStream_t sm = c->stream;
+    const int S = M.nsys * B;
+    const dim3 g = sgrid<B>(c->N), lanes(1, S);
+    const PcgMg a = pcg_args<B>(c, op);
+    QPAT_TRY(tile_setup<B>(c, M));
+    const TileGeo tg = M.tiles[B];
+    hipLaunchKernelGGL(k_mgp_bstats<B>, g, dim3(kMgT), 0, sm, a, c->b64);
+    hipLaunchKernelGGL(k_mgp_init, lanes, dim3(kMgT), 0, sm, a, c->delta > 0 ? 1.0 / c->delta : 0.0);
+    hipLaunchKernelGGL(k_mgp_start<B>, g, dim3(kMgT), 0, sm, a, c->b64, has_x0 ? 1 : 0);
+    if (has_x0) {   // r = b - A x0; lanes that x0 already solves stop here
+        true_residual<B>(M, a, tg, c->b64, sm);
+        hipLaunchKernelGGL(k_mgp_true_fin, lanes, dim3(kMgT), 0, sm, a, 1);
+    }
+    QPAT_HIP(c, hipGetLastError());
+    auto fetch = [&]() -> qpat_status {
+        QPAT_HIP(c, hipMemcpyAsync(M.sc_host, M.sc, S * sizeof(MgScal), hipMemcpyDeviceToHost, sm));
+        QPAT_HIP(c, hipStreamSynchronize(sm));
+        return QPAT_OK;
+    };
+    auto any_active = [&]() {
+        for (int i = 0; i < S; ++i)
+            if (M.sc_host[i].active) return true;
+        return false;
+    };
+    for (int restart = 0; restart < 4; ++restart) {
+        QPAT_TRY(fetch());
+        if (!any_active()) break;
+        // first direction of a run: z = V(r), p = z - c
+        vcycle<B>(M, sm, tg);
+        hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, sm, a, 3);
+        QPAT_HIP(c, hipGetLastError());
+        int chunk = 4;
+        for (;;) {
+            QPAT_TRY(fetch());
+            if (!any_active()) break;
+            if (c->opts.use_graphs) {
+                char key[96];
+                snprintf(key, sizeof key, "%d/%d/%.17g/%d/%d", B, chunk, a.rtol2, a.maxit, a.deflate);
+                auto it = M.graphs.find(key);
+                hipGraphExec_t ex = nullptr;
+                if (it != M.graphs.end()) {
+                    ex = it->second;
+                } else {
+                    if (!M.cap) QPAT_HIP(c, hipStreamCreateWithFlags(&M.cap, hipStreamNonBlocking));
+                    hipGraph_t gr = nullptr;
+                    QPAT_HIP(c, hipStreamBeginCapture(M.cap, hipStreamCaptureModeThreadLocal));
+                    for (int i = 0; i < chunk; ++i) iteration<B>(M, a, tg, M.cap, i & 1);
+                    QPAT_HIP(c, hipStreamEndCapture(M.cap, &gr));
+                    QPAT_HIP(c, hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+                    QPAT_HIP(c, hipGraphDestroy(gr));
+                    M.graphs[key] = ex;
+                }
+                QPAT_HIP(c, hipGraphLaunch(ex, sm));
+            } else {
+                for (int i = 0; i < chunk; ++i) iteration<B>(M, a, tg, sm, i & 1);
+            }
+            QPAT_HIP(c, hipGetLastError());
+            chunk = std::min(chunk * 2, 16);
+        }
+        // confirm on the true residual; a failed check restarts from the true residual
+        true_residual<B>(M, a, tg, c->b64, sm);
+        hipLaunchKernelGGL(k_mgp_true_fin, lanes, dim3(kMgT), 0, sm, a, restart < 3 ? 1 : 0);
+        QPAT_HIP(c, hipGetLastError());
+    }
+    QPAT_TRY(fetch());
+    for (int i = 0; i < S; ++i) {
+        const MgScal& s = M.sc_host[i];
+        if (op == Op::Prior)   // the output kernel of the prior solve adds mean(b)/delta
+            QPAT_HIP(c, hipMemcpyAsync(&c->scal[i].mean, &M.sc[i].mean, sizeof(double), hipMemcpyDeviceToDevice, sm));
+        st->n_solves += 1;
+        st->iters_max = std::max(st->iters_max, s.iters);
+        st->iters_sum += s.iters;
+        const double rel = s.bnorm2 > 0 ? std::sqrt(s.rr / s.bnorm2) : 0.0;
+        st->relres_max = std::max(st->relres_max, rel);
+        if (!s.done) st->noconv = true;
+    }
+    return QPAT_OK;
 }
 
 }  // namespace
 
+static void mg_drop(qpat_ctx* c, Op op) {
+    MgState*& M = state_of(c, op);
+    if (!M) return;
+    for (auto& kv : M->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (M->cap) (void)hipStreamDestroy(M->cap);
+    if (M->sc_host) (void)hipHostFree(M->sc_host);
+    delete M;
+    M = nullptr;
+}
+
 void mg_destroy(qpat_ctx* c) {
-    if (!c->mg) return;
-    for (auto& kv : c->mg->graphs) (void)hipGraphExecDestroy(kv.second);
-    if (c->mg->cap) (void)hipStreamDestroy(c->mg->cap);
-    if (c->mg->sc_host) (void)hipHostFree(c->mg->sc_host);
-    delete c->mg;
-    c->mg = nullptr;
+    mg_drop(c, Op::K);
+    mg_drop(c, Op::Prior);
 }
 
-bool mg_available(const qpat_ctx* c) {
-    return c->lat.on && c->opts.operator_format == 1 && c->opts.prior_precond == 1 && c->MU64 &&
-           (int64_t)(c->lat.m + 1) * c->N * 8 < (int64_t(1) << 31);
+bool mg_available(const qpat_ctx* c, Op op) {
+    const bool want = op == Op::K ? c->opts.pcg_precond == 1 : c->opts.prior_precond == 1;
+    const double* U = op == Op::K ? c->KU64 : c->MU64;
+    // 32-bit element offsets in the kernels: [N][m+1] operator rows, [N][B] vectors
+    return want && c->lat.on && c->opts.operator_format == 1 && U &&
+           (int64_t)(c->lat.m + 1) * c->N * 8 < (int64_t(1) << 31) && c->N * kMaxRhs < (int64_t(1) << 31);
 }
 
-// Hierarchy for the current M_delta (after prior assembly and its stencil form).
-qpat_status mg_setup(qpat_ctx* c) {
-    if (!mg_available(c)) return QPAT_OK;
-    if (!c->mg) {
-        c->mg = new MgState();
-        MgState& M = *c->mg;
+bool mg_ready(qpat_ctx* c, Op op) {
+    const MgState* M = state_of(c, op);
+    return mg_available(c, op) && M && M->current;
+}
+
+// Hierarchy for the current operator (after its assembly and stencil form).
+// Called after every assembly: when the options turn multigrid off, an older
+// hierarchy is marked stale so that turning it on again cannot pick it up.
+qpat_status mg_setup(qpat_ctx* c, Op op) {
+    MgState*& Mp = state_of(c, op);
+    if (Mp) Mp->current = false;
+    if (!mg_available(c, op)) return QPAT_OK;
+    const int nsys = op == Op::K ? 1 : 2;
+    if (!Mp) {
+        Mp = new MgState();
+        MgState& M = *Mp;
+        M.nsys = nsys;
+        M.bmax = op == Op::K ? kMaxRhs : 1;
         MgLevel L0;
         L0.nx = c->lat.nx;
         L0.ny = c->lat.ny;
@@ -781,10 +1478,11 @@ qpat_status mg_setup(qpat_ctx* c) {
         }
         const int nl = static_cast<int>(M.lv.size());
         const int64_t Nc = M.lv.back().N;
-        if (Nc > 4096) {   // dense coarsest solve would be too large: keep Jacobi-PCG
-            mg_destroy(c);
+        if (Nc > 4096 || nl < 2) {   // no useful hierarchy: keep Jacobi-PCG
+            mg_drop(c, op);
             return QPAT_OK;
         }
+        const int64_t V = (int64_t)nsys * M.bmax;
         for (int l = 0; l < nl; ++l) {
             MgLevel& L = M.lv[l];
             if (l > 0) {
@@ -800,59 +1498,62 @@ qpat_status mg_setup(qpat_ctx* c) {
                 QPAT_TRY(dalloc(c, &L.tab_own, 13));
                 QPAT_HIP(c, hipMemcpyAsync(L.tab_own, tab, sizeof tab, hipMemcpyHostToDevice, c->stream));
                 L.tab = L.tab_own;
-                QPAT_TRY(dalloc(c, &L.U, 2 * L.N * 14));
-                QPAT_TRY(dalloc(c, &L.b, 2 * L.N));
+                QPAT_TRY(dalloc(c, &L.U, nsys * L.N * 14));
+                QPAT_TRY(dalloc(c, &L.b, V * L.N));
             }
-            QPAT_TRY(dalloc(c, &L.dinv, 2 * L.N));
-            QPAT_TRY(dalloc(c, &L.x, 2 * L.N));
-            QPAT_TRY(dalloc(c, &L.t, 2 * L.N));
-            QPAT_TRY(dalloc(c, &L.r, 2 * L.N));
+            QPAT_TRY(dalloc(c, &L.dinv, nsys * L.N));
+            QPAT_TRY(dalloc(c, &L.x, V * L.N));
+            QPAT_TRY(dalloc(c, &L.t, V * L.N));
+            QPAT_TRY(dalloc(c, &L.r, V * L.N));
         }
-        QPAT_TRY(dalloc(c, &M.w, 2 * nl));
-        QPAT_TRY(dalloc(c, &M.gmax, 2 * nl));
-        QPAT_TRY(dalloc(c, &M.ainv, 2 * Nc * Nc));
-        QPAT_TRY(dalloc(c, &M.pr, 2 * c->N));
-        QPAT_TRY(dalloc(c, &M.pp, 2 * c->N));
-        QPAT_TRY(dalloc(c, &M.pq, 2 * c->N));
-        QPAT_TRY(dalloc(c, &M.parts, 2 * 4 * kMgBlocks));
-        QPAT_TRY(dalloc(c, &M.sc, 2));
-        QPAT_HIP(c, hipHostMalloc((void**)&M.sc_host, 2 * sizeof(MgScal), hipHostMallocDefault));
+        QPAT_TRY(dalloc(c, &M.w, nsys * nl));
+        QPAT_TRY(dalloc(c, &M.gmax, nsys * nl));
+        QPAT_TRY(dalloc(c, &M.ainv, nsys * Nc * Nc));
+        QPAT_TRY(dalloc(c, &M.pr, V * c->N));
+        QPAT_TRY(dalloc(c, &M.pa, V * c->N));
+        QPAT_TRY(dalloc(c, &M.pb, V * c->N));
+        QPAT_TRY(dalloc(c, &M.pq, V * c->N));
+        QPAT_TRY(dalloc(c, &M.parts, (int64_t)kMgLanes * 4 * kMgBlocks));
+        QPAT_TRY(dalloc(c, &M.sc, kMgLanes));
+        QPAT_HIP(c, hipMemsetAsync(M.sc, 0, kMgLanes * sizeof(MgScal), c->stream));
+        QPAT_HIP(c, hipHostMalloc((void**)&M.sc_host, kMgLanes * sizeof(MgScal), hipHostMallocDefault));
         M.lv[0].b = M.pr;   // the V-cycle acts on the PCG residual
     }
-    MgState& M = *c->mg;
+    MgState& M = *Mp;
     const int nl = static_cast<int>(M.lv.size());
-    M.lv[0].U = c->MU64;
+    M.lv[0].U = op == Op::K ? c->KU64 : c->MU64;
     for (int l = 0; l + 1 < nl; ++l) {
         const MgLevel& F = M.lv[l];
         const MgLevel& C = M.lv[l + 1];
-        hipLaunchKernelGGL(k_mg_rap, dim3((unsigned)((C.N + kMgT - 1) / kMgT), 2), dim3(kMgT), 0, c->stream,
+        hipLaunchKernelGGL(k_mg_rap, dim3((unsigned)((C.N + kMgT - 1) / kMgT), nsys), dim3(kMgT), 0, c->stream,
                            lv_args(F), C.U, C.nx, C.ny, C.nz);
     }
-    QPAT_HIP(c, hipMemsetAsync(M.gmax, 0, 2 * nl * sizeof(uint64_t), c->stream));
+    QPAT_HIP(c, hipMemsetAsync(M.gmax, 0, nsys * nl * sizeof(uint64_t), c->stream));
     for (int l = 0; l < nl; ++l)
-        hipLaunchKernelGGL(k_mg_diag, vgrid(M.lv[l].N), dim3(kMgT), 0, c->stream, lv_args(M.lv[l]), M.lv[l].dinv,
-                           M.gmax, nl, l);
+        hipLaunchKernelGGL(k_mg_diag, dim3(grid_for(M.lv[l].N, kMgT, kMgBlocks), nsys), dim3(kMgT), 0, c->stream,
+                           lv_args(M.lv[l]), M.lv[l].dinv, M.gmax, nl, l);
     QPAT_HIP(c, hipGetLastError());
-    std::vector<uint64_t> gm(2 * nl);
+    std::vector<uint64_t> gm(nsys * nl);
     QPAT_HIP(c, hipMemcpyAsync(gm.data(), M.gmax, gm.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
     // coarsest operator to the host for its dense inverse
     const MgLevel& K = M.lv[nl - 1];
-    std::vector<double> Uk(2 * K.N * (K.m + 1));
+    std::vector<double> Uk(nsys * K.N * (K.m + 1));
     QPAT_HIP(c, hipMemcpyAsync(Uk.data(), K.U, Uk.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     int32_t tabk[4 * 13];
     QPAT_HIP(c, hipMemcpyAsync(tabk, K.tab, sizeof(int32_t) * 4 * K.m, hipMemcpyDeviceToHost, c->stream));
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
-    std::vector<double> w(2 * nl);
-    for (int i = 0; i < 2 * nl; ++i) {
+    const char* what = op == Op::K ? "K" : "M_delta";
+    std::vector<double> w(nsys * nl);
+    for (int i = 0; i < nsys * nl; ++i) {
         double g;
         std::memcpy(&g, &gm[i], sizeof g);
-        if (!(g > 0.0) || !std::isfinite(g)) return fail(c, QPAT_ERR_ARG, "multigrid: non-positive diagonal in M_delta");
+        if (!(g > 0.0) || !std::isfinite(g)) return fail(c, QPAT_ERR_ARG, "multigrid: non-positive diagonal in %s", what);
         w[i] = 4.0 / (3.0 * g);
     }
     QPAT_HIP(c, hipMemcpyAsync(M.w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     const int n = static_cast<int>(K.N), M1 = K.m + 1;
-    std::vector<double> inv(2 * (size_t)n * n);
-    for (int sys = 0; sys < 2; ++sys) {
+    std::vector<double> inv(nsys * (size_t)n * n);
+    for (int sys = 0; sys < nsys; ++sys) {
         std::vector<double> A((size_t)n * n, 0.0);
         const double* U = Uk.data() + (size_t)sys * n * M1;
         for (int i = 0; i < n; ++i) {
@@ -865,85 +1566,28 @@ qpat_status mg_setup(qpat_ctx* c) {
                 A[(size_t)i * n + k] = A[(size_t)k * n + i] = U[(size_t)i * M1 + j + 1];
             }
         }
-        if (!spd_inverse(A, n)) return fail(c, QPAT_ERR_ARG, "multigrid: coarsest M_delta is not positive definite");
+        if (!spd_inverse(A, n)) return fail(c, QPAT_ERR_ARG, "multigrid: coarsest %s is not positive definite", what);
         std::copy(A.begin(), A.end(), inv.begin() + (size_t)sys * n * n);
     }
     QPAT_HIP(c, hipMemcpyAsync(M.ainv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    M.current = true;
     return QPAT_OK;
 }
 
-// M_delta x = b for both blocks: b in c->b64 [2][N] (overwritten by its
-// deflated form), x in c->x64; c->scal[sys].mean receives mean(b)/delta.
-qpat_status mg_solve(qpat_ctx* c, SolveStats* st) {
-    MgState& M = *c->mg;
-    hipStream_t sm = c->stream;
-    const dim3 g = vgrid(c->N), one(1, 2);
-    // the V-cycle's output buffer is fixed by the sequence of ping-pong swaps
-    if (!M.zout) M.zout = vcycle(c, sm, false);
-    PcgMg a = pcg_args(c);
-    hipLaunchKernelGGL(k_mgp_bstats, g, dim3(kMgT), 0, sm, a, c->b64);
-    hipLaunchKernelGGL(k_mgp_init, one, dim3(kMgT), 0, sm, a, c->delta > 0 ? 1.0 / c->delta : 0.0);
-    hipLaunchKernelGGL(k_mgp_start, g, dim3(kMgT), 0, sm, a, c->b64);
-    QPAT_HIP(c, hipGetLastError());
-    auto fetch = [&]() -> qpat_status {
-        QPAT_HIP(c, hipMemcpyAsync(M.sc_host, M.sc, 2 * sizeof(MgScal), hipMemcpyDeviceToHost, sm));
-        QPAT_HIP(c, hipStreamSynchronize(sm));
-        return QPAT_OK;
-    };
-    for (int restart = 0; restart < 4; ++restart) {
-        // first direction of a run: z = V(r), p = z - c
-        (void)vcycle(c, sm);
-        hipLaunchKernelGGL(k_mgp_dots, g, dim3(kMgT), 0, sm, a);
-        hipLaunchKernelGGL(k_mgp_scalars, one, dim3(kMgT), 0, sm, a, 3);
-        QPAT_HIP(c, hipGetLastError());
-        int chunk = 4;
-        for (;;) {
-            QPAT_TRY(fetch());
-            if (!M.sc_host[0].active && !M.sc_host[1].active) break;
-            if (c->opts.use_graphs) {
-                char key[96];
-                snprintf(key, sizeof key, "%d/%.17g/%d/%d", chunk, a.rtol2, a.maxit, a.deflate);
-                auto it = M.graphs.find(key);
-                hipGraphExec_t ex = nullptr;
-                if (it != M.graphs.end()) {
-                    ex = it->second;
-                } else {
-                    if (!M.cap) QPAT_HIP(c, hipStreamCreateWithFlags(&M.cap, hipStreamNonBlocking));
-                    hipGraph_t gr = nullptr;
-                    QPAT_HIP(c, hipStreamBeginCapture(M.cap, hipStreamCaptureModeThreadLocal));
-                    for (int i = 0; i < chunk; ++i) iteration(c, a, M.cap);
-                    QPAT_HIP(c, hipStreamEndCapture(M.cap, &gr));
-                    QPAT_HIP(c, hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
-                    QPAT_HIP(c, hipGraphDestroy(gr));
-                    M.graphs[key] = ex;
-                }
-                QPAT_HIP(c, hipGraphLaunch(ex, sm));
-            } else {
-                for (int i = 0; i < chunk; ++i) iteration(c, a, sm);
-            }
-            QPAT_HIP(c, hipGetLastError());
-            chunk = std::min(chunk * 2, 16);
-        }
-        // confirm on the true residual; a failed check restarts from the true residual
-        hipLaunchKernelGGL(k_mgp_true, sgrid(c->N), dim3(kMgT), 0, sm, a, c->b64);
-        hipLaunchKernelGGL(k_mgp_true_fin, one, dim3(kMgT), 0, sm, a, restart < 3 ? 1 : 0);
-        QPAT_HIP(c, hipGetLastError());
-        QPAT_TRY(fetch());
-        if (!M.sc_host[0].active && !M.sc_host[1].active) break;
+// A x = b with the multigrid-preconditioned PCG: b in c->b64 ([nsys][N][B],
+// overwritten by its deflated form), x in c->x64 (has_x0: it holds the
+// start); for M_delta c->scal[sys].mean receives mean(b)/delta.
+qpat_status mg_solve(qpat_ctx* c, Op op, int B, SolveStats* st, bool has_x0) {
+    if (B > state_of(c, op)->bmax) return fail(c, QPAT_ERR_ARG, "multigrid: block of %d right-hand sides", B);
+    switch (B) {
+        case 1: return solve_B<1>(c, op, st, has_x0);
+        case 2: return solve_B<2>(c, op, st, has_x0);
+        case 4: return solve_B<4>(c, op, st, has_x0);
+        case 8: return solve_B<8>(c, op, st, has_x0);
+        case 16: return solve_B<16>(c, op, st, has_x0);
+        default: return fail(c, QPAT_ERR_ARG, "multigrid: block size %d not supported", B);
     }
-    // hand the means to the output kernel of the prior solve
-    for (int sys = 0; sys < 2; ++sys) {
-        const MgScal& s = M.sc_host[sys];
-        QPAT_HIP(c, hipMemcpyAsync(&c->scal[sys].mean, &M.sc[sys].mean, sizeof(double), hipMemcpyDeviceToDevice, sm));
-        st->n_solves += 1;
-        st->iters_max = std::max(st->iters_max, s.iters);
-        st->iters_sum += s.iters;
-        const double rel = s.bnorm2 > 0 ? std::sqrt(s.rr / s.bnorm2) : 0.0;
-        st->relres_max = std::max(st->relres_max, rel);
-        if (!s.done) st->noconv = true;
-    }
-    return QPAT_OK;
 }
 
 }  // namespace qpat

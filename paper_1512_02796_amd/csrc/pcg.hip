@@ -195,33 +195,6 @@ __global__ __launch_bounds__(kThreads) void k_dir_spmv(PcgArgs<T> a) {
 // lattice form is only enabled when N (m+1) and N B fit).
 constexpr int kStThreads = 512;
 
-// Raw buffer access with 32-bit byte offsets: one vector register per
-// address, and offsets at or past the resource's size read 0 / are dropped
-// (the hardware range check), which handles halo and tile edges.
-constexpr uint32_t kOut = 0x80000000u;   // an offset past every resource used here
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), static_cast<short>(0), static_cast<int>(bytes),
-                                             0x00020000);
-}
-template <typename T>
-__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t b, uint32_t off) {
-    if constexpr (sizeof(T) == 4)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(b, off, 0, 0));
-    else
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(b, off, 0, 0));
-}
-template <typename T>
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t b, uint32_t off, T v) {
-    if constexpr (sizeof(T) == 4)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b, off, 0, 0);
-    else
-    {
-        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b, off, 0, 0);
-    }
-}
-
 template <int B, int NT>
 __device__ __forceinline__ double block_sum_n(double v, double* sm) {
 #pragma unroll

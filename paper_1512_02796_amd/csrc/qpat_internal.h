@@ -21,6 +21,32 @@ constexpr int kMaxRhs = 16;          // right-hand sides per block solve
 constexpr int kMaxSys = 32;          // systems x right-hand sides tracked by one PCG run
 constexpr int kTetGeo = 12;          // doubles per tetrahedron: |T|, grad l1, grad l2, grad l3, pad
 
+// Raw buffer access with 32-bit byte offsets: one vector register per
+// address, and offsets at or past the resource's size read 0 / are dropped
+// (the hardware range check), which handles halo and tile edges.
+constexpr uint32_t kOut = 0x80000000u;   // an offset past every resource used here
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), static_cast<short>(0), static_cast<int>(bytes),
+                                             0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t b, uint32_t off) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(b, off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(b, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t b, uint32_t off, T v) {
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b, off, 0, 0);
+    else {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b, off, 0, 0);
+    }
+}
+
 struct Error {
     qpat_status st;
     std::string msg;
@@ -209,8 +235,9 @@ struct qpat_ctx {
     // learned initial guess (conv net on the node lattice)
     qpat::GuessNet* guess = nullptr;
 
-    // multigrid hierarchy of M_delta (lattice meshes)
+    // multigrid hierarchies of M_delta and K (lattice meshes)
     qpat::MgState* mg = nullptr;
+    qpat::MgState* mgk = nullptr;
 
     // resident blocks per kernel configuration (occupancy x compute units)
     std::map<int, int> occupancy;
@@ -311,9 +338,15 @@ void guess_destroy(qpat_ctx* c);
 qpat_status forward_solve_x0(qpat_ctx* c, const double* x0, SolveStats* st);
 
 // ---- mg.hip
-bool mg_available(const qpat_ctx* c);
-qpat_status mg_setup(qpat_ctx* c);
-qpat_status mg_solve(qpat_ctx* c, SolveStats* st);
+// The multigrid-preconditioned PCG for op: wanted by the options and possible
+// on this mesh (lattice numbering, stencil form).
+bool mg_available(const qpat_ctx* c, Op op);
+// available and its hierarchy built
+bool mg_ready(qpat_ctx* c, Op op);
+// (Re)builds op's hierarchy from its current stencil arrays; no-op when unavailable.
+qpat_status mg_setup(qpat_ctx* c, Op op);
+// The same contract as pcg_solve (b in c->b64, x in c->x64, has_x0 for K).
+qpat_status mg_solve(qpat_ctx* c, Op op, int B, SolveStats* st, bool has_x0 = false);
 void mg_destroy(qpat_ctx* c);
 
 // ---- lsqr.hip

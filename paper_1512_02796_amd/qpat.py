@@ -32,7 +32,8 @@ class Opts(ctypes.Structure):
                 ("prior_rtol", ctypes.c_double), ("prior_deflate", ctypes.c_int32),
                 ("lsqr_reorth", ctypes.c_int32), ("lsqr_max_steps", ctypes.c_int32),
                 ("ru_delta", ctypes.c_double), ("use_graphs", ctypes.c_int32),
-                ("operator_format", ctypes.c_int32), ("prior_precond", ctypes.c_int32)]
+                ("operator_format", ctypes.c_int32), ("prior_precond", ctypes.c_int32),
+                ("pcg_precond", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

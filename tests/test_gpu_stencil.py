@@ -1,11 +1,13 @@
 """The lattice (stencil) form of the PCG operators against the sliced-ELL form
-and the FP64 oracle.
+and the FP64 oracle, and the multigrid-preconditioned solves built on it.
 
 On a node numbering that is a lattice the library applies K and M_delta in
 the stencil form (diagonal + upper offsets, LDS-tiled); operator_format = 0
-forces the sliced-ELL kernels. Both solve the same systems to the same true
-residual, so their solutions agree to the solver tolerance. Boxes with
-unequal sides and odd sizes put ragged tiles on every face of the tiling.
+forces the sliced-ELL kernels, pcg_precond / prior_precond = 0 Jacobi-PCG in
+place of the multigrid V-cycle. All of them solve the same systems to the
+same true residual, so their solutions agree to the solver tolerance. Boxes
+with unequal sides and odd sizes put ragged tiles on every face of the
+tiling and ragged coarse levels into the multigrid hierarchy.
 """
 import numpy as np
 import pytest
@@ -84,7 +86,7 @@ def test_stencil_matches_oracle_on_boxes(dims, block, precision):
     g = fem.geometry(coords, tets, bfaces)
     lin = Linearisation(g, kappa, mu, src)
     ctx, phi, info = solve(coords, tets, bfaces, kappa, mu, src, max_rhs_block=block, precision=precision,
-                           pcg_rtol=1e-12)
+                           pcg_rtol=1e-12, pcg_precond=0)
     lay = ctx.operator_layout()
     assert lay["lattice"] and (lay["nx"], lay["ny"], lay["nz"]) == tuple(d + 1 for d in dims)
     tol = 1e-10 if precision == 0 else 1e-6
@@ -94,7 +96,8 @@ def test_stencil_matches_oracle_on_boxes(dims, block, precision):
 
 @pytest.mark.parametrize("block,precision", [(1, 0), (16, 0), (16, 1), (8, 1)])
 def test_stencil_and_sell_agree(block, precision):
-    G1 = GpuProblem("T24", GpuProblem.opts(max_rhs_block=block, precision=precision, pcg_rtol=1e-12))
+    G1 = GpuProblem("T24", GpuProblem.opts(max_rhs_block=block, precision=precision, pcg_rtol=1e-12,
+                                           pcg_precond=0))
     G0 = GpuProblem("T24", GpuProblem.opts(max_rhs_block=block, precision=precision, pcg_rtol=1e-12,
                                            operator_format=0))
     phi1, _, i1 = G1.forward()
@@ -186,3 +189,58 @@ def test_prior_multigrid_on_boxes(dims):
     info = ctx.prior_solve(dev(p), out)
     assert info["relres_max"] <= 1e-11
     assert rel(host(out), ref) <= 1e-7
+
+
+@pytest.mark.parametrize("dims", [(13, 7, 5), (30, 3, 9), (16, 16, 16)])
+@pytest.mark.parametrize("block,n_ill", [(1, 3), (4, 5), (16, 16), (8, 11)])
+def test_k_multigrid_matches_oracle_on_boxes(dims, block, n_ill):
+    """Forward solves with the multigrid-preconditioned block PCG (FP64)
+    against the oracle; n_ill not a multiple of the block leaves zero
+    right-hand sides in the last block."""
+    coords, tets, bfaces, kappa, mu, src = box_problem(*dims, n_ill, seed=3 * sum(dims) + block)
+    g = fem.geometry(coords, tets, bfaces)
+    lin = Linearisation(g, kappa, mu, src)
+    ctx, phi, info = solve(coords, tets, bfaces, kappa, mu, src, max_rhs_block=block, pcg_rtol=1e-12)
+    assert rel(phi, lin.phi) <= 1e-10, info
+    assert info["relres_max"] <= 1e-12
+    assert info["iters_max"] <= 40, info
+
+
+@pytest.mark.parametrize("block", [1, 16])
+def test_k_multigrid_and_jacobi_agree(block):
+    """Same forward solution and Jacobian products from the multigrid and the
+    Jacobi preconditioner; the V-cycle needs far fewer iterations."""
+    Gm = GpuProblem("T24", GpuProblem.opts(max_rhs_block=block, pcg_rtol=1e-12))
+    Gj = GpuProblem("T24", GpuProblem.opts(max_rhs_block=block, pcg_rtol=1e-12, pcg_precond=0))
+    phim, _, im = Gm.forward()
+    phij, _, ij = Gj.forward()
+    assert rel(host(phim), host(phij)) <= 1e-10
+    assert im["iters_max"] * 5 < ij["iters_max"], (im, ij)
+    N = Gm.N
+    s = dev(np.random.default_rng(5).standard_normal(2 * N))
+    t = dev(np.random.default_rng(6).standard_normal((Gm.n_ill, N)))
+    outs = []
+    for G in (Gm, Gj):
+        jv = torch.empty(Gm.n_ill * N, dtype=torch.float64, device="cuda")
+        G.ctx.jvp(s, jv)
+        jt = torch.empty(2 * N, dtype=torch.float64, device="cuda")
+        G.ctx.vjp(t.reshape(-1), jt)
+        outs.append((host(jv), host(jt)))
+    assert rel(outs[0][0], outs[1][0]) <= 1e-9
+    assert rel(outs[0][1], outs[1][1]) <= 1e-9
+
+
+def test_k_multigrid_from_initial_guess():
+    """A start x0 enters through the true residual: the solution is the
+    plain solve's, and a start at the solution takes no iterations."""
+    G = GpuProblem("T12", GpuProblem.opts(pcg_rtol=1e-11))
+    phi, _, info0 = G.forward()
+    x0 = phi.clone().reshape(-1)
+    out = torch.empty_like(x0)
+    info = G.ctx.forward_x0(G.kappa, G.mu, x0, out)
+    assert info["iters_max"] == 0
+    pert = x0 * (1.0 + 1e-3 * torch.cos(torch.arange(x0.numel(), device="cuda", dtype=torch.float64)))
+    info2 = G.ctx.forward_x0(G.kappa, G.mu, pert, out)
+    assert info2["relres_max"] <= 1e-11
+    assert rel(host(out), host(x0)) <= 1e-9
+    assert info2["iters_max"] <= info0["iters_max"]
