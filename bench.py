@@ -4,12 +4,13 @@
 Workload (default): 128^3 Kuhn voxels of a 40 mm cube (N = 2,146,689 nodes,
 E = 12,582,912 tetrahedra), 16 Gaussian illuminations, seeded ellipsoid
 phantom, linearised at the true phantom. A timed step is one J s + J^T t pair
-(16 tangent and 16 adjoint solves as 16-RHS block PCG, FP32 operator with FP64
-reliable updates, true FP64 residual <= 1e-10 ||b||). After the timed pairs:
-seconds per priorconditioned-LSQR iteration (pair + M_delta^{-1} +
-reorthogonalisation), the same pair in plain FP64 (one right-hand side at a
-time), live per-launch timing of the dominant PCG kernel for the roofline,
-and the FP64 CPU oracle timed on a bounded sample of the same system.
+(16 tangent and 16 adjoint solves as 16-RHS block PCG preconditioned by a
+geometric-multigrid V-cycle, FP64, true residual <= 1e-10 ||b||). After the
+timed pairs: seconds per priorconditioned-LSQR iteration (pair + M_delta^{-1}
++ reorthogonalisation), the same pair one right-hand side at a time and with
+the Jacobi preconditioner (FP64 and mixed), live per-launch timing of the
+PCG and V-cycle kernels for the roofline, and the FP64 CPU oracle timed on a
+bounded sample of the same system.
 
 Prints one JSON line.
 """
@@ -54,6 +55,25 @@ def algorithmic_bytes(kind, N, layout, V, stat):
         op = layout["sell_len"] * (4 + V) + 4 * N
         return lanes * 4 * N * V + L * (op + N * V)
     return lanes * 6 * N * V + L * N * V
+
+
+# the multigrid K kernels timed by the library (profile counters 4-7), the
+# names rocprofv3 reports for them, and their algorithmic bytes: vectors of
+# N B doubles per active right-hand side and the stencil rows (m + 1 doubles
+# per node) and 1/a_ii once per launch
+MG_KERNELS = {
+    "K_mg_dir_spmv": ("k_mg_tile<0,16>", 4, True, False),    # read z, p_old; write p, q
+    "K_mg_update": ("k_mgp_update<16>", 6, False, False),    # read x, p, r, q; write x, r
+    "K_mg_resid0": ("k_mg_tile<1,16>", 2, True, True),       # read r; write r - A (w D^-1 r)
+    "K_mg_smooth0": ("k_mg_tile<2,16>", 3, True, True),      # read x, r; write z
+}
+
+
+def mg_algorithmic_bytes(key, N, layout, stat):
+    """Bytes one launch must move, summed over the measured launches."""
+    _, vecs, op, diag = MG_KERNELS[key]
+    per_launch = (N * layout["stencil_arrays"] * 8 if op else 0) + (N * 8 if diag else 0)
+    return stat["lanes"] * vecs * N * 8 + stat["launches"] * per_launch
 
 
 def measured_traffic(kernel):
@@ -118,7 +138,7 @@ def main():
     m = P.mesh
     N, K = m.N, P.n_ill
     log(f"problem {args.grid}^3: N={N} E={m.E} n_ill={K} ({time.time() - t_setup:.1f}s)")
-    opts = qpat.default_opts(precision=1, max_rhs_block=16)
+    opts = qpat.default_opts(max_rhs_block=16)          # multigrid-preconditioned block PCG, FP64
     ctx = qpat.Context(d(m.coords), d(m.tets, torch.int32), d(m.bfaces, torch.int32), opts=opts)
     ctx.set_sources(d(P.phi_src))
     h = torch.empty(K * N, dtype=torch.float64, device=dev)
@@ -134,22 +154,27 @@ def main():
     Js = torch.empty(K * N, dtype=torch.float64, device=dev)
     Jt = torch.empty(2 * N, dtype=torch.float64, device=dev)
 
-    # ---- timed J s + J^T t pairs (batched + mixed)
+    # ---- timed J s + J^T t pairs
     for _ in range(args.warmup):
         ctx.jvp(s, Js)
         ctx.vjp(t, Jt)
     torch.cuda.synchronize()
-    ctx.profile(True)
     infos = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         infos.append((ctx.jvp(s, Js), ctx.vjp(t, Jt)))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    pair_s = (t1 - t0) / args.steps
+    log(f"pair: {pair_s * 1e3:.1f} ms", infos[-1])
+
+    # ---- one more pair with per-launch HIP-event timing (no graph replay)
+    ctx.profile(True)
+    ctx.jvp(s, Js)
+    ctx.vjp(t, Jt)
+    torch.cuda.synchronize()
     ctx.profile(False)
     kst = ctx.profile_read()
-    pair_s = (t1 - t0) / args.steps
-    log(f"batched mixed pair: {pair_s * 1e3:.1f} ms", infos[-1])
 
     # ---- one PLSQR iteration (pair + M_delta^{-1} + reorthogonalisation)
     kt = np.log(P.kappa / P.kappa0)
@@ -175,23 +200,26 @@ def main():
         prior_s = time.perf_counter() - p_t0
         log(f"M_delta^-1: {prior_s * 1e3:.1f} ms", pinfo)
 
-    # ---- plain FP64 pair (one right-hand side at a time) and batched FP64
+    # ---- the same pair one right-hand side at a time, and with the Jacobi preconditioner
     plain = None
     if not args.no_plain:
         out = {}
-        for label, prec, blk in (("plain_fp64", 0, 1), ("batched_fp64", 0, 16)):
-            ctx.set_opts(precision=prec, max_rhs_block=blk)
+        for label, o in (("multigrid_fp64_one_rhs", dict(max_rhs_block=1)),
+                         ("jacobi_fp64_16rhs", dict(pcg_precond=0, precision=0)),
+                         ("jacobi_mixed_16rhs", dict(pcg_precond=0, precision=1))):
+            ctx.set_opts(**o)
+            ctx.forward(d(P.kappa), d(P.mu), None, None)     # hierarchy / operator for these options
             torch.cuda.synchronize()
             a = time.perf_counter()
             i1 = ctx.jvp(s, Js)
             i2 = ctx.vjp(t, Jt)
             torch.cuda.synchronize()
             dt = time.perf_counter() - a
-            out[label] = {"pairs_per_s": 1.0 / dt, "ms_per_pair": dt * 1e3,
+            out[label] = {"pairs_per_s": round(1.0 / dt, 4), "ms_per_pair": round(dt * 1e3, 2),
                           "pcg_iters_sum": i1["iters_sum"] + i2["iters_sum"],
                           "pcg_iters_max": max(i1["iters_max"], i2["iters_max"])}
             log(label, out[label])
-        ctx.set_opts(precision=1, max_rhs_block=16)
+        ctx.set_opts(max_rhs_block=16, pcg_precond=1, precision=0)
         plain = out
 
     # ---- calibration copy for HBM counters (profiling runs only)
@@ -204,25 +232,22 @@ def main():
 
     # ---- roofline of the dominant kernel (live HIP-event timing)
     layout = ctx.operator_layout()
-    V = 4  # FP32 vectors and values in the mixed K solve
-    dir_name = "k_dir_stencil<float,16>" if layout["lattice"] else "k_dir_spmv<float,16>"
-    cand = {dir_name: ("dir_spmv", kst["K_dir_spmv"]),
-            "k_update<float,16>": ("update", kst["K_update"])}
-    name, (kind, st) = max(cand.items(), key=lambda kv: kv[1][1]["total_ms"])
-    bytes_total = algorithmic_bytes(kind, N, layout, V, st)
+    timed = {k: kst[k] for k in MG_KERNELS if kst[k]["launches"]}
+    key = max(timed, key=lambda k: timed[k]["total_ms"])
+    st = timed[key]
+    name = MG_KERNELS[key][0]
+    bytes_total = mg_algorithmic_bytes(key, N, layout, st)
     avg_ms = st["total_ms"] / st["launches"]
     achieved = bytes_total / st["launches"] / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_ms": round(avg_ms, 4), "launches": st["launches"],
                 "bytes_per_launch": round(bytes_total / st["launches"]),
-                "operator": "stencil (diagonal + %d upper offsets)" % (layout["stencil_arrays"] - 1)
-                            if layout["lattice"] else "sliced ELL",
-                "other_kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "launches": v["launches"],
-                                      "GB/s": round(algorithmic_bytes(
-                                          "dir_spmv" if "dir" in k else "update", N, layout, V, v)
-                                          / max(v["total_ms"], 1e-9) / 1e6, 1) if v["launches"] else 0}
-                                  for k, v in kst.items() if k.startswith("K_")}}
+                "operator": "stencil (diagonal + %d upper offsets)" % (layout["stencil_arrays"] - 1),
+                "other_kernels": {MG_KERNELS[k][0]: {
+                    "avg_ms": round(v["total_ms"] / v["launches"], 4), "launches": v["launches"],
+                    "GB/s": round(mg_algorithmic_bytes(k, N, layout, v) / v["total_ms"] / 1e6, 1)}
+                    for k, v in timed.items() if k != key}}
     roofline["traffic"] = measured_traffic(name)
     log("roofline", roofline)
 
@@ -244,18 +269,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32/f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"QPAT J s + J^T t pair, {args.grid}^3 Kuhn voxels (N={N}, E={m.E}), "
-                               f"{K} Gaussian illuminations, seeded ellipsoid phantom, 16-RHS block PCG, "
-                               "FP32 apply + FP64 reliable updates, rtol 1e-10",
-                   "grid": args.grid, "nodes": N, "tets": m.E, "n_ill": K, "precision": "mixed",
+                               f"{K} Gaussian illuminations, seeded ellipsoid phantom, 16-RHS block PCG "
+                               "with a geometric-multigrid V-cycle, FP64, rtol 1e-10",
+                   "grid": args.grid, "nodes": N, "tets": m.E, "n_ill": K, "precision": "fp64",
+                   "preconditioner": "multigrid V(1,1), weighted Jacobi, Galerkin coarse levels",
                    "rhs_block": 16, "pcg_rtol": 1e-10},
         "s_per_lsqr_iter": round(lsqr_s, 4) if lsqr_s else None,
         "prior_solve_s": round(prior_s, 4) if prior_s else None,
         "pcg_iters": {"pair_sum": infos[-1][0]["iters_sum"] + infos[-1][1]["iters_sum"],
                       "tangent_max": infos[-1][0]["iters_max"], "adjoint_max": infos[-1][1]["iters_max"],
-                      "prior": pinfo["iters_max"], "reliable_updates": infos[-1][0]["updates"] + infos[-1][1]["updates"]},
+                      "prior": pinfo["iters_max"]},
         "plain": plain,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -426,7 +452,8 @@ def bench_batch(args):
 def cpu_baseline(P, iters, plain):
     """FP64 oracle on the same 128^3 system: Jacobi-PCG iterations of one
     right-hand side (the oracle's K solve), timed over `iters` iterations and
-    scaled to one J s + J^T t pair by the pair's FP64 PCG iteration count."""
+    scaled to one J s + J^T t pair by the pair's Jacobi-PCG iteration count
+    in FP64 (the oracle's algorithm; measured on the GPU)."""
     from oracle import fem
     from oracle.solve import pcg
     m = P.mesh
@@ -441,14 +468,15 @@ def cpu_baseline(P, iters, plain):
     except RuntimeError:
         pass                              # stopped at maxit by design
     dt = (time.perf_counter() - t0) / iters
-    pair_iters = plain["plain_fp64"]["pcg_iters_sum"] if plain else None
+    pair_iters = plain["jacobi_fp64_16rhs"]["pcg_iters_sum"] if plain else None
     out = {"kind": "oracle", "cores": 1, "unit": "pairs/s",
            "sample": f"oracle Jacobi-PCG on the {m.n}^3 K system, {iters} iterations of one right-hand side "
                      f"({dt * 1e3:.1f} ms/iteration, single-threaded scipy/numpy; assembly {setup:.0f}s untimed)",
            "s_per_pcg_iter": round(dt, 5)}
     if pair_iters:
         out["value"] = round(1.0 / (dt * pair_iters), 6)
-        out["sample"] += f", scaled by the {pair_iters} FP64 PCG iterations of one pair (32 solves)"
+        out["sample"] += (f", scaled by the {pair_iters} Jacobi-PCG iterations (the oracle's solver) of one pair "
+                          "(32 solves, FP64, measured on the GPU)")
     else:
         out["value"] = None
     return out

@@ -186,12 +186,16 @@ qpat_status qpat_lsqr_init(qpat_ctx* ctx, const double* chi, const double* w,
  * freezes the iterate. */
 qpat_status qpat_lsqr_step(qpat_ctx* ctx, double* resnorm_out, qpat_info* info);
 
-/* Per-launch timing of the two PCG iteration kernels, for roofline
- * measurements. While enabled, every launch of the direction+SpMV kernel and
- * of the update kernel is bracketed by HIP events on the context's stream
- * and its duration accumulated. Index 0: K solves, direction+SpMV;
- * 1: K solves, update; 2: M_delta solves, direction+SpMV; 3: M_delta solves,
- * update. qpat_profile(ctx, 1) clears the counters and starts, 0 stops. */
+/* Per-launch timing of the PCG iteration kernels, for roofline
+ * measurements. While enabled, the solves run without graph replay and every
+ * launch of the kernels below is bracketed by HIP events on the context's
+ * stream and its duration accumulated (launches after every right-hand side
+ * stopped are not counted). Jacobi-PCG: 0 K direction+SpMV, 1 K update,
+ * 2 M_delta direction+SpMV, 3 M_delta update. Multigrid-PCG: 4 K direction
+ * + product, 5 K update, 6 K finest-level residual (with the first sweep),
+ * 7 K finest-level last sweep (with the dot products); 8-11 the same for
+ * M_delta. qpat_profile(ctx, 1) clears the counters and starts, 0 stops. */
+#define QPAT_NKSTAT 12
 typedef struct {
     int64_t launches;       /* launches that did work                                */
     int64_t lanes;          /* sum over those launches of the right-hand sides still
@@ -201,7 +205,7 @@ typedef struct {
     double  max_ms;
 } qpat_kstat;
 qpat_status qpat_profile(qpat_ctx* ctx, int32_t enable);
-qpat_status qpat_profile_read(const qpat_ctx* ctx, qpat_kstat out[4]);
+qpat_status qpat_profile_read(const qpat_ctx* ctx, qpat_kstat out[QPAT_NKSTAT]);
 
 /* Batched instances (several independent reconstructions, e.g. meshes of
  * different sizes and illumination counts): run one call on n contexts at

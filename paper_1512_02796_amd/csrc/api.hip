@@ -569,9 +569,9 @@ qpat_status qpat_profile(qpat_ctx* c, int32_t enable) {
     return QPAT_OK;
 }
 
-qpat_status qpat_profile_read(const qpat_ctx* c, qpat_kstat out[4]) {
+qpat_status qpat_profile_read(const qpat_ctx* c, qpat_kstat out[QPAT_NKSTAT]) {
     if (!c || !out) return QPAT_ERR_ARG;
-    for (int i = 0; i < 4; ++i) out[i] = c->prof[i];
+    for (int i = 0; i < QPAT_NKSTAT; ++i) out[i] = c->prof[i];
     return QPAT_OK;
 }
 

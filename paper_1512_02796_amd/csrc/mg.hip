@@ -68,6 +68,7 @@ struct MgState {
     MgScal* sc = nullptr;          // [lanes], lane = sys B + k
     MgScal* sc_host = nullptr;
     std::map<int, TileGeo> tiles;  // by block size
+    std::vector<hipEvent_t> ev;    // per-launch timing (profiling)
     std::map<std::string, hipGraphExec_t> graphs;
     hipStream_t cap = nullptr;
 };
@@ -79,6 +80,7 @@ constexpr int kMgNu = 1;          // Jacobi sweeps before and after the coarse c
 constexpr int kMgBlocks = 512;    // blocks of the vector kernels (partial sums)
 constexpr int kMgT = 256;
 constexpr int kMgLanes = 32;      // systems x right-hand sides
+constexpr int kMgChunk0 = 4;      // PCG iterations before the first host check of a run
 
 __device__ __forceinline__ void coords(int32_t i, int nx, int ny, int& ix, int& iy, int& iz) {
     ix = i % nx;
@@ -891,6 +893,11 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
     double* ring = reinterpret_cast<double*>(mg_smem);   // [3][RS]: [halo node][B]
     double* ust = ring + 3 * RS;                          // [3][US]: [halo node][8]
     const int tid = threadIdx.x, k = tid % B;
+    if constexpr (MODE != kTTrue) {   // every right-hand side stopped: nothing to do
+        bool any = false;
+        for (int j = 0; j < B; ++j) any = any || g.sc[j].active != 0;
+        if (!any) return;
+    }
     const MgScal scl = g.sc[k];
     const bool act = MODE == kTTrue || scl.active != 0;
     const double cc_ = MODE == kTDirSpmv ? scl.c : 0.0, beta = MODE == kTDirSpmv ? scl.beta : 0.0;
@@ -1212,7 +1219,7 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
 // kernel stages it and the prolongation recomputes it. Level 0 takes
 // 2 kMgNu - 1 ping-pong sweeps (an odd number), so z ends in level 0's t.
 template <int B>
-void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg) {
+void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev = nullptr) {
     const int nl = static_cast<int>(M.lv.size());
     const bool fused0 = tg.on && kMgNu == 1;
     std::vector<double*> xl(nl), tl(nl);
@@ -1241,12 +1248,14 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg) {
             launch_smooth<B, false>(L.kind, g, st, a, L.b, xl[l], tl[l], nullptr);
             std::swap(xl[l], tl[l]);
         }
+        if (l == 0 && ev) (void)hipEventRecord(ev[0], st);
         if (l == 0 && fused0)
             launch_tile<kTResidFirst, B>(M, tg, st, L.b, nullptr, L.b, L.r, nullptr);
         else if (l == 0 && tg.on)
             launch_tile<kTResid, B>(M, tg, st, xl[0], nullptr, L.b, L.r, nullptr);
         else
             QPAT_MG_KIND(L.kind, B, k_mg_resid, g, dim3(kMgT), 0, st, a, L.b, xl[l], L.r);
+        if (l == 0 && ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL(k_mg_restrict<B>, sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny, L.nz, L.r, C.b,
                            xl[l + 1]);
     }
@@ -1263,12 +1272,15 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg) {
             hipLaunchKernelGGL((k_mg_prolong<B, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1], L.b,
                                xl[l]);
         for (int k = 0; k < kMgNu; ++k) {
-            if (l == 0 && k == kMgNu - 1 && tg.on)
+            const bool last = l == 0 && k == kMgNu - 1;
+            if (last && ev) (void)hipEventRecord(ev[2], st);
+            if (last && tg.on)
                 launch_tile<kTSmoothDots, B>(M, tg, st, xl[0], nullptr, L.b, tl[0], nullptr);
-            else if (l == 0 && k == kMgNu - 1)
+            else if (last)
                 launch_smooth<B, true>(L.kind, g, st, a, L.b, xl[l], tl[l], M.parts);
             else
                 launch_smooth<B, false>(L.kind, g, st, a, L.b, xl[l], tl[l], nullptr);
+            if (last && ev) (void)hipEventRecord(ev[3], st);
             std::swap(xl[l], tl[l]);
         }
     }
@@ -1301,20 +1313,26 @@ PcgMg pcg_args(qpat_ctx* c, Op op) {
 // one iteration after the first direction: direction and product, alpha,
 // update, rr, V-cycle (with r.z, sum z, sum r), beta. Iterations alternate
 // the two direction buffers (par); chunks of iterations have even length.
+// ev (profiling): 8 events, recorded around the direction + product, the
+// update, and the finest-level residual and last sweep of the V-cycle.
 template <int B>
-void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int par) {
+void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int par, hipEvent_t* ev = nullptr) {
     if (par) std::swap(a.po, a.pn);
     const dim3 g = sgrid<B>(a.L.N), lanes(1, a.nsys * B);
+    if (ev) (void)hipEventRecord(ev[0], st);
     if (tg.on) {
         launch_tile<kTDirSpmv, B>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn);
     } else {
         hipLaunchKernelGGL(k_mgp_dir<B>, g, dim3(kMgT), 0, st, a);
         QPAT_MG_KIND(a.L.kind, B, k_mgp_spmv, g, dim3(kMgT), 0, st, a);
     }
+    if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 0);
+    if (ev) (void)hipEventRecord(ev[2], st);
     hipLaunchKernelGGL(k_mgp_update<B>, g, dim3(kMgT), 0, st, a);
+    if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 1);
-    vcycle<B>(M, st, tg);
+    vcycle<B>(M, st, tg, ev ? ev + 4 : nullptr);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 2);
 }
 
@@ -1361,10 +1379,66 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
         vcycle<B>(M, sm, tg);
         hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, sm, a, 3);
         QPAT_HIP(c, hipGetLastError());
-        int chunk = 4;
+        // Iterations run in chunks of even length between host checks. The
+        // first is kMgChunk0 long; later ones cover the iterations that the
+        // slowest lane still needs at its observed contraction rate (within
+        // [2, 16]), so few iterations run after convergence.
+        int chunk = kMgChunk0;
+        std::vector<int> iters_before(S, -1);
+        std::vector<double> rr_before(S, 0.0);
         for (;;) {
             QPAT_TRY(fetch());
             if (!any_active()) break;
+            if (iters_before[0] >= 0) {
+                double need = 0.0;
+                for (int i = 0; i < S; ++i) {
+                    const MgScal& h = M.sc_host[i];
+                    if (!h.active) continue;
+                    const int done_its = h.iters - iters_before[i];
+                    const double target = a.rtol2 * h.bnorm2;
+                    if (done_its <= 0 || !(rr_before[i] > 0.0) || !(h.rr > 0.0) || h.rr >= rr_before[i]) {
+                        need = 16.0;
+                        continue;
+                    }
+                    const double rate = std::log(h.rr / rr_before[i]) / done_its;   // < 0
+                    need = std::max(need, std::log(target / h.rr) / rate);
+                }
+                const int n = static_cast<int>(std::ceil(need));
+                chunk = std::min(16, std::max(2, n + (n & 1)));
+            }
+            for (int i = 0; i < S; ++i) {
+                iters_before[i] = M.sc_host[i].iters;
+                rr_before[i] = M.sc_host[i].rr;
+            }
+            const bool prof = c->prof_on;
+            if (prof) {
+                if (M.ev.size() < (size_t)8 * chunk) {
+                    const size_t old = M.ev.size();
+                    M.ev.resize((size_t)8 * chunk);
+                    for (size_t e = old; e < M.ev.size(); ++e) QPAT_HIP(c, hipEventCreate(&M.ev[e]));
+                }
+                for (int i = 0; i < chunk; ++i) iteration<B>(M, a, tg, sm, i & 1, &M.ev[8 * i]);
+                QPAT_HIP(c, hipGetLastError());
+                QPAT_TRY(fetch());
+                // iterations after every lane stopped do no work: count the live ones
+                const int base = op == Op::K ? 4 : 8;
+                for (int i = 0; i < chunk; ++i) {
+                    int lanes_on = 0;
+                    for (int l = 0; l < S; ++l) lanes_on += (M.sc_host[l].iters - iters_before[l]) > i;
+                    if (lanes_on == 0) break;
+                    for (int kk = 0; kk < 4; ++kk) {
+                        float t = 0.f;
+                        QPAT_HIP(c, hipEventElapsedTime(&t, M.ev[8 * i + 2 * kk], M.ev[8 * i + 2 * kk + 1]));
+                        qpat_kstat& ks = c->prof[base + kk];
+                        ks.launches += 1;
+                        ks.lanes += lanes_on;
+                        ks.total_ms += t;
+                        ks.min_ms = ks.launches == 1 ? t : std::min(ks.min_ms, (double)t);
+                        ks.max_ms = std::max(ks.max_ms, (double)t);
+                    }
+                }
+                continue;
+            }
             if (c->opts.use_graphs) {
                 char key[96];
                 snprintf(key, sizeof key, "%d/%d/%.17g/%d/%d", B, chunk, a.rtol2, a.maxit, a.deflate);
@@ -1387,7 +1461,6 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
                 for (int i = 0; i < chunk; ++i) iteration<B>(M, a, tg, sm, i & 1);
             }
             QPAT_HIP(c, hipGetLastError());
-            chunk = std::min(chunk * 2, 16);
         }
         // confirm on the true residual; a failed check restarts from the true residual
         true_residual<B>(M, a, tg, c->b64, sm);
@@ -1415,6 +1488,7 @@ static void mg_drop(qpat_ctx* c, Op op) {
     MgState*& M = state_of(c, op);
     if (!M) return;
     for (auto& kv : M->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipEvent_t e : M->ev) (void)hipEventDestroy(e);
     if (M->cap) (void)hipStreamDestroy(M->cap);
     if (M->sc_host) (void)hipHostFree(M->sc_host);
     delete M;

@@ -229,7 +229,7 @@ struct qpat_ctx {
 
     // per-launch timing of the PCG iteration kernels
     bool prof_on = false;
-    qpat_kstat prof[4]{};
+    qpat_kstat prof[QPAT_NKSTAT]{};
     std::vector<hipEvent_t> ev_pool;
 
     // learned initial guess (conv net on the node lattice)

@@ -55,7 +55,9 @@ class KStat(ctypes.Structure):
         return d
 
 
-KSTAT_NAMES = ("K_dir_spmv", "K_update", "prior_dir_spmv", "prior_update")
+KSTAT_NAMES = ("K_dir_spmv", "K_update", "prior_dir_spmv", "prior_update",
+               "K_mg_dir_spmv", "K_mg_update", "K_mg_resid0", "K_mg_smooth0",
+               "prior_mg_dir_spmv", "prior_mg_update", "prior_mg_resid0", "prior_mg_smooth0")
 
 _P = ctypes.c_void_p
 _D = ctypes.c_double
@@ -347,9 +349,9 @@ class Context:
         self._check(_lib.qpat_profile(self._h, 1 if enable else 0))
 
     def profile_read(self):
-        arr = (KStat * 4)()
+        arr = (KStat * len(KSTAT_NAMES))()
         self._check(_lib.qpat_profile_read(self._h, arr))
-        return {KSTAT_NAMES[i]: arr[i].as_dict() for i in range(4)}
+        return {KSTAT_NAMES[i]: arr[i].as_dict() for i in range(len(KSTAT_NAMES))}
 
     def operator_layout(self):
         arr = (_I64 * 6)()
