@@ -42,6 +42,7 @@ struct MgLevel {
     double* x = nullptr;           // [nsys][N][B]
     double* t = nullptr;           // ping-pong partner of x
     double* r = nullptr;           // residual before restriction
+    double* W = nullptr;           // [nsys][N][8] operator-dependent prolongation weights to the next level
 };
 
 struct MgScal {
@@ -57,6 +58,7 @@ struct TileGeo {
 
 struct MgState {
     int32_t nsys = 1;              // 1 (K) or 2 (the blocks of M_delta)
+    bool opdep = false;            // operator-dependent prolongation (else trilinear)
     int32_t bmax = 1;              // right-hand sides the vectors are sized for
     bool current = false;          // built from the operator now assembled
     std::vector<MgLevel> lv;
@@ -67,6 +69,15 @@ struct MgState {
     uint64_t* gmax = nullptr;      // [nsys][levels] Gershgorin bounds (bit patterns)
     MgScal* sc = nullptr;          // [lanes], lane = sys B + k
     MgScal* sc_host = nullptr;
+    // region coarse space (M_delta): z += Z E^{-1} Z^T r, E = Z^T A Z
+    int32_t kreg = 0;              // regions of the system with most (0: off)
+    int32_t nreg[2] = {0, 0};
+    int32_t* reg = nullptr;        // [nsys][N] region of each node, -1: none
+    double* einv = nullptr;        // [nsys][kRegMax][kRegMax]
+    double* rsize = nullptr;       // [nsys][kRegMax] nodes per region
+    double* rparts = nullptr;      // [nsys][kRegMax][kMgBlocks] partial sums of Z^T r
+    double* ry = nullptr;          // [nsys][kRegMax] y = E^{-1} Z^T r
+    double* rcorr = nullptr;       // [nsys][2] r.(Z y), sum(Z y)
     std::map<int, TileGeo> tiles;  // by block size
     std::vector<hipEvent_t> ev;    // per-launch timing (profiling)
     std::map<std::string, hipGraphExec_t> graphs;
@@ -81,6 +92,13 @@ constexpr int kMgBlocks = 512;    // blocks of the vector kernels (partial sums)
 constexpr int kMgT = 256;
 constexpr int kMgLanes = 32;      // systems x right-hand sides
 constexpr int kMgChunk0 = 4;      // PCG iterations before the first host check of a run
+// Region coarse space of M_delta: regions are the connected components of the
+// graph of strong couplings |a_ij| > kRegTheta sqrt(a_ii a_jj); the kRegMax
+// largest with at least kRegMin nodes get an indicator vector.
+constexpr int kRegMax = 16;
+constexpr int kRegMin = 64;
+constexpr double kRegTheta = 1e-2;
+constexpr int kRegList = 4096;    // candidate regions collected per system
 
 __device__ __forceinline__ void coords(int32_t i, int nx, int ny, int& ix, int& iy, int& iz) {
     ix = i % nx;
@@ -308,17 +326,33 @@ __global__ __launch_bounds__(kMgT) void k_mg_diag(LvArgs L, double* __restrict__
 
 __device__ __forceinline__ double pw(int d) { return d == 0 ? 1.0 : 0.5; }
 
+// Prolongation weight of fine node i (coords fx, fy, fz) towards coarse node
+// J0(i) + corner c, J0(i) = (fx/2, fy/2, fz/2), c = cz 4 + cy 2 + cx. W: the
+// operator-dependent weights [N][8] of the system, or null for trilinear
+// interpolation (1 on an even axis, 1/2 to both sides on an odd one).
+__device__ __forceinline__ double pweight(const double* __restrict__ W, int64_t i, int fx, int fy, int fz, int c) {
+    if (W) return W[i * 8 + c];
+    const int bx = c & 1, by = (c >> 1) & 1, bz = c >> 2;
+    const double wx = (fx & 1) ? 0.5 : (bx ? 0.0 : 1.0);
+    const double wy = (fy & 1) ? 0.5 : (by ? 0.0 : 1.0);
+    const double wz = (fz & 1) ? 0.5 : (bz ? 0.0 : 1.0);
+    return wx * wy * wz;
+}
+
 // Galerkin coarse operator A_c = P^T A P, diagonal and the 13 upper offsets
 // (code order (dx+1) + 3 (dy+1) + 9 (dz+1) = 13 ... 26) of every coarse node:
 // sum over the fine nodes i in the support of I, the fine stencil entries
 // a_ij, and the coarse nodes J whose support holds j, of P(i,I) a_ij P(j,J).
-__global__ __launch_bounds__(kMgT) void k_mg_rap(LvArgs F, double* __restrict__ Uc, int cx, int cy, int cz) {
+// W: [nsys][N][8] weights of P, or null (trilinear).
+__global__ __launch_bounds__(kMgT) void k_mg_rap(LvArgs F, const double* __restrict__ Wall, double* __restrict__ Uc,
+                                                 int cx, int cy, int cz) {
     __shared__ double acc[kMgT][14];
     const int sys = blockIdx.y;
     const int64_t Nc = (int64_t)cx * cy * cz;
     const int64_t I = blockIdx.x * (int64_t)kMgT + threadIdx.x;
     const int Mf = F.m + 1;
     const double* U = F.U + (int64_t)sys * F.N * Mf;
+    const double* W = Wall ? Wall + (int64_t)sys * F.N * 8 : nullptr;
     for (int k = 0; k < 14; ++k) acc[threadIdx.x][k] = 0.0;
     if (I < Nc) {
         int Ix, Iy, Iz;
@@ -327,8 +361,10 @@ __global__ __launch_bounds__(kMgT) void k_mg_rap(LvArgs F, double* __restrict__ 
             const int ax = di % 3 - 1, ay = (di / 3) % 3 - 1, az = di / 9 - 1;
             const int fx = 2 * Ix + ax, fy = 2 * Iy + ay, fz = 2 * Iz + az;
             if (fx < 0 || fx >= F.nx || fy < 0 || fy >= F.ny || fz < 0 || fz >= F.nz) continue;
-            const double wi = pw(ax) * pw(ay) * pw(az);
             const int32_t i = fx + F.nx * (fy + F.ny * fz);
+            // I = J0(i) + corner, corner 1 exactly along the axes where i sits below 2 I
+            const double wi = pweight(W, i, fx, fy, fz, (ax < 0 ? 1 : 0) + (ay < 0 ? 2 : 0) + (az < 0 ? 4 : 0));
+            if (wi == 0.0) continue;
             // the fine row: diagonal, upper and lower entries
             for (int s = -F.m; s <= F.m; ++s) {
                 int sx = 0, sy = 0, sz = 0, lin = 0;
@@ -347,25 +383,94 @@ __global__ __launch_bounds__(kMgT) void k_mg_rap(LvArgs F, double* __restrict__ 
                     a = s > 0 ? U[(int64_t)i * Mf + s] : U[(int64_t)(i + lin) * Mf + (-s)];
                 }
                 const int jx = fx + sx, jy = fy + sy, jz = fz + sz;
-                // coarse nodes J with j in their support: per axis one (even) or two (odd)
-                for (int Jz = jz >> 1; Jz <= (jz + 1) >> 1; ++Jz) {
-                    if (Jz >= cz) continue;
-                    const double wz = pw(jz - 2 * Jz);
-                    for (int Jy = jy >> 1; Jy <= (jy + 1) >> 1; ++Jy) {
-                        if (Jy >= cy) continue;
-                        const double wy = pw(jy - 2 * Jy);
-                        for (int Jx = jx >> 1; Jx <= (jx + 1) >> 1; ++Jx) {
-                            if (Jx >= cx) continue;
-                            const int code = (Jx - Ix + 1) + 3 * (Jy - Iy + 1) + 9 * (Jz - Iz + 1);
-                            if (code < 13) continue;   // lower half: stored at the partner row
-                            acc[threadIdx.x][code - 13] += wi * a * wz * wy * pw(jx - 2 * Jx);
-                        }
-                    }
+                const int32_t j = i + lin;
+                for (int cj = 0; cj < 8; ++cj) {
+                    const double wj = pweight(W, j, jx, jy, jz, cj);
+                    if (wj == 0.0) continue;
+                    const int Jx = (jx >> 1) + (cj & 1), Jy = (jy >> 1) + ((cj >> 1) & 1), Jz = (jz >> 1) + (cj >> 2);
+                    const int code = (Jx - Ix + 1) + 3 * (Jy - Iy + 1) + 9 * (Jz - Iz + 1);
+                    if (code < 13) continue;   // lower half: stored at the partner row
+                    acc[threadIdx.x][code - 13] += wi * a * wj;
                 }
             }
         }
         double* out = Uc + ((int64_t)sys * Nc + I) * 14;
         for (int k = 0; k < 14; ++k) out[k] = acc[threadIdx.x][k];
+    }
+}
+
+// ------------------------------------------------ operator-dependent transfer
+// Prolongation weights from the operator (M_delta, whose diffusivity drops by
+// orders of magnitude across the edges of the image). A fine node with one odd
+// coordinate takes its two coarse neighbours along that axis with weights
+// -C(-1)/C(0), -C(+1)/C(0) of its stencil collapsed onto the axis (summed
+// over the two even axes); one with two odd coordinates combines its eight
+// in-plane neighbours (interpolated already) with the stencil collapsed over
+// the even axis; one with three odd coordinates its 26 neighbours with the
+// stencil itself. Across an interface the weights towards the weakly coupled
+// side vanish, so the coarse levels keep the regions apart where trilinear
+// interpolation would mix them. A node whose collapsed centre is not positive,
+// or that has no +1 neighbour along an odd axis, keeps the trilinear weights.
+// Parity class = number of odd coordinates; classes run in order 0 ... 3.
+template <int CLASS>
+__global__ __launch_bounds__(kMgT) void k_mg_pweights(LvArgs L, double* __restrict__ Wall) {
+    const int sys = blockIdx.y;
+    const int M1 = L.m + 1;
+    const double* U = L.U + (int64_t)sys * L.N * M1;
+    double* W = Wall + (int64_t)sys * L.N * 8;
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * kMgT) {
+        int ix, iy, iz;
+        coords(static_cast<int32_t>(i), L.nx, L.ny, ix, iy, iz);
+        const int px = ix & 1, py = iy & 1, pz = iz & 1;
+        if (px + py + pz != CLASS) continue;
+        double w[8];
+        for (int c = 0; c < 8; ++c) w[c] = pweight(nullptr, i, ix, iy, iz, c);
+        bool ok = CLASS > 0 && !(px && ix + 1 >= L.nx) && !(py && iy + 1 >= L.ny) && !(pz && iz + 1 >= L.nz);
+        if (ok) {
+            // the row, collapsed over the even axes: C[(dx+1) + 3 (dy+1) + 9 (dz+1)]
+            double C[27];
+            for (int k = 0; k < 27; ++k) C[k] = 0.0;
+            auto put_c = [&](int dx, int dy, int dz, double v) {
+                C[(px ? dx + 1 : 1) + 3 * (py ? dy + 1 : 1) + 9 * (pz ? dz + 1 : 1)] += v;
+            };
+            put_c(0, 0, 0, U[i * M1]);
+            for (int j = 0; j < L.m; ++j) {
+                const int4 t = L.tab[j];
+                if (ix + t.x >= 0 && ix + t.x < L.nx && iy + t.y >= 0 && iy + t.y < L.ny && iz + t.z < L.nz)
+                    put_c(t.x, t.y, t.z, U[i * M1 + j + 1]);
+                if (ix - t.x >= 0 && ix - t.x < L.nx && iy - t.y >= 0 && iy - t.y < L.ny && iz - t.z >= 0)
+                    put_c(-t.x, -t.y, -t.z, U[(i - t.w) * M1 + j + 1]);
+            }
+            const double c0 = C[13];
+            double acc[8];
+            for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+            for (int k = 0; k < 27 && ok; ++k) {
+                if (k == 13 || C[k] == 0.0) continue;
+                const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+                const int nxp = ix + dx, nyp = iy + dy, nzp = iz + dz;
+                if (nxp < 0 || nxp >= L.nx || nyp < 0 || nyp >= L.ny || nzp < 0 || nzp >= L.nz) continue;
+                const int64_t n = nxp + (int64_t)L.nx * (nyp + (int64_t)L.ny * nzp);
+                const double f = -C[k] / c0;
+                // the neighbour's weights, re-indexed to this node's corners
+                for (int cn = 0; cn < 8; ++cn) {
+                    const double wn = W[n * 8 + cn];
+                    if (wn == 0.0) continue;
+                    const int rx = (nxp >> 1) + (cn & 1) - (ix >> 1);
+                    const int ry = (nyp >> 1) + ((cn >> 1) & 1) - (iy >> 1);
+                    const int rz = (nzp >> 1) + (cn >> 2) - (iz >> 1);
+                    if (rx < 0 || rx > 1 || ry < 0 || ry > 1 || rz < 0 || rz > 1) {
+                        ok = false;
+                        break;
+                    }
+                    acc[rx + 2 * ry + 4 * rz] += f * wn;
+                }
+            }
+            ok = ok && c0 > 0.0;
+            for (int c = 0; c < 8 && ok; ++c) ok = isfinite(acc[c]);
+            if (ok)
+                for (int c = 0; c < 8; ++c) w[c] = acc[c];
+        }
+        for (int c = 0; c < 8; ++c) W[i * 8 + c] = w[c];
     }
 }
 
@@ -469,12 +574,13 @@ struct Span {
 };
 
 // bc = P^T r on the coarse level c, and the first sweep there, xc = w D^{-1} bc.
-// Fine nodes 2 I + {-1, 0, 1} per axis, weights 1/2, 1, 1/2; the ones past
-// the lattice get weight 0 (their loads are clamped inside it).
+// Fine nodes 2 I + {-1, 0, 1} per axis, weights 1/2, 1, 1/2 (trilinear) or
+// from Wall ([nsys][Nf][8], operator-dependent); the ones past the lattice
+// get weight 0 (their loads are clamped inside it).
 template <int B>
 __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int32_t ny, int32_t nz,
                                                       const double* __restrict__ r, double* __restrict__ bc,
-                                                      double* __restrict__ xc) {
+                                                      double* __restrict__ xc, const double* __restrict__ Wall) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V;
     const int v = threadIdx.x % Pk<B>::BV;
@@ -484,6 +590,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
         const double w = c.w[sys * c.nlev + c.lev];
         const double* dinv = c.dinv + sys * Nc;
         const double* rs = r + sys * Nf * B + v * V;
+        const double* Ws = Wall ? Wall + sys * Nf * 8 : nullptr;
         const int64_t oc = sys * Nc * B + v * V;
         walk<Pk<B>::BV>(c.L.nx, c.L.ny, c.L.nz, [&](int32_t Ix, int32_t Iy, int32_t Iz, int32_t I, int32_t) {
             int32_t fx[3], fy[3], fz[3];
@@ -507,7 +614,12 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
                     const int32_t row = nx * (fy[dy] + ny * fz[dz]);
                     const double wyz = wy[dy] * wz[dz];
 #pragma unroll
-                    for (int dx = 0; dx < 3; ++dx) s += (wyz * wx[dx]) * vld<T>(rs + (row + fx[dx]) * B);
+                    for (int dx = 0; dx < 3; ++dx) {
+                        double wgt = wyz * wx[dx];
+                        if (Ws && wgt != 0.0)   // I is corner (d == 0 per axis) of fine node 2 I + d - 1
+                            wgt = Ws[(int64_t)(row + fx[dx]) * 8 + (dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)];
+                        s += wgt * vld<T>(rs + (row + fx[dx]) * B);
+                    }
                 }
             vst<T>(bc + oc + I * B, s);
             vst<T>(xc + oc + I * B, (w * dinv[I]) * s);
@@ -516,11 +628,12 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
 }
 
 // x = base + P xc on fine level f (coarse lattice cx, cy, cz). base = x, or
-// with FIRST the first sweep w D^{-1} b, which is then never stored.
+// with FIRST the first sweep w D^{-1} b, which is then never stored. P:
+// trilinear, or the weights Wall ([nsys][Nf][8]).
 template <int B, bool FIRST>
 __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32_t cy, int32_t cz,
                                                      const double* __restrict__ xc, const double* __restrict__ b,
-                                                     double* __restrict__ x) {
+                                                     double* __restrict__ x, const double* __restrict__ Wall) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V;
     const int v = threadIdx.x % Pk<B>::BV;
@@ -532,6 +645,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
         const double* xs = xc + sys * Nc * B + v * V;
         const double* bs = b + sys * Nf * B + v * V;
         double* xf = x + sys * Nf * B + v * V;
+        const double* Ws = Wall ? Wall + sys * Nf * 8 : nullptr;
         walk<Pk<B>::BV>(f.L.nx, f.L.ny, f.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
             const Span sx(ix, cx), sy(iy, cy), sz(iz, cz);
             const int32_t jx[2] = {sx.j0, sx.j1}, jy[2] = {sy.j0, sy.j1}, jz[2] = {sz.j0, sz.j1};
@@ -544,31 +658,50 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
                     const int32_t row = cx * (jy[b2] + cy * jz[c2]);
                     const double wyz = wy[b2] * wz[c2];
 #pragma unroll
-                    for (int a2 = 0; a2 < 2; ++a2) s += (wyz * wx[a2]) * vld<T>(xs + (row + jx[a2]) * B);
+                    for (int a2 = 0; a2 < 2; ++a2) {
+                        // corner (a2, b2, c2) from J0 = (ix/2, iy/2, iz/2); Span
+                        // clamps the index of a zero-weight corner
+                        const double wgt = Ws ? Ws[(int64_t)i * 8 + a2 + 2 * b2 + 4 * c2] : wyz * wx[a2];
+                        s += wgt * vld<T>(xs + (row + jx[a2]) * B);
+                    }
                 }
             vst<T>(xf + i * B, s);
         });
     }
 }
 
-// x = Ainv b on the coarsest level
+// x = Ainv b on the coarsest level: one wavefront per output (system, row,
+// thread-in-node), its lanes splitting the row and summing by shuffles
 template <int B>
 __global__ __launch_bounds__(kMgT) void k_mg_dense(int64_t Nc, int nsys, const double* __restrict__ ainv,
                                                    const double* __restrict__ b, double* __restrict__ x,
                                                    const MgScal* __restrict__ sc) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V, BV = Pk<B>::BV;
-    const int v = threadIdx.x % BV;
-    for (int sys = 0; sys < nsys; ++sys) {
-        if (!pair_active<B>(sc, sys, v)) continue;
-        const double* A = ainv + sys * Nc * Nc;
-        const double* bs = b + sys * Nc * B + v * V;
-        QPAT_MG_ELEMS(e, Nc * BV) {
-            const int64_t I = e / BV;
-            T s = 0.0;
-            for (int64_t J = 0; J < Nc; ++J) s += A[I * Nc + J] * vld<T>(bs + J * B);
-            vst<T>(x + sys * Nc * B + v * V + I * B, s);
-        }
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = blockIdx.x * (int64_t)(kMgT / 64) + (threadIdx.x >> 6);
+    const int64_t per_sys = Nc * BV;
+    if (wid >= nsys * per_sys) return;   // whole wavefronts
+    const int sys = static_cast<int>(wid / per_sys);
+    const int64_t I = (wid % per_sys) / BV;
+    const int v = static_cast<int>(wid % BV);
+    if (!pair_active<B>(sc, sys, v)) return;
+    const double* A = ainv + (sys * Nc + I) * Nc;
+    const double* bs = b + sys * Nc * B + v * V;
+    T s = 0.0;
+    for (int64_t J = lane; J < Nc; J += 64) s += A[J] * vld<T>(bs + J * B);
+    double out[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+        double t = comp(s, c);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off);
+        out[c] = t;
+    }
+    if (lane == 0) {
+        double* xs = x + sys * Nc * B + v * V + I * B;
+#pragma unroll
+        for (int c = 0; c < V; ++c) xs[c] = out[c];
     }
 }
 
@@ -589,6 +722,11 @@ struct PcgMg {
     double rtol2;
     int32_t maxit, deflate, nsys;
     int32_t nb;           // blocks of the kernels that write partials
+    // region coarse space (one right-hand side per system), kreg = 0: off
+    int32_t kreg;
+    const int32_t* reg;   // [nsys][N]
+    const double* ry;     // [nsys][kRegMax]
+    const double* rcorr;  // [nsys][2]
 };
 
 // per-component choice between two V-wide values
@@ -634,7 +772,14 @@ __global__ __launch_bounds__(kMgT) void k_mgp_dir(PcgMg a) {
         const int64_t o = sys * a.L.N * B + v * V;
         QPAT_MG_ELEMS(e, a.L.N * BV) {
             const int64_t at = o + (e / BV) * B;
-            const T pn = vld<T>(a.z + at) - s.c + s.beta * vld<T>(a.po + at);
+            T zc = vld<T>(a.z + at);
+            if constexpr (B == 1) {   // the region coarse-space part of z
+                if (a.kreg > 0) {
+                    const int32_t rg = a.reg[sys * a.L.N + e];
+                    if (rg >= 0) zc += a.ry[sys * kRegMax + rg];
+                }
+            }
+            const T pn = zc - s.c + s.beta * vld<T>(a.po + at);
             vst<T>(a.pn + at, pick(pn, vld<T>(a.pn + at), s.on0, s.on1));
         }
     }
@@ -726,9 +871,13 @@ __global__ __launch_bounds__(kMgT) void k_mgp_scalars(PcgMg a, int phase) {
         }
     } else {
         double rz = red(a.parts, a.nb, lane, 0, sm);
-        const double z1 = red(a.parts, a.nb, lane, 2, sm);
+        double z1 = red(a.parts, a.nb, lane, 2, sm);
         const double r1 = red(a.parts, a.nb, lane, 3, sm);
         if (threadIdx.x == 0) {
+            if (a.kreg > 0) {   // z = V(r) + Z y: r.(Z y) and sum(Z y) from the region sums
+                rz += a.rcorr[2 * lane];
+                z1 += a.rcorr[2 * lane + 1];
+            }
             const double c = a.deflate ? z1 / static_cast<double>(a.L.N) : 0.0;
             rz -= c * r1;     // r.(z - c)
             s.c = c;
@@ -736,6 +885,208 @@ __global__ __launch_bounds__(kMgT) void k_mgp_scalars(PcgMg a, int phase) {
             s.rz = rz;
         }
     }
+}
+
+// ---------------------------------------------------------- region coarse space
+// Partial sums of Z^T r (one right-hand side per system): every thread adds
+// its nodes into kRegMax register accumulators, then fixed-order block sums.
+__global__ __launch_bounds__(kMgT) void k_reg_rsum(PcgMg a, double* __restrict__ rparts) {
+    __shared__ double sm[(kMgT / 64) * kRegMax];
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        if (!a.sc[sys].active) continue;   // uniform over the block
+        double acc[kRegMax];
+#pragma unroll
+        for (int j = 0; j < kRegMax; ++j) acc[j] = 0.0;
+        const int32_t* rg = a.reg + sys * a.L.N;
+        const double* r = a.r + sys * a.L.N;
+        QPAT_MG_ELEMS(i, a.L.N) {
+            const int32_t g = rg[i];
+            const double v = r[i];
+#pragma unroll
+            for (int j = 0; j < kRegMax; ++j) acc[j] += g == j ? v : 0.0;
+        }
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int j = 0; j < kRegMax; ++j) {
+            double t = acc[j];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off);
+            if (lane == 0) sm[wave * kRegMax + j] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < kRegMax) {
+            double t = 0.0;
+            for (int w = 0; w < kMgT / 64; ++w) t += sm[w * kRegMax + threadIdx.x];
+            rparts[(sys * kRegMax + threadIdx.x) * kMgBlocks + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// y = E^{-1} Z^T r and the corrections r.(Z y), sum(Z y) of the dot products;
+// one block per system (blockIdx.y)
+__global__ __launch_bounds__(kMgT) void k_reg_solve(PcgMg a, const double* __restrict__ rparts,
+                                                    const double* __restrict__ einv, const double* __restrict__ rsize,
+                                                    double* __restrict__ ry, double* __restrict__ rcorr) {
+    __shared__ double zr[kRegMax], yy[kRegMax];
+    const int sys = blockIdx.y;
+    if (!a.sc[sys].active) return;
+    const int t = threadIdx.x;
+    if (t < kRegMax) {
+        double s = 0.0;
+        for (int b = 0; b < a.nb; ++b) s += rparts[(sys * kRegMax + t) * kMgBlocks + b];
+        zr[t] = t < a.kreg ? s : 0.0;
+    }
+    __syncthreads();
+    if (t < kRegMax) {
+        double y = 0.0;
+        for (int b = 0; b < a.kreg; ++b) y += einv[(sys * kRegMax + t) * kRegMax + b] * zr[b];
+        yy[t] = t < a.kreg ? y : 0.0;
+        ry[sys * kRegMax + t] = yy[t];
+    }
+    __syncthreads();
+    if (t == 0) {
+        double c0 = 0.0, c1 = 0.0;
+        for (int j = 0; j < a.kreg; ++j) {
+            c0 += yy[j] * zr[j];
+            c1 += yy[j] * rsize[sys * kRegMax + j];
+        }
+        rcorr[2 * sys] = c0;
+        rcorr[2 * sys + 1] = c1;
+    }
+}
+
+// ---- set-up: connected components of the strong couplings (labels converge
+// to the smallest node id of each component), region sizes, E = Z^T A Z
+
+// strong coupling of nodes i and j through a_ij
+__device__ __forceinline__ bool strong(double aij, double aii, double ajj) {
+    return fabs(aij) > kRegTheta * sqrt(fabs(aii * ajj));
+}
+
+__global__ __launch_bounds__(kMgT) void k_reg_init(int32_t* __restrict__ lab, int64_t N) {
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kMgT)
+        lab[i] = static_cast<int32_t>(i);
+}
+
+// hook: every node and the root of its label take the smallest label among
+// its strong neighbours
+__global__ __launch_bounds__(kMgT) void k_reg_prop(LvArgs L, int32_t* lab, int32_t* __restrict__ flag) {
+    const int M1 = L.m + 1;
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * kMgT) {
+        int ix, iy, iz;
+        coords(static_cast<int32_t>(i), L.nx, L.ny, ix, iy, iz);
+        const double aii = L.U[i * M1];
+        const int32_t li = __hip_atomic_load(lab + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int32_t mi = li;
+        for (int j = 0; j < L.m; ++j) {
+            const int4 t = L.tab[j];
+            if (ix + t.x >= 0 && ix + t.x < L.nx && iy + t.y >= 0 && iy + t.y < L.ny && iz + t.z < L.nz) {
+                const int64_t k = i + t.w;
+                if (strong(L.U[i * M1 + j + 1], aii, L.U[k * M1]))
+                    mi = min(mi, __hip_atomic_load(lab + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            }
+            if (ix - t.x >= 0 && ix - t.x < L.nx && iy - t.y >= 0 && iy - t.y < L.ny && iz - t.z >= 0) {
+                const int64_t k = i - t.w;
+                if (strong(L.U[k * M1 + j + 1], aii, L.U[k * M1]))
+                    mi = min(mi, __hip_atomic_load(lab + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            }
+        }
+        if (mi < li) {
+            atomicMin(lab + li, mi);
+            atomicMin(lab + i, mi);
+            *flag = 1;
+        }
+    }
+}
+
+// pointer jumping: lab[i] <- lab[lab[i]]
+__global__ __launch_bounds__(kMgT) void k_reg_jump(int32_t* lab, int64_t N) {
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kMgT) {
+        const int32_t l = __hip_atomic_load(lab + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t ll = __hip_atomic_load(lab + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ll < l) atomicMin(lab + i, ll);
+    }
+}
+
+__global__ __launch_bounds__(kMgT) void k_reg_count(const int32_t* __restrict__ lab, int32_t* __restrict__ cnt,
+                                                    int64_t N) {
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kMgT)
+        atomicAdd(cnt + lab[i], 1);
+}
+
+// components with at least kRegMin nodes: (root, size) pairs, in any order
+__global__ __launch_bounds__(kMgT) void k_reg_roots(const int32_t* __restrict__ lab, const int32_t* __restrict__ cnt,
+                                                    int64_t N, int32_t* __restrict__ list, int32_t* __restrict__ n) {
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kMgT) {
+        if (lab[i] != i || cnt[i] < kRegMin) continue;
+        const int32_t at = atomicAdd(n, 1);
+        if (at < kRegList) {
+            list[2 * at] = static_cast<int32_t>(i);
+            list[2 * at + 1] = cnt[i];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kMgT) void k_reg_assign(const int32_t* __restrict__ lab, int64_t N, int k,
+                                                     const int32_t* __restrict__ roots, int32_t* __restrict__ reg) {
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kMgT) {
+        int32_t r = -1;
+        for (int j = 0; j < k; ++j)
+            if (lab[i] == roots[j]) r = j;
+        reg[i] = r;
+    }
+}
+
+// largest |a_ij| (bit pattern of a non-negative double)
+__global__ __launch_bounds__(kMgT) void k_reg_absmax(const double* __restrict__ U, int64_t n,
+                                                     unsigned long long* __restrict__ out) {
+    __shared__ double sm[kMgT / 64];
+    double m = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)kMgT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kMgT)
+        m = fmax(m, fabs(U[e]));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kMgT / 64; ++w) m = fmax(m, sm[w]);
+        atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(m)));
+    }
+}
+
+// E = Z^T A Z in fixed point (scale: exact, order-independent integer sums):
+// the diagonal entry of every node and each stored upper entry a_ij in both
+// (reg i, reg j) and (reg j, reg i)
+__global__ __launch_bounds__(kMgT) void k_reg_e(LvArgs L, const int32_t* __restrict__ reg, double scale,
+                                                unsigned long long* __restrict__ eint) {
+    __shared__ unsigned long long se[kRegMax * kRegMax];
+    for (int t = threadIdx.x; t < kRegMax * kRegMax; t += kMgT) se[t] = 0ull;
+    __syncthreads();
+    const int M1 = L.m + 1;
+    auto add = [&](int a, int b, double v) {
+        const long long q = llrint(v * scale);
+        atomicAdd(se + a * kRegMax + b, static_cast<unsigned long long>(q));
+    };
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * kMgT) {
+        const int a = reg[i];
+        if (a < 0) continue;
+        int ix, iy, iz;
+        coords(static_cast<int32_t>(i), L.nx, L.ny, ix, iy, iz);
+        add(a, a, L.U[i * M1]);
+        for (int j = 0; j < L.m; ++j) {
+            const int4 t = L.tab[j];
+            if (!(ix + t.x >= 0 && ix + t.x < L.nx && iy + t.y >= 0 && iy + t.y < L.ny && iz + t.z < L.nz)) continue;
+            const int b = reg[i + t.w];
+            if (b < 0) continue;
+            const double v = L.U[i * M1 + j + 1];
+            add(a, b, v);
+            add(b, a, v);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kRegMax * kRegMax; t += kMgT)
+        if (se[t]) atomicAdd(eint + t, se[t]);
 }
 
 // partial sums of b and b.b per lane
@@ -1257,20 +1608,22 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
             QPAT_MG_KIND(L.kind, B, k_mg_resid, g, dim3(kMgT), 0, st, a, L.b, xl[l], L.r);
         if (l == 0 && ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL(k_mg_restrict<B>, sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny, L.nz, L.r, C.b,
-                           xl[l + 1]);
+                           xl[l + 1], M.opdep ? L.W : nullptr);
     }
     const MgLevel& K = M.lv[nl - 1];
-    hipLaunchKernelGGL(k_mg_dense<B>, sgrid<B>(K.N), dim3(kMgT), 0, st, K.N, M.nsys, M.ainv, K.b, xl[nl - 1], M.sc);
+    hipLaunchKernelGGL(k_mg_dense<B>, dim3((unsigned)((M.nsys * K.N * Pk<B>::BV + kMgT / 64 - 1) / (kMgT / 64))),
+                       dim3(kMgT), 0, st, K.N, M.nsys, M.ainv, K.b, xl[nl - 1], M.sc);
     for (int l = nl - 2; l >= 0; --l) {
         const MgLevel& L = M.lv[l];
         const MgLevel& C = M.lv[l + 1];
         const SmArgs a = sm(l);
         const dim3 g = sgrid<B>(L.N);
         if (l == 0 && fused0)
-            hipLaunchKernelGGL((k_mg_prolong<B, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], L.b, xl[0]);
+            hipLaunchKernelGGL((k_mg_prolong<B, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], L.b, xl[0],
+                               M.opdep ? L.W : nullptr);
         else
             hipLaunchKernelGGL((k_mg_prolong<B, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1], L.b,
-                               xl[l]);
+                               xl[l], M.opdep ? L.W : nullptr);
         for (int k = 0; k < kMgNu; ++k) {
             const bool last = l == 0 && k == kMgNu - 1;
             if (last && ev) (void)hipEventRecord(ev[2], st);
@@ -1307,7 +1660,19 @@ PcgMg pcg_args(qpat_ctx* c, Op op) {
     a.deflate = op == Op::Prior ? c->opts.prior_deflate : 0;
     a.nsys = M.nsys;
     a.nb = static_cast<int32_t>(sgrid<B>(c->N).x);
+    a.kreg = B == 1 ? M.kreg : 0;
+    a.reg = M.reg;
+    a.ry = M.ry;
+    a.rcorr = M.rcorr;
     return a;
+}
+
+// the region coarse-space part of the preconditioner for the current r
+template <int B>
+void region_solve(const MgState& M, const PcgMg& a, hipStream_t st) {
+    if (a.kreg <= 0) return;
+    hipLaunchKernelGGL(k_reg_rsum, sgrid<B>(a.L.N), dim3(kMgT), 0, st, a, M.rparts);
+    hipLaunchKernelGGL(k_reg_solve, dim3(1, a.nsys), dim3(kMgT), 0, st, a, M.rparts, M.einv, M.rsize, M.ry, M.rcorr);
 }
 
 // one iteration after the first direction: direction and product, alpha,
@@ -1332,6 +1697,7 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
     hipLaunchKernelGGL(k_mgp_update<B>, g, dim3(kMgT), 0, st, a);
     if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 1);
+    region_solve<B>(M, a, st);
     vcycle<B>(M, st, tg, ev ? ev + 4 : nullptr);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 2);
 }
@@ -1375,7 +1741,8 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
     for (int restart = 0; restart < 4; ++restart) {
         QPAT_TRY(fetch());
         if (!any_active()) break;
-        // first direction of a run: z = V(r), p = z - c
+        // first direction of a run: z = V(r) (+ Z y), p = z - c
+        region_solve<B>(M, a, sm);
         vcycle<B>(M, sm, tg);
         hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, sm, a, 3);
         QPAT_HIP(c, hipGetLastError());
@@ -1513,6 +1880,113 @@ bool mg_ready(qpat_ctx* c, Op op) {
     return mg_available(c, op) && M && M->current;
 }
 
+// Region coarse space of the finest level of M (one system at a time): labels
+// of the strong-coupling components, the kRegMax largest regions with at
+// least kRegMin nodes, E = Z^T A Z (exact integer sums) and its inverse.
+static qpat_status region_setup(qpat_ctx* c, MgState& M) {
+    const MgLevel& F = M.lv[0];
+    const int64_t N = F.N;
+    const int M1 = F.m + 1;
+    if (!M.reg) {
+        QPAT_TRY(dalloc(c, &M.reg, M.nsys * N));
+        QPAT_TRY(dalloc(c, &M.einv, M.nsys * kRegMax * kRegMax));
+        QPAT_TRY(dalloc(c, &M.rsize, M.nsys * kRegMax));
+        QPAT_TRY(dalloc(c, &M.rparts, (int64_t)M.nsys * kRegMax * kMgBlocks));
+        QPAT_TRY(dalloc(c, &M.ry, M.nsys * kRegMax));
+        QPAT_TRY(dalloc(c, &M.rcorr, 2 * M.nsys));
+    }
+    int32_t *lab = nullptr, *cnt = nullptr, *flag = nullptr, *list = nullptr, *roots = nullptr;
+    unsigned long long *eint = nullptr, *amax = nullptr;
+    QPAT_TRY(dalloc(c, &lab, N));
+    QPAT_TRY(dalloc(c, &cnt, N));
+    QPAT_TRY(dalloc(c, &flag, 2));
+    QPAT_TRY(dalloc(c, &list, 2 * kRegList));
+    QPAT_TRY(dalloc(c, &roots, kRegMax));
+    QPAT_TRY(dalloc(c, &eint, kRegMax * kRegMax));
+    QPAT_TRY(dalloc(c, &amax, 1));
+    hipStream_t st = c->stream;
+    const dim3 g(grid_for(N, kMgT, 4096)), b(kMgT);
+    std::vector<double> einv_h(M.nsys * kRegMax * kRegMax, 0.0), size_h(M.nsys * kRegMax, 0.0);
+    M.kreg = 0;
+    for (int sys = 0; sys < M.nsys; ++sys) {
+        LvArgs L = lv_args(F);
+        L.U = F.U + sys * N * M1;
+        hipLaunchKernelGGL(k_reg_init, g, b, 0, st, lab, N);
+        for (int round = 0;; ++round) {
+            if (round > 4096) return fail(c, QPAT_ERR_DEVICE, "region labels did not settle");
+            QPAT_HIP(c, hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+            hipLaunchKernelGGL(k_reg_prop, g, b, 0, st, L, lab, flag);
+            hipLaunchKernelGGL(k_reg_jump, g, b, 0, st, lab, N);
+            hipLaunchKernelGGL(k_reg_jump, g, b, 0, st, lab, N);
+            int32_t fh = 0;
+            QPAT_HIP(c, hipMemcpyAsync(&fh, flag, sizeof fh, hipMemcpyDeviceToHost, st));
+            QPAT_HIP(c, hipStreamSynchronize(st));
+            if (!fh) break;
+        }
+        QPAT_HIP(c, hipMemsetAsync(cnt, 0, N * sizeof(int32_t), st));
+        hipLaunchKernelGGL(k_reg_count, g, b, 0, st, lab, cnt, N);
+        QPAT_HIP(c, hipMemsetAsync(flag + 1, 0, sizeof(int32_t), st));
+        hipLaunchKernelGGL(k_reg_roots, g, b, 0, st, lab, cnt, N, list, flag + 1);
+        int32_t nl = 0;
+        QPAT_HIP(c, hipMemcpyAsync(&nl, flag + 1, sizeof nl, hipMemcpyDeviceToHost, st));
+        QPAT_HIP(c, hipStreamSynchronize(st));
+        nl = std::min(nl, kRegList);
+        std::vector<int32_t> lh(2 * std::max(nl, 1));
+        if (nl > 0)
+            QPAT_HIP(c, hipMemcpyAsync(lh.data(), list, 2 * nl * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        QPAT_HIP(c, hipStreamSynchronize(st));
+        std::vector<std::pair<int32_t, int32_t>> cand;   // (size, root)
+        for (int i = 0; i < nl; ++i) cand.push_back({lh[2 * i + 1], lh[2 * i]});
+        std::sort(cand.begin(), cand.end(), [](const auto& x, const auto& y) {
+            return x.first != y.first ? x.first > y.first : x.second < y.second;
+        });
+        int k = std::min<int>(kRegMax, static_cast<int>(cand.size()));
+        int32_t rt[kRegMax] = {};
+        for (int j = 0; j < k; ++j) rt[j] = cand[j].second;
+        QPAT_HIP(c, hipMemcpyAsync(roots, rt, sizeof rt, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_reg_assign, g, b, 0, st, lab, N, k, roots, M.reg + sys * N);
+        // E in fixed point: every sum of |contributions| stays below 2^62
+        QPAT_HIP(c, hipMemsetAsync(amax, 0, sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(k_reg_absmax, g, b, 0, st, L.U, N * M1, amax);
+        unsigned long long ab = 0;
+        QPAT_HIP(c, hipMemcpyAsync(&ab, amax, sizeof ab, hipMemcpyDeviceToHost, st));
+        QPAT_HIP(c, hipStreamSynchronize(st));
+        double maxabs;
+        std::memcpy(&maxabs, &ab, sizeof maxabs);
+        if (k > 0 && maxabs > 0.0 && std::isfinite(maxabs)) {
+            const double bound = static_cast<double>(N) * (2 * F.m + 1) * maxabs;
+            const double scale = std::ldexp(1.0, static_cast<int>(std::floor(62.0 - std::log2(bound))));
+            QPAT_HIP(c, hipMemsetAsync(eint, 0, kRegMax * kRegMax * sizeof(unsigned long long), st));
+            hipLaunchKernelGGL(k_reg_e, g, b, 0, st, L, M.reg + sys * N, scale, eint);
+            std::vector<unsigned long long> eh(kRegMax * kRegMax);
+            QPAT_HIP(c, hipMemcpyAsync(eh.data(), eint, eh.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                       st));
+            QPAT_HIP(c, hipStreamSynchronize(st));
+            std::vector<double> E((size_t)k * k);
+            for (int i = 0; i < k; ++i)
+                for (int j = 0; j < k; ++j)
+                    E[(size_t)i * k + j] = static_cast<double>(static_cast<long long>(eh[i * kRegMax + j])) / scale;
+            if (!spd_inverse(E, k)) k = 0;   // not positive definite in fixed point: no region space
+            for (int i = 0; i < k; ++i) {
+                size_h[sys * kRegMax + i] = cand[i].first;
+                for (int j = 0; j < k; ++j) einv_h[(sys * kRegMax + i) * kRegMax + j] = E[(size_t)i * k + j];
+            }
+        } else {
+            k = 0;
+        }
+        if (k == 0) hipLaunchKernelGGL(k_reg_assign, g, b, 0, st, lab, N, 0, roots, M.reg + sys * N);
+        M.nreg[sys] = k;
+        M.kreg = std::max(M.kreg, k);
+    }
+    QPAT_HIP(c, hipMemcpyAsync(M.einv, einv_h.data(), einv_h.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    QPAT_HIP(c, hipMemcpyAsync(M.rsize, size_h.data(), size_h.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    QPAT_HIP(c, hipGetLastError());
+    QPAT_HIP(c, hipStreamSynchronize(st));
+    for (void* p : {(void*)lab, (void*)cnt, (void*)flag, (void*)list, (void*)roots, (void*)eint, (void*)amax})
+        QPAT_TRY(dfree(c, p));
+    return QPAT_OK;
+}
+
 // Hierarchy for the current operator (after its assembly and stencil form).
 // Called after every assembly: when the options turn multigrid off, an older
 // hierarchy is marked stale so that turning it on again cannot pick it up.
@@ -1579,6 +2053,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             QPAT_TRY(dalloc(c, &L.x, V * L.N));
             QPAT_TRY(dalloc(c, &L.t, V * L.N));
             QPAT_TRY(dalloc(c, &L.r, V * L.N));
+            if (op == Op::Prior && l + 1 < nl) QPAT_TRY(dalloc(c, &L.W, nsys * L.N * 8));
         }
         QPAT_TRY(dalloc(c, &M.w, nsys * nl));
         QPAT_TRY(dalloc(c, &M.gmax, nsys * nl));
@@ -1596,11 +2071,19 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     MgState& M = *Mp;
     const int nl = static_cast<int>(M.lv.size());
     M.lv[0].U = op == Op::K ? c->KU64 : c->MU64;
+    M.opdep = op == Op::Prior;
     for (int l = 0; l + 1 < nl; ++l) {
         const MgLevel& F = M.lv[l];
         const MgLevel& C = M.lv[l + 1];
+        if (M.opdep) {   // prolongation weights from this level's operator, by parity class
+            const dim3 g(grid_for(F.N, kMgT, 4096), nsys);
+            hipLaunchKernelGGL(k_mg_pweights<0>, g, dim3(kMgT), 0, c->stream, lv_args(F), F.W);
+            hipLaunchKernelGGL(k_mg_pweights<1>, g, dim3(kMgT), 0, c->stream, lv_args(F), F.W);
+            hipLaunchKernelGGL(k_mg_pweights<2>, g, dim3(kMgT), 0, c->stream, lv_args(F), F.W);
+            hipLaunchKernelGGL(k_mg_pweights<3>, g, dim3(kMgT), 0, c->stream, lv_args(F), F.W);
+        }
         hipLaunchKernelGGL(k_mg_rap, dim3((unsigned)((C.N + kMgT - 1) / kMgT), nsys), dim3(kMgT), 0, c->stream,
-                           lv_args(F), C.U, C.nx, C.ny, C.nz);
+                           lv_args(F), M.opdep ? F.W : nullptr, C.U, C.nx, C.ny, C.nz);
     }
     QPAT_HIP(c, hipMemsetAsync(M.gmax, 0, nsys * nl * sizeof(uint64_t), c->stream));
     for (int l = 0; l < nl; ++l)
@@ -1645,6 +2128,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     }
     QPAT_HIP(c, hipMemcpyAsync(M.ainv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    if (op == Op::Prior) QPAT_TRY(region_setup(c, M));
     M.current = true;
     return QPAT_OK;
 }
