@@ -1473,6 +1473,13 @@ bool spd_inverse(std::vector<double>& A, int n) {
         }
         for (int i = 0; i < n; ++i) A[(size_t)i * n + col] = y[i];
     }
+    // the columns carry independent rounding: make the inverse exactly
+    // symmetric, as the preconditioner it is part of must be
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+            A[(size_t)i * n + j] = A[(size_t)j * n + i] = v;
+        }
     return true;
 }
 
