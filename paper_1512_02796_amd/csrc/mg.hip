@@ -577,7 +577,7 @@ struct Span {
 // Fine nodes 2 I + {-1, 0, 1} per axis, weights 1/2, 1, 1/2 (trilinear) or
 // from Wall ([nsys][Nf][8], operator-dependent); the ones past the lattice
 // get weight 0 (their loads are clamped inside it).
-template <int B>
+template <int B, bool OPW>
 __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int32_t ny, int32_t nz,
                                                       const double* __restrict__ r, double* __restrict__ bc,
                                                       double* __restrict__ xc, const double* __restrict__ Wall) {
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
         const double w = c.w[sys * c.nlev + c.lev];
         const double* dinv = c.dinv + sys * Nc;
         const double* rs = r + sys * Nf * B + v * V;
-        const double* Ws = Wall ? Wall + sys * Nf * 8 : nullptr;
+        const double* Ws = OPW ? Wall + sys * Nf * 8 : nullptr;
         const int64_t oc = sys * Nc * B + v * V;
         walk<Pk<B>::BV>(c.L.nx, c.L.ny, c.L.nz, [&](int32_t Ix, int32_t Iy, int32_t Iz, int32_t I, int32_t) {
             int32_t fx[3], fy[3], fz[3];
@@ -616,8 +616,9 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
 #pragma unroll
                     for (int dx = 0; dx < 3; ++dx) {
                         double wgt = wyz * wx[dx];
-                        if (Ws && wgt != 0.0)   // I is corner (d == 0 per axis) of fine node 2 I + d - 1
-                            wgt = Ws[(int64_t)(row + fx[dx]) * 8 + (dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)];
+                        if constexpr (OPW)   // I is corner (d == 0 per axis) of fine node 2 I + d - 1
+                            if (wgt != 0.0)
+                                wgt = Ws[(int64_t)(row + fx[dx]) * 8 + (dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)];
                         s += wgt * vld<T>(rs + (row + fx[dx]) * B);
                     }
                 }
@@ -630,7 +631,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
 // x = base + P xc on fine level f (coarse lattice cx, cy, cz). base = x, or
 // with FIRST the first sweep w D^{-1} b, which is then never stored. P:
 // trilinear, or the weights Wall ([nsys][Nf][8]).
-template <int B, bool FIRST>
+template <int B, bool FIRST, bool OPW>
 __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32_t cy, int32_t cz,
                                                      const double* __restrict__ xc, const double* __restrict__ b,
                                                      double* __restrict__ x, const double* __restrict__ Wall) {
@@ -645,7 +646,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
         const double* xs = xc + sys * Nc * B + v * V;
         const double* bs = b + sys * Nf * B + v * V;
         double* xf = x + sys * Nf * B + v * V;
-        const double* Ws = Wall ? Wall + sys * Nf * 8 : nullptr;
+        const double* Ws = OPW ? Wall + sys * Nf * 8 : nullptr;
         walk<Pk<B>::BV>(f.L.nx, f.L.ny, f.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
             const Span sx(ix, cx), sy(iy, cy), sz(iz, cz);
             const int32_t jx[2] = {sx.j0, sx.j1}, jy[2] = {sy.j0, sy.j1}, jz[2] = {sz.j0, sz.j1};
@@ -661,7 +662,11 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
                     for (int a2 = 0; a2 < 2; ++a2) {
                         // corner (a2, b2, c2) from J0 = (ix/2, iy/2, iz/2); Span
                         // clamps the index of a zero-weight corner
-                        const double wgt = Ws ? Ws[(int64_t)i * 8 + a2 + 2 * b2 + 4 * c2] : wyz * wx[a2];
+                        double wgt;
+                        if constexpr (OPW)
+                            wgt = Ws[(int64_t)i * 8 + a2 + 2 * b2 + 4 * c2];
+                        else
+                            wgt = wyz * wx[a2];
                         s += wgt * vld<T>(xs + (row + jx[a2]) * B);
                     }
                 }
@@ -1009,10 +1014,23 @@ __global__ __launch_bounds__(kMgT) void k_reg_jump(int32_t* lab, int64_t N) {
     }
 }
 
+// component sizes; the lanes of a wavefront that share a label add once
+// (one component holds most nodes, so per-node atomics would serialise)
 __global__ __launch_bounds__(kMgT) void k_reg_count(const int32_t* __restrict__ lab, int32_t* __restrict__ cnt,
                                                     int64_t N) {
-    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kMgT)
-        atomicAdd(cnt + lab[i], 1);
+    const int lane = threadIdx.x & 63;
+    for (int64_t i0 = blockIdx.x * (int64_t)kMgT; i0 < N; i0 += (int64_t)gridDim.x * kMgT) {
+        const int64_t i = i0 + threadIdx.x;
+        const int32_t l = i < N ? lab[i] : -1;
+        unsigned long long todo = __ballot(l >= 0);
+        while (todo) {
+            const int leader = __ffsll(static_cast<long long>(todo)) - 1;
+            const int32_t ll = __shfl(l, leader);
+            const unsigned long long same = __ballot(l == ll) & todo;
+            if (lane == leader) atomicAdd(cnt + ll, __popcll(same));
+            todo &= ~same;
+        }
+    }
 }
 
 // components with at least kRegMin nodes: (root, size) pairs, in any order
@@ -1614,8 +1632,12 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         else
             QPAT_MG_KIND(L.kind, B, k_mg_resid, g, dim3(kMgT), 0, st, a, L.b, xl[l], L.r);
         if (l == 0 && ev) (void)hipEventRecord(ev[1], st);
-        hipLaunchKernelGGL(k_mg_restrict<B>, sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny, L.nz, L.r, C.b,
-                           xl[l + 1], M.opdep ? L.W : nullptr);
+        if (M.opdep)
+            hipLaunchKernelGGL((k_mg_restrict<B, true>), sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny,
+                               L.nz, L.r, C.b, xl[l + 1], L.W);
+        else
+            hipLaunchKernelGGL((k_mg_restrict<B, false>), sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny,
+                               L.nz, L.r, C.b, xl[l + 1], nullptr);
     }
     const MgLevel& K = M.lv[nl - 1];
     hipLaunchKernelGGL(k_mg_dense<B>, dim3((unsigned)((M.nsys * K.N * Pk<B>::BV + kMgT / 64 - 1) / (kMgT / 64))),
@@ -1625,12 +1647,18 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         const MgLevel& C = M.lv[l + 1];
         const SmArgs a = sm(l);
         const dim3 g = sgrid<B>(L.N);
-        if (l == 0 && fused0)
-            hipLaunchKernelGGL((k_mg_prolong<B, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], L.b, xl[0],
-                               M.opdep ? L.W : nullptr);
+        if (l == 0 && fused0 && M.opdep)
+            hipLaunchKernelGGL((k_mg_prolong<B, true, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], L.b,
+                               xl[0], L.W);
+        else if (l == 0 && fused0)
+            hipLaunchKernelGGL((k_mg_prolong<B, true, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], L.b,
+                               xl[0], nullptr);
+        else if (M.opdep)
+            hipLaunchKernelGGL((k_mg_prolong<B, false, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1],
+                               L.b, xl[l], L.W);
         else
-            hipLaunchKernelGGL((k_mg_prolong<B, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1], L.b,
-                               xl[l], M.opdep ? L.W : nullptr);
+            hipLaunchKernelGGL((k_mg_prolong<B, false, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1],
+                               L.b, xl[l], nullptr);
         for (int k = 0; k < kMgNu; ++k) {
             const bool last = l == 0 && k == kMgNu - 1;
             if (last && ev) (void)hipEventRecord(ev[2], st);
