@@ -11,7 +11,11 @@
 // with S(u)_ab = mean_T(u) |T| grad(l_a).grad(l_b) and
 // Mass(u)_ab = |T| (1 + d_ab) (sum_T u + u_a + u_b) / 120.
 // Data-space vectors inside the library are interleaved [N][n_pad]; the
-// illuminations are solved in blocks of B right-hand sides.
+// illuminations are solved in blocks of B right-hand sides. J s: on lattice
+// meshes S(u1) + Mass(u2) is assembled once per product in the stencil form
+// and applied to each block by the tiled stencil kernel; elsewhere a node
+// loop over the adjacent elements per block. J^T t: the G^T terms are summed
+// per element over the blocks, then gathered per node.
 #include "qpat_internal.h"
 
 namespace qpat {
@@ -94,82 +98,154 @@ __global__ __launch_bounds__(kThreads) void k_gfwd(int64_t N, const int32_t* __r
     for (int i = 0; i < KG; ++i) b[row * B + k0 + i] = acc[i];
 }
 
-// a1[row] (+)= -sum_k sum_T |T|/4 grad(phi_k).grad(z_k)
-// a2[row] (+)= sum_k [ -(Mass(phi_k) z_k)_row + phi_k,row t_k,row ]
-// tmode 0: t external [n_ill][N]; tmode 1: t = W u interleaved [N][n_pad]
-template <int B>
-__global__ __launch_bounds__(kThreads) void k_gadj(int64_t N, const int32_t* __restrict__ tets,
-                                                  const double* __restrict__ geo, const int32_t* __restrict__ n2t_ptr,
-                                                  const int32_t* __restrict__ n2t, const double* __restrict__ phi,
-                                                  int n_pad, int n_ill, int col0, const double* __restrict__ z,
-                                                  int tmode, const double* __restrict__ t_ext,
-                                                  const double* __restrict__ W, const double* __restrict__ U,
-                                                  int first, double* __restrict__ a1, double* __restrict__ a2) {
-    constexpr int KG = kGroup<B>, G = B / KG;
-    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool valid = t < N * G;
-    const int64_t row = valid ? t / G : 0;
-    const int k0 = static_cast<int>(t % G) * KG;
-    double acc1 = 0.0, acc2 = 0.0;
-    if (valid) {
-        for (int32_t q = n2t_ptr[row]; q < n2t_ptr[row + 1]; ++q) {
-            const int32_t e = n2t[q] >> 2, a = n2t[q] & 3;
-            Geo4 G4;
-            load_geo4(geo, e, G4);
-            int32_t v[4];
+// ---- lattice meshes: the same products through the stencil form
+// dK(s) = S(kappa s1) + Mass(mu s2) in the stencil form of the lattice
+// (diagonal and upper offsets, [N][m+1]): the element sums of the assembly of
+// K without the boundary term, so G(1) diag(kappa) s1 + G(2) diag(mu) s2 =
+// -dK(s) phi for every illumination, one stencil product per block.
+__global__ __launch_bounds__(kThreads) void k_dk_lattice(int64_t N, Lattice lat, const int32_t* __restrict__ tets,
+                                                         const double* __restrict__ geo,
+                                                         const int32_t* __restrict__ n2t_ptr,
+                                                         const int32_t* __restrict__ n2t,
+                                                         const double* __restrict__ kappa,
+                                                         const double* __restrict__ mu, const double* __restrict__ s,
+                                                         double* __restrict__ U) {
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (row >= N) return;
+    const int M1 = lat.m + 1;
+    const int64_t nxy = (int64_t)lat.nx * lat.ny;
+    const int rx = static_cast<int>(row % lat.nx), ry = static_cast<int>((row / lat.nx) % lat.ny),
+              rz = static_cast<int>(row / nxy);
+    double acc[kMaxUpper + 1];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) v[c] = tets[4 * e + c];
+    for (int j = 0; j <= kMaxUpper; ++j) acc[j] = 0.0;
+    for (int32_t q = n2t_ptr[row]; q < n2t_ptr[row + 1]; ++q) {
+        const int32_t e = n2t[q] >> 2, a = n2t[q] & 3;
+        Geo4 G4;
+        load_geo4(geo, e, G4);
+        int32_t v[4];
+        double u1 = 0.0, u2[4], s2 = 0.0;
 #pragma unroll
-            for (int i = 0; i < KG; ++i) {
-                const int kk = col0 + k0 + i;
-                double ph[4], zz[4], sp = 0.0;
-                double gp[3] = {0.0, 0.0, 0.0}, gz[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    ph[c] = phi[(int64_t)v[c] * n_pad + kk];
-                    zz[c] = z[(int64_t)v[c] * B + k0 + i];
-                    sp += ph[c];
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        gp[d] += ph[c] * G4.g[c][d];
-                        gz[d] += zz[c] * G4.g[c][d];
-                    }
-                }
-                acc1 -= 0.25 * G4.vol * (gp[0] * gz[0] + gp[1] * gz[1] + gp[2] * gz[2]);
-                double pa = 0.0;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) pa = c == a ? ph[c] : pa;
-                double mass = 0.0;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) mass += (c == a ? 2.0 : 1.0) * (sp + pa + ph[c]) * zz[c];
-                acc2 -= G4.vol * (1.0 / 120.0) * mass;
-            }
+        for (int c = 0; c < 4; ++c) {
+            v[c] = tets[4 * e + c];
+            u1 += kappa[v[c]] * s[v[c]];
+            u2[c] = mu[v[c]] * s[N + v[c]];
+            s2 += u2[c];
         }
+        u1 *= 0.25;
+        double ga[3], u2a = 0.0;
 #pragma unroll
-        for (int i = 0; i < KG; ++i) {
-            const int kk = col0 + k0 + i;
-            double tv = 0.0;
-            if (kk < n_ill) {
-                if (tmode == 0) tv = t_ext[(int64_t)kk * N + row];
-                else tv = W[row * n_pad + kk] * U[row * n_pad + kk];
+        for (int c = 0; c < 4; ++c)
+            if (c == a) u2a = u2[c];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ga[d] = G4.g[a][d];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double gg = ga[0] * G4.g[c][0] + ga[1] * G4.g[c][1] + ga[2] * G4.g[c][2];
+            const double w = u1 * G4.vol * gg + G4.vol * (1.0 / 120.0) * (c == a ? 2.0 : 1.0) * (s2 + u2a + u2[c]);
+            const int64_t vc = v[c];
+            const int dx = static_cast<int>(vc % lat.nx) - rx, dy = static_cast<int>((vc / lat.nx) % lat.ny) - ry,
+                      dz = static_cast<int>(vc / nxy) - rz;
+            const int slot = lat.code[(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)];   // -1: a lower entry
+#pragma unroll
+            for (int j = 0; j <= kMaxUpper; ++j) acc[j] += slot == j ? w : 0.0;
+        }
+    }
+    for (int j = 0; j < M1; ++j) U[row * M1 + j] = acc[j];
+}
+
+// J^T t, element by element: per tetrahedron and block of illuminations,
+//   tq[T]   (+)= sum_k |T|/4 grad(phi_k).grad(z_k)
+//   tr[T][a] (+)= sum_k (Mass_T(phi_k) z_k)_a,
+// KT right-hand sides per thread, the B / KT threads of a tetrahedron summing
+// by shuffles. first: overwrite (first block) instead of accumulating.
+template <int B>
+constexpr int kTetRhs = B >= 4 ? 4 : B;
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_gadj_tet(int64_t E, const int32_t* __restrict__ tets,
+                                                       const double* __restrict__ geo, const double* __restrict__ phi,
+                                                       int n_pad, int col0, const double* __restrict__ z, int first,
+                                                       double* __restrict__ tq, double* __restrict__ tr) {
+    constexpr int KT = kTetRhs<B>, G = B / KT;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool valid = t < E * G;
+    const int64_t e = valid ? t / G : 0;
+    const int k0 = static_cast<int>(t % G) * KT;
+    double q = 0.0, r[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+        Geo4 G4;
+        load_geo4(geo, static_cast<int32_t>(e), G4);
+        int32_t v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = tets[4 * e + c];
+#pragma unroll
+        for (int i = 0; i < KT; ++i) {
+            double ph[4], zz[4], sp = 0.0, gp[3] = {0.0, 0.0, 0.0}, gz[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                ph[c] = phi[(int64_t)v[c] * n_pad + col0 + k0 + i];
+                zz[c] = z[(int64_t)v[c] * B + k0 + i];
+                sp += ph[c];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    gp[d] += ph[c] * G4.g[c][d];
+                    gz[d] += zz[c] * G4.g[c][d];
+                }
             }
-            acc2 += phi[row * n_pad + kk] * tv;
+            q += 0.25 * G4.vol * (gp[0] * gz[0] + gp[1] * gz[1] + gp[2] * gz[2]);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                double m = 0.0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) m += (c == a ? 2.0 : 1.0) * (sp + ph[a] + ph[c]) * zz[c];
+                r[a] += G4.vol * (1.0 / 120.0) * m;
+            }
         }
     }
 #pragma unroll
     for (int off = G >> 1; off >= 1; off >>= 1) {
-        acc1 += __shfl_xor(acc1, off);
-        acc2 += __shfl_xor(acc2, off);
+        q += __shfl_xor(q, off);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) r[a] += __shfl_xor(r[a], off);
     }
     if (valid && k0 == 0) {
         if (first) {
-            a1[row] = acc1;
-            a2[row] = acc2;
+            tq[e] = q;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) tr[4 * e + a] = r[a];
         } else {
-            a1[row] += acc1;
-            a2[row] += acc2;
+            tq[e] += q;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) tr[4 * e + a] += r[a];
         }
     }
+}
+
+// a1[row] = -sum_{T at row} tq[T], a2[row] = -sum_{T at row} tr[T][a] + sum_k phi_k,row t_k,row
+// (tmode 0: t external [n_ill][N]; tmode 1: t = W u interleaved [N][n_pad])
+__global__ __launch_bounds__(kThreads) void k_gadj_gather(int64_t N, const int32_t* __restrict__ n2t_ptr,
+                                                          const int32_t* __restrict__ n2t,
+                                                          const double* __restrict__ tq,
+                                                          const double* __restrict__ tr,
+                                                          const double* __restrict__ phi, int n_pad, int n_ill,
+                                                          int tmode, const double* __restrict__ t_ext,
+                                                          const double* __restrict__ W, const double* __restrict__ U,
+                                                          double* __restrict__ a1, double* __restrict__ a2) {
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (row >= N) return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int32_t q = n2t_ptr[row]; q < n2t_ptr[row + 1]; ++q) {
+        const int32_t e = n2t[q] >> 2, a = n2t[q] & 3;
+        s1 -= tq[e];
+        s2 -= tr[4 * (int64_t)e + a];
+    }
+    for (int kk = 0; kk < n_ill; ++kk) {
+        const double tv = tmode == 0 ? t_ext[(int64_t)kk * N + row] : W[row * n_pad + kk] * U[row * n_pad + kk];
+        s2 += phi[row * n_pad + kk] * tv;
+    }
+    a1[row] = s1;
+    a2[row] = s2;
 }
 
 // solver block <- columns col0..col0+B-1 of an interleaved data array
@@ -304,10 +380,22 @@ qpat_status forward_solve_x0(qpat_ctx* c, const double* x0, SolveStats* st) {
 qpat_status jvp_core(qpat_ctx* c, const double* s, int mode, double* out, SolveStats* st) {
     const int B = block_size(c);
     const dim3 g(grid_for(c->N * B, kThreads, 1 << 30)), blk(kThreads);
+    // lattice meshes: dK(s) once in the stencil form, then one tiled stencil
+    // product per block (else the element loop per block)
+    const bool lat = c->lat.on && c->opts.operator_format == 1 && B >= 8;
+    if (lat) {
+        if (!c->dK) QPAT_TRY(dalloc(c, &c->dK, (int64_t)(c->lat.m + 1) * c->N));
+        hipLaunchKernelGGL(k_dk_lattice, dim3(grid_for(c->N, kThreads, 1 << 30)), blk, 0, c->stream, c->N, c->lat,
+                           c->tets, c->geo, c->n2t_ptr, c->n2t, c->kappa, c->mu, s, c->dK);
+    }
     for (int col0 = 0; col0 < c->n_pad; col0 += B) {
-        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gfwd<BB>, dim3(grid_for(c->N * (BB / kGroup<BB>), kThreads, 1 << 30)),
-                                              blk, 0, c->stream, c->N, c->tets, c->geo, c->n2t_ptr, c->n2t, c->kappa,
-                                              c->mu, s, c->phi, c->n_pad, col0, c->b64));
+        bool done = false;
+        if (lat) QPAT_TRY(mg_stencil_apply(c, B, c->dK, c->phi, c->n_pad, col0, c->b64, -1.0, &done));
+        if (!done)
+            QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gfwd<BB>,
+                                                  dim3(grid_for(c->N * (BB / kGroup<BB>), kThreads, 1 << 30)), blk, 0,
+                                                  c->stream, c->N, c->tets, c->geo, c->n2t_ptr, c->n2t, c->kappa,
+                                                  c->mu, s, c->phi, c->n_pad, col0, c->b64));
         QPAT_TRY(k_solve(c, B, st));
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_jvp_out<BB>, g, blk, 0, c->stream, c->N, c->mu, c->phi, s, c->x64,
                                               c->n_pad, c->n_ill, col0, mode, out, c->lw, c->lu, c->ls));
@@ -319,19 +407,27 @@ qpat_status jvp_core(qpat_ctx* c, const double* s, int mode, double* out, SolveS
 // mode 0: t external [n_ill][N], out = J^T t
 // mode 1: t = W u (c->lw, c->lu), out = J^T t
 // mode 2: as 1, out = J^T t - beta what
+// The G^T terms are summed per tetrahedron over the blocks of illuminations,
+// then gathered per node once.
 qpat_status vjp_core(qpat_ctx* c, const double* t, int mode, double* out, SolveStats* st) {
     const int B = block_size(c);
     const dim3 g(grid_for(c->N * B, kThreads, 1 << 30)), blk(kThreads);
     const int tmode = mode == 0 ? 0 : 1;
+    if (!c->tq) {
+        QPAT_TRY(dalloc(c, &c->tq, c->E));
+        QPAT_TRY(dalloc(c, &c->tr, 4 * c->E));
+    }
     for (int col0 = 0; col0 < c->n_pad; col0 += B) {
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_adj_rhs<BB>, g, blk, 0, c->stream, c->N, c->mu, c->n_pad, c->n_ill,
                                               col0, tmode, t, c->lw, c->lu, c->b64));
         QPAT_TRY(k_solve(c, B, st));
-        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gadj<BB>, dim3(grid_for(c->N * (BB / kGroup<BB>), kThreads, 1 << 30)),
-                                              blk, 0, c->stream, c->N, c->tets, c->geo, c->n2t_ptr, c->n2t, c->phi,
-                                              c->n_pad, c->n_ill, col0, c->x64, tmode, t, c->lw, c->lu,
-                                              col0 == 0 ? 1 : 0, c->acc1, c->acc2));
+        QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gadj_tet<BB>,
+                                              dim3(grid_for(c->E * (BB / kTetRhs<BB>), kThreads, 1 << 30)), blk, 0,
+                                              c->stream, c->E, c->tets, c->geo, c->phi, c->n_pad, col0, c->x64,
+                                              col0 == 0 ? 1 : 0, c->tq, c->tr));
     }
+    hipLaunchKernelGGL(k_gadj_gather, dim3(grid_for(c->N, kThreads, 1 << 30)), blk, 0, c->stream, c->N, c->n2t_ptr,
+                       c->n2t, c->tq, c->tr, c->phi, c->n_pad, c->n_ill, tmode, t, c->lw, c->lu, c->acc1, c->acc2);
     hipLaunchKernelGGL(k_vjp_out, dim3(grid_for(c->N, kThreads, 1 << 30)), blk, 0, c->stream, c->N, c->kappa, c->mu,
                        c->acc1, c->acc2, out, mode == 2 ? 1 : 0, c->lwh, c->ls);
     QPAT_HIP(c, hipGetLastError());

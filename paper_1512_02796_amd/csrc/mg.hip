@@ -77,7 +77,7 @@ struct MgState {
     double* rsize = nullptr;       // [nsys][kRegMax] nodes per region
     double* rparts = nullptr;      // [nsys][kRegMax][kMgBlocks] partial sums of Z^T r
     double* ry = nullptr;          // [nsys][kRegMax] y = E^{-1} Z^T r
-    double* rcorr = nullptr;       // [nsys][2] r.(Z y), sum(Z y)
+    double* rcorr = nullptr;       // [nsys][2] r.(Z y), mean(Z y) (0 without deflation)
     std::map<int, TileGeo> tiles;  // by block size
     std::vector<hipEvent_t> ev;    // per-launch timing (profiling)
     std::map<std::string, hipGraphExec_t> graphs;
@@ -249,6 +249,43 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
         }
         return s;
     }
+}
+
+// Compensated accumulation of s - a x: the product's rounding error comes
+// from a fused multiply-add and the sum's from a two-sum, so that s + c holds
+// b - sum a_j x_j to a few ulps of the result instead of ulps of
+// sum |a_j x_j| (the true residual near the attainable accuracy of PCG).
+struct CompSum {
+    double s, c;
+    __device__ __forceinline__ explicit CompSum(double b) : s(b), c(0.0) {}
+    __device__ __forceinline__ void sub(double a, double x) {
+        const double p = a * x;
+        const double e = fma(a, x, -p);   // a x = p + e exactly
+        const double t = s - p;
+        const double bp = t - s;
+        const double err = (s - (t - bp)) + (-p - bp);   // s - p = t + err exactly
+        s = t;
+        c += err - e;
+    }
+    __device__ __forceinline__ double value() const { return s + c; }
+};
+
+// b_i - (A x)_i of one right-hand side (x: its entry of node 0, stride B),
+// compensated; any stencil form (the offset table)
+template <int B>
+__device__ double resid_comp(const LvArgs& L, const double* __restrict__ U, const double* __restrict__ x, double bi,
+                             int32_t ix, int32_t iy, int32_t iz, int32_t i) {
+    const int32_t M1 = L.m + 1;
+    CompSum r(bi);
+    r.sub(U[i * M1], x[i * B]);
+    for (int j = 0; j < L.m; ++j) {
+        const int4 t = L.tab[j];
+        if (ix + t.x >= 0 && ix + t.x < L.nx && iy + t.y >= 0 && iy + t.y < L.ny && iz + t.z < L.nz)
+            r.sub(U[i * M1 + j + 1], x[(i + t.w) * B]);
+        if (ix - t.x >= 0 && ix - t.x < L.nx && iy - t.y >= 0 && iy - t.y < L.ny && iz - t.z >= 0)
+            r.sub(U[(i - t.w) * M1 + j + 1], x[(i - t.w) * B]);
+    }
+    return r.value();
 }
 
 // plain grid-stride loop over n elements (one right-hand side each; the lane
@@ -731,7 +768,7 @@ struct PcgMg {
     int32_t kreg;
     const int32_t* reg;   // [nsys][N]
     const double* ry;     // [nsys][kRegMax]
-    const double* rcorr;  // [nsys][2]
+    const double* rcorr;  // [nsys][2]: r.(Z y), mean(Z y)
 };
 
 // per-component choice between two V-wide values
@@ -778,10 +815,10 @@ __global__ __launch_bounds__(kMgT) void k_mgp_dir(PcgMg a) {
         QPAT_MG_ELEMS(e, a.L.N * BV) {
             const int64_t at = o + (e / BV) * B;
             T zc = vld<T>(a.z + at);
-            if constexpr (B == 1) {   // the region coarse-space part of z
+            if constexpr (B == 1) {   // the region coarse-space part of z, y_reg(i) - ybar
                 if (a.kreg > 0) {
                     const int32_t rg = a.reg[sys * a.L.N + e];
-                    if (rg >= 0) zc += a.ry[sys * kRegMax + rg];
+                    zc += (rg >= 0 ? a.ry[sys * kRegMax + rg] : 0.0) - a.rcorr[2 * sys + 1];
                 }
             }
             const T pn = zc - s.c + s.beta * vld<T>(a.po + at);
@@ -876,15 +913,19 @@ __global__ __launch_bounds__(kMgT) void k_mgp_scalars(PcgMg a, int phase) {
         }
     } else {
         double rz = red(a.parts, a.nb, lane, 0, sm);
-        double z1 = red(a.parts, a.nb, lane, 2, sm);
+        const double z1 = red(a.parts, a.nb, lane, 2, sm);
         const double r1 = red(a.parts, a.nb, lane, 3, sm);
         if (threadIdx.x == 0) {
-            if (a.kreg > 0) {   // z = V(r) + Z y: r.(Z y) and sum(Z y) from the region sums
+            // z = V(r) + Z y; with deflation its mean is mean(V(r)) + ybar, and the
+            // direction takes (V(r) - mean V(r)) + (Z y - ybar): the large, nearly
+            // constant part of Z y never passes through the sum with V(r)
+            double ybar = 0.0;
+            if (a.kreg > 0) {
                 rz += a.rcorr[2 * lane];
-                z1 += a.rcorr[2 * lane + 1];
+                ybar = a.rcorr[2 * lane + 1];
             }
             const double c = a.deflate ? z1 / static_cast<double>(a.L.N) : 0.0;
-            rz -= c * r1;     // r.(z - c)
+            rz -= (c + ybar) * r1;     // r.(z - mean z)
             s.c = c;
             s.beta = (phase == 2 && s.rz != 0.0) ? rz / s.rz : 0.0;
             s.rz = rz;
@@ -928,8 +969,8 @@ __global__ __launch_bounds__(kMgT) void k_reg_rsum(PcgMg a, double* __restrict__
     }
 }
 
-// y = E^{-1} Z^T r and the corrections r.(Z y), sum(Z y) of the dot products;
-// one block per system (blockIdx.y)
+// y = E^{-1} Z^T r and the corrections r.(Z y), mean(Z y) (deflation) of the
+// dot products and the direction; one block per system (blockIdx.y)
 __global__ __launch_bounds__(kMgT) void k_reg_solve(PcgMg a, const double* __restrict__ rparts,
                                                     const double* __restrict__ einv, const double* __restrict__ rsize,
                                                     double* __restrict__ ry, double* __restrict__ rcorr) {
@@ -950,14 +991,14 @@ __global__ __launch_bounds__(kMgT) void k_reg_solve(PcgMg a, const double* __res
         ry[sys * kRegMax + t] = yy[t];
     }
     __syncthreads();
-    if (t == 0) {
+    if (t == 0) {   // r.(Z y), and with deflation ybar = mean(Z y)
         double c0 = 0.0, c1 = 0.0;
         for (int j = 0; j < a.kreg; ++j) {
             c0 += yy[j] * zr[j];
             c1 += yy[j] * rsize[sys * kRegMax + j];
         }
         rcorr[2 * sys] = c0;
-        rcorr[2 * sys + 1] = c1;
+        rcorr[2 * sys + 1] = a.deflate ? c1 / static_cast<double>(a.L.N) : 0.0;
     }
 }
 
@@ -1164,7 +1205,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_start(PcgMg a, double* __restrict_
     }
 }
 
-// true residual r = b - A x, partial r.r (also the start of a run from x0)
+// true residual r = b - A x (compensated), partial r.r (also the start of a run from x0)
 template <int KIND, int B>
 __global__ __launch_bounds__(kMgT) void k_mgp_true(PcgMg a, const double* __restrict__ b) {
     using T = TB<B>;
@@ -1180,7 +1221,14 @@ __global__ __launch_bounds__(kMgT) void k_mgp_true(PcgMg a, const double* __rest
         double* rs = a.r + o;
         T rr = 0.0;
         walk<Pk<B>::BV>(a.L.nx, a.L.ny, a.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
-            const T ri = vld<T>(bs + i * B) - apply<KIND, B>(a.L, U, xs, ix, iy, iz, i);
+            const T bi = vld<T>(bs + i * B);
+            T ri;
+            if constexpr (V == 2) {
+                ri.x = resid_comp<B>(a.L, U, xs, bi.x, ix, iy, iz, i);
+                ri.y = resid_comp<B>(a.L, U, xs + 1, bi.y, ix, iy, iz, i);
+            } else {
+                ri = resid_comp<B>(a.L, U, xs, bi, ix, iy, iz, i);
+            }
             vst<T>(rs + i * B, ri);
             rr += ri * ri;
         });
@@ -1224,11 +1272,13 @@ struct MgTile {
     static constexpr int NU = (kTHN * 8 + kTT - 1) / kTT;     // operator values per thread and plane
     static constexpr size_t LDS = (size_t)3 * (NPF + NU) * kTT * sizeof(double);
 };
-enum TileMode { kTDirSpmv = 0, kTResidFirst = 1, kTSmoothDots = 2, kTTrue = 3, kTResid = 4 };
+enum TileMode { kTDirSpmv = 0, kTResidFirst = 1, kTSmoothDots = 2, kTTrue = 3, kTResid = 4, kTApply = 5 };
 
 struct TileArgs {
     int32_t nx, ny, nz;
     int32_t tiles_x, tiles_y, zc, items;
+    int32_t ld, col;      // `in` is [N][ld], columns col ... col + B - 1 (ld = B, col = 0 but in kTApply)
+    double scale;         // kTApply: out = scale A in
     const double* U;      // [N][8] the Kuhn stencil form
     const double* in;     // the vector staged in LDS (see the modes), [N][B]
     const double* in2;    // kTDirSpmv: the old direction
@@ -1249,30 +1299,40 @@ struct TileArgs {
 //   partial out.out.
 // kTSmoothDots: out = in + w D^{-1} (b - A in), partial b.out, sum out,
 //   sum b (the last finest-level sweep of the V-cycle: b = r, out = z).
+// kTApply: out = scale A in for every right-hand side (any Kuhn stencil
+//   form U, e.g. the derivative of K in the Jacobian product).
 template <int MODE, int B>
 __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
     using TL = MgTile<B>;
     constexpr int NPF = TL::NPF, NU = TL::NU, RS = NPF * kTT, US = NU * kTT;
     constexpr int TX = kTHX - 2, TY = kTHY - 2, M1 = 8;
     constexpr uint32_t SZ = sizeof(double);
-    constexpr bool HAS_B = MODE != kTDirSpmv;
+    constexpr bool HAS_B = MODE != kTDirSpmv && MODE != kTApply;
     constexpr bool CENTER_D = MODE == kTSmoothDots;
     extern __shared__ __align__(16) unsigned char mg_smem[];
     __shared__ double sm[(kTT / 64) * 16];
     double* ring = reinterpret_cast<double*>(mg_smem);   // [3][RS]: [halo node][B]
     double* ust = ring + 3 * RS;                          // [3][US]: [halo node][8]
     const int tid = threadIdx.x, k = tid % B;
-    if constexpr (MODE != kTTrue) {   // every right-hand side stopped: nothing to do
+    constexpr bool ALL = MODE == kTTrue || MODE == kTApply;   // every right-hand side, no PCG scalars
+    if constexpr (!ALL) {   // every right-hand side stopped: nothing to do
         bool any = false;
         for (int j = 0; j < B; ++j) any = any || g.sc[j].active != 0;
         if (!any) return;
     }
-    const MgScal scl = g.sc[k];
-    const bool act = MODE == kTTrue || scl.active != 0;
-    const double cc_ = MODE == kTDirSpmv ? scl.c : 0.0, beta = MODE == kTDirSpmv ? scl.beta : 0.0;
+    bool act = true;
+    double cc_ = 0.0, beta = 0.0;
+    if constexpr (!ALL) {
+        const MgScal scl = g.sc[k];
+        act = scl.active != 0;
+        if constexpr (MODE == kTDirSpmv) {
+            cc_ = scl.c;
+            beta = scl.beta;
+        }
+    }
     const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
     const uint32_t nxy = static_cast<uint32_t>(nx) * ny;
-    const uint32_t pv = nxy * B * SZ, pu = nxy * M1 * SZ, pd = nxy * SZ;
+    const uint32_t pv = nxy * B * SZ, pu = nxy * M1 * SZ, pd = nxy * SZ, pin = nxy * g.ld * SZ;
     const double w = (MODE == kTSmoothDots || MODE == kTResidFirst) ? *g.w : 0.0;
     auto plane = [&](const double* base, int pl, uint32_t stride, uint32_t bytes) {
         const bool in = pl >= 0 && pl < nz;
@@ -1302,7 +1362,7 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
             const int nl = (tid + u * kTT) / B;
             const int gx = x0 - 1 + nl % kTHX, gy = y0 - 1 + nl / kTHX;
             const bool fin = nl < kTHN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-            fo[u] = fin ? (static_cast<uint32_t>(gy * nx + gx) * B + k) * SZ : kOut;
+            fo[u] = fin ? (static_cast<uint32_t>(gy * nx + gx) * g.ld + g.col + k) * SZ : kOut;
             const int ox = x0 + nl % TX, oy = y0 + nl / TX;
             const bool oin = nl < TX * TY && ox < nx && oy < ny;
             oo[u] = oin ? (static_cast<uint32_t>(oy * nx + ox) * B + k) * SZ : kOut;
@@ -1317,7 +1377,7 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
                         : kOut;
         }
         auto fetch = [&](int pl) {
-            const auto bi = plane(g.in, pl, nxy * B, pv), bu = plane(g.U, pl, nxy * M1, pu);
+            const auto bi = plane(g.in, pl, nxy * g.ld, pin), bu = plane(g.U, pl, nxy * M1, pu);
 #pragma unroll
             for (int u = 0; u < NPF; ++u) fr[u] = bload<double>(bi, fo[u]);
             if constexpr (MODE == kTDirSpmv) {
@@ -1374,13 +1434,27 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
                     const double* ub = ust + (oc[u] - kTHX - 1) * M1;
                     constexpr int cc = kTHX + 1;
                     const double xc = rb[sz * RS + cc * B];
-                    double sum = ub[sz * US + cc * M1] * xc;
+                    double sum = 0.0, rtrue = 0.0;
+                    if constexpr (MODE == kTTrue) {   // b - A x, compensated
+                        CompSum rc(bc[u]);
+                        rc.sub(ub[sz * US + cc * M1], xc);
 #pragma unroll
-                    for (int j = 0; j < 7; ++j) {
-                        const int d = kKy[j] * kTHX + kKx[j];
-                        const int up = kKz[j] ? sp : sz, lo = kKz[j] ? sl : sz;
-                        sum += ub[sz * US + cc * M1 + j + 1] * rb[up * RS + (cc + d) * B] +
-                               ub[lo * US + (cc - d) * M1 + j + 1] * rb[lo * RS + (cc - d) * B];
+                        for (int j = 0; j < 7; ++j) {
+                            const int d = kKy[j] * kTHX + kKx[j];
+                            const int up = kKz[j] ? sp : sz, lo = kKz[j] ? sl : sz;
+                            rc.sub(ub[sz * US + cc * M1 + j + 1], rb[up * RS + (cc + d) * B]);
+                            rc.sub(ub[lo * US + (cc - d) * M1 + j + 1], rb[lo * RS + (cc - d) * B]);
+                        }
+                        rtrue = rc.value();
+                    } else {
+                        sum = ub[sz * US + cc * M1] * xc;
+#pragma unroll
+                        for (int j = 0; j < 7; ++j) {
+                            const int d = kKy[j] * kTHX + kKx[j];
+                            const int up = kKz[j] ? sp : sz, lo = kKz[j] ? sl : sz;
+                            sum += ub[sz * US + cc * M1 + j + 1] * rb[up * RS + (cc + d) * B] +
+                                   ub[lo * US + (cc - d) * M1 + j + 1] * rb[lo * RS + (cc - d) * B];
+                        }
                     }
                     const bool in = oo[u] != kOut;
                     double o;
@@ -1388,13 +1462,15 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
                         o = sum;
                         a0 += in ? xc * sum : 0.0;
                         bstore<double>(bo2, oo[u], xc);
+                    } else if constexpr (MODE == kTApply) {
+                        o = g.scale * sum;
                     } else if constexpr (MODE == kTSmoothDots) {
                         o = xc + w * dc[u] * (bc[u] - sum);
                         a0 += in ? bc[u] * o : 0.0;
                         a1 += in ? o : 0.0;
                         a2 += in ? bc[u] : 0.0;
                     } else {
-                        o = bc[u] - sum;
+                        o = MODE == kTTrue ? rtrue : bc[u] - sum;
                         if constexpr (MODE == kTTrue) a1 += in ? o * o : 0.0;
                     }
                     bstore<double>(bo, oo[u], o);
@@ -1530,6 +1606,9 @@ void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const doubl
         g.tiles_y = t.tiles_y;
         g.zc = t.zc;
         g.items = t.items;
+        g.ld = B;
+        g.col = 0;
+        g.scale = 1.0;
         g.U = L.U;
         g.in = in;
         g.in2 = in2;
@@ -1557,11 +1636,12 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
     if constexpr (B >= 8) {
         if (M.nsys != 1 || L.kind != 1 || L.N * B * (int64_t)sizeof(double) >= (int64_t(1) << 31)) return QPAT_OK;
         static_assert(MgTile<B>::LDS <= 159 * 1024, "tiled multigrid LDS budget");
-        const void* fns[5] = {reinterpret_cast<const void*>(&k_mg_tile<kTDirSpmv, B>),
+        const void* fns[6] = {reinterpret_cast<const void*>(&k_mg_tile<kTDirSpmv, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTResidFirst, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTSmoothDots, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTTrue, B>),
-                              reinterpret_cast<const void*>(&k_mg_tile<kTResid, B>)};
+                              reinterpret_cast<const void*>(&k_mg_tile<kTResid, B>),
+                              reinterpret_cast<const void*>(&k_mg_tile<kTApply, B>)};
         for (const void* f : fns)   // dynamic LDS beyond the default limit is allowed per kernel
             QPAT_HIP(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MgTile<B>::LDS));
         int occ = 1, cus = 256;
@@ -1917,7 +1997,8 @@ bool mg_ready(qpat_ctx* c, Op op) {
 
 // Region coarse space of the finest level of M (one system at a time): labels
 // of the strong-coupling components, the kRegMax largest regions with at
-// least kRegMin nodes, E = Z^T A Z (exact integer sums) and its inverse.
+// least kRegMin nodes (with deflation: after the largest), E = Z^T A Z (exact
+// integer sums) and its inverse.
 static qpat_status region_setup(qpat_ctx* c, MgState& M) {
     const MgLevel& F = M.lv[0];
     const int64_t N = F.N;
@@ -1975,6 +2056,13 @@ static qpat_status region_setup(qpat_ctx* c, MgState& M) {
         std::sort(cand.begin(), cand.end(), [](const auto& x, const auto& y) {
             return x.first != y.first ? x.first > y.first : x.second < y.second;
         });
+        // With deflation the constant vector is solved exactly; the largest
+        // region's indicator is then nearly that vector, and keeping it makes
+        // the coarse correction all but repeat the deflated direction (PCG
+        // stagnated near rtol 1e-12 with it); the other regions span its
+        // complement part anyway.
+        const int skip = c->opts.prior_deflate && !cand.empty() ? 1 : 0;
+        cand.erase(cand.begin(), cand.begin() + skip);
         int k = std::min<int>(kRegMax, static_cast<int>(cand.size()));
         int32_t rt[kRegMax] = {};
         for (int j = 0; j < k; ++j) rt[j] = cand[j].second;
@@ -2166,6 +2254,51 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     if (op == Op::Prior) QPAT_TRY(region_setup(c, M));
     M.current = true;
     return QPAT_OK;
+}
+
+// out [N][B] = scale U in, U a Kuhn stencil form [N][8] of the lattice, in
+// [N][ld] (columns col ... col + B - 1), with the LDS-tiled kernel of the K
+// hierarchy's finest level. false: that tiling is not available for B.
+template <int B>
+static qpat_status apply_B(qpat_ctx* c, const double* U, const double* in, int ld, int col, double* out,
+                           double scale, bool* done) {
+    *done = false;
+    if constexpr (B >= 8) {
+        MgState* M = state_of(c, Op::K);
+        if (!M || !mg_ready(c, Op::K)) return QPAT_OK;
+        QPAT_TRY(tile_setup<B>(c, *M));
+        const TileGeo& t = M->tiles[B];
+        if (!t.on) return QPAT_OK;
+        const MgLevel& L = M->lv[0];
+        if ((int64_t)L.nx * L.ny * ld * (int64_t)sizeof(double) >= (int64_t(1) << 31)) return QPAT_OK;
+        TileArgs g{};
+        g.nx = L.nx;
+        g.ny = L.ny;
+        g.nz = L.nz;
+        g.tiles_x = t.tiles_x;
+        g.tiles_y = t.tiles_y;
+        g.zc = t.zc;
+        g.items = t.items;
+        g.ld = ld;
+        g.col = col;
+        g.scale = scale;
+        g.U = U;
+        g.in = in;
+        g.out = out;
+        hipLaunchKernelGGL((k_mg_tile<kTApply, B>), sgrid<B>(L.N), dim3(kTT), MgTile<B>::LDS, c->stream, g);
+        QPAT_HIP(c, hipGetLastError());
+        *done = true;
+    }
+    return QPAT_OK;
+}
+
+qpat_status mg_stencil_apply(qpat_ctx* c, int B, const double* U, const double* in, int ld, int col, double* out,
+                             double scale, bool* done) {
+    switch (B) {
+        case 8: return apply_B<8>(c, U, in, ld, col, out, scale, done);
+        case 16: return apply_B<16>(c, U, in, ld, col, out, scale, done);
+        default: *done = false; return QPAT_OK;
+    }
 }
 
 // A x = b with the multigrid-preconditioned PCG: b in c->b64 ([nsys][N][B],

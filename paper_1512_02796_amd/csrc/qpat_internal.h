@@ -197,6 +197,9 @@ struct qpat_ctx {
     double* acc1 = nullptr;        // [N]
     double* acc2 = nullptr;        // [N]
     double* dvec = nullptr;        // [N][n_pad] scratch in data space
+    double* dK = nullptr;          // lattice meshes: dK(s) of J s in the stencil form [N][m+1]
+    double* tq = nullptr;          // [E] per-tetrahedron sums of J^T t (stiffness part)
+    double* tr = nullptr;          // [E][4] per-tetrahedron sums of J^T t (mass part)
 
     // LSQR
     bool lsqr_ready = false;
@@ -348,6 +351,11 @@ qpat_status mg_setup(qpat_ctx* c, Op op);
 // The same contract as pcg_solve (b in c->b64, x in c->x64, has_x0 for K).
 qpat_status mg_solve(qpat_ctx* c, Op op, int B, SolveStats* st, bool has_x0 = false);
 void mg_destroy(qpat_ctx* c);
+// out [N][B] = scale U in for a Kuhn stencil form U [N][8] and in [N][ld]
+// (columns col ... col + B - 1), LDS-tiled; *done = false when that path is
+// not available (no current K hierarchy, B < 8, offsets past 32 bits).
+qpat_status mg_stencil_apply(qpat_ctx* c, int B, const double* U, const double* in, int ld, int col, double* out,
+                             double scale, bool* done);
 
 // ---- lsqr.hip
 qpat_status dot(qpat_ctx* c, const double* a, const double* b, int64_t n, double* dev_out);
