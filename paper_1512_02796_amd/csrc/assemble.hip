@@ -73,9 +73,17 @@ __global__ void k_assemble_K(const Sell s, const int32_t* __restrict__ tets, con
             sm += m[b];
         }
         kb *= 0.25;
+        double ga[3] = {0.0, 0.0, 0.0}, ma = 0.0;   // row vertex a: selected with compile-time indices
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ga[d] = c == a ? G.g[c][d] : ga[d];
+            ma = c == a ? m[c] : ma;
+        }
+#pragma unroll
         for (int b = 0; b < 4; ++b) {
-            double val = kb * G.vol * dot3(G.g[a], G.g[b]) +
-                         G.vol * (a == b ? 2.0 : 1.0) * (sm + m[a] + m[b]) * (1.0 / 120.0);
+            double val = kb * G.vol * dot3(ga, G.g[b]) +
+                         G.vol * (a == b ? 2.0 : 1.0) * (sm + ma + m[b]) * (1.0 / 120.0);
             int pos = find_col(s.cols, base, n, v[b]);
             K64[base + pos * kSlice] += val;
         }
@@ -128,8 +136,14 @@ __global__ void k_assemble_prior(const Sell s, const int32_t* __restrict__ tets,
             gu[2] += ub * G.g[b][2];
         }
         double cT = 1.0 / (1.0 + dot3(gu, gu) * invT2);
+        double ga[3] = {0.0, 0.0, 0.0};   // row vertex a: selected with compile-time indices
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ga[d] = c == a ? G.g[c][d] : ga[d];
+#pragma unroll
         for (int b = 0; b < 4; ++b) {
-            double val = scale * cT * G.vol * dot3(G.g[a], G.g[b]);
+            double val = scale * cT * G.vol * dot3(ga, G.g[b]);
             int pos = find_col(s.cols, base, n, v[b]);
             V[base + pos * kSlice] += val;
         }

@@ -76,9 +76,11 @@ __global__ __launch_bounds__(kThreads) void k_gfwd(int64_t N, const int32_t* __r
             s2 += u2[c];
         }
         u1 *= 0.25;
-        double ga[3];
+        double ga[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) ga[d] = G4.g[a][d];   // runtime vertex: select once
+        for (int c = 0; c < 4; ++c)   // select with compile-time indices: no scratch copy
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ga[d] = c == a ? G4.g[c][d] : ga[d];   // runtime vertex: select once
         double w[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -103,23 +105,59 @@ __global__ __launch_bounds__(kThreads) void k_gfwd(int64_t N, const int32_t* __r
 // (diagonal and upper offsets, [N][m+1]): the element sums of the assembly of
 // K without the boundary term, so G(1) diag(kappa) s1 + G(2) diag(mu) s2 =
 // -dK(s) phi for every illumination, one stencil product per block.
+// kSplit consecutive threads share a node's element list (one element in
+// kSplit each) and sum by shuffles: the list's loads are independent, so
+// more of them are in flight than with one thread per node.
+constexpr int kSplit = 8;
+
+// the coefficients of dK(s) per node: uu[i] = (kappa_i s1_i, mu_i s2_i)
+__global__ __launch_bounds__(kThreads) void k_dk_coef(int64_t N, const double* __restrict__ kappa,
+                                                      const double* __restrict__ mu, const double* __restrict__ s,
+                                                      double* __restrict__ uu) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    uu[2 * i] = kappa[i] * s[i];
+    uu[2 * i + 1] = mu[i] * s[N + i];
+}
+
+// M1: stored entries per row (8 on the Kuhn lattice, else kMaxUpper + 1)
+template <int M1>
 __global__ __launch_bounds__(kThreads) void k_dk_lattice(int64_t N, Lattice lat, const int32_t* __restrict__ tets,
                                                          const double* __restrict__ geo,
                                                          const int32_t* __restrict__ n2t_ptr,
                                                          const int32_t* __restrict__ n2t,
-                                                         const double* __restrict__ kappa,
-                                                         const double* __restrict__ mu, const double* __restrict__ s,
-                                                         double* __restrict__ U) {
-    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (row >= N) return;
-    const int M1 = lat.m + 1;
-    const int64_t nxy = (int64_t)lat.nx * lat.ny;
-    const int rx = static_cast<int>(row % lat.nx), ry = static_cast<int>((row / lat.nx) % lat.ny),
-              rz = static_cast<int>(row / nxy);
-    double acc[kMaxUpper + 1];
+                                                         const double* __restrict__ uu, double* __restrict__ U) {
+    // Node order: the blocks of XCD x (block b runs on XCD b mod 8) take the
+    // y-strip [x ny / 8, (x + 1) ny / 8) of every plane (z-slabs when ny < 8)
+    // plane by plane, so the elements around the strip's planes stay in that
+    // XCD's L2 while the four nodes of each element read them.
+    const int64_t nx = lat.nx, ny = lat.ny, nxy = nx * ny;
+    const int xcd = blockIdx.x & 7;
+    int64_t y0 = 0, ys = ny, z0 = 0, zs = lat.nz;
+    if (ny >= 8) {
+        y0 = xcd * ny / 8;
+        ys = (xcd + 1) * ny / 8 - y0;
+    } else {
+        z0 = xcd * lat.nz / 8;
+        zs = (xcd + 1) * (int64_t)lat.nz / 8 - z0;
+    }
+    const int64_t span = nx * ys * zs;
+    const int part = threadIdx.x % kSplit;
+    const int64_t gpb = kThreads / kSplit, per = (gridDim.x >> 3) * gpb;
+    // neighbour offsets: with nx, ny >= 3 the linear offset of a neighbour at
+    // most one step away per axis determines (dx, dy, dz) by comparisons
+    const bool fast = lat.nx >= 3 && lat.ny >= 3;
+    for (int64_t n0 = (blockIdx.x >> 3) * gpb; n0 < span; n0 += per) {   // uniform over the block
+    const int64_t n = n0 + threadIdx.x / kSplit;
+    const bool valid = n < span;   // whole groups of kSplit lanes
+    const int rx = static_cast<int>(n % nx);
+    const int ry = static_cast<int>(y0 + (n / nx) % ys), rz = static_cast<int>(z0 + n / (nx * ys));
+    const int64_t row = rx + nx * (ry + ny * (int64_t)rz);
+    double acc[M1];
 #pragma unroll
-    for (int j = 0; j <= kMaxUpper; ++j) acc[j] = 0.0;
-    for (int32_t q = n2t_ptr[row]; q < n2t_ptr[row + 1]; ++q) {
+    for (int j = 0; j < M1; ++j) acc[j] = 0.0;
+    const int32_t q0 = valid ? n2t_ptr[row] : 0, q1 = valid ? n2t_ptr[row + 1] : 0;
+    for (int32_t q = q0 + part; q < q1; q += kSplit) {
         const int32_t e = n2t[q] >> 2, a = n2t[q] & 3;
         Geo4 G4;
         load_geo4(geo, e, G4);
@@ -128,30 +166,49 @@ __global__ __launch_bounds__(kThreads) void k_dk_lattice(int64_t N, Lattice lat,
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             v[c] = tets[4 * e + c];
-            u1 += kappa[v[c]] * s[v[c]];
-            u2[c] = mu[v[c]] * s[N + v[c]];
+            const double2 w2 = *reinterpret_cast<const double2*>(uu + 2 * (int64_t)v[c]);
+            u1 += w2.x;
+            u2[c] = w2.y;
             s2 += u2[c];
         }
         u1 *= 0.25;
-        double ga[3], u2a = 0.0;
+        double ga[3] = {0.0, 0.0, 0.0}, u2a = 0.0;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
             if (c == a) u2a = u2[c];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) ga[d] = G4.g[a][d];
+        for (int c = 0; c < 4; ++c)   // select with compile-time indices: no scratch copy
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ga[d] = c == a ? G4.g[c][d] : ga[d];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const double gg = ga[0] * G4.g[c][0] + ga[1] * G4.g[c][1] + ga[2] * G4.g[c][2];
             const double w = u1 * G4.vol * gg + G4.vol * (1.0 / 120.0) * (c == a ? 2.0 : 1.0) * (s2 + u2a + u2[c]);
-            const int64_t vc = v[c];
-            const int dx = static_cast<int>(vc % lat.nx) - rx, dy = static_cast<int>((vc / lat.nx) % lat.ny) - ry,
-                      dz = static_cast<int>(vc / nxy) - rz;
+            int dx, dy, dz;
+            if (fast) {
+                int64_t lin = v[c] - row;
+                dz = lin > nxy / 2 ? 1 : (lin < -nxy / 2 ? -1 : 0);
+                lin -= dz * nxy;
+                dy = lin > nx / 2 ? 1 : (lin < -nx / 2 ? -1 : 0);
+                dx = static_cast<int>(lin - dy * nx);
+            } else {
+                const int64_t vc = v[c];
+                dx = static_cast<int>(vc % nx) - rx;
+                dy = static_cast<int>((vc / nx) % lat.ny) - ry;
+                dz = static_cast<int>(vc / nxy) - rz;
+            }
             const int slot = lat.code[(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)];   // -1: a lower entry
 #pragma unroll
-            for (int j = 0; j <= kMaxUpper; ++j) acc[j] += slot == j ? w : 0.0;
+            for (int j = 0; j < M1; ++j) acc[j] += slot == j ? w : 0.0;
         }
     }
-    for (int j = 0; j < M1; ++j) U[row * M1 + j] = acc[j];
+#pragma unroll
+    for (int j = 0; j < M1; ++j)
+#pragma unroll
+        for (int off = kSplit / 2; off >= 1; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
+    if (valid && part == 0)
+        for (int j = 0; j < lat.m + 1; ++j) U[row * (lat.m + 1) + j] = acc[j];
+    }
 }
 
 // J^T t, element by element: per tetrahedron and block of illuminations,
@@ -232,20 +289,31 @@ __global__ __launch_bounds__(kThreads) void k_gadj_gather(int64_t N, const int32
                                                           int tmode, const double* __restrict__ t_ext,
                                                           const double* __restrict__ W, const double* __restrict__ U,
                                                           double* __restrict__ a1, double* __restrict__ a2) {
-    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (row >= N) return;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t row = t / kSplit;
+    const int part = static_cast<int>(t % kSplit);
+    const bool valid = row < N;   // whole groups of kSplit lanes
     double s1 = 0.0, s2 = 0.0;
-    for (int32_t q = n2t_ptr[row]; q < n2t_ptr[row + 1]; ++q) {
-        const int32_t e = n2t[q] >> 2, a = n2t[q] & 3;
-        s1 -= tq[e];
-        s2 -= tr[4 * (int64_t)e + a];
+    if (valid) {
+        for (int32_t q = n2t_ptr[row] + part; q < n2t_ptr[row + 1]; q += kSplit) {
+            const int32_t e = n2t[q] >> 2, a = n2t[q] & 3;
+            s1 -= tq[e];
+            s2 -= tr[4 * (int64_t)e + a];
+        }
+        for (int kk = part; kk < n_ill; kk += kSplit) {
+            const double tv = tmode == 0 ? t_ext[(int64_t)kk * N + row] : W[row * n_pad + kk] * U[row * n_pad + kk];
+            s2 += phi[row * n_pad + kk] * tv;
+        }
     }
-    for (int kk = 0; kk < n_ill; ++kk) {
-        const double tv = tmode == 0 ? t_ext[(int64_t)kk * N + row] : W[row * n_pad + kk] * U[row * n_pad + kk];
-        s2 += phi[row * n_pad + kk] * tv;
+#pragma unroll
+    for (int off = kSplit / 2; off >= 1; off >>= 1) {
+        s1 += __shfl_xor(s1, off);
+        s2 += __shfl_xor(s2, off);
     }
-    a1[row] = s1;
-    a2[row] = s2;
+    if (valid && part == 0) {
+        a1[row] = s1;
+        a2[row] = s2;
+    }
 }
 
 // solver block <- columns col0..col0+B-1 of an interleaved data array
@@ -384,9 +452,20 @@ qpat_status jvp_core(qpat_ctx* c, const double* s, int mode, double* out, SolveS
     // product per block (else the element loop per block)
     const bool lat = c->lat.on && c->opts.operator_format == 1 && B >= 8;
     if (lat) {
-        if (!c->dK) QPAT_TRY(dalloc(c, &c->dK, (int64_t)(c->lat.m + 1) * c->N));
-        hipLaunchKernelGGL(k_dk_lattice, dim3(grid_for(c->N, kThreads, 1 << 30)), blk, 0, c->stream, c->N, c->lat,
-                           c->tets, c->geo, c->n2t_ptr, c->n2t, c->kappa, c->mu, s, c->dK);
+        if (!c->dK) {
+            QPAT_TRY(dalloc(c, &c->dK, (int64_t)(c->lat.m + 1) * c->N));
+            QPAT_TRY(dalloc(c, &c->dKc, 2 * c->N));
+        }
+        hipLaunchKernelGGL(k_dk_coef, dim3(grid_for(c->N, kThreads, 1 << 30)), blk, 0, c->stream, c->N, c->kappa, c->mu,
+                           s, c->dKc);
+        // a multiple of 8 blocks (the XCD strips), several per compute unit
+        const dim3 gd((std::min<int64_t>((c->N * kSplit + kThreads - 1) / kThreads, 4096) + 7) & ~7);
+        if (c->lat.m == 7)
+            hipLaunchKernelGGL(k_dk_lattice<8>, gd, blk, 0, c->stream, c->N, c->lat, c->tets, c->geo, c->n2t_ptr,
+                               c->n2t, c->dKc, c->dK);
+        else
+            hipLaunchKernelGGL(k_dk_lattice<kMaxUpper + 1>, gd, blk, 0, c->stream, c->N, c->lat, c->tets, c->geo,
+                               c->n2t_ptr, c->n2t, c->dKc, c->dK);
     }
     for (int col0 = 0; col0 < c->n_pad; col0 += B) {
         bool done = false;
@@ -426,7 +505,7 @@ qpat_status vjp_core(qpat_ctx* c, const double* t, int mode, double* out, SolveS
                                               c->stream, c->E, c->tets, c->geo, c->phi, c->n_pad, col0, c->x64,
                                               col0 == 0 ? 1 : 0, c->tq, c->tr));
     }
-    hipLaunchKernelGGL(k_gadj_gather, dim3(grid_for(c->N, kThreads, 1 << 30)), blk, 0, c->stream, c->N, c->n2t_ptr,
+    hipLaunchKernelGGL(k_gadj_gather, dim3(grid_for(c->N * kSplit, kThreads, 1 << 30)), blk, 0, c->stream, c->N, c->n2t_ptr,
                        c->n2t, c->tq, c->tr, c->phi, c->n_pad, c->n_ill, tmode, t, c->lw, c->lu, c->acc1, c->acc2);
     hipLaunchKernelGGL(k_vjp_out, dim3(grid_for(c->N, kThreads, 1 << 30)), blk, 0, c->stream, c->N, c->kappa, c->mu,
                        c->acc1, c->acc2, out, mode == 2 ? 1 : 0, c->lwh, c->ls);

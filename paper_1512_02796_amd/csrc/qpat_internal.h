@@ -198,6 +198,7 @@ struct qpat_ctx {
     double* acc2 = nullptr;        // [N]
     double* dvec = nullptr;        // [N][n_pad] scratch in data space
     double* dK = nullptr;          // lattice meshes: dK(s) of J s in the stencil form [N][m+1]
+    double* dKc = nullptr;         // [N][2] its coefficients kappa s1, mu s2
     double* tq = nullptr;          // [E] per-tetrahedron sums of J^T t (stiffness part)
     double* tr = nullptr;          // [E][4] per-tetrahedron sums of J^T t (mass part)
 
