@@ -33,7 +33,7 @@ struct MgLevel {
     int32_t nx = 0, ny = 0, nz = 0;
     int64_t N = 0;
     int32_t m = 0;                 // stored upper offsets
-    int32_t kind = 0;              // row kernel: 0 generic table, 1 Kuhn offsets, 2 full 27-point
+    int32_t kind = 0;              // row kernel: 0 generic table, 1 Kuhn offsets, 2 full 27-point, 3 whole Kuhn rows (Uf)
     const int4* tab = nullptr;     // [m]: dx, dy, dz, dx + nx (dy + ny dz)
     int4* tab_own = nullptr;
     double* U = nullptr;           // [nsys][N][m+1] (level 0: the context's stencil arrays)
@@ -43,6 +43,7 @@ struct MgLevel {
     double* t = nullptr;           // ping-pong partner of x
     double* r = nullptr;           // residual before restriction
     double* W = nullptr;           // [nsys][N][8] operator-dependent prolongation weights to the next level
+    double* Uf = nullptr;          // kind 3: [nsys][N][kFullRow] whole Kuhn rows
 };
 
 struct MgScal {
@@ -201,8 +202,21 @@ struct LvArgs {
     const int4* tab;
     int32_t m, nx, ny, nz;
     int64_t N;
-    int32_t kind;         // 0 generic table, 1 Kuhn offsets, 2 full 27-point
+    int32_t kind;         // row kernel: 0 generic table, 1 Kuhn offsets, 2 full 27-point, 3 Kuhn full rows
+    const double* Uf;     // kind 3: [nsys][N][kFullRow] full rows of the Kuhn stencil
 };
+
+// Kuhn rows stored whole for the one-right-hand-side kernels: diagonal, the 7
+// upper entries, the 7 lower ones (offset order), padding: one 128-byte line
+// per node instead of a gather of the lower entries from 7 partner rows
+constexpr int kFullRow = 16;
+
+// first stored row of system sys in the form the row kernel KIND reads
+template <int KIND>
+__device__ __forceinline__ const double* rows_of(const LvArgs& L, int sys) {
+    if constexpr (KIND == 3) return L.Uf + (int64_t)sys * L.N * kFullRow;
+    return L.U + (int64_t)sys * L.N * (L.m + 1);
+}
 
 // (A x)_i for the thread's V right-hand sides; x points at the thread's
 // first right-hand side of node 0 ([N][B] interleaved). Interior rows skip
@@ -220,6 +234,27 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
                 s += U[i * M1 + j + 1] * vld<T>(x + (i + t.w) * B);
             if (ix - t.x >= 0 && ix - t.x < L.nx && iy - t.y >= 0 && iy - t.y < L.ny && iz - t.z >= 0)
                 s += U[(i - t.w) * M1 + j + 1] * vld<T>(x + (i - t.w) * B);
+        }
+        return s;
+    } else if constexpr (KIND == 3) {
+        double u[kFullRow];
+        const d2v* Ur = reinterpret_cast<const d2v*>(U + i * kFullRow);
+#pragma unroll
+        for (int k = 0; k < kFullRow / 2; ++k) {
+            const d2v t = Ur[k];
+            u[2 * k] = t.x;
+            u[2 * k + 1] = t.y;
+        }
+        const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
+        T s = u[0] * vld<T>(x + i * B);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            const int dx = kKx[j], dy = kKy[j], dz = kKz[j];
+            const int32_t lin = dx + L.nx * (dy + L.ny * dz);
+            const bool up = inner || (ix + dx < L.nx && iy + dy < L.ny && iz + dz < L.nz);
+            const bool lo = inner || (ix - dx >= 0 && iy - dy >= 0 && iz - dz >= 0);
+            if (up) s += u[1 + j] * vld<T>(x + (i + lin) * B);
+            if (lo) s += u[8 + j] * vld<T>(x + (i - lin) * B);
         }
         return s;
     } else {
@@ -330,6 +365,34 @@ __device__ __forceinline__ void put_sums(double* parts, int sys, int slot, TB<B>
     for (int c = 0; c < Pk<B>::V; ++c) {
         const double t = group_sum<Pk<B>::BV>(comp(acc, c), sm);
         if (threadIdx.x < Pk<B>::BV) put(parts, sys * B + threadIdx.x * Pk<B>::V + c, slot, t);
+    }
+}
+
+// whole Kuhn rows (diagonal, upper entries, lower entries gathered from the
+// partner rows, zero where the partner is off the lattice) for the row kind 3
+__global__ __launch_bounds__(kMgT) void k_mg_fullrows(LvArgs L, double* __restrict__ Uf) {
+    const int sys = blockIdx.y;
+    constexpr int M1 = 8;
+    const double* U = L.U + (int64_t)sys * L.N * M1;
+    double* F = Uf + (int64_t)sys * L.N * kFullRow;
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * kMgT) {
+        int ix, iy, iz;
+        coords(static_cast<int32_t>(i), L.nx, L.ny, ix, iy, iz);
+        double u[kFullRow];
+        u[0] = U[i * M1];
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            const int dx = kKx[j], dy = kKy[j], dz = kKz[j];
+            const int64_t lin = dx + (int64_t)L.nx * (dy + (int64_t)L.ny * dz);
+            const bool up = ix + dx < L.nx && iy + dy < L.ny && iz + dz < L.nz;
+            const bool lo = ix - dx >= 0 && iy - dy >= 0 && iz - dz >= 0;
+            u[1 + j] = up ? U[i * M1 + 1 + j] : 0.0;
+            u[8 + j] = lo ? U[(i - lin) * M1 + 1 + j] : 0.0;
+        }
+        u[15] = 0.0;
+        d2v* o = reinterpret_cast<d2v*>(F + i * kFullRow);
+#pragma unroll
+        for (int k = 0; k < kFullRow / 2; ++k) o[k] = d2v{u[2 * k], u[2 * k + 1]};
     }
 }
 
@@ -547,7 +610,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_smooth(SmArgs a, const double* __re
     const int32_t M1 = a.L.m + 1;
     for (int sys = 0; sys < a.nsys; ++sys) {
         const double w = a.w[sys * a.nlev + a.lev];
-        const double* U = a.L.U + sys * a.L.N * M1;
+        const double* U = rows_of<KIND>(a.L, sys);
         const double* dinv = a.dinv + sys * a.L.N;
         const int64_t o = sys * a.L.N * B + v * V;
         const double* bs = b + o;
@@ -585,7 +648,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_resid(SmArgs a, const double* __res
     const int32_t M1 = a.L.m + 1;
     for (int sys = 0; sys < a.nsys; ++sys) {
         if (!pair_active<B>(a.sc, sys, v)) continue;
-        const double* U = a.L.U + sys * a.L.N * M1;
+        const double* U = rows_of<KIND>(a.L, sys);
         const int64_t o = sys * a.L.N * B + v * V;
         const double* bs = b + o;
         const double* xs = x + o;
@@ -822,7 +885,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_dir(PcgMg a) {
                 }
             }
             const T pn = zc - s.c + s.beta * vld<T>(a.po + at);
-            vst<T>(a.pn + at, pick(pn, vld<T>(a.pn + at), s.on0, s.on1));
+            vst<T>(a.pn + at, s.on0 && s.on1 ? pn : pick(pn, vld<T>(a.pn + at), s.on0, s.on1));
         }
     }
 }
@@ -836,7 +899,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_spmv(PcgMg a) {
     const int v = threadIdx.x % Pk<B>::BV;
     const int32_t M1 = a.L.m + 1;
     for (int sys = 0; sys < a.nsys; ++sys) {
-        const double* U = a.L.U + sys * a.L.N * M1;
+        const double* U = rows_of<KIND>(a.L, sys);
         const int64_t o = sys * a.L.N * B + v * V;
         const double* ps = a.pn + o;
         double* qs = a.q + o;
@@ -974,15 +1037,17 @@ __global__ __launch_bounds__(kMgT) void k_reg_rsum(PcgMg a, double* __restrict__
 __global__ __launch_bounds__(kMgT) void k_reg_solve(PcgMg a, const double* __restrict__ rparts,
                                                     const double* __restrict__ einv, const double* __restrict__ rsize,
                                                     double* __restrict__ ry, double* __restrict__ rcorr) {
-    __shared__ double zr[kRegMax], yy[kRegMax];
+    __shared__ double zr[kRegMax], yy[kRegMax], sm[kMgT / 64];
     const int sys = blockIdx.y;
     if (!a.sc[sys].active) return;
     const int t = threadIdx.x;
-    if (t < kRegMax) {
+    for (int j = 0; j < a.kreg; ++j) {   // fixed-order block sums of the partials
         double s = 0.0;
-        for (int b = 0; b < a.nb; ++b) s += rparts[(sys * kRegMax + t) * kMgBlocks + b];
-        zr[t] = t < a.kreg ? s : 0.0;
+        for (int b = t; b < a.nb; b += kMgT) s += rparts[(sys * kRegMax + j) * kMgBlocks + b];
+        s = group_sum<1>(s, sm);
+        if (t == 0) zr[j] = s;
     }
+    if (t >= a.kreg && t < kRegMax) zr[t] = 0.0;
     __syncthreads();
     if (t < kRegMax) {
         double y = 0.0;
@@ -1214,7 +1279,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_true(PcgMg a, const double* __rest
     const int v = threadIdx.x % Pk<B>::BV;
     const int32_t M1 = a.L.m + 1;
     for (int sys = 0; sys < a.nsys; ++sys) {
-        const double* U = a.L.U + sys * a.L.N * M1;
+        const double* U = a.L.U + sys * a.L.N * M1;   // upper rows: the compensated sum walks the offset table
         const int64_t o = sys * a.L.N * B + v * V;
         const double* bs = b + o;
         const double* xs = a.x + o;
@@ -1524,6 +1589,7 @@ inline LvArgs lv_args(const MgLevel& L) {
     a.nz = L.nz;
     a.N = L.N;
     a.kind = L.kind;
+    a.Uf = L.Uf;
     return a;
 }
 
@@ -1534,6 +1600,7 @@ inline dim3 vgrid(int64_t n) { return dim3((grid_for(n, kMgT, kMgBlocks) + 7) & 
     switch (kind) {                                                         \
         case 1: hipLaunchKernelGGL((KERNEL<1, B>), __VA_ARGS__); break;     \
         case 2: hipLaunchKernelGGL((KERNEL<2, B>), __VA_ARGS__); break;     \
+        case 3: hipLaunchKernelGGL((KERNEL<3, B>), __VA_ARGS__); break;     \
         default: hipLaunchKernelGGL((KERNEL<0, B>), __VA_ARGS__); break;    \
     }
 
@@ -1583,6 +1650,7 @@ void launch_smooth(int kind, dim3 g, hipStream_t st, const SmArgs& a, const doub
     switch (kind) {
         case 1: hipLaunchKernelGGL((k_mg_smooth<1, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
         case 2: hipLaunchKernelGGL((k_mg_smooth<2, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
+        case 3: hipLaunchKernelGGL((k_mg_smooth<3, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
         default: hipLaunchKernelGGL((k_mg_smooth<0, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
     }
 }
@@ -2177,6 +2245,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             QPAT_TRY(dalloc(c, &L.t, V * L.N));
             QPAT_TRY(dalloc(c, &L.r, V * L.N));
             if (op == Op::Prior && l + 1 < nl) QPAT_TRY(dalloc(c, &L.W, nsys * L.N * 8));
+            if (op == Op::Prior && l == 0 && L.kind == 1) QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kFullRow));
         }
         QPAT_TRY(dalloc(c, &M.w, nsys * nl));
         QPAT_TRY(dalloc(c, &M.gmax, nsys * nl));
@@ -2195,6 +2264,11 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     const int nl = static_cast<int>(M.lv.size());
     M.lv[0].U = op == Op::K ? c->KU64 : c->MU64;
     M.opdep = op == Op::Prior;
+    if (M.lv[0].Uf) {   // the one-right-hand-side walk kernels read whole rows
+        M.lv[0].kind = 1;
+        hipLaunchKernelGGL(k_mg_fullrows, dim3(grid_for(M.lv[0].N, kMgT, 4096), nsys), dim3(kMgT), 0, c->stream,
+                           lv_args(M.lv[0]), M.lv[0].Uf);
+    }
     for (int l = 0; l + 1 < nl; ++l) {
         const MgLevel& F = M.lv[l];
         const MgLevel& C = M.lv[l + 1];
@@ -2252,6 +2326,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     QPAT_HIP(c, hipMemcpyAsync(M.ainv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
     if (op == Op::Prior) QPAT_TRY(region_setup(c, M));
+    if (M.lv[0].Uf) M.lv[0].kind = 3;
     M.current = true;
     return QPAT_OK;
 }
