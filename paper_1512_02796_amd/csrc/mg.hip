@@ -55,6 +55,8 @@ struct MgScal {
 struct TileGeo {
     bool ready = false, on = false;
     int32_t tiles_x = 0, tiles_y = 0, zc = 0, items = 0;
+    // the tiled restriction to level 1 (coarse tiles, coarse z-chunk, blocks)
+    int32_t rtiles_x = 0, rtiles_y = 0, rzc = 0, ritems = 0, rblocks = 0;
 };
 
 struct MgState {
@@ -1579,6 +1581,122 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
     }
 }
 
+// ------------------------------------------------ LDS-tiled restriction
+// Finest to first coarse level of the K hierarchy (trilinear weights, B >= 8
+// right-hand sides): a work item is a tile of kRX x RY coarse columns over a
+// chunk of coarse planes. The block stages each fine plane of the tile's
+// support, (2 kRX + 1) x (2 RY + 1) nodes, in LDS with row-contiguous loads
+// (double-buffered: the next plane's loads are in flight during the sums)
+// and forms the in-plane 3 x 3 weighted sums from LDS; the weights along z
+// (1/2 for planes 2K - 1 and 2K + 1, 1 for 2K) are applied as the planes
+// stream by, so a fine plane is read once per chunk, the chunk's first plane
+// twice. Fine nodes off the lattice load as 0 (their weight is 0).
+constexpr int kRX = 8;
+template <int B>
+struct MgRst {
+    static constexpr int RY = kTT / B / kRX;                  // coarse rows per tile (one coarse node per B threads)
+    static constexpr int FX = 2 * kRX + 1, FY = 2 * RY + 1;   // fine support of the tile
+    static constexpr int NPF = (FX * FY * B + kTT - 1) / kTT;  // fine values per thread and plane
+    static constexpr size_t LDS = (size_t)2 * NPF * kTT * sizeof(double);
+};
+
+struct RstArgs {
+    int32_t nx, ny, nz;      // fine lattice
+    int32_t cx, cy, cz;      // coarse lattice
+    int32_t tiles_x, tiles_y, zc, items;
+    const double* r;         // fine residual [Nf][B]
+    const double* dinv;      // coarse 1 / a_ii [Nc]
+    const double* w;         // coarse level's Jacobi weight
+    double* bc;              // coarse right-hand side [Nc][B]
+    double* xc;              // coarse first sweep w D^{-1} bc [Nc][B]
+    const MgScal* sc;        // [B]
+};
+
+template <int B>
+__global__ __launch_bounds__(kTT) void k_mg_restrict_tile(RstArgs g) {
+    using TR = MgRst<B>;
+    constexpr int RY = TR::RY, FX = TR::FX, FY = TR::FY, NPF = TR::NPF, RS = NPF * kTT;
+    constexpr uint32_t SZ = sizeof(double);
+    extern __shared__ __align__(16) unsigned char mg_smem[];
+    double* buf = reinterpret_cast<double*>(mg_smem);   // [2][RS]: [support node][B]
+    const int tid = threadIdx.x, k = tid % B, cn = tid / B;
+    bool any = false;
+    for (int j = 0; j < B; ++j) any = any || g.sc[j].active != 0;
+    if (!any) return;   // every right-hand side stopped
+    const bool act = g.sc[k].active != 0;
+    const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
+    const uint32_t nxy = static_cast<uint32_t>(nx) * ny, pv = nxy * B * SZ;
+    const int64_t cxy = (int64_t)g.cx * g.cy;
+    const double wc = *g.w;   // system 0 of the coarse level (the caller passes that entry)
+    const int lx = cn % kRX, ly = cn / kRX;
+    const int c0 = ((2 * ly + 1) * FX + 2 * lx + 1) * B + k;   // LDS index of the node's centre fine node
+
+    const int32_t xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
+    const int32_t wx = (g.items + 7) / 8;
+    const int32_t it_end = min(g.items, (xcd + 1) * wx);
+    const int32_t tiles = g.tiles_x * g.tiles_y;
+    double fr[NPF];
+    for (int32_t item = xcd * wx + slot; item < it_end; item += per) {
+        const int32_t ch = item / tiles, t2 = item % tiles;
+        const int32_t X0 = (t2 % g.tiles_x) * kRX, Y0 = (t2 / g.tiles_x) * RY;
+        const int32_t Kb = ch * g.zc, Ke = min(Kb + g.zc, g.cz);
+        uint32_t fo[NPF];
+#pragma unroll
+        for (int u = 0; u < NPF; ++u) {
+            const int e = tid + u * kTT, nl = e / B;
+            const int gx = 2 * X0 - 1 + nl % FX, gy = 2 * Y0 - 1 + nl / FX;
+            const bool in = nl < FX * FY && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            fo[u] = in ? (static_cast<uint32_t>(gy * nx + gx) * B + e % B) * SZ : kOut;
+        }
+        auto fetch = [&](int pl) {
+            const bool in = pl >= 0 && pl < nz;
+            const auto br = rsrc(g.r + (in ? (int64_t)pl * nxy * B : 0), in ? pv : 0u);
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) fr[u] = bload<double>(br, fo[u]);
+        };
+        auto store = [&](int sl) {
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) buf[sl * RS + tid + u * kTT] = fr[u];
+        };
+        auto psum = [&](int sl) {   // in-plane weights 1/2, 1, 1/2 along x and y
+            const double* f = buf + sl * RS + c0;
+            double rows[3];
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const double* q = f + dy * FX * B;
+                rows[dy + 1] = 0.5 * (q[-B] + q[B]) + q[0];
+            }
+            return 0.5 * (rows[0] + rows[2]) + rows[1];
+        };
+        const int32_t Ix = X0 + lx, Iy = Y0 + ly;
+        const bool own = act && Ix < g.cx && Iy < g.cy;
+        const int p0 = 2 * Kb - 1, p1 = 2 * Ke - 1;
+        fetch(p0);
+        store(0);
+        double acc = 0.0;
+        for (int p = p0; p <= p1; ++p) {
+            __syncthreads();
+            if (p < p1) fetch(p + 1);
+            const double s = psum((p - p0) & 1);
+            if (((p - p0) & 1) == 0) {   // odd plane p = 2K - 1 or 2K + 1
+                if (p > p0) {            // closes coarse plane K = (p - 1) / 2
+                    const double v = acc + 0.5 * s;
+                    if (own) {
+                        const int64_t I = (int64_t)((p - 1) / 2) * cxy + (int64_t)Iy * g.cx + Ix;
+                        g.bc[I * B + k] = v;
+                        g.xc[I * B + k] = wc * g.dinv[I] * v;
+                    }
+                }
+                acc = 0.5 * s;
+            } else {
+                acc += s;
+            }
+            if (p < p1) store((p + 1 - p0) & 1);
+        }
+        __syncthreads();   // the next item's first store overwrites slot 0
+    }
+}
+
 inline LvArgs lv_args(const MgLevel& L) {
     LvArgs a;
     a.U = L.U;
@@ -1691,6 +1809,33 @@ void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const doubl
     }
 }
 
+// level 0's residual to level 1's b and first sweep xc (tiled; trilinear)
+template <int B>
+void launch_restrict(const MgState& M, const TileGeo& t, hipStream_t st, double* xc) {
+    if constexpr (B >= 8) {
+        const MgLevel& L = M.lv[0];
+        const MgLevel& C = M.lv[1];
+        RstArgs g;
+        g.nx = L.nx;
+        g.ny = L.ny;
+        g.nz = L.nz;
+        g.cx = C.nx;
+        g.cy = C.ny;
+        g.cz = C.nz;
+        g.tiles_x = t.rtiles_x;
+        g.tiles_y = t.rtiles_y;
+        g.zc = t.rzc;
+        g.items = t.ritems;
+        g.r = L.r;
+        g.dinv = C.dinv;
+        g.w = M.w + 1;   // system 0, level 1
+        g.bc = C.b;
+        g.xc = xc;
+        g.sc = M.sc;
+        hipLaunchKernelGGL(k_mg_restrict_tile<B>, dim3(t.rblocks), dim3(kTT), MgRst<B>::LDS, st, g);
+    }
+}
+
 // The finest-level tiling for block size B: on for the Kuhn stencil of one
 // system with B >= 8 whose plane offsets fit 32 bits; the z-chunk length
 // balances the work items over the blocks resident per XCD.
@@ -1733,6 +1878,29 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
         t.zc = static_cast<int32_t>(best_zc);
         t.items = static_cast<int32_t>(tx * ty * ((L.nz + best_zc - 1) / best_zc));
         t.on = true;
+        // restriction to level 1: the same balance with (2 zc + 1) fine planes per item
+        const MgLevel& C = M.lv[1];
+        const void* fr = reinterpret_cast<const void*>(&k_mg_restrict_tile<B>);
+        QPAT_HIP(c, hipFuncSetAttribute(fr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MgRst<B>::LDS));
+        int rocc = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&rocc, fr, kTT, MgRst<B>::LDS) != hipSuccess) rocc = 1;
+        const int64_t rconc = (int64_t)std::max(rocc, 1) * (cus / 8);
+        const int64_t rtx = (C.nx + kRX - 1) / kRX, rty = (C.ny + MgRst<B>::RY - 1) / MgRst<B>::RY;
+        int64_t rbest = -1, rzc = C.nz;
+        for (int64_t nch = 1; nch <= C.nz; ++nch) {
+            const int64_t zc = (C.nz + nch - 1) / nch;
+            const int64_t items = rtx * rty * ((C.nz + zc - 1) / zc);
+            const int64_t cost = (((items + 7) / 8 + rconc - 1) / rconc) * (2 * zc + 2);
+            if (rbest < 0 || cost < rbest) {
+                rbest = cost;
+                rzc = zc;
+            }
+        }
+        t.rtiles_x = static_cast<int32_t>(rtx);
+        t.rtiles_y = static_cast<int32_t>(rty);
+        t.rzc = static_cast<int32_t>(rzc);
+        t.ritems = static_cast<int32_t>(rtx * rty * ((C.nz + rzc - 1) / rzc));
+        t.rblocks = static_cast<int32_t>(8 * std::min<int64_t>(rconc, (t.ritems + 7) / 8));
     }
     return QPAT_OK;
 }
@@ -1780,7 +1948,9 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         else
             QPAT_MG_KIND(L.kind, B, k_mg_resid, g, dim3(kMgT), 0, st, a, L.b, xl[l], L.r);
         if (l == 0 && ev) (void)hipEventRecord(ev[1], st);
-        if (M.opdep)
+        if (l == 0 && tg.on && !M.opdep)
+            launch_restrict<B>(M, tg, st, xl[1]);
+        else if (M.opdep)
             hipLaunchKernelGGL((k_mg_restrict<B, true>), sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny,
                                L.nz, L.r, C.b, xl[l + 1], L.W);
         else
