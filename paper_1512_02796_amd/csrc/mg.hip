@@ -11,8 +11,9 @@
 //   * coarse operators by Galerkin products A_c = P^T A P, stored like the fine
 //     stencil form (diagonal + upper offsets, node-major), 27-point;
 //   * smoother: kMgNu weighted Jacobi sweeps before and after the coarse
-//     correction, weight 4/(3 g) with g >= lambda_max(D^{-1} A) the Gershgorin
-//     bound;
+//     correction, weight 8/(5 g) with g >= lambda_max(D^{-1} A) the Gershgorin
+//     bound: the first-degree Chebyshev weight for the interval [g/4, g] that
+//     the sweep has to damp (w lambda <= 8/5 < 2 keeps the cycle SPD);
 //   * coarsest level: the explicit inverse (dense, computed on the host).
 // Vectors hold B right-hand sides interleaved ([sys][N][B]); every lane
 // (system, right-hand side) has its own PCG scalars and stops on its own.
@@ -1376,6 +1377,8 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
     constexpr uint32_t SZ = sizeof(double);
     constexpr bool HAS_B = MODE != kTDirSpmv && MODE != kTApply;
     constexpr bool CENTER_D = MODE == kTSmoothDots;
+    // the right-hand side's loads go out a plane ahead where the registers allow
+    constexpr bool PRE_B = HAS_B && !CENTER_D;
     extern __shared__ __align__(16) unsigned char mg_smem[];
     __shared__ double sm[(kTT / 64) * 16];
     double* ring = reinterpret_cast<double*>(mg_smem);   // [3][RS]: [halo node][B]
@@ -1460,6 +1463,13 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
 #pragma unroll
             for (int v = 0; v < NU; ++v) fu[v] = bload<double>(bu, uo[v]);
         };
+        auto loadb = [&](int z, double(&to)[NPF]) {
+            const auto bb = plane(g.b, z, nxy * B, act ? pv : 0u);
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) to[u] = bload<double>(bb, oo[u]);
+        };
+        double bn[NPF];   // PRE_B: b of the next plane
+        if constexpr (PRE_B) loadb(zb, bn);
         auto store = [&](int sl) {
 #pragma unroll
             for (int u = 0; u < NPF; ++u) {
@@ -1479,10 +1489,12 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
             if (z + 1 < ze) fetch(z + 2);
             // per-node inputs of plane z: loads in flight during the arithmetic
             double bc[NPF], dc[NPF];
-            if constexpr (HAS_B) {
-                const auto bb = plane(g.b, z, nxy * B, act ? pv : 0u);
+            if constexpr (PRE_B) {   // loaded one step earlier
 #pragma unroll
-                for (int u = 0; u < NPF; ++u) bc[u] = bload<double>(bb, oo[u]);
+                for (int u = 0; u < NPF; ++u) bc[u] = bn[u];
+                if (z + 1 < ze) loadb(z + 1, bn);
+            } else if constexpr (HAS_B) {
+                loadb(z, bc);
             }
             if constexpr (CENTER_D) {
                 const auto bd = plane(g.dinv, z, nxy, act ? pd : 0u);
@@ -2472,7 +2484,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
         double g;
         std::memcpy(&g, &gm[i], sizeof g);
         if (!(g > 0.0) || !std::isfinite(g)) return fail(c, QPAT_ERR_ARG, "multigrid: non-positive diagonal in %s", what);
-        w[i] = 4.0 / (3.0 * g);
+        w[i] = 8.0 / (5.0 * g);
     }
     QPAT_HIP(c, hipMemcpyAsync(M.w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     const int n = static_cast<int>(K.N), M1 = K.m + 1;
