@@ -58,6 +58,9 @@ struct TileGeo {
     int32_t tiles_x = 0, tiles_y = 0, zc = 0, items = 0;
     // the tiled restriction to level 1 (coarse tiles, coarse z-chunk, blocks)
     int32_t rtiles_x = 0, rtiles_y = 0, rzc = 0, ritems = 0, rblocks = 0;
+    // the 27-point kernels of level 1 (16 right-hand sides)
+    bool on27 = false;
+    int32_t t27x = 0, t27y = 0, t27zc = 0, t27items = 0, t27blocks = 0;
 };
 
 struct MgState {
@@ -1709,6 +1712,208 @@ __global__ __launch_bounds__(kTT) void k_mg_restrict_tile(RstArgs g) {
     }
 }
 
+// ------------------------------------------------ LDS-tiled 27-point kernels
+// The first coarse level of the K hierarchy with 16 right-hand sides: the
+// same 2.5D tiling as the finest level (the input vector's planes in LDS),
+// with the Galerkin operator's 27-point rows stored whole ([N][kRow27]:
+// diagonal, 13 upper, 13 lower entries, zero where the partner is off the
+// lattice, padding). The 16 lanes of a node load its row as two 128-byte
+// lines, lane k holding entries k and 16 + k, and every entry reaches the
+// row's lanes by a DPP row broadcast, so the operator never passes through
+// LDS and the partner rows are never gathered.
+constexpr int kRow27 = 32;
+enum Tile27Mode { kT27Resid = 0, kT27Smooth = 1 };
+
+__global__ __launch_bounds__(kMgT) void k_mg_fullrows27(LvArgs L, double* __restrict__ Uf) {
+    const int sys = blockIdx.y;
+    constexpr int M1 = 14;
+    const double* U = L.U + (int64_t)sys * L.N * M1;
+    double* F = Uf + (int64_t)sys * L.N * kRow27;
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * kMgT) {
+        int ix, iy, iz;
+        coords(static_cast<int32_t>(i), L.nx, L.ny, ix, iy, iz);
+        double* o = F + i * kRow27;
+        o[0] = U[i * M1];
+        for (int j = 0; j < 13; ++j) {
+            const int code = 14 + j;
+            const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
+            const int64_t lin = dx + (int64_t)L.nx * (dy + (int64_t)L.ny * dz);
+            const bool up = ix + dx >= 0 && ix + dx < L.nx && iy + dy >= 0 && iy + dy < L.ny && iz + dz < L.nz;
+            const bool lo = ix - dx >= 0 && ix - dx < L.nx && iy - dy >= 0 && iy - dy < L.ny && iz - dz >= 0;
+            o[1 + j] = up ? U[i * M1 + 1 + j] : 0.0;
+            o[14 + j] = lo ? U[(i - lin) * M1 + 1 + j] : 0.0;
+        }
+        for (int j = 27; j < kRow27; ++j) o[j] = 0.0;
+    }
+}
+
+// lane J of each 16-lane row, to the whole row
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + J, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + J, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// sum over the 13 offset pairs: entry 1 + j (upper) and 14 + j (lower) of
+// the row held as (ua: entries 0-15, ub: 16-31) times the LDS neighbours
+template <int J>
+__device__ __forceinline__ double pair27(double ua, double ub, const double* rb, int sz, int sp, int sl) {
+    constexpr int code = 14 + J;
+    constexpr int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
+    constexpr int d = (dy * kTHX + dx) * 16;
+    const int up = dz ? sp : sz, lo = dz ? sl : sz;
+    const double cu = row_bcast<1 + J>(ua);
+    double cl;
+    if constexpr (14 + J < 16)
+        cl = row_bcast<14 + J>(ua);
+    else
+        cl = row_bcast<J - 2>(ub);
+    return cu * rb[up + d] + cl * rb[lo - d];
+}
+template <int... J>
+__device__ __forceinline__ double apply27(double ua, double ub, const double* rb, int sz, int sp, int sl,
+                                          std::integer_sequence<int, J...>) {
+    double s = row_bcast<0>(ua) * rb[sz];
+    ((s += pair27<J>(ua, ub, rb, sz, sp, sl)), ...);
+    return s;
+}
+
+struct Tile27Args {
+    int32_t nx, ny, nz;
+    int32_t tiles_x, tiles_y, zc, items;
+    const double* Uf;     // [N][kRow27]
+    const double* x;      // staged vector [N][16]
+    const double* b;      // [N][16]
+    const double* dinv;   // [N] (kT27Smooth)
+    const double* w;      // the level's Jacobi weight (kT27Smooth)
+    double* out;          // kT27Resid: b - A x; kT27Smooth: x + w D^{-1} (b - A x)
+    const MgScal* sc;     // [16]
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
+    constexpr int B = 16;
+    constexpr int NPF = MgTile<B>::NPF, RS = NPF * kTT;
+    constexpr int TX = kTHX - 2, TY = kTHY - 2;
+    constexpr int NO = (TX * TY * B + kTT - 1) / kTT;   // output slots per thread
+    constexpr uint32_t SZ = sizeof(double);
+    extern __shared__ __align__(16) unsigned char mg_smem[];
+    double* ring = reinterpret_cast<double*>(mg_smem);   // [3][RS]: [halo node][B]
+    const int tid = threadIdx.x, k = tid % B;
+    bool any = false;
+    for (int j = 0; j < B; ++j) any = any || g.sc[j].active != 0;
+    if (!any) return;   // every right-hand side stopped
+    const bool act = g.sc[k].active != 0;
+    const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
+    const uint32_t nxy = static_cast<uint32_t>(nx) * ny;
+    const uint32_t pv = nxy * B * SZ, pr = nxy * kRow27 * SZ, pd = nxy * SZ;
+    const double w = MODE == kT27Smooth ? *g.w : 0.0;
+    auto plane = [&](const double* base, int pl, uint32_t stride, uint32_t bytes) {
+        const bool in = pl >= 0 && pl < nz;
+        return rsrc(base + (in ? (int64_t)pl * stride : 0), in ? bytes : 0u);
+    };
+    int32_t oc[NO];
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {
+        const int nl = (tid + u * kTT) / B;
+        oc[u] = nl < TX * TY ? (nl / TX + 1) * kTHX + nl % TX + 1 : kTHX + 1;
+    }
+    double fr[NPF];
+    const int32_t xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
+    const int32_t wx = (g.items + 7) / 8;
+    const int32_t it_end = min(g.items, (xcd + 1) * wx);
+    const int32_t tiles = g.tiles_x * g.tiles_y;
+    for (int32_t item = xcd * wx + slot; item < it_end; item += per) {
+        const int32_t ch = item / tiles, t2 = item % tiles;
+        const int32_t x0 = (t2 % g.tiles_x) * TX, y0 = (t2 / g.tiles_x) * TY;
+        const int32_t zb = ch * g.zc, ze = min(zb + g.zc, nz);
+        uint32_t fo[NPF], oo[NO], od[NO], ro[NO];
+#pragma unroll
+        for (int u = 0; u < NPF; ++u) {
+            const int nl = (tid + u * kTT) / B;
+            const int gx = x0 - 1 + nl % kTHX, gy = y0 - 1 + nl / kTHX;
+            const bool fin = nl < kTHN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            fo[u] = fin ? (static_cast<uint32_t>(gy * nx + gx) * B + k) * SZ : kOut;
+        }
+#pragma unroll
+        for (int u = 0; u < NO; ++u) {
+            const int nl = (tid + u * kTT) / B;
+            const int ox = x0 + nl % TX, oy = y0 + nl / TX;
+            const bool oin = nl < TX * TY && ox < nx && oy < ny;
+            oo[u] = oin ? (static_cast<uint32_t>(oy * nx + ox) * B + k) * SZ : kOut;
+            od[u] = oin ? static_cast<uint32_t>(oy * nx + ox) * SZ : kOut;
+            ro[u] = oin ? (static_cast<uint32_t>(oy * nx + ox) * kRow27 + k) * SZ : kOut;
+        }
+        auto fetch = [&](int pl) {
+            const auto bx = plane(g.x, pl, nxy * B, pv);
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) fr[u] = bload<double>(bx, fo[u]);
+        };
+        auto store = [&](int sl) {
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) ring[sl * RS + tid + u * kTT] = fr[u];
+        };
+        // the operator rows and b of plane z, loaded a plane ahead
+        double ua[NO], ub[NO], bn[NO];
+        auto load_node = [&](int z) {
+            const auto bu = plane(g.Uf, z, nxy * kRow27, pr);
+            const auto bb = plane(g.b, z, nxy * B, act ? pv : 0u);
+#pragma unroll
+            for (int u = 0; u < NO; ++u) {
+                ua[u] = bload<double>(bu, ro[u]);
+                ub[u] = bload<double>(bu, ro[u] == kOut ? kOut : ro[u] + 16 * SZ);
+                bn[u] = bload<double>(bb, oo[u]);
+            }
+        };
+        load_node(zb);
+        auto step = [&](int z, auto SZ0, auto SP0, auto SL0) {
+            constexpr int sz = decltype(SZ0)::value, sp = decltype(SP0)::value, sl = decltype(SL0)::value;
+            store(sp);
+            __syncthreads();
+            if (z + 1 < ze) fetch(z + 2);
+            double ca[NO], cb[NO], bc[NO], dc[NO];
+#pragma unroll
+            for (int u = 0; u < NO; ++u) {
+                ca[u] = ua[u];
+                cb[u] = ub[u];
+                bc[u] = bn[u];
+            }
+            if (z + 1 < ze) load_node(z + 1);
+            if constexpr (MODE == kT27Smooth) {   // 1 / a_ii of this plane (one value per node)
+                const auto bd = plane(g.dinv, z, nxy, pd);
+#pragma unroll
+                for (int u = 0; u < NO; ++u) dc[u] = bload<double>(bd, od[u]);
+            }
+            const auto bo = plane(g.out, z, nxy * B, act ? pv : 0u);
+#pragma unroll
+            for (int u = 0; u < NO; ++u) {
+                if (tid + u * kTT >= TX * TY * B) continue;   // whole waves past the tile skip
+                const double* rb = ring + oc[u] * B + k;
+                const double ax = apply27(ca[u], cb[u], rb, sz * RS, sp * RS, sl * RS,
+                                          std::make_integer_sequence<int, 13>{});
+                double o = bc[u] - ax;
+                if constexpr (MODE == kT27Smooth) o = rb[sz * RS] + w * dc[u] * o;
+                bstore<double>(bo, oo[u], o);
+            }
+            __syncthreads();
+        };
+        fetch(zb - 1);
+        store(0);
+        fetch(zb);
+        store(1);
+        fetch(zb + 1);
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        for (int z = zb; z < ze; z += 3) {   // plane z - zb + 1 lives in slot (z - zb + 1) % 3
+            step(z, I1{}, I2{}, I0{});
+            if (z + 1 < ze) step(z + 1, I2{}, I0{}, I1{});
+            if (z + 2 < ze) step(z + 2, I0{}, I1{}, I2{});
+        }
+    }
+}
+
 inline LvArgs lv_args(const MgLevel& L) {
     LvArgs a;
     a.U = L.U;
@@ -1821,6 +2026,29 @@ void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const doubl
     }
 }
 
+// level 1: out = b - A x (kT27Resid) or x + w D^{-1} (b - A x) (kT27Smooth)
+template <int MODE>
+void launch_tile27(const MgState& M, const TileGeo& t, hipStream_t st, const double* x, const double* b, double* out) {
+    const MgLevel& L = M.lv[1];
+    Tile27Args g;
+    g.nx = L.nx;
+    g.ny = L.ny;
+    g.nz = L.nz;
+    g.tiles_x = t.t27x;
+    g.tiles_y = t.t27y;
+    g.zc = t.t27zc;
+    g.items = t.t27items;
+    g.Uf = L.Uf;
+    g.x = x;
+    g.b = b;
+    g.dinv = L.dinv;
+    g.w = M.w + 1;   // system 0, level 1
+    g.out = out;
+    g.sc = M.sc;
+    hipLaunchKernelGGL(k_mg_tile27<MODE>, dim3(t.t27blocks), dim3(kTT), (size_t)3 * MgTile<16>::NPF * kTT * sizeof(double),
+                       st, g);
+}
+
 // level 0's residual to level 1's b and first sweep xc (tiled; trilinear)
 template <int B>
 void launch_restrict(const MgState& M, const TileGeo& t, hipStream_t st, double* xc) {
@@ -1913,6 +2141,35 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
         t.rzc = static_cast<int32_t>(rzc);
         t.ritems = static_cast<int32_t>(rtx * rty * ((C.nz + rzc - 1) / rzc));
         t.rblocks = static_cast<int32_t>(8 * std::min<int64_t>(rconc, (t.ritems + 7) / 8));
+        if constexpr (B == 16) {   // level 1's 27-point kernels
+            if (C.Uf) {
+                const void* f27[2] = {reinterpret_cast<const void*>(&k_mg_tile27<kT27Resid>),
+                                      reinterpret_cast<const void*>(&k_mg_tile27<kT27Smooth>)};
+                constexpr size_t lds27 = (size_t)3 * MgTile<16>::NPF * kTT * sizeof(double);
+                for (const void* f : f27)
+                    QPAT_HIP(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds27));
+                int occ27 = 1;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ27, f27[1], kTT, lds27) != hipSuccess) occ27 = 1;
+                const int64_t conc27 = (int64_t)std::max(occ27, 1) * (cus / 8);
+                const int64_t tx27 = (C.nx + kTHX - 3) / (kTHX - 2), ty27 = (C.ny + kTHY - 3) / (kTHY - 2);
+                int64_t best27 = -1, zc27 = C.nz;
+                for (int64_t nch = 1; nch <= C.nz; ++nch) {
+                    const int64_t zc = (C.nz + nch - 1) / nch;
+                    const int64_t items = tx27 * ty27 * ((C.nz + zc - 1) / zc);
+                    const int64_t cost = (((items + 7) / 8 + conc27 - 1) / conc27) * (zc + 2);
+                    if (best27 < 0 || cost < best27) {
+                        best27 = cost;
+                        zc27 = zc;
+                    }
+                }
+                t.t27x = static_cast<int32_t>(tx27);
+                t.t27y = static_cast<int32_t>(ty27);
+                t.t27zc = static_cast<int32_t>(zc27);
+                t.t27items = static_cast<int32_t>(tx27 * ty27 * ((C.nz + zc27 - 1) / zc27));
+                t.t27blocks = static_cast<int32_t>(8 * std::min<int64_t>(conc27, (t.t27items + 7) / 8));
+                t.on27 = true;
+            }
+        }
     }
     return QPAT_OK;
 }
@@ -1957,6 +2214,8 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
             launch_tile<kTResidFirst, B>(M, tg, st, L.b, nullptr, L.b, L.r, nullptr);
         else if (l == 0 && tg.on)
             launch_tile<kTResid, B>(M, tg, st, xl[0], nullptr, L.b, L.r, nullptr);
+        else if (l == 1 && tg.on27 && B == 16)
+            launch_tile27<kT27Resid>(M, tg, st, xl[1], L.b, L.r);
         else
             QPAT_MG_KIND(L.kind, B, k_mg_resid, g, dim3(kMgT), 0, st, a, L.b, xl[l], L.r);
         if (l == 0 && ev) (void)hipEventRecord(ev[1], st);
@@ -1996,6 +2255,8 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
                 launch_tile<kTSmoothDots, B>(M, tg, st, xl[0], nullptr, L.b, tl[0], nullptr);
             else if (last)
                 launch_smooth<B, true>(L.kind, g, st, a, L.b, xl[l], tl[l], M.parts);
+            else if (l == 1 && tg.on27 && B == 16)
+                launch_tile27<kT27Smooth>(M, tg, st, xl[1], L.b, tl[1]);
             else
                 launch_smooth<B, false>(L.kind, g, st, a, L.b, xl[l], tl[l], nullptr);
             if (last && ev) (void)hipEventRecord(ev[3], st);
@@ -2428,6 +2689,9 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             QPAT_TRY(dalloc(c, &L.r, V * L.N));
             if (op == Op::Prior && l + 1 < nl) QPAT_TRY(dalloc(c, &L.W, nsys * L.N * 8));
             if (op == Op::Prior && l == 0 && L.kind == 1) QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kFullRow));
+            if (op == Op::K && l == 1 && M.bmax == 16 && M.lv[0].kind == 1 &&
+                L.N * kRow27 * (int64_t)sizeof(double) < (int64_t(1) << 31))
+                QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kRow27));
         }
         QPAT_TRY(dalloc(c, &M.w, nsys * nl));
         QPAT_TRY(dalloc(c, &M.gmax, nsys * nl));
@@ -2464,6 +2728,9 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
         hipLaunchKernelGGL(k_mg_rap, dim3((unsigned)((C.N + kMgT - 1) / kMgT), nsys), dim3(kMgT), 0, c->stream,
                            lv_args(F), M.opdep ? F.W : nullptr, C.U, C.nx, C.ny, C.nz);
     }
+    if (nl > 1 && M.lv[1].Uf)
+        hipLaunchKernelGGL(k_mg_fullrows27, dim3(grid_for(M.lv[1].N, kMgT, 4096), nsys), dim3(kMgT), 0, c->stream,
+                           lv_args(M.lv[1]), M.lv[1].Uf);
     QPAT_HIP(c, hipMemsetAsync(M.gmax, 0, nsys * nl * sizeof(uint64_t), c->stream));
     for (int l = 0; l < nl; ++l)
         hipLaunchKernelGGL(k_mg_diag, dim3(grid_for(M.lv[l].N, kMgT, kMgBlocks), nsys), dim3(kMgT), 0, c->stream,
