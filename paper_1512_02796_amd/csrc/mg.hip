@@ -53,14 +53,18 @@ struct MgScal {
 };
 
 // Tiling of the finest level for one block size (LDS-tiled kernels)
+constexpr int kMgMaxLevels = 12;   // levels with a tiled-kernel geometry (more levels run untiled)
 struct TileGeo {
     bool ready = false, on = false;
     int32_t tiles_x = 0, tiles_y = 0, zc = 0, items = 0;
     // the tiled restriction to level 1 (coarse tiles, coarse z-chunk, blocks)
     int32_t rtiles_x = 0, rtiles_y = 0, rzc = 0, ritems = 0, rblocks = 0;
-    // the 27-point kernels of level 1 (16 right-hand sides)
-    bool on27 = false;
-    int32_t t27x = 0, t27y = 0, t27zc = 0, t27items = 0, t27blocks = 0;
+    // the tiled 27-point kernels of the coarse levels (16 right-hand sides)
+    struct Lv27 {
+        bool on = false;
+        int32_t tx = 0, ty = 0, zc = 0, items = 0, blocks = 0;
+    };
+    Lv27 t27[kMgMaxLevels];
 };
 
 struct MgState {
@@ -1722,6 +1726,7 @@ __global__ __launch_bounds__(kTT) void k_mg_restrict_tile(RstArgs g) {
 // row's lanes by a DPP row broadcast, so the operator never passes through
 // LDS and the partner rows are never gathered.
 constexpr int kRow27 = 32;
+constexpr int64_t kTile27Min = 16384;   // smaller levels keep the walk kernels (launch-bound anyway)
 enum Tile27Mode { kT27Resid = 0, kT27Smooth = 1 };
 
 __global__ __launch_bounds__(kMgT) void k_mg_fullrows27(LvArgs L, double* __restrict__ Uf) {
@@ -2026,28 +2031,31 @@ void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const doubl
     }
 }
 
-// level 1: out = b - A x (kT27Resid) or x + w D^{-1} (b - A x) (kT27Smooth)
+// coarse level l: out = b - A x (kT27Resid) or x + w D^{-1} (b - A x) (kT27Smooth)
 template <int MODE>
-void launch_tile27(const MgState& M, const TileGeo& t, hipStream_t st, const double* x, const double* b, double* out) {
-    const MgLevel& L = M.lv[1];
+void launch_tile27(const MgState& M, const TileGeo& t, int l, hipStream_t st, const double* x, const double* b,
+                   double* out) {
+    const MgLevel& L = M.lv[l];
+    const TileGeo::Lv27& q = t.t27[l];
     Tile27Args g;
     g.nx = L.nx;
     g.ny = L.ny;
     g.nz = L.nz;
-    g.tiles_x = t.t27x;
-    g.tiles_y = t.t27y;
-    g.zc = t.t27zc;
-    g.items = t.t27items;
+    g.tiles_x = q.tx;
+    g.tiles_y = q.ty;
+    g.zc = q.zc;
+    g.items = q.items;
     g.Uf = L.Uf;
     g.x = x;
     g.b = b;
     g.dinv = L.dinv;
-    g.w = M.w + 1;   // system 0, level 1
+    g.w = M.w + l;   // system 0, level l
     g.out = out;
     g.sc = M.sc;
-    hipLaunchKernelGGL(k_mg_tile27<MODE>, dim3(t.t27blocks), dim3(kTT), (size_t)3 * MgTile<16>::NPF * kTT * sizeof(double),
+    hipLaunchKernelGGL(k_mg_tile27<MODE>, dim3(q.blocks), dim3(kTT), (size_t)3 * MgTile<16>::NPF * kTT * sizeof(double),
                        st, g);
 }
+inline bool tiled27(const TileGeo& t, int l) { return l >= 1 && l < kMgMaxLevels && t.t27[l].on; }
 
 // level 0's residual to level 1's b and first sweep xc (tiled; trilinear)
 template <int B>
@@ -2141,33 +2149,36 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
         t.rzc = static_cast<int32_t>(rzc);
         t.ritems = static_cast<int32_t>(rtx * rty * ((C.nz + rzc - 1) / rzc));
         t.rblocks = static_cast<int32_t>(8 * std::min<int64_t>(rconc, (t.ritems + 7) / 8));
-        if constexpr (B == 16) {   // level 1's 27-point kernels
-            if (C.Uf) {
-                const void* f27[2] = {reinterpret_cast<const void*>(&k_mg_tile27<kT27Resid>),
-                                      reinterpret_cast<const void*>(&k_mg_tile27<kT27Smooth>)};
-                constexpr size_t lds27 = (size_t)3 * MgTile<16>::NPF * kTT * sizeof(double);
-                for (const void* f : f27)
-                    QPAT_HIP(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds27));
-                int occ27 = 1;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ27, f27[1], kTT, lds27) != hipSuccess) occ27 = 1;
-                const int64_t conc27 = (int64_t)std::max(occ27, 1) * (cus / 8);
-                const int64_t tx27 = (C.nx + kTHX - 3) / (kTHX - 2), ty27 = (C.ny + kTHY - 3) / (kTHY - 2);
-                int64_t best27 = -1, zc27 = C.nz;
-                for (int64_t nch = 1; nch <= C.nz; ++nch) {
-                    const int64_t zc = (C.nz + nch - 1) / nch;
-                    const int64_t items = tx27 * ty27 * ((C.nz + zc - 1) / zc);
+        if constexpr (B == 16) {   // the coarse levels' 27-point kernels
+            const void* f27[2] = {reinterpret_cast<const void*>(&k_mg_tile27<kT27Resid>),
+                                  reinterpret_cast<const void*>(&k_mg_tile27<kT27Smooth>)};
+            constexpr size_t lds27 = (size_t)3 * MgTile<16>::NPF * kTT * sizeof(double);
+            for (const void* f : f27)
+                QPAT_HIP(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds27));
+            int occ27 = 1;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ27, f27[1], kTT, lds27) != hipSuccess) occ27 = 1;
+            const int64_t conc27 = (int64_t)std::max(occ27, 1) * (cus / 8);
+            for (int l = 1; l < (int)M.lv.size() && l < kMgMaxLevels; ++l) {
+                const MgLevel& Q = M.lv[l];
+                if (!Q.Uf) continue;
+                const int64_t tx27 = (Q.nx + kTHX - 3) / (kTHX - 2), ty27 = (Q.ny + kTHY - 3) / (kTHY - 2);
+                int64_t best27 = -1, zc27 = Q.nz;
+                for (int64_t nch = 1; nch <= Q.nz; ++nch) {
+                    const int64_t zc = (Q.nz + nch - 1) / nch;
+                    const int64_t items = tx27 * ty27 * ((Q.nz + zc - 1) / zc);
                     const int64_t cost = (((items + 7) / 8 + conc27 - 1) / conc27) * (zc + 2);
                     if (best27 < 0 || cost < best27) {
                         best27 = cost;
                         zc27 = zc;
                     }
                 }
-                t.t27x = static_cast<int32_t>(tx27);
-                t.t27y = static_cast<int32_t>(ty27);
-                t.t27zc = static_cast<int32_t>(zc27);
-                t.t27items = static_cast<int32_t>(tx27 * ty27 * ((C.nz + zc27 - 1) / zc27));
-                t.t27blocks = static_cast<int32_t>(8 * std::min<int64_t>(conc27, (t.t27items + 7) / 8));
-                t.on27 = true;
+                TileGeo::Lv27& g27 = t.t27[l];
+                g27.tx = static_cast<int32_t>(tx27);
+                g27.ty = static_cast<int32_t>(ty27);
+                g27.zc = static_cast<int32_t>(zc27);
+                g27.items = static_cast<int32_t>(tx27 * ty27 * ((Q.nz + zc27 - 1) / zc27));
+                g27.blocks = static_cast<int32_t>(8 * std::min<int64_t>(conc27, (g27.items + 7) / 8));
+                g27.on = true;
             }
         }
     }
@@ -2214,8 +2225,8 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
             launch_tile<kTResidFirst, B>(M, tg, st, L.b, nullptr, L.b, L.r, nullptr);
         else if (l == 0 && tg.on)
             launch_tile<kTResid, B>(M, tg, st, xl[0], nullptr, L.b, L.r, nullptr);
-        else if (l == 1 && tg.on27 && B == 16)
-            launch_tile27<kT27Resid>(M, tg, st, xl[1], L.b, L.r);
+        else if (B == 16 && tiled27(tg, l))
+            launch_tile27<kT27Resid>(M, tg, l, st, xl[l], L.b, L.r);
         else
             QPAT_MG_KIND(L.kind, B, k_mg_resid, g, dim3(kMgT), 0, st, a, L.b, xl[l], L.r);
         if (l == 0 && ev) (void)hipEventRecord(ev[1], st);
@@ -2255,8 +2266,8 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
                 launch_tile<kTSmoothDots, B>(M, tg, st, xl[0], nullptr, L.b, tl[0], nullptr);
             else if (last)
                 launch_smooth<B, true>(L.kind, g, st, a, L.b, xl[l], tl[l], M.parts);
-            else if (l == 1 && tg.on27 && B == 16)
-                launch_tile27<kT27Smooth>(M, tg, st, xl[1], L.b, tl[1]);
+            else if (B == 16 && tiled27(tg, l))
+                launch_tile27<kT27Smooth>(M, tg, l, st, xl[l], L.b, tl[l]);
             else
                 launch_smooth<B, false>(L.kind, g, st, a, L.b, xl[l], tl[l], nullptr);
             if (last && ev) (void)hipEventRecord(ev[3], st);
@@ -2689,8 +2700,8 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             QPAT_TRY(dalloc(c, &L.r, V * L.N));
             if (op == Op::Prior && l + 1 < nl) QPAT_TRY(dalloc(c, &L.W, nsys * L.N * 8));
             if (op == Op::Prior && l == 0 && L.kind == 1) QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kFullRow));
-            if (op == Op::K && l == 1 && M.bmax == 16 && M.lv[0].kind == 1 &&
-                L.N * kRow27 * (int64_t)sizeof(double) < (int64_t(1) << 31))
+            if (op == Op::K && l >= 1 && l < kMgMaxLevels && M.bmax == 16 && M.lv[0].kind == 1 &&
+                L.N >= kTile27Min && L.N * kRow27 * (int64_t)sizeof(double) < (int64_t(1) << 31))
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kRow27));
         }
         QPAT_TRY(dalloc(c, &M.w, nsys * nl));
@@ -2728,9 +2739,10 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
         hipLaunchKernelGGL(k_mg_rap, dim3((unsigned)((C.N + kMgT - 1) / kMgT), nsys), dim3(kMgT), 0, c->stream,
                            lv_args(F), M.opdep ? F.W : nullptr, C.U, C.nx, C.ny, C.nz);
     }
-    if (nl > 1 && M.lv[1].Uf)
-        hipLaunchKernelGGL(k_mg_fullrows27, dim3(grid_for(M.lv[1].N, kMgT, 4096), nsys), dim3(kMgT), 0, c->stream,
-                           lv_args(M.lv[1]), M.lv[1].Uf);
+    for (int l = 1; l < nl; ++l)
+        if (M.lv[l].Uf)
+            hipLaunchKernelGGL(k_mg_fullrows27, dim3(grid_for(M.lv[l].N, kMgT, 4096), nsys), dim3(kMgT), 0,
+                               c->stream, lv_args(M.lv[l]), M.lv[l].Uf);
     QPAT_HIP(c, hipMemsetAsync(M.gmax, 0, nsys * nl * sizeof(uint64_t), c->stream));
     for (int l = 0; l < nl; ++l)
         hipLaunchKernelGGL(k_mg_diag, dim3(grid_for(M.lv[l].N, kMgT, kMgBlocks), nsys), dim3(kMgT), 0, c->stream,
