@@ -194,7 +194,9 @@ qpat_status qpat_lsqr_step(qpat_ctx* ctx, double* resnorm_out, qpat_info* info);
  * 2 M_delta direction+SpMV, 3 M_delta update. Multigrid-PCG: 4 K direction
  * + product, 5 K update, 6 K finest-level residual (with the first sweep),
  * 7 K finest-level last sweep (with the dot products); 8-11 the same for
- * M_delta. qpat_profile(ctx, 1) clears the counters and starts, 0 stops. */
+ * M_delta. Where one kernel does the update and the finest-level residual
+ * (the LDS-tiled path of 8 or 16 right-hand sides), 5 counts it and 6 stays
+ * empty. qpat_profile(ctx, 1) clears the counters and starts, 0 stops. */
 #define QPAT_NKSTAT 12
 typedef struct {
     int64_t launches;       /* launches that did work                                */

@@ -76,6 +76,7 @@ struct MgState {
     double* w = nullptr;           // [nsys][levels] Jacobi weights
     double* ainv = nullptr;        // [nsys][Nc][Nc]
     double *pr = nullptr, *pa = nullptr, *pb = nullptr, *pq = nullptr;  // PCG r, p (two), q: [nsys][N][bmax]
+    double* pr2 = nullptr;         // the other residual buffer of the fused update (odd iterations write r here)
     double* parts = nullptr;       // [lanes][4][kMgBlocks]
     uint64_t* gmax = nullptr;      // [nsys][levels] Gershgorin bounds (bit patterns)
     MgScal* sc = nullptr;          // [lanes], lane = sys B + k
@@ -1347,7 +1348,7 @@ struct MgTile {
     static constexpr int NU = (kTHN * 8 + kTT - 1) / kTT;     // operator values per thread and plane
     static constexpr size_t LDS = (size_t)3 * (NPF + NU) * kTT * sizeof(double);
 };
-enum TileMode { kTDirSpmv = 0, kTResidFirst = 1, kTSmoothDots = 2, kTTrue = 3, kTResid = 4, kTApply = 5 };
+enum TileMode { kTDirSpmv = 0, kTResidFirst = 1, kTSmoothDots = 2, kTTrue = 3, kTResid = 4, kTApply = 5, kTUpdResid = 6 };
 
 struct TileArgs {
     int32_t nx, ny, nz;
@@ -1364,6 +1365,8 @@ struct TileArgs {
     double* out2;         // kTDirSpmv: the new direction
     double* parts;        // partial sums, [lanes][4][kMgBlocks]
     const MgScal* sc;     // [B]
+    double* x3;           // kTUpdResid: the iterate (updated in place)
+    const double* p3;     // kTUpdResid: the direction
 };
 
 // kTDirSpmv: the PCG direction and product, p = in - c + beta in2 (in = z,
@@ -1376,13 +1379,18 @@ struct TileArgs {
 //   sum b (the last finest-level sweep of the V-cycle: b = r, out = z).
 // kTApply: out = scale A in for every right-hand side (any Kuhn stencil
 //   form U, e.g. the derivative of K in the Jacobian product).
+// kTUpdResid: the PCG update fused with kTResidFirst: r' = in - alpha in2
+//   (in = r, in2 = q = A p) to out2, x3 += alpha p3, partial r'.r', and the
+//   first sweep x = w D^{-1} r' staged, out = r' - A x. r' goes to another
+//   buffer than r: neighbouring tiles still read r's halo.
 template <int MODE, int B>
-__global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
+__global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
     using TL = MgTile<B>;
     constexpr int NPF = TL::NPF, NU = TL::NU, RS = NPF * kTT, US = NU * kTT;
     constexpr int TX = kTHX - 2, TY = kTHY - 2, M1 = 8;
     constexpr uint32_t SZ = sizeof(double);
-    constexpr bool HAS_B = MODE != kTDirSpmv && MODE != kTApply;
+    constexpr bool UPD = MODE == kTUpdResid;
+    constexpr bool HAS_B = MODE != kTDirSpmv && MODE != kTApply && !UPD;
     constexpr bool CENTER_D = MODE == kTSmoothDots;
     // the right-hand side's loads go out a plane ahead where the registers allow
     constexpr bool PRE_B = HAS_B && !CENTER_D;
@@ -1398,7 +1406,7 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
         if (!any) return;
     }
     bool act = true;
-    double cc_ = 0.0, beta = 0.0;
+    double cc_ = 0.0, beta = 0.0, alpha = 0.0;
     if constexpr (!ALL) {
         const MgScal scl = g.sc[k];
         act = scl.active != 0;
@@ -1406,11 +1414,12 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
             cc_ = scl.c;
             beta = scl.beta;
         }
+        if constexpr (UPD) alpha = scl.alpha;
     }
     const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
     const uint32_t nxy = static_cast<uint32_t>(nx) * ny;
     const uint32_t pv = nxy * B * SZ, pu = nxy * M1 * SZ, pd = nxy * SZ, pin = nxy * g.ld * SZ;
-    const double w = (MODE == kTSmoothDots || MODE == kTResidFirst) ? *g.w : 0.0;
+    const double w = (MODE == kTSmoothDots || MODE == kTResidFirst || UPD) ? *g.w : 0.0;
     auto plane = [&](const double* base, int pl, uint32_t stride, uint32_t bytes) {
         const bool in = pl >= 0 && pl < nz;
         return rsrc(base + (in ? (int64_t)pl * stride : 0), in ? bytes : 0u);
@@ -1422,7 +1431,7 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
         const int nl = (tid + u * kTT) / B;
         oc[u] = nl < TX * TY ? (nl / TX + 1) * kTHX + nl % TX + 1 : kTHX + 1;
     }
-    double fr[NPF], f2[NPF], fu[NU];
+    double fr[NPF], f2[NPF], fu[NU], f3[UPD ? NPF : 1];
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 
     const int32_t xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
@@ -1457,15 +1466,21 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
             const auto bi = plane(g.in, pl, nxy * g.ld, pin), bu = plane(g.U, pl, nxy * M1, pu);
 #pragma unroll
             for (int u = 0; u < NPF; ++u) fr[u] = bload<double>(bi, fo[u]);
-            if constexpr (MODE == kTDirSpmv) {
+            if constexpr (MODE == kTDirSpmv || UPD) {
                 const auto b2 = plane(g.in2, pl, nxy * B, pv);
 #pragma unroll
                 for (int u = 0; u < NPF; ++u) f2[u] = bload<double>(b2, fo[u]);
             }
-            if constexpr (MODE == kTResidFirst) {
+            if constexpr (MODE == kTResidFirst || UPD) {
                 const auto bd = plane(g.dinv, pl, nxy, pd);
 #pragma unroll
-                for (int u = 0; u < NPF; ++u) f2[u] = bload<double>(bd, fo[u] == kOut ? kOut : (fo[u] / SZ - k) / B * SZ);
+                for (int u = 0; u < NPF; ++u) {
+                    const double dv = bload<double>(bd, fo[u] == kOut ? kOut : (fo[u] / SZ - k) / B * SZ);
+                    if constexpr (UPD)
+                        f3[u] = dv;
+                    else
+                        f2[u] = dv;
+                }
             }
 #pragma unroll
             for (int v = 0; v < NU; ++v) fu[v] = bload<double>(bu, uo[v]);
@@ -1483,6 +1498,7 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
                 double val = fr[u];
                 if constexpr (MODE == kTDirSpmv) val = fo[u] != kOut ? fr[u] - cc_ + beta * f2[u] : 0.0;
                 if constexpr (MODE == kTResidFirst) val = w * f2[u] * fr[u];
+                if constexpr (UPD) val = w * f3[u] * (fr[u] - alpha * f2[u]);
                 ring[sl * RS + tid + u * kTT] = val;
             }
 #pragma unroll
@@ -1508,9 +1524,23 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
 #pragma unroll
                 for (int u = 0; u < NPF; ++u) dc[u] = bload<double>(bd, od[u]);
             }
+            constexpr int NO = UPD ? (TX * TY * B + kTT - 1) / kTT : 1;   // output slots in use
+            double qc[NO], xv[NO], pq[NO];
+            const auto bx = plane(g.x3, z, nxy * B, UPD && act ? pv : 0u);
+            if constexpr (UPD) {   // r and q of this plane's nodes (read as halo two steps ago: L2), x and p
+                const auto br = plane(g.in, z, nxy * B, act ? pv : 0u), bq = plane(g.in2, z, nxy * B, act ? pv : 0u);
+                const auto bp = plane(g.p3, z, nxy * B, act ? pv : 0u);
+#pragma unroll
+                for (int u = 0; u < NO; ++u) {
+                    bc[u] = bload<double>(br, oo[u]);
+                    qc[u] = bload<double>(bq, oo[u]);
+                    xv[u] = bload<double>(bx, oo[u]);
+                    pq[u] = bload<double>(bp, oo[u]);
+                }
+            }
             const auto bo = plane(g.out, z, nxy * B, act ? pv : 0u);
             if (act) {
-                const auto bo2 = plane(g.out2, z, nxy * B, MODE == kTDirSpmv ? pv : 0u);
+                const auto bo2 = plane(g.out2, z, nxy * B, MODE == kTDirSpmv || UPD ? pv : 0u);
 #pragma unroll
                 for (int u = 0; u < NPF; ++u) {
                     if (tid + u * kTT >= TX * TY * B) continue;   // whole waves past the tile skip
@@ -1550,6 +1580,12 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
                         bstore<double>(bo2, oo[u], xc);
                     } else if constexpr (MODE == kTApply) {
                         o = g.scale * sum;
+                    } else if constexpr (UPD) {
+                        const double rnew = bc[u] - alpha * qc[u];
+                        o = rnew - sum;
+                        a1 += in ? rnew * rnew : 0.0;
+                        bstore<double>(bo2, oo[u], rnew);
+                        bstore<double>(bx, oo[u], xv[u] + alpha * pq[u]);
                     } else if constexpr (MODE == kTSmoothDots) {
                         o = xc + w * dc[u] * (bc[u] - sum);
                         a0 += in ? bc[u] * o : 0.0;
@@ -1592,7 +1628,7 @@ __global__ __launch_bounds__(kTT, 2) void k_mg_tile(TileArgs g) {
         __syncthreads();
     };
     if constexpr (MODE == kTDirSpmv) out_sum(a0, 0);
-    if constexpr (MODE == kTTrue) out_sum(a1, 1);
+    if constexpr (MODE == kTTrue || UPD) out_sum(a1, 1);
     if constexpr (MODE == kTSmoothDots) {
         out_sum(a0, 0);
         out_sum(a1, 2);
@@ -2003,7 +2039,7 @@ dim3 sgrid(int64_t n) {
 
 template <int MODE, int B>
 void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const double* in, const double* in2,
-                 const double* b, double* out, double* out2) {
+                 const double* b, double* out, double* out2, double* x3 = nullptr, const double* p3 = nullptr) {
     if constexpr (B >= 8) {   // tile_setup turns the tiling on only there
         const MgLevel& L = M.lv[0];
         TileArgs g;
@@ -2027,6 +2063,8 @@ void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const doubl
         g.out2 = out2;
         g.parts = M.parts;
         g.sc = M.sc;
+        g.x3 = x3;
+        g.p3 = p3;
         hipLaunchKernelGGL((k_mg_tile<MODE, B>), sgrid<B>(L.N), dim3(kTT), MgTile<B>::LDS, st, g);
     }
 }
@@ -2097,12 +2135,13 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
     if constexpr (B >= 8) {
         if (M.nsys != 1 || L.kind != 1 || L.N * B * (int64_t)sizeof(double) >= (int64_t(1) << 31)) return QPAT_OK;
         static_assert(MgTile<B>::LDS <= 159 * 1024, "tiled multigrid LDS budget");
-        const void* fns[6] = {reinterpret_cast<const void*>(&k_mg_tile<kTDirSpmv, B>),
+        const void* fns[7] = {reinterpret_cast<const void*>(&k_mg_tile<kTDirSpmv, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTResidFirst, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTSmoothDots, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTTrue, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTResid, B>),
-                              reinterpret_cast<const void*>(&k_mg_tile<kTApply, B>)};
+                              reinterpret_cast<const void*>(&k_mg_tile<kTApply, B>),
+                              reinterpret_cast<const void*>(&k_mg_tile<kTUpdResid, B>)};
         for (const void* f : fns)   // dynamic LDS beyond the default limit is allowed per kernel
             QPAT_HIP(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MgTile<B>::LDS));
         int occ = 1, cus = 256;
@@ -2185,15 +2224,20 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
     return QPAT_OK;
 }
 
+// the tiled path fuses the PCG update with the V-cycle's first residual
+inline bool fused_update(const TileGeo& tg) { return tg.on && kMgNu == 1; }
+
 // One V-cycle on every lane: z = V(r), r = level 0's b. The last sweep also
 // leaves the partial sums r.z, sum z, sum r. On a tiled finest level with one
 // sweep each way the first sweep w D^{-1} r is never stored: the residual
 // kernel stages it and the prolongation recomputes it. Level 0 takes
 // 2 kMgNu - 1 ping-pong sweeps (an odd number), so z ends in level 0's t.
 template <int B>
-void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev = nullptr) {
+void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev = nullptr, const double* b0 = nullptr,
+            bool resid_done = false) {
     const int nl = static_cast<int>(M.lv.size());
     const bool fused0 = tg.on && kMgNu == 1;
+    const double* r0 = b0 ? b0 : M.lv[0].b;   // level 0's right-hand side (the PCG residual)
     std::vector<double*> xl(nl), tl(nl);
     for (int l = 0; l < nl; ++l) {
         xl[l] = M.lv[l].x;
@@ -2215,20 +2259,23 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         const MgLevel& C = M.lv[l + 1];
         const SmArgs a = sm(l);
         const dim3 g = sgrid<B>(L.N);
-        if (l == 0 && !fused0) hipLaunchKernelGGL(k_mg_first<B>, vgrid(L.N * B), dim3(kMgT), 0, st, a, L.b, xl[0]);
+        const double* bl = l == 0 ? r0 : L.b;
+        if (l == 0 && !fused0) hipLaunchKernelGGL(k_mg_first<B>, vgrid(L.N * B), dim3(kMgT), 0, st, a, r0, xl[0]);
         for (int k = 1; k < kMgNu; ++k) {
-            launch_smooth<B, false>(L.kind, g, st, a, L.b, xl[l], tl[l], nullptr);
+            launch_smooth<B, false>(L.kind, g, st, a, bl, xl[l], tl[l], nullptr);
             std::swap(xl[l], tl[l]);
         }
         if (l == 0 && ev) (void)hipEventRecord(ev[0], st);
-        if (l == 0 && fused0)
-            launch_tile<kTResidFirst, B>(M, tg, st, L.b, nullptr, L.b, L.r, nullptr);
+        if (l == 0 && fused0 && resid_done)
+            ;   // the PCG update produced level 0's residual (kTUpdResid)
+        else if (l == 0 && fused0)
+            launch_tile<kTResidFirst, B>(M, tg, st, r0, nullptr, r0, L.r, nullptr);
         else if (l == 0 && tg.on)
-            launch_tile<kTResid, B>(M, tg, st, xl[0], nullptr, L.b, L.r, nullptr);
+            launch_tile<kTResid, B>(M, tg, st, xl[0], nullptr, r0, L.r, nullptr);
         else if (B == 16 && tiled27(tg, l))
             launch_tile27<kT27Resid>(M, tg, l, st, xl[l], L.b, L.r);
         else
-            QPAT_MG_KIND(L.kind, B, k_mg_resid, g, dim3(kMgT), 0, st, a, L.b, xl[l], L.r);
+            QPAT_MG_KIND(L.kind, B, k_mg_resid, g, dim3(kMgT), 0, st, a, bl, xl[l], L.r);
         if (l == 0 && ev) (void)hipEventRecord(ev[1], st);
         if (l == 0 && tg.on && !M.opdep)
             launch_restrict<B>(M, tg, st, xl[1]);
@@ -2247,29 +2294,30 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         const MgLevel& C = M.lv[l + 1];
         const SmArgs a = sm(l);
         const dim3 g = sgrid<B>(L.N);
+        const double* bl = l == 0 ? r0 : L.b;
         if (l == 0 && fused0 && M.opdep)
-            hipLaunchKernelGGL((k_mg_prolong<B, true, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], L.b,
+            hipLaunchKernelGGL((k_mg_prolong<B, true, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], r0,
                                xl[0], L.W);
         else if (l == 0 && fused0)
-            hipLaunchKernelGGL((k_mg_prolong<B, true, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], L.b,
+            hipLaunchKernelGGL((k_mg_prolong<B, true, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], r0,
                                xl[0], nullptr);
         else if (M.opdep)
             hipLaunchKernelGGL((k_mg_prolong<B, false, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1],
-                               L.b, xl[l], L.W);
+                               bl, xl[l], L.W);
         else
             hipLaunchKernelGGL((k_mg_prolong<B, false, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1],
-                               L.b, xl[l], nullptr);
+                               bl, xl[l], nullptr);
         for (int k = 0; k < kMgNu; ++k) {
             const bool last = l == 0 && k == kMgNu - 1;
             if (last && ev) (void)hipEventRecord(ev[2], st);
             if (last && tg.on)
-                launch_tile<kTSmoothDots, B>(M, tg, st, xl[0], nullptr, L.b, tl[0], nullptr);
+                launch_tile<kTSmoothDots, B>(M, tg, st, xl[0], nullptr, r0, tl[0], nullptr);
             else if (last)
-                launch_smooth<B, true>(L.kind, g, st, a, L.b, xl[l], tl[l], M.parts);
+                launch_smooth<B, true>(L.kind, g, st, a, bl, xl[l], tl[l], M.parts);
             else if (B == 16 && tiled27(tg, l))
                 launch_tile27<kT27Smooth>(M, tg, l, st, xl[l], L.b, tl[l]);
             else
-                launch_smooth<B, false>(L.kind, g, st, a, L.b, xl[l], tl[l], nullptr);
+                launch_smooth<B, false>(L.kind, g, st, a, bl, xl[l], tl[l], nullptr);
             if (last && ev) (void)hipEventRecord(ev[3], st);
             std::swap(xl[l], tl[l]);
         }
@@ -2331,11 +2379,18 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 0);
     if (ev) (void)hipEventRecord(ev[2], st);
-    hipLaunchKernelGGL(k_mgp_update<B>, g, dim3(kMgT), 0, st, a);
+    if (fused_update(tg)) {   // r, x and the V-cycle's first sweep + residual in one pass; r alternates buffers
+        double* r_old = par ? M.pr2 : M.pr;
+        double* r_new = par ? M.pr : M.pr2;
+        launch_tile<kTUpdResid, B>(M, tg, st, r_old, a.q, nullptr, M.lv[0].r, r_new, a.x, a.pn);
+        a.r = r_new;
+    } else {
+        hipLaunchKernelGGL(k_mgp_update<B>, g, dim3(kMgT), 0, st, a);
+    }
     if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 1);
     region_solve<B>(M, a, st);
-    vcycle<B>(M, st, tg, ev ? ev + 4 : nullptr);
+    vcycle<B>(M, st, tg, ev ? ev + 4 : nullptr, a.r, fused_update(tg));
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 2);
 }
 
@@ -2431,6 +2486,7 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
                     for (int l = 0; l < S; ++l) lanes_on += (M.sc_host[l].iters - iters_before[l]) > i;
                     if (lanes_on == 0) break;
                     for (int kk = 0; kk < 4; ++kk) {
+                        if (kk == 2 && fused_update(tg)) continue;   // the update's kernel did it
                         float t = 0.f;
                         QPAT_HIP(c, hipEventElapsedTime(&t, M.ev[8 * i + 2 * kk], M.ev[8 * i + 2 * kk + 1]));
                         qpat_kstat& ks = c->prof[base + kk];
@@ -2708,6 +2764,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
         QPAT_TRY(dalloc(c, &M.gmax, nsys * nl));
         QPAT_TRY(dalloc(c, &M.ainv, nsys * Nc * Nc));
         QPAT_TRY(dalloc(c, &M.pr, V * c->N));
+        QPAT_TRY(dalloc(c, &M.pr2, V * c->N));
         QPAT_TRY(dalloc(c, &M.pa, V * c->N));
         QPAT_TRY(dalloc(c, &M.pb, V * c->N));
         QPAT_TRY(dalloc(c, &M.pq, V * c->N));
