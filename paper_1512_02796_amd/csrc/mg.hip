@@ -1346,7 +1346,7 @@ template <int B>
 struct MgTile {
     static constexpr int NPF = (kTHN * B + kTT - 1) / kTT;   // input elements per thread and plane
     static constexpr int NU = (kTHN * 8 + kTT - 1) / kTT;     // operator values per thread and plane
-    static constexpr size_t LDS = (size_t)3 * (NPF + NU) * kTT * sizeof(double);
+    static constexpr size_t LDS = (size_t)3 * (NPF + NU) * kTT * sizeof(double) + 3 * kTHN * sizeof(double);
 };
 enum TileMode { kTDirSpmv = 0, kTResidFirst = 1, kTSmoothDots = 2, kTTrue = 3, kTResid = 4, kTApply = 5, kTUpdResid = 6 };
 
@@ -1398,6 +1398,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
     __shared__ double sm[(kTT / 64) * 16];
     double* ring = reinterpret_cast<double*>(mg_smem);   // [3][RS]: [halo node][B]
     double* ust = ring + 3 * RS;                          // [3][US]: [halo node][8]
+    double* dring = ust + 3 * US;                         // UPD: [3][kTHN] 1 / a_ii of the halo nodes
     const int tid = threadIdx.x, k = tid % B;
     constexpr bool ALL = MODE == kTTrue || MODE == kTApply;   // every right-hand side, no PCG scalars
     if constexpr (!ALL) {   // every right-hand side stopped: nothing to do
@@ -1431,7 +1432,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
         const int nl = (tid + u * kTT) / B;
         oc[u] = nl < TX * TY ? (nl / TX + 1) * kTHX + nl % TX + 1 : kTHX + 1;
     }
-    double fr[NPF], f2[NPF], fu[NU], f3[UPD ? NPF : 1];
+    double fr[NPF], f2[NPF], fu[NU], dd = 0.0;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 
     const int32_t xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
@@ -1454,6 +1455,11 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
             oo[u] = oin ? (static_cast<uint32_t>(oy * nx + ox) * B + k) * SZ : kOut;
             od[u] = oin ? static_cast<uint32_t>(oy * nx + ox) * SZ : kOut;
         }
+        uint32_t dof = kOut;   // UPD: thread tid < kTHN loads 1 / a_ii of halo node tid
+        if (UPD && tid < kTHN) {
+            const int gx = x0 - 1 + tid % kTHX, gy = y0 - 1 + tid / kTHX;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) dof = static_cast<uint32_t>(gy * nx + gx) * SZ;
+        }
 #pragma unroll
         for (int v = 0; v < NU; ++v) {
             const int e = tid + v * kTT, nl = e / M1;
@@ -1471,22 +1477,20 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
 #pragma unroll
                 for (int u = 0; u < NPF; ++u) f2[u] = bload<double>(b2, fo[u]);
             }
-            if constexpr (MODE == kTResidFirst || UPD) {
+            if constexpr (MODE == kTResidFirst) {
                 const auto bd = plane(g.dinv, pl, nxy, pd);
 #pragma unroll
-                for (int u = 0; u < NPF; ++u) {
-                    const double dv = bload<double>(bd, fo[u] == kOut ? kOut : (fo[u] / SZ - k) / B * SZ);
-                    if constexpr (UPD)
-                        f3[u] = dv;
-                    else
-                        f2[u] = dv;
-                }
+                for (int u = 0; u < NPF; ++u) f2[u] = bload<double>(bd, fo[u] == kOut ? kOut : (fo[u] / SZ - k) / B * SZ);
+            }
+            if constexpr (UPD) {   // one value per halo node, through LDS (dring)
+                const auto bd = plane(g.dinv, pl, nxy, pd);
+                dd = bload<double>(bd, dof);
             }
 #pragma unroll
             for (int v = 0; v < NU; ++v) fu[v] = bload<double>(bu, uo[v]);
         };
         auto loadb = [&](int z, double(&to)[NPF]) {
-            const auto bb = plane(g.b, z, nxy * B, act ? pv : 0u);
+            const auto bb = plane(g.b, z, nxy * B, pv);
 #pragma unroll
             for (int u = 0; u < NPF; ++u) to[u] = bload<double>(bb, oo[u]);
         };
@@ -1498,7 +1502,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                 double val = fr[u];
                 if constexpr (MODE == kTDirSpmv) val = fo[u] != kOut ? fr[u] - cc_ + beta * f2[u] : 0.0;
                 if constexpr (MODE == kTResidFirst) val = w * f2[u] * fr[u];
-                if constexpr (UPD) val = w * f3[u] * (fr[u] - alpha * f2[u]);
+                if constexpr (UPD) val = w * dring[sl * kTHN + (tid + u * kTT) / B] * (fr[u] - alpha * f2[u]);
                 ring[sl * RS + tid + u * kTT] = val;
             }
 #pragma unroll
@@ -1520,25 +1524,24 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                 loadb(z, bc);
             }
             if constexpr (CENTER_D) {
-                const auto bd = plane(g.dinv, z, nxy, act ? pd : 0u);
+                const auto bd = plane(g.dinv, z, nxy, pd);
 #pragma unroll
                 for (int u = 0; u < NPF; ++u) dc[u] = bload<double>(bd, od[u]);
             }
             constexpr int NO = UPD ? (TX * TY * B + kTT - 1) / kTT : 1;   // output slots in use
-            double qc[NO], xv[NO], pq[NO];
-            const auto bx = plane(g.x3, z, nxy * B, UPD && act ? pv : 0u);
-            if constexpr (UPD) {   // r and q of this plane's nodes (read as halo two steps ago: L2), x and p
-                const auto br = plane(g.in, z, nxy * B, act ? pv : 0u), bq = plane(g.in2, z, nxy * B, act ? pv : 0u);
-                const auto bp = plane(g.p3, z, nxy * B, act ? pv : 0u);
+            double qc[NO];
+            if constexpr (UPD) {   // r and q of this plane's nodes (read as halo two steps ago: L2)
+                const auto br = plane(g.in, z, nxy * B, pv), bq = plane(g.in2, z, nxy * B, pv);
 #pragma unroll
                 for (int u = 0; u < NO; ++u) {
                     bc[u] = bload<double>(br, oo[u]);
                     qc[u] = bload<double>(bq, oo[u]);
-                    xv[u] = bload<double>(bx, oo[u]);
-                    pq[u] = bload<double>(bp, oo[u]);
                 }
             }
-            const auto bo = plane(g.out, z, nxy * B, act ? pv : 0u);
+            // descriptors stay uniform over the wavefront (a per-lane size would
+            // turn every access into a loop over the distinct values); the
+            // stores of stopped right-hand sides are skipped by the branch
+            const auto bo = plane(g.out, z, nxy * B, pv);
             if (act) {
                 const auto bo2 = plane(g.out2, z, nxy * B, MODE == kTDirSpmv || UPD ? pv : 0u);
 #pragma unroll
@@ -1585,7 +1588,6 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                         o = rnew - sum;
                         a1 += in ? rnew * rnew : 0.0;
                         bstore<double>(bo2, oo[u], rnew);
-                        bstore<double>(bx, oo[u], xv[u] + alpha * pq[u]);
                     } else if constexpr (MODE == kTSmoothDots) {
                         o = xc + w * dc[u] * (bc[u] - sum);
                         a0 += in ? bc[u] * o : 0.0;
@@ -1597,14 +1599,33 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                     }
                     bstore<double>(bo, oo[u], o);
                 }
+                if constexpr (UPD) {   // x += alpha p on this plane's nodes, after the stencil work
+                    __builtin_amdgcn_sched_barrier(0);
+                    const auto bx = plane(g.x3, z, nxy * B, pv), bp = plane(g.p3, z, nxy * B, pv);
+#pragma unroll
+                    for (int u = 0; u < NO; ++u) {
+                        if (tid + u * kTT >= TX * TY * B) continue;
+                        bstore<double>(bx, oo[u], bload<double>(bx, oo[u]) + alpha * bload<double>(bp, oo[u]));
+                    }
+                }
             }
+            if (UPD && tid < kTHN && z + 1 < ze) dring[sl * kTHN + tid] = dd;   // plane z + 2 lives in slot sl
             __syncthreads();
         };
+        auto put_d = [&](int sl) {
+            if constexpr (UPD) {
+                if (tid < kTHN) dring[sl * kTHN + tid] = dd;
+                __syncthreads();
+            }
+        };
         fetch(zb - 1);
+        put_d(0);
         store(0);
         fetch(zb);
+        put_d(1);
         store(1);
         fetch(zb + 1);
+        put_d(2);
         using I0 = std::integral_constant<int, 0>;
         using I1 = std::integral_constant<int, 1>;
         using I2 = std::integral_constant<int, 2>;
@@ -1899,7 +1920,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
         double ua[NO], ub[NO], bn[NO];
         auto load_node = [&](int z) {
             const auto bu = plane(g.Uf, z, nxy * kRow27, pr);
-            const auto bb = plane(g.b, z, nxy * B, act ? pv : 0u);
+            const auto bb = plane(g.b, z, nxy * B, pv);
 #pragma unroll
             for (int u = 0; u < NO; ++u) {
                 ua[u] = bload<double>(bu, ro[u]);
@@ -1926,7 +1947,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
 #pragma unroll
                 for (int u = 0; u < NO; ++u) dc[u] = bload<double>(bd, od[u]);
             }
-            const auto bo = plane(g.out, z, nxy * B, act ? pv : 0u);
+            const auto bo = plane(g.out, z, nxy * B, pv);   // uniform descriptor; stopped lanes store nowhere
 #pragma unroll
             for (int u = 0; u < NO; ++u) {
                 if (tid + u * kTT >= TX * TY * B) continue;   // whole waves past the tile skip
@@ -1935,7 +1956,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
                                           std::make_integer_sequence<int, 13>{});
                 double o = bc[u] - ax;
                 if constexpr (MODE == kT27Smooth) o = rb[sz * RS] + w * dc[u] * o;
-                bstore<double>(bo, oo[u], o);
+                bstore<double>(bo, act ? oo[u] : kOut, o);
             }
             __syncthreads();
         };

@@ -341,13 +341,16 @@ __global__ __launch_bounds__(kStThreads, 4) void k_dir_stencil(PcgArgs<T> a, StA
             const auto bpn = plane(pn, z, nxy * B, pv), bq = plane(q, z, nxy * B, pv);
             // the deferred iterate update of the output nodes: loads issued here,
             // in flight during the arithmetic below
-            const auto bx = plane(xv, z, nxy * B, alpha != T(0) ? pv : 0u);
-            const auto bo = plane(po, z, nxy * B, (alpha != T(0) || !act) ? pv : 0u);   // inactive lanes copy p
+            // (per-lane choices go into the offsets: a descriptor must stay
+            // uniform over the wavefront)
+            const auto bx = plane(xv, z, nxy * B, pv);
+            const auto bo = plane(po, z, nxy * B, pv);   // inactive lanes copy p
+            const bool xup = alpha != T(0), pold = alpha != T(0) || !act;
             T xo[NPF], pov[NPF];
 #pragma unroll
             for (int u = 0; u < NPF; ++u) {
-                xo[u] = bload<T>(bx, oo[u]);
-                pov[u] = bload<T>(bo, oo[u]);
+                xo[u] = bload<T>(bx, xup ? oo[u] : kOut);
+                pov[u] = bload<T>(bo, pold ? oo[u] : kOut);
             }
             if (act) {
                 const T* Rz = ring + sz * RS;
@@ -406,9 +409,9 @@ __global__ __launch_bounds__(kStThreads, 4) void k_dir_stencil(PcgArgs<T> a, StA
 #pragma unroll
                 for (int u = 0; u < NPF; ++u) bstore<T>(bpn, oo[u], pov[u]);
             }
-            // with alpha = 0 the resources have no records: nothing is stored
+            // with alpha = 0 nothing is stored
 #pragma unroll
-            for (int u = 0; u < NPF; ++u) bstore<T>(bx, oo[u], xo[u] + alpha * pov[u]);
+            for (int u = 0; u < NPF; ++u) bstore<T>(bx, xup ? oo[u] : kOut, xo[u] + alpha * pov[u]);
             __syncthreads();
         };
 
