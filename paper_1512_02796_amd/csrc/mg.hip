@@ -44,7 +44,7 @@ struct MgLevel {
     double* t = nullptr;           // ping-pong partner of x
     double* r = nullptr;           // residual before restriction
     double* W = nullptr;           // [nsys][N][8] operator-dependent prolongation weights to the next level
-    double* Uf = nullptr;          // kind 3: [nsys][N][kFullRow] whole Kuhn rows
+    double* Uf = nullptr;          // kind 3: [nsys][kFullRow][N] whole Kuhn rows, entry-major; K levels >= 1: [N][kRow27]
 };
 
 struct MgScal {
@@ -56,7 +56,7 @@ struct MgScal {
 constexpr int kMgMaxLevels = 12;   // levels with a tiled-kernel geometry (more levels run untiled)
 struct TileGeo {
     bool ready = false, on = false;
-    int32_t tiles_x = 0, tiles_y = 0, zc = 0, items = 0;
+    int32_t tiles_x = 0, tiles_y = 0, zc = 0, items = 0, blocks = 0;
     // the tiled restriction to level 1 (coarse tiles, coarse z-chunk, blocks)
     int32_t rtiles_x = 0, rtiles_y = 0, rzc = 0, ritems = 0, rblocks = 0;
     // the tiled 27-point kernels of the coarse levels (16 right-hand sides)
@@ -100,7 +100,8 @@ namespace {
 
 constexpr int kMgCoarse = 5;      // coarsest lattice: at most this many nodes per axis
 constexpr int kMgNu = 1;          // Jacobi sweeps before and after the coarse correction
-constexpr int kMgBlocks = 512;    // blocks of the vector kernels (partial sums)
+constexpr int kMgBlocks = 2048;   // most blocks of a kernel that writes partial sums (8 per CU)
+constexpr int kMgGrid = 512;      // blocks of the vector kernels of several right-hand sides
 constexpr int kMgT = 256;
 constexpr int kMgLanes = 32;      // systems x right-hand sides
 constexpr int kMgChunk0 = 4;      // PCG iterations before the first host check of a run
@@ -214,12 +215,13 @@ struct LvArgs {
     int32_t m, nx, ny, nz;
     int64_t N;
     int32_t kind;         // row kernel: 0 generic table, 1 Kuhn offsets, 2 full 27-point, 3 Kuhn full rows
-    const double* Uf;     // kind 3: [nsys][N][kFullRow] full rows of the Kuhn stencil
+    const double* Uf;     // kind 3: [nsys][kFullRow][N] whole rows of the Kuhn stencil
 };
 
 // Kuhn rows stored whole for the one-right-hand-side kernels: diagonal, the 7
-// upper entries, the 7 lower ones (offset order), padding: one 128-byte line
-// per node instead of a gather of the lower entries from 7 partner rows
+// upper entries, the 7 lower ones (offset order), entry-major ([kFullRow][N]
+// per system) so that a wavefront's loads of one entry for consecutive nodes
+// are contiguous: no gather of the lower entries from 7 partner rows
 constexpr int kFullRow = 16;
 
 // first stored row of system sys in the form the row kernel KIND reads
@@ -248,14 +250,9 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
         }
         return s;
     } else if constexpr (KIND == 3) {
-        double u[kFullRow];
-        const d2v* Ur = reinterpret_cast<const d2v*>(U + i * kFullRow);
+        double u[15];
 #pragma unroll
-        for (int k = 0; k < kFullRow / 2; ++k) {
-            const d2v t = Ur[k];
-            u[2 * k] = t.x;
-            u[2 * k + 1] = t.y;
-        }
+        for (int k = 0; k < 15; ++k) u[k] = U[k * L.N + i];
         const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
         T s = u[0] * vld<T>(x + i * B);
 #pragma unroll
@@ -365,8 +362,12 @@ __device__ __forceinline__ bool pair_active(const MgScal* sc, int sys, int v) {
 }
 
 // partial sums of the block: parts[lane][slot][block]
+// a block's partial sum; a grid smaller than kMgBlocks also clears the slots
+// no block of it owns, so that the reductions can read a fixed count
 __device__ __forceinline__ void put(double* parts, int lane, int slot, double val) {
-    parts[(lane * 4 + slot) * kMgBlocks + blockIdx.x] = val;
+    double* p = parts + (lane * 4 + slot) * kMgBlocks;
+    p[blockIdx.x] = val;
+    for (int b = blockIdx.x + gridDim.x; b < kMgBlocks; b += gridDim.x) p[b] = 0.0;
 }
 
 // per-right-hand-side block sums of a V-wide accumulator, written as partials
@@ -401,9 +402,8 @@ __global__ __launch_bounds__(kMgT) void k_mg_fullrows(LvArgs L, double* __restri
             u[8 + j] = lo ? U[(i - lin) * M1 + 1 + j] : 0.0;
         }
         u[15] = 0.0;
-        d2v* o = reinterpret_cast<d2v*>(F + i * kFullRow);
 #pragma unroll
-        for (int k = 0; k < kFullRow / 2; ++k) o[k] = d2v{u[2 * k], u[2 * k + 1]};
+        for (int k = 0; k < kFullRow; ++k) F[k * L.N + i] = u[k];
     }
 }
 
@@ -1990,8 +1990,8 @@ inline LvArgs lv_args(const MgLevel& L) {
     return a;
 }
 
-// a multiple of 8 blocks (the XCD row split), at most kMgBlocks
-inline dim3 vgrid(int64_t n) { return dim3((grid_for(n, kMgT, kMgBlocks) + 7) & ~7); }
+// a multiple of 8 blocks (the XCD row split), at most cap (<= kMgBlocks)
+inline dim3 vgrid(int64_t n, int cap = kMgGrid) { return dim3((grid_for(n, kMgT, cap) + 7) & ~7); }
 
 #define QPAT_MG_KIND(kind, B, KERNEL, ...)                                 \
     switch (kind) {                                                         \
@@ -2055,7 +2055,8 @@ void launch_smooth(int kind, dim3 g, hipStream_t st, const SmArgs& a, const doub
 // grid of the stencil and V-cycle kernels of a level with n nodes
 template <int B>
 dim3 sgrid(int64_t n) {
-    return vgrid(n * Pk<B>::BV);
+    // one right-hand side per thread (the M_delta solves) is latency-bound: more blocks
+    return vgrid(n * Pk<B>::BV, B == 1 ? kMgBlocks : kMgGrid);
 }
 
 template <int MODE, int B>
@@ -2086,7 +2087,7 @@ void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const doubl
         g.sc = M.sc;
         g.x3 = x3;
         g.p3 = p3;
-        hipLaunchKernelGGL((k_mg_tile<MODE, B>), sgrid<B>(L.N), dim3(kTT), MgTile<B>::LDS, st, g);
+        hipLaunchKernelGGL((k_mg_tile<MODE, B>), dim3(t.blocks), dim3(kTT), MgTile<B>::LDS, st, g);
     }
 }
 
@@ -2185,6 +2186,7 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
         t.tiles_y = static_cast<int32_t>(ty);
         t.zc = static_cast<int32_t>(best_zc);
         t.items = static_cast<int32_t>(tx * ty * ((L.nz + best_zc - 1) / best_zc));
+        t.blocks = static_cast<int32_t>(8 * std::min<int64_t>(conc, (t.items + 7) / 8));
         t.on = true;
         // restriction to level 1: the same balance with (2 zc + 1) fine planes per item
         const MgLevel& C = M.lv[1];
@@ -2899,7 +2901,7 @@ static qpat_status apply_B(qpat_ctx* c, const double* U, const double* in, int l
         g.U = U;
         g.in = in;
         g.out = out;
-        hipLaunchKernelGGL((k_mg_tile<kTApply, B>), sgrid<B>(L.N), dim3(kTT), MgTile<B>::LDS, c->stream, g);
+        hipLaunchKernelGGL((k_mg_tile<kTApply, B>), dim3(t.blocks), dim3(kTT), MgTile<B>::LDS, c->stream, g);
         QPAT_HIP(c, hipGetLastError());
         *done = true;
     }
