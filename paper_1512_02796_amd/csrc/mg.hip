@@ -43,7 +43,7 @@ struct MgLevel {
     double* x = nullptr;           // [nsys][N][B]
     double* t = nullptr;           // ping-pong partner of x
     double* r = nullptr;           // residual before restriction
-    double* W = nullptr;           // [nsys][N][8] operator-dependent prolongation weights to the next level
+    double* W = nullptr;           // [nsys][8][N] operator-dependent prolongation weights to the next level (corner-major)
     double* Uf = nullptr;          // kind 3: [nsys][kFullRow][N] whole Kuhn rows, entry-major; K levels >= 1: [N][kRow27]
 };
 
@@ -439,10 +439,12 @@ __device__ __forceinline__ double pw(int d) { return d == 0 ? 1.0 : 0.5; }
 
 // Prolongation weight of fine node i (coords fx, fy, fz) towards coarse node
 // J0(i) + corner c, J0(i) = (fx/2, fy/2, fz/2), c = cz 4 + cy 2 + cx. W: the
-// operator-dependent weights [N][8] of the system, or null for trilinear
+// operator-dependent weights of the system, corner-major ([8][N]: the loads of
+// one corner for consecutive nodes are contiguous), or null for trilinear
 // interpolation (1 on an even axis, 1/2 to both sides on an odd one).
-__device__ __forceinline__ double pweight(const double* __restrict__ W, int64_t i, int fx, int fy, int fz, int c) {
-    if (W) return W[i * 8 + c];
+__device__ __forceinline__ double pweight(const double* __restrict__ W, int64_t N, int64_t i, int fx, int fy, int fz,
+                                          int c) {
+    if (W) return W[c * N + i];
     const int bx = c & 1, by = (c >> 1) & 1, bz = c >> 2;
     const double wx = (fx & 1) ? 0.5 : (bx ? 0.0 : 1.0);
     const double wy = (fy & 1) ? 0.5 : (by ? 0.0 : 1.0);
@@ -454,7 +456,7 @@ __device__ __forceinline__ double pweight(const double* __restrict__ W, int64_t 
 // (code order (dx+1) + 3 (dy+1) + 9 (dz+1) = 13 ... 26) of every coarse node:
 // sum over the fine nodes i in the support of I, the fine stencil entries
 // a_ij, and the coarse nodes J whose support holds j, of P(i,I) a_ij P(j,J).
-// W: [nsys][N][8] weights of P, or null (trilinear).
+// W: [nsys][8][N] weights of P, or null (trilinear).
 __global__ __launch_bounds__(kMgT) void k_mg_rap(LvArgs F, const double* __restrict__ Wall, double* __restrict__ Uc,
                                                  int cx, int cy, int cz) {
     __shared__ double acc[kMgT][14];
@@ -474,7 +476,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_rap(LvArgs F, const double* __restr
             if (fx < 0 || fx >= F.nx || fy < 0 || fy >= F.ny || fz < 0 || fz >= F.nz) continue;
             const int32_t i = fx + F.nx * (fy + F.ny * fz);
             // I = J0(i) + corner, corner 1 exactly along the axes where i sits below 2 I
-            const double wi = pweight(W, i, fx, fy, fz, (ax < 0 ? 1 : 0) + (ay < 0 ? 2 : 0) + (az < 0 ? 4 : 0));
+            const double wi = pweight(W, F.N, i, fx, fy, fz, (ax < 0 ? 1 : 0) + (ay < 0 ? 2 : 0) + (az < 0 ? 4 : 0));
             if (wi == 0.0) continue;
             // the fine row: diagonal, upper and lower entries
             for (int s = -F.m; s <= F.m; ++s) {
@@ -496,7 +498,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_rap(LvArgs F, const double* __restr
                 const int jx = fx + sx, jy = fy + sy, jz = fz + sz;
                 const int32_t j = i + lin;
                 for (int cj = 0; cj < 8; ++cj) {
-                    const double wj = pweight(W, j, jx, jy, jz, cj);
+                    const double wj = pweight(W, F.N, j, jx, jy, jz, cj);
                     if (wj == 0.0) continue;
                     const int Jx = (jx >> 1) + (cj & 1), Jy = (jy >> 1) + ((cj >> 1) & 1), Jz = (jz >> 1) + (cj >> 2);
                     const int code = (Jx - Ix + 1) + 3 * (Jy - Iy + 1) + 9 * (Jz - Iz + 1);
@@ -535,7 +537,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_pweights(LvArgs L, double* __restri
         const int px = ix & 1, py = iy & 1, pz = iz & 1;
         if (px + py + pz != CLASS) continue;
         double w[8];
-        for (int c = 0; c < 8; ++c) w[c] = pweight(nullptr, i, ix, iy, iz, c);
+        for (int c = 0; c < 8; ++c) w[c] = pweight(nullptr, L.N, i, ix, iy, iz, c);
         bool ok = CLASS > 0 && !(px && ix + 1 >= L.nx) && !(py && iy + 1 >= L.ny) && !(pz && iz + 1 >= L.nz);
         if (ok) {
             // the row, collapsed over the even axes: C[(dx+1) + 3 (dy+1) + 9 (dz+1)]
@@ -564,7 +566,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_pweights(LvArgs L, double* __restri
                 const double f = -C[k] / c0;
                 // the neighbour's weights, re-indexed to this node's corners
                 for (int cn = 0; cn < 8; ++cn) {
-                    const double wn = W[n * 8 + cn];
+                    const double wn = W[cn * L.N + n];
                     if (wn == 0.0) continue;
                     const int rx = (nxp >> 1) + (cn & 1) - (ix >> 1);
                     const int ry = (nyp >> 1) + ((cn >> 1) & 1) - (iy >> 1);
@@ -581,7 +583,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_pweights(LvArgs L, double* __restri
             if (ok)
                 for (int c = 0; c < 8; ++c) w[c] = acc[c];
         }
-        for (int c = 0; c < 8; ++c) W[i * 8 + c] = w[c];
+        for (int c = 0; c < 8; ++c) W[c * L.N + i] = w[c];
     }
 }
 
@@ -686,7 +688,7 @@ struct Span {
 
 // bc = P^T r on the coarse level c, and the first sweep there, xc = w D^{-1} bc.
 // Fine nodes 2 I + {-1, 0, 1} per axis, weights 1/2, 1, 1/2 (trilinear) or
-// from Wall ([nsys][Nf][8], operator-dependent); the ones past the lattice
+// from Wall ([nsys][8][Nf], operator-dependent); the ones past the lattice
 // get weight 0 (their loads are clamped inside it).
 template <int B, bool OPW>
 __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int32_t ny, int32_t nz,
@@ -729,7 +731,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
                         double wgt = wyz * wx[dx];
                         if constexpr (OPW)   // I is corner (d == 0 per axis) of fine node 2 I + d - 1
                             if (wgt != 0.0)
-                                wgt = Ws[(int64_t)(row + fx[dx]) * 8 + (dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)];
+                                wgt = Ws[((dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)) * Nf + (row + fx[dx])];
                         s += wgt * vld<T>(rs + (row + fx[dx]) * B);
                     }
                 }
@@ -741,7 +743,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
 
 // x = base + P xc on fine level f (coarse lattice cx, cy, cz). base = x, or
 // with FIRST the first sweep w D^{-1} b, which is then never stored. P:
-// trilinear, or the weights Wall ([nsys][Nf][8]).
+// trilinear, or the weights Wall ([nsys][8][Nf]).
 template <int B, bool FIRST, bool OPW>
 __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32_t cy, int32_t cz,
                                                      const double* __restrict__ xc, const double* __restrict__ b,
@@ -775,7 +777,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
                         // clamps the index of a zero-weight corner
                         double wgt;
                         if constexpr (OPW)
-                            wgt = Ws[(int64_t)i * 8 + a2 + 2 * b2 + 4 * c2];
+                            wgt = Ws[(a2 + 2 * b2 + 4 * c2) * Nf + i];
                         else
                             wgt = wyz * wx[a2];
                         s += wgt * vld<T>(xs + (row + jx[a2]) * B);
