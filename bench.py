@@ -68,21 +68,27 @@ MG_KERNELS = {
     "K_mg_smooth0": ("k_mg_tile<2,16>", 3, True, True),      # read x, r; write z
 }
 # on the tiled path counter 5 times the update fused with the finest-level
-# residual (counter 6 then stays empty): read r, q, x, p; write r', x, r' - A (w D^-1 r')
-MG_FUSED_UPDATE = ("k_mg_tile<6,16>", 7, True, True)
+# residual (counter 6 then stays empty): read r, q, x, p; write r', x, r' - A (w D^-1 r'),
+# and counter 7 the prolongation fused with the last sweep: read r, level 1's x
+# (1/8 vector), the whole stencil rows (16 doubles a node: 2x the stored form); write z
+MG_FUSED_UPDATE = ("k_mg_tile<6,16>", 7, 1, True)
+MG_FUSED_SMOOTH = ("k_mg_prolong_smooth", 2.125, 2, True)
 
 
 def mg_kernel(key, kst):
     """(rocprofv3 name, vectors, stencil, 1/a_ii) of profile counter `key`."""
-    if key == "K_mg_update" and kst["K_mg_resid0"]["launches"] == 0:
+    fused = kst["K_mg_resid0"]["launches"] == 0
+    if key == "K_mg_update" and fused:
         return MG_FUSED_UPDATE
+    if key == "K_mg_smooth0" and fused:
+        return MG_FUSED_SMOOTH
     return MG_KERNELS[key]
 
 
 def mg_algorithmic_bytes(key, N, layout, stat, kst):
     """Bytes one launch must move, summed over the measured launches."""
     _, vecs, op, diag = mg_kernel(key, kst)
-    per_launch = (N * layout["stencil_arrays"] * 8 if op else 0) + (N * 8 if diag else 0)
+    per_launch = N * layout["stencil_arrays"] * 8 * int(op) + (N * 8 if diag else 0)
     return stat["lanes"] * vecs * N * 8 + stat["launches"] * per_launch
 
 

@@ -196,7 +196,9 @@ qpat_status qpat_lsqr_step(qpat_ctx* ctx, double* resnorm_out, qpat_info* info);
  * 7 K finest-level last sweep (with the dot products); 8-11 the same for
  * M_delta. Where one kernel does the update and the finest-level residual
  * (the LDS-tiled path of 8 or 16 right-hand sides), 5 counts it and 6 stays
- * empty. qpat_profile(ctx, 1) clears the counters and starts, 0 stops. */
+ * empty; with 16 right-hand sides 7 then also covers the prolongation to the
+ * finest level, which that sweep's kernel forms on the fly.
+ * qpat_profile(ctx, 1) clears the counters and starts, 0 stops. */
 #define QPAT_NKSTAT 12
 typedef struct {
     int64_t launches;       /* launches that did work                                */

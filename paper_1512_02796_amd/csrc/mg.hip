@@ -34,7 +34,7 @@ struct MgLevel {
     int32_t nx = 0, ny = 0, nz = 0;
     int64_t N = 0;
     int32_t m = 0;                 // stored upper offsets
-    int32_t kind = 0;              // row kernel: 0 generic table, 1 Kuhn offsets, 2 full 27-point, 3 whole Kuhn rows (Uf)
+    int32_t kind = 0;              // row kernel: 0 generic table, 1 Kuhn offsets, 2 27-point, 3 whole Kuhn rows, 4 whole 27-point rows (Uf)
     const int4* tab = nullptr;     // [m]: dx, dy, dz, dx + nx (dy + ny dz)
     int4* tab_own = nullptr;
     double* U = nullptr;           // [nsys][N][m+1] (level 0: the context's stencil arrays)
@@ -59,6 +59,9 @@ struct TileGeo {
     int32_t tiles_x = 0, tiles_y = 0, zc = 0, items = 0, blocks = 0;
     // the tiled restriction to level 1 (coarse tiles, coarse z-chunk, blocks)
     int32_t rtiles_x = 0, rtiles_y = 0, rzc = 0, ritems = 0, rblocks = 0;
+    // the fused prolongation + last sweep (16 right-hand sides; even z-chunks)
+    bool ps_on = false;
+    int32_t ps_zc = 0, ps_items = 0, ps_blocks = 0;
     // the tiled 27-point kernels of the coarse levels (16 right-hand sides)
     struct Lv27 {
         bool on = false;
@@ -228,6 +231,7 @@ constexpr int kFullRow = 16;
 template <int KIND>
 __device__ __forceinline__ const double* rows_of(const LvArgs& L, int sys) {
     if constexpr (KIND == 3) return L.Uf + (int64_t)sys * L.N * kFullRow;
+    if constexpr (KIND == 4) return L.Uf + (int64_t)sys * L.N * 27;
     return L.U + (int64_t)sys * L.N * (L.m + 1);
 }
 
@@ -247,6 +251,20 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
                 s += U[i * M1 + j + 1] * vld<T>(x + (i + t.w) * B);
             if (ix - t.x >= 0 && ix - t.x < L.nx && iy - t.y >= 0 && iy - t.y < L.ny && iz - t.z >= 0)
                 s += U[(i - t.w) * M1 + j + 1] * vld<T>(x + (i - t.w) * B);
+        }
+        return s;
+    } else if constexpr (KIND == 4) {   // 27-point whole rows, entry-major ([27][N])
+        const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
+        T s = U[i] * vld<T>(x + i * B);
+#pragma unroll
+        for (int j = 0; j < 13; ++j) {
+            const int code = 14 + j;
+            const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
+            const int32_t lin = dx + L.nx * (dy + L.ny * dz);
+            const bool up = inner || (ix + dx >= 0 && ix + dx < L.nx && iy + dy >= 0 && iy + dy < L.ny && iz + dz < L.nz);
+            const bool lo = inner || (ix - dx >= 0 && ix - dx < L.nx && iy - dy >= 0 && iy - dy < L.ny && iz - dz >= 0);
+            if (up) s += U[(1 + j) * L.N + i] * vld<T>(x + (i + lin) * B);
+            if (lo) s += U[(14 + j) * L.N + i] * vld<T>(x + (i - lin) * B);
         }
         return s;
     } else if constexpr (KIND == 3) {
@@ -381,7 +399,9 @@ __device__ __forceinline__ void put_sums(double* parts, int sys, int slot, TB<B>
 }
 
 // whole Kuhn rows (diagonal, upper entries, lower entries gathered from the
-// partner rows, zero where the partner is off the lattice) for the row kind 3
+// partner rows, zero where the partner is off the lattice): entry-major for
+// the row kind 3 (ENTRY), node-major [N][kFullRow] for the 16-lane kernels
+template <bool ENTRY>
 __global__ __launch_bounds__(kMgT) void k_mg_fullrows(LvArgs L, double* __restrict__ Uf) {
     const int sys = blockIdx.y;
     constexpr int M1 = 8;
@@ -403,7 +423,12 @@ __global__ __launch_bounds__(kMgT) void k_mg_fullrows(LvArgs L, double* __restri
         }
         u[15] = 0.0;
 #pragma unroll
-        for (int k = 0; k < kFullRow; ++k) F[k * L.N + i] = u[k];
+        for (int k = 0; k < kFullRow; ++k) {
+            if constexpr (ENTRY)
+                F[k * L.N + i] = u[k];
+            else
+                F[i * kFullRow + k] = u[k];
+        }
     }
 }
 
@@ -1788,26 +1813,30 @@ constexpr int kRow27 = 32;
 constexpr int64_t kTile27Min = 16384;   // smaller levels keep the walk kernels (launch-bound anyway)
 enum Tile27Mode { kT27Resid = 0, kT27Smooth = 1 };
 
+// ENTRY: entry-major [27][N] per system (the one-right-hand-side walk
+// kernels, row kind 4) instead of node-major [N][kRow27]
+template <bool ENTRY>
 __global__ __launch_bounds__(kMgT) void k_mg_fullrows27(LvArgs L, double* __restrict__ Uf) {
     const int sys = blockIdx.y;
     constexpr int M1 = 14;
     const double* U = L.U + (int64_t)sys * L.N * M1;
-    double* F = Uf + (int64_t)sys * L.N * kRow27;
+    double* F = Uf + (int64_t)sys * L.N * (ENTRY ? 27 : kRow27);
     for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * kMgT) {
         int ix, iy, iz;
         coords(static_cast<int32_t>(i), L.nx, L.ny, ix, iy, iz);
-        double* o = F + i * kRow27;
-        o[0] = U[i * M1];
+        auto o = [&](int e) -> double& { return ENTRY ? F[e * L.N + i] : F[i * kRow27 + e]; };
+        o(0) = U[i * M1];
         for (int j = 0; j < 13; ++j) {
             const int code = 14 + j;
             const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
             const int64_t lin = dx + (int64_t)L.nx * (dy + (int64_t)L.ny * dz);
             const bool up = ix + dx >= 0 && ix + dx < L.nx && iy + dy >= 0 && iy + dy < L.ny && iz + dz < L.nz;
             const bool lo = ix - dx >= 0 && ix - dx < L.nx && iy - dy >= 0 && iy - dy < L.ny && iz - dz >= 0;
-            o[1 + j] = up ? U[i * M1 + 1 + j] : 0.0;
-            o[14 + j] = lo ? U[(i - lin) * M1 + 1 + j] : 0.0;
+            o(1 + j) = up ? U[i * M1 + 1 + j] : 0.0;
+            o(14 + j) = lo ? U[(i - lin) * M1 + 1 + j] : 0.0;
         }
-        for (int j = 27; j < kRow27; ++j) o[j] = 0.0;
+        if constexpr (!ENTRY)
+            for (int j = 27; j < kRow27; ++j) o(j) = 0.0;
     }
 }
 
@@ -1978,6 +2007,245 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
     }
 }
 
+// ------------------------------------------------ fused prolongation + last sweep
+// The finest level of the K hierarchy with 16 right-hand sides: the staged
+// vector of the last sweep is the prolonged correction itself,
+// x0 = w D^{-1} r + P x1 (the first sweep recomputed, P trilinear), formed
+// plane by plane in LDS from r, 1/a_ii and the coarse planes of the tile's
+// support (a 7 x 6 patch of level 1, two coarse planes in LDS), so x0 never
+// goes to memory. Then z = x0 + w D^{-1} (r - A x0) with the partial sums
+// r.z, sum z, sum r. The stencil rows come whole ([N][16], lane k holds entry
+// k) and reach the node's lanes by DPP row broadcasts, which keeps the LDS
+// at two blocks per CU. Chunks start on even planes (even zc).
+constexpr int kPCX = (kTHX - 2) / 2 + 2, kPCY = (kTHY - 2) / 2 + 2;   // coarse patch of a tile
+constexpr int kPCN = kPCX * kPCY * 16;                                // its values per coarse plane
+struct PSArgs {
+    int32_t nx, ny, nz, cx, cy, cz;
+    int32_t tiles_x, tiles_y, zc, items;
+    const double* Uf;     // [N][16] whole Kuhn rows
+    const double* r;      // [N][16] the PCG residual (level 0's b)
+    const double* xc;     // [Nc][16] level 1's solution
+    const double* dinv;   // [N]
+    const double* w;      // level 0's Jacobi weight
+    double* z;            // [N][16]
+    double* parts;
+    const MgScal* sc;
+};
+
+template <int J>
+__device__ __forceinline__ double kuhn_pair(double ua, const double* rb, int sz, int sp, int sl) {
+    constexpr int d = (kKy[J] * kTHX + kKx[J]) * 16;
+    const int up = kKz[J] ? sp : sz, lo = kKz[J] ? sl : sz;
+    return row_bcast<1 + J>(ua) * rb[up + d] + row_bcast<8 + J>(ua) * rb[lo - d];
+}
+template <int... J>
+__device__ __forceinline__ double apply_kuhn16(double ua, const double* rb, int sz, int sp, int sl,
+                                               std::integer_sequence<int, J...>) {
+    double s = row_bcast<0>(ua) * rb[sz];
+    ((s += kuhn_pair<J>(ua, rb, sz, sp, sl)), ...);
+    return s;
+}
+
+__global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
+    constexpr int B = 16;
+    constexpr int NPF = MgTile<B>::NPF, RS = NPF * kTT;
+    constexpr int TX = kTHX - 2, TY = kTHY - 2;
+    constexpr int NO = (TX * TY * B + kTT - 1) / kTT;
+    constexpr int NC = (kPCN + kTT - 1) / kTT;   // coarse patch values per thread
+    constexpr uint32_t SZ = sizeof(double);
+    extern __shared__ __align__(16) unsigned char mg_smem[];
+    __shared__ double sm[(kTT / 64) * 16];
+    double* ring = reinterpret_cast<double*>(mg_smem);   // [3][RS]: x0 of the halo nodes, [node][16]
+    double* dring = ring + 3 * RS;                        // [3][kTHN]: 1 / a_ii of the halo nodes
+    double* cring = dring + 3 * kTHN;                     // [2][kPCN]: coarse planes, slot Z & 1
+    const int tid = threadIdx.x, k = tid % B;
+    bool any = false;
+    for (int j = 0; j < B; ++j) any = any || g.sc[j].active != 0;
+    if (!any) return;
+    const bool act = g.sc[k].active != 0;
+    const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
+    const uint32_t nxy = static_cast<uint32_t>(nx) * ny, cxy = static_cast<uint32_t>(g.cx) * g.cy;
+    const uint32_t pv = nxy * B * SZ, pd = nxy * SZ, pc = cxy * B * SZ;
+    const double w = *g.w;
+    auto plane = [&](const double* base, int pl, int n, uint32_t stride, uint32_t bytes) {
+        const bool in = pl >= 0 && pl < n;
+        return rsrc(base + (in ? (int64_t)pl * stride : 0), in ? bytes : 0u);
+    };
+    int32_t oc[NO];
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {
+        const int nl = (tid + u * kTT) / B;
+        oc[u] = nl < TX * TY ? (nl / TX + 1) * kTHX + nl % TX + 1 : kTHX + 1;
+    }
+    double fr[NPF], dd = 0.0, cv[NC];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    const int32_t xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
+    const int32_t wx = (g.items + 7) / 8;
+    const int32_t it_end = min(g.items, (xcd + 1) * wx);
+    const int32_t tiles = g.tiles_x * g.tiles_y;
+    for (int32_t item = xcd * wx + slot; item < it_end; item += per) {
+        const int32_t ch = item / tiles, t2 = item % tiles;
+        const int32_t x0 = (t2 % g.tiles_x) * TX, y0 = (t2 / g.tiles_x) * TY;
+        const int32_t zb = ch * g.zc, ze = min(zb + g.zc, nz);   // zb even
+        const int32_t cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1;        // the patch's first coarse column, row
+        uint32_t fo[NPF], oo[NO], dof = kOut, co[NC];
+#pragma unroll
+        for (int u = 0; u < NPF; ++u) {
+            const int nl = (tid + u * kTT) / B;
+            const int gx = x0 - 1 + nl % kTHX, gy = y0 - 1 + nl / kTHX;
+            const bool fin = nl < kTHN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            fo[u] = fin ? (static_cast<uint32_t>(gy * nx + gx) * B + k) * SZ : kOut;
+        }
+#pragma unroll
+        for (int u = 0; u < NO; ++u) {
+            const int nl = (tid + u * kTT) / B;
+            const int ox = x0 + nl % TX, oy = y0 + nl / TX;
+            oo[u] = nl < TX * TY && ox < nx && oy < ny ? (static_cast<uint32_t>(oy * nx + ox) * B + k) * SZ : kOut;
+        }
+        if (tid < kTHN) {
+            const int gx = x0 - 1 + tid % kTHX, gy = y0 - 1 + tid / kTHX;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) dof = static_cast<uint32_t>(gy * nx + gx) * SZ;
+        }
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+            const int e = tid + u * kTT, cn = e / B;
+            const int X = cx0 + cn % kPCX, Y = cy0 + cn / kPCX;
+            co[u] = e < kPCN && X >= 0 && X < g.cx && Y >= 0 && Y < g.cy
+                        ? (static_cast<uint32_t>(Y * g.cx + X) * B + (e % B)) * SZ : kOut;
+        }
+        // fine plane p: r and 1/a_ii; odd p also the coarse plane (p + 1) / 2
+        auto fetch = [&](int pl) {
+            const auto br = plane(g.r, pl, nz, nxy * B, pv), bd = plane(g.dinv, pl, nz, nxy, pd);
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) fr[u] = bload<double>(br, fo[u]);
+            dd = bload<double>(bd, dof);
+            if (pl & 1) {
+                const auto bc = plane(g.xc, (pl + 1) / 2, g.cz, cxy * B, pc);
+#pragma unroll
+                for (int u = 0; u < NC; ++u) cv[u] = bload<double>(bc, co[u]);
+            }
+        };
+        auto load_coarse = [&](int Z) {
+            const auto bc = plane(g.xc, Z, g.cz, cxy * B, pc);
+#pragma unroll
+            for (int u = 0; u < NC; ++u) cv[u] = bload<double>(bc, co[u]);
+        };
+        auto put_coarse = [&](int Z) {   // coarse plane Z to its slot
+#pragma unroll
+            for (int u = 0; u < NC; ++u)
+                if (tid + u * kTT < kPCN) cring[(Z & 1) * kPCN + tid + u * kTT] = cv[u];
+        };
+        auto put_d = [&](int sl) {
+            if (tid < kTHN) dring[sl * kTHN + tid] = dd;
+        };
+        // x0 of fine plane pl into ring slot sl (its 1/a_ii already in dring[sl])
+        auto store = [&](int sl, int pl) {
+            const bool pin = pl >= 0 && pl < nz;
+            const int z0 = pl >> 1, z1 = (pl + 1) >> 1;
+            const double wz1 = (pl & 1) ? 0.5 : 0.0, wz0 = 1.0 - wz1;
+            const double* c0 = cring + (z0 & 1) * kPCN + k;
+            const double* c1 = cring + (z1 & 1) * kPCN + k;
+            // two passes over the thread's own elements (no barrier between them):
+            // w D^{-1} r from the registers, then P x1 added in a rolled loop that
+            // keeps one element's coarse reads live at a time
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) {
+                const int nl = (tid + u * kTT) / B;
+                ring[sl * RS + tid + u * kTT] = pin && fo[u] != kOut ? w * dring[sl * kTHN + nl] * fr[u] : 0.0;
+            }
+            if (!pin) return;
+#pragma unroll 1
+            for (int u = 0; u < NPF; ++u) {
+                const int nl = (tid + u * kTT) / B;
+                const int gx = x0 - 1 + nl % kTHX, gy = y0 - 1 + nl / kTHX;
+                if (nl >= kTHN || gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
+                const int o = (((gy >> 1) - cy0) * kPCX + (gx >> 1) - cx0) * B;
+                const int dx = (gx & 1) ? B : 0, dy = (gy & 1) ? kPCX * B : 0;
+                const double wx1 = dx ? 0.5 : 0.0, wx0 = 1.0 - wx1;
+                const double wy1 = dy ? 0.5 : 0.0, wy0 = 1.0 - wy1;
+                auto bil = [&](const double* cp) {
+                    const double* q = cp + o;
+                    return wy0 * (wx0 * q[0] + wx1 * q[dx]) + wy1 * (wx0 * q[dy] + wx1 * q[dy + dx]);
+                };
+                ring[sl * RS + tid + u * kTT] += wz0 * bil(c0) + wz1 * bil(c1);
+            }
+        };
+        auto step = [&](int z, auto SZ0, auto SP0, auto SL0) {
+            constexpr int sz = decltype(SZ0)::value, sp = decltype(SP0)::value, sl = decltype(SL0)::value;
+            store(sp, z + 1);
+            __syncthreads();
+            if (z + 1 < ze) fetch(z + 2);
+            double bc[NO], ua[NO];   // b = r of this plane's nodes (read as halo: L2), their rows
+            const auto bu = plane(g.Uf, z, nz, nxy * B, pv), bb = plane(g.r, z, nz, nxy * B, pv);
+#pragma unroll
+            for (int u = 0; u < NO; ++u) {
+                bc[u] = bload<double>(bb, oo[u]);
+                ua[u] = bload<double>(bu, oo[u]);
+            }
+            const auto bo = plane(g.z, z, nz, nxy * B, pv);
+#pragma unroll
+            for (int u = 0; u < NO; ++u) {
+                if (tid + u * kTT >= TX * TY * B) continue;   // whole waves past the tile skip
+                const double* rb = ring + oc[u] * B + k;
+                const double ax = apply_kuhn16(ua[u], rb, sz * RS, sp * RS, sl * RS, std::make_integer_sequence<int, 7>{});
+                const double xc = rb[sz * RS];
+                const double o = xc + w * dring[sz * kTHN + oc[u]] * (bc[u] - ax);
+                const bool in = act && oo[u] != kOut;
+                a0 += in ? bc[u] * o : 0.0;
+                a1 += in ? o : 0.0;
+                a2 += in ? bc[u] : 0.0;
+                bstore<double>(bo, act ? oo[u] : kOut, o);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (z + 1 < ze) {   // plane z + 2's 1/a_ii (slot sl) and, odd, coarse plane (z + 3) / 2
+                put_d(sl);
+                if ((z + 2) & 1) put_coarse((z + 3) / 2);
+            }
+            __syncthreads();
+        };
+        load_coarse(zb / 2 - 1);   // staging plane zb - 1 needs coarse planes zb/2 - 1 and zb/2
+        put_coarse(zb / 2 - 1);
+        fetch(zb - 1);             // odd: also coarse plane zb / 2
+        put_d(0);
+        put_coarse(zb / 2);
+        __syncthreads();
+        store(0, zb - 1);
+        fetch(zb);
+        put_d(1);
+        __syncthreads();
+        store(1, zb);
+        fetch(zb + 1);             // odd: coarse plane zb / 2 + 1
+        put_d(2);
+        put_coarse(zb / 2 + 1);    // slot of zb/2 - 1, whose last use (plane zb - 1) is staged
+        __syncthreads();
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        for (int z = zb; z < ze; z += 3) {   // plane z - zb + 1 lives in slot (z - zb + 1) % 3
+            step(z, I1{}, I2{}, I0{});
+            if (z + 1 < ze) step(z + 1, I2{}, I0{}, I1{});
+            if (z + 2 < ze) step(z + 2, I0{}, I1{}, I2{});
+        }
+    }
+    auto out_sum = [&](double v, int slot_) {
+#pragma unroll
+        for (int off = 32; off >= B; off >>= 1) v += __shfl_xor(v, off);
+        const int lane = tid & 63, wave = tid >> 6;
+        if (lane < B) sm[wave * B + lane] = v;
+        __syncthreads();
+        if (tid < B) {
+            double t = 0.0;
+            for (int wv = 0; wv < kTT / 64; ++wv) t += sm[wv * B + tid];
+            put(g.parts, tid, slot_, t);
+        }
+        __syncthreads();
+    };
+    out_sum(a0, 0);
+    out_sum(a1, 2);
+    out_sum(a2, 3);
+}
+constexpr size_t kPSLds = (size_t)(3 * MgTile<16>::NPF * kTT + 3 * kTHN + 2 * kPCN) * sizeof(double);
+
 inline LvArgs lv_args(const MgLevel& L) {
     LvArgs a;
     a.U = L.U;
@@ -2000,6 +2268,9 @@ inline dim3 vgrid(int64_t n, int cap = kMgGrid) { return dim3((grid_for(n, kMgT,
         case 1: hipLaunchKernelGGL((KERNEL<1, B>), __VA_ARGS__); break;     \
         case 2: hipLaunchKernelGGL((KERNEL<2, B>), __VA_ARGS__); break;     \
         case 3: hipLaunchKernelGGL((KERNEL<3, B>), __VA_ARGS__); break;     \
+        case 4:                                                             \
+            if constexpr (B == 1) hipLaunchKernelGGL((KERNEL<4, 1>), __VA_ARGS__); \
+            break;                                                          \
         default: hipLaunchKernelGGL((KERNEL<0, B>), __VA_ARGS__); break;    \
     }
 
@@ -2050,6 +2321,9 @@ void launch_smooth(int kind, dim3 g, hipStream_t st, const SmArgs& a, const doub
         case 1: hipLaunchKernelGGL((k_mg_smooth<1, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
         case 2: hipLaunchKernelGGL((k_mg_smooth<2, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
         case 3: hipLaunchKernelGGL((k_mg_smooth<3, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
+        case 4:
+            if constexpr (B == 1) hipLaunchKernelGGL((k_mg_smooth<4, 1, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts);
+            break;
         default: hipLaunchKernelGGL((k_mg_smooth<0, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
     }
 }
@@ -2118,6 +2392,32 @@ void launch_tile27(const MgState& M, const TileGeo& t, int l, hipStream_t st, co
                        st, g);
 }
 inline bool tiled27(const TileGeo& t, int l) { return l >= 1 && l < kMgMaxLevels && t.t27[l].on; }
+
+// level 0: z = x0 + w D^{-1} (r - A x0), x0 = w D^{-1} r + P x1 (fused, 16 right-hand sides)
+inline void launch_ps(const MgState& M, const TileGeo& t, hipStream_t st, const double* r, const double* x1, double* z) {
+    const MgLevel& L = M.lv[0];
+    const MgLevel& C = M.lv[1];
+    PSArgs g;
+    g.nx = L.nx;
+    g.ny = L.ny;
+    g.nz = L.nz;
+    g.cx = C.nx;
+    g.cy = C.ny;
+    g.cz = C.nz;
+    g.tiles_x = t.tiles_x;
+    g.tiles_y = t.tiles_y;
+    g.zc = t.ps_zc;
+    g.items = t.ps_items;
+    g.Uf = L.Uf;
+    g.r = r;
+    g.xc = x1;
+    g.dinv = L.dinv;
+    g.w = M.w;   // system 0, level 0
+    g.z = z;
+    g.parts = M.parts;
+    g.sc = M.sc;
+    hipLaunchKernelGGL(k_mg_prolong_smooth, dim3(t.ps_blocks), dim3(kTT), kPSLds, st, g);
+}
 
 // level 0's residual to level 1's b and first sweep xc (tiled; trilinear)
 template <int B>
@@ -2213,6 +2513,30 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
         t.rzc = static_cast<int32_t>(rzc);
         t.ritems = static_cast<int32_t>(rtx * rty * ((C.nz + rzc - 1) / rzc));
         t.rblocks = static_cast<int32_t>(8 * std::min<int64_t>(rconc, (t.ritems + 7) / 8));
+        if constexpr (B == 16) {   // the fused prolongation + last sweep: the same tiles, even chunks
+            if (L.Uf) {
+                const void* fps = reinterpret_cast<const void*>(&k_mg_prolong_smooth);
+                QPAT_HIP(c, hipFuncSetAttribute(fps, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPSLds));
+                int occ_ps = 1;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_ps, fps, kTT, kPSLds) != hipSuccess) occ_ps = 1;
+                const int64_t conc_ps = (int64_t)std::max(occ_ps, 1) * (cus / 8);
+                int64_t best_ps = -1, zc_ps = L.nz + (L.nz & 1);
+                for (int64_t nch = 1; nch <= L.nz; ++nch) {
+                    int64_t zc = (L.nz + nch - 1) / nch;
+                    zc += zc & 1;
+                    const int64_t items = tx * ty * ((L.nz + zc - 1) / zc);
+                    const int64_t cost = (((items + 7) / 8 + conc_ps - 1) / conc_ps) * (zc + 2);
+                    if (best_ps < 0 || cost < best_ps) {
+                        best_ps = cost;
+                        zc_ps = zc;
+                    }
+                }
+                t.ps_zc = static_cast<int32_t>(zc_ps);
+                t.ps_items = static_cast<int32_t>(tx * ty * ((L.nz + zc_ps - 1) / zc_ps));
+                t.ps_blocks = static_cast<int32_t>(8 * std::min<int64_t>(conc_ps, (t.ps_items + 7) / 8));
+                t.ps_on = true;
+            }
+        }
         if constexpr (B == 16) {   // the coarse levels' 27-point kernels
             const void* f27[2] = {reinterpret_cast<const void*>(&k_mg_tile27<kT27Resid>),
                                   reinterpret_cast<const void*>(&k_mg_tile27<kT27Smooth>)};
@@ -2320,6 +2644,13 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         const SmArgs a = sm(l);
         const dim3 g = sgrid<B>(L.N);
         const double* bl = l == 0 ? r0 : L.b;
+        if (l == 0 && B == 16 && fused0 && tg.ps_on && !M.opdep) {   // prolongation fused into the last sweep
+            if (ev) (void)hipEventRecord(ev[2], st);
+            launch_ps(M, tg, st, r0, xl[1], tl[0]);
+            if (ev) (void)hipEventRecord(ev[3], st);
+            std::swap(xl[0], tl[0]);
+            continue;
+        }
         if (l == 0 && fused0 && M.opdep)
             hipLaunchKernelGGL((k_mg_prolong<B, true, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], r0,
                                xl[0], L.W);
@@ -2781,9 +3112,14 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             QPAT_TRY(dalloc(c, &L.r, V * L.N));
             if (op == Op::Prior && l + 1 < nl) QPAT_TRY(dalloc(c, &L.W, nsys * L.N * 8));
             if (op == Op::Prior && l == 0 && L.kind == 1) QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kFullRow));
+            if (op == Op::K && l == 0 && L.kind == 1 && M.bmax == 16 && nl > 1 &&
+                L.N * kFullRow * (int64_t)sizeof(double) < (int64_t(1) << 31))   // node-major, for k_mg_prolong_smooth
+                QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kFullRow));
             if (op == Op::K && l >= 1 && l < kMgMaxLevels && M.bmax == 16 && M.lv[0].kind == 1 &&
                 L.N >= kTile27Min && L.N * kRow27 * (int64_t)sizeof(double) < (int64_t(1) << 31))
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kRow27));
+            if (op == Op::Prior && l >= 1 && l + 1 < nl && L.N >= kTile27Min)   // entry-major rows (kind 4)
+                QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * 27));
         }
         QPAT_TRY(dalloc(c, &M.w, nsys * nl));
         QPAT_TRY(dalloc(c, &M.gmax, nsys * nl));
@@ -2803,10 +3139,14 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     const int nl = static_cast<int>(M.lv.size());
     M.lv[0].U = op == Op::K ? c->KU64 : c->MU64;
     M.opdep = op == Op::Prior;
-    if (M.lv[0].Uf) {   // the one-right-hand-side walk kernels read whole rows
+    if (M.lv[0].Uf) {   // whole rows: M_delta's walk kernels, K's fused prolongation + sweep
         M.lv[0].kind = 1;
-        hipLaunchKernelGGL(k_mg_fullrows, dim3(grid_for(M.lv[0].N, kMgT, 4096), nsys), dim3(kMgT), 0, c->stream,
-                           lv_args(M.lv[0]), M.lv[0].Uf);
+        if (op == Op::K)
+            hipLaunchKernelGGL(k_mg_fullrows<false>, dim3(grid_for(M.lv[0].N, kMgT, 4096), nsys), dim3(kMgT), 0,
+                               c->stream, lv_args(M.lv[0]), M.lv[0].Uf);
+        else
+            hipLaunchKernelGGL(k_mg_fullrows<true>, dim3(grid_for(M.lv[0].N, kMgT, 4096), nsys), dim3(kMgT), 0,
+                               c->stream, lv_args(M.lv[0]), M.lv[0].Uf);
     }
     for (int l = 0; l + 1 < nl; ++l) {
         const MgLevel& F = M.lv[l];
@@ -2822,8 +3162,11 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
                            lv_args(F), M.opdep ? F.W : nullptr, C.U, C.nx, C.ny, C.nz);
     }
     for (int l = 1; l < nl; ++l)
-        if (M.lv[l].Uf)
-            hipLaunchKernelGGL(k_mg_fullrows27, dim3(grid_for(M.lv[l].N, kMgT, 4096), nsys), dim3(kMgT), 0,
+        if (M.lv[l].Uf && op == Op::K)
+            hipLaunchKernelGGL(k_mg_fullrows27<false>, dim3(grid_for(M.lv[l].N, kMgT, 4096), nsys), dim3(kMgT), 0,
+                               c->stream, lv_args(M.lv[l]), M.lv[l].Uf);
+        else if (M.lv[l].Uf)
+            hipLaunchKernelGGL(k_mg_fullrows27<true>, dim3(grid_for(M.lv[l].N, kMgT, 4096), nsys), dim3(kMgT), 0,
                                c->stream, lv_args(M.lv[l]), M.lv[l].Uf);
     QPAT_HIP(c, hipMemsetAsync(M.gmax, 0, nsys * nl * sizeof(uint64_t), c->stream));
     for (int l = 0; l < nl; ++l)
@@ -2869,7 +3212,9 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     QPAT_HIP(c, hipMemcpyAsync(M.ainv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
     if (op == Op::Prior) QPAT_TRY(region_setup(c, M));
-    if (M.lv[0].Uf) M.lv[0].kind = 3;
+    if (M.lv[0].Uf && op == Op::Prior) M.lv[0].kind = 3;
+    for (int l = 1; op == Op::Prior && l < nl; ++l)
+        if (M.lv[l].Uf) M.lv[l].kind = 4;
     M.current = true;
     return QPAT_OK;
 }
