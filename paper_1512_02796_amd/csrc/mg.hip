@@ -1407,9 +1407,10 @@ struct TileArgs {
 // kTApply: out = scale A in for every right-hand side (any Kuhn stencil
 //   form U, e.g. the derivative of K in the Jacobian product).
 // kTUpdResid: the PCG update fused with kTResidFirst: r' = in - alpha in2
-//   (in = r, in2 = q = A p) to out2, x3 += alpha p3, partial r'.r', and the
-//   first sweep x = w D^{-1} r' staged, out = r' - A x. r' goes to another
-//   buffer than r: neighbouring tiles still read r's halo.
+//   (in = r, in2 = q = A p) staged, to out2, x3 += alpha p3, partial r'.r',
+//   and out = r' - A x with the first sweep x = w D^{-1} r' (w / a_jj from
+//   LDS per neighbour). r' goes to another buffer than r: neighbouring tiles
+//   still read r's halo.
 template <int MODE, int B>
 __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
     using TL = MgTile<B>;
@@ -1425,7 +1426,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
     __shared__ double sm[(kTT / 64) * 16];
     double* ring = reinterpret_cast<double*>(mg_smem);   // [3][RS]: [halo node][B]
     double* ust = ring + 3 * RS;                          // [3][US]: [halo node][8]
-    double* dring = ust + 3 * US;                         // UPD: [3][kTHN] 1 / a_ii of the halo nodes
+    double* dring = ust + 3 * US;                         // UPD: [3][kTHN] w / a_ii of the halo nodes
     const int tid = threadIdx.x, k = tid % B;
     constexpr bool ALL = MODE == kTTrue || MODE == kTApply;   // every right-hand side, no PCG scalars
     if constexpr (!ALL) {   // every right-hand side stopped: nothing to do
@@ -1529,7 +1530,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                 double val = fr[u];
                 if constexpr (MODE == kTDirSpmv) val = fo[u] != kOut ? fr[u] - cc_ + beta * f2[u] : 0.0;
                 if constexpr (MODE == kTResidFirst) val = w * f2[u] * fr[u];
-                if constexpr (UPD) val = w * dring[sl * kTHN + (tid + u * kTT) / B] * (fr[u] - alpha * f2[u]);
+                if constexpr (UPD) val = fr[u] - alpha * f2[u];   // r' itself: the sweep scales it per neighbour
                 ring[sl * RS + tid + u * kTT] = val;
             }
 #pragma unroll
@@ -1556,15 +1557,6 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                 for (int u = 0; u < NPF; ++u) dc[u] = bload<double>(bd, od[u]);
             }
             constexpr int NO = UPD ? (TX * TY * B + kTT - 1) / kTT : 1;   // output slots in use
-            double qc[NO];
-            if constexpr (UPD) {   // r and q of this plane's nodes (read as halo two steps ago: L2)
-                const auto br = plane(g.in, z, nxy * B, pv), bq = plane(g.in2, z, nxy * B, pv);
-#pragma unroll
-                for (int u = 0; u < NO; ++u) {
-                    bc[u] = bload<double>(br, oo[u]);
-                    qc[u] = bload<double>(bq, oo[u]);
-                }
-            }
             // descriptors stay uniform over the wavefront (a per-lane size would
             // turn every access into a loop over the distinct values); the
             // stores of stopped right-hand sides are skipped by the branch
@@ -1592,6 +1584,16 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                             rc.sub(ub[lo * US + (cc - d) * M1 + j + 1], rb[lo * RS + (cc - d) * B]);
                         }
                         rtrue = rc.value();
+                    } else if constexpr (UPD) {   // A (w D^{-1} r'): each neighbour scaled by its w / a_jj
+                        const double* db = dring + (oc[u] - kTHX - 1);
+                        sum = ub[sz * US + cc * M1] * (db[sz * kTHN + cc] * xc);
+#pragma unroll
+                        for (int j = 0; j < 7; ++j) {
+                            const int d = kKy[j] * kTHX + kKx[j];
+                            const int up = kKz[j] ? sp : sz, lo = kKz[j] ? sl : sz;
+                            sum += ub[sz * US + cc * M1 + j + 1] * (db[up * kTHN + cc + d] * rb[up * RS + (cc + d) * B]) +
+                                   ub[lo * US + (cc - d) * M1 + j + 1] * (db[lo * kTHN + cc - d] * rb[lo * RS + (cc - d) * B]);
+                        }
                     } else {
                         sum = ub[sz * US + cc * M1] * xc;
 #pragma unroll
@@ -1611,7 +1613,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                     } else if constexpr (MODE == kTApply) {
                         o = g.scale * sum;
                     } else if constexpr (UPD) {
-                        const double rnew = bc[u] - alpha * qc[u];
+                        const double rnew = xc;   // the staged r' of the node
                         o = rnew - sum;
                         a1 += in ? rnew * rnew : 0.0;
                         bstore<double>(bo2, oo[u], rnew);
@@ -1636,12 +1638,12 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                     }
                 }
             }
-            if (UPD && tid < kTHN && z + 1 < ze) dring[sl * kTHN + tid] = dd;   // plane z + 2 lives in slot sl
+            if (UPD && tid < kTHN && z + 1 < ze) dring[sl * kTHN + tid] = w * dd;   // plane z + 2 lives in slot sl
             __syncthreads();
         };
         auto put_d = [&](int sl) {
             if constexpr (UPD) {
-                if (tid < kTHN) dring[sl * kTHN + tid] = dd;
+                if (tid < kTHN) dring[sl * kTHN + tid] = w * dd;
                 __syncthreads();
             }
         };
@@ -1811,6 +1813,7 @@ __global__ __launch_bounds__(kTT) void k_mg_restrict_tile(RstArgs g) {
 // LDS and the partner rows are never gathered.
 constexpr int kRow27 = 32;
 constexpr int64_t kTile27Min = 16384;   // smaller levels keep the walk kernels (launch-bound anyway)
+constexpr int64_t kRow27Min = 131072;   // M_delta: whole 27-point rows pay off from about this size on
 enum Tile27Mode { kT27Resid = 0, kT27Smooth = 1 };
 
 // ENTRY: entry-major [27][N] per system (the one-right-hand-side walk
@@ -3118,7 +3121,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             if (op == Op::K && l >= 1 && l < kMgMaxLevels && M.bmax == 16 && M.lv[0].kind == 1 &&
                 L.N >= kTile27Min && L.N * kRow27 * (int64_t)sizeof(double) < (int64_t(1) << 31))
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kRow27));
-            if (op == Op::Prior && l >= 1 && l + 1 < nl && L.N >= kTile27Min)   // entry-major rows (kind 4)
+            if (op == Op::Prior && l >= 1 && l + 1 < nl && L.N >= kRow27Min)   // entry-major rows (kind 4)
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * 27));
         }
         QPAT_TRY(dalloc(c, &M.w, nsys * nl));
