@@ -2051,7 +2051,7 @@ __device__ __forceinline__ double apply_kuhn16(double ua, const double* rb, int 
 
 __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
     constexpr int B = 16;
-    constexpr int NPF = MgTile<B>::NPF, RS = NPF * kTT;
+    constexpr int NPF = MgTile<B>::NPF, RS = kTHN * B;   // ring slot: exactly the halo tile
     constexpr int TX = kTHX - 2, TY = kTHY - 2;
     constexpr int NO = (TX * TY * B + kTT - 1) / kTT;
     constexpr int NC = (kPCN + kTT - 1) / kTT;   // coarse patch values per thread
@@ -2061,6 +2061,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
     double* ring = reinterpret_cast<double*>(mg_smem);   // [3][RS]: x0 of the halo nodes, [node][16]
     double* dring = ring + 3 * RS;                        // [3][kTHN]: 1 / a_ii of the halo nodes
     double* cring = dring + 3 * kTHN;                     // [2][kPCN]: coarse planes, slot Z & 1
+    double* rint = cring + 2 * kPCN;                      // [2][TX TY B]: r of the tile's own nodes, slot p & 1
     const int tid = threadIdx.x, k = tid % B;
     bool any = false;
     for (int j = 0; j < B; ++j) any = any || g.sc[j].active != 0;
@@ -2153,8 +2154,11 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
             // keeps one element's coarse reads live at a time
 #pragma unroll
             for (int u = 0; u < NPF; ++u) {
-                const int nl = (tid + u * kTT) / B;
-                ring[sl * RS + tid + u * kTT] = pin && fo[u] != kOut ? w * dring[sl * kTHN + nl] * fr[u] : 0.0;
+                const int e = tid + u * kTT, nl = e / B;
+                if (e >= RS) continue;
+                ring[sl * RS + e] = pin && fo[u] != kOut ? w * dring[sl * kTHN + nl] * fr[u] : 0.0;
+                const int lx = nl % kTHX - 1, ly = nl / kTHX - 1;   // the sweep's b: r of the tile's own nodes
+                if (lx >= 0 && lx < TX && ly >= 0 && ly < TY) rint[(pl & 1) * (TX * TY * B) + (ly * TX + lx) * B + k] = fr[u];
             }
             if (!pin) return;
 #pragma unroll 1
@@ -2178,13 +2182,10 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
             store(sp, z + 1);
             __syncthreads();
             if (z + 1 < ze) fetch(z + 2);
-            double bc[NO], ua[NO];   // b = r of this plane's nodes (read as halo: L2), their rows
-            const auto bu = plane(g.Uf, z, nz, nxy * B, pv), bb = plane(g.r, z, nz, nxy * B, pv);
+            double ua[NO];   // the rows of this plane's nodes
+            const auto bu = plane(g.Uf, z, nz, nxy * B, pv);
 #pragma unroll
-            for (int u = 0; u < NO; ++u) {
-                bc[u] = bload<double>(bb, oo[u]);
-                ua[u] = bload<double>(bu, oo[u]);
-            }
+            for (int u = 0; u < NO; ++u) ua[u] = bload<double>(bu, oo[u]);
             const auto bo = plane(g.z, z, nz, nxy * B, pv);
 #pragma unroll
             for (int u = 0; u < NO; ++u) {
@@ -2192,11 +2193,12 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
                 const double* rb = ring + oc[u] * B + k;
                 const double ax = apply_kuhn16(ua[u], rb, sz * RS, sp * RS, sl * RS, std::make_integer_sequence<int, 7>{});
                 const double xc = rb[sz * RS];
-                const double o = xc + w * dring[sz * kTHN + oc[u]] * (bc[u] - ax);
+                const double bcu = rint[(z & 1) * (TX * TY * B) + tid + u * kTT];
+                const double o = xc + w * dring[sz * kTHN + oc[u]] * (bcu - ax);
                 const bool in = act && oo[u] != kOut;
-                a0 += in ? bc[u] * o : 0.0;
+                a0 += in ? bcu * o : 0.0;
                 a1 += in ? o : 0.0;
-                a2 += in ? bc[u] : 0.0;
+                a2 += in ? bcu : 0.0;
                 bstore<double>(bo, act ? oo[u] : kOut, o);
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -2247,7 +2249,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
     out_sum(a1, 2);
     out_sum(a2, 3);
 }
-constexpr size_t kPSLds = (size_t)(3 * MgTile<16>::NPF * kTT + 3 * kTHN + 2 * kPCN) * sizeof(double);
+constexpr size_t kPSLds = (size_t)(3 * kTHN * 16 + 3 * kTHN + 2 * kPCN + 2 * (kTHX - 2) * (kTHY - 2) * 16) * sizeof(double);
 
 inline LvArgs lv_args(const MgLevel& L) {
     LvArgs a;
