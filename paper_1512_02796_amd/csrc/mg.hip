@@ -2179,13 +2179,13 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
         };
         auto step = [&](int z, auto SZ0, auto SP0, auto SL0) {
             constexpr int sz = decltype(SZ0)::value, sp = decltype(SP0)::value, sl = decltype(SL0)::value;
-            store(sp, z + 1);
-            __syncthreads();
-            if (z + 1 < ze) fetch(z + 2);
-            double ua[NO];   // the rows of this plane's nodes
+            double ua[NO];   // the rows of this plane's nodes: in flight during the staging
             const auto bu = plane(g.Uf, z, nz, nxy * B, pv);
 #pragma unroll
             for (int u = 0; u < NO; ++u) ua[u] = bload<double>(bu, oo[u]);
+            store(sp, z + 1);
+            __syncthreads();
+            if (z + 1 < ze) fetch(z + 2);
             const auto bo = plane(g.z, z, nz, nxy * B, pv);
 #pragma unroll
             for (int u = 0; u < NO; ++u) {
