@@ -57,8 +57,12 @@ constexpr int kMgMaxLevels = 12;   // levels with a tiled-kernel geometry (more 
 struct TileGeo {
     bool ready = false, on = false;
     int32_t tiles_x = 0, tiles_y = 0, zc = 0, items = 0, blocks = 0;
-    // the tiled restriction to level 1 (coarse tiles, coarse z-chunk, blocks)
-    int32_t rtiles_x = 0, rtiles_y = 0, rzc = 0, ritems = 0, rblocks = 0;
+    // the tiled restrictions, level l to l + 1 (coarse tiles, coarse z-chunk, blocks)
+    struct Rst {
+        bool on = false;
+        int32_t tx = 0, ty = 0, zc = 0, items = 0, blocks = 0;
+    };
+    Rst rst[kMgMaxLevels];
     // the fused prolongation + last sweep (16 right-hand sides; even z-chunks)
     bool ps_on = false;
     int32_t ps_zc = 0, ps_items = 0, ps_blocks = 0;
@@ -2424,12 +2428,13 @@ inline void launch_ps(const MgState& M, const TileGeo& t, hipStream_t st, const 
     hipLaunchKernelGGL(k_mg_prolong_smooth, dim3(t.ps_blocks), dim3(kTT), kPSLds, st, g);
 }
 
-// level 0's residual to level 1's b and first sweep xc (tiled; trilinear)
+// level l's residual to level l + 1's b and first sweep xc (tiled; trilinear)
 template <int B>
-void launch_restrict(const MgState& M, const TileGeo& t, hipStream_t st, double* xc) {
+void launch_restrict(const MgState& M, const TileGeo& t, int l, hipStream_t st, double* xc) {
     if constexpr (B >= 8) {
-        const MgLevel& L = M.lv[0];
-        const MgLevel& C = M.lv[1];
+        const MgLevel& L = M.lv[l];
+        const MgLevel& C = M.lv[l + 1];
+        const TileGeo::Rst& q = t.rst[l];
         RstArgs g;
         g.nx = L.nx;
         g.ny = L.ny;
@@ -2437,17 +2442,17 @@ void launch_restrict(const MgState& M, const TileGeo& t, hipStream_t st, double*
         g.cx = C.nx;
         g.cy = C.ny;
         g.cz = C.nz;
-        g.tiles_x = t.rtiles_x;
-        g.tiles_y = t.rtiles_y;
-        g.zc = t.rzc;
-        g.items = t.ritems;
+        g.tiles_x = q.tx;
+        g.tiles_y = q.ty;
+        g.zc = q.zc;
+        g.items = q.items;
         g.r = L.r;
         g.dinv = C.dinv;
-        g.w = M.w + 1;   // system 0, level 1
+        g.w = M.w + l + 1;   // system 0, level l + 1
         g.bc = C.b;
         g.xc = xc;
         g.sc = M.sc;
-        hipLaunchKernelGGL(k_mg_restrict_tile<B>, dim3(t.rblocks), dim3(kTT), MgRst<B>::LDS, st, g);
+        hipLaunchKernelGGL(k_mg_restrict_tile<B>, dim3(q.blocks), dim3(kTT), MgRst<B>::LDS, st, g);
     }
 }
 
@@ -2495,29 +2500,36 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
         t.items = static_cast<int32_t>(tx * ty * ((L.nz + best_zc - 1) / best_zc));
         t.blocks = static_cast<int32_t>(8 * std::min<int64_t>(conc, (t.items + 7) / 8));
         t.on = true;
-        // restriction to level 1: the same balance with (2 zc + 1) fine planes per item
+        // restrictions to levels 1, 2, ... (coarse level of at least kTile27Min nodes): the
+        // same balance with (2 zc + 1) fine planes per item
         const MgLevel& C = M.lv[1];
         const void* fr = reinterpret_cast<const void*>(&k_mg_restrict_tile<B>);
         QPAT_HIP(c, hipFuncSetAttribute(fr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MgRst<B>::LDS));
         int rocc = 1;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&rocc, fr, kTT, MgRst<B>::LDS) != hipSuccess) rocc = 1;
         const int64_t rconc = (int64_t)std::max(rocc, 1) * (cus / 8);
-        const int64_t rtx = (C.nx + kRX - 1) / kRX, rty = (C.ny + MgRst<B>::RY - 1) / MgRst<B>::RY;
-        int64_t rbest = -1, rzc = C.nz;
-        for (int64_t nch = 1; nch <= C.nz; ++nch) {
-            const int64_t zc = (C.nz + nch - 1) / nch;
-            const int64_t items = rtx * rty * ((C.nz + zc - 1) / zc);
-            const int64_t cost = (((items + 7) / 8 + rconc - 1) / rconc) * (2 * zc + 2);
-            if (rbest < 0 || cost < rbest) {
-                rbest = cost;
-                rzc = zc;
+        for (int l = 0; l + 1 < (int)M.lv.size() && l < kMgMaxLevels; ++l) {
+            const MgLevel& Q = M.lv[l + 1];
+            if (l > 0 && Q.N < kTile27Min) break;
+            const int64_t rtx = (Q.nx + kRX - 1) / kRX, rty = (Q.ny + MgRst<B>::RY - 1) / MgRst<B>::RY;
+            int64_t rbest = -1, rzc = Q.nz;
+            for (int64_t nch = 1; nch <= Q.nz; ++nch) {
+                const int64_t zc = (Q.nz + nch - 1) / nch;
+                const int64_t items = rtx * rty * ((Q.nz + zc - 1) / zc);
+                const int64_t cost = (((items + 7) / 8 + rconc - 1) / rconc) * (2 * zc + 2);
+                if (rbest < 0 || cost < rbest) {
+                    rbest = cost;
+                    rzc = zc;
+                }
             }
+            TileGeo::Rst& q = t.rst[l];
+            q.tx = static_cast<int32_t>(rtx);
+            q.ty = static_cast<int32_t>(rty);
+            q.zc = static_cast<int32_t>(rzc);
+            q.items = static_cast<int32_t>(rtx * rty * ((Q.nz + rzc - 1) / rzc));
+            q.blocks = static_cast<int32_t>(8 * std::min<int64_t>(rconc, (q.items + 7) / 8));
+            q.on = true;
         }
-        t.rtiles_x = static_cast<int32_t>(rtx);
-        t.rtiles_y = static_cast<int32_t>(rty);
-        t.rzc = static_cast<int32_t>(rzc);
-        t.ritems = static_cast<int32_t>(rtx * rty * ((C.nz + rzc - 1) / rzc));
-        t.rblocks = static_cast<int32_t>(8 * std::min<int64_t>(rconc, (t.ritems + 7) / 8));
         if constexpr (B == 16) {   // the fused prolongation + last sweep: the same tiles, even chunks
             if (L.Uf) {
                 const void* fps = reinterpret_cast<const void*>(&k_mg_prolong_smooth);
@@ -2631,8 +2643,8 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         else
             QPAT_MG_KIND(L.kind, B, k_mg_resid, g, dim3(kMgT), 0, st, a, bl, xl[l], L.r);
         if (l == 0 && ev) (void)hipEventRecord(ev[1], st);
-        if (l == 0 && tg.on && !M.opdep)
-            launch_restrict<B>(M, tg, st, xl[1]);
+        if (tg.on && l < kMgMaxLevels && tg.rst[l].on && !M.opdep)
+            launch_restrict<B>(M, tg, l, st, xl[l + 1]);
         else if (M.opdep)
             hipLaunchKernelGGL((k_mg_restrict<B, true>), sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny,
                                L.nz, L.r, C.b, xl[l + 1], L.W);
