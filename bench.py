@@ -68,10 +68,11 @@ MG_KERNELS = {
     "K_mg_smooth0": ("k_mg_tile<2,16>", 3, True, True),      # read x, r; write z
 }
 # on the tiled path counter 5 times the update fused with the finest-level
-# residual (counter 6 then stays empty): read r, q, x, p; write r', x, r' - A (w D^-1 r'),
+# residual (counter 6 then stays empty): read r, q, x, p; write r', x, and
+# r' - A (w D^-1 r') in FP32 (half a vector),
 # and counter 7 the prolongation fused with the last sweep: read r, level 1's x
 # (1/8 vector), the whole stencil rows (16 doubles a node: 2x the stored form); write z
-MG_FUSED_UPDATE = ("k_mg_tile<6,16>", 7, 1, True)
+MG_FUSED_UPDATE = ("k_mg_tile<6,16>", 6.5, 1, True)
 MG_FUSED_SMOOTH = ("k_mg_prolong_smooth", 2.125, 2, True)
 
 

@@ -1422,6 +1422,9 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
     constexpr int TX = kTHX - 2, TY = kTHY - 2, M1 = 8;
     constexpr uint32_t SZ = sizeof(double);
     constexpr bool UPD = MODE == kTUpdResid;
+    // the finest level's residual for the restriction is stored in FP32 (it only
+    // feeds the coarse levels of the preconditioner)
+    constexpr bool RES32 = MODE == kTResidFirst || MODE == kTResid || UPD;
     constexpr bool HAS_B = MODE != kTDirSpmv && MODE != kTApply && !UPD;
     constexpr bool CENTER_D = MODE == kTSmoothDots;
     // the right-hand side's loads go out a plane ahead where the registers allow
@@ -1564,7 +1567,9 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
             // descriptors stay uniform over the wavefront (a per-lane size would
             // turn every access into a loop over the distinct values); the
             // stores of stopped right-hand sides are skipped by the branch
-            const auto bo = plane(g.out, z, nxy * B, pv);
+            // RES32: float [N][B] planes
+            const auto bo = RES32 ? rsrc(reinterpret_cast<const float*>(g.out) + (int64_t)z * nxy * B, pv / 2)
+                                  : plane(g.out, z, nxy * B, pv);
             if (act) {
                 const auto bo2 = plane(g.out2, z, nxy * B, MODE == kTDirSpmv || UPD ? pv : 0u);
 #pragma unroll
@@ -1630,7 +1635,10 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                         o = MODE == kTTrue ? rtrue : bc[u] - sum;
                         if constexpr (MODE == kTTrue) a1 += in ? o * o : 0.0;
                     }
-                    bstore<double>(bo, oo[u], o);
+                    if constexpr (RES32)
+                        bstore<float>(bo, oo[u] == kOut ? kOut : oo[u] / 2, static_cast<float>(o));
+                    else
+                        bstore<double>(bo, oo[u], o);
                 }
                 if constexpr (UPD) {   // x += alpha p on this plane's nodes, after the stencil work
                     __builtin_amdgcn_sched_barrier(0);
@@ -1713,7 +1721,7 @@ struct RstArgs {
     int32_t nx, ny, nz;      // fine lattice
     int32_t cx, cy, cz;      // coarse lattice
     int32_t tiles_x, tiles_y, zc, items;
-    const double* r;         // fine residual [Nf][B]
+    const void* r;           // fine residual [Nf][B], FP64 or (R32) FP32
     const double* dinv;      // coarse 1 / a_ii [Nc]
     const double* w;         // coarse level's Jacobi weight
     double* bc;              // coarse right-hand side [Nc][B]
@@ -1721,7 +1729,7 @@ struct RstArgs {
     const MgScal* sc;        // [B]
 };
 
-template <int B>
+template <int B, bool R32>
 __global__ __launch_bounds__(kTT) void k_mg_restrict_tile(RstArgs g) {
     using TR = MgRst<B>;
     constexpr int RY = TR::RY, FX = TR::FX, FY = TR::FY, NPF = TR::NPF, RS = NPF * kTT;
@@ -1734,7 +1742,8 @@ __global__ __launch_bounds__(kTT) void k_mg_restrict_tile(RstArgs g) {
     if (!any) return;   // every right-hand side stopped
     const bool act = g.sc[k].active != 0;
     const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
-    const uint32_t nxy = static_cast<uint32_t>(nx) * ny, pv = nxy * B * SZ;
+    constexpr uint32_t RZ = R32 ? 4 : 8;   // bytes per fine value
+    const uint32_t nxy = static_cast<uint32_t>(nx) * ny, pv = nxy * B * RZ;
     const int64_t cxy = (int64_t)g.cx * g.cy;
     const double wc = *g.w;   // system 0 of the coarse level (the caller passes that entry)
     const int lx = cn % kRX, ly = cn / kRX;
@@ -1755,13 +1764,18 @@ __global__ __launch_bounds__(kTT) void k_mg_restrict_tile(RstArgs g) {
             const int e = tid + u * kTT, nl = e / B;
             const int gx = 2 * X0 - 1 + nl % FX, gy = 2 * Y0 - 1 + nl / FX;
             const bool in = nl < FX * FY && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-            fo[u] = in ? (static_cast<uint32_t>(gy * nx + gx) * B + e % B) * SZ : kOut;
+            fo[u] = in ? (static_cast<uint32_t>(gy * nx + gx) * B + e % B) * RZ : kOut;
         }
         auto fetch = [&](int pl) {
             const bool in = pl >= 0 && pl < nz;
-            const auto br = rsrc(g.r + (in ? (int64_t)pl * nxy * B : 0), in ? pv : 0u);
+            const auto br = rsrc(static_cast<const char*>(g.r) + (in ? (int64_t)pl * pv : 0), in ? pv : 0u);
 #pragma unroll
-            for (int u = 0; u < NPF; ++u) fr[u] = bload<double>(br, fo[u]);
+            for (int u = 0; u < NPF; ++u) {
+                if constexpr (R32)
+                    fr[u] = static_cast<double>(bload<float>(br, fo[u]));
+                else
+                    fr[u] = bload<double>(br, fo[u]);
+            }
         };
         auto store = [&](int sl) {
 #pragma unroll
@@ -2452,7 +2466,10 @@ void launch_restrict(const MgState& M, const TileGeo& t, int l, hipStream_t st, 
         g.bc = C.b;
         g.xc = xc;
         g.sc = M.sc;
-        hipLaunchKernelGGL(k_mg_restrict_tile<B>, dim3(q.blocks), dim3(kTT), MgRst<B>::LDS, st, g);
+        if (l == 0)   // the finest level's residual comes from the tiled kernels in FP32
+            hipLaunchKernelGGL((k_mg_restrict_tile<B, true>), dim3(q.blocks), dim3(kTT), MgRst<B>::LDS, st, g);
+        else
+            hipLaunchKernelGGL((k_mg_restrict_tile<B, false>), dim3(q.blocks), dim3(kTT), MgRst<B>::LDS, st, g);
     }
 }
 
@@ -2503,8 +2520,9 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
         // restrictions to levels 1, 2, ... (coarse level of at least kTile27Min nodes): the
         // same balance with (2 zc + 1) fine planes per item
         const MgLevel& C = M.lv[1];
-        const void* fr = reinterpret_cast<const void*>(&k_mg_restrict_tile<B>);
-        QPAT_HIP(c, hipFuncSetAttribute(fr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MgRst<B>::LDS));
+        const void* fr = reinterpret_cast<const void*>(&k_mg_restrict_tile<B, true>);
+        for (const void* f : {fr, reinterpret_cast<const void*>(&k_mg_restrict_tile<B, false>)})
+            QPAT_HIP(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MgRst<B>::LDS));
         int rocc = 1;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&rocc, fr, kTT, MgRst<B>::LDS) != hipSuccess) rocc = 1;
         const int64_t rconc = (int64_t)std::max(rocc, 1) * (cus / 8);
