@@ -13,7 +13,8 @@
 //   * smoother: kMgNu weighted Jacobi sweeps before and after the coarse
 //     correction, weight 8/(5 g) with g >= lambda_max(D^{-1} A) the Gershgorin
 //     bound: the first-degree Chebyshev weight for the interval [g/4, g] that
-//     the sweep has to damp (w lambda <= 8/5 < 2 keeps the cycle SPD);
+//     the sweep has to damp; 9/(5 g) on the coarse levels (w lambda < 2 keeps
+//     the cycle SPD);
 //   * coarsest level: the explicit inverse (dense, computed on the host).
 // Vectors hold B right-hand sides interleaved ([sys][N][B]); every lane
 // (system, right-hand side) has its own PCG scalars and stops on its own.
@@ -1294,6 +1295,31 @@ __global__ __launch_bounds__(kMgT) void k_mgp_init(PcgMg a, double inv_delta) {
     }
 }
 
+// The start of a run without deflation or initial guess in one pass: r = b,
+// x = 0 and the partial sums of b and b.b that k_mgp_init reduces. (The
+// first direction of the tiled path ignores the old direction, beta = 0.)
+template <int B>
+__global__ __launch_bounds__(kMgT) void k_mgp_start0(PcgMg a, const double* __restrict__ b) {
+    __shared__ double sm[(kMgT / 64) * 16];
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        const int64_t o = sys * a.L.N * B;
+        double s1 = 0.0, s2 = 0.0;
+        QPAT_MG_ELEMS(e, a.L.N * B) {
+            const double v = b[o + e];
+            a.r[o + e] = v;
+            a.x[o + e] = 0.0;
+            s1 += v;
+            s2 += v * v;
+        }
+        s1 = group_sum<B>(s1, sm);
+        s2 = group_sum<B>(s2, sm);
+        if (threadIdx.x < B) {
+            put(a.parts, sys * B + threadIdx.x, 2, s1);
+            put(a.parts, sys * B + threadIdx.x, 3, s2);
+        }
+    }
+}
+
 // b -= mean; r = b; po = 0; x = 0 unless a start is given (and b != 0)
 template <int B>
 __global__ __launch_bounds__(kMgT) void k_mgp_start(PcgMg a, double* __restrict__ b, int has_x0) {
@@ -1535,7 +1561,9 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
 #pragma unroll
             for (int u = 0; u < NPF; ++u) {
                 double val = fr[u];
-                if constexpr (MODE == kTDirSpmv) val = fo[u] != kOut ? fr[u] - cc_ + beta * f2[u] : 0.0;
+                // beta = 0 (a run's first direction) never reads the old direction's values
+                if constexpr (MODE == kTDirSpmv)
+                    val = fo[u] != kOut ? (beta != 0.0 ? fr[u] - cc_ + beta * f2[u] : fr[u] - cc_) : 0.0;
                 if constexpr (MODE == kTResidFirst) val = w * f2[u] * fr[u];
                 if constexpr (UPD) val = fr[u] - alpha * f2[u];   // r' itself: the sweep scales it per neighbour
                 ring[sl * RS + tid + u * kTT] = val;
@@ -2803,9 +2831,14 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
     const PcgMg a = pcg_args<B>(c, op);
     QPAT_TRY(tile_setup<B>(c, M));
     const TileGeo tg = M.tiles[B];
-    hipLaunchKernelGGL(k_mgp_bstats<B>, g, dim3(kMgT), 0, sm, a, c->b64);
-    hipLaunchKernelGGL(k_mgp_init, lanes, dim3(kMgT), 0, sm, a, c->delta > 0 ? 1.0 / c->delta : 0.0);
-    hipLaunchKernelGGL(k_mgp_start<B>, g, dim3(kMgT), 0, sm, a, c->b64, has_x0 ? 1 : 0);
+    if (tg.on && !a.deflate && !has_x0) {   // one pass over b
+        hipLaunchKernelGGL(k_mgp_start0<B>, g, dim3(kMgT), 0, sm, a, c->b64);
+        hipLaunchKernelGGL(k_mgp_init, lanes, dim3(kMgT), 0, sm, a, c->delta > 0 ? 1.0 / c->delta : 0.0);
+    } else {
+        hipLaunchKernelGGL(k_mgp_bstats<B>, g, dim3(kMgT), 0, sm, a, c->b64);
+        hipLaunchKernelGGL(k_mgp_init, lanes, dim3(kMgT), 0, sm, a, c->delta > 0 ? 1.0 / c->delta : 0.0);
+        hipLaunchKernelGGL(k_mgp_start<B>, g, dim3(kMgT), 0, sm, a, c->b64, has_x0 ? 1 : 0);
+    }
     if (has_x0) {   // r = b - A x0; lanes that x0 already solves stop here
         true_residual<B>(M, a, tg, c->b64, sm);
         hipLaunchKernelGGL(k_mgp_true_fin, lanes, dim3(kMgT), 0, sm, a, 1);
@@ -3223,7 +3256,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
         double g;
         std::memcpy(&g, &gm[i], sizeof g);
         if (!(g > 0.0) || !std::isfinite(g)) return fail(c, QPAT_ERR_ARG, "multigrid: non-positive diagonal in %s", what);
-        w[i] = 8.0 / (5.0 * g);
+        w[i] = (i % nl == 0 ? 8.0 / 5.0 : 9.0 / 5.0) / g;   // finest level, coarse levels
     }
     QPAT_HIP(c, hipMemcpyAsync(M.w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     const int n = static_cast<int>(K.N), M1 = K.m + 1;
