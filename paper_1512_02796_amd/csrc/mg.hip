@@ -46,6 +46,8 @@ struct MgLevel {
     double* r = nullptr;           // residual before restriction
     double* W = nullptr;           // [nsys][8][N] operator-dependent prolongation weights to the next level (corner-major)
     double* Uf = nullptr;          // kind 3: [nsys][kFullRow][N] whole Kuhn rows, entry-major; K levels >= 1: [N][kRow27]
+    float* Uf32 = nullptr;         // kind 5: the kind-3 rows in FP32 (M_delta's V-cycle)
+    int32_t vkind = -1;            // row kind of the V-cycle's kernels on this level (-1: kind)
 };
 
 struct MgScal {
@@ -224,6 +226,7 @@ struct LvArgs {
     int64_t N;
     int32_t kind;         // row kernel: 0 generic table, 1 Kuhn offsets, 2 full 27-point, 3 Kuhn full rows
     const double* Uf;     // kind 3: [nsys][kFullRow][N] whole rows of the Kuhn stencil
+    const float* Uf32;    // kind 5: the same in FP32
 };
 
 // Kuhn rows stored whole for the one-right-hand-side kernels: diagonal, the 7
@@ -237,6 +240,7 @@ template <int KIND>
 __device__ __forceinline__ const double* rows_of(const LvArgs& L, int sys) {
     if constexpr (KIND == 3) return L.Uf + (int64_t)sys * L.N * kFullRow;
     if constexpr (KIND == 4) return L.Uf + (int64_t)sys * L.N * 27;
+    if constexpr (KIND == 5) return reinterpret_cast<const double*>(L.Uf32 + (int64_t)sys * L.N * kFullRow);
     return L.U + (int64_t)sys * L.N * (L.m + 1);
 }
 
@@ -270,6 +274,23 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             const bool lo = inner || (ix - dx >= 0 && ix - dx < L.nx && iy - dy >= 0 && iy - dy < L.ny && iz - dz >= 0);
             if (up) s += U[(1 + j) * L.N + i] * vld<T>(x + (i + lin) * B);
             if (lo) s += U[(14 + j) * L.N + i] * vld<T>(x + (i - lin) * B);
+        }
+        return s;
+    } else if constexpr (KIND == 5) {   // the kind-3 rows in FP32 (a preconditioner's operator)
+        const float* Uw = reinterpret_cast<const float*>(U);
+        double u[15];
+#pragma unroll
+        for (int k = 0; k < 15; ++k) u[k] = static_cast<double>(Uw[k * L.N + i]);
+        const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
+        T s = u[0] * vld<T>(x + i * B);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            const int dx = kKx[j], dy = kKy[j], dz = kKz[j];
+            const int32_t lin = dx + L.nx * (dy + L.ny * dz);
+            const bool up = inner || (ix + dx < L.nx && iy + dy < L.ny && iz + dz < L.nz);
+            const bool lo = inner || (ix - dx >= 0 && iy - dy >= 0 && iz - dz >= 0);
+            if (up) s += u[1 + j] * vld<T>(x + (i + lin) * B);
+            if (lo) s += u[8 + j] * vld<T>(x + (i - lin) * B);
         }
         return s;
     } else if constexpr (KIND == 3) {
@@ -435,6 +456,11 @@ __global__ __launch_bounds__(kMgT) void k_mg_fullrows(LvArgs L, double* __restri
                 F[i * kFullRow + k] = u[k];
         }
     }
+}
+
+__global__ __launch_bounds__(kMgT) void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kMgT)
+        b[i] = static_cast<float>(a[i]);
 }
 
 // 1 / a_ii and the Gershgorin bound max_i sum_j |a_ij| / a_ii
@@ -2308,6 +2334,7 @@ inline LvArgs lv_args(const MgLevel& L) {
     a.N = L.N;
     a.kind = L.kind;
     a.Uf = L.Uf;
+    a.Uf32 = L.Uf32;
     return a;
 }
 
@@ -2321,6 +2348,9 @@ inline dim3 vgrid(int64_t n, int cap = kMgGrid) { return dim3((grid_for(n, kMgT,
         case 3: hipLaunchKernelGGL((KERNEL<3, B>), __VA_ARGS__); break;     \
         case 4:                                                             \
             if constexpr (B == 1) hipLaunchKernelGGL((KERNEL<4, 1>), __VA_ARGS__); \
+            break;                                                          \
+        case 5:                                                             \
+            if constexpr (B == 1) hipLaunchKernelGGL((KERNEL<5, 1>), __VA_ARGS__); \
             break;                                                          \
         default: hipLaunchKernelGGL((KERNEL<0, B>), __VA_ARGS__); break;    \
     }
@@ -2374,6 +2404,9 @@ void launch_smooth(int kind, dim3 g, hipStream_t st, const SmArgs& a, const doub
         case 3: hipLaunchKernelGGL((k_mg_smooth<3, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
         case 4:
             if constexpr (B == 1) hipLaunchKernelGGL((k_mg_smooth<4, 1, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts);
+            break;
+        case 5:
+            if constexpr (B == 1) hipLaunchKernelGGL((k_mg_smooth<5, 1, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts);
             break;
         default: hipLaunchKernelGGL((k_mg_smooth<0, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
     }
@@ -2636,6 +2669,9 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
     return QPAT_OK;
 }
 
+// row kind of the V-cycle's kernels on a level
+inline int vkind(const MgLevel& L) { return L.vkind >= 0 ? L.vkind : L.kind; }
+
 // the tiled path fuses the PCG update with the V-cycle's first residual
 inline bool fused_update(const TileGeo& tg) { return tg.on && kMgNu == 1; }
 
@@ -2674,7 +2710,7 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         const double* bl = l == 0 ? r0 : L.b;
         if (l == 0 && !fused0) hipLaunchKernelGGL(k_mg_first<B>, vgrid(L.N * B), dim3(kMgT), 0, st, a, r0, xl[0]);
         for (int k = 1; k < kMgNu; ++k) {
-            launch_smooth<B, false>(L.kind, g, st, a, bl, xl[l], tl[l], nullptr);
+            launch_smooth<B, false>(vkind(L), g, st, a, bl, xl[l], tl[l], nullptr);
             std::swap(xl[l], tl[l]);
         }
         if (l == 0 && ev) (void)hipEventRecord(ev[0], st);
@@ -2687,7 +2723,7 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         else if (B == 16 && tiled27(tg, l))
             launch_tile27<kT27Resid>(M, tg, l, st, xl[l], L.b, L.r);
         else
-            QPAT_MG_KIND(L.kind, B, k_mg_resid, g, dim3(kMgT), 0, st, a, bl, xl[l], L.r);
+            QPAT_MG_KIND(vkind(L), B, k_mg_resid, g, dim3(kMgT), 0, st, a, bl, xl[l], L.r);
         if (l == 0 && ev) (void)hipEventRecord(ev[1], st);
         if (tg.on && l < kMgMaxLevels && tg.rst[l].on && !M.opdep)
             launch_restrict<B>(M, tg, l, st, xl[l + 1]);
@@ -2732,11 +2768,11 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
             if (last && tg.on)
                 launch_tile<kTSmoothDots, B>(M, tg, st, xl[0], nullptr, r0, tl[0], nullptr);
             else if (last)
-                launch_smooth<B, true>(L.kind, g, st, a, bl, xl[l], tl[l], M.parts);
+                launch_smooth<B, true>(vkind(L), g, st, a, bl, xl[l], tl[l], M.parts);
             else if (B == 16 && tiled27(tg, l))
                 launch_tile27<kT27Smooth>(M, tg, l, st, xl[l], L.b, tl[l]);
             else
-                launch_smooth<B, false>(L.kind, g, st, a, bl, xl[l], tl[l], nullptr);
+                launch_smooth<B, false>(vkind(L), g, st, a, bl, xl[l], tl[l], nullptr);
             if (last && ev) (void)hipEventRecord(ev[3], st);
             std::swap(xl[l], tl[l]);
         }
@@ -3179,7 +3215,10 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             QPAT_TRY(dalloc(c, &L.t, V * L.N));
             QPAT_TRY(dalloc(c, &L.r, V * L.N));
             if (op == Op::Prior && l + 1 < nl) QPAT_TRY(dalloc(c, &L.W, nsys * L.N * 8));
-            if (op == Op::Prior && l == 0 && L.kind == 1) QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kFullRow));
+            if (op == Op::Prior && l == 0 && L.kind == 1) {
+                QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kFullRow));
+                QPAT_TRY(dalloc(c, &L.Uf32, nsys * L.N * kFullRow));
+            }
             if (op == Op::K && l == 0 && L.kind == 1 && M.bmax == 16 && nl > 1 &&
                 L.N * kFullRow * (int64_t)sizeof(double) < (int64_t(1) << 31))   // node-major, for k_mg_prolong_smooth
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kFullRow));
@@ -3215,6 +3254,9 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
         else
             hipLaunchKernelGGL(k_mg_fullrows<true>, dim3(grid_for(M.lv[0].N, kMgT, 4096), nsys), dim3(kMgT), 0,
                                c->stream, lv_args(M.lv[0]), M.lv[0].Uf);
+        if (M.lv[0].Uf32)
+            hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nsys * M.lv[0].N * kFullRow, kMgT, 4096)), dim3(kMgT), 0,
+                               c->stream, M.lv[0].Uf, M.lv[0].Uf32, nsys * M.lv[0].N * kFullRow);
     }
     for (int l = 0; l + 1 < nl; ++l) {
         const MgLevel& F = M.lv[l];
@@ -3281,6 +3323,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
     if (op == Op::Prior) QPAT_TRY(region_setup(c, M));
     if (M.lv[0].Uf && op == Op::Prior) M.lv[0].kind = 3;
+    if (M.lv[0].Uf32) M.lv[0].vkind = 5;   // the V-cycle's sweeps and residuals on FP32 rows
     for (int l = 1; op == Op::Prior && l < nl; ++l)
         if (M.lv[l].Uf) M.lv[l].kind = 4;
     M.current = true;
