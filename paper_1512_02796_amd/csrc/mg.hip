@@ -13,8 +13,8 @@
 //   * smoother: kMgNu weighted Jacobi sweeps before and after the coarse
 //     correction, weight 8/(5 g) with g >= lambda_max(D^{-1} A) the Gershgorin
 //     bound: the first-degree Chebyshev weight for the interval [g/4, g] that
-//     the sweep has to damp; 9/(5 g) on the coarse levels (w lambda < 2 keeps
-//     the cycle SPD);
+//     the sweep has to damp; 19/(10 g) on the coarse levels (w lambda < 2
+//     keeps the cycle SPD);
 //   * coarsest level: the explicit inverse (dense, computed on the host).
 // Vectors hold B right-hand sides interleaved ([sys][N][B]); every lane
 // (system, right-hand side) has its own PCG scalars and stops on its own.
@@ -3298,7 +3298,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
         double g;
         std::memcpy(&g, &gm[i], sizeof g);
         if (!(g > 0.0) || !std::isfinite(g)) return fail(c, QPAT_ERR_ARG, "multigrid: non-positive diagonal in %s", what);
-        w[i] = (i % nl == 0 ? 8.0 / 5.0 : 9.0 / 5.0) / g;   // finest level, coarse levels
+        w[i] = (i % nl == 0 ? 8.0 / 5.0 : 19.0 / 10.0) / g;   // finest level, coarse levels
     }
     QPAT_HIP(c, hipMemcpyAsync(M.w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     const int n = static_cast<int>(K.N), M1 = K.m + 1;
