@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstring>
 
+
 #include "qpat_internal.h"
 
 namespace qpat {
@@ -108,7 +109,9 @@ struct MgState {
 
 namespace {
 
-constexpr int kMgCoarse = 5;      // coarsest lattice: at most this many nodes per axis
+constexpr int kMgCoarse = 5;      // coarsest lattice: at most this many nodes per axis, or
+constexpr int64_t kMgDenseK = 1000;   // K: the first coarse level of at most this many nodes
+constexpr int64_t kMgHostDense = 256;   // coarsest inverses up to this order on the host, larger ones on the GPU
 constexpr int kMgNu = 1;          // Jacobi sweeps before and after the coarse correction
 constexpr int kMgBlocks = 2048;   // most blocks of a kernel that writes partial sums (8 per CU)
 constexpr int kMgGrid = 512;      // blocks of the vector kernels of several right-hand sides
@@ -850,20 +853,23 @@ template <int B>
 __global__ __launch_bounds__(kMgT) void k_mg_dense(int64_t Nc, int nsys, const double* __restrict__ ainv,
                                                    const double* __restrict__ b, double* __restrict__ x,
                                                    const MgScal* __restrict__ sc) {
+    // block: kMgT / 64 rows (one per wavefront) of system blockIdx.z for the
+    // thread-in-node pair blockIdx.y; that pair's column of b is staged in LDS
     using T = TB<B>;
-    constexpr int V = Pk<B>::V, BV = Pk<B>::BV;
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = blockIdx.x * (int64_t)(kMgT / 64) + (threadIdx.x >> 6);
-    const int64_t per_sys = Nc * BV;
-    if (wid >= nsys * per_sys) return;   // whole wavefronts
-    const int sys = static_cast<int>(wid / per_sys);
-    const int64_t I = (wid % per_sys) / BV;
-    const int v = static_cast<int>(wid % BV);
-    if (!pair_active<B>(sc, sys, v)) return;
-    const double* A = ainv + (sys * Nc + I) * Nc;
+    constexpr int V = Pk<B>::V;
+    extern __shared__ __align__(16) unsigned char mg_smem[];
+    T* bl = reinterpret_cast<T*>(mg_smem);   // [Nc]
+    const int sys = blockIdx.z, v = blockIdx.y;
+    if (!pair_active<B>(sc, sys, v)) return;   // uniform over the block
     const double* bs = b + sys * Nc * B + v * V;
+    for (int64_t J = threadIdx.x; J < Nc; J += kMgT) bl[J] = vld<T>(bs + J * B);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t I = blockIdx.x * (int64_t)(kMgT / 64) + (threadIdx.x >> 6);
+    if (I >= Nc) return;   // whole wavefronts, after the barrier
+    const double* A = ainv + (sys * Nc + I) * Nc;
     T s = 0.0;
-    for (int64_t J = lane; J < Nc; J += 64) s += A[J] * vld<T>(bs + J * B);
+    for (int64_t J = lane; J < Nc; J += 64) s += A[J] * bl[J];
     double out[V];
 #pragma unroll
     for (int c = 0; c < V; ++c) {
@@ -2735,8 +2741,9 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
                                L.nz, L.r, C.b, xl[l + 1], nullptr);
     }
     const MgLevel& K = M.lv[nl - 1];
-    hipLaunchKernelGGL(k_mg_dense<B>, dim3((unsigned)((M.nsys * K.N * Pk<B>::BV + kMgT / 64 - 1) / (kMgT / 64))),
-                       dim3(kMgT), 0, st, K.N, M.nsys, M.ainv, K.b, xl[nl - 1], M.sc);
+    hipLaunchKernelGGL(k_mg_dense<B>,
+                       dim3((unsigned)((K.N + kMgT / 64 - 1) / (kMgT / 64)), (unsigned)Pk<B>::BV, (unsigned)M.nsys),
+                       dim3(kMgT), K.N * sizeof(TB<B>), st, K.N, M.nsys, M.ainv, K.b, xl[nl - 1], M.sc);
     for (int l = nl - 2; l >= 0; --l) {
         const MgLevel& L = M.lv[l];
         const MgLevel& C = M.lv[l + 1];
@@ -3148,6 +3155,66 @@ static qpat_status region_setup(qpat_ctx* c, MgState& M) {
     return QPAT_OK;
 }
 
+// One step of the symmetric sweep operator (Gauss-Jordan elimination without
+// pivoting) on each system's [n][n] matrix, pivot k, from S to T:
+//   T_kk = -1/d, T_ik = S_ik/d, T_kj = S_kj/d, T_ij = S_ij - S_ik S_kj/d,  d = S_kk.
+// Sweeping every pivot of an SPD matrix turns it into minus its inverse, and
+// each pivot d is then a Schur-complement diagonal, so positive; the last step
+// flips the sign. A pivot that is not positive sets bad[sys].
+__global__ __launch_bounds__(kMgT) void k_sweep(const double* __restrict__ S, double* __restrict__ T, int n, int k,
+                                                int* __restrict__ bad) {
+    const int sys = blockIdx.y;
+    const int64_t nn = (int64_t)n * n;
+    const int64_t e = blockIdx.x * (int64_t)kMgT + threadIdx.x;
+    if (e >= nn) return;
+    const double* s = S + sys * nn;
+    const int i = static_cast<int>(e / n), j = static_cast<int>(e % n);
+    const double d = s[(int64_t)k * n + k];
+    const double sg = k == n - 1 ? -1.0 : 1.0;
+    double v;
+    if (i == k && j == k) {
+        if (!(d > 0.0) || !std::isfinite(d)) bad[sys] = 1;
+        v = -1.0 / d;
+    } else if (i == k) {
+        v = s[e] / d;
+    } else if (j == k) {
+        v = s[e] / d;
+    } else {
+        v = s[e] - s[(int64_t)i * n + k] * s[(int64_t)k * n + j] / d;
+    }
+    T[sys * nn + e] = sg * v;
+}
+
+// In-place inverse of each system's SPD [n][n] matrix in M.ainv on the GPU by
+// n sweep steps between M.ainv and a scratch copy (no pivoting: the matrix is
+// SPD), with a check of every pivot.
+qpat_status dense_spd_inverse(qpat_ctx* c, MgState& M, int n, const char* what) {
+    const int64_t nn = (int64_t)n * n;
+    double* tmp = nullptr;
+    int* bad = nullptr;
+    QPAT_TRY(dalloc(c, &tmp, M.nsys * nn));
+    QPAT_TRY(dalloc(c, &bad, M.nsys));
+    QPAT_HIP(c, hipMemsetAsync(bad, 0, M.nsys * sizeof(int), c->stream));
+    const dim3 g((unsigned)((nn + kMgT - 1) / kMgT), (unsigned)M.nsys);
+    double* src = M.ainv;
+    double* dst = tmp;
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_sweep, g, dim3(kMgT), 0, c->stream, src, dst, n, k, bad);
+        std::swap(src, dst);
+    }
+    QPAT_HIP(c, hipGetLastError());
+    if (src != M.ainv)
+        QPAT_HIP(c, hipMemcpyAsync(M.ainv, src, M.nsys * nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    std::vector<int> bad_h(M.nsys, 0);
+    QPAT_HIP(c, hipMemcpyAsync(bad_h.data(), bad, M.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    QPAT_TRY(dfree(c, tmp));
+    QPAT_TRY(dfree(c, bad));
+    for (int sys = 0; sys < M.nsys; ++sys)
+        if (bad_h[sys]) return fail(c, QPAT_ERR_ARG, "multigrid: coarsest %s is not positive definite", what);
+    return QPAT_OK;
+}
+
 // Hierarchy for the current operator (after its assembly and stencil form).
 // Called after every assembly: when the options turn multigrid off, an older
 // hierarchy is marked stale so that turning it on again cannot pick it up.
@@ -3173,7 +3240,10 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             kuhn = c->lat.dx[j] == kKx[j] && c->lat.dy[j] == kKy[j] && c->lat.dz[j] == kKz[j];
         L0.kind = kuhn ? 1 : 0;
         M.lv.push_back(L0);
-        while (std::max(M.lv.back().nx, std::max(M.lv.back().ny, M.lv.back().nz)) > kMgCoarse) {
+        // K stops at the first coarse level small enough for a dense inverse (the
+        // levels below it cost a launch each for almost no work); M_delta at kMgCoarse
+        while (std::max(M.lv.back().nx, std::max(M.lv.back().ny, M.lv.back().nz)) > kMgCoarse &&
+               !(op == Op::K && M.lv.size() >= 2 && M.lv.back().N <= kMgDenseK)) {
             const MgLevel& F = M.lv.back();
             MgLevel C;
             C.nx = F.nx > 2 ? F.nx / 2 + 1 : F.nx;
@@ -3187,7 +3257,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
         }
         const int nl = static_cast<int>(M.lv.size());
         const int64_t Nc = M.lv.back().N;
-        if (Nc > 4096 || nl < 2) {   // no useful hierarchy: keep Jacobi-PCG
+        if (Nc > (op == Op::K ? kMgDenseK : 4096) || nl < 2) {   // no useful hierarchy: keep Jacobi-PCG
             mg_drop(c, op);
             return QPAT_OK;
         }
@@ -3302,6 +3372,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     }
     QPAT_HIP(c, hipMemcpyAsync(M.w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     const int n = static_cast<int>(K.N), M1 = K.m + 1;
+    const bool on_gpu = n > kMgHostDense;
     std::vector<double> inv(nsys * (size_t)n * n);
     for (int sys = 0; sys < nsys; ++sys) {
         std::vector<double> A((size_t)n * n, 0.0);
@@ -3316,10 +3387,12 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
                 A[(size_t)i * n + k] = A[(size_t)k * n + i] = U[(size_t)i * M1 + j + 1];
             }
         }
-        if (!spd_inverse(A, n)) return fail(c, QPAT_ERR_ARG, "multigrid: coarsest %s is not positive definite", what);
+        if (!on_gpu && !spd_inverse(A, n))
+            return fail(c, QPAT_ERR_ARG, "multigrid: coarsest %s is not positive definite", what);
         std::copy(A.begin(), A.end(), inv.begin() + (size_t)sys * n * n);
     }
     QPAT_HIP(c, hipMemcpyAsync(M.ainv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (on_gpu) QPAT_TRY(dense_spd_inverse(c, M, n, what));
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
     if (op == Op::Prior) QPAT_TRY(region_setup(c, M));
     if (M.lv[0].Uf && op == Op::Prior) M.lv[0].kind = 3;
