@@ -153,6 +153,23 @@ qpat_status qpat_vjp(qpat_ctx* ctx, const double* t, double* out, qpat_info* inf
 qpat_status qpat_prior_setup(qpat_ctx* ctx, const double* kt, const double* mt,
                              double T, double b_over_a, double delta);
 
+/* The same prior with another choice of r in R(u) = int r(|grad u|) (Sec. 3,
+ * eq. (3.6) and the remark after eq. (3.7) that smoothed TV and TV^q fit the
+ * algorithm unchanged; Sec. 4 eq. (4.3): c_u = r'(|grad u|) / |grad u|).
+ *   kind QPAT_PRIOR_PM  : Perona-Malik, exactly qpat_prior_setup (q ignored).
+ *   kind QPAT_PRIOR_TVQ : r(t) = T^(2-q) (t^2 + T^2)^(q/2) / q, so
+ *                         c_T = (1 + |grad u_T|^2 / T^2)^((q-2)/2); q = 1 is
+ *                         smoothed total variation, q = 2 the plain Laplacian.
+ *                         The factor T^(2-q) gives c(0) = 1 as for
+ *                         Perona-Malik; a constant factor of r is absorbed in
+ *                         the prior weights a, b. Needs 0 < q <= 2.
+ * Other arguments and errors as qpat_prior_setup; an unknown kind or a q
+ * outside (0, 2] returns QPAT_ERR_ARG before any device work. */
+#define QPAT_PRIOR_PM 0
+#define QPAT_PRIOR_TVQ 1
+qpat_status qpat_prior_setup_r(qpat_ctx* ctx, const double* kt, const double* mt, int32_t kind,
+                               double T, double q, double b_over_a, double delta);
+
 /* y = M_delta x; x, y: [2N] (device). */
 qpat_status qpat_prior_apply(qpat_ctx* ctx, const double* x, double* y);
 

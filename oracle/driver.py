@@ -32,7 +32,7 @@ def initial_guess(geo, phi_src, chi, kappa0, mu0, solver="direct", rtol=1e-10):
 
 def reconstruct(geo, phi_src, chi, W, kappa0, mu0, outer, inner, T=5e-3,
                 b_over_a=1.0, delta=1e-6, solver="direct", rtol=1e-10,
-                beta0=None, stop_on_reject=False, m0=None, tau=None):
+                beta0=None, stop_on_reject=False, m0=None, tau=None, prior="pm", q=1.0):
     chi = np.asarray(chi)
     W = np.asarray(W)
     N = geo.N
@@ -46,7 +46,7 @@ def reconstruct(geo, phi_src, chi, W, kappa0, mu0, outer, inner, T=5e-3,
         res = np.linalg.norm(W * (chi - lin.h))
         log["res_nl"].append(res)
         yt = (W * (chi - lin.h + lin.jvp(beta))).ravel()
-        prior = Prior(geo, beta[:N], beta[N:], T, b_over_a, delta, solver, rtol)
+        Md = Prior(geo, beta[:N], beta[N:], T, b_over_a, delta, solver, rtol, kind=prior, q=q)
         n_ill = lin.n_ill
 
         def A(v, lin=lin):
@@ -55,7 +55,7 @@ def reconstruct(geo, phi_src, chi, W, kappa0, mu0, outer, inner, T=5e-3,
         def At(u, lin=lin):
             return lin.vjp(W * u.reshape(n_ill, N))
 
-        it = plsqr(A, At, prior.solve, yt, inner, m0, tau)
+        it = plsqr(A, At, Md.solve, yt, inner, m0, tau)
         log["lsqr"].append(list(it.history))
         beta_new = it.x
         kappa_n, mu_n = params(kappa0, mu0, beta_new)

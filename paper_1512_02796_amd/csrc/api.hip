@@ -431,11 +431,20 @@ qpat_status qpat_vjp(qpat_ctx* c, const double* t, double* out, qpat_info* info)
 
 qpat_status qpat_prior_setup(qpat_ctx* c, const double* kt, const double* mt, double T, double b_over_a,
                              double delta) {
+    return qpat_prior_setup_r(c, kt, mt, QPAT_PRIOR_PM, T, 1.0, b_over_a, delta);
+}
+
+qpat_status qpat_prior_setup_r(qpat_ctx* c, const double* kt, const double* mt, int32_t kind, double T, double q,
+                               double b_over_a, double delta) {
     if (!c) return QPAT_ERR_ARG;
     DeviceGuard g(c->device);
     if (!kt || !mt || !(T > 0.0) || !(b_over_a > 0.0) || !(delta > 0.0))
         return fail(c, QPAT_ERR_ARG, "prior_setup: need kt, mt and T, b_over_a, delta > 0");
-    QPAT_TRY(assemble_prior(c, kt, mt, T, b_over_a, delta));
+    if (kind != QPAT_PRIOR_PM && kind != QPAT_PRIOR_TVQ)
+        return fail(c, QPAT_ERR_ARG, "prior_setup: unknown prior kind %d", (int)kind);
+    if (kind == QPAT_PRIOR_TVQ && !(q > 0.0 && q <= 2.0))
+        return fail(c, QPAT_ERR_ARG, "prior_setup: TV^q needs 0 < q <= 2");
+    QPAT_TRY(assemble_prior(c, kt, mt, kind, T, q, b_over_a, delta));
     QPAT_TRY(lattice_convert(c, Op::Prior));
     c->delta = delta;
     QPAT_TRY(mg_setup(c, Op::Prior));

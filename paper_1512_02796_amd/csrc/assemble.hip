@@ -103,12 +103,15 @@ __global__ void k_assemble_K(const Sell s, const int32_t* __restrict__ tets, con
     dinv32[row] = static_cast<float>(1.0 / d);
 }
 
-// Perona-Malik lagged diffusivity: c_T = r'(t)/t = 1 / (1 + t^2 / T^2), t = |grad u_T|.
+// Lagged diffusivity c_T = r'(t)/t, t = |grad u_T|, constant per tetrahedron:
+//   Perona-Malik (kind 0)  r(t) = (T^2/2) log(1 + t^2/T^2)      c_T = 1 / (1 + t^2/T^2)
+//   TV^q (kind 1)          r(t) = T^(2-q) (t^2 + T^2)^(q/2) / q  c_T = (1 + t^2/T^2)^((q-2)/2)
+// (qexp = (q - 2) / 2; q = 1 is smoothed total variation).
 // blockIdx.y selects the block of M_delta: 0 -> M(kt), 1 -> (b/a) M(mt).
 __global__ void k_assemble_prior(const Sell s, const int32_t* __restrict__ tets, const double* __restrict__ geo,
                                  const int32_t* __restrict__ n2t_ptr, const int32_t* __restrict__ n2t,
                                  const double* __restrict__ kt, const double* __restrict__ mt, double invT2,
-                                 double b_over_a, double delta, double* __restrict__ M64, float* __restrict__ M32,
+                                 int kind, double qexp, double b_over_a, double delta, double* __restrict__ M64, float* __restrict__ M32,
                                  double* __restrict__ dinv64, float* __restrict__ dinv32) {
     int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (row >= s.N) return;
@@ -135,7 +138,8 @@ __global__ void k_assemble_prior(const Sell s, const int32_t* __restrict__ tets,
             gu[1] += ub * G.g[b][1];
             gu[2] += ub * G.g[b][2];
         }
-        double cT = 1.0 / (1.0 + dot3(gu, gu) * invT2);
+        const double s1 = 1.0 + dot3(gu, gu) * invT2;
+        const double cT = kind == 0 ? 1.0 / s1 : pow(s1, qexp);
         double ga[3] = {0.0, 0.0, 0.0};   // row vertex a: selected with compile-time indices
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -201,10 +205,11 @@ qpat_status assemble_K(qpat_ctx* c) {
     return QPAT_OK;
 }
 
-qpat_status assemble_prior(qpat_ctx* c, const double* kt, const double* mt, double T, double b_over_a,
-                           double delta) {
+qpat_status assemble_prior(qpat_ctx* c, const double* kt, const double* mt, int kind, double T, double q,
+                           double b_over_a, double delta) {
     hipLaunchKernelGGL(k_assemble_prior, dim3(grid_for(c->N, kThreads, 1 << 30), 2), dim3(kThreads), 0, c->stream,
-                       c->sell, c->tets, c->geo, c->n2t_ptr, c->n2t, kt, mt, 1.0 / (T * T), b_over_a, delta, c->M64,
+                       c->sell, c->tets, c->geo, c->n2t_ptr, c->n2t, kt, mt, 1.0 / (T * T), kind, 0.5 * (q - 2.0),
+                       b_over_a, delta, c->M64,
                        c->M32, c->Mdinv64, c->Mdinv32);
     QPAT_HIP(c, hipGetLastError());
     return QPAT_OK;

@@ -293,8 +293,8 @@ qpat_status mesh_build(qpat_ctx* c, const double* coords, const int32_t* tets_in
 
 // ---- assemble.hip
 qpat_status assemble_K(qpat_ctx* c);
-qpat_status assemble_prior(qpat_ctx* c, const double* kt, const double* mt, double T,
-                           double b_over_a, double delta);
+qpat_status assemble_prior(qpat_ctx* c, const double* kt, const double* mt, int kind, double T,
+                           double q, double b_over_a, double delta);
 qpat_status assemble_load(qpat_ctx* c, const double* phi_src);
 qpat_status exp_params(qpat_ctx* c, double kappa0, double mu0, const double* beta);
 qpat_status check_positive(qpat_ctx* c, const double* a, int64_t n, bool* ok);

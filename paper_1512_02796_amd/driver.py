@@ -27,7 +27,9 @@ def window_ratio(history, m, m0):
 
 
 def reconstruct(ctx, chi, W, kappa0, mu0, outer, inner, T=5e-3, b_over_a=1.0, delta=1e-6,
-                beta0=None, stop_on_reject=False, m0=None, tau=None):
+                beta0=None, stop_on_reject=False, m0=None, tau=None, prior="pm", q=1.0):
+    """prior: "pm" (Perona-Malik) or "tvq" (r(t) = T^(2-q) (t^2 + T^2)^(q/2) / q)."""
+    kind = {"pm": 0, "tvq": 1}[prior]
     N = ctx.N
     dev = chi.device
     beta = torch.zeros(2 * N, dtype=torch.float64, device=dev)
@@ -42,7 +44,10 @@ def reconstruct(ctx, chi, W, kappa0, mu0, outer, inner, T=5e-3, b_over_a=1.0, de
     res = ctx.misfit(chi, W)
     for _ in range(outer):
         log["res_nl"].append(res)
-        ctx.prior_setup(beta[:N], beta[N:], T, b_over_a, delta)
+        if kind == 0:
+            ctx.prior_setup(beta[:N], beta[N:], T, b_over_a, delta)
+        else:
+            ctx.prior_setup_r(beta[:N], beta[N:], kind, T, q, b_over_a, delta)
         ctx.lsqr_init(chi, W, beta, beta_new)
         hist = [ctx.lsqr_residual()]
         iters = 0

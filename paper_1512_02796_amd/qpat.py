@@ -77,6 +77,7 @@ SIGNATURES = {
     "qpat_jvp": (_S, [_P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_vjp": (_S, [_P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_prior_setup": (_S, [_P, _P, _P, _D, _D, _D]),
+    "qpat_prior_setup_r": (_S, [_P, _P, _P, _I32, _D, _D, _D, _D]),
     "qpat_prior_apply": (_S, [_P, _P, _P]),
     "qpat_prior_solve": (_S, [_P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_misfit": (_S, [_P, _P, _P, ctypes.POINTER(_D)]),
@@ -301,6 +302,12 @@ class Context:
                                           _ptr(mt, torch.float64, self.N, "mt"), float(T), float(b_over_a),
                                           float(delta)))
 
+    def prior_setup_r(self, kt, mt, kind, T=5e-3, q=1.0, b_over_a=1.0, delta=1e-6):
+        """kind: PRIOR_PM or PRIOR_TVQ (r(t) = T^(2-q) (t^2 + T^2)^(q/2) / q)."""
+        self._check(_lib.qpat_prior_setup_r(self._h, _ptr(kt, torch.float64, self.N, "kt"),
+                                            _ptr(mt, torch.float64, self.N, "mt"), int(kind), float(T), float(q),
+                                            float(b_over_a), float(delta)))
+
     def prior_apply(self, x, y):
         self._check(_lib.qpat_prior_apply(self._h, _ptr(x, torch.float64, 2 * self.N, "x"),
                                           _ptr(y, torch.float64, 2 * self.N, "y")))
@@ -360,6 +367,7 @@ class Context:
                 "sell_len": arr[5]}
 
 
+PRIOR_PM, PRIOR_TVQ = 0, 1   # QPAT_PRIOR_PM, QPAT_PRIOR_TVQ
 BATCH_OPS = {"forward": 0, "jvp": 1, "vjp": 2, "pair": 3, "lsqr_step": 4}
 
 

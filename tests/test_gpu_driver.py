@@ -42,6 +42,21 @@ def test_algorithm1_matches_oracle():
     assert log["res_nl"][-1] < 0.25 * log["res_nl"][0]
 
 
+def test_algorithm1_tv_prior_matches_oracle():
+    """One outer step with the smoothed-TV prior (q = 1) on both sides."""
+    from paper_1512_02796_amd import qpat
+    from paper_1512_02796_amd.driver import reconstruct
+    G = GpuProblem("C1", qpat.default_opts(pcg_rtol=1e-12, prior_rtol=1e-12))
+    P = G.P
+    g, lin = oracle_of(P)
+    chi, W = data_of(P, lin)
+    beta, log = reconstruct(G.ctx, dev(chi), dev(W), P.kappa0, P.mu0, outer=1, inner=6, prior="tvq", q=1.0)
+    ref_beta, ref_log = oracle_reconstruct(g, P.phi_src, chi, W, P.kappa0, P.mu0, outer=1, inner=6,
+                                           prior="tvq", q=1.0)
+    assert np.allclose(log["lsqr"][0], ref_log["lsqr"][0], rtol=1e-6)
+    assert rel(host(beta), ref_beta) <= 1e-4
+
+
 def test_step4_rejection_returns_previous_iterate():
     from paper_1512_02796_amd.driver import reconstruct
     G = GpuProblem("T4")

@@ -106,6 +106,41 @@ def test_prior_apply_and_solve(deflate, rtol):
     assert res <= max(2 * rtol, 1e-10)
 
 
+@pytest.mark.parametrize("q,precond", [(1.0, 1), (0.5, 1), (1.5, 0)])
+def test_prior_tvq_apply_and_solve(q, precond):
+    """TV^q prior (r(t) = T^(2-q) (t^2 + T^2)^(q/2) / q): the library's M_delta and
+    M_delta^{-1} against the oracle's, multigrid and Jacobi preconditioners."""
+    from paper_1512_02796_amd import qpat
+    G = GpuProblem("T12", opts(prior_precond=precond, prior_rtol=1e-11))
+    P = G.P
+    kt = np.log(P.kappa / P.kappa0)
+    mt = np.log(P.mu / P.mu0)
+    G.ctx.prior_setup_r(dev(kt), dev(mt), qpat.PRIOR_TVQ, 5e-3, q, 1.7, 1e-6)
+    g, _ = oracle_of(P)
+    Md = oprior.M_delta(g, kt, mt, 5e-3, 1.7, 1e-6, kind="tvq", q=q)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal(2 * G.N)
+    y = torch.empty(2 * G.N, dtype=torch.float64, device="cuda")
+    G.ctx.prior_apply(dev(x), y)
+    assert rel(host(y), Md @ x) <= 1e-14
+    r = torch.empty_like(y)
+    info = G.ctx.prior_solve(dev(x), r)
+    assert rel(host(r), Direct(Md)(x)) <= 1e-8, info
+    res = np.linalg.norm(Md @ host(r) - x) / np.linalg.norm(x)
+    assert res <= 1e-10, info
+
+
+def test_prior_setup_r_rejects_bad_arguments():
+    from paper_1512_02796_amd import qpat
+    G = GpuProblem("T4")
+    z = torch.zeros(G.N, dtype=torch.float64, device="cuda")
+    for kind, q in ((qpat.PRIOR_TVQ, 0.0), (qpat.PRIOR_TVQ, 2.5), (7, 1.0)):
+        with pytest.raises(qpat.QpatError) as e:
+            G.ctx.prior_setup_r(z, z, kind, 5e-3, q)
+        assert "ERR_ARG" in str(e.value)
+    G.ctx.prior_setup_r(z, z, qpat.PRIOR_PM, 5e-3, -1.0)   # q is ignored for Perona-Malik
+
+
 @pytest.mark.parametrize("whiten,hist_tol,x_tol", [("const", 1e-10, 1e-8), ("noise", 1e-6, 1e-4)])
 def test_lsqr_matches_oracle(whiten, hist_tol, x_tol):
     """8 PLSQR steps from the same chi and W. With a constant W the history

@@ -1,5 +1,6 @@
-"""Pins of the oracle's Perona-Malik lagged-diffusivity prior."""
+"""Pins of the oracle's lagged-diffusivity priors (Perona-Malik and TV^q)."""
 import numpy as np
+import pytest
 
 from qpat_inputs import kuhn_mesh, make_problem
 from oracle import fem, prior
@@ -95,3 +96,52 @@ def test_M_delta_solve_direct_vs_pcg():
     N = g.N
     assert abs(1e-6 * xd[:N].sum() - p[:N].sum()) <= 1e-9 * np.abs(p[:N]).sum()
     assert abs(1e-6 * xd[N:].sum() - p[N:].sum()) <= 1e-9 * np.abs(p[N:]).sum()
+
+
+KINDS = [("pm", 1.0), ("tvq", 1.0), ("tvq", 0.5), ("tvq", 1.5)]
+
+
+@pytest.mark.parametrize("kind,q", KINDS)
+def test_gradient_of_R_is_M_u(kind, q):
+    """grad R(u) = M(u) u (Sec. 4, after eq. (4.2)), with R(u) = sum_T |T| r(|grad u_T|)
+    evaluated from r alone and differentiated by central differences: this pins
+    c = r'(t)/t against r for each choice, independently of how M is formed."""
+    m, g = geo(3)
+    rng = np.random.default_rng(5)
+    u = 0.01 * rng.standard_normal(m.N)   # |grad u| ~ T, where r bends most
+    Mu = prior.M_of(g, u, T, kind, q) @ u
+    h = 1e-7
+    fd = np.empty(m.N)
+    for i in range(m.N):
+        e = np.zeros(m.N)
+        e[i] = h
+        fd[i] = (prior.R_of(g, u + e, T, kind, q) - prior.R_of(g, u - e, T, kind, q)) / (2 * h)
+    assert np.linalg.norm(fd - Mu) <= 1e-6 * np.linalg.norm(Mu)
+
+
+@pytest.mark.parametrize("q", [0.5, 1.0, 1.5, 2.0])
+def test_tvq_linear_u_closed_form(q):
+    """u = g.x: |grad u| = |g| on every tetrahedron, so M = S(1) (1 + |g|^2/T^2)^((q-2)/2);
+    q = 2 gives the plain Laplacian stiffness for any u."""
+    m, g = geo(3)
+    gvec = np.array([2e-3, -4e-3, 1e-3])
+    M = prior.M_of(g, m.coords @ gvec, T, "tvq", q)
+    S = fem.stiffness(g, np.ones(m.N))
+    want = S * (1 + (gvec @ gvec) / T ** 2) ** ((q - 2) / 2)
+    assert np.allclose(M.toarray(), want.toarray(), rtol=1e-12, atol=1e-15)
+    if q == 2.0:
+        rng = np.random.default_rng(3)
+        M2 = prior.M_of(g, rng.standard_normal(m.N), T, "tvq", 2.0)
+        assert np.allclose(M2.toarray(), S.toarray(), rtol=1e-13, atol=1e-15)
+
+
+def test_smoothed_tv_limits():
+    """q = 1: r(t) = T sqrt(t^2 + T^2), so c(t) -> T/t for t >> T (the TV diffusivity
+    1/|grad u| scaled by T), c(0) = 1, and r is increasing (Sec. 3 asks for that)."""
+    t = np.array([1e-1, 1.0, 10.0])
+    c = prior.diffusivity(t, T, "tvq", 1.0)
+    assert np.allclose(c, T / t, rtol=(T / t).max() ** 2)
+    assert prior.diffusivity(np.array([0.0]), T, "tvq", 1.0)[0] == 1.0
+    tt = np.linspace(0, 0.1, 101)
+    for q in (0.5, 1.0, 1.5, 2.0):
+        assert np.all(np.diff(prior.r_of(tt, T, "tvq", q)) > 0)
