@@ -187,6 +187,27 @@ qpat_status qpat_misfit(qpat_ctx* ctx, const double* chi, const double* w, doubl
  * ratio clamped below at 1e-12 mu0. chi: [n_ill][N]; beta_out: [2N] (device). */
 qpat_status qpat_init_guess(qpat_ctx* ctx, const double* chi, double mu0, double* beta_out);
 
+/* Background values of Algorithm 1's preamble: the homogeneous pair
+ * (kappa0, mu0) minimising |W (chi - h(log(kappa) 1, log(mu) 1))| over
+ * positive reals (W = Gamma^{-1/2} diagonal), by Gauss-Newton in
+ * (log kappa, log mu) with the columns J [1; 0], J [0; 1] of the Jacobian at
+ * the current homogeneous point (one forward solve and two J products per
+ * iteration). Steps longer than 1 in either log are shortened to 1, then
+ * halved up to 30 times until the misfit does not increase. Stops after maxit
+ * iterations, when an accepted step is at most tol in both logs, or when no
+ * halving decreases the misfit.
+ *   chi, w       : [n_ill][N] (device).
+ *   kappa0, mu0  : host in/out: the starting pair in, the fitted pair out.
+ *   iters        : host out (may be NULL): Gauss-Newton iterations taken.
+ * On return the context's forward state (phi, h) is at the fitted pair, so
+ * qpat_init_guess may follow directly. Errors: QPAT_ERR_ARG (null pointer,
+ * non-positive or non-finite start, maxit < 0, tol < 0), QPAT_ERR_STATE (no
+ * sources), QPAT_ERR_NOCONV (a PCG solve), QPAT_ERR_BREAKDOWN (singular 2 x 2
+ * normal matrix or an iterate whose exponential overflows). */
+qpat_status qpat_fit_background(qpat_ctx* ctx, const double* chi, const double* w, double* kappa0,
+                                double* mu0, int32_t maxit, double tol, int32_t* iters,
+                                qpat_info* info);
+
 /* Start priorconditioned LSQR (Sec. 4 eq. (4.10); Algorithm 1 steps 1 and 3)
  * at the last forward point with the last prior:
  *   A = W J, yt = W (chi - h + J beta_lin), iterate x = 0.
@@ -196,6 +217,13 @@ qpat_status qpat_init_guess(qpat_ctx* ctx, const double* chi, double mu0, double
  * qpat_lsqr_step until the next qpat_lsqr_init or qpat_destroy. */
 qpat_status qpat_lsqr_init(qpat_ctx* ctx, const double* chi, const double* w,
                            const double* beta_lin, double* beta_out, qpat_info* info);
+
+/* The zeroth step of Sec. 5: the same priorconditioned LSQR for the diffusion
+ * block alone, A = W J_kt (the first N columns of J), prior M_delta's kt
+ * block M(kt) + delta I, yt = W (chi - h + J [beta_lin[0:N]; 0]). Arguments
+ * as qpat_lsqr_init; beta_out[N:2N] stays 0. qpat_lsqr_step continues it. */
+qpat_status qpat_lsqr_init_kappa(qpat_ctx* ctx, const double* chi, const double* w,
+                                 const double* beta_lin, double* beta_out, qpat_info* info);
 
 /* One LSQR step: one J v, one J^T u, one M_delta^{-1}, scalar recurrences in
  * FP64 on the device. *resnorm_out (host) = |phibar| = ||A x - yt|| in exact

@@ -6,7 +6,13 @@ Initialisation (Algorithm 1 preamble; several illuminations: Sec. 4, the
 paragraph after the algorithm; Sec. 5 Test 1):
   kt_init = 0;  mu_init = mean_k chi_k / phi0_k with phi0_k the fluence of
   the homogeneous (kappa0, mu0);  mt_init = log(mu_init / mu0).
-  (kappa0, mu0) are given (the background fit of the preamble is not done).
+  (kappa0, mu0) are given, or fitted first (fit=True): the homogeneous pair
+  minimising |W (chi - h(log(kappa) 1, log(mu) 1))| (Algorithm 1 preamble),
+  by Gauss-Newton in (log kappa, log mu) -- the paper does not say how the
+  minimiser is found; see fit_background.
+Optional zeroth step (Sec. 5, step0_inner > 0): PLSQR for kt alone with the
+  Jacobian's kt columns and M(kt_init) + delta I, from kt = 0, with the
+  right-hand side W (chi - h + J_kt kt_init); its solution replaces kt_init.
 Each outer step l:
   1. h = h(beta_l), yt = W (chi - h + J beta_l)         (W = Gamma^{-1/2}, diagonal)
   2. M_delta from kt_l, mt_l
@@ -17,9 +23,83 @@ Each outer step l:
 """
 import numpy as np
 
+import scipy.sparse as sp
+
 from .jacobian import Linearisation, params
-from .prior import Prior
+from .prior import Prior, M_of
 from .plsqr import plsqr
+from .solve import make_solver
+
+
+def background_misfit(geo, phi_src, chi, W, kappa, mu, solver="direct", rtol=1e-10):
+    """|W (chi - h(kappa 1, mu 1))|^2 and the homogeneous linearisation."""
+    lin = Linearisation(geo, np.full(geo.N, kappa), np.full(geo.N, mu), phi_src, solver, rtol)
+    return float(np.sum((W * (chi - lin.h)) ** 2)), lin
+
+
+def fit_background(geo, phi_src, chi, W, kappa_start, mu_start, maxit=30, tol=1e-10,
+                   solver="direct", rtol=1e-10):
+    """Gauss-Newton for (a, b) = (log kappa, log mu) minimising
+    F = |W (chi - h(e^a 1, e^b 1))|^2. The columns of the 2-parameter Jacobian
+    are J [1; 0] and J [0; 1] (derivatives in the log-parameters, Appendix);
+    the step solves the linear least-squares problem min |C d - r| with
+    C = [W J[1;0], W J[0;1]], r = W (chi - h). A step longer than 1 in either
+    log is shortened to 1, then halved (at most 30 times) until F does not
+    increase. Stops when the accepted step is <= tol in both logs, when no
+    halving decreases F, or after maxit steps. Returns (kappa0, mu0, iters)."""
+    chi = np.asarray(chi)
+    W = np.asarray(W)
+    N = geo.N
+    a, b = np.log(kappa_start), np.log(mu_start)
+    F, lin = background_misfit(geo, phi_src, chi, W, np.exp(a), np.exp(b), solver, rtol)
+    one, zero = np.ones(N), np.zeros(N)
+    it = 0
+    while it < maxit:
+        c1 = (W * lin.jvp(np.concatenate([one, zero]))).ravel()
+        c2 = (W * lin.jvp(np.concatenate([zero, one]))).ravel()
+        r = (W * (chi - lin.h)).ravel()
+        d = np.linalg.lstsq(np.column_stack([c1, c2]), r, rcond=None)[0]
+        d = d / max(1.0, np.abs(d).max())
+        t = 1.0
+        for _ in range(31):
+            Fn, lin_n = background_misfit(geo, phi_src, chi, W, np.exp(a + t * d[0]), np.exp(b + t * d[1]),
+                                          solver, rtol)
+            if Fn <= F:
+                break
+            t *= 0.5
+        else:
+            break
+        a, b, F, lin = a + t * d[0], b + t * d[1], Fn, lin_n
+        it += 1
+        if np.abs(t * d).max() <= tol:
+            break
+    return float(np.exp(a)), float(np.exp(b)), it
+
+
+def step0(geo, phi_src, chi, W, kappa0, mu0, beta_init, inner, T=5e-3, delta=1e-6,
+          solver="direct", rtol=1e-10, m0=None, tau=None, prior="pm", q=1.0):
+    """Zeroth step of Sec. 5: PLSQR on A = W J_kt (the kt columns of J at
+    beta_init) with prior M(kt_init) + delta I (N x N), right-hand side
+    W (chi - h + J_kt kt_init), from 0. Returns (beta with kt replaced, history)."""
+    chi = np.asarray(chi)
+    W = np.asarray(W)
+    N = geo.N
+    kappa, mu = params(kappa0, mu0, beta_init)
+    lin = Linearisation(geo, kappa, mu, phi_src, solver, rtol)
+    zero = np.zeros(N)
+    kt = np.asarray(beta_init[:N])
+    yt = (W * (chi - lin.h + lin.jvp(np.concatenate([kt, zero])))).ravel()
+    Mk = (M_of(geo, kt, T, prior, q) + delta * sp.identity(N)).tocsr()
+    n_ill = lin.n_ill
+
+    def A(v):
+        return (W * lin.jvp(np.concatenate([v, zero]))).ravel()
+
+    def At(u):
+        return lin.vjp(W * u.reshape(n_ill, N))[:N]
+
+    it = plsqr(A, At, make_solver(Mk, solver, rtol), yt, inner, m0, tau)
+    return np.concatenate([it.x, np.asarray(beta_init[N:])]), list(it.history)
 
 
 def initial_guess(geo, phi_src, chi, kappa0, mu0, solver="direct", rtol=1e-10):
@@ -32,13 +112,20 @@ def initial_guess(geo, phi_src, chi, kappa0, mu0, solver="direct", rtol=1e-10):
 
 def reconstruct(geo, phi_src, chi, W, kappa0, mu0, outer, inner, T=5e-3,
                 b_over_a=1.0, delta=1e-6, solver="direct", rtol=1e-10,
-                beta0=None, stop_on_reject=False, m0=None, tau=None, prior="pm", q=1.0):
+                beta0=None, stop_on_reject=False, m0=None, tau=None, prior="pm", q=1.0,
+                fit=False, step0_inner=0):
     chi = np.asarray(chi)
     W = np.asarray(W)
     N = geo.N
+    log = dict(res_nl=[], lsqr=[], rejected=[])
+    if fit:
+        kappa0, mu0, log["fit_iters"] = fit_background(geo, phi_src, chi, W, kappa0, mu0, solver=solver, rtol=rtol)
+    log["kappa0"], log["mu0"] = kappa0, mu0
     beta = initial_guess(geo, phi_src, chi, kappa0, mu0, solver, rtol) if beta0 is None \
         else np.array(beta0, dtype=np.float64)
-    log = dict(res_nl=[], lsqr=[], rejected=[])
+    if step0_inner > 0:
+        beta, log["step0"] = step0(geo, phi_src, chi, W, kappa0, mu0, beta, step0_inner, T, delta, solver, rtol,
+                                   m0, tau, prior, q)
     lin = None
     for l in range(outer):
         kappa, mu = params(kappa0, mu0, beta)

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <algorithm>
 
+#include <functional>
 #include <thread>
 
 #include "qpat_internal.h"
@@ -493,19 +494,142 @@ qpat_status qpat_init_guess(qpat_ctx* c, const double* chi, double mu0, double* 
     return QPAT_OK;
 }
 
-qpat_status qpat_lsqr_init(qpat_ctx* c, const double* chi, const double* w, const double* beta_lin,
-                           double* beta_out, qpat_info* info) {
+static qpat_status lsqr_init_common(qpat_ctx* c, const double* chi, const double* w, const double* beta_lin,
+                                    double* beta_out, qpat_info* info, bool kappa_only) {
     if (!c) return QPAT_ERR_ARG;
     DeviceGuard g(c->device);
     if (!chi || !w || !beta_out) return fail(c, QPAT_ERR_ARG, "lsqr_init: null pointer");
     if (!c->have_forward || !c->have_prior)
         return fail(c, QPAT_ERR_STATE, "lsqr_init: needs qpat_forward and qpat_prior_setup");
     c->lsqr_ready = false;
+    c->ls_kappa_only = kappa_only;
     if (c->opts.lsqr_reorth) QPAT_TRY(alloc_bases(c));
     c->lx = beta_out;
     QPAT_TRY(lsqr_init_core(c, chi, w, beta_lin));
     c->lsqr_ready = true;
     fill_info(info, SolveStats());
+    return QPAT_OK;
+}
+
+qpat_status qpat_lsqr_init(qpat_ctx* c, const double* chi, const double* w, const double* beta_lin,
+                           double* beta_out, qpat_info* info) {
+    return lsqr_init_common(c, chi, w, beta_lin, beta_out, info, false);
+}
+
+qpat_status qpat_lsqr_init_kappa(qpat_ctx* c, const double* chi, const double* w, const double* beta_lin,
+                                 double* beta_out, qpat_info* info) {
+    return lsqr_init_common(c, chi, w, beta_lin, beta_out, info, true);
+}
+
+// Background fit of Algorithm 1's preamble: (log kappa, log mu) by Gauss-Newton
+// on |W (chi - h(kappa 1, mu 1))|^2. The two Jacobian columns are J [1; 0] and
+// J [0; 1] at the current homogeneous point (d/dlog kappa = kappa d/dkappa).
+// A step longer than 1 in either log is shortened to 1, and halved (up to 30
+// times) until the misfit does not increase; the fit stops when the accepted
+// step is at most tol in both logs, or when no halving decreases the misfit.
+qpat_status qpat_fit_background(qpat_ctx* c, const double* chi, const double* w, double* kappa0, double* mu0,
+                                int32_t maxit, double tol, int32_t* iters, qpat_info* info) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!chi || !w || !kappa0 || !mu0 || !(*kappa0 > 0.0) || !(*mu0 > 0.0) || !std::isfinite(*kappa0) ||
+        !std::isfinite(*mu0) || maxit < 0 || !(tol >= 0.0))
+        return fail(c, QPAT_ERR_ARG, "fit_background: need chi, w, finite kappa0, mu0 > 0, maxit >= 0, tol >= 0");
+    if (c->n_ill == 0) return fail(c, QPAT_ERR_STATE, "fit_background: call qpat_set_sources first");
+    const int64_t N = c->N, nd = N * c->n_ill;
+    double *zero = nullptr, *s1 = nullptr, *s2 = nullptr, *j1 = nullptr, *j2 = nullptr, *rr = nullptr;
+    auto release = [&]() {
+        for (double* p : {zero, s1, s2, j1, j2, rr})
+            if (p) (void)dfree(c, p);
+    };
+    struct Guard {
+        std::function<void()> f;
+        ~Guard() { f(); }
+    } guard{release};
+    QPAT_TRY(dalloc(c, &zero, 2 * N));
+    QPAT_TRY(dalloc(c, &s1, 2 * N));
+    QPAT_TRY(dalloc(c, &s2, 2 * N));
+    QPAT_TRY(dalloc(c, &j1, nd));
+    QPAT_TRY(dalloc(c, &j2, nd));
+    QPAT_TRY(dalloc(c, &rr, nd));
+    QPAT_TRY(zero_fill(c, zero, 2 * N));
+    QPAT_TRY(zero_fill(c, s1 + N, N));
+    QPAT_TRY(zero_fill(c, s2, N));
+    QPAT_TRY(exp_params(c, 1.0, 1.0, zero));   // kappa = mu = 1: the all-ones halves of s1, s2
+    QPAT_HIP(c, hipMemcpyAsync(s1, c->kappa, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    QPAT_HIP(c, hipMemcpyAsync(s2 + N, c->mu, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    SolveStats st;
+    c->have_forward = false;
+    c->lsqr_ready = false;
+    // misfit^2 at the homogeneous point (exp a, exp b); leaves the forward state there
+    auto evaluate = [&](double a, double b, double* F) -> qpat_status {
+        const double k = std::exp(a), m = std::exp(b);
+        if (!(k > 0.0) || !(m > 0.0) || !std::isfinite(k) || !std::isfinite(m))
+            return fail(c, QPAT_ERR_BREAKDOWN, "fit_background: the iterate left the positive reals");
+        c->have_forward = false;
+        QPAT_TRY(exp_params(c, k, m, zero));
+        QPAT_TRY(assemble_K(c));
+        QPAT_TRY(lattice_convert(c, Op::K));
+        QPAT_TRY(mg_setup(c, Op::K));
+        QPAT_TRY(forward_solve(c, &st));
+        if (st.noconv)
+            return fail(c, QPAT_ERR_NOCONV, "fit_background: PCG did not converge (relres %.3e)", st.relres_max);
+        c->have_forward = true;
+        double r = 0.0;
+        QPAT_TRY(misfit_core(c, chi, w, &r));
+        *F = r * r;
+        return QPAT_OK;
+    };
+    double a = std::log(*kappa0), b = std::log(*mu0), F = 0.0;
+    QPAT_TRY(evaluate(a, b, &F));
+    int it = 0;
+    bool at_ab = true;
+    for (; it < maxit; ++it) {
+        SolveStats sj;
+        QPAT_TRY(jvp_core(c, s1, 0, j1, &sj));
+        QPAT_TRY(jvp_core(c, s2, 0, j2, &sj));
+        if (sj.noconv) return fail(c, QPAT_ERR_NOCONV, "fit_background: PCG did not converge in J");
+        st.n_solves += sj.n_solves;
+        st.iters_sum += sj.iters_sum;
+        st.iters_max = std::max(st.iters_max, sj.iters_max);
+        st.relres_max = std::max(st.relres_max, sj.relres_max);
+        double S[6];
+        QPAT_TRY(fit_sums(c, chi, w, j1, j2, rr, S));
+        const double det = S[0] * S[2] - S[1] * S[1];
+        if (!(det > 0.0) || !std::isfinite(det))
+            return fail(c, QPAT_ERR_BREAKDOWN, "fit_background: singular Gauss-Newton matrix");
+        double da = (S[2] * S[3] - S[1] * S[4]) / det, db = (S[0] * S[4] - S[1] * S[3]) / det;
+        const double len = std::max(std::fabs(da), std::fabs(db));
+        if (len > 1.0) {
+            da /= len;
+            db /= len;
+        }
+        double t = 1.0, Fn = 0.0;
+        bool accepted = false;
+        for (int h = 0; h <= 30; ++h, t *= 0.5) {
+            QPAT_TRY(evaluate(a + t * da, b + t * db, &Fn));
+            if (Fn <= F) {
+                accepted = true;
+                break;
+            }
+        }
+        if (!accepted) {
+            at_ab = false;
+            break;
+        }
+        a += t * da;
+        b += t * db;
+        F = Fn;
+        if (std::max(std::fabs(t * da), std::fabs(t * db)) <= tol) {
+            ++it;
+            break;
+        }
+    }
+    if (!at_ab) QPAT_TRY(evaluate(a, b, &F));   // leave the forward state at the returned point
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    *kappa0 = std::exp(a);
+    *mu0 = std::exp(b);
+    if (iters) *iters = it;
+    fill_info(info, st);
     return QPAT_OK;
 }
 

@@ -278,7 +278,49 @@ __global__ void k_init_guess(int64_t N, int n_ill, int n_pad, const double* __re
 
 inline dim3 grid1(int64_t n) { return dim3(grid_for(n, kThreads, 8192)); }
 
+// background fit: rr = W (chi - mu phi) and j1, j2 scaled by W, all [n_ill][N]
+__global__ void k_fit_weight(int64_t N, int n_ill, int n_pad, const double* __restrict__ chi,
+                             const double* __restrict__ w, const double* __restrict__ mu,
+                             const double* __restrict__ phi, double* __restrict__ j1, double* __restrict__ j2,
+                             double* __restrict__ rr) {
+    const int64_t n = N * n_ill;
+    for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = e % N;
+        const int k = static_cast<int>(e / N);
+        const double we = w[e];
+        rr[e] = we * (chi[e] - mu[i] * phi[i * n_pad + k]);
+        j1[e] *= we;
+        j2[e] *= we;
+    }
+}
+
+__global__ void k_fill0(int64_t n, double* __restrict__ p) {
+    for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads)
+        p[e] = 0.0;
+}
+
 }  // namespace
+
+qpat_status zero_fill(qpat_ctx* c, double* p, int64_t n) {
+    hipLaunchKernelGGL(k_fill0, grid1(n), dim3(kThreads), 0, c->stream, n, p);
+    QPAT_HIP(c, hipGetLastError());
+    return QPAT_OK;
+}
+
+qpat_status fit_sums(qpat_ctx* c, const double* chi, const double* w, double* j1, double* j2, double* rr,
+                     double out[6]) {
+    const int64_t n = c->N * c->n_ill;
+    hipLaunchKernelGGL(k_fit_weight, grid1(n), dim3(kThreads), 0, c->stream, c->N, c->n_ill, c->n_pad, chi, w,
+                       c->mu, c->phi, j1, j2, rr);
+    const double* a[6] = {j1, j1, j2, j1, j2, rr};
+    const double* b[6] = {j1, j2, j2, rr, rr, rr};
+    for (int q = 0; q < 6; ++q) QPAT_TRY(dot(c, a[q], b[q], n, c->red_out + 16 + q));
+    QPAT_HIP(c, hipMemcpyAsync(c->red_host + 16, c->red_out + 16, 6 * sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    for (int q = 0; q < 6; ++q) out[q] = c->red_host[16 + q];
+    return QPAT_OK;
+}
 
 qpat_status dot(qpat_ctx* c, const double* a, const double* b, int64_t n, double* dev_out) {
     const int nb = grid_for(n, kThreads * 8, kRedBlocks);
@@ -341,7 +383,13 @@ qpat_status lsqr_init_core(qpat_ctx* c, const double* chi, const double* w, cons
     SolveStats st;
     const double* Jb = nullptr;
     if (beta_lin) {
-        QPAT_TRY(jvp_core(c, beta_lin, 2, c->dvec, &st));
+        const double* bl = beta_lin;
+        if (c->ls_kappa_only) {   // J [kt; 0]: c->lr is free until the first M_delta solve
+            hipLaunchKernelGGL(k_copy, grid1(c->N), dim3(kThreads), 0, c->stream, c->N, beta_lin, c->lr);
+            QPAT_TRY(zero_fill(c, c->lr + c->N, c->N));
+            bl = c->lr;
+        }
+        QPAT_TRY(jvp_core(c, bl, 2, c->dvec, &st));
         Jb = c->dvec;
     }
     hipLaunchKernelGGL(k_lsqr_rhs, dim3(grid_for(nd, kThreads, 1 << 30)), dim3(kThreads), 0, c->stream, c->N,
@@ -350,6 +398,7 @@ qpat_status lsqr_init_core(qpat_ctx* c, const double* chi, const double* w, cons
     hipLaunchKernelGGL(k_ls_init_beta, dim3(1), dim3(64), 0, c->stream, c->ls, c->red_out);
     hipLaunchKernelGGL(k_ls_scale_u, grid1(nd), dim3(kThreads), 0, c->stream, c->ls, nd, c->lq, c->lu, 1);
     QPAT_TRY(vjp_core(c, nullptr, 1, c->lp, &st));
+    if (c->ls_kappa_only) QPAT_TRY(zero_fill(c, c->lp + c->N, c->N));
     QPAT_TRY(prior_solve_core(c, c->lp, c->lr, &st));
     QPAT_TRY(dot(c, c->lp, c->lr, n2, c->red_out));
     hipLaunchKernelGGL(k_ls_init_alpha, dim3(1), dim3(64), 0, c->stream, c->ls, c->red_out);
@@ -386,6 +435,7 @@ qpat_status lsqr_step_core(qpat_ctx* c, SolveStats* st) {
     hipLaunchKernelGGL(k_ls_scale_u, grid1(nd), dim3(kThreads), 0, c->stream, c->ls, nd, c->lq, c->lu, 0);
     // p = W^T... : p = J^T (W u) - beta what
     QPAT_TRY(vjp_core(c, nullptr, 2, c->lp, st));
+    if (c->ls_kappa_only) QPAT_TRY(zero_fill(c, c->lp + c->N, c->N));
     if (ro) QPAT_TRY(reorth(c, c->lp, n2, c->V, c->WH, n2, c->nbasis));
     QPAT_TRY(prior_solve_core(c, c->lp, c->lr, st));
     QPAT_TRY(dot(c, c->lp, c->lr, n2, c->red_out));

@@ -218,6 +218,7 @@ struct qpat_ctx {
     double* WH = nullptr;          // [max_steps+1][2N]
     int32_t basis_cap = 0;
     int32_t nbasis = 0;
+    bool ls_kappa_only = false;    // LSQR over the kt block only (step 0 of Sec. 5), fixed at init
     bool reorth_on = false;        // reorthogonalisation state fixed at qpat_lsqr_init
     double* coef = nullptr;        // [max_steps+1] Gram-Schmidt coefficients
     qpat::LsqrScal* ls = nullptr;
@@ -364,6 +365,13 @@ qpat_status lsqr_init_core(qpat_ctx* c, const double* chi, const double* w, cons
 qpat_status lsqr_step_core(qpat_ctx* c, SolveStats* st);
 qpat_status misfit_core(qpat_ctx* c, const double* chi, const double* w, double* out);
 qpat_status init_guess_core(qpat_ctx* c, const double* chi, double mu0, double* beta_out);
+// Gauss-Newton sums of the background fit: with r = W (chi - h) and the
+// whitened columns W j1, W j2 ([n_ill][N], scaled in place), out[0..5] =
+// (Wj1.Wj1, Wj1.Wj2, Wj2.Wj2, Wj1.r, Wj2.r, r.r) on the host.
+qpat_status fit_sums(qpat_ctx* c, const double* chi, const double* w, double* j1, double* j2, double* rr,
+                     double out[6]);
+// zero [n] doubles on the context's stream (a kernel, not a memset node)
+qpat_status zero_fill(qpat_ctx* c, double* p, int64_t n);
 qpat_status prior_apply_core(qpat_ctx* c, const double* x, double* y);
 qpat_status prior_solve_core(qpat_ctx* c, const double* p, double* r, SolveStats* st);
 

@@ -4,9 +4,13 @@ Host control flow only: every vector operation is a libqpat call (forward
 solve, misfit, initial guess, prior assembly, LSQR). The host sees scalars
 (residual norms) and decides what to call next.
 
+  fit   : optionally the homogeneous (kappa0, mu0) minimising |W (chi - h)|
+          (preamble; qpat_fit_background)
   init  : kt = 0, mt = log(mean_k chi_k / phi0_k / mu0), phi0 the fluence of
           the homogeneous (kappa0, mu0) (preamble; several illuminations:
           paragraph after Algorithm 1 and Sec. 5)
+  step 0: optionally PLSQR for kt alone with M(kt_init) + delta I (Sec. 5;
+          qpat_lsqr_init_kappa); its solution replaces kt_init
   step 1: h = h(beta_l); yt = W (chi - h + J beta_l)     (inside qpat_lsqr_init)
   step 2: M_delta from kt_l, mt_l                          (qpat_prior_setup)
   step 3: PLSQR from 0: `inner` steps, or until r_m <= tau over a window of
@@ -27,31 +31,30 @@ def window_ratio(history, m, m0):
 
 
 def reconstruct(ctx, chi, W, kappa0, mu0, outer, inner, T=5e-3, b_over_a=1.0, delta=1e-6,
-                beta0=None, stop_on_reject=False, m0=None, tau=None, prior="pm", q=1.0):
-    """prior: "pm" (Perona-Malik) or "tvq" (r(t) = T^(2-q) (t^2 + T^2)^(q/2) / q)."""
+                beta0=None, stop_on_reject=False, m0=None, tau=None, prior="pm", q=1.0,
+                fit=False, step0_inner=0):
+    """prior: "pm" (Perona-Malik) or "tvq" (r(t) = T^(2-q) (t^2 + T^2)^(q/2) / q).
+    fit: first fit the homogeneous (kappa0, mu0) to the data (qpat_fit_background),
+    starting from the given pair; the pair used is returned in log["kappa0"], log["mu0"].
+    step0_inner > 0: the zeroth step of Sec. 5 (PLSQR for kt alone, qpat_lsqr_init_kappa)
+    with at most that many steps (and the window rule when m0, tau are given)."""
     kind = {"pm": 0, "tvq": 1}[prior]
     N = ctx.N
     dev = chi.device
     beta = torch.zeros(2 * N, dtype=torch.float64, device=dev)
     beta_new = torch.zeros_like(beta)
-    if beta0 is None:
-        ctx.forward_log(kappa0, mu0, beta)          # homogeneous (kappa0, mu0)
-        ctx.init_guess(chi, mu0, beta)
-    else:
-        beta.copy_(beta0)
     log = {"res_nl": [], "lsqr": [], "rejected": [], "pcg_iters": []}
-    ctx.forward_log(kappa0, mu0, beta)
-    res = ctx.misfit(chi, W)
-    for _ in range(outer):
-        log["res_nl"].append(res)
+
+    def setup_prior(b):
         if kind == 0:
-            ctx.prior_setup(beta[:N], beta[N:], T, b_over_a, delta)
+            ctx.prior_setup(b[:N], b[N:], T, b_over_a, delta)
         else:
-            ctx.prior_setup_r(beta[:N], beta[N:], kind, T, q, b_over_a, delta)
-        ctx.lsqr_init(chi, W, beta, beta_new)
+            ctx.prior_setup_r(b[:N], b[N:], kind, T, q, b_over_a, delta)
+
+    def run_lsqr(count):
         hist = [ctx.lsqr_residual()]
         iters = 0
-        for m in range(1, inner + 1):
+        for m in range(1, count + 1):
             r, info = ctx.lsqr_step()
             hist.append(r)
             iters += info["iters_sum"]
@@ -59,6 +62,29 @@ def reconstruct(ctx, chi, W, kappa0, mu0, outer, inner, T=5e-3, b_over_a=1.0, de
                 rm = window_ratio(hist, m, m0)
                 if rm is not None and rm <= tau:
                     break
+        return hist, iters
+
+    if fit:
+        kappa0, mu0, log["fit_iters"], _ = ctx.fit_background(chi, W, kappa0, mu0)
+    log["kappa0"], log["mu0"] = kappa0, mu0
+    if beta0 is None:
+        ctx.forward_log(kappa0, mu0, beta)          # homogeneous (kappa0, mu0)
+        ctx.init_guess(chi, mu0, beta)
+    else:
+        beta.copy_(beta0)
+    if step0_inner > 0:
+        ctx.forward_log(kappa0, mu0, beta)
+        setup_prior(beta)
+        ctx.lsqr_init_kappa(chi, W, beta, beta_new)
+        log["step0"], _ = run_lsqr(step0_inner)
+        beta[:N] = beta_new[:N]
+    ctx.forward_log(kappa0, mu0, beta)
+    res = ctx.misfit(chi, W)
+    for _ in range(outer):
+        log["res_nl"].append(res)
+        setup_prior(beta)
+        ctx.lsqr_init(chi, W, beta, beta_new)
+        hist, iters = run_lsqr(inner)
         log["lsqr"].append(hist)
         log["pcg_iters"].append(iters)
         ctx.forward_log(kappa0, mu0, beta_new)

@@ -78,6 +78,9 @@ SIGNATURES = {
     "qpat_vjp": (_S, [_P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_prior_setup": (_S, [_P, _P, _P, _D, _D, _D]),
     "qpat_prior_setup_r": (_S, [_P, _P, _P, _I32, _D, _D, _D, _D]),
+    "qpat_fit_background": (_S, [_P, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D), _I32, _D,
+                                 ctypes.POINTER(_I32), ctypes.POINTER(Info)]),
+    "qpat_lsqr_init_kappa": (_S, [_P, _P, _P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_prior_apply": (_S, [_P, _P, _P]),
     "qpat_prior_solve": (_S, [_P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_misfit": (_S, [_P, _P, _P, ctypes.POINTER(_D)]),
@@ -328,6 +331,29 @@ class Context:
     def init_guess(self, chi, mu0, beta_out):
         self._check(_lib.qpat_init_guess(self._h, _ptr(chi, torch.float64, self.n_ill * self.N, "chi"),
                                          float(mu0), _ptr(beta_out, torch.float64, 2 * self.N, "beta_out")))
+
+    def fit_background(self, chi, w, kappa0, mu0, maxit=30, tol=1e-10):
+        """Homogeneous (kappa0, mu0) minimising |W (chi - h)|; returns (kappa0, mu0, iters, info)."""
+        nd = self.n_ill * self.N
+        k = ctypes.c_double(kappa0)
+        m = ctypes.c_double(mu0)
+        it = ctypes.c_int32(0)
+        info = Info()
+        self._check(_lib.qpat_fit_background(self._h, _ptr(chi, torch.float64, nd, "chi"),
+                                             _ptr(w, torch.float64, nd, "w"), ctypes.byref(k), ctypes.byref(m),
+                                             int(maxit), float(tol), ctypes.byref(it), ctypes.byref(info)))
+        return k.value, m.value, it.value, info.as_dict()
+
+    def lsqr_init_kappa(self, chi, w, beta_lin, beta_out):
+        info = Info()
+        nd = self.n_ill * self.N
+        self._beta_out = beta_out
+        self._check(_lib.qpat_lsqr_init_kappa(self._h, _ptr(chi, torch.float64, nd, "chi"),
+                                              _ptr(w, torch.float64, nd, "w"),
+                                              _ptr(beta_lin, torch.float64, 2 * self.N, "beta_lin", True),
+                                              _ptr(beta_out, torch.float64, 2 * self.N, "beta_out"),
+                                              ctypes.byref(info)))
+        return info.as_dict()
 
     def lsqr_init(self, chi, w, beta_lin, beta_out):
         info = Info()

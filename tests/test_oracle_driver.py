@@ -67,3 +67,73 @@ def test_stop_on_reject_returns_previous_iterate():
                             beta0=beta0, stop_on_reject=True)
     assert log["rejected"] == [True]
     assert np.array_equal(beta, beta0)
+
+
+def test_fit_recovers_a_homogeneous_pair():
+    """Noiseless data of a homogeneous medium (kappa*, mu*) other than the start:
+    the background fit of the preamble returns (kappa*, mu*)."""
+    from oracle.driver import fit_background
+    P = make_problem("T4", phantom="background")
+    g = fem.geometry(P.mesh.coords, P.mesh.tets, P.mesh.bfaces)
+    ks, ms = 1.3 * P.kappa0, 0.8 * P.mu0
+    h = Linearisation(g, np.full(g.N, ks), np.full(g.N, ms), P.phi_src).h
+    k, m, it = fit_background(g, P.phi_src, h, 1.0 / np.abs(h), P.kappa0, P.mu0)
+    assert abs(k / ks - 1) < 1e-9 and abs(m / ms - 1) < 1e-9, (k, m, it)
+    assert 2 <= it < 30
+
+
+def test_fit_matches_scipy_least_squares():
+    """The fitted pair is the minimiser that a different method finds: SciPy's
+    Levenberg-Marquardt on the same two-parameter residual, with a finite-difference
+    Jacobian (no use of J)."""
+    from scipy.optimize import least_squares
+    from oracle.driver import fit_background
+    P = make_problem("T4")
+    g = fem.geometry(P.mesh.coords, P.mesh.tets, P.mesh.bfaces)
+    chi, W, _ = simulate(P, g)
+    k, m, _ = fit_background(g, P.phi_src, chi, W, P.kappa0, P.mu0)
+
+    def resid(x):
+        lin = Linearisation(g, np.full(g.N, np.exp(x[0])), np.full(g.N, np.exp(x[1])), P.phi_src)
+        return (W * (chi - lin.h)).ravel()
+
+    sol = least_squares(resid, np.log([P.kappa0, P.mu0]), method="lm", jac="2-point",
+                        xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    assert abs(k / np.exp(sol.x[0]) - 1) < 1e-6 and abs(m / np.exp(sol.x[1]) - 1) < 1e-6, (k, m, sol.x)
+    # the fit moved off the configured background: the data's mean level differs from it
+    assert abs(m / P.mu0 - 1) > 1e-3
+
+
+def test_step0_is_lsqr_on_the_kappa_block():
+    """Step 0 of Sec. 5 on a 4^3 problem against textbook LSQR (SciPy) on the dense
+    A L^{-1}, with A = W J_kt built column by column from J (brute force), L the
+    Cholesky factor of M(kt_init) + delta I, the right-hand side
+    W (chi - h + A kt_init) and the result mapped back by L^{-1}; mt is untouched."""
+    from scipy.sparse.linalg import lsqr
+    from oracle.driver import step0
+    from oracle.jacobian import params
+    from oracle import prior
+    P = make_problem("T4")
+    g = fem.geometry(P.mesh.coords, P.mesh.tets, P.mesh.bfaces)
+    N = g.N
+    chi, W, _ = simulate(P, g)
+    beta = initial_guess(g, P.phi_src, chi, P.kappa0, P.mu0)
+    beta[:N] = 0.05 * np.sin(np.arange(N))          # a non-zero kt_init
+    lin = Linearisation(g, *params(P.kappa0, P.mu0, beta), P.phi_src)
+    cols = []
+    for j in range(N):
+        e = np.zeros(2 * N)
+        e[j] = 1.0
+        cols.append((W * lin.jvp(e)).ravel())
+    A = np.column_stack(cols)
+    yt = (W * (chi - lin.h)).ravel() + A @ beta[:N]
+    Mk = prior.M_of(g, beta[:N], METHOD["T"]).toarray() + METHOD["delta"] * np.eye(N)
+    Linv = np.linalg.inv(np.linalg.cholesky(Mk).T)
+    # a graded operator: plain LSQR (SciPy's, without reorthogonalisation) stays
+    # accurate only for the first steps, as for the full problem
+    for m in (1, 2):
+        ref = Linv @ lsqr(A @ Linv, yt, atol=0, btol=0, conlim=0, iter_lim=m)[0]
+        out, hist = step0(g, P.phi_src, chi, W, P.kappa0, P.mu0, beta, m, METHOD["T"], METHOD["delta"])
+        assert np.linalg.norm(out[:N] - ref) <= 1e-9 * np.linalg.norm(ref), m
+        assert np.array_equal(out[N:], beta[N:])
+        assert abs(np.linalg.norm(A @ out[:N] - yt) - hist[-1]) <= 1e-9 * hist[-1]
