@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--train-phantoms", type=int, default=125)
     ap.add_argument("--held-phantoms", type=int, default=13)
     ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--no-init", action="store_true",
+                    help="skip the background fit, step 0 and TV-prior measurements")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -247,6 +249,55 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    # ---- Algorithm 1's initialisation (background fit, step 0) and the TV prior
+    init = None
+    if not args.no_init and args.lsqr_steps > 0:
+        init = {}
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        k0, m0, fit_it, finf = ctx.fit_background(d(chi), d(W), 1.5 * P.kappa0, 0.7 * P.mu0)
+        torch.cuda.synchronize()
+        init["fit_s"] = round(time.perf_counter() - a, 4)
+        init["fit"] = {"start": [1.5 * P.kappa0, 0.7 * P.mu0], "kappa0": k0, "mu0": m0, "gauss_newton_iters": fit_it,
+                       "pcg_solves": finf["n_solves"], "pcg_iters_sum": finf["iters_sum"]}
+        beta0 = torch.zeros(2 * N, dtype=torch.float64, device=dev)
+        ctx.init_guess(d(chi), m0, beta0)                  # the context is at the fitted pair
+        ctx.forward_log(k0, m0, beta0)
+        ctx.prior_setup(beta0[:N], beta0[N:])
+        x0 = torch.zeros(2 * N, dtype=torch.float64, device=dev)
+        ctx.lsqr_init_kappa(d(chi), d(W), beta0, x0)
+        ctx.lsqr_step()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.lsqr_steps):
+            ctx.lsqr_step()
+        torch.cuda.synchronize()
+        init["step0_s_per_iter"] = round((time.perf_counter() - a) / args.lsqr_steps, 4)
+        ctx.prior_setup_r(d(kt), d(mt), qpat.PRIOR_TVQ, 5e-3, 1.0)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        tinf = ctx.prior_solve(d(s_np), torch.empty(2 * N, dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+        init["tv_prior_solve_s"] = round(time.perf_counter() - a, 4)
+        init["tv_prior_iters"] = tinf["iters_max"]
+        log("initialisation", init)
+
+    # ---- measured bandwidth ceiling: STREAM triad a = b + s c in FP64 (3 x 512 MiB)
+    n_tr = (512 << 20) // 8
+    tb = torch.ones(n_tr, dtype=torch.float64, device=dev)
+    tc = torch.ones_like(tb)
+    ta = torch.empty_like(tb)
+    for _ in range(2):
+        torch.add(tb, tc, alpha=3.0, out=ta)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        torch.add(tb, tc, alpha=3.0, out=ta)
+    e1.record()
+    torch.cuda.synchronize()
+    triad_gbs = 3 * n_tr * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del ta, tb, tc
+
     # ---- roofline of the dominant kernel (live HIP-event timing)
     layout = ctx.operator_layout()
     timed = {k: kst[k] for k in MG_KERNELS if kst[k]["launches"]}
@@ -266,6 +317,8 @@ def main():
                     "GB/s": round(mg_algorithmic_bytes(k, N, layout, v, kst) / v["total_ms"] / 1e6, 1)}
                     for k, v in timed.items() if k != key}}
     roofline["traffic"] = measured_traffic(name)
+    roofline["stream_triad_GBs"] = round(triad_gbs, 1)
+    roofline["frac_of_triad"] = round(achieved / triad_gbs, 4)
     log("roofline", roofline)
 
     # ---- CPU oracle on a bounded sample of the same system
@@ -300,6 +353,7 @@ def main():
                       "tangent_max": infos[-1][0]["iters_max"], "adjoint_max": infos[-1][1]["iters_max"],
                       "prior": pinfo["iters_max"]},
         "plain": plain,
+        "init": init,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
