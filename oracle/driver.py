@@ -156,3 +156,13 @@ def reconstruct(geo, phi_src, chi, W, kappa0, mu0, outer, inner, T=5e-3,
         beta, lin = beta_new, lin_new
     log["res_nl"].append(np.linalg.norm(W * (chi - lin.h)) if lin is not None else None)
     return beta, log
+
+
+def finer_mesh_data(geo_fine, kappa_fine, mu_fine, phi_src_fine, inj, solver="direct", rtol=1e-10):
+    """Noiseless data without the obvious inverse crime (Sec. 2, the footnote on
+    the measurement model; Sec. 5): H = mu phi computed with P1 elements on a
+    denser mesh, then its nodal values at the reconstruction mesh's nodes. On
+    nested Kuhn meshes every coarse node is a fine node, so interpolation is the
+    index map inj. Returns [n_ill][N_coarse]."""
+    lin = Linearisation(geo_fine, kappa_fine, mu_fine, phi_src_fine, solver, rtol)
+    return lin.h[:, inj]

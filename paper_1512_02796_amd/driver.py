@@ -99,3 +99,13 @@ def reconstruct(ctx, chi, W, kappa0, mu0, outer, inner, T=5e-3, b_over_a=1.0, de
         res = res_new
     log["res_nl"].append(res)
     return beta, log
+
+
+def finer_mesh_data(ctx_fine, kappa_fine, mu_fine, inj):
+    """Noiseless data without the obvious inverse crime: h = mu phi from the
+    forward solves of a context on the 2n mesh (qpat_forward), read at the
+    reconstruction mesh's nodes (inj: their indices among the fine nodes, a
+    device int64 tensor). Returns [n_ill][N_coarse] on the device."""
+    h = torch.empty(ctx_fine.n_ill * ctx_fine.N, dtype=torch.float64, device=kappa_fine.device)
+    ctx_fine.forward(kappa_fine, mu_fine, None, h)
+    return h.view(ctx_fine.n_ill, ctx_fine.N).index_select(1, inj).contiguous()

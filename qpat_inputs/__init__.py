@@ -10,7 +10,7 @@ stream 0 = phantom, 1 = noise draws, 2 = test vectors s and t,
 3 = training samples of the learned guess, 4 = held-out samples, 5 = initial
 network weights, 6 = sizes of the batched instances.
 """
-from .mesh import kuhn_mesh, KuhnMesh, FACE_NAMES
+from .mesh import kuhn_mesh, KuhnMesh, FACE_NAMES, coarse_in_fine
 from .phantom import (sphere_phantom, ellipsoid_phantom, background_phantom,
                       kappa_from_optics)
 from .sources import face_sources, gaussian_sources

@@ -46,6 +46,11 @@ CONFIGS = {
                 noise=0.01, outer=2, inner=10, precision="fp64"),
     "T24": dict(id=124, n=24, n_ill=6, source="gauss", phantom="ellipsoids",
                 noise=0.02, outer=2, inner=10, precision="fp64"),
+    # illumination study on a small cube (Sec. 5, second test: 1, 2 or 3 face
+    # illuminations; its inclusion sizes are not given, so two seeded ellipsoids
+    # sized for an 11 mm cube), data simulated on the 2n mesh and injected
+    "S2": dict(id=7, n=32, n_ill=3, source="face", phantom="ellipsoids", L=11.0, count=2,
+               axes=(1.0, 2.5), noise=0.01, outer=3, inner=30, precision="fp64"),
 }
 
 METHOD = dict(T=5e-3, delta=1e-6, b_over_a=1.0, m0=10, tau=1e-2, pcg_rtol=1e-10)
@@ -88,12 +93,14 @@ class Problem:
 
 def make_problem(name, L=40.0, **over):
     c = config(name, **over)
+    L = c.get("L", L)
     mesh = kuhn_mesh(c["n"], L)
     g = rng(c["id"], 0)
     if c["phantom"] == "spheres":
         mua, mus, shapes = sphere_phantom(mesh.coords, g, L=L)
     elif c["phantom"] == "ellipsoids":
-        mua, mus, shapes = ellipsoid_phantom(mesh.coords, g, L=L)
+        kw = {k: c[k] for k in ("count", "axes") if k in c}
+        mua, mus, shapes = ellipsoid_phantom(mesh.coords, g, L=L, **kw)
     elif c["phantom"] == "background":
         mua = np.full(mesh.N, BG_MUA)
         mus = np.full(mesh.N, BG_MUS)

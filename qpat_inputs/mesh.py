@@ -100,3 +100,15 @@ def kuhn_mesh(n: int, L: float = 40.0) -> KuhnMesh:
     bface_tag = np.concatenate(tags)
     return KuhnMesh(n=n, L=float(L), coords=coords, tets=tets,
                     bfaces=bfaces, bface_tag=bface_tag)
+
+
+def coarse_in_fine(n: int) -> np.ndarray:
+    """Node indices, in the Kuhn mesh of 2n voxels per side, of the nodes of the
+    mesh of n voxels per side on the same cube (node (i, j, k) of the coarse
+    lattice is node (2i, 2j, 2k) of the fine one; both x fastest). The coarse
+    Kuhn mesh's nodes are all fine nodes, so evaluating a fine P1 function at
+    the coarse nodes is this index map."""
+    m, mf = n + 1, 2 * n + 1
+    i = 2 * np.arange(m, dtype=np.int64)
+    kk, jj, ii = np.meshgrid(i, i, i, indexing="ij")
+    return (ii + mf * (jj + mf * kk)).ravel()

@@ -165,3 +165,29 @@ def test_algorithm1_with_fit_and_step0():
     assert np.allclose(log["step0"], ref_log["step0"], rtol=1e-6)
     assert np.allclose(log["lsqr"][0], ref_log["lsqr"][0], rtol=1e-6)
     assert rel(host(beta), ref_beta) <= 1e-4
+
+
+def test_finer_mesh_data_matches_oracle():
+    """Inverse-crime-free data (the 12^3 mesh's nodes read from the 24^3 solution) on
+    the library against the oracle, and a short reconstruction from it on both sides."""
+    from paper_1512_02796_amd import qpat
+    from paper_1512_02796_amd.driver import finer_mesh_data, reconstruct
+    from oracle.driver import finer_mesh_data as ofine, reconstruct as oref
+    from qpat_inputs import coarse_in_fine
+    tight = qpat.default_opts(pcg_rtol=1e-12, prior_rtol=1e-12)
+    # the 24^3 K solves stall near a relative residual of 1.3e-12 in FP64
+    F = GpuProblem("T12", qpat.default_opts(pcg_rtol=1e-11), n=24)
+    G = GpuProblem("T12", tight)
+    inj = coarse_in_fine(12)
+    h = finer_mesh_data(F.ctx, F.kappa, F.mu, dev(inj, torch.int64))
+    gf, _ = oracle_of(F.P)
+    ref = ofine(gf, F.P.kappa, F.P.mu, F.P.phi_src, inj)
+    assert rel(host(h), ref) <= 1e-10
+    g, lin = oracle_of(G.P)
+    gap = rel(ref, lin.h)                       # the inverse-crime gap, O(h^2) with jumps
+    assert 1e-4 < gap < 0.2, gap
+    W = 1.0 / (0.01 * np.abs(ref))
+    beta, log = reconstruct(G.ctx, h, dev(W), G.P.kappa0, G.P.mu0, outer=1, inner=6)
+    rbeta, rlog = oref(g, G.P.phi_src, ref, W, G.P.kappa0, G.P.mu0, outer=1, inner=6)
+    assert np.allclose(log["lsqr"][0], rlog["lsqr"][0], rtol=1e-6)
+    assert rel(host(beta), rbeta) <= 1e-4

@@ -85,3 +85,21 @@ def test_problem_seeded_and_physical():
     c1 = make_problem("C1")
     assert c1.mesh.N == 4913 and c1.n_ill == 4
     assert set(np.unique(c1.mu)) <= {0.01, 0.02}
+
+
+def test_coarse_in_fine_maps_nodes_onto_nodes():
+    from qpat_inputs import coarse_in_fine
+    for n in (1, 3, 8):
+        c, f = kuhn_mesh(n, 40.0), kuhn_mesh(2 * n, 40.0)
+        idx = coarse_in_fine(n)
+        assert idx.shape == (c.N,) and len(np.unique(idx)) == c.N
+        assert np.array_equal(f.coords[idx], c.coords)
+
+
+def test_illumination_study_phantom_fits_the_small_cube():
+    """S2: the same shapes at n and 2n (same seed), inside the 11 mm cube."""
+    from qpat_inputs import coarse_in_fine
+    P, Pf = make_problem("S2", n=8), make_problem("S2", n=16)
+    assert P.mesh.coords.max() == 11.0 and P.n_ill == 3
+    assert np.array_equal(Pf.mu[coarse_in_fine(8)], P.mu)
+    assert P.mu.max() > P.mu0 * 1.2        # an inclusion is resolved

@@ -188,3 +188,30 @@ def test_load_matrices_match_coefficient_derivatives():
         assert np.allclose(G1[:, j], -(fem.stiffness(g, e) @ phi), atol=1e-13)
         assert np.allclose(G2[:, j], -(fem.mass(g, e) @ phi), atol=1e-13)
     assert np.allclose(G2, G2.T, atol=1e-15)
+
+
+def test_finer_mesh_data_is_the_fine_solution_at_coarse_nodes():
+    """Data without the obvious inverse crime (simulated on the 2n mesh, read at the
+    coarse nodes) for the closed form exp(-kx): it carries the fine mesh's O((h/2)^2)
+    nodal error, a quarter of the coarse mesh's own. A wrong node map would leave an
+    O(1) error."""
+    from qpat_inputs import coarse_in_fine
+    from oracle.jacobian import Linearisation
+    from oracle.driver import finer_mesh_data
+    kap, mu, n = 1 / 3.03, 0.01, 8
+    k = np.sqrt(mu / kap)
+
+    def robin(m):
+        pts = m.coords[m.bfaces]
+        e = np.exp(-k * pts[..., 0])
+        return (0.25 * e + 0.5 * kap * (-k * e * NORMALS[m.bface_tag][:, None, 0]))[None]
+
+    mc, mf = kuhn_mesh(n, L), kuhn_mesh(2 * n, L)
+    gc, gf = geo_of(mc), geo_of(mf)
+    hc = Linearisation(gc, np.full(mc.N, kap), np.full(mc.N, mu), robin(mc)).h[0]
+    hf = finer_mesh_data(gf, np.full(mf.N, kap), np.full(mf.N, mu), robin(mf), coarse_in_fine(n))[0]
+    exact = mu * np.exp(-k * mc.coords[:, 0])
+    ec = np.sqrt(np.mean((hc - exact) ** 2))
+    ef = np.sqrt(np.mean((hf - exact) ** 2))
+    assert 3.5 < ec / ef < 4.6, (ec, ef)
+    assert np.abs(hf - exact).max() < 1e-2 * np.abs(exact).max()
