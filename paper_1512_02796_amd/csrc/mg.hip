@@ -1706,7 +1706,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
 #pragma unroll
                     for (int u = 0; u < NO; ++u) {
                         if (tid + u * kTT >= TX * TY * B) continue;
-                        bstore<double>(bx, oo[u], bload<double>(bx, oo[u]) + alpha * bload<double>(bp, oo[u]));
+                        bstore_nt(bx, oo[u], bload_nt(bx, oo[u]) + alpha * bload_nt(bp, oo[u]));
                     }
                 }
             }

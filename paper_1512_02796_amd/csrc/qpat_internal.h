@@ -37,6 +37,14 @@ __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t b, uint32_t off) {
     else
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(b, off, 0, 0));
 }
+// the same with the non-temporal hint (cache policy NT): data touched once per pass
+__device__ __forceinline__ double bload_nt(__amdgpu_buffer_rsrc_t b, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b, off, 0, 2));
+}
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t b, uint32_t off, double v) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b, off, 0, 2);
+}
 template <typename T>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t b, uint32_t off, T v) {
     if constexpr (sizeof(T) == 4)
