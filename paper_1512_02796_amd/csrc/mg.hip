@@ -1678,14 +1678,14 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                     if constexpr (MODE == kTDirSpmv) {
                         o = sum;
                         a0 += in ? xc * sum : 0.0;
-                        bstore<double>(bo2, oo[u], xc);
+                        bstore_nt(bo2, oo[u], xc);   // p: next read by the update pass
                     } else if constexpr (MODE == kTApply) {
                         o = g.scale * sum;
                     } else if constexpr (UPD) {
                         const double rnew = xc;   // the staged r' of the node
                         o = rnew - sum;
                         a1 += in ? rnew * rnew : 0.0;
-                        bstore<double>(bo2, oo[u], rnew);
+                        bstore_nt(bo2, oo[u], rnew);
                     } else if constexpr (MODE == kTSmoothDots) {
                         o = xc + w * dc[u] * (bc[u] - sum);
                         a0 += in ? bc[u] * o : 0.0;
@@ -1696,9 +1696,9 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                         if constexpr (MODE == kTTrue) a1 += in ? o * o : 0.0;
                     }
                     if constexpr (RES32)
-                        bstore<float>(bo, oo[u] == kOut ? kOut : oo[u] / 2, static_cast<float>(o));
+                        bstore<float>(bo, oo[u] == kOut ? kOut : oo[u] / 2, static_cast<float>(o));   // read next
                     else
-                        bstore<double>(bo, oo[u], o);
+                        bstore_nt(bo, oo[u], o);
                 }
                 if constexpr (UPD) {   // x += alpha p on this plane's nodes, after the stencil work
                     __builtin_amdgcn_sched_barrier(0);
@@ -2277,7 +2277,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
                 a0 += in ? bcu * o : 0.0;
                 a1 += in ? o : 0.0;
                 a2 += in ? bcu : 0.0;
-                bstore<double>(bo, act ? oo[u] : kOut, o);
+                bstore_nt(bo, act ? oo[u] : kOut, o);
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (z + 1 < ze) {   // plane z + 2's 1/a_ii (slot sl) and, odd, coarse plane (z + 3) / 2
