@@ -1924,15 +1924,16 @@ __global__ __launch_bounds__(kMgT) void k_mg_fullrows27(LvArgs L, double* __rest
 // lane J of each 16-lane row, to the whole row
 template <int J>
 __device__ __forceinline__ double row_bcast(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + J, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + J, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
+    // one 64-bit DPP move (row_newbcast takes 64-bit operands); every lane is
+    // written (row broadcast, full masks), so the old value is never used
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + J, 0xF, 0xF, true);
 }
 
 // sum over the 13 offset pairs: entry 1 + j (upper) and 14 + j (lower) of
 // the row held as (ua: entries 0-15, ub: 16-31) times the LDS neighbours
 template <int J>
-__device__ __forceinline__ double pair27(double ua, double ub, const double* rb, int sz, int sp, int sl) {
+__device__ __forceinline__ double pair27(double s, double ua, double ub, const double* rb, int sz, int sp,
+                                         int sl) {
     constexpr int code = 14 + J;
     constexpr int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
     constexpr int d = (dy * kTHX + dx) * 16;
@@ -1943,13 +1944,13 @@ __device__ __forceinline__ double pair27(double ua, double ub, const double* rb,
         cl = row_bcast<14 + J>(ua);
     else
         cl = row_bcast<J - 2>(ub);
-    return cu * rb[up + d] + cl * rb[lo - d];
+    return fma(cl, rb[lo - d], fma(cu, rb[up + d], s));
 }
 template <int... J>
 __device__ __forceinline__ double apply27(double ua, double ub, const double* rb, int sz, int sp, int sl,
                                           std::integer_sequence<int, J...>) {
     double s = row_bcast<0>(ua) * rb[sz];
-    ((s += pair27<J>(ua, ub, rb, sz, sp, sl)), ...);
+    ((s = pair27<J>(s, ua, ub, rb, sz, sp, sl)), ...);
     return s;
 }
 
@@ -2114,16 +2115,16 @@ struct PSArgs {
 };
 
 template <int J>
-__device__ __forceinline__ double kuhn_pair(double ua, const double* rb, int sz, int sp, int sl) {
+__device__ __forceinline__ double kuhn_pair(double s, double ua, const double* rb, int sz, int sp, int sl) {
     constexpr int d = (kKy[J] * kTHX + kKx[J]) * 16;
     const int up = kKz[J] ? sp : sz, lo = kKz[J] ? sl : sz;
-    return row_bcast<1 + J>(ua) * rb[up + d] + row_bcast<8 + J>(ua) * rb[lo - d];
+    return fma(row_bcast<8 + J>(ua), rb[lo - d], fma(row_bcast<1 + J>(ua), rb[up + d], s));
 }
 template <int... J>
 __device__ __forceinline__ double apply_kuhn16(double ua, const double* rb, int sz, int sp, int sl,
                                                std::integer_sequence<int, J...>) {
     double s = row_bcast<0>(ua) * rb[sz];
-    ((s += kuhn_pair<J>(ua, rb, sz, sp, sl)), ...);
+    ((s = kuhn_pair<J>(s, ua, rb, sz, sp, sl)), ...);
     return s;
 }
 
@@ -2252,7 +2253,8 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
                     const double* q = cp + o;
                     return wy0 * (wx0 * q[0] + wx1 * q[dx]) + wy1 * (wx0 * q[dy] + wx1 * q[dy + dx]);
                 };
-                ring[sl * RS + tid + u * kTT] += wz0 * bil(c0) + wz1 * bil(c1);
+                double& rv = ring[sl * RS + tid + u * kTT];
+                rv = fma(wz1, bil(c1), fma(wz0, bil(c0), rv));
             }
         };
         auto step = [&](int z, auto SZ0, auto SP0, auto SL0) {
