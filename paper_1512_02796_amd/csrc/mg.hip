@@ -1669,8 +1669,8 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                         for (int j = 0; j < 7; ++j) {
                             const int d = kKy[j] * kTHX + kKx[j];
                             const int up = kKz[j] ? sp : sz, lo = kKz[j] ? sl : sz;
-                            sum += ub[sz * US + cc * M1 + j + 1] * rb[up * RS + (cc + d) * B] +
-                                   ub[lo * US + (cc - d) * M1 + j + 1] * rb[lo * RS + (cc - d) * B];
+                            sum = fma(ub[sz * US + cc * M1 + j + 1], rb[up * RS + (cc + d) * B], sum);
+                            sum = fma(ub[lo * US + (cc - d) * M1 + j + 1], rb[lo * RS + (cc - d) * B], sum);
                         }
                     }
                     const bool in = oo[u] != kOut;
