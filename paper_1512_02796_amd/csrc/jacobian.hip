@@ -26,6 +26,13 @@ struct Geo4 {
     double g[4][3];
 };
 
+// per-tetrahedron geometry, or its class in a small table (qpat_ctx::geo_cls)
+struct GeoRef {
+    const double* geo;
+    const uint8_t* cls;   // null: no classes
+    const double* tab;
+};
+
 __device__ __forceinline__ void load_geo4(const double* __restrict__ geo, int32_t e, Geo4& G) {
     const double* p = geo + (int64_t)kTetGeo * e;
     G.vol = p[0];
@@ -36,6 +43,13 @@ __device__ __forceinline__ void load_geo4(const double* __restrict__ geo, int32_
         G.g[3][d] = p[7 + d];
         G.g[0][d] = -(G.g[1][d] + G.g[2][d] + G.g[3][d]);
     }
+}
+
+__device__ __forceinline__ void load_geo4(const GeoRef& r, int32_t e, Geo4& G) {
+    if (r.cls)
+        load_geo4(r.tab, static_cast<int32_t>(r.cls[e]), G);
+    else
+        load_geo4(r.geo, e, G);
 }
 
 // right-hand sides handled by one thread of the G kernels: the per-tetrahedron
@@ -123,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_dk_coef(int64_t N, const double* _
 // M1: stored entries per row (8 on the Kuhn lattice, else kMaxUpper + 1)
 template <int M1>
 __global__ __launch_bounds__(kThreads) void k_dk_lattice(int64_t N, Lattice lat, const int32_t* __restrict__ tets,
-                                                         const double* __restrict__ geo,
+                                                         GeoRef geo,
                                                          const int32_t* __restrict__ n2t_ptr,
                                                          const int32_t* __restrict__ n2t,
                                                          const double* __restrict__ uu, double* __restrict__ U) {
@@ -221,7 +235,7 @@ constexpr int kTetRhs = B >= 4 ? 4 : B;
 
 template <int B>
 __global__ __launch_bounds__(kThreads) void k_gadj_tet(int64_t E, const int32_t* __restrict__ tets,
-                                                       const double* __restrict__ geo, const double* __restrict__ phi,
+                                                       GeoRef geo, const double* __restrict__ phi,
                                                        int n_pad, int col0, const double* __restrict__ z, int first,
                                                        double* __restrict__ tq, double* __restrict__ tr) {
     constexpr int KT = kTetRhs<B>, G = B / KT;
@@ -414,6 +428,8 @@ int block_size(const qpat_ctx* c) {
 
 // K x = b for one block of B right-hand sides: multigrid-preconditioned PCG
 // where its hierarchy is built, Jacobi-PCG otherwise
+inline GeoRef geo_ref(const qpat_ctx* c) { return GeoRef{c->geo, c->geo_cls, c->geo_tab}; }
+
 static qpat_status k_solve(qpat_ctx* c, int B, SolveStats* st, bool has_x0 = false) {
     if (mg_ready(c, Op::K)) return mg_solve(c, Op::K, B, st, has_x0);
     return pcg_solve(c, Op::K, B, st, has_x0);
@@ -461,10 +477,10 @@ qpat_status jvp_core(qpat_ctx* c, const double* s, int mode, double* out, SolveS
         // a multiple of 8 blocks (the XCD strips), several per compute unit
         const dim3 gd((std::min<int64_t>((c->N * kSplit + kThreads - 1) / kThreads, 4096) + 7) & ~7);
         if (c->lat.m == 7)
-            hipLaunchKernelGGL(k_dk_lattice<8>, gd, blk, 0, c->stream, c->N, c->lat, c->tets, c->geo, c->n2t_ptr,
+            hipLaunchKernelGGL(k_dk_lattice<8>, gd, blk, 0, c->stream, c->N, c->lat, c->tets, geo_ref(c), c->n2t_ptr,
                                c->n2t, c->dKc, c->dK);
         else
-            hipLaunchKernelGGL(k_dk_lattice<kMaxUpper + 1>, gd, blk, 0, c->stream, c->N, c->lat, c->tets, c->geo,
+            hipLaunchKernelGGL(k_dk_lattice<kMaxUpper + 1>, gd, blk, 0, c->stream, c->N, c->lat, c->tets, geo_ref(c),
                                c->n2t_ptr, c->n2t, c->dKc, c->dK);
     }
     for (int col0 = 0; col0 < c->n_pad; col0 += B) {
@@ -502,7 +518,7 @@ qpat_status vjp_core(qpat_ctx* c, const double* t, int mode, double* out, SolveS
         QPAT_TRY(k_solve(c, B, st));
         QPAT_DISPATCH_B(B, hipLaunchKernelGGL(k_gadj_tet<BB>,
                                               dim3(grid_for(c->E * (BB / kTetRhs<BB>), kThreads, 1 << 30)), blk, 0,
-                                              c->stream, c->E, c->tets, c->geo, c->phi, c->n_pad, col0, c->x64,
+                                              c->stream, c->E, c->tets, geo_ref(c), c->phi, c->n_pad, col0, c->x64,
                                               col0 == 0 ? 1 : 0, c->tq, c->tr));
     }
     hipLaunchKernelGGL(k_gadj_gather, dim3(grid_for(c->N * kSplit, kThreads, 1 << 30)), blk, 0, c->stream, c->N, c->n2t_ptr,

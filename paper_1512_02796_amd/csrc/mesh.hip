@@ -4,6 +4,7 @@
 // P1 basis on a tetrahedral partition (Sec. 3, eq. (3.2)); every FEM matrix
 // of the path (K, the load operators G(1), G(2), the prior M) lives on the
 // node-node pattern of that partition.
+#include <cstring>
 #include <hipcub/hipcub.hpp>
 
 #include "qpat_internal.h"
@@ -60,6 +61,30 @@ __global__ void k_geometry(const double* __restrict__ X, const int32_t* __restri
         g[4] = cax * inv; g[5] = cay * inv; g[6] = caz * inv;
         g[7] = abx * inv; g[8] = aby * inv; g[9] = abz * inv;
         g[10] = 0.0; g[11] = 0.0;
+    }
+}
+
+// geometry class of each tetrahedron: the first of the K candidates whose
+// kTetGeo doubles equal its own bit for bit; a tetrahedron matching none sets
+// *flag (then the classes are not used)
+__global__ void k_geo_classify(const double* __restrict__ geo, int64_t E, const double* __restrict__ cand, int K,
+                               uint8_t* __restrict__ cls, int32_t* flag) {
+    for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < E; e += (int64_t)gridDim.x * kThreads) {
+        const unsigned long long* g = reinterpret_cast<const unsigned long long*>(geo + kTetGeo * e);
+        int found = -1;
+        for (int k = 0; k < K && found < 0; ++k) {
+            const unsigned long long* c = reinterpret_cast<const unsigned long long*>(cand + kTetGeo * k);
+            bool same = true;
+#pragma unroll
+            for (int d = 0; d < kTetGeo; ++d) same = same && g[d] == c[d];
+            if (same) found = k;
+        }
+        if (found < 0) {
+            *flag = 1;
+            cls[e] = 0;
+        } else {
+            cls[e] = static_cast<uint8_t>(found);
+        }
     }
 }
 
@@ -235,6 +260,52 @@ qpat_status read_flag(qpat_ctx* c, int32_t* out) {
     return QPAT_OK;
 }
 
+// Geometry classes (see qpat_ctx::geo_cls): candidates are the distinct
+// geometries among the first kGeoProbe tetrahedra; every tetrahedron must
+// match one of at most kGeoMaxCls of them bit for bit, else no classes.
+constexpr int kGeoProbe = 64, kGeoMaxCls = 16;
+qpat_status classify_geometry(qpat_ctx* c) {
+    const int64_t E = c->E;
+    const int probe = static_cast<int>(std::min<int64_t>(E, kGeoProbe));
+    std::vector<double> first(static_cast<size_t>(probe) * kTetGeo);
+    QPAT_HIP(c, hipMemcpyAsync(first.data(), c->geo, first.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    std::vector<double> cand;
+    for (int e = 0; e < probe; ++e) {
+        const double* g = first.data() + static_cast<size_t>(e) * kTetGeo;
+        bool seen = false;
+        for (size_t k = 0; k < cand.size() / kTetGeo && !seen; ++k)
+            seen = std::memcmp(cand.data() + k * kTetGeo, g, kTetGeo * sizeof(double)) == 0;
+        if (!seen) cand.insert(cand.end(), g, g + kTetGeo);
+    }
+    const int K = static_cast<int>(cand.size() / kTetGeo);
+    if (K == 0 || K > kGeoMaxCls) return QPAT_OK;
+    double* tab = nullptr;
+    uint8_t* cls = nullptr;
+    int32_t* miss = nullptr;   // its own flag: the mesh checks share dev_flag
+    QPAT_TRY(dalloc(c, &tab, cand.size()));
+    QPAT_TRY(dalloc(c, &cls, E));
+    QPAT_TRY(dalloc(c, &miss, 1));
+    QPAT_HIP(c, hipMemcpyAsync(tab, cand.data(), cand.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    QPAT_HIP(c, hipMemsetAsync(miss, 0, sizeof(int32_t), c->stream));
+    hipLaunchKernelGGL(k_geo_classify, dim3(grid_for(E, kThreads, 65536)), dim3(kThreads), 0, c->stream, c->geo, E,
+                       tab, K, cls, miss);
+    QPAT_HIP(c, hipGetLastError());
+    int32_t flag = 0;
+    QPAT_HIP(c, hipMemcpyAsync(&flag, miss, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    QPAT_TRY(dfree(c, miss));
+    if (flag) {
+        QPAT_TRY(dfree(c, cls));
+        QPAT_TRY(dfree(c, tab));
+        return QPAT_OK;
+    }
+    c->geo_cls = cls;
+    c->geo_tab = tab;
+    c->geo_ncls = K;
+    return QPAT_OK;
+}
+
 }  // namespace
 
 qpat_status mesh_build(qpat_ctx* c, const double* coords, const int32_t* tets_in, const int32_t* bfaces_in) {
@@ -270,6 +341,7 @@ qpat_status mesh_build(qpat_ctx* c, const double* coords, const int32_t* tets_in
     if (flag & kFlagDegenerate) return fail(c, QPAT_ERR_MESH, "degenerate (zero-volume) tetrahedron");
     if (flag & kFlagFaceDegenerate) return fail(c, QPAT_ERR_MESH, "degenerate boundary triangle");
 
+    QPAT_TRY(classify_geometry(c));
     QPAT_TRY(build_adjacency(c, c->tets, 4 * E, &c->n2t_ptr, &c->n2t));
     QPAT_TRY(build_adjacency(c, c->bfaces, 3 * F, &c->n2f_ptr, &c->n2f));
 

@@ -151,6 +151,13 @@ struct qpat_ctx {
     int64_t N = 0, E = 0, Fb = 0;
     int32_t* tets = nullptr;       // [E][4]
     double* geo = nullptr;         // [E][kTetGeo]
+    // geometry classes: when every tetrahedron's geometry equals, bit for bit,
+    // one of a few candidates (a uniform lattice with an exactly representable
+    // spacing has 6), geo_cls[e] names it and geo_tab holds the candidates
+    // ([geo_ncls][kTetGeo]); otherwise geo_cls is null
+    uint8_t* geo_cls = nullptr;    // [E]
+    double* geo_tab = nullptr;
+    int32_t geo_ncls = 0;
     int32_t* bfaces = nullptr;     // [Fb][3]
     double* barea = nullptr;       // [Fb]
     int32_t* n2t_ptr = nullptr;    // [N+1]
