@@ -319,6 +319,15 @@ qpat_status qpat_forward_x0(qpat_ctx* ctx, const double* kappa, const double* mu
                             double* phi_out, double* h_out, qpat_info* info);
 
 /* Steps taken since qpat_lsqr_init. */
+/* Number of geometry classes the Jacobian's element kernels use: at mesh
+ * set-up every tetrahedron's geometry (|T| and the barycentric gradients)
+ * is compared bit for bit with the distinct geometries of the first 64
+ * tetrahedra; when each matches one of at most 16, the kernels read a class
+ * id instead of the per-tetrahedron row (results unchanged). 0: per-
+ * tetrahedron rows. A uniform Kuhn lattice whose spacing is exact in binary
+ * has 6. Host-only; -1 for a null context. */
+int32_t qpat_geometry_classes(const qpat_ctx* ctx);
+
 int32_t qpat_lsqr_steps(const qpat_ctx* ctx);
 
 /* |phibar| after the last qpat_lsqr_init (= ||yt||) or qpat_lsqr_step, from

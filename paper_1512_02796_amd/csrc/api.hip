@@ -719,6 +719,8 @@ qpat_status qpat_operator_layout(const qpat_ctx* c, int64_t out[6]) {
     return QPAT_OK;
 }
 
+int32_t qpat_geometry_classes(const qpat_ctx* c) { return c ? c->geo_ncls : -1; }
+
 int32_t qpat_lsqr_steps(const qpat_ctx* c) { return c && c->ls_host ? c->ls_host->steps : 0; }
 
 double qpat_lsqr_residual(const qpat_ctx* c) {

@@ -88,6 +88,7 @@ SIGNATURES = {
     "qpat_lsqr_init": (_S, [_P, _P, _P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_lsqr_step": (_S, [_P, ctypes.POINTER(_D), ctypes.POINTER(Info)]),
     "qpat_lsqr_steps": (_I32, [_P]),
+    "qpat_geometry_classes": (_I32, [_P]),
     "qpat_lsqr_residual": (_D, [_P]),
     "qpat_profile": (_S, [_P, _I32]),
     "qpat_profile_read": (_S, [_P, ctypes.POINTER(KStat)]),
@@ -374,6 +375,9 @@ class Context:
 
     def lsqr_steps(self):
         return _lib.qpat_lsqr_steps(self._h)
+
+    def geometry_classes(self):
+        return int(_lib.qpat_geometry_classes(self._h))
 
     def lsqr_residual(self):
         return _lib.qpat_lsqr_residual(self._h)

@@ -242,3 +242,22 @@ def test_graph_replays_match_eager():
         G.ctx.set_opts(use_graphs=0)
         c, _, _ = G.forward()
         assert np.array_equal(a, host(c))
+
+
+def test_geometry_classes_on_an_exact_lattice():
+    """8^3 voxels on 40 mm (spacing 5, exact): the 6 Kuhn tetrahedron shapes are the
+    classes, and the forward/J products through them match the oracle (the other
+    parity tests run meshes with inexact spacings through the per-tetrahedron rows)."""
+    G = GpuProblem("T8", opts())
+    assert G.ctx.geometry_classes() == 6
+    G.forward()
+    g, lin = oracle_of(G.P)
+    s, t = probe_vectors(G.P.cfg["id"], G.n_ill, G.N)
+    out = torch.empty(G.n_ill * G.N, dtype=torch.float64, device="cuda")
+    G.ctx.jvp(dev(s), out)
+    assert rel(host(out).reshape(G.n_ill, G.N), lin.jvp(s)) <= 1e-10
+    outT = torch.empty(2 * G.N, dtype=torch.float64, device="cuda")
+    G.ctx.vjp(dev(t), outT)
+    assert rel(host(outT), lin.vjp(t)) <= 1e-10
+    H = GpuProblem("T12", opts())
+    assert H.ctx.geometry_classes() in (0, 6)
