@@ -1098,10 +1098,12 @@ __global__ __launch_bounds__(kMgT) void k_reg_rsum(PcgMg a, double* __restrict__
             if (lane == 0) sm[wave * kRegMax + j] = t;
         }
         __syncthreads();
-        if (threadIdx.x < kRegMax) {
+        if (threadIdx.x < kRegMax) {   // the slots no block owns read 0 (fewer blocks than kMgBlocks)
             double t = 0.0;
             for (int w = 0; w < kMgT / 64; ++w) t += sm[w * kRegMax + threadIdx.x];
-            rparts[(sys * kRegMax + threadIdx.x) * kMgBlocks + blockIdx.x] = t;
+            double* p = rparts + (sys * kRegMax + threadIdx.x) * kMgBlocks;
+            p[blockIdx.x] = t;
+            for (int b = blockIdx.x + gridDim.x; b < kMgBlocks; b += gridDim.x) p[b] = 0.0;
         }
         __syncthreads();
     }
@@ -2820,7 +2822,8 @@ PcgMg pcg_args(qpat_ctx* c, Op op) {
 template <int B>
 void region_solve(const MgState& M, const PcgMg& a, hipStream_t st) {
     if (a.kreg <= 0) return;
-    hipLaunchKernelGGL(k_reg_rsum, sgrid<B>(a.L.N), dim3(kMgT), 0, st, a, M.rparts);
+    // each block reduces kRegMax sums: fewer, fuller blocks than the walk kernels
+    hipLaunchKernelGGL(k_reg_rsum, vgrid(a.L.N, kMgGrid), dim3(kMgT), 0, st, a, M.rparts);
     hipLaunchKernelGGL(k_reg_solve, dim3(1, a.nsys), dim3(kMgT), 0, st, a, M.rparts, M.einv, M.rsize, M.ry, M.rcorr);
 }
 
