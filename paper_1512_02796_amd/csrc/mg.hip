@@ -3373,7 +3373,12 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
         double g;
         std::memcpy(&g, &gm[i], sizeof g);
         if (!(g > 0.0) || !std::isfinite(g)) return fail(c, QPAT_ERR_ARG, "multigrid: non-positive diagonal in %s", what);
-        w[i] = (i % nl == 0 ? 8.0 / 5.0 : 19.0 / 10.0) / g;   // finest level, coarse levels
+        // finest level, coarse levels; M_delta's (strongly varying diffusivity)
+        // take larger weights, still below 2 / g so that the cycle stays SPD
+        if (op == Op::Prior)
+            w[i] = (i % nl == 0 ? 7.0 / 4.0 : 39.0 / 20.0) / g;
+        else
+            w[i] = (i % nl == 0 ? 8.0 / 5.0 : 19.0 / 10.0) / g;
     }
     QPAT_HIP(c, hipMemcpyAsync(M.w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     const int n = static_cast<int>(K.N), M1 = K.m + 1;
