@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--train-phantoms", type=int, default=125)
     ap.add_argument("--held-phantoms", type=int, default=13)
     ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--rhs-block", type=int, default=16,
+                    help="recon workload: right-hand sides per block solve (1 = plain, one at a time)")
     ap.add_argument("--no-init", action="store_true",
                     help="skip the background fit, step 0 and TV-prior measurements")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -455,6 +457,7 @@ def bench_recon(args):
     chi = hh + sig * np.abs(hh) * noise_draws(P.cfg["id"], K, N)
     W = 1.0 / (sig * np.abs(hh))
     outer, inner = P.cfg["outer"], P.cfg["inner"]
+    ctx.set_opts(max_rhs_block=args.rhs_block)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     beta, lg = reconstruct(ctx, d(chi), d(W), P.kappa0, P.mu0, outer=outer, inner=inner)
@@ -478,7 +481,8 @@ def bench_recon(args):
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"Algorithm 1, {args.grid}^3 Kuhn voxels (N={N}), {K} Gaussian illuminations, "
                                   f"seeded ellipsoid phantom, 2% noise, {outer} x {inner} PLSQR steps, FP64 "
-                                  "multigrid block PCG"},
+                                  f"multigrid PCG, {args.rhs_block} right-hand side(s) per block solve",
+                      "rhs_block": args.rhs_block},
            "reconstruction": out}
     print(json.dumps(res), flush=True)
 
