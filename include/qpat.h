@@ -197,7 +197,8 @@ qpat_status qpat_init_guess(qpat_ctx* ctx, const double* chi, double mu0, double
  * iterations, when an accepted step is at most tol in both logs, or when no
  * halving decreases the misfit.
  *   chi, w       : [n_ill][N] (device).
- *   kappa0, mu0  : host in/out: the starting pair in, the fitted pair out.
+ *   kappa0, mu0  : host in/out: the starting pair in, the fitted pair out
+ *                  (unchanged, bit for bit, when no step is accepted).
  *   iters        : host out (may be NULL): Gauss-Newton iterations taken.
  * On return the context's forward state (phi, h) is at the fitted pair, so
  * qpat_init_guess may follow directly. Errors: QPAT_ERR_ARG (null pointer,

@@ -626,8 +626,10 @@ qpat_status qpat_fit_background(qpat_ctx* c, const double* chi, const double* w,
     }
     if (!at_ab) QPAT_TRY(evaluate(a, b, &F));   // leave the forward state at the returned point
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
-    *kappa0 = std::exp(a);
-    *mu0 = std::exp(b);
+    if (it > 0) {   // with no accepted step the caller's pair is returned as given
+        *kappa0 = std::exp(a);
+        *mu0 = std::exp(b);
+    }
     if (iters) *iters = it;
     fill_info(info, st);
     return QPAT_OK;

@@ -191,3 +191,23 @@ def test_finer_mesh_data_matches_oracle():
     rbeta, rlog = oref(g, G.P.phi_src, ref, W, G.P.kappa0, G.P.mu0, outer=1, inner=6)
     assert np.allclose(log["lsqr"][0], rlog["lsqr"][0], rtol=1e-6)
     assert rel(host(beta), rbeta) <= 1e-4
+
+
+def test_fit_background_with_no_iterations_and_kappa_lsqr_state_check():
+    """maxit = 0 returns the starting pair and leaves the forward state there (its misfit
+    is the oracle's at that homogeneous pair); the kt-only LSQR needs a prior first."""
+    from paper_1512_02796_amd import qpat
+    from oracle.jacobian import Linearisation
+    G = GpuProblem("T4", qpat.default_opts(pcg_rtol=1e-12))
+    P = G.P
+    g, lin = oracle_of(P)
+    chi, W = data_of(P, lin)
+    k, m, it, _ = G.ctx.fit_background(dev(chi), dev(W), 1.2 * P.kappa0, 0.9 * P.mu0, maxit=0)
+    assert (k, m, it) == (1.2 * P.kappa0, 0.9 * P.mu0, 0)
+    h0 = Linearisation(g, np.full(g.N, k), np.full(g.N, m), P.phi_src).h
+    ref = np.linalg.norm(W * (chi - h0))
+    assert abs(G.ctx.misfit(dev(chi), dev(W)) / ref - 1) <= 1e-9
+    out = torch.zeros(2 * G.N, dtype=torch.float64, device="cuda")
+    with pytest.raises(qpat.QpatError) as e:
+        G.ctx.lsqr_init_kappa(dev(chi), dev(W), None, out)
+    assert "ERR_STATE" in str(e.value)
