@@ -16,7 +16,10 @@ Optional zeroth step (Sec. 5, step0_inner > 0): PLSQR for kt alone with the
 Each outer step l:
   1. h = h(beta_l), yt = W (chi - h + J beta_l)         (W = Gamma^{-1/2}, diagonal)
   2. M_delta from kt_l, mt_l
-  3. PLSQR on A = W J from 0 -> beta_{l+1}
+  3. PLSQR on A = W J from 0 -> beta_{l+1}; a fixed count, the window rule
+     r_m <= tau (eq. (4.11)) and/or the discrepancy principle of the remark
+     after Algorithm 1 (stop once the linearised residual is below
+     fudge * sqrt(n_ill N), the whitened noise level; option `discrepancy`)
   4. nonlinear residual ||W (chi - h(beta_{l+1}))|| compared with ||W (chi - h)||;
      with stop_on_reject the previous iterate is returned when it did not
      decrease, otherwise the comparison is only recorded.
@@ -26,7 +29,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .jacobian import Linearisation, params
-from .prior import Prior, M_of
+from .prior import Prior, M_of, DeflatedDirect
 from .plsqr import plsqr
 from .solve import make_solver
 
@@ -77,7 +80,7 @@ def fit_background(geo, phi_src, chi, W, kappa_start, mu_start, maxit=30, tol=1e
 
 
 def step0(geo, phi_src, chi, W, kappa0, mu0, beta_init, inner, T=5e-3, delta=1e-6,
-          solver="direct", rtol=1e-10, m0=None, tau=None, prior="pm", q=1.0):
+          solver="direct", rtol=1e-10, m0=None, tau=None, prior="pm", q=1.0, prior_solver=None):
     """Zeroth step of Sec. 5: PLSQR on A = W J_kt (the kt columns of J at
     beta_init) with prior M(kt_init) + delta I (N x N), right-hand side
     W (chi - h + J_kt kt_init), from 0. Returns (beta with kt replaced, history)."""
@@ -98,7 +101,9 @@ def step0(geo, phi_src, chi, W, kappa0, mu0, beta_init, inner, T=5e-3, delta=1e-
     def At(u):
         return lin.vjp(W * u.reshape(n_ill, N))[:N]
 
-    it = plsqr(A, At, make_solver(Mk, solver, rtol), yt, inner, m0, tau)
+    ps = prior_solver or solver
+    Minv = DeflatedDirect(Mk, N, delta) if ps == "deflated" else make_solver(Mk, ps, rtol)
+    it = plsqr(A, At, Minv, yt, inner, m0, tau)
     return np.concatenate([it.x, np.asarray(beta_init[N:])]), list(it.history)
 
 
@@ -113,11 +118,17 @@ def initial_guess(geo, phi_src, chi, kappa0, mu0, solver="direct", rtol=1e-10):
 def reconstruct(geo, phi_src, chi, W, kappa0, mu0, outer, inner, T=5e-3,
                 b_over_a=1.0, delta=1e-6, solver="direct", rtol=1e-10,
                 beta0=None, stop_on_reject=False, m0=None, tau=None, prior="pm", q=1.0,
-                fit=False, step0_inner=0):
+                fit=False, step0_inner=0, discrepancy=None, prior_solver=None):
+    """discrepancy: None, or the factor of the noise level sqrt(n_ill N) at
+    which step 3 stops (1.0: the plain discrepancy principle); log["discrepancy_fired"]
+    records per outer step whether it ended the LSQR run. prior_solver: how
+    M_delta^{-1} is applied ("direct", "pcg" or "deflated"; default: solver)."""
+    ps = prior_solver or solver
     chi = np.asarray(chi)
     W = np.asarray(W)
     N = geo.N
-    log = dict(res_nl=[], lsqr=[], rejected=[])
+    log = dict(res_nl=[], lsqr=[], rejected=[], discrepancy_fired=[])
+    level = None if discrepancy is None else float(discrepancy) * np.sqrt(chi.size)
     if fit:
         kappa0, mu0, log["fit_iters"] = fit_background(geo, phi_src, chi, W, kappa0, mu0, solver=solver, rtol=rtol)
     log["kappa0"], log["mu0"] = kappa0, mu0
@@ -125,7 +136,7 @@ def reconstruct(geo, phi_src, chi, W, kappa0, mu0, outer, inner, T=5e-3,
         else np.array(beta0, dtype=np.float64)
     if step0_inner > 0:
         beta, log["step0"] = step0(geo, phi_src, chi, W, kappa0, mu0, beta, step0_inner, T, delta, solver, rtol,
-                                   m0, tau, prior, q)
+                                   m0, tau, prior, q, prior_solver=ps)
     lin = None
     for l in range(outer):
         kappa, mu = params(kappa0, mu0, beta)
@@ -133,7 +144,7 @@ def reconstruct(geo, phi_src, chi, W, kappa0, mu0, outer, inner, T=5e-3,
         res = np.linalg.norm(W * (chi - lin.h))
         log["res_nl"].append(res)
         yt = (W * (chi - lin.h + lin.jvp(beta))).ravel()
-        Md = Prior(geo, beta[:N], beta[N:], T, b_over_a, delta, solver, rtol, kind=prior, q=q)
+        Md = Prior(geo, beta[:N], beta[N:], T, b_over_a, delta, ps, rtol, kind=prior, q=q)
         n_ill = lin.n_ill
 
         def A(v, lin=lin):
@@ -142,8 +153,9 @@ def reconstruct(geo, phi_src, chi, W, kappa0, mu0, outer, inner, T=5e-3,
         def At(u, lin=lin):
             return lin.vjp(W * u.reshape(n_ill, N))
 
-        it = plsqr(A, At, Md.solve, yt, inner, m0, tau)
+        it = plsqr(A, At, Md.solve, yt, inner, m0, tau, noise_level=level)
         log["lsqr"].append(list(it.history))
+        log["discrepancy_fired"].append(level is not None and it.history[-1] < level)
         beta_new = it.x
         kappa_n, mu_n = params(kappa0, mu0, beta_new)
         lin_new = Linearisation(geo, kappa_n, mu_n, phi_src, solver, rtol)

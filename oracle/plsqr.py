@@ -144,11 +144,23 @@ def window_ratio(history, m, m0):
     return 1.0 - history[m] / den if den > 0 else 0.0
 
 
-def plsqr(A, At, Minv, yt, iters, m0=None, tau=None, reorth=True):
-    """Run a fixed number of steps, or stop early once r_m <= tau when m0, tau given."""
+def discrepancy_reached(history, m, level):
+    """Morozov's discrepancy principle (Sec. 4, the remark after Algorithm 1):
+    the residual of the linearised model after m steps has fallen below the
+    whitened noise level, res_m < level (level = sqrt(K N) for K illuminations
+    of N nodes, times an optional factor)."""
+    return history[m] < level
+
+
+def plsqr(A, At, Minv, yt, iters, m0=None, tau=None, reorth=True, noise_level=None):
+    """Run a fixed number of steps, or stop early once r_m <= tau when m0, tau
+    given, or once the residual is below noise_level when that is given (the
+    discrepancy principle); the first rule that fires ends the run."""
     it = PLSQR(A, At, Minv, yt, reorth=reorth)
     for m in range(1, iters + 1):
         it.step()
+        if noise_level is not None and discrepancy_reached(it.history, m, noise_level):
+            break
         if m0 is not None and tau is not None:
             rm = window_ratio(it.history, m, m0)
             if rm is not None and rm <= tau:

@@ -18,6 +18,7 @@ Test infrastructure only (see the package docstring).
 """
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from .fem import _assemble
 from .solve import make_solver
@@ -76,11 +77,51 @@ def M_delta(geo, kt, mt, T=5e-3, b_over_a=1.0, delta=1e-6, kind="pm", q=1.0):
     return (sp.block_diag([Mk, b_over_a * Mm]) + delta * sp.identity(2 * geo.N)).tocsr()
 
 
+class DeflatedDirect:
+    """r = M_delta^{-1} p with the delta-eigenvector of each block taken exactly.
+
+    Each diagonal block D = c M(u) + delta I of M_delta (eq. (4.8); c = 1 for
+    kt, b/a for mt, eq. (4.5)) has c M(u) 1 = 0: M(u) is the stiffness matrix
+    of -div(c_u grad) with a natural boundary condition, whose rows sum to
+    zero. Hence D 1 = delta 1, and as D is symmetric it maps the mean-free
+    vectors onto themselves. With m = mean(p):
+
+        r = (m / delta) 1 + y,   D y = p - m 1,   mean(y) = 0.
+
+    y comes from a sparse LU factorisation of D; the LU's rounding error along
+    1 is amplified by 1/delta, so y's mean -- zero in exact arithmetic -- is
+    removed. What remains is the error of D on the mean-free vectors, whose
+    smallest eigenvalue is far above delta."""
+
+    def __init__(self, Md, N, delta):
+        Md = Md.tocsr()
+        self.N, self.delta = N, float(delta)
+        self.nb = Md.shape[0] // N          # diagonal blocks of N (2 for M_delta, 1 for one block)
+        self.lus = [spla.splu(Md[j * N:(j + 1) * N, j * N:(j + 1) * N].tocsc()) for j in range(self.nb)]
+
+    def __call__(self, p):
+        p = np.asarray(p, dtype=np.float64)
+        N = self.N
+        out = np.empty(self.nb * N)
+        for j in range(self.nb):
+            pj = p[j * N:(j + 1) * N]
+            m = pj.mean()
+            y = self.lus[j].solve(pj - m)
+            out[j * N:(j + 1) * N] = (y - y.mean()) + m / self.delta
+        return out
+
+
 class Prior:
+    """M_delta at (kt, mt) and its inverse. solver: "direct" (sparse LU of
+    the whole matrix), "pcg" (Jacobi-PCG) or "deflated" (DeflatedDirect)."""
+
     def __init__(self, geo, kt, mt, T=5e-3, b_over_a=1.0, delta=1e-6,
                  solver="direct", rtol=1e-10, kind="pm", q=1.0):
         self.Md = M_delta(geo, kt, mt, T, b_over_a, delta, kind, q)
-        self._solve = make_solver(self.Md, solver, rtol)
+        if solver == "deflated":
+            self._solve = DeflatedDirect(self.Md, geo.N, delta)
+        else:
+            self._solve = make_solver(self.Md, solver, rtol)
 
     def apply(self, x):
         return self.Md @ x

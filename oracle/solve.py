@@ -16,10 +16,17 @@ import scipy.sparse.linalg as spla
 
 
 class Direct:
-    """Factor once, solve many right-hand sides."""
+    """Factor once, solve many right-hand sides. symmetric=True orders the
+    columns for the symmetric pattern (minimum degree on K + K^T) and pivots on
+    the diagonal -- the same factorisation of an SPD matrix, with far less
+    fill on 3D meshes than the default column ordering."""
 
-    def __init__(self, K):
-        self.lu = spla.splu(K.tocsc())
+    def __init__(self, K, symmetric=False):
+        if symmetric:
+            self.lu = spla.splu(K.tocsc(), permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
+                                options=dict(SymmetricMode=True))
+        else:
+            self.lu = spla.splu(K.tocsc())
 
     def __call__(self, b):
         b = np.asarray(b, dtype=np.float64)
@@ -85,6 +92,8 @@ class Iterative:
 def make_solver(K, method="direct", rtol=1e-10):
     if method == "direct":
         return Direct(K)
+    if method == "direct_sym":
+        return Direct(K, symmetric=True)
     if method == "pcg":
         return Iterative(K, rtol=rtol)
     raise ValueError(method)

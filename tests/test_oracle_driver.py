@@ -137,3 +137,43 @@ def test_step0_is_lsqr_on_the_kappa_block():
         assert np.linalg.norm(out[:N] - ref) <= 1e-9 * np.linalg.norm(ref), m
         assert np.array_equal(out[N:], beta[N:])
         assert abs(np.linalg.norm(A @ out[:N] - yt) - hist[-1]) <= 1e-9 * hist[-1]
+
+
+def test_initial_guess_averages_exponentials_over_illuminations():
+    """Sec. 4, paragraph after Algorithm 1: with several illuminations exp(mt_init)
+    is the average over k of exp(mt_init^(k)) = chi_k / (mu0 phi0_k). Data
+    chi_k = c_k mu0 phi0_k with distinct c_k give mt_init = log(mean_k c_k) at
+    every node; a geometric mean (a mean of the logs) would give
+    log(prod c_k)/4 = log(sqrt 2), far from log(1.875), and kt_init = 0."""
+    P = make_problem("T4", n_ill=4)
+    g = fem.geometry(P.mesh.coords, P.mesh.tets, P.mesh.bfaces)
+    lin0 = Linearisation(g, np.full(g.N, P.kappa0), np.full(g.N, P.mu0), P.phi_src)
+    c = np.array([0.5, 1.0, 2.0, 4.0])
+    chi = c[:, None] * P.mu0 * lin0.phi
+    beta = initial_guess(g, P.phi_src, chi, P.kappa0, P.mu0)
+    assert np.all(beta[:g.N] == 0.0)
+    assert np.abs(beta[g.N:] - np.log(1.875)).max() <= 1e-14
+    assert abs(np.log(1.875) - np.log(np.sqrt(2.0))) > 0.2
+
+
+def test_discrepancy_principle_stops_below_the_noise_level():
+    """Remark after Algorithm 1: stop PLSQR at the first step whose linearised
+    residual is below sqrt(K N), the whitened noise level. On the 16^3 workload
+    (data simulated on the reconstruction mesh, i.e. with the inverse crime) it
+    fires in the third outer step; every history is a prefix of the fixed-count
+    run's, ending at the first value under the level."""
+    P = make_problem("C1")
+    g = fem.geometry(P.mesh.coords, P.mesh.tets, P.mesh.bfaces)
+    chi, W, _ = simulate(P, g)
+    level = np.sqrt(chi.size)
+    _, full = reconstruct(g, P.phi_src, chi, W, P.kappa0, P.mu0, outer=3, inner=30)
+    _, dp = reconstruct(g, P.phi_src, chi, W, P.kappa0, P.mu0, outer=3, inner=30, discrepancy=1.0)
+    assert dp["discrepancy_fired"] == [False, False, True]
+    for h_full, h_dp in zip(full["lsqr"], dp["lsqr"]):
+        m = len(h_dp) - 1
+        np.testing.assert_allclose(h_dp, h_full[:m + 1], rtol=1e-12)
+        below = [i for i in range(1, len(h_full)) if h_full[i] < level]
+        if below:
+            assert m == below[0] and h_dp[-1] < level <= h_dp[-2]
+        else:
+            assert m == 30

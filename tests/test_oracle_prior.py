@@ -145,3 +145,91 @@ def test_smoothed_tv_limits():
     tt = np.linspace(0, 0.1, 101)
     for q in (0.5, 1.0, 1.5, 2.0):
         assert np.all(np.diff(prior.r_of(tt, T, "tvq", q)) > 0)
+
+
+def _exact_solve(A, b, delta):
+    """(A0 + delta I) x = b in exact rational arithmetic, where A0 has the
+    off-diagonal entries of A (exact binary rationals) and the diagonal that
+    makes every row sum to zero exactly -- the kernel property M(u) 1 = 0 that
+    the floating-point assembly holds only to rounding. Gaussian elimination
+    over Fractions, rounded once at the end."""
+    from fractions import Fraction
+    n = A.shape[0]
+    M = [[Fraction(float(A[i, j])) if i != j else Fraction(0) for j in range(n)] for i in range(n)]
+    for i in range(n):
+        M[i][i] = -sum(M[i]) + Fraction(delta)
+        M[i].append(Fraction(float(b[i])))
+    for k in range(n):
+        piv = next(i for i in range(k, n) if M[i][k] != 0)
+        M[k], M[piv] = M[piv], M[k]
+        for i in range(k + 1, n):
+            f = M[i][k] / M[k][k]
+            if f:
+                row_k = M[k]
+                M[i] = [a - f * c for a, c in zip(M[i], row_k)]
+    x = [Fraction(0)] * n
+    for i in range(n - 1, -1, -1):
+        s = M[i][n] - sum(M[i][j] * x[j] for j in range(i + 1, n))
+        x[i] = s / M[i][i]
+    return np.array([float(v) for v in x])
+
+
+def _ideal_residual(Md, N, x, p, delta):
+    """M_delta x - p with each block's rows made to sum to zero exactly: the
+    constant part of x (mean/delta, of size ~1/delta) is multiplied by zero
+    instead of by the assembly's rounding."""
+    out = np.empty(2 * N)
+    for j in range(2):
+        B = Md[j * N:(j + 1) * N, j * N:(j + 1) * N]
+        xj = x[j * N:(j + 1) * N]
+        xc = xj - xj.mean()
+        rowsum = np.asarray(B.sum(axis=1)).ravel() - delta
+        out[j * N:(j + 1) * N] = B @ xc - rowsum * xc + delta * xj.mean() - p[j * N:(j + 1) * N]
+    return out
+
+
+def test_deflated_solve_matches_exact_rational_solve():
+    """M_delta^{-1} with the delta-eigenvector taken exactly (mean(p)/delta per
+    block, LU on the mean-free rest) equals the exact rational solution of the
+    same matrix with M(u) 1 = 0 imposed exactly, to 1e-13 element by element, on
+    a 2^3 mesh with jumps of kt and mt that take c_T down to ~1e-2 and
+    b/a != 1 (so a swapped block scale or a dropped mean term fails)."""
+    m, g = geo(2)
+    rng = np.random.default_rng(5)
+    kt = np.where(rng.random(g.N) < 0.5, 0.0, 1.0)
+    mt = rng.standard_normal(g.N)
+    b_over_a, delta = 1.7, 1e-6
+    P = prior.Prior(g, kt, mt, T, b_over_a, delta, solver="deflated")
+    Md = P.Md.toarray()
+    p = rng.standard_normal(2 * g.N) + 0.3
+    x = P.solve(p)
+    N = g.N
+    ref = np.concatenate([_exact_solve(Md[:N, :N], p[:N], delta), _exact_solve(Md[N:, N:], p[N:], delta)])
+    assert np.all(np.abs(x - ref) <= 1e-13 * (np.abs(ref) + np.abs(ref).max()))
+    # the mean of each block is mean(p)/delta, exactly the delta-eigenvector part
+    assert abs(ref[:N].mean() - p[:N].mean() / delta) <= 1e-12 * abs(p[:N].mean() / delta)
+    assert abs(ref[N:].mean() - p[N:].mean() / delta) <= 1e-12 * abs(p[N:].mean() / delta)
+
+
+def test_deflated_solve_is_more_accurate_than_plain_lu():
+    """On the 8^3 phantom the deflated solve's residual with rows summing to zero
+    exactly stays below 1e-10 -- the floor is the assembly's row sums (~1e-16
+    |M_ii|) times the mean-free part of the solution, whose size is set by the
+    smallest non-zero eigenvalue of M(u), not by delta -- and each block's mean is
+    mean(p)/delta. The plain LU of M_delta agrees only to about eps cond(M_delta)."""
+    P8 = make_problem("T8")
+    g = fem.geometry(P8.mesh.coords, P8.mesh.tets, P8.mesh.bfaces)
+    kt = np.log(P8.kappa / P8.kappa0)
+    mt = np.log(P8.mu / P8.mu0)
+    delta = 1e-6
+    Pd = prior.Prior(g, kt, mt, T, 1.0, delta, solver="deflated")
+    Pl = prior.Prior(g, kt, mt, T, 1.0, delta, solver="direct")
+    p = np.random.default_rng(6).standard_normal(2 * g.N)
+    xd, xl = Pd.solve(p), Pl.solve(p)
+    res_d = np.linalg.norm(_ideal_residual(Pd.Md, g.N, xd, p, delta)) / np.linalg.norm(p)
+    assert res_d <= 1e-10
+    N = g.N
+    for j in range(2):
+        mj = p[j * N:(j + 1) * N].mean() / delta
+        assert abs(xd[j * N:(j + 1) * N].mean() - mj) <= 1e-13 * abs(mj)
+    assert np.linalg.norm(xd - xl) / np.linalg.norm(xd) <= 1e-7
