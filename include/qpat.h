@@ -49,20 +49,26 @@ typedef enum {
 typedef struct {
     int32_t precision;      /* 0: FP64 throughout. 1: mixed -- FP32 operator, FP32 Jacobi and
                                FP32 PCG vectors, FP64 dot products, FP64 true-residual
-                               recomputation (reliable updates) and FP64 iterate.            */
+                               recomputation (reliable updates) and FP64 iterate. Mixed is
+                               an arithmetic of the Jacobi-PCG K solves: it requires
+                               pcg_precond = 0 (QPAT_ERR_ARG otherwise). M_delta solves and
+                               LSQR are FP64 in both modes.                                   */
     int32_t max_rhs_block;  /* right-hand sides per block PCG (1, 2, 4, 8 or 16). 1 solves the
                                illuminations one after another ("plain").                    */
     double  pcg_rtol;       /* K solves stop when ||b - K x||_2 <= pcg_rtol ||b||_2 (true
                                residual, FP64).                                                */
     int32_t pcg_maxit;      /* iteration cap per solve -> QPAT_ERR_NOCONV.                    */
-    double  prior_rtol;     /* same rule for M_delta solves (default 1e-8: with delta = 1e-6
-                               and Perona-Malik diffusivities down to ~1e-5 across edges,
-                               FP64 PCG attains ~1e-9 on 128^3 meshes).                      */
+    double  prior_rtol;     /* same rule for M_delta solves (default 1e-10; with deflation and
+                               the multigrid preconditioner the 128^3 phantom's M_delta
+                               reaches 1e-11, Jacobi-PCG only ~1e-9 there).                  */
     int32_t prior_deflate;  /* 1: the constant vector of each block (the delta-eigenvector of
                                M_delta) is solved exactly and PCG runs on its complement.    */
     int32_t lsqr_reorth;    /* 1: full reorthogonalisation of both bidiagonalisation bases.
                                0: plain Paige-Saunders recurrences.                           */
-    int32_t lsqr_max_steps; /* capacity of the stored bases when lsqr_reorth = 1.             */
+    int32_t lsqr_max_steps; /* initial capacity (steps) of the stored bases when lsqr_reorth = 1;
+                               a run that fills them doubles the capacity, or -- when the
+                               device cannot hold more -- continues with the plain
+                               recurrences (qpat_lsqr_basis then reports 0).             */
     double  ru_delta;       /* mixed precision: recompute the FP64 residual whenever the
                                recursive one fell by this factor since the last recompute.   */
     int32_t use_graphs;     /* 1: replay chunks of PCG iterations as captured HIP graphs.     */
@@ -75,21 +81,33 @@ typedef struct {
                                (lattice meshes with the stencil form; otherwise Jacobi),
                                0 = Jacobi-PCG. Same stopping rule either way.               */
     int32_t pcg_precond;    /* K solves: 1 = PCG with a geometric multigrid V-cycle in FP64
-                               (lattice meshes with the stencil form; elsewhere, and with
-                               0, Jacobi-PCG in the arithmetic `precision` selects). Same
-                               stopping rule either way.                                      */
+                               (lattice meshes with the stencil form; elsewhere Jacobi-PCG
+                               in FP64); 0 = Jacobi-PCG in the arithmetic `precision`
+                               selects. Same stopping rule either way.                       */
 } qpat_opts;
 
+/* Solve report of a call (host struct). The first five fields are outputs.
+ * The last three are inputs that the call only reads: host arrays of rhs_cap
+ * entries that receive, for every linear system the call solved (one per
+ * right-hand side, block by block in the order solved; the padding columns
+ * of a block of illuminations included, with zero right-hand sides, 0
+ * iterations and residual 0), its PCG iteration count and its final true
+ * relative residual ||b - A x|| / ||b||. Entries past rhs_cap are dropped;
+ * rhs_cap = 0 or NULL arrays ask for none. Zero-initialise the struct when
+ * the per-system arrays are not wanted. */
 typedef struct {
     int32_t n_solves;       /* linear systems solved by the call                               */
     int32_t iters_max;      /* largest PCG iteration count among them                          */
     int64_t iters_sum;      /* total PCG iterations                                            */
     int32_t updates;        /* FP64 true-residual recomputations                              */
     double  relres_max;     /* largest final true relative residual                           */
+    int32_t rhs_cap;        /* in: capacity of rhs_iters / rhs_relres                          */
+    int32_t* rhs_iters;     /* in: host array [rhs_cap] or NULL                                */
+    double* rhs_relres;     /* in: host array [rhs_cap] or NULL                                */
 } qpat_info;
 
 /* Fill *opts with the defaults: FP64, block 16, rtol 1e-10, maxit 20000,
- * prior_rtol 1e-8, deflation on, reorthogonalisation on with 64 steps,
+ * prior_rtol 1e-10, deflation on, reorthogonalisation on with 64 steps,
  * ru_delta 1e-3, graphs on, stencil form on lattice meshes, multigrid for M_delta. */
 void qpat_default_opts(qpat_opts* opts);
 
@@ -319,7 +337,6 @@ qpat_status qpat_guess_fluence(qpat_ctx* ctx, const double* kappa, const double*
 qpat_status qpat_forward_x0(qpat_ctx* ctx, const double* kappa, const double* mu, const double* x0,
                             double* phi_out, double* h_out, qpat_info* info);
 
-/* Steps taken since qpat_lsqr_init. */
 /* Number of geometry classes the Jacobian's element kernels use: at mesh
  * set-up every tetrahedron's geometry (|T| and the barycentric gradients)
  * is compared bit for bit with the distinct geometries of the first 64
@@ -329,7 +346,14 @@ qpat_status qpat_forward_x0(qpat_ctx* ctx, const double* kappa, const double* mu
  * has 6. Host-only; -1 for a null context. */
 int32_t qpat_geometry_classes(const qpat_ctx* ctx);
 
+/* Steps taken since qpat_lsqr_init (0 before any init or for a null context). */
 int32_t qpat_lsqr_steps(const qpat_ctx* ctx);
+
+/* Vectors in the stored bases that the reorthogonalisation of the current
+ * LSQR run works against (steps + 1 while it is on); 0 when it is off --
+ * lsqr_reorth = 0, or the run went on with the plain recurrences because the
+ * device could not hold larger bases. */
+int32_t qpat_lsqr_basis(const qpat_ctx* ctx);
 
 /* |phibar| after the last qpat_lsqr_init (= ||yt||) or qpat_lsqr_step, from
  * the host copy made when that call returned; -1 before any init. */

@@ -67,6 +67,12 @@ qpat_status check_opts(qpat_ctx* c, const qpat_opts* o) {
         return fail(c, QPAT_ERR_ARG, "operator_format must be 0 or 1");
     if (o->prior_precond != 0 && o->prior_precond != 1) return fail(c, QPAT_ERR_ARG, "prior_precond must be 0 or 1");
     if (o->pcg_precond != 0 && o->pcg_precond != 1) return fail(c, QPAT_ERR_ARG, "pcg_precond must be 0 or 1");
+    // the multigrid K solves are FP64 throughout; the mixed arithmetic (FP32
+    // operator and vectors, FP64 reductions and reliable updates) is the
+    // Jacobi-PCG path's, so asking for both is an error rather than a silent
+    // FP64 run
+    if (o->precision == 1 && o->pcg_precond == 1)
+        return fail(c, QPAT_ERR_ARG, "precision = 1 (mixed) needs pcg_precond = 0: the multigrid K solves are FP64");
     return QPAT_OK;
 }
 
@@ -77,6 +83,11 @@ void fill_info(qpat_info* info, const SolveStats& s) {
     info->iters_sum = s.iters_sum;
     info->updates = s.updates;
     info->relres_max = s.relres_max;
+    const int32_t n = std::min<int32_t>(std::max(info->rhs_cap, 0), static_cast<int32_t>(s.rhs_iters.size()));
+    if (info->rhs_iters)
+        for (int32_t i = 0; i < n; ++i) info->rhs_iters[i] = s.rhs_iters[i];
+    if (info->rhs_relres)
+        for (int32_t i = 0; i < n; ++i) info->rhs_relres[i] = s.rhs_relres[i];
 }
 
 qpat_status finish(qpat_ctx* c, const SolveStats& s, qpat_info* info) {
@@ -134,7 +145,7 @@ qpat_status alloc_core(qpat_ctx* c) {
 
 qpat_status alloc_bases(qpat_ctx* c) {
     const int cap = c->opts.lsqr_max_steps + 1;
-    if (c->basis_cap == cap && c->U) return QPAT_OK;
+    if (c->basis_cap >= cap && c->U) return QPAT_OK;   // possibly grown by an earlier run
     QPAT_TRY(dfree(c, c->U));
     QPAT_TRY(dfree(c, c->V));
     QPAT_TRY(dfree(c, c->WH));
@@ -173,7 +184,7 @@ void qpat_default_opts(qpat_opts* o) {
     o->max_rhs_block = 16;
     o->pcg_rtol = 1e-10;
     o->pcg_maxit = 20000;
-    o->prior_rtol = 1e-8;
+    o->prior_rtol = 1e-10;
     o->prior_deflate = 1;
     o->lsqr_reorth = 1;
     o->lsqr_max_steps = 64;
@@ -588,10 +599,7 @@ qpat_status qpat_fit_background(qpat_ctx* c, const double* chi, const double* w,
         QPAT_TRY(jvp_core(c, s1, 0, j1, &sj));
         QPAT_TRY(jvp_core(c, s2, 0, j2, &sj));
         if (sj.noconv) return fail(c, QPAT_ERR_NOCONV, "fit_background: PCG did not converge in J");
-        st.n_solves += sj.n_solves;
-        st.iters_sum += sj.iters_sum;
-        st.iters_max = std::max(st.iters_max, sj.iters_max);
-        st.relres_max = std::max(st.relres_max, sj.relres_max);
+        st.merge(sj);
         double S[6];
         QPAT_TRY(fit_sums(c, chi, w, j1, j2, rr, S));
         const double det = S[0] * S[2] - S[1] * S[1];
@@ -663,7 +671,14 @@ qpat_status qpat_batch(qpat_ctx* const* ctxs, int32_t n, int32_t op, const doubl
     std::vector<qpat_info> inf(n);
     auto work = [&](int i) {
         qpat_ctx* c = ctxs[i];
+        // the caller's per-right-hand-side arrays (if any) are kept; the pair's
+        // second call continues where the first stopped
         qpat_info a{}, b{};
+        if (infos) {
+            a.rhs_cap = infos[i].rhs_cap;
+            a.rhs_iters = infos[i].rhs_iters;
+            a.rhs_relres = infos[i].rhs_relres;
+        }
         switch (op) {
             case QPAT_BATCH_FORWARD:
                 st[i] = qpat_forward(c, in0[i], in1[i], nullptr, out0 ? out0[i] : nullptr, &a);
@@ -672,6 +687,11 @@ qpat_status qpat_batch(qpat_ctx* const* ctxs, int32_t n, int32_t op, const doubl
             case QPAT_BATCH_VJP: st[i] = qpat_vjp(c, in0[i], out0[i], &a); break;
             case QPAT_BATCH_PAIR:
                 st[i] = qpat_jvp(c, in0[i], out0[i], &a);
+                if (a.rhs_cap > a.n_solves) {
+                    b.rhs_cap = a.rhs_cap - a.n_solves;
+                    b.rhs_iters = a.rhs_iters ? a.rhs_iters + a.n_solves : nullptr;
+                    b.rhs_relres = a.rhs_relres ? a.rhs_relres + a.n_solves : nullptr;
+                }
                 if (st[i] == QPAT_OK) st[i] = qpat_vjp(c, in1[i], out1[i], &b);
                 a.n_solves += b.n_solves;
                 a.iters_max = std::max(a.iters_max, b.iters_max);
@@ -724,6 +744,8 @@ qpat_status qpat_operator_layout(const qpat_ctx* c, int64_t out[6]) {
 int32_t qpat_geometry_classes(const qpat_ctx* c) { return c ? c->geo_ncls : -1; }
 
 int32_t qpat_lsqr_steps(const qpat_ctx* c) { return c && c->ls_host ? c->ls_host->steps : 0; }
+
+int32_t qpat_lsqr_basis(const qpat_ctx* c) { return c && c->reorth_on ? c->nbasis : 0; }
 
 double qpat_lsqr_residual(const qpat_ctx* c) {
     if (!c || !c->ls_host || !c->lsqr_ready) return -1.0;

@@ -419,12 +419,46 @@ qpat_status lsqr_init_core(qpat_ctx* c, const double* chi, const double* w, cons
     return QPAT_OK;
 }
 
+// The stored bases are full: double their capacity (the stored vectors are
+// copied over). When the device cannot hold the larger bases the run goes on
+// with the plain recurrences (reorthogonalisation off until the next init;
+// qpat_lsqr_basis reports 0 then).
+static qpat_status grow_bases(qpat_ctx* c) {
+    const int64_t nd = c->N * c->n_pad, n2 = 2 * c->N;
+    const int cap = 2 * c->basis_cap;
+    void *u = nullptr, *v = nullptr, *wh = nullptr, *cf = nullptr;
+    bool ok = hipMalloc(&u, (size_t)cap * nd * sizeof(double)) == hipSuccess &&
+              hipMalloc(&v, (size_t)cap * n2 * sizeof(double)) == hipSuccess &&
+              hipMalloc(&wh, (size_t)cap * n2 * sizeof(double)) == hipSuccess &&
+              hipMalloc(&cf, (size_t)cap * sizeof(double)) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();   // the failed allocation is not an error of the run
+        for (void* p : {u, v, wh, cf})
+            if (p) (void)hipFree(p);
+        c->reorth_on = false;
+        c->nbasis = 0;
+        return QPAT_OK;
+    }
+    const size_t nb = static_cast<size_t>(c->nbasis);
+    QPAT_HIP(c, hipMemcpyAsync(u, c->U, nb * nd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    QPAT_HIP(c, hipMemcpyAsync(v, c->V, nb * n2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    QPAT_HIP(c, hipMemcpyAsync(wh, c->WH, nb * n2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    QPAT_HIP(c, hipStreamSynchronize(c->stream));
+    for (double* p : {c->U, c->V, c->WH, c->coef}) QPAT_TRY(dfree(c, p));
+    for (void* p : {u, v, wh, cf}) c->allocs.push_back(p);
+    c->U = static_cast<double*>(u);
+    c->V = static_cast<double*>(v);
+    c->WH = static_cast<double*>(wh);
+    c->coef = static_cast<double*>(cf);
+    c->basis_cap = cap;
+    return QPAT_OK;
+}
+
 qpat_status lsqr_step_core(qpat_ctx* c, SolveStats* st) {
     const int64_t nd = c->N * c->n_pad, n2 = 2 * c->N;
     if (c->ls_host->done) return QPAT_OK;
+    if (c->reorth_on && c->nbasis >= c->basis_cap) QPAT_TRY(grow_bases(c));
     const bool ro = c->reorth_on;
-    if (ro && c->nbasis >= c->basis_cap)
-        return fail(c, QPAT_ERR_STATE, "lsqr_max_steps (%d) reached with reorthogonalisation on", c->basis_cap - 1);
     // q = W J v - alpha u
     QPAT_TRY(jvp_core(c, c->lv, 1, c->lq, st));
     if (ro) QPAT_TRY(reorth(c, c->lq, nd, c->U, c->U, nd, c->nbasis));

@@ -5,7 +5,6 @@
 // of the path (K, the load operators G(1), G(2), the prior M) lives on the
 // node-node pattern of that partition.
 #include <cstring>
-#include <hipcub/hipcub.hpp>
 
 #include "qpat_internal.h"
 
@@ -222,13 +221,61 @@ __global__ void k_fill_sell(const int32_t* __restrict__ tmp, const int32_t* __re
     }
 }
 
+// Exclusive prefix sum (set-up only: adjacency offsets, slice offsets). A block
+// scans a tile of kScanTile values -- each thread a run of kScanPer, then the
+// thread totals in LDS -- and writes the tile's total; the totals are scanned
+// the same way (recursively) and added back. Each block reads its whole tile
+// before writing it, so `in` may alias `out`.
+constexpr int kScanT = 256, kScanPer = 16, kScanTile = kScanT * kScanPer;
+
+__global__ __launch_bounds__(kScanT) void k_scan_tile(const int32_t* in, int32_t* out, int64_t n,
+                                                       int32_t* __restrict__ tile_sum) {
+    __shared__ int32_t part[kScanT];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int32_t v[kScanPer];
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        s += v[k];
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanT; off <<= 1) {   // inclusive scan of the thread totals
+        const int32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int32_t run = part[threadIdx.x] - s;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == kScanT - 1) tile_sum[blockIdx.x] = part[kScanT - 1];
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ out, int64_t n, const int32_t* __restrict__ tile_off) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] += tile_off[i / kScanTile];
+}
+
 qpat_status exclusive_scan(qpat_ctx* c, const int32_t* in, int32_t* out, int64_t n) {
-    size_t bytes = 0;
-    QPAT_HIP(c, hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, c->stream));
-    void* tmp = nullptr;
-    QPAT_TRY(dalloc(c, reinterpret_cast<char**>(&tmp), bytes));
-    QPAT_HIP(c, hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, (int)n, c->stream));
-    QPAT_TRY(dfree(c, tmp));
+    if (n <= 0) return QPAT_OK;
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    int32_t *sum = nullptr, *off = nullptr;
+    QPAT_TRY(dalloc(c, &sum, tiles));
+    QPAT_TRY(dalloc(c, &off, tiles));
+    hipLaunchKernelGGL(k_scan_tile, dim3(static_cast<uint32_t>(tiles)), dim3(kScanT), 0, c->stream, in, out, n, sum);
+    if (tiles > 1) {
+        QPAT_TRY(exclusive_scan(c, sum, off, tiles));
+        hipLaunchKernelGGL(k_scan_add, dim3(static_cast<uint32_t>((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                           c->stream, out, n, off);
+    }
+    QPAT_HIP(c, hipGetLastError());
+    QPAT_TRY(dfree(c, sum));   // hipFree waits for the kernels above
+    QPAT_TRY(dfree(c, off));
     return QPAT_OK;
 }
 

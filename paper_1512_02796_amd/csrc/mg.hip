@@ -2972,8 +2972,10 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
                 continue;
             }
             if (c->opts.use_graphs) {
-                char key[96];
-                snprintf(key, sizeof key, "%d/%d/%.17g/%d/%d", B, chunk, a.rtol2, a.maxit, a.deflate);
+                // every by-value argument of the captured kernels that can change
+                // between runs: the region count is recomputed at each prior set-up
+                char key[112];
+                snprintf(key, sizeof key, "%d/%d/%.17g/%d/%d/%d", B, chunk, a.rtol2, a.maxit, a.deflate, a.kreg);
                 auto it = M.graphs.find(key);
                 hipGraphExec_t ex = nullptr;
                 if (it != M.graphs.end()) {
@@ -3004,12 +3006,8 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
         const MgScal& s = M.sc_host[i];
         if (op == Op::Prior)   // the output kernel of the prior solve adds mean(b)/delta
             QPAT_HIP(c, hipMemcpyAsync(&c->scal[i].mean, &M.sc[i].mean, sizeof(double), hipMemcpyDeviceToDevice, sm));
-        st->n_solves += 1;
-        st->iters_max = std::max(st->iters_max, s.iters);
-        st->iters_sum += s.iters;
         const double rel = s.bnorm2 > 0 ? std::sqrt(s.rr / s.bnorm2) : 0.0;
-        st->relres_max = std::max(st->relres_max, rel);
-        if (!s.done) st->noconv = true;
+        st->add(s.iters, rel, 0, s.done != 0);
     }
     return QPAT_OK;
 }

@@ -769,7 +769,13 @@ __global__ __launch_bounds__(kRedThreads) void k_red_true(RedArgs a) {
             c.rz_prev = rzn;
             c.rz = rzn;
         } else {
-            c.beta = c.rz_prev != 0.0 ? rzn / c.rz_prev : 0.0;
+            // the residual replaced here is the recursive one's continuation only
+            // while the two agree; one far above it (a failed convergence check,
+            // or FP32 drift past a reliable-update point) would scale the old
+            // direction by rz_true / rz_prev and stall the iteration, so the lane
+            // restarts from the true residual (beta = 0: p = z)
+            const bool stale = rrt > 4.0 * c.rr;
+            c.beta = (!stale && c.rz_prev != 0.0) ? rzn / c.rz_prev : 0.0;
             c.rz = rzn;
             c.updates += 1;
         }
@@ -1250,13 +1256,8 @@ struct Runner {
             }
         }
         for (int i = 0; i < S; ++i) {
-            st->n_solves += 1;
-            st->iters_max = std::max(st->iters_max, hs[i].iters);
-            st->iters_sum += hs[i].iters;
-            st->updates += hs[i].updates;
-            double rel = hs[i].bnorm2 > 0 ? std::sqrt(hs[i].truerr / hs[i].bnorm2) : 0.0;
-            st->relres_max = std::max(st->relres_max, rel);
-            if (!hs[i].done) st->noconv = true;
+            const double rel = hs[i].bnorm2 > 0 ? std::sqrt(hs[i].truerr / hs[i].bnorm2) : 0.0;
+            st->add(hs[i].iters, rel, hs[i].updates, hs[i].done != 0);
         }
         return QPAT_OK;
     }

@@ -329,6 +329,29 @@ struct SolveStats {
     int64_t iters_sum = 0;
     double relres_max = 0.0;
     bool noconv = false;
+    // per system solved, in order (block by block, right-hand side by right-hand side)
+    std::vector<int32_t> rhs_iters;
+    std::vector<double> rhs_relres;
+    void add(int32_t iters, double relres, int32_t upd, bool done) {
+        n_solves += 1;
+        iters_max = std::max(iters_max, iters);
+        iters_sum += iters;
+        updates += upd;
+        relres_max = std::max(relres_max, relres);
+        if (!done) noconv = true;
+        rhs_iters.push_back(iters);
+        rhs_relres.push_back(relres);
+    }
+    void merge(const SolveStats& o) {
+        n_solves += o.n_solves;
+        iters_max = std::max(iters_max, o.iters_max);
+        iters_sum += o.iters_sum;
+        updates += o.updates;
+        relres_max = std::max(relres_max, o.relres_max);
+        noconv = noconv || o.noconv;
+        rhs_iters.insert(rhs_iters.end(), o.rhs_iters.begin(), o.rhs_iters.end());
+        rhs_relres.insert(rhs_relres.end(), o.rhs_relres.begin(), o.rhs_relres.end());
+    }
 };
 // Solve op * x = b for B right-hand sides (interleaved [N][B], b in c->b64,
 // result in c->x64). For Op::Prior, nsys = 2 systems with B = 1 ([2][N]).

@@ -39,10 +39,25 @@ class Opts(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("n_solves", ctypes.c_int32), ("iters_max", ctypes.c_int32),
                 ("iters_sum", ctypes.c_int64), ("updates", ctypes.c_int32),
-                ("relres_max", ctypes.c_double)]
+                ("relres_max", ctypes.c_double), ("rhs_cap", ctypes.c_int32),
+                ("rhs_iters", ctypes.POINTER(ctypes.c_int32)), ("rhs_relres", ctypes.POINTER(ctypes.c_double))]
+    RHS_CAP = 4096
+
+    def __init__(self):
+        super().__init__()
+        # host buffers for the per-system report, owned by this object
+        self._it = (ctypes.c_int32 * self.RHS_CAP)()
+        self._rr = (ctypes.c_double * self.RHS_CAP)()
+        self.rhs_cap = self.RHS_CAP
+        self.rhs_iters = ctypes.cast(self._it, ctypes.POINTER(ctypes.c_int32))
+        self.rhs_relres = ctypes.cast(self._rr, ctypes.POINTER(ctypes.c_double))
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_[:5]}
+        n = max(0, min(self.n_solves, self.rhs_cap))
+        d["rhs_iters"] = list(self.rhs_iters[:n]) if self.rhs_iters else []
+        d["rhs_relres"] = list(self.rhs_relres[:n]) if self.rhs_relres else []
+        return d
 
 
 class KStat(ctypes.Structure):
@@ -88,6 +103,7 @@ SIGNATURES = {
     "qpat_lsqr_init": (_S, [_P, _P, _P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_lsqr_step": (_S, [_P, ctypes.POINTER(_D), ctypes.POINTER(Info)]),
     "qpat_lsqr_steps": (_I32, [_P]),
+    "qpat_lsqr_basis": (_I32, [_P]),
     "qpat_geometry_classes": (_I32, [_P]),
     "qpat_lsqr_residual": (_D, [_P]),
     "qpat_profile": (_S, [_P, _I32]),
@@ -376,6 +392,9 @@ class Context:
     def lsqr_steps(self):
         return _lib.qpat_lsqr_steps(self._h)
 
+    def lsqr_basis(self):
+        return _lib.qpat_lsqr_basis(self._h)
+
     def geometry_classes(self):
         return int(_lib.qpat_geometry_classes(self._h))
 
@@ -415,7 +434,8 @@ def batch(ctxs, op, in0=None, out0=None, in1=None, out1=None):
         for i, t in enumerate(lst):
             arr[i] = None if t is None else _ptr(t, dtype, name=f"{what}[{i}]").value
         return arr
-    infos = (Info * n)()
+    owners = [Info() for _ in range(n)]     # own the per-system buffers the array entries point at
+    infos = (Info * n)(*owners)
     st = _lib.qpat_batch(hs, n, BATCH_OPS[op], ptrs(in0, "in0"), ptrs(out0, "out0"), ptrs(in1, "in1"),
                          ptrs(out1, "out1"), infos)
     if st != 0:
