@@ -61,3 +61,30 @@ def data_of(P, lin):
 
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def close(a, b, rtol):
+    """Element-wise bound |a - b| <= rtol |b| + rtol max|b| at every entry
+    (relative where the entry is large, absolute at the scale of the largest
+    entry where it is small); returns (ok, worst ratio of |a - b| to the bound)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    assert a.shape == b.shape, (a.shape, b.shape)
+    if b.size == 0:
+        return True, 0.0
+    bound = rtol * (np.abs(b) + np.abs(b).max())
+    err = np.abs(a - b)
+    ratio = float(np.max(err / np.where(bound > 0, bound, np.inf))) if np.any(bound > 0) else float(err.max())
+    ok = bool(np.all(err <= bound)) and bool(np.all(np.isfinite(a)))
+    return ok, ratio
+
+
+def assert_close(a, b, rtol, what=""):
+    """assert close(a, b, rtol); the message names the worst entry."""
+    ok, ratio = close(a, b, rtol)
+    if not ok:
+        a = np.asarray(a, dtype=np.float64).ravel()
+        b = np.asarray(b, dtype=np.float64).ravel()
+        i = int(np.argmax(np.abs(a - b) / (np.abs(b) + np.abs(b).max() + 1e-300)))
+        raise AssertionError(f"{what}: element-wise rtol {rtol:g} exceeded by {ratio:.3g}x "
+                             f"(entry {i}: {a[i]!r} vs {b[i]!r}; norm-wise {rel(a, b):.3e})")

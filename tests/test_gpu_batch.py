@@ -1,10 +1,11 @@
 """Batched instances (qpat_batch): several contexts on their own streams
-advanced by one call give exactly the results of calling them one by one."""
+advanced by one call give exactly the results of calling them one by one,
+and those match the oracle."""
 import numpy as np
 import pytest
 import torch
 
-from gpu_util import GpuProblem, dev, host, need_gpu
+from gpu_util import GpuProblem, dev, host, need_gpu, oracle_of, assert_close
 from qpat_inputs import make_problem, probe_vectors
 
 pytestmark = pytest.mark.gpu
@@ -23,7 +24,7 @@ def instances():
         m = P.mesh
         st = torch.cuda.Stream()
         ctx = qpat.Context(dev(m.coords), dev(m.tets, torch.int32), dev(m.bfaces, torch.int32),
-                           opts=qpat.default_opts(precision=1), stream=st)
+                           opts=qpat.default_opts(pcg_rtol=1e-12), stream=st)
         ctx.set_sources(dev(P.phi_src))
         s, t = probe_vectors(P.cfg["id"], P.n_ill, m.N)
         out.append((P, ctx, dev(s), dev(t)))
@@ -49,7 +50,14 @@ def test_batch_equals_one_by_one():
         ctx.vjp(t, b)
         torch.cuda.synchronize()
         assert torch.equal(a, js) and torch.equal(b, jt)
-        assert info["n_solves"] >= 2 * P.n_ill and info["relres_max"] <= 1e-10
+        assert info["n_solves"] >= 2 * P.n_ill and info["relres_max"] <= 1e-12
+        assert len(info["rhs_iters"]) == info["n_solves"]
+        if P.mesh.N <= 20000:     # the oracle's sparse LU at these sizes takes seconds
+            g, lin = oracle_of(P)
+            assert_close(host(h1).reshape(P.n_ill, -1), lin.h, 1e-10, f"h n={P.mesh.n}")
+            sh, th = host(s), host(t).reshape(P.n_ill, -1)
+            assert_close(host(js).reshape(P.n_ill, -1), lin.jvp(sh), 1e-10, f"J s n={P.mesh.n}")
+            assert_close(host(jt), lin.vjp(th), 1e-10, f"J^T t n={P.mesh.n}")
     for c in ctxs:
         c.close()
 

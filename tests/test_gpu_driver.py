@@ -1,22 +1,26 @@
 """Algorithm 1 on the GPU library vs the oracle's Algorithm 1 (16^3 face-source workload).
 
 Both sides get the same data chi, W (simulated by the oracle from the seeded
-phantom). LSQR iterates of this strongly graded operator move by about 1e-6
-relative under a 1e-12 relative perturbation of M_delta^{-1} (measured on
-the oracle with reorthogonalisation; see tests/test_oracle_plsqr.py), and two
-outer steps compound that, so beta is compared at 1e-4. The whitened
-residual norms inherit the pointwise relative error of h at nodes of tiny
-fluence (W = 1/(sigma |h|) amplifies it; the solves bound it only in norm),
-about 1e-7, and are compared at 1e-6.
+phantom); the oracle applies M_delta^{-1} with its delta-eigenvector taken
+exactly, the library with deflated PCG at prior_rtol 1e-12. LSQR iterates of
+this strongly graded operator are sensitive to perturbations of M_delta^{-1}
+(tests/test_oracle_plsqr.py), and the whitened residual norms inherit the
+pointwise error of h at nodes of tiny fluence (W = 1/(sigma |h|) amplifies
+it; the K solves bound it only in norm). Measured: histories agree to 1e-8
+with the Perona-Malik prior and to 2e-8 - 5e-8 with smoothed TV and after the
+background fit; they are compared at 1e-8 and 1e-7, beta element by element
+at 1e-6.
 """
 import numpy as np
 import pytest
 import torch
 
-from gpu_util import GpuProblem, oracle_of, data_of, dev, host, rel, need_gpu
+from gpu_util import GpuProblem, oracle_of, data_of, dev, host, rel, need_gpu, assert_close
 from oracle.driver import reconstruct as oracle_reconstruct
 
 pytestmark = pytest.mark.gpu
+
+DEFL = dict(prior_solver="deflated")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -32,11 +36,11 @@ def test_algorithm1_matches_oracle():
     g, lin = oracle_of(P)
     chi, W = data_of(P, lin)
     beta, log = reconstruct(G.ctx, dev(chi), dev(W), P.kappa0, P.mu0, outer=2, inner=8)
-    ref_beta, ref_log = oracle_reconstruct(g, P.phi_src, chi, W, P.kappa0, P.mu0, outer=2, inner=8)
-    assert np.allclose(log["res_nl"], ref_log["res_nl"], rtol=1e-6), (log["res_nl"], ref_log["res_nl"])
+    ref_beta, ref_log = oracle_reconstruct(g, P.phi_src, chi, W, P.kappa0, P.mu0, outer=2, inner=8, **DEFL)
+    assert_close(log["res_nl"], ref_log["res_nl"], 1e-8, "nonlinear residuals")
     for a, b in zip(log["lsqr"], ref_log["lsqr"]):
-        assert np.allclose(a, b, rtol=1e-6)
-    assert rel(host(beta), ref_beta) <= 1e-4
+        assert_close(a, b, 1e-8, "LSQR residual history")
+    assert_close(host(beta), ref_beta, 1e-6, "beta")
     assert log["rejected"] == ref_log["rejected"] == [False, False]
     # reconstruction quality (qualitative): residual falls towards sqrt(n_ill N)
     assert log["res_nl"][-1] < 0.25 * log["res_nl"][0]
@@ -52,9 +56,9 @@ def test_algorithm1_tv_prior_matches_oracle():
     chi, W = data_of(P, lin)
     beta, log = reconstruct(G.ctx, dev(chi), dev(W), P.kappa0, P.mu0, outer=1, inner=6, prior="tvq", q=1.0)
     ref_beta, ref_log = oracle_reconstruct(g, P.phi_src, chi, W, P.kappa0, P.mu0, outer=1, inner=6,
-                                           prior="tvq", q=1.0)
-    assert np.allclose(log["lsqr"][0], ref_log["lsqr"][0], rtol=1e-6)
-    assert rel(host(beta), ref_beta) <= 1e-4
+                                           prior="tvq", q=1.0, **DEFL)
+    assert_close(log["lsqr"][0], ref_log["lsqr"][0], 1e-7, "LSQR residual history")
+    assert_close(host(beta), ref_beta, 1e-6, "beta")
 
 
 def test_step4_rejection_returns_previous_iterate():
@@ -133,9 +137,9 @@ def test_step0_matches_oracle():
     g, lin = oracle_of(P)
     chi, W = data_of(P, lin)
     beta, log = reconstruct(G.ctx, dev(chi), dev(W), P.kappa0, P.mu0, outer=0, inner=0, step0_inner=6)
-    rbeta, rlog = oref(g, P.phi_src, chi, W, P.kappa0, P.mu0, outer=0, inner=0, step0_inner=6)
-    assert np.allclose(log["step0"], rlog["step0"], rtol=1e-6), (log["step0"], rlog["step0"])
-    assert rel(host(beta), rbeta) <= 1e-4
+    rbeta, rlog = oref(g, P.phi_src, chi, W, P.kappa0, P.mu0, outer=0, inner=0, step0_inner=6, **DEFL)
+    assert_close(log["step0"], rlog["step0"], 1e-8, "step-0 history")
+    assert_close(host(beta), rbeta, 1e-6, "beta after step 0")
     # direct use: the iterate's mt half stays exactly zero
     N = G.N
     b = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
@@ -159,12 +163,12 @@ def test_algorithm1_with_fit_and_step0():
     chi, W = data_of(P, lin)
     kw = dict(outer=1, inner=6, fit=True, step0_inner=4)
     beta, log = reconstruct(G.ctx, dev(chi), dev(W), 1.5 * P.kappa0, 0.7 * P.mu0, **kw)
-    ref_beta, ref_log = oracle_reconstruct(g, P.phi_src, chi, W, 1.5 * P.kappa0, 0.7 * P.mu0, **kw)
+    ref_beta, ref_log = oracle_reconstruct(g, P.phi_src, chi, W, 1.5 * P.kappa0, 0.7 * P.mu0, **kw, **DEFL)
     assert abs(log["kappa0"] / ref_log["kappa0"] - 1) <= 1e-8
     assert abs(log["mu0"] / ref_log["mu0"] - 1) <= 1e-8
-    assert np.allclose(log["step0"], ref_log["step0"], rtol=1e-6)
-    assert np.allclose(log["lsqr"][0], ref_log["lsqr"][0], rtol=1e-6)
-    assert rel(host(beta), ref_beta) <= 1e-4
+    assert_close(log["step0"], ref_log["step0"], 1e-7, "step-0 history")
+    assert_close(log["lsqr"][0], ref_log["lsqr"][0], 1e-7, "LSQR residual history")
+    assert_close(host(beta), ref_beta, 1e-6, "beta")
 
 
 def test_finer_mesh_data_matches_oracle():
@@ -182,15 +186,15 @@ def test_finer_mesh_data_matches_oracle():
     h = finer_mesh_data(F.ctx, F.kappa, F.mu, dev(inj, torch.int64))
     gf, _ = oracle_of(F.P)
     ref = ofine(gf, F.P.kappa, F.P.mu, F.P.phi_src, inj)
-    assert rel(host(h), ref) <= 1e-10
+    assert_close(host(h), ref, 1e-10, "finer-mesh data")
     g, lin = oracle_of(G.P)
     gap = rel(ref, lin.h)                       # the inverse-crime gap, O(h^2) with jumps
     assert 1e-4 < gap < 0.2, gap
     W = 1.0 / (0.01 * np.abs(ref))
     beta, log = reconstruct(G.ctx, h, dev(W), G.P.kappa0, G.P.mu0, outer=1, inner=6)
-    rbeta, rlog = oref(g, G.P.phi_src, ref, W, G.P.kappa0, G.P.mu0, outer=1, inner=6)
-    assert np.allclose(log["lsqr"][0], rlog["lsqr"][0], rtol=1e-6)
-    assert rel(host(beta), rbeta) <= 1e-4
+    rbeta, rlog = oref(g, G.P.phi_src, ref, W, G.P.kappa0, G.P.mu0, outer=1, inner=6, **DEFL)
+    assert_close(log["lsqr"][0], rlog["lsqr"][0], 1e-8, "LSQR residual history")
+    assert_close(host(beta), rbeta, 1e-6, "beta")
 
 
 def test_fit_background_with_no_iterations_and_kappa_lsqr_state_check():
@@ -211,3 +215,25 @@ def test_fit_background_with_no_iterations_and_kappa_lsqr_state_check():
     with pytest.raises(qpat.QpatError) as e:
         G.ctx.lsqr_init_kappa(dev(chi), dev(W), None, out)
     assert "ERR_STATE" in str(e.value)
+
+
+def test_discrepancy_principle_matches_oracle():
+    """Morozov's discrepancy principle (the remark after Algorithm 1) on the 16^3
+    workload: both drivers stop PLSQR at the same first step whose linearised
+    residual is below sqrt(K N); with data simulated on the reconstruction mesh it
+    fires in the third outer step."""
+    from paper_1512_02796_amd import qpat
+    from paper_1512_02796_amd.driver import reconstruct
+    G = GpuProblem("C1", qpat.default_opts(pcg_rtol=1e-12, prior_rtol=1e-12))
+    P = G.P
+    g, lin = oracle_of(P)
+    chi, W = data_of(P, lin)
+    kw = dict(outer=3, inner=30, discrepancy=1.0)
+    beta, log = reconstruct(G.ctx, dev(chi), dev(W), P.kappa0, P.mu0, **kw)
+    rbeta, rlog = oracle_reconstruct(g, P.phi_src, chi, W, P.kappa0, P.mu0, **kw, **DEFL)
+    assert log["discrepancy_fired"] == rlog["discrepancy_fired"] == [False, False, True]
+    level = np.sqrt(chi.size)
+    for a, b in zip(log["lsqr"], rlog["lsqr"]):
+        assert len(a) == len(b)
+        assert_close(a, b, 1e-6, "LSQR residual history")
+    assert log["lsqr"][-1][-1] < level <= log["lsqr"][-1][-2]

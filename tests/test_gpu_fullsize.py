@@ -1,6 +1,6 @@
 """Full-size checks at the benchmarked configuration: 128^3 Kuhn voxels
-(N = 2,146,689), 16 Gaussian illuminations, 16-RHS block PCG in mixed
-precision (FP32 apply, FP64 reliable updates), rtol 1e-10.
+(N = 2,146,689), 16 Gaussian illuminations, 16-RHS block PCG with the
+multigrid preconditioner in FP64 (the default path), rtol 1e-10.
 
 The oracle cannot solve this size in test time, so it computes sampled rows
 exactly (rows of K, f and M_delta from the elements around sampled nodes) and
@@ -27,7 +27,7 @@ def big():
     P = make_problem("C3", n=GRID, n_ill=N_ILL)
     m = P.mesh
     ctx = qpat.Context(dev(m.coords), dev(m.tets, torch.int32), dev(m.bfaces, torch.int32),
-                       opts=qpat.default_opts(precision=1, max_rhs_block=16))
+                       opts=qpat.default_opts(max_rhs_block=16))
     ctx.set_sources(dev(P.phi_src))
     phi = torch.empty(N_ILL * m.N, dtype=torch.float64, device="cuda")
     info = ctx.forward(dev(P.kappa), dev(P.mu), phi)
@@ -83,15 +83,14 @@ def test_prior_apply_on_sampled_rows(big):
     for part in (rows, N + rows):
         err = np.abs(yy[part] - ref[part]).max() / np.abs(ref[part]).max()
         assert err <= 1e-13
-    # M_delta^{-1} at the default prior_rtol (1e-8: with delta = 1e-6 and
-    # Perona-Malik diffusivities ~1e-5 across the phantom's edges FP64 PCG
-    # attains ~4e-9 at this size)
+    # M_delta^{-1} at the default prior_rtol 1e-10 (deflated multigrid PCG; the
+    # phantom's diffusivities drop to ~1e-5 across its edges)
     r = torch.empty_like(y)
     pinfo = ctx.prior_solve(dev(x), r)
-    assert pinfo["relres_max"] <= 1e-8
+    assert pinfo["relres_max"] <= 1e-10
     # sampled residual of the solve
     res = (x - Md @ host(r))[np.concatenate([rows, N + rows])]
-    assert np.abs(res).max() <= 1e-8 * np.linalg.norm(x)
+    assert np.abs(res).max() <= 1e-10 * np.linalg.norm(x)
 
 
 def test_adjoint_identity_and_central_differences(big):
@@ -112,12 +111,12 @@ def test_adjoint_identity_and_central_differences(big):
     eps = 1e-3
     hp = torch.empty(N_ILL * N, dtype=torch.float64, device="cuda")
     hm = torch.empty_like(hp)
-    ctx.set_opts(pcg_rtol=1e-12, precision=0)
+    ctx.set_opts(pcg_rtol=1e-12)
     ctx.forward_log(P.kappa0, P.mu0, dev(beta + eps * s), None, hp)
     ctx.forward_log(P.kappa0, P.mu0, dev(beta - eps * s), None, hm)
     fd = (hp - hm) / (2 * eps)
     ctx.forward_log(P.kappa0, P.mu0, dev(beta), None, None)
     ctx.jvp(dev(s), Js)
-    ctx.set_opts(pcg_rtol=1e-10, precision=1)
+    ctx.set_opts(pcg_rtol=1e-10)
     err = float(torch.linalg.norm(Js - fd) / torch.linalg.norm(Js))
     assert err <= 1e-5, err

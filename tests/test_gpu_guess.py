@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import GpuProblem, dev, host, rel, need_gpu
+from gpu_util import GpuProblem, dev, host, rel, need_gpu, assert_close
 from oracle import convnet
 
 pytestmark = pytest.mark.gpu
@@ -65,7 +65,7 @@ def test_net_forward_matches_oracle(n):
     out = torch.empty(m.N, dtype=torch.float32, device="cuda")
     ctx.guess_eval(dev(x.reshape(3, -1), torch.float32), out)
     ref, _ = convnet.forward(params, x)
-    assert rel(host(out).astype(np.float64), ref.ravel()) <= 3e-2
+    assert_close(host(out).astype(np.float64), ref.ravel(), 3e-2, f"net output n={n}")
     # the parameters come back unchanged
     p = torch.empty(15601, dtype=torch.float32, device="cuda")
     ctx.guess_get_params(p)
@@ -90,8 +90,8 @@ def test_net_gradients_match_oracle():
         off += w.size
         gb = gg[off:off + b.size]
         off += b.size
-        assert rel(gw, w.ravel()) <= 3e-2
-        assert rel(gb, b) <= 3e-2
+        assert_close(gw, w.ravel(), 3e-2, "weight gradient")
+        assert_close(gb, b, 3e-2, "bias gradient")
 
 
 def test_training_reduces_the_loss():
@@ -117,13 +117,13 @@ def test_forward_from_initial_guess():
     out = torch.empty_like(phi0)
     info = G.ctx.forward_x0(G.kappa, G.mu, phi0, out)
     assert info["iters_max"] <= 1
-    assert rel(host(out), host(phi0)) <= 1e-9
+    assert_close(host(out), host(phi0), 1e-9, "start at the solution")
     # a perturbed start converges to the same tolerance with fewer iterations
     pert = phi0 * (1.0 + 0.01 * torch.sin(torch.arange(phi0.numel(), device="cuda", dtype=torch.float64)))
     info2 = G.ctx.forward_x0(G.kappa, G.mu, pert, out)
     assert info2["relres_max"] <= 1e-10
     assert info2["iters_max"] < info0["iters_max"]
-    assert rel(host(out), host(phi0)) <= 1e-8
+    assert_close(host(out), host(phi0), 1e-8, "start near the solution")
     # a zero start is the plain solve
     info3 = G.ctx.forward_x0(G.kappa, G.mu, torch.zeros_like(phi0), out)
     assert info3["iters_max"] == info0["iters_max"]
