@@ -199,6 +199,20 @@ qpat_status qpat_prior_solve(qpat_ctx* ctx, const double* p, double* r, qpat_inf
  * diagonal. The result is written to *out (host). */
 qpat_status qpat_misfit(qpat_ctx* ctx, const double* chi, const double* w, double* out);
 
+/* qpat_misfit for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sum, but it calls no allocating routine and does not synchronise. The
+ * partial sums go to a file-scope device array of 1024 doubles, one copy per
+ * GPU, whose address qpat_setup_mesh looks up once per device; every size of
+ * problem fits it (the reduction's grid is capped at 1024 blocks), so no size
+ * is rejected. The result ||W (chi - h)||_2 is written to out_dev[0] (device,
+ * 1 double) in stream order on the context's stream.
+ * Every call on one GPU shares that array: calls that overlap on one GPU (two
+ * contexts on different streams) race and may return wrong sums; serialise
+ * them. Errors as qpat_misfit (QPAT_ERR_ARG null pointer, QPAT_ERR_STATE
+ * before qpat_forward). */
+qpat_status qpat_misfit_noalloc(qpat_ctx* ctx, const double* chi, const double* w, double* out_dev);
+
 /* Initial guess of Algorithm 1 (preamble; several illuminations: Sec. 4 and
  * Sec. 5): call after qpat_forward at the homogeneous (kappa0, mu0).
  * beta_out[0:N] = 0, beta_out[N:2N] = log(mean_k(chi_k / phi_k) / mu0), the

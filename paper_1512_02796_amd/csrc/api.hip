@@ -216,6 +216,7 @@ qpat_status qpat_setup_mesh(qpat_ctx** out, int64_t N, const double* coords, int
     c->N = N;
     c->E = E;
     c->Fb = F_b;
+    QPAT_TRY(scratch_setup(c));
     QPAT_TRY(mesh_build(c, coords, tets, bfaces));
     QPAT_TRY(alloc_core(c));
     QPAT_TRY(lattice_setup(c, coords));
@@ -493,6 +494,14 @@ qpat_status qpat_misfit(qpat_ctx* c, const double* chi, const double* w, double*
     if (!chi || !w || !out) return fail(c, QPAT_ERR_ARG, "misfit: null pointer");
     if (!c->have_forward) return fail(c, QPAT_ERR_STATE, "misfit: call qpat_forward first");
     return misfit_core(c, chi, w, out);
+}
+
+qpat_status qpat_misfit_noalloc(qpat_ctx* c, const double* chi, const double* w, double* out_dev) {
+    if (!c) return QPAT_ERR_ARG;
+    DeviceGuard g(c->device);
+    if (!chi || !w || !out_dev) return fail(c, QPAT_ERR_ARG, "misfit_noalloc: null pointer");
+    if (!c->have_forward) return fail(c, QPAT_ERR_STATE, "misfit_noalloc: call qpat_forward first");
+    return misfit_noalloc_core(c, chi, w, out_dev);
 }
 
 qpat_status qpat_init_guess(qpat_ctx* c, const double* chi, double mu0, double* beta_out) {

@@ -18,6 +18,7 @@
 // Dot products are two kernels: per-block partial sums, then one block adds
 // them in a fixed order.
 #include <cmath>
+#include <mutex>
 
 #include "qpat_internal.h"
 
@@ -326,6 +327,62 @@ qpat_status dot(qpat_ctx* c, const double* a, const double* b, int64_t n, double
     const int nb = grid_for(n, kThreads * 8, kRedBlocks);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kThreads), 0, c->stream, a, b, n, c->red_partials);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, c->stream, c->red_partials, nb, dev_out);
+    QPAT_HIP(c, hipGetLastError());
+    return QPAT_OK;
+}
+
+// ---- allocation-free misfit
+// The partial sums of qpat_misfit_noalloc live in a file-scope device array
+// (one copy per GPU, held until the process ends) instead of the context's
+// workspace. The grid of k_misfit is capped at kRedBlocks blocks (each sums a
+// contiguous chunk), so kRedBlocks partials cover every problem size. In host
+// code `scratch` is only a stand-in for the symbol: its device address comes
+// from hipGetSymbolAddress, looked up once per device.
+static __device__ __align__(256) double scratch[kRedBlocks];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+__global__ __launch_bounds__(kThreads) void k_sum_sqrt(const double* __restrict__ partials, int nb,
+                                                       double* __restrict__ out) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) s += partials[b];
+    s = block_total(s);
+    if (threadIdx.x == 0) *out = sqrt(s);
+}
+
+}  // namespace
+
+// Device address of this GPU's scratch array; the context's device must be current.
+qpat_status scratch_setup(qpat_ctx* c) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (c->device < 0 || c->device >= kMaxDevices)
+        return fail(c, QPAT_ERR_DEVICE, "scratch: device %d beyond the %d supported", c->device, kMaxDevices);
+    if (g_scratch_ptr[c->device]) return QPAT_OK;
+    void* p = nullptr;
+    QPAT_HIP(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[c->device] = static_cast<double*>(p);
+    return QPAT_OK;
+}
+
+qpat_status misfit_noalloc_core(qpat_ctx* c, const double* chi, const double* w, double* out_dev) {
+    double* part = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (c->device >= 0 && c->device < kMaxDevices) part = g_scratch_ptr[c->device];
+    }
+    if (!part) return fail(c, QPAT_ERR_STATE, "misfit_noalloc: no scratch address for device %d", c->device);
+    const int64_t n = c->N * c->n_ill;
+    const int nb = grid_for(n, kThreads * 8, kRedBlocks);
+    if (nb > kRedBlocks)
+        return fail(c, QPAT_ERR_ARG, "misfit_noalloc: %d partial sums exceed the scratch of %d", nb, kRedBlocks);
+    // every partial the sum reads is written by k_misfit first: nothing to clear
+    hipLaunchKernelGGL(k_misfit, dim3(nb), dim3(kThreads), 0, c->stream, c->N, c->n_ill, c->n_pad, chi, w, c->mu,
+                       c->phi, part);
+    hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(kThreads), 0, c->stream, part, nb, out_dev);
     QPAT_HIP(c, hipGetLastError());
     return QPAT_OK;
 }

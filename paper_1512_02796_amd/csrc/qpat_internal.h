@@ -402,6 +402,11 @@ qpat_status dot(qpat_ctx* c, const double* a, const double* b, int64_t n, double
 qpat_status lsqr_init_core(qpat_ctx* c, const double* chi, const double* w, const double* beta_lin);
 qpat_status lsqr_step_core(qpat_ctx* c, SolveStats* st);
 qpat_status misfit_core(qpat_ctx* c, const double* chi, const double* w, double* out);
+// the file-scope scratch of the allocation-free misfit: its device address for
+// c->device (looked up once per device; the device must be current)
+qpat_status scratch_setup(qpat_ctx* c);
+// ||W (chi - h)|| into out_dev[0] (device) with the partial sums in that scratch
+qpat_status misfit_noalloc_core(qpat_ctx* c, const double* chi, const double* w, double* out_dev);
 qpat_status init_guess_core(qpat_ctx* c, const double* chi, double mu0, double* beta_out);
 // Gauss-Newton sums of the background fit: with r = W (chi - h) and the
 // whitened columns W j1, W j2 ([n_ill][N], scaled in place), out[0..5] =

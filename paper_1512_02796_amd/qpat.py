@@ -99,6 +99,7 @@ SIGNATURES = {
     "qpat_prior_apply": (_S, [_P, _P, _P]),
     "qpat_prior_solve": (_S, [_P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_misfit": (_S, [_P, _P, _P, ctypes.POINTER(_D)]),
+    "qpat_misfit_noalloc": (_S, [_P, _P, _P, _P]),
     "qpat_init_guess": (_S, [_P, _P, _D, _P]),
     "qpat_lsqr_init": (_S, [_P, _P, _P, _P, _P, ctypes.POINTER(Info)]),
     "qpat_lsqr_step": (_S, [_P, ctypes.POINTER(_D), ctypes.POINTER(Info)]),
@@ -344,6 +345,13 @@ class Context:
         self._check(_lib.qpat_misfit(self._h, _ptr(chi, torch.float64, nd, "chi"), _ptr(w, torch.float64, nd, "w"),
                                      ctypes.byref(out)))
         return out.value
+
+    def misfit_noalloc(self, chi, w, out):
+        """||W (chi - h)|| into out[0] (a device FP64 tensor), stream-ordered, no
+        allocation and no synchronisation (qpat_misfit_noalloc)."""
+        nd = self.n_ill * self.N
+        self._check(_lib.qpat_misfit_noalloc(self._h, _ptr(chi, torch.float64, nd, "chi"),
+                                             _ptr(w, torch.float64, nd, "w"), _ptr(out, torch.float64, 1, "out")))
 
     def init_guess(self, chi, mu0, beta_out):
         self._check(_lib.qpat_init_guess(self._h, _ptr(chi, torch.float64, self.n_ill * self.N, "chi"),
