@@ -93,6 +93,76 @@ def mg_algorithmic_bytes(key, N, layout, stat, kst):
     return stat["lanes"] * vecs * N * 8 + stat["launches"] * per_launch
 
 
+def mg_levels(nx, ny, nz, dense_max=1000, coarse_axis=5):
+    """Node lattices of the K hierarchy: n -> n/2 + 1 per axis until the first
+    coarse level of at most dense_max nodes (solved by its explicit inverse)."""
+    lv = [(nx, ny, nz)]
+    while max(lv[-1]) > coarse_axis and not (len(lv) >= 2 and np.prod(lv[-1]) <= dense_max):
+        c = tuple(a // 2 + 1 if a > 2 else a for a in lv[-1])
+        if c == lv[-1]:
+            break
+        lv.append(c)
+    return [int(np.prod(v)) for v in lv]
+
+
+def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled27_min=16384):
+    """Algorithmic HBM bytes of one J s + J^T t pair on the multigrid path: every
+    kernel's reads and writes counted once (FP64 vectors of N B values, the
+    finest level's residual for the restriction in FP32), with the measured
+    PCG iteration counts. Per multigrid-PCG iteration (levels N_0 > N_1 > ...):
+      finest level: direction + product 4 V_0 + rows, update + first residual
+        6.5 V_0 + rows + 1/a_ii, restriction 0.5 V_0 + 2 V_1, prolongation +
+        last sweep 2 V_0 + V_1 + whole rows (16 a node) + 1/a_ii;
+      coarse level l: residual 3 V_l + rows, restriction V_l + 2 V_l+1,
+        prolongation 2 V_l + V_l+1, sweep 3 V_l + rows (27-point rows: 32
+        doubles a node on tiled levels, 27 elsewhere); coarsest: its dense
+        inverse (N_c^2 doubles) and 2 V_c.
+    Per solve: start 3 V_0, the first V-cycle's finest residual 1.5 V_0 + rows,
+    one V-cycle more than iterations, the final true residual 3 V_0 + rows.
+    Jacobian kernels per block: J s -- dK(s) rows from the elements (tets 16 B,
+    class 1 B per element; 80 B a node), the stencil product 2 V_0 + rows, the
+    output 3 V_0; J^T t -- right-hand side 2 V_0, element sums 2 V_0 + 57 B a
+    tetrahedron, gather 2 V_0 + 56 B a tetrahedron, output 48 B a node.
+    Returns (total bytes, dict of the parts)."""
+    vb = 8 * B
+    V = [n * vb for n in levels]
+    rows0, whole0, d0 = 64 * N, 128 * N, 8 * N
+    L = len(levels)
+
+    def coarse_rows(l):
+        return (256 if levels[l] >= tiled27_min else 216) * levels[l]
+
+    vc = 0.5 * V[0] + 2 * V[1] + 8 * levels[1]
+    for l in range(1, L - 1):
+        vc += 3 * V[l] + coarse_rows(l) + V[l] + 2 * V[l + 1] + 8 * levels[l + 1]      # down
+        vc += 2 * V[l] + V[l + 1] + 3 * V[l] + coarse_rows(l) + 8 * levels[l]         # up
+    vc += 8 * levels[-1] ** 2 + 2 * V[-1]
+    vc += 2 * V[0] + V[1] + whole0 + d0                                               # prolongation + last sweep
+    pcg_it = 4 * V[0] + rows0 + 6.5 * V[0] + rows0 + d0
+
+    def solve(it):
+        return 3 * V[0] + 1.5 * V[0] + rows0 + d0 + (it + 1) * vc + it * pcg_it + 3 * V[0] + rows0
+
+    jv = blocks * (80 * N + 17 * E + 2 * V[0] + rows0 + 3 * V[0])
+    jt = blocks * (2 * V[0] + 2 * V[0] + 57 * E + 2 * V[0] + 56 * E) + 48 * N
+    parts = {"vcycle_per_iter": vc, "pcg_per_iter": pcg_it, "tangent_solves": blocks * solve(iters_tan),
+             "adjoint_solves": blocks * solve(iters_adj), "jacobian_kernels": jv + jt}
+    return parts["tangent_solves"] + parts["adjoint_solves"] + parts["jacobian_kernels"], parts
+
+
+# M_delta's multigrid kernels (one right-hand side per system, two systems; profile
+# counters 8-11) and their algorithmic bytes per node: vectors of 2 N doubles
+# (16 B a node), Kuhn rows stored whole and entry-major (16 entries: FP64 for the
+# PCG product, FP32 for the V-cycle's finest sweeps), 1/a_ii (FP64) and the
+# region map (int32) of the coarse space
+PRIOR_MG_BYTES_PER_NODE = {
+    "prior_mg_dir_spmv": ("k_mgp_dir + k_mgp_spmv<3,1>", 5 * 16 + 2 * 16 * 8 + 2 * 4),
+    "prior_mg_update": ("k_mgp_update<1>", 6 * 16),
+    "prior_mg_resid0": ("k_mg_resid<5,1>", 3 * 16 + 2 * 16 * 4),
+    "prior_mg_smooth0": ("k_mg_smooth<5,1,true>", 3 * 16 + 2 * 16 * 4 + 2 * 8),
+}
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE runs (profiles/hbm_traffic.json, copy-calibrated), or None when
@@ -132,6 +202,10 @@ def main():
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--rhs-block", type=int, default=16,
                     help="recon workload: right-hand sides per block solve (1 = plain, one at a time)")
+    ap.add_argument("--config", choices=("C1", "C2", "C3"), default="C3",
+                    help="recon workload: the 16^3 face-source (C1), 64^3 (C2) or 128^3 (C3) configuration")
+    ap.add_argument("--oracle-recon", action="store_true",
+                    help="recon workload: also time the FP64 oracle's Algorithm 1 on the same data (C1 size)")
     ap.add_argument("--no-init", action="store_true",
                     help="skip the background fit, step 0 and TV-prior measurements")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -249,6 +323,34 @@ def main():
         ctx.set_opts(max_rhs_block=16, pcg_precond=1, precision=0)
         plain = out
 
+    # ---- mixed precision (FP32 operator and vectors in Jacobi-PCG K solves, FP64
+    # dots, reliable updates and LSQR) against the FP64 multigrid path: seconds per
+    # PLSQR iteration from the same start, and the final LSQR residuals
+    precision_cmp = None
+    if args.lsqr_steps > 0 and not args.no_plain:
+        precision_cmp = {}
+        beta_lin = d(np.concatenate([kt, mt]))
+        for label, o in (("fp64_multigrid", dict(pcg_precond=1, precision=0)),
+                         ("mixed_jacobi", dict(pcg_precond=0, precision=1))):
+            ctx.set_opts(max_rhs_block=16, **o)
+            ctx.forward(d(P.kappa), d(P.mu), None, None)
+            ctx.prior_setup(d(kt), d(mt))
+            x = torch.zeros(2 * N, dtype=torch.float64, device=dev)
+            ctx.lsqr_init(d(chi), d(W), beta_lin, x)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(args.lsqr_steps):
+                r, _ = ctx.lsqr_step()
+            torch.cuda.synchronize()
+            precision_cmp[label] = {"s_per_lsqr_iter": round((time.perf_counter() - a) / args.lsqr_steps, 4),
+                                    "final_lsqr_residual": r, "steps": args.lsqr_steps}
+        ctx.set_opts(max_rhs_block=16, pcg_precond=1, precision=0)
+        ctx.forward(d(P.kappa), d(P.mu), None, None)
+        r64 = precision_cmp["fp64_multigrid"]["final_lsqr_residual"]
+        r32 = precision_cmp["mixed_jacobi"]["final_lsqr_residual"]
+        precision_cmp["final_residual_rel_diff"] = abs(r32 - r64) / r64
+        log("precision", precision_cmp)
+
     # ---- calibration copy for HBM counters (profiling runs only)
     if args.copy_calib_mib:
         a = torch.empty(args.copy_calib_mib * (1 << 20) // 8, dtype=torch.float64, device=dev).fill_(1.0)
@@ -329,10 +431,46 @@ def main():
     roofline["frac_of_triad"] = round(achieved / triad_gbs, 4)
     log("roofline", roofline)
 
-    # ---- CPU oracle on a bounded sample of the same system
+    # ---- the whole pair against the HBM roofline: algorithmic bytes of every kernel
+    n1 = args.grid + 1
+    levels = mg_levels(n1, n1, n1)
+    it_t, it_a = infos[-1][0]["iters_max"], infos[-1][1]["iters_max"]
+    blocks = (K + 15) // 16
+    pb, parts = pair_algorithmic_bytes(N, m.E, levels, 16, blocks, it_t, it_a)
+    roofline["pair"] = {"bytes": round(pb), "GB_per_s": round(pb / pair_s / 1e9, 1),
+                        "frac": round(pb / pair_s / 1e9 / HBM_PEAK_GBS, 4),
+                        "frac_of_triad": round(pb / pair_s / 1e9 / triad_gbs, 4),
+                        "levels": levels, "pcg_iters": [it_t, it_a],
+                        "bytes_per_iteration": round(parts["vcycle_per_iter"] + parts["pcg_per_iter"]),
+                        "jacobian_kernels_bytes": round(parts["jacobian_kernels"])}
+    log("pair roofline", roofline["pair"])
+
+    # ---- M_delta^{-1}'s multigrid kernels (one right-hand side per system)
+    if args.lsqr_steps > 0:
+        ctx.profile(True)
+        ctx.prior_solve(d(s_np), torch.empty(2 * N, dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+        ctx.profile(False)
+        pst = ctx.profile_read()
+        pk = {}
+        for key, (kname, bpn) in PRIOR_MG_BYTES_PER_NODE.items():
+            v = pst[key]
+            if v["launches"]:
+                avg = v["total_ms"] / v["launches"]
+                gbs = bpn * N / (avg * 1e-3) / 1e9
+                pk[kname] = {"avg_ms": round(avg, 4), "launches": v["launches"], "bytes_per_launch": bpn * N,
+                             "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        roofline["prior_kernels"] = pk
+        log("M_delta kernels", pk)
+
+    # ---- CPU oracle on a bounded sample of the same system, and a whole oracle
+    # pair at the 16^3 workload beside the GPU's
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(P, args.cpu_iters, plain)
+        cpu["measured_pair_16cube"] = small_pair_both_sides(ctx_factory=lambda Q: qpat.Context(
+            d(Q.mesh.coords), d(Q.mesh.tets, torch.int32), d(Q.mesh.bfaces, torch.int32),
+            opts=qpat.default_opts(max_rhs_block=16)), d=d)
         log("cpu_baseline", cpu)
 
     ctx.close()
@@ -361,6 +499,7 @@ def main():
                       "tangent_max": infos[-1][0]["iters_max"], "adjoint_max": infos[-1][1]["iters_max"],
                       "prior": pinfo["iters_max"]},
         "plain": plain,
+        "precision": precision_cmp,
         "init": init,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -383,7 +522,7 @@ def bench_learned(args):
     N, K = m.N, P.n_ill
     ctx = qpat.Context(torch.as_tensor(m.coords, device=dev), torch.as_tensor(m.tets, device=dev),
                        torch.as_tensor(m.bfaces, device=dev),
-                       opts=qpat.default_opts(precision=1, max_rhs_block=8))
+                       opts=qpat.default_opts(max_rhs_block=8))
     ctx.set_sources(torch.as_tensor(P.phi_src, device=dev))
     n1 = m.n + 1
     ctx.guess_setup(n1, n1, n1)
@@ -444,7 +583,7 @@ def bench_recon(args):
     def d(a, dt=torch.float64):
         return torch.as_tensor(np.ascontiguousarray(a)).to(device=dev, dtype=dt)
 
-    P = make_problem("C3", n=args.grid, n_ill=args.n_ill)
+    P = make_problem("C3", n=args.grid, n_ill=args.n_ill) if args.config == "C3" else make_problem(args.config)
     m = P.mesh
     N, K = m.N, P.n_ill
     ctx = qpat.Context(d(m.coords), d(m.tets, torch.int32), d(m.bfaces, torch.int32),
@@ -452,6 +591,7 @@ def bench_recon(args):
     ctx.set_sources(d(P.phi_src))
     h = torch.empty(K * N, dtype=torch.float64, device=dev)
     ctx.forward(d(P.kappa), d(P.mu), None, h)
+    src = "face" if P.cfg["source"] == "face" else "Gaussian"
     hh = h.cpu().numpy().reshape(K, N)
     sig = P.cfg["noise"]
     chi = hh + sig * np.abs(hh) * noise_draws(P.cfg["id"], K, N)
@@ -475,14 +615,29 @@ def bench_recon(args):
            "rel_err_mu": round(float(np.linalg.norm(mu - P.mu) / np.linalg.norm(P.mu)), 4)}
     log("reconstruction", out)
     ctx.close()
-    res = {"metric": "seconds per PLSQR iteration over the whole Algorithm 1 reconstruction at 128^3",
+    if args.oracle_recon:
+        # the FP64 oracle's Algorithm 1 on the same data (sparse LU for K and M_delta)
+        from oracle import fem
+        from oracle.driver import reconstruct as oracle_reconstruct
+        g = fem.geometry(m.coords, m.tets, m.bfaces)
+        a = time.perf_counter()
+        ob, olg = oracle_reconstruct(g, P.phi_src, chi, W, P.kappa0, P.mu0, outer, inner)
+        osec = time.perf_counter() - a
+        osteps = sum(len(hst) - 1 for hst in olg["lsqr"])
+        out["oracle"] = {"seconds": round(osec, 3), "s_per_lsqr_iter": round(osec / osteps, 4), "cores": 1,
+                         "final_lsqr_residuals": [round(hst[-1], 2) for hst in olg["lsqr"]],
+                         "res_nl": [round(r, 1) for r in olg["res_nl"]],
+                         "gpu_speedup": round(osec / total, 1)}
+        log("oracle reconstruction", out["oracle"])
+    n_vox = m.n
+    res = {"metric": f"seconds per PLSQR iteration over the whole Algorithm 1 reconstruction at {n_vox}^3",
            "value": out["s_per_lsqr_iter"], "unit": "s", "n_gpus": 1, "steps": steps, "warmup": 0,
            "ms_per_step": round(total / steps * 1e3, 2), "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"Algorithm 1, {args.grid}^3 Kuhn voxels (N={N}), {K} Gaussian illuminations, "
-                                  f"seeded ellipsoid phantom, 2% noise, {outer} x {inner} PLSQR steps, FP64 "
+           "config": {"workload": f"Algorithm 1, {n_vox}^3 Kuhn voxels (N={N}), {K} {src} illuminations, "
+                                  f"seeded phantom, {round(100 * sig)}% noise, {outer} x {inner} PLSQR steps, FP64 "
                                   f"multigrid PCG, {args.rhs_block} right-hand side(s) per block solve",
-                      "rhs_block": args.rhs_block},
+                      "rhs_block": args.rhs_block, "config": args.config},
            "reconstruction": out}
     print(json.dumps(res), flush=True)
 
@@ -646,6 +801,47 @@ def bench_batch(args):
         "pcg_iters_sum": int(sum(i["iters_sum"] for i in infos)),
     }
     print(json.dumps(res), flush=True)
+
+
+def small_pair_both_sides(ctx_factory, d, reps=20):
+    """One J s + J^T t pair at the 16^3 face-source workload (N = 4913, 4
+    illuminations), timed whole on the FP64 oracle (sparse LU factorisation of
+    K untimed, as the GPU's forward solve is; the first products form the
+    Appendix's G(1), G(2) matrices, which is how the oracle applies J) and on
+    the GPU (median of `reps` pairs after a warm-up)."""
+    import torch
+    from qpat_inputs import make_problem, probe_vectors
+    from oracle import fem
+    from oracle.jacobian import Linearisation
+    Q = make_problem("C1")
+    g = fem.geometry(Q.mesh.coords, Q.mesh.tets, Q.mesh.bfaces)
+    lin = Linearisation(g, Q.kappa, Q.mu, Q.phi_src)
+    s, t = probe_vectors(Q.cfg["id"], Q.n_ill, g.N)
+    a = time.perf_counter()
+    lin.jvp(s)
+    lin.vjp(t)
+    oracle_s = time.perf_counter() - a
+    ctx = ctx_factory(Q)
+    ctx.set_sources(d(Q.phi_src))
+    ctx.forward(d(Q.kappa), d(Q.mu))
+    Js = torch.empty(Q.n_ill * g.N, dtype=torch.float64, device="cuda")
+    Jt = torch.empty(2 * g.N, dtype=torch.float64, device="cuda")
+    sd, td = d(s), d(t)
+    ctx.jvp(sd, Js)
+    ctx.vjp(td, Jt)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        ctx.jvp(sd, Js)
+        ctx.vjp(td, Jt)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - a)
+    ctx.close()
+    gpu_s = float(np.median(ts))
+    return {"workload": "16^3 Kuhn voxels (N=4913), 4 face illuminations, J s + J^T t, FP64",
+            "oracle_s": round(oracle_s, 4), "oracle_cores": 1, "gpu_s": round(gpu_s, 5),
+            "gpu_over_oracle": round(oracle_s / gpu_s, 1)}
 
 
 def cpu_baseline(P, iters, plain):
