@@ -62,7 +62,7 @@ def algorithmic_bytes(kind, N, layout, V, stat):
 # N B doubles per active right-hand side and the stencil rows (m + 1 doubles
 # per node) and 1/a_ii once per launch
 MG_KERNELS = {
-    "K_mg_dir_spmv": ("k_mg_tile<0,16>", 4, True, False),    # read z, p_old; write p, q
+    "K_mg_dir_spmv": ("k_mg_tile<0,16>", 3.5, True, False),  # read z (FP32), p_old; write p, q
     "K_mg_update": ("k_mgp_update<16>", 6, False, False),    # read x, p, r, q; write x, r
     "K_mg_resid0": ("k_mg_tile<1,16>", 2, True, True),       # read r; write r - A (w D^-1 r)
     "K_mg_smooth0": ("k_mg_tile<2,16>", 3, True, True),      # read x, r; write z
@@ -71,24 +71,32 @@ MG_KERNELS = {
 # residual (counter 6 then stays empty): read r, q, x, p; write r', x, and
 # r' - A (w D^-1 r') in FP32 (half a vector),
 # and counter 7 the prolongation fused with the last sweep: read r, level 1's x
-# (1/8 vector), the whole stencil rows (16 doubles a node: 2x the stored form); write z
+# (1/8 vector), the whole stencil rows (16 FP32 values a node: the bytes of the
+# stored form); write z in FP32 (half a vector)
 MG_FUSED_UPDATE = ("k_mg_tile<6,16>", 6.5, 1, True)
-MG_FUSED_SMOOTH = ("k_mg_prolong_smooth", 2.125, 2, True)
+MG_FUSED_SMOOTH = ("k_mg_prolong_smooth", 1.625, 1, True)
 
 
-def mg_kernel(key, kst):
-    """(rocprofv3 name, vectors, stencil, 1/a_ii) of profile counter `key`."""
+def mg_kernel(key, kst, p32=False):
+    """(rocprofv3 name, vectors, stencil, 1/a_ii) of profile counter `key`; with
+    p32 (mixed precision) the direction p is read and written in FP32: half a
+    vector less in the direction kernel's read of the old p and its write of
+    p, and in the update's read of p."""
     fused = kst["K_mg_resid0"]["launches"] == 0
     if key == "K_mg_update" and fused:
-        return MG_FUSED_UPDATE
+        n, v, o, d = MG_FUSED_UPDATE
+        return ("k_mg_tile<6,16,false,true>", v - 0.5, o, d) if p32 else (n, v, o, d)
     if key == "K_mg_smooth0" and fused:
         return MG_FUSED_SMOOTH
-    return MG_KERNELS[key]
+    n, v, o, d = MG_KERNELS[key]
+    if p32 and key == "K_mg_dir_spmv":
+        return ("k_mg_tile<0,16,true,true>", v - 1.0, o, d)
+    return (n, v, o, d)
 
 
-def mg_algorithmic_bytes(key, N, layout, stat, kst):
+def mg_algorithmic_bytes(key, N, layout, stat, kst, p32=False):
     """Bytes one launch must move, summed over the measured launches."""
-    _, vecs, op, diag = mg_kernel(key, kst)
+    _, vecs, op, diag = mg_kernel(key, kst, p32)
     per_launch = N * layout["stencil_arrays"] * 8 * int(op) + (N * 8 if diag else 0)
     return stat["lanes"] * vecs * N * 8 + stat["launches"] * per_launch
 
@@ -105,18 +113,21 @@ def mg_levels(nx, ny, nz, dense_max=1000, coarse_axis=5):
     return [int(np.prod(v)) for v in lv]
 
 
-def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled27_min=16384):
+def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled27_min=16384, p32=False):
     """Algorithmic HBM bytes of one J s + J^T t pair on the multigrid path: every
-    kernel's reads and writes counted once (FP64 vectors of N B values, the
-    finest level's residual for the restriction in FP32), with the measured
-    PCG iteration counts. Per multigrid-PCG iteration (levels N_0 > N_1 > ...):
-      finest level: direction + product 4 V_0 + rows, update + first residual
+    kernel's reads and writes counted once (FP64 vectors of N B values; in
+    FP32 the finest level's residual for the restriction, the V-cycle's output
+    z and the last sweep's whole rows), with the measured PCG iteration counts.
+    Per multigrid-PCG iteration (levels N_0 > N_1 > ...):
+      finest level: direction + product 3.5 V_0 + rows, update + first residual
         6.5 V_0 + rows + 1/a_ii, restriction 0.5 V_0 + 2 V_1, prolongation +
-        last sweep 2 V_0 + V_1 + whole rows (16 a node) + 1/a_ii;
+        last sweep 1.5 V_0 + V_1 + whole FP32 rows (16 a node) + 1/a_ii;
       coarse level l: residual 3 V_l + rows, restriction V_l + 2 V_l+1,
         prolongation 2 V_l + V_l+1, sweep 3 V_l + rows (27-point rows: 32
         doubles a node on tiled levels, 27 elsewhere); coarsest: its dense
         inverse (N_c^2 doubles) and 2 V_c.
+    Mixed precision (p32): the direction in FP32 takes 1.5 V_0 off each iteration
+    (the old p and the new p in the direction kernel, p in the update).
     Per solve: start 3 V_0, the first V-cycle's finest residual 1.5 V_0 + rows,
     one V-cycle more than iterations, the final true residual 3 V_0 + rows.
     Jacobian kernels per block: J s -- dK(s) rows from the elements (tets 16 B,
@@ -126,7 +137,7 @@ def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled2
     Returns (total bytes, dict of the parts)."""
     vb = 8 * B
     V = [n * vb for n in levels]
-    rows0, whole0, d0 = 64 * N, 128 * N, 8 * N
+    rows0, whole0, d0 = 64 * N, 64 * N, 8 * N
     L = len(levels)
 
     def coarse_rows(l):
@@ -137,8 +148,8 @@ def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled2
         vc += 3 * V[l] + coarse_rows(l) + V[l] + 2 * V[l + 1] + 8 * levels[l + 1]      # down
         vc += 2 * V[l] + V[l + 1] + 3 * V[l] + coarse_rows(l) + 8 * levels[l]         # up
     vc += 8 * levels[-1] ** 2 + 2 * V[-1]
-    vc += 2 * V[0] + V[1] + whole0 + d0                                               # prolongation + last sweep
-    pcg_it = 4 * V[0] + rows0 + 6.5 * V[0] + rows0 + d0
+    vc += 1.5 * V[0] + V[1] + whole0 + d0                                             # prolongation + last sweep
+    pcg_it = 3.5 * V[0] + rows0 + 6.5 * V[0] + rows0 + d0 - (1.5 * V[0] if p32 else 0.0)
 
     def solve(it):
         return 3 * V[0] + 1.5 * V[0] + rows0 + d0 + (it + 1) * vc + it * pcg_it + 3 * V[0] + rows0
@@ -202,6 +213,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--rhs-block", type=int, default=16,
                     help="recon workload: right-hand sides per block solve (1 = plain, one at a time)")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed",
+                    help="K solves of the timed pairs: FP64 multigrid PCG, or mixed (the PCG direction in "
+                         "FP32 on the tiled kernels; x, r, A p and the dots FP64)")
     ap.add_argument("--config", choices=("C1", "C2", "C3"), default="C3",
                     help="recon workload: the 16^3 face-source (C1), 64^3 (C2) or 128^3 (C3) configuration")
     ap.add_argument("--oracle-recon", action="store_true",
@@ -239,7 +253,8 @@ def main():
     m = P.mesh
     N, K = m.N, P.n_ill
     log(f"problem {args.grid}^3: N={N} E={m.E} n_ill={K} ({time.time() - t_setup:.1f}s)")
-    opts = qpat.default_opts(max_rhs_block=16)          # multigrid-preconditioned block PCG, FP64
+    prec = 1 if args.precision == "mixed" else 0
+    opts = qpat.default_opts(max_rhs_block=16, precision=prec)   # multigrid-preconditioned block PCG
     ctx = qpat.Context(d(m.coords), d(m.tets, torch.int32), d(m.bfaces, torch.int32), opts=opts)
     ctx.set_sources(d(P.phi_src))
     h = torch.empty(K * N, dtype=torch.float64, device=dev)
@@ -320,7 +335,7 @@ def main():
                           "pcg_iters_sum": i1["iters_sum"] + i2["iters_sum"],
                           "pcg_iters_max": max(i1["iters_max"], i2["iters_max"])}
             log(label, out[label])
-        ctx.set_opts(max_rhs_block=16, pcg_precond=1, precision=0)
+        ctx.set_opts(max_rhs_block=16, pcg_precond=1, precision=prec)
         plain = out
 
     # ---- mixed precision (FP32 operator and vectors in Jacobi-PCG K solves, FP64
@@ -331,6 +346,7 @@ def main():
         precision_cmp = {}
         beta_lin = d(np.concatenate([kt, mt]))
         for label, o in (("fp64_multigrid", dict(pcg_precond=1, precision=0)),
+                         ("mixed_multigrid", dict(pcg_precond=1, precision=1)),
                          ("mixed_jacobi", dict(pcg_precond=0, precision=1))):
             ctx.set_opts(max_rhs_block=16, **o)
             ctx.forward(d(P.kappa), d(P.mu), None, None)
@@ -344,11 +360,12 @@ def main():
             torch.cuda.synchronize()
             precision_cmp[label] = {"s_per_lsqr_iter": round((time.perf_counter() - a) / args.lsqr_steps, 4),
                                     "final_lsqr_residual": r, "steps": args.lsqr_steps}
-        ctx.set_opts(max_rhs_block=16, pcg_precond=1, precision=0)
+        ctx.set_opts(max_rhs_block=16, pcg_precond=1, precision=prec)
         ctx.forward(d(P.kappa), d(P.mu), None, None)
         r64 = precision_cmp["fp64_multigrid"]["final_lsqr_residual"]
-        r32 = precision_cmp["mixed_jacobi"]["final_lsqr_residual"]
-        precision_cmp["final_residual_rel_diff"] = abs(r32 - r64) / r64
+        for label in ("mixed_multigrid", "mixed_jacobi"):
+            rr = precision_cmp[label]["final_lsqr_residual"]
+            precision_cmp[label]["final_residual_rel_diff_vs_fp64"] = abs(rr - r64) / r64
         log("precision", precision_cmp)
 
     # ---- calibration copy for HBM counters (profiling runs only)
@@ -413,8 +430,9 @@ def main():
     timed = {k: kst[k] for k in MG_KERNELS if kst[k]["launches"]}
     key = max(timed, key=lambda k: timed[k]["total_ms"])
     st = timed[key]
-    name = mg_kernel(key, kst)[0]
-    bytes_total = mg_algorithmic_bytes(key, N, layout, st, kst)
+    p32 = prec == 1
+    name = mg_kernel(key, kst, p32)[0]
+    bytes_total = mg_algorithmic_bytes(key, N, layout, st, kst, p32)
     avg_ms = st["total_ms"] / st["launches"]
     achieved = bytes_total / st["launches"] / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -422,9 +440,9 @@ def main():
                 "avg_ms": round(avg_ms, 4), "launches": st["launches"],
                 "bytes_per_launch": round(bytes_total / st["launches"]),
                 "operator": "stencil (diagonal + %d upper offsets)" % (layout["stencil_arrays"] - 1),
-                "other_kernels": {mg_kernel(k, kst)[0]: {
+                "other_kernels": {mg_kernel(k, kst, p32)[0]: {
                     "avg_ms": round(v["total_ms"] / v["launches"], 4), "launches": v["launches"],
-                    "GB/s": round(mg_algorithmic_bytes(k, N, layout, v, kst) / v["total_ms"] / 1e6, 1)}
+                    "GB/s": round(mg_algorithmic_bytes(k, N, layout, v, kst, p32) / v["total_ms"] / 1e6, 1)}
                     for k, v in timed.items() if k != key}}
     roofline["traffic"] = measured_traffic(name)
     roofline["stream_triad_GBs"] = round(triad_gbs, 1)
@@ -436,7 +454,7 @@ def main():
     levels = mg_levels(n1, n1, n1)
     it_t, it_a = infos[-1][0]["iters_max"], infos[-1][1]["iters_max"]
     blocks = (K + 15) // 16
-    pb, parts = pair_algorithmic_bytes(N, m.E, levels, 16, blocks, it_t, it_a)
+    pb, parts = pair_algorithmic_bytes(N, m.E, levels, 16, blocks, it_t, it_a, p32=prec == 1)
     roofline["pair"] = {"bytes": round(pb), "GB_per_s": round(pb / pair_s / 1e9, 1),
                         "frac": round(pb / pair_s / 1e9 / HBM_PEAK_GBS, 4),
                         "frac_of_triad": round(pb / pair_s / 1e9 / triad_gbs, 4),
@@ -485,12 +503,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == 0 else "f64 (PCG direction stored f32)",
         "data": "synthetic",
         "config": {"workload": f"QPAT J s + J^T t pair, {args.grid}^3 Kuhn voxels (N={N}, E={m.E}), "
                                f"{K} Gaussian illuminations, seeded ellipsoid phantom, 16-RHS block PCG "
-                               "with a geometric-multigrid V-cycle, FP64, rtol 1e-10",
-                   "grid": args.grid, "nodes": N, "tets": m.E, "n_ill": K, "precision": "fp64",
+                               "with a geometric-multigrid V-cycle, "
+                               + ("FP64" if prec == 0 else "mixed (direction FP32; x, r, A p, dots FP64)")
+                               + ", true residual <= 1e-10 ||b|| in FP64",
+                   "grid": args.grid, "nodes": N, "tets": m.E, "n_ill": K, "precision": args.precision,
                    "preconditioner": "multigrid V(1,1), weighted Jacobi, Galerkin coarse levels",
                    "rhs_block": 16, "pcg_rtol": 1e-10},
         "s_per_lsqr_iter": round(lsqr_s, 4) if lsqr_s else None,

@@ -47,12 +47,21 @@ typedef enum {
 } qpat_status;
 
 typedef struct {
-    int32_t precision;      /* 0: FP64 throughout. 1: mixed -- FP32 operator, FP32 Jacobi and
-                               FP32 PCG vectors, FP64 dot products, FP64 true-residual
-                               recomputation (reliable updates) and FP64 iterate. Mixed is
-                               an arithmetic of the Jacobi-PCG K solves: it requires
-                               pcg_precond = 0 (QPAT_ERR_ARG otherwise). M_delta solves and
-                               LSQR are FP64 in both modes.                                   */
+    int32_t precision;      /* K solves. 0: FP64 PCG (iterate, residual, direction, operator,
+                               dot products). 1: mixed. On the multigrid path's LDS-tiled
+                               kernels (lattice meshes, blocks of 16 right-hand sides) the
+                               search direction p is stored in FP32; x, r, q = A p (FP64
+                               operator), the dot products and the true-residual check stay
+                               FP64, and x and r are both updated with the stored p, so the
+                               solves meet the same FP64 stopping rule (other multigrid
+                               blocks run FP64). On the Jacobi-PCG path (pcg_precond = 0, or
+                               meshes without a lattice) the operator, the Jacobi diagonal
+                               and the PCG vectors are FP32, with FP64 dot products, FP64
+                               true-residual recomputation (reliable updates) and an FP64
+                               iterate. In both modes the multigrid V-cycle keeps parts of its
+                               own work in FP32 (the finest residual it restricts and, on the
+                               tiled path, the last sweep's rows and its output z). M_delta
+                               solves and LSQR are FP64 in both modes.                      */
     int32_t max_rhs_block;  /* right-hand sides per block PCG (1, 2, 4, 8 or 16). 1 solves the
                                illuminations one after another ("plain").                    */
     double  pcg_rtol;       /* K solves stop when ||b - K x||_2 <= pcg_rtol ||b||_2 (true
@@ -81,10 +90,10 @@ typedef struct {
     int32_t prior_precond;  /* M_delta solves: 1 = PCG with a geometric multigrid V-cycle
                                (lattice meshes with the stencil form; otherwise Jacobi),
                                0 = Jacobi-PCG. Same stopping rule either way.               */
-    int32_t pcg_precond;    /* K solves: 1 = PCG with a geometric multigrid V-cycle in FP64
-                               (lattice meshes with the stencil form; elsewhere Jacobi-PCG
-                               in FP64); 0 = Jacobi-PCG in the arithmetic `precision`
-                               selects. Same stopping rule either way.                       */
+    int32_t pcg_precond;    /* K solves: 1 = PCG with a geometric multigrid V-cycle (lattice
+                               meshes with the stencil form; elsewhere Jacobi-PCG); 0 =
+                               Jacobi-PCG. `precision` selects the arithmetic of either.
+                               Same stopping rule either way.                                */
 } qpat_opts;
 
 /* Solve report of a call (host struct). The first five fields are outputs.

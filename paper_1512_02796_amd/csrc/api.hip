@@ -67,12 +67,6 @@ qpat_status check_opts(qpat_ctx* c, const qpat_opts* o) {
         return fail(c, QPAT_ERR_ARG, "operator_format must be 0 or 1");
     if (o->prior_precond != 0 && o->prior_precond != 1) return fail(c, QPAT_ERR_ARG, "prior_precond must be 0 or 1");
     if (o->pcg_precond != 0 && o->pcg_precond != 1) return fail(c, QPAT_ERR_ARG, "pcg_precond must be 0 or 1");
-    // the multigrid K solves are FP64 throughout; the mixed arithmetic (FP32
-    // operator and vectors, FP64 reductions and reliable updates) is the
-    // Jacobi-PCG path's, so asking for both is an error rather than a silent
-    // FP64 run
-    if (o->precision == 1 && o->pcg_precond == 1)
-        return fail(c, QPAT_ERR_ARG, "precision = 1 (mixed) needs pcg_precond = 0: the multigrid K solves are FP64");
     return QPAT_OK;
 }
 

@@ -48,6 +48,7 @@ struct MgLevel {
     double* W = nullptr;           // [nsys][8][N] operator-dependent prolongation weights to the next level (corner-major)
     double* Uf = nullptr;          // kind 3: [nsys][kFullRow][N] whole Kuhn rows, entry-major; K levels >= 1: [N][kRow27]
     float* Uf32 = nullptr;         // kind 5: the kind-3 rows in FP32 (M_delta's V-cycle)
+    float* Ufk32 = nullptr;        // K level 0: the whole Kuhn rows [N][16] in FP32 (fused prolongation + last sweep)
     int32_t vkind = -1;            // row kind of the V-cycle's kernels on this level (-1: kind)
 };
 
@@ -904,6 +905,7 @@ struct PcgMg {
     int32_t nb;           // blocks of the kernels that write partials
     // region coarse space (one right-hand side per system), kreg = 0: off
     int32_t kreg;
+    int32_t p32;          // 1: the direction in FP32 on the tiled 16-right-hand-side path (mixed precision)
     const int32_t* reg;   // [nsys][N]
     const double* ry;     // [nsys][kRegMax]
     const double* rcorr;  // [nsys][2]: r.(Z y), mean(Z y)
@@ -1475,7 +1477,13 @@ struct TileArgs {
 //   and out = r' - A x with the first sweep x = w D^{-1} r' (w / a_jj from
 //   LDS per neighbour). r' goes to another buffer than r: neighbouring tiles
 //   still read r's halo.
-template <int MODE, int B>
+// Z32 (kTDirSpmv only): `in` (z, the V-cycle's output) is FP32 [N][B].
+// P32 (kTDirSpmv, kTUpdResid): the PCG direction p is stored in FP32. The
+// direction kernel rounds p before staging it, so q = A p is the FP64 product of
+// exactly the stored p, and the update adds alpha times that same p to the FP64
+// iterate: x and r stay consistent (r = b - A x up to FP64 rounding), and the
+// rounding only perturbs the choice of the next direction.
+template <int MODE, int B, bool Z32 = false, bool P32 = false>
 __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
     using TL = MgTile<B>;
     constexpr int NPF = TL::NPF, NU = TL::NU, RS = NPF * kTT, US = NU * kTT;
@@ -1516,10 +1524,12 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
     const uint32_t nxy = static_cast<uint32_t>(nx) * ny;
     const uint32_t pv = nxy * B * SZ, pu = nxy * M1 * SZ, pd = nxy * SZ, pin = nxy * g.ld * SZ;
     const double w = (MODE == kTSmoothDots || MODE == kTResidFirst || UPD) ? *g.w : 0.0;
-    auto plane = [&](const double* base, int pl, uint32_t stride, uint32_t bytes) {
+    auto plane = [&](const auto* base, int pl, uint32_t stride, uint32_t bytes) {
         const bool in = pl >= 0 && pl < nz;
         return rsrc(base + (in ? (int64_t)pl * stride : 0), in ? bytes : 0u);
     };
+    static_assert(!Z32 || MODE == kTDirSpmv, "FP32 input only for the direction + product");
+    static_assert(!P32 || MODE == kTDirSpmv || MODE == kTUpdResid, "FP32 direction: direction and update only");
     // LDS node of output slot u (slots past the tile point at an interior node)
     int32_t oc[NPF];
 #pragma unroll
@@ -1564,10 +1574,23 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                         : kOut;
         }
         auto fetch = [&](int pl) {
-            const auto bi = plane(g.in, pl, nxy * g.ld, pin), bu = plane(g.U, pl, nxy * M1, pu);
+            const auto bu = plane(g.U, pl, nxy * M1, pu);
+            if constexpr (Z32) {
+                const auto bi = plane(reinterpret_cast<const float*>(g.in), pl, nxy * g.ld, pin / 2);
 #pragma unroll
-            for (int u = 0; u < NPF; ++u) fr[u] = bload<double>(bi, fo[u]);
-            if constexpr (MODE == kTDirSpmv || UPD) {
+                for (int u = 0; u < NPF; ++u)
+                    fr[u] = static_cast<double>(bload<float>(bi, fo[u] == kOut ? kOut : fo[u] / 2));
+            } else {
+                const auto bi = plane(g.in, pl, nxy * g.ld, pin);
+#pragma unroll
+                for (int u = 0; u < NPF; ++u) fr[u] = bload<double>(bi, fo[u]);
+            }
+            if constexpr (MODE == kTDirSpmv && P32) {   // the old direction, FP32
+                const auto b2 = plane(reinterpret_cast<const float*>(g.in2), pl, nxy * B, pv / 2);
+#pragma unroll
+                for (int u = 0; u < NPF; ++u)
+                    f2[u] = static_cast<double>(bload<float>(b2, fo[u] == kOut ? kOut : fo[u] / 2));
+            } else if constexpr (MODE == kTDirSpmv || UPD) {
                 const auto b2 = plane(g.in2, pl, nxy * B, pv);
 #pragma unroll
                 for (int u = 0; u < NPF; ++u) f2[u] = bload<double>(b2, fo[u]);
@@ -1598,6 +1621,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                 // beta = 0 (a run's first direction) never reads the old direction's values
                 if constexpr (MODE == kTDirSpmv)
                     val = fo[u] != kOut ? (beta != 0.0 ? fr[u] - cc_ + beta * f2[u] : fr[u] - cc_) : 0.0;
+                if constexpr (MODE == kTDirSpmv && P32) val = static_cast<double>(static_cast<float>(val));
                 if constexpr (MODE == kTResidFirst) val = w * f2[u] * fr[u];
                 if constexpr (UPD) val = fr[u] - alpha * f2[u];   // r' itself: the sweep scales it per neighbour
                 ring[sl * RS + tid + u * kTT] = val;
@@ -1633,7 +1657,9 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
             const auto bo = RES32 ? rsrc(reinterpret_cast<const float*>(g.out) + (int64_t)z * nxy * B, pv / 2)
                                   : plane(g.out, z, nxy * B, pv);
             if (act) {
-                const auto bo2 = plane(g.out2, z, nxy * B, MODE == kTDirSpmv || UPD ? pv : 0u);
+                const auto bo2 = (MODE == kTDirSpmv && P32)
+                                     ? plane(reinterpret_cast<const float*>(g.out2), z, nxy * B, pv / 2)
+                                     : plane(g.out2, z, nxy * B, MODE == kTDirSpmv || UPD ? pv : 0u);
 #pragma unroll
                 for (int u = 0; u < NPF; ++u) {
                     if (tid + u * kTT >= TX * TY * B) continue;   // whole waves past the tile skip
@@ -1680,7 +1706,10 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                     if constexpr (MODE == kTDirSpmv) {
                         o = sum;
                         a0 += in ? xc * sum : 0.0;
-                        bstore_nt(bo2, oo[u], xc);   // p: next read by the update pass
+                        if constexpr (P32)   // xc is already an FP32 value
+                            bstore_nt_f32(bo2, oo[u] == kOut ? kOut : oo[u] / 2, static_cast<float>(xc));
+                        else
+                            bstore_nt(bo2, oo[u], xc);   // p: next read by the update pass
                     } else if constexpr (MODE == kTApply) {
                         o = g.scale * sum;
                     } else if constexpr (UPD) {
@@ -1704,11 +1733,22 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                 }
                 if constexpr (UPD) {   // x += alpha p on this plane's nodes, after the stencil work
                     __builtin_amdgcn_sched_barrier(0);
-                    const auto bx = plane(g.x3, z, nxy * B, pv), bp = plane(g.p3, z, nxy * B, pv);
+                    const auto bx = plane(g.x3, z, nxy * B, pv);
+                    if constexpr (P32) {
+                        const auto bp = plane(reinterpret_cast<const float*>(g.p3), z, nxy * B, pv / 2);
 #pragma unroll
-                    for (int u = 0; u < NO; ++u) {
-                        if (tid + u * kTT >= TX * TY * B) continue;
-                        bstore_nt(bx, oo[u], bload_nt(bx, oo[u]) + alpha * bload_nt(bp, oo[u]));
+                        for (int u = 0; u < NO; ++u) {
+                            if (tid + u * kTT >= TX * TY * B) continue;
+                            const double pu = static_cast<double>(bload<float>(bp, oo[u] == kOut ? kOut : oo[u] / 2));
+                            bstore_nt(bx, oo[u], bload_nt(bx, oo[u]) + alpha * pu);
+                        }
+                    } else {
+                        const auto bp = plane(g.p3, z, nxy * B, pv);
+#pragma unroll
+                        for (int u = 0; u < NO; ++u) {
+                            if (tid + u * kTT >= TX * TY * B) continue;
+                            bstore_nt(bx, oo[u], bload_nt(bx, oo[u]) + alpha * bload_nt(bp, oo[u]));
+                        }
                     }
                 }
             }
@@ -2101,17 +2141,21 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
 // r.z, sum z, sum r. The stencil rows come whole ([N][16], lane k holds entry
 // k) and reach the node's lanes by DPP row broadcasts, which keeps the LDS
 // at two blocks per CU. Chunks start on even planes (even zc).
+// The sweep is preconditioner work: its rows are read in FP32 and z is stored
+// in FP32 (the arithmetic stays FP64); the dot products use the stored z, the
+// vector the PCG direction is built from. The PCG vectors themselves and the
+// operator of q = A p stay FP64.
 constexpr int kPCX = (kTHX - 2) / 2 + 2, kPCY = (kTHY - 2) / 2 + 2;   // coarse patch of a tile
 constexpr int kPCN = kPCX * kPCY * 16;                                // its values per coarse plane
 struct PSArgs {
     int32_t nx, ny, nz, cx, cy, cz;
     int32_t tiles_x, tiles_y, zc, items;
-    const double* Uf;     // [N][16] whole Kuhn rows
+    const float* Uf;      // [N][16] whole Kuhn rows, FP32
     const double* r;      // [N][16] the PCG residual (level 0's b)
     const double* xc;     // [Nc][16] level 1's solution
     const double* dinv;   // [N]
     const double* w;      // level 0's Jacobi weight
-    double* z;            // [N][16]
+    float* z;             // [N][16], FP32
     double* parts;
     const MgScal* sc;
 };
@@ -2152,7 +2196,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
     const uint32_t nxy = static_cast<uint32_t>(nx) * ny, cxy = static_cast<uint32_t>(g.cx) * g.cy;
     const uint32_t pv = nxy * B * SZ, pd = nxy * SZ, pc = cxy * B * SZ;
     const double w = *g.w;
-    auto plane = [&](const double* base, int pl, int n, uint32_t stride, uint32_t bytes) {
+    auto plane = [&](const auto* base, int pl, int n, uint32_t stride, uint32_t bytes) {
         const bool in = pl >= 0 && pl < n;
         return rsrc(base + (in ? (int64_t)pl * stride : 0), in ? bytes : 0u);
     };
@@ -2173,7 +2217,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
         const int32_t x0 = (t2 % g.tiles_x) * TX, y0 = (t2 / g.tiles_x) * TY;
         const int32_t zb = ch * g.zc, ze = min(zb + g.zc, nz);   // zb even
         const int32_t cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1;        // the patch's first coarse column, row
-        uint32_t fo[NPF], oo[NO], dof = kOut, co[NC];
+        uint32_t fo[NPF], oo[NO], o4[NO], dof = kOut, co[NC];
 #pragma unroll
         for (int u = 0; u < NPF; ++u) {
             const int nl = (tid + u * kTT) / B;
@@ -2186,6 +2230,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
             const int nl = (tid + u * kTT) / B;
             const int ox = x0 + nl % TX, oy = y0 + nl / TX;
             oo[u] = nl < TX * TY && ox < nx && oy < ny ? (static_cast<uint32_t>(oy * nx + ox) * B + k) * SZ : kOut;
+            o4[u] = oo[u] == kOut ? kOut : oo[u] / 2;   // the same element of an FP32 [N][16] array
         }
         if (tid < kTHN) {
             const int gx = x0 - 1 + tid % kTHX, gy = y0 - 1 + tid / kTHX;
@@ -2261,27 +2306,29 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
         };
         auto step = [&](int z, auto SZ0, auto SP0, auto SL0) {
             constexpr int sz = decltype(SZ0)::value, sp = decltype(SP0)::value, sl = decltype(SL0)::value;
-            double ua[NO];   // the rows of this plane's nodes: in flight during the staging
-            const auto bu = plane(g.Uf, z, nz, nxy * B, pv);
+            float ua32[NO];   // the rows of this plane's nodes: in flight during the staging
+            const auto bu = plane(g.Uf, z, nz, nxy * B, pv / 2);
 #pragma unroll
-            for (int u = 0; u < NO; ++u) ua[u] = bload<double>(bu, oo[u]);
+            for (int u = 0; u < NO; ++u) ua32[u] = bload<float>(bu, o4[u]);
             store(sp, z + 1);
             __syncthreads();
             if (z + 1 < ze) fetch(z + 2);
-            const auto bo = plane(g.z, z, nz, nxy * B, pv);
+            const auto bo = plane(g.z, z, nz, nxy * B, pv / 2);
 #pragma unroll
             for (int u = 0; u < NO; ++u) {
                 if (tid + u * kTT >= TX * TY * B) continue;   // whole waves past the tile skip
                 const double* rb = ring + oc[u] * B + k;
-                const double ax = apply_kuhn16(ua[u], rb, sz * RS, sp * RS, sl * RS, std::make_integer_sequence<int, 7>{});
+                const double ax = apply_kuhn16(static_cast<double>(ua32[u]), rb, sz * RS, sp * RS, sl * RS,
+                                               std::make_integer_sequence<int, 7>{});
                 const double xc = rb[sz * RS];
                 const double bcu = rint[(z & 1) * (TX * TY * B) + tid + u * kTT];
-                const double o = xc + w * dring[sz * kTHN + oc[u]] * (bcu - ax);
+                const float o32 = static_cast<float>(xc + w * dring[sz * kTHN + oc[u]] * (bcu - ax));
+                const double o = static_cast<double>(o32);
                 const bool in = act && oo[u] != kOut;
                 a0 += in ? bcu * o : 0.0;
                 a1 += in ? o : 0.0;
                 a2 += in ? bcu : 0.0;
-                bstore_nt(bo, act ? oo[u] : kOut, o);
+                bstore_nt_f32(bo, act ? o4[u] : kOut, o32);
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (z + 1 < ze) {   // plane z + 2's 1/a_ii (slot sl) and, odd, coarse plane (z + 3) / 2
@@ -2429,7 +2476,7 @@ dim3 sgrid(int64_t n) {
     return vgrid(n * Pk<B>::BV, B == 1 ? kMgBlocks : kMgGrid);
 }
 
-template <int MODE, int B>
+template <int MODE, int B, bool Z32 = false, bool P32 = false>
 void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const double* in, const double* in2,
                  const double* b, double* out, double* out2, double* x3 = nullptr, const double* p3 = nullptr) {
     if constexpr (B >= 8) {   // tile_setup turns the tiling on only there
@@ -2457,7 +2504,7 @@ void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const doubl
         g.sc = M.sc;
         g.x3 = x3;
         g.p3 = p3;
-        hipLaunchKernelGGL((k_mg_tile<MODE, B>), dim3(t.blocks), dim3(kTT), MgTile<B>::LDS, st, g);
+        hipLaunchKernelGGL((k_mg_tile<MODE, B, Z32, P32>), dim3(t.blocks), dim3(kTT), MgTile<B>::LDS, st, g);
     }
 }
 
@@ -2502,12 +2549,12 @@ inline void launch_ps(const MgState& M, const TileGeo& t, hipStream_t st, const 
     g.tiles_y = t.tiles_y;
     g.zc = t.ps_zc;
     g.items = t.ps_items;
-    g.Uf = L.Uf;
+    g.Uf = L.Ufk32;
     g.r = r;
     g.xc = x1;
     g.dinv = L.dinv;
     g.w = M.w;   // system 0, level 0
-    g.z = z;
+    g.z = reinterpret_cast<float*>(z);   // FP32 in the double buffer's first half
     g.parts = M.parts;
     g.sc = M.sc;
     hipLaunchKernelGGL(k_mg_prolong_smooth, dim3(t.ps_blocks), dim3(kTT), kPSLds, st, g);
@@ -2557,13 +2604,16 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
     if constexpr (B >= 8) {
         if (M.nsys != 1 || L.kind != 1 || L.N * B * (int64_t)sizeof(double) >= (int64_t(1) << 31)) return QPAT_OK;
         static_assert(MgTile<B>::LDS <= 159 * 1024, "tiled multigrid LDS budget");
-        const void* fns[7] = {reinterpret_cast<const void*>(&k_mg_tile<kTDirSpmv, B>),
+        const void* fns[10] = {reinterpret_cast<const void*>(&k_mg_tile<kTDirSpmv, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTResidFirst, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTSmoothDots, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTTrue, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTResid, B>),
                               reinterpret_cast<const void*>(&k_mg_tile<kTApply, B>),
-                              reinterpret_cast<const void*>(&k_mg_tile<kTUpdResid, B>)};
+                              reinterpret_cast<const void*>(&k_mg_tile<kTUpdResid, B>),
+                              reinterpret_cast<const void*>(&k_mg_tile<kTDirSpmv, B, true>),
+                              reinterpret_cast<const void*>(&k_mg_tile<kTDirSpmv, B, true, true>),
+                              reinterpret_cast<const void*>(&k_mg_tile<kTUpdResid, B, false, true>)};
         for (const void* f : fns)   // dynamic LDS beyond the default limit is allowed per kernel
             QPAT_HIP(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MgTile<B>::LDS));
         int occ = 1, cus = 256;
@@ -2620,7 +2670,7 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
             q.on = true;
         }
         if constexpr (B == 16) {   // the fused prolongation + last sweep: the same tiles, even chunks
-            if (L.Uf) {
+            if (L.Uf && L.Ufk32) {
                 const void* fps = reinterpret_cast<const void*>(&k_mg_prolong_smooth);
                 QPAT_HIP(c, hipFuncSetAttribute(fps, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPSLds));
                 int occ_ps = 1;
@@ -2684,6 +2734,13 @@ inline int vkind(const MgLevel& L) { return L.vkind >= 0 ? L.vkind : L.kind; }
 
 // the tiled path fuses the PCG update with the V-cycle's first residual
 inline bool fused_update(const TileGeo& tg) { return tg.on && kMgNu == 1; }
+
+// the V-cycle's last finest-level sweep is the fused prolongation + sweep,
+// which leaves z in FP32 (16 right-hand sides, trilinear transfer: K)
+template <int B>
+inline bool z32_path(const MgState& M, const TileGeo& tg) {
+    return B == 16 && fused_update(tg) && tg.ps_on && !M.opdep;
+}
 
 // One V-cycle on every lane: z = V(r), r = level 0's b. The last sweep also
 // leaves the partial sums r.z, sum z, sum r. On a tiled finest level with one
@@ -2754,7 +2811,7 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         const SmArgs a = sm(l);
         const dim3 g = sgrid<B>(L.N);
         const double* bl = l == 0 ? r0 : L.b;
-        if (l == 0 && B == 16 && fused0 && tg.ps_on && !M.opdep) {   // prolongation fused into the last sweep
+        if (l == 0 && z32_path<B>(M, tg)) {   // prolongation fused into the last sweep (z in FP32)
             if (ev) (void)hipEventRecord(ev[2], st);
             launch_ps(M, tg, st, r0, xl[1], tl[0]);
             if (ev) (void)hipEventRecord(ev[3], st);
@@ -2812,6 +2869,7 @@ PcgMg pcg_args(qpat_ctx* c, Op op) {
     a.nsys = M.nsys;
     a.nb = static_cast<int32_t>(sgrid<B>(c->N).x);
     a.kreg = B == 1 ? M.kreg : 0;
+    a.p32 = op == Op::K && c->opts.precision == 1 ? 1 : 0;
     a.reg = M.reg;
     a.ry = M.ry;
     a.rcorr = M.rcorr;
@@ -2837,7 +2895,12 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
     if (par) std::swap(a.po, a.pn);
     const dim3 g = sgrid<B>(a.L.N), lanes(1, a.nsys * B);
     if (ev) (void)hipEventRecord(ev[0], st);
-    if (tg.on) {
+    const bool p32 = a.p32 && z32_path<B>(M, tg);   // mixed precision: the direction in FP32
+    if (tg.on && p32) {
+        launch_tile<kTDirSpmv, B, true, true>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn);
+    } else if (tg.on && z32_path<B>(M, tg)) {   // z from the fused prolongation + last sweep, FP32
+        launch_tile<kTDirSpmv, B, true>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn);
+    } else if (tg.on) {
         launch_tile<kTDirSpmv, B>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn);
     } else {
         hipLaunchKernelGGL(k_mgp_dir<B>, g, dim3(kMgT), 0, st, a);
@@ -2849,7 +2912,10 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
     if (fused_update(tg)) {   // r, x and the V-cycle's first sweep + residual in one pass; r alternates buffers
         double* r_old = par ? M.pr2 : M.pr;
         double* r_new = par ? M.pr : M.pr2;
-        launch_tile<kTUpdResid, B>(M, tg, st, r_old, a.q, nullptr, M.lv[0].r, r_new, a.x, a.pn);
+        if (p32)
+            launch_tile<kTUpdResid, B, false, true>(M, tg, st, r_old, a.q, nullptr, M.lv[0].r, r_new, a.x, a.pn);
+        else
+            launch_tile<kTUpdResid, B>(M, tg, st, r_old, a.q, nullptr, M.lv[0].r, r_new, a.x, a.pn);
         a.r = r_new;
     } else {
         hipLaunchKernelGGL(k_mgp_update<B>, g, dim3(kMgT), 0, st, a);
@@ -2974,8 +3040,9 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
             if (c->opts.use_graphs) {
                 // every by-value argument of the captured kernels that can change
                 // between runs: the region count is recomputed at each prior set-up
-                char key[112];
-                snprintf(key, sizeof key, "%d/%d/%.17g/%d/%d/%d", B, chunk, a.rtol2, a.maxit, a.deflate, a.kreg);
+                char key[128];
+                snprintf(key, sizeof key, "%d/%d/%.17g/%d/%d/%d/%d", B, chunk, a.rtol2, a.maxit, a.deflate, a.kreg,
+                         a.p32);
                 auto it = M.graphs.find(key);
                 hipGraphExec_t ex = nullptr;
                 if (it != M.graphs.end()) {
@@ -3293,8 +3360,10 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
                 QPAT_TRY(dalloc(c, &L.Uf32, nsys * L.N * kFullRow));
             }
             if (op == Op::K && l == 0 && L.kind == 1 && M.bmax == 16 && nl > 1 &&
-                L.N * kFullRow * (int64_t)sizeof(double) < (int64_t(1) << 31))   // node-major, for k_mg_prolong_smooth
+                L.N * kFullRow * (int64_t)sizeof(double) < (int64_t(1) << 31)) {   // node-major, for k_mg_prolong_smooth
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kFullRow));
+                QPAT_TRY(dalloc(c, &L.Ufk32, nsys * L.N * kFullRow));
+            }
             if (op == Op::K && l >= 1 && l < kMgMaxLevels && M.bmax == 16 && M.lv[0].kind == 1 &&
                 L.N >= kTile27Min && L.N * kRow27 * (int64_t)sizeof(double) < (int64_t(1) << 31))
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kRow27));
@@ -3330,6 +3399,9 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
         if (M.lv[0].Uf32)
             hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nsys * M.lv[0].N * kFullRow, kMgT, 4096)), dim3(kMgT), 0,
                                c->stream, M.lv[0].Uf, M.lv[0].Uf32, nsys * M.lv[0].N * kFullRow);
+        if (M.lv[0].Ufk32)
+            hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nsys * M.lv[0].N * kFullRow, kMgT, 4096)), dim3(kMgT), 0,
+                               c->stream, M.lv[0].Uf, M.lv[0].Ufk32, nsys * M.lv[0].N * kFullRow);
     }
     for (int l = 0; l + 1 < nl; ++l) {
         const MgLevel& F = M.lv[l];
@@ -3404,7 +3476,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     QPAT_HIP(c, hipStreamSynchronize(c->stream));
     if (op == Op::Prior) QPAT_TRY(region_setup(c, M));
     if (M.lv[0].Uf && op == Op::Prior) M.lv[0].kind = 3;
-    if (M.lv[0].Uf32) M.lv[0].vkind = 5;   // the V-cycle's sweeps and residuals on FP32 rows
+    if (M.lv[0].Uf32 && op == Op::Prior) M.lv[0].vkind = 5;   // the V-cycle's sweeps and residuals on FP32 rows
     for (int l = 1; op == Op::Prior && l < nl; ++l)
         if (M.lv[l].Uf) M.lv[l].kind = 4;
     M.current = true;

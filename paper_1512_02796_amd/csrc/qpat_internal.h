@@ -45,6 +45,9 @@ __device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t b, uint32_t off
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b, off, 0, 2);
 }
+__device__ __forceinline__ void bstore_nt_f32(__amdgpu_buffer_rsrc_t b, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b, off, 0, 2);
+}
 template <typename T>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t b, uint32_t off, T v) {
     if constexpr (sizeof(T) == 4)

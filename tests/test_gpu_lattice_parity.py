@@ -75,3 +75,24 @@ def test_slab_jvp_vjp_parity(slab):
     outT = torch.empty(2 * N, dtype=torch.float64, device="cuda")
     ctx.vjp(dev(slab["t"]), outT)
     assert_close(host(outT), lin.vjp(slab["t"]), 1e-10, "slab J^T t")
+
+
+def test_slab_mixed_precision_parity(slab):
+    """The same products with precision = 1: the tiled 16-right-hand-side path
+    stores the PCG direction in FP32 (x, r, q = A p and the dots in FP64), so the
+    FP64 tolerance still holds."""
+    ctx, lin, N = slab["ctx"], slab["lin"], slab["N"]
+    ctx.set_opts(precision=1)
+    try:
+        phi = torch.empty(N_ILL * N, dtype=torch.float64, device="cuda")
+        info = ctx.forward(dev(slab["kappa"]), dev(slab["mu"]), phi)
+        assert info["relres_max"] <= 1e-12
+        assert_close(host(phi).reshape(N_ILL, N), lin.phi, 1e-10, "slab fluence, mixed")
+        out = torch.empty(N_ILL * N, dtype=torch.float64, device="cuda")
+        ctx.jvp(dev(slab["s"]), out)
+        assert_close(host(out).reshape(N_ILL, N), lin.jvp(slab["s"]), 1e-10, "slab J s, mixed")
+        outT = torch.empty(2 * N, dtype=torch.float64, device="cuda")
+        ctx.vjp(dev(slab["t"]), outT)
+        assert_close(host(outT), lin.vjp(slab["t"]), 1e-10, "slab J^T t, mixed")
+    finally:
+        ctx.set_opts(precision=0)

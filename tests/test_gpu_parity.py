@@ -70,18 +70,25 @@ def test_jvp_vjp_parity(name, block, precision):
     assert_close(host(outT), lin.vjp(t), tol, f"J^T t {name}")
 
 
-def test_mixed_precision_needs_the_jacobi_path():
-    """precision = 1 with the multigrid K solves (FP64 only) is refused, not run in FP64."""
-    from paper_1512_02796_amd import qpat
-    with pytest.raises(qpat.QpatError) as e:
-        GpuProblem("T4", qpat.default_opts(precision=1))
-    assert e.value.status == qpat.QPAT_ERR_ARG
-    G = GpuProblem("T8")
-    with pytest.raises(qpat.QpatError) as e:
-        G.ctx.set_opts(precision=1)
-    assert e.value.status == qpat.QPAT_ERR_ARG
-    G.ctx.set_opts(precision=1, pcg_precond=0)
-    G.forward()
+@pytest.mark.parametrize("name,n_ill", [("T8", 16), ("T12", 9)])
+def test_mixed_multigrid_parity(name, n_ill):
+    """precision = 1 on the multigrid path: with 16 right-hand sides on the tiled
+    kernels (9 or 16 illuminations: one block of 16) the direction p is stored in
+    FP32 while x, r, q = A p and the dots stay FP64, so the solves meet the same
+    FP64 true-residual rule and the products match the oracle at the FP64
+    tolerance."""
+    G = GpuProblem(name, opts(max_rhs_block=16, precision=1), n_ill=n_ill)
+    phi, h, info = G.forward()
+    g, lin = oracle_of(G.P)
+    assert info["relres_max"] <= 1e-12
+    assert_close(host(phi), lin.phi, 1e-10, f"phi {name} mixed multigrid")
+    s, t = probe_vectors(G.P.cfg["id"], G.n_ill, G.N)
+    out = torch.empty(G.n_ill * G.N, dtype=torch.float64, device="cuda")
+    G.ctx.jvp(dev(s), out)
+    assert_close(host(out).reshape(G.n_ill, G.N), lin.jvp(s), 1e-10, f"J s {name} mixed multigrid")
+    outT = torch.empty(2 * G.N, dtype=torch.float64, device="cuda")
+    G.ctx.vjp(dev(t), outT)
+    assert_close(host(outT), lin.vjp(t), 1e-10, f"J^T t {name} mixed multigrid")
 
 
 def test_per_rhs_report():
