@@ -46,6 +46,8 @@ struct MgLevel {
     double* t = nullptr;           // ping-pong partner of x
     double* r = nullptr;           // residual before restriction
     double* W = nullptr;           // [nsys][8][N] operator-dependent prolongation weights to the next level (corner-major)
+    float* W32 = nullptr;          // the same in FP32: the V-cycle's restriction and prolongation read these (the
+                                   // Galerkin set-up the FP64 ones; both transfers use the same rounded P)
     double* Uf = nullptr;          // kind 3: [nsys][kFullRow][N] whole Kuhn rows, entry-major; K levels >= 1: [N][kRow27]
     float* Uf32 = nullptr;         // kind 5: the kind-3 rows in FP32 (M_delta's V-cycle)
     float* Ufk32 = nullptr;        // K level 0: the whole Kuhn rows [N][16] in FP32 (fused prolongation + last sweep)
@@ -462,6 +464,16 @@ __global__ __launch_bounds__(kMgT) void k_mg_fullrows(LvArgs L, double* __restri
     }
 }
 
+// b = a rounded to FP32, and a replaced by that rounded value (the FP64 users
+// then see exactly the FP32 numbers)
+__global__ __launch_bounds__(kMgT) void k_round_f32(double* __restrict__ a, float* __restrict__ b, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = static_cast<float>(a[i]);
+        b[i] = v;
+        a[i] = static_cast<double>(v);
+    }
+}
+
 __global__ __launch_bounds__(kMgT) void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kMgT)
         b[i] = static_cast<float>(a[i]);
@@ -750,10 +762,10 @@ struct Span {
 // Fine nodes 2 I + {-1, 0, 1} per axis, weights 1/2, 1, 1/2 (trilinear) or
 // from Wall ([nsys][8][Nf], operator-dependent); the ones past the lattice
 // get weight 0 (their loads are clamped inside it).
-template <int B, bool OPW>
+template <int B, bool OPW, typename WT = double>
 __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int32_t ny, int32_t nz,
                                                       const double* __restrict__ r, double* __restrict__ bc,
-                                                      double* __restrict__ xc, const double* __restrict__ Wall) {
+                                                      double* __restrict__ xc, const WT* __restrict__ Wall) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V;
     const int v = threadIdx.x % Pk<B>::BV;
@@ -763,7 +775,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
         const double w = c.w[sys * c.nlev + c.lev];
         const double* dinv = c.dinv + sys * Nc;
         const double* rs = r + sys * Nf * B + v * V;
-        const double* Ws = OPW ? Wall + sys * Nf * 8 : nullptr;
+        const WT* Ws = OPW ? Wall + sys * Nf * 8 : nullptr;
         const int64_t oc = sys * Nc * B + v * V;
         walk<Pk<B>::BV>(c.L.nx, c.L.ny, c.L.nz, [&](int32_t Ix, int32_t Iy, int32_t Iz, int32_t I, int32_t) {
             int32_t fx[3], fy[3], fz[3];
@@ -791,7 +803,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
                         double wgt = wyz * wx[dx];
                         if constexpr (OPW)   // I is corner (d == 0 per axis) of fine node 2 I + d - 1
                             if (wgt != 0.0)
-                                wgt = Ws[((dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)) * Nf + (row + fx[dx])];
+                                wgt = static_cast<double>(Ws[((dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)) * Nf + (row + fx[dx])]);
                         s += wgt * vld<T>(rs + (row + fx[dx]) * B);
                     }
                 }
@@ -804,10 +816,10 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
 // x = base + P xc on fine level f (coarse lattice cx, cy, cz). base = x, or
 // with FIRST the first sweep w D^{-1} b, which is then never stored. P:
 // trilinear, or the weights Wall ([nsys][8][Nf]).
-template <int B, bool FIRST, bool OPW>
+template <int B, bool FIRST, bool OPW, typename WT = double>
 __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32_t cy, int32_t cz,
                                                      const double* __restrict__ xc, const double* __restrict__ b,
-                                                     double* __restrict__ x, const double* __restrict__ Wall) {
+                                                     double* __restrict__ x, const WT* __restrict__ Wall) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V;
     const int v = threadIdx.x % Pk<B>::BV;
@@ -819,7 +831,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
         const double* xs = xc + sys * Nc * B + v * V;
         const double* bs = b + sys * Nf * B + v * V;
         double* xf = x + sys * Nf * B + v * V;
-        const double* Ws = OPW ? Wall + sys * Nf * 8 : nullptr;
+        const WT* Ws = OPW ? Wall + sys * Nf * 8 : nullptr;
         walk<Pk<B>::BV>(f.L.nx, f.L.ny, f.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
             const Span sx(ix, cx), sy(iy, cy), sz(iz, cz);
             const int32_t jx[2] = {sx.j0, sx.j1}, jy[2] = {sy.j0, sy.j1}, jz[2] = {sz.j0, sz.j1};
@@ -837,7 +849,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
                         // clamps the index of a zero-weight corner
                         double wgt;
                         if constexpr (OPW)
-                            wgt = Ws[(a2 + 2 * b2 + 4 * c2) * Nf + i];
+                            wgt = static_cast<double>(Ws[(a2 + 2 * b2 + 4 * c2) * Nf + i]);
                         else
                             wgt = wyz * wx[a2];
                         s += wgt * vld<T>(xs + (row + jx[a2]) * B);
@@ -2301,7 +2313,10 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
                     return wy0 * (wx0 * q[0] + wx1 * q[dx]) + wy1 * (wx0 * q[dy] + wx1 * q[dy + dx]);
                 };
                 double& rv = ring[sl * RS + tid + u * kTT];
-                rv = fma(wz1, bil(c1), fma(wz0, bil(c0), rv));
+                if (pl & 1)   // odd planes lie halfway between two coarse planes
+                    rv = fma(wz1, bil(c1), fma(wz0, bil(c0), rv));
+                else          // even planes on one (weight 1: fma(1, a, b) = a + b exactly)
+                    rv += bil(c0);
             }
         };
         auto step = [&](int z, auto SZ0, auto SP0, auto SL0) {
@@ -2795,11 +2810,11 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         if (tg.on && l < kMgMaxLevels && tg.rst[l].on && !M.opdep)
             launch_restrict<B>(M, tg, l, st, xl[l + 1]);
         else if (M.opdep)
-            hipLaunchKernelGGL((k_mg_restrict<B, true>), sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny,
-                               L.nz, L.r, C.b, xl[l + 1], L.W);
+            hipLaunchKernelGGL((k_mg_restrict<B, true, float>), sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx,
+                               L.ny, L.nz, L.r, C.b, xl[l + 1], L.W32);
         else
             hipLaunchKernelGGL((k_mg_restrict<B, false>), sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny,
-                               L.nz, L.r, C.b, xl[l + 1], nullptr);
+                               L.nz, L.r, C.b, xl[l + 1], static_cast<const double*>(nullptr));
     }
     const MgLevel& K = M.lv[nl - 1];
     hipLaunchKernelGGL(k_mg_dense<B>,
@@ -2819,17 +2834,17 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
             continue;
         }
         if (l == 0 && fused0 && M.opdep)
-            hipLaunchKernelGGL((k_mg_prolong<B, true, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], r0,
-                               xl[0], L.W);
+            hipLaunchKernelGGL((k_mg_prolong<B, true, true, float>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1],
+                               r0, xl[0], L.W32);
         else if (l == 0 && fused0)
             hipLaunchKernelGGL((k_mg_prolong<B, true, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], r0,
-                               xl[0], nullptr);
+                               xl[0], static_cast<const double*>(nullptr));
         else if (M.opdep)
-            hipLaunchKernelGGL((k_mg_prolong<B, false, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1],
-                               bl, xl[l], L.W);
+            hipLaunchKernelGGL((k_mg_prolong<B, false, true, float>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz,
+                               xl[l + 1], bl, xl[l], L.W32);
         else
             hipLaunchKernelGGL((k_mg_prolong<B, false, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1],
-                               bl, xl[l], nullptr);
+                               bl, xl[l], static_cast<const double*>(nullptr));
         for (int k = 0; k < kMgNu; ++k) {
             const bool last = l == 0 && k == kMgNu - 1;
             if (last && ev) (void)hipEventRecord(ev[2], st);
@@ -3354,7 +3369,10 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             QPAT_TRY(dalloc(c, &L.x, V * L.N));
             QPAT_TRY(dalloc(c, &L.t, V * L.N));
             QPAT_TRY(dalloc(c, &L.r, V * L.N));
-            if (op == Op::Prior && l + 1 < nl) QPAT_TRY(dalloc(c, &L.W, nsys * L.N * 8));
+            if (op == Op::Prior && l + 1 < nl) {
+                QPAT_TRY(dalloc(c, &L.W, nsys * L.N * 8));
+                QPAT_TRY(dalloc(c, &L.W32, nsys * L.N * 8));
+            }
             if (op == Op::Prior && l == 0 && L.kind == 1) {
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kFullRow));
                 QPAT_TRY(dalloc(c, &L.Uf32, nsys * L.N * kFullRow));
@@ -3412,6 +3430,10 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             hipLaunchKernelGGL(k_mg_pweights<1>, g, dim3(kMgT), 0, c->stream, lv_args(F), F.W);
             hipLaunchKernelGGL(k_mg_pweights<2>, g, dim3(kMgT), 0, c->stream, lv_args(F), F.W);
             hipLaunchKernelGGL(k_mg_pweights<3>, g, dim3(kMgT), 0, c->stream, lv_args(F), F.W);
+            // the transfers read the weights in FP32; the Galerkin product below uses
+            // the same rounded values, so A_c = P^T A P holds for the P applied
+            hipLaunchKernelGGL(k_round_f32, dim3(grid_for(nsys * F.N * 8, kMgT, 4096)), dim3(kMgT), 0, c->stream,
+                               F.W, F.W32, nsys * F.N * 8);
         }
         hipLaunchKernelGGL(k_mg_rap, dim3((unsigned)((C.N + kMgT - 1) / kMgT), nsys), dim3(kMgT), 0, c->stream,
                            lv_args(F), M.opdep ? F.W : nullptr, C.U, C.nx, C.ny, C.nz);
