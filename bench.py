@@ -208,11 +208,16 @@ def main():
                          "with 1, 2, 3 illuminations and data from a 2x finer mesh; recon: the whole 3 x 30 "
                          "Algorithm 1 reconstruction at 128^3")
     ap.add_argument("--instances", type=int, default=32)
-    ap.add_argument("--train-phantoms", type=int, default=125)
-    ap.add_argument("--held-phantoms", type=int, default=13)
+    ap.add_argument("--train-phantoms", type=int, default=250,
+                    help="learned workload: training phantoms (x 8 illuminations = 2000 samples)")
+    ap.add_argument("--held-phantoms", type=int, default=25,
+                    help="learned workload: held-out phantoms (x 8 illuminations = 200 samples)")
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--rhs-block", type=int, default=16,
                     help="recon workload: right-hand sides per block solve (1 = plain, one at a time)")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="hardware queues per process (GPU_MAX_HW_QUEUES, 1-32); 0 keeps HIP's default "
+                         "(4); the batch workload's streams share these")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed",
                     help="K solves of the timed pairs: FP64 multigrid PCG, or mixed (the PCG direction in "
                          "FP32 on the tiled kernels; x, r, A p and the dots FP64)")
@@ -229,6 +234,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding by illumination is described in DESIGN.md, not built)"}))
         sys.exit(2)
+    if args.hw_queues:   # read by the HIP runtime when it initialises (before the first device call)
+        if not 1 <= args.hw_queues <= 32:
+            sys.exit("--hw-queues must be in 1..32")
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
 
     import torch
     from paper_1512_02796_amd import qpat
@@ -571,7 +580,7 @@ def bench_learned(args):
         "value": round(agg["zero_ms"] / agg["net_ms"], 4),
         "unit": "x speed-up of the forward block solve (zero start / learned start)",
         "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": round(t_train / steps * 1e3, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16/f32 net, f32/f64 solve",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16/f32 net, f64 solve",
         "data": "synthetic",
         "config": {"workload": f"learned PCG initial guess, {m.n}^3 Kuhn voxels (N={N}), {K} Gaussian "
                                f"illuminations, 4-layer 3x3x3 conv net 3-16-16-16-1, "
@@ -746,7 +755,8 @@ def bench_batch(args):
         P = make_problem("C4", n=spec["n"], n_ill=spec["n_ill"], id=spec["id"])
         m = P.mesh
         st = torch.cuda.Stream(device=dev)
-        opts = qpat.default_opts(precision=0, max_rhs_block=16, lsqr_max_steps=8)
+        opts = qpat.default_opts(precision=1 if args.precision == "mixed" else 0, max_rhs_block=16,
+                                 lsqr_max_steps=8)
         ctx = qpat.Context(d(m.coords), d(m.tets).to(torch.int32), d(m.bfaces).to(torch.int32), opts=opts,
                            stream=st)
         ctx.set_sources(d(P.phi_src))
@@ -776,11 +786,12 @@ def bench_batch(args):
     log(f"batched round of {len(ctxs)} pairs: {t_batch * 1e3:.1f} ms")
     # the same pairs one instance after another
     a = time.perf_counter()
-    for i, ctx in enumerate(ctxs):
-        ctx.jvp(S[i], JS[i])
-        ctx.vjp(T[i], JT[i])
+    for _ in range(args.steps):
+        for i, ctx in enumerate(ctxs):
+            ctx.jvp(S[i], JS[i])
+            ctx.vjp(T[i], JT[i])
     torch.cuda.synchronize()
-    t_seq = time.perf_counter() - a
+    t_seq = (time.perf_counter() - a) / args.steps
     log(f"sequential round: {t_seq * 1e3:.1f} ms")
     # PLSQR: each instance initialised at its true phantom, then batched steps
     lsqr_s = None
@@ -809,12 +820,14 @@ def bench_batch(args):
         "value": round(len(ctxs) / t_batch, 4),
         "unit": "pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(t_batch * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64 (PCG direction stored f32)",
         "data": "synthetic",
         "config": {"workload": f"{len(ctxs)} instances, n ~ U{{24..96}}^3 Kuhn voxels ({nodes} nodes in all), "
-                               f"4-12 Gaussian illuminations each, FP64 multigrid 16-RHS block PCG, rtol 1e-10, "
-                               f"one stream and host thread per instance",
-                   "instances": len(ctxs), "nodes_total": nodes},
+                               f"4-12 Gaussian illuminations each, {args.precision} multigrid 16-RHS block PCG, "
+                               f"rtol 1e-10, one stream and host thread per instance",
+                   "instances": len(ctxs), "nodes_total": nodes, "precision": args.precision,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "sequential_ms_per_round": round(t_seq * 1e3, 3),
         "batched_speedup": round(t_seq / t_batch, 3),
         "s_per_batched_lsqr_step": round(lsqr_s, 4) if lsqr_s else None,

@@ -178,7 +178,7 @@ void qpat_default_opts(qpat_opts* o) {
     o->max_rhs_block = 16;
     o->pcg_rtol = 1e-10;
     o->pcg_maxit = 20000;
-    o->prior_rtol = 1e-9;
+    o->prior_rtol = 1e-8;
     o->prior_deflate = 1;
     o->lsqr_reorth = 1;
     o->lsqr_max_steps = 64;
