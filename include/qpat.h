@@ -67,10 +67,12 @@ typedef struct {
     double  pcg_rtol;       /* K solves stop when ||b - K x||_2 <= pcg_rtol ||b||_2 (true
                                residual, FP64).                                                */
     int32_t pcg_maxit;      /* iteration cap per solve -> QPAT_ERR_NOCONV.                    */
-    double  prior_rtol;     /* same rule for M_delta solves (default 1e-9). The FP64 result's
+    double  prior_rtol;     /* same rule for M_delta solves (default 1e-8). The FP64 result's
                                own rounding bounds the attainable relative residual by about
-                               eps ||M_delta|| ||x|| / ||p||: on the 128^3 phantom a random p
-                               reaches 1e-11, an LSQR direction p stalls near 1.2e-10.      */
+                               eps ||M_delta|| ||x|| / ||p||, which depends on the problem:
+                               on the 128^3 phantom a random p reaches 1e-11 and an LSQR
+                               direction stalls near 1.2e-10; on one of the batched 24^3 -
+                               96^3 instances a direction stalls at 1.3e-9.                 */
     int32_t prior_deflate;  /* 1: the constant vector of each block (the delta-eigenvector of
                                M_delta) is solved exactly and PCG runs on its complement.    */
     int32_t lsqr_reorth;    /* 1: full reorthogonalisation of both bidiagonalisation bases.
@@ -117,7 +119,7 @@ typedef struct {
 } qpat_info;
 
 /* Fill *opts with the defaults: FP64, block 16, rtol 1e-10, maxit 20000,
- * prior_rtol 1e-9, deflation on, reorthogonalisation on with 64 steps,
+ * prior_rtol 1e-8, deflation on, reorthogonalisation on with 64 steps,
  * ru_delta 1e-3, graphs on, stencil form on lattice meshes, multigrid for M_delta. */
 void qpat_default_opts(qpat_opts* opts);
 
