@@ -74,7 +74,7 @@ MG_KERNELS = {
 # (1/8 vector), the whole stencil rows (16 FP32 values a node: the bytes of the
 # stored form); write z in FP32 (half a vector)
 MG_FUSED_UPDATE = ("k_mg_tile<6,16>", 6.5, 1, True)
-MG_FUSED_SMOOTH = ("k_mg_prolong_smooth", 1.625, 1, True)
+MG_FUSED_SMOOTH = ("k_mg_prolong_smooth<false>", 1.625, 1, True)
 
 
 def mg_kernel(key, kst, p32=False):
@@ -86,8 +86,9 @@ def mg_kernel(key, kst, p32=False):
     if key == "K_mg_update" and fused:
         n, v, o, d = MG_FUSED_UPDATE
         return ("k_mg_tile<6,16,false,true>", v - 0.5, o, d) if p32 else (n, v, o, d)
-    if key == "K_mg_smooth0" and fused:
-        return MG_FUSED_SMOOTH
+    if key == "K_mg_smooth0" and fused:   # mixed precision stages its x0 in FP32 (same HBM bytes)
+        n, v, o, d = MG_FUSED_SMOOTH
+        return ("k_mg_prolong_smooth<true>", v, o, d) if p32 else (n, v, o, d)
     n, v, o, d = MG_KERNELS[key]
     if p32 and key == "K_mg_dir_spmv":
         return ("k_mg_tile<0,16,true,true>", v - 1.0, o, d)

@@ -73,6 +73,7 @@ struct TileGeo {
     // the fused prolongation + last sweep (16 right-hand sides; even z-chunks)
     bool ps_on = false;
     int32_t ps_zc = 0, ps_items = 0, ps_blocks = 0;
+    int32_t ps_zc32 = 0, ps_items32 = 0, ps_blocks32 = 0;   // its FP32-staged form
     // the tiled 27-point kernels of the coarse levels (16 right-hand sides)
     struct Lv27 {
         bool on = false;
@@ -2154,9 +2155,11 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
 // k) and reach the node's lanes by DPP row broadcasts, which keeps the LDS
 // at two blocks per CU. Chunks start on even planes (even zc).
 // The sweep is preconditioner work: its rows are read in FP32 and z is stored
-// in FP32 (the arithmetic stays FP64); the dot products use the stored z, the
-// vector the PCG direction is built from. The PCG vectors themselves and the
-// operator of q = A p stay FP64.
+// in FP32; the dot products use the stored z, the vector the PCG direction is
+// built from. In the FP64 form x0 is staged and A x0 summed in FP64; the FP32
+// form (mixed precision) stages x0 in FP32 and sums A x0 in FP32, and forms
+// r - A x0 and z in FP64. The PCG vectors themselves and the operator of
+// q = A p stay FP64.
 constexpr int kPCX = (kTHX - 2) / 2 + 2, kPCY = (kTHY - 2) / 2 + 2;   // coarse patch of a tile
 constexpr int kPCN = kPCX * kPCY * 16;                                // its values per coarse plane
 struct PSArgs {
@@ -2186,7 +2189,41 @@ __device__ __forceinline__ double apply_kuhn16(double ua, const double* rb, int 
     return s;
 }
 
+// The FP32 form (mixed precision) stages x0 in FP32 and sums A x0 in FP32:
+// lane k of a node's 16 holds the row entries k and k + 8 as one 64-bit pair,
+// so 8 pair broadcasts deliver the diagonal, the 7 upper and the 7 lower
+// entries (pair i: entry i low, entry i + 8 high).
+__device__ __forceinline__ double row_pair(float v) {
+    const int hi = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128, 0xF, 0xF, true);   // row_ror:8
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                          static_cast<uint32_t>(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float pair_lo(double p) {
+    return __builtin_bit_cast(float, static_cast<uint32_t>(__builtin_bit_cast(uint64_t, p)));
+}
+__device__ __forceinline__ float pair_hi(double p) {
+    return __builtin_bit_cast(float, static_cast<uint32_t>(__builtin_bit_cast(uint64_t, p) >> 32));
+}
+template <int... J>
+__device__ __forceinline__ float apply_kuhn16_f32(double pr, const float* rb, int sz, int sp, int sl,
+                                                  std::integer_sequence<int, J...>) {
+    static_assert(sizeof...(J) == 7, "the 7 offset pairs of a Kuhn row");
+    const double bc[8] = {row_bcast<0>(pr), row_bcast<J + 1>(pr)...};   // pairs 0..7
+    float s = pair_lo(bc[0]) * rb[sz];
+    // offset J: upper entry 1 + J (pair J + 1, low), lower entry 8 + J (pair J, high)
+    auto term = [&](auto JJ) {
+        constexpr int j = decltype(JJ)::value;
+        constexpr int d = (kKy[j] * kTHX + kKx[j]) * 16;
+        const int up = kKz[j] ? sp : sz, lo = kKz[j] ? sl : sz;
+        s = fmaf(pair_hi(bc[j]), rb[lo - d], fmaf(pair_lo(bc[j + 1]), rb[up + d], s));
+    };
+    (term(std::integral_constant<int, J>{}), ...);
+    return s;
+}
+
+template <bool F32>
 __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
+    using RT = std::conditional_t<F32, float, double>;   // x0 as staged
     constexpr int B = 16;
     constexpr int NPF = MgTile<B>::NPF, RS = kTHN * B;   // ring slot: exactly the halo tile
     constexpr int TX = kTHX - 2, TY = kTHY - 2;
@@ -2195,10 +2232,10 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
     constexpr uint32_t SZ = sizeof(double);
     extern __shared__ __align__(16) unsigned char mg_smem[];
     __shared__ double sm[(kTT / 64) * 16];
-    double* ring = reinterpret_cast<double*>(mg_smem);   // [3][RS]: x0 of the halo nodes, [node][16]
-    double* dring = ring + 3 * RS;                        // [3][kTHN]: 1 / a_ii of the halo nodes
-    double* cring = dring + 3 * kTHN;                     // [2][kPCN]: coarse planes, slot Z & 1
-    double* rint = cring + 2 * kPCN;                      // [2][TX TY B]: r of the tile's own nodes, slot p & 1
+    double* dring = reinterpret_cast<double*>(mg_smem);   // [3][kTHN]: 1 / a_ii of the halo nodes
+    double* cring = dring + 3 * kTHN;                      // [2][kPCN]: coarse planes, slot Z & 1
+    double* rint = cring + 2 * kPCN;                       // [2][TX TY B]: r of the tile's own nodes, slot p & 1
+    RT* ring = reinterpret_cast<RT*>(rint + 2 * TX * TY * B);   // [3][RS]: x0 of the halo nodes, [node][16]
     const int tid = threadIdx.x, k = tid % B;
     bool any = false;
     for (int j = 0; j < B; ++j) any = any || g.sc[j].active != 0;
@@ -2218,7 +2255,8 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
         const int nl = (tid + u * kTT) / B;
         oc[u] = nl < TX * TY ? (nl / TX + 1) * kTHX + nl % TX + 1 : kTHX + 1;
     }
-    double fr[NPF], dd = 0.0, cv[NC];
+    double fr[NPF], dd = 0.0, cv[NC], cy[NPF];
+    bool cy_ok = false;   // cy holds coarse plane (pl + 1) / 2 of the last staged plane pl
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     const int32_t xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
     const int32_t wx = (g.items + 7) / 8;
@@ -2229,7 +2267,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
         const int32_t x0 = (t2 % g.tiles_x) * TX, y0 = (t2 / g.tiles_x) * TY;
         const int32_t zb = ch * g.zc, ze = min(zb + g.zc, nz);   // zb even
         const int32_t cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1;        // the patch's first coarse column, row
-        uint32_t fo[NPF], oo[NO], o4[NO], dof = kOut, co[NC];
+        uint32_t fo[NPF], o4[NO], dof = kOut;
 #pragma unroll
         for (int u = 0; u < NPF; ++u) {
             const int nl = (tid + u * kTT) / B;
@@ -2241,20 +2279,20 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
         for (int u = 0; u < NO; ++u) {
             const int nl = (tid + u * kTT) / B;
             const int ox = x0 + nl % TX, oy = y0 + nl / TX;
-            oo[u] = nl < TX * TY && ox < nx && oy < ny ? (static_cast<uint32_t>(oy * nx + ox) * B + k) * SZ : kOut;
-            o4[u] = oo[u] == kOut ? kOut : oo[u] / 2;   // the same element of an FP32 [N][16] array
+            // the element's byte offset in an FP32 [N][16] array
+            o4[u] = nl < TX * TY && ox < nx && oy < ny ? (static_cast<uint32_t>(oy * nx + ox) * B + k) * 4u : kOut;
         }
         if (tid < kTHN) {
             const int gx = x0 - 1 + tid % kTHX, gy = y0 - 1 + tid / kTHX;
             if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) dof = static_cast<uint32_t>(gy * nx + gx) * SZ;
         }
-#pragma unroll
-        for (int u = 0; u < NC; ++u) {
+        // the patch's coarse values of this thread (offsets formed at each load)
+        auto coarse_off = [&](int u) {
             const int e = tid + u * kTT, cn = e / B;
             const int X = cx0 + cn % kPCX, Y = cy0 + cn / kPCX;
-            co[u] = e < kPCN && X >= 0 && X < g.cx && Y >= 0 && Y < g.cy
-                        ? (static_cast<uint32_t>(Y * g.cx + X) * B + (e % B)) * SZ : kOut;
-        }
+            return e < kPCN && X >= 0 && X < g.cx && Y >= 0 && Y < g.cy
+                       ? (static_cast<uint32_t>(Y * g.cx + X) * B + (e % B)) * SZ : kOut;
+        };
         // fine plane p: r and 1/a_ii; odd p also the coarse plane (p + 1) / 2
         auto fetch = [&](int pl) {
             const auto br = plane(g.r, pl, nz, nxy * B, pv), bd = plane(g.dinv, pl, nz, nxy, pd);
@@ -2264,13 +2302,13 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
             if (pl & 1) {
                 const auto bc = plane(g.xc, (pl + 1) / 2, g.cz, cxy * B, pc);
 #pragma unroll
-                for (int u = 0; u < NC; ++u) cv[u] = bload<double>(bc, co[u]);
+                for (int u = 0; u < NC; ++u) cv[u] = bload<double>(bc, coarse_off(u));
             }
         };
         auto load_coarse = [&](int Z) {
             const auto bc = plane(g.xc, Z, g.cz, cxy * B, pc);
 #pragma unroll
-            for (int u = 0; u < NC; ++u) cv[u] = bload<double>(bc, co[u]);
+            for (int u = 0; u < NC; ++u) cv[u] = bload<double>(bc, coarse_off(u));
         };
         auto put_coarse = [&](int Z) {   // coarse plane Z to its slot
 #pragma unroll
@@ -2280,44 +2318,52 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
         auto put_d = [&](int sl) {
             if (tid < kTHN) dring[sl * kTHN + tid] = dd;
         };
-        // x0 of fine plane pl into ring slot sl (its 1/a_ii already in dring[sl])
+        // x0 of fine plane pl into ring slot sl (its 1/a_ii already in dring[sl]),
+        // with the r of the tile's own nodes (the sweep's b) into rint
         auto store = [&](int sl, int pl) {
             const bool pin = pl >= 0 && pl < nz;
             const int z0 = pl >> 1, z1 = (pl + 1) >> 1;
             const double wz1 = (pl & 1) ? 0.5 : 0.0, wz0 = 1.0 - wz1;
             const double* c0 = cring + (z0 & 1) * kPCN + k;
             const double* c1 = cring + (z1 & 1) * kPCN + k;
-            // two passes over the thread's own elements (no barrier between them):
-            // w D^{-1} r from the registers, then P x1 added in a rolled loop that
-            // keeps one element's coarse reads live at a time
+            // the bilinear value of coarse plane (pl + 1) / 2 at each element is
+            // kept in cy: an odd plane's upper coarse plane is the next even
+            // plane's own, so each coarse plane is interpolated once per item
 #pragma unroll
             for (int u = 0; u < NPF; ++u) {
                 const int e = tid + u * kTT, nl = e / B;
                 if (e >= RS) continue;
-                ring[sl * RS + e] = pin && fo[u] != kOut ? w * dring[sl * kTHN + nl] * fr[u] : 0.0;
-                const int lx = nl % kTHX - 1, ly = nl / kTHX - 1;   // the sweep's b: r of the tile's own nodes
+                const int lx = nl % kTHX - 1, ly = nl / kTHX - 1;
                 if (lx >= 0 && lx < TX && ly >= 0 && ly < TY) rint[(pl & 1) * (TX * TY * B) + (ly * TX + lx) * B + k] = fr[u];
+                double v = 0.0;
+                if (pin && fo[u] != kOut) {   // inside the halo tile and the grid
+                    v = w * dring[sl * kTHN + nl] * fr[u];
+                    const int gx = x0 - 1 + nl % kTHX, gy = y0 - 1 + nl / kTHX;
+                    const int o = (((gy >> 1) - cy0) * kPCX + (gx >> 1) - cx0) * B;
+                    const int dx = (gx & 1) ? B : 0, dy = (gy & 1) ? kPCX * B : 0;
+                    // trilinear weights are 1 or 1/2 per axis: with the even-parity
+                    // neighbour read twice, every case is a quarter of a four-term
+                    // sum (scaling by powers of two is exact)
+                    auto bil = [&](const double* cp) {
+                        const double* q = cp + o;
+                        return 0.25 * ((q[0] + q[dx]) + (q[dy] + q[dy + dx]));
+                    };
+                    double b0;
+                    if (cy_ok) b0 = cy[u];
+                    else b0 = bil(c0);
+                    if (pl & 1) {   // odd planes lie halfway between two coarse planes
+                        const double b1 = bil(c1);
+                        v = fma(wz1, b1, fma(wz0, b0, v));
+                        cy[u] = b1;
+                    } else {        // even planes on one (weight 1: fma(1, a, b) = a + b exactly)
+                        v += b0;
+                        cy[u] = b0;
+                    }
+                }
+                ring[sl * RS + e] = static_cast<RT>(v);
+                __builtin_amdgcn_sched_barrier(0);   // one element's coarse reads live at a time
             }
-            if (!pin) return;
-#pragma unroll 1
-            for (int u = 0; u < NPF; ++u) {
-                const int nl = (tid + u * kTT) / B;
-                const int gx = x0 - 1 + nl % kTHX, gy = y0 - 1 + nl / kTHX;
-                if (nl >= kTHN || gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
-                const int o = (((gy >> 1) - cy0) * kPCX + (gx >> 1) - cx0) * B;
-                const int dx = (gx & 1) ? B : 0, dy = (gy & 1) ? kPCX * B : 0;
-                const double wx1 = dx ? 0.5 : 0.0, wx0 = 1.0 - wx1;
-                const double wy1 = dy ? 0.5 : 0.0, wy0 = 1.0 - wy1;
-                auto bil = [&](const double* cp) {
-                    const double* q = cp + o;
-                    return wy0 * (wx0 * q[0] + wx1 * q[dx]) + wy1 * (wx0 * q[dy] + wx1 * q[dy + dx]);
-                };
-                double& rv = ring[sl * RS + tid + u * kTT];
-                if (pl & 1)   // odd planes lie halfway between two coarse planes
-                    rv = fma(wz1, bil(c1), fma(wz0, bil(c0), rv));
-                else          // even planes on one (weight 1: fma(1, a, b) = a + b exactly)
-                    rv += bil(c0);
-            }
+            cy_ok = pin;
         };
         auto step = [&](int z, auto SZ0, auto SP0, auto SL0) {
             constexpr int sz = decltype(SZ0)::value, sp = decltype(SP0)::value, sl = decltype(SL0)::value;
@@ -2332,14 +2378,19 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
 #pragma unroll
             for (int u = 0; u < NO; ++u) {
                 if (tid + u * kTT >= TX * TY * B) continue;   // whole waves past the tile skip
-                const double* rb = ring + oc[u] * B + k;
-                const double ax = apply_kuhn16(static_cast<double>(ua32[u]), rb, sz * RS, sp * RS, sl * RS,
-                                               std::make_integer_sequence<int, 7>{});
+                const RT* rb = ring + oc[u] * B + k;
+                double ax;
+                if constexpr (F32)
+                    ax = apply_kuhn16_f32(row_pair(ua32[u]), rb, sz * RS, sp * RS, sl * RS,
+                                          std::make_integer_sequence<int, 7>{});
+                else
+                    ax = apply_kuhn16(static_cast<double>(ua32[u]), rb, sz * RS, sp * RS, sl * RS,
+                                      std::make_integer_sequence<int, 7>{});
                 const double xc = rb[sz * RS];
                 const double bcu = rint[(z & 1) * (TX * TY * B) + tid + u * kTT];
                 const float o32 = static_cast<float>(xc + w * dring[sz * kTHN + oc[u]] * (bcu - ax));
                 const double o = static_cast<double>(o32);
-                const bool in = act && oo[u] != kOut;
+                const bool in = act && o4[u] != kOut;
                 a0 += in ? bcu * o : 0.0;
                 a1 += in ? o : 0.0;
                 a2 += in ? bcu : 0.0;
@@ -2352,6 +2403,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
             }
             __syncthreads();
         };
+        cy_ok = false;
         load_coarse(zb / 2 - 1);   // staging plane zb - 1 needs coarse planes zb/2 - 1 and zb/2
         put_coarse(zb / 2 - 1);
         fetch(zb - 1);             // odd: also coarse plane zb / 2
@@ -2393,7 +2445,9 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
     out_sum(a1, 2);
     out_sum(a2, 3);
 }
-constexpr size_t kPSLds = (size_t)(3 * kTHN * 16 + 3 * kTHN + 2 * kPCN + 2 * (kTHX - 2) * (kTHY - 2) * 16) * sizeof(double);
+template <bool F32>
+constexpr size_t kPSLds = (size_t)(3 * kTHN + 2 * kPCN + 2 * (kTHX - 2) * (kTHY - 2) * 16) * sizeof(double) +
+                          (size_t)3 * kTHN * 16 * (F32 ? sizeof(float) : sizeof(double));
 
 inline LvArgs lv_args(const MgLevel& L) {
     LvArgs a;
@@ -2550,7 +2604,8 @@ void launch_tile27(const MgState& M, const TileGeo& t, int l, hipStream_t st, co
 inline bool tiled27(const TileGeo& t, int l) { return l >= 1 && l < kMgMaxLevels && t.t27[l].on; }
 
 // level 0: z = x0 + w D^{-1} (r - A x0), x0 = w D^{-1} r + P x1 (fused, 16 right-hand sides)
-inline void launch_ps(const MgState& M, const TileGeo& t, hipStream_t st, const double* r, const double* x1, double* z) {
+inline void launch_ps(const MgState& M, const TileGeo& t, hipStream_t st, const double* r, const double* x1, double* z,
+                      bool f32) {
     const MgLevel& L = M.lv[0];
     const MgLevel& C = M.lv[1];
     PSArgs g;
@@ -2562,8 +2617,8 @@ inline void launch_ps(const MgState& M, const TileGeo& t, hipStream_t st, const 
     g.cz = C.nz;
     g.tiles_x = t.tiles_x;
     g.tiles_y = t.tiles_y;
-    g.zc = t.ps_zc;
-    g.items = t.ps_items;
+    g.zc = f32 ? t.ps_zc32 : t.ps_zc;
+    g.items = f32 ? t.ps_items32 : t.ps_items;
     g.Uf = L.Ufk32;
     g.r = r;
     g.xc = x1;
@@ -2572,7 +2627,10 @@ inline void launch_ps(const MgState& M, const TileGeo& t, hipStream_t st, const 
     g.z = reinterpret_cast<float*>(z);   // FP32 in the double buffer's first half
     g.parts = M.parts;
     g.sc = M.sc;
-    hipLaunchKernelGGL(k_mg_prolong_smooth, dim3(t.ps_blocks), dim3(kTT), kPSLds, st, g);
+    if (f32)
+        hipLaunchKernelGGL(k_mg_prolong_smooth<true>, dim3(t.ps_blocks32), dim3(kTT), kPSLds<true>, st, g);
+    else
+        hipLaunchKernelGGL(k_mg_prolong_smooth<false>, dim3(t.ps_blocks), dim3(kTT), kPSLds<false>, st, g);
 }
 
 // level l's residual to level l + 1's b and first sweep xc (tiled; trilinear)
@@ -2686,25 +2744,31 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
         }
         if constexpr (B == 16) {   // the fused prolongation + last sweep: the same tiles, even chunks
             if (L.Uf && L.Ufk32) {
-                const void* fps = reinterpret_cast<const void*>(&k_mg_prolong_smooth);
-                QPAT_HIP(c, hipFuncSetAttribute(fps, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPSLds));
-                int occ_ps = 1;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_ps, fps, kTT, kPSLds) != hipSuccess) occ_ps = 1;
-                const int64_t conc_ps = (int64_t)std::max(occ_ps, 1) * (cus / 8);
-                int64_t best_ps = -1, zc_ps = L.nz + (L.nz & 1);
-                for (int64_t nch = 1; nch <= L.nz; ++nch) {
-                    int64_t zc = (L.nz + nch - 1) / nch;
-                    zc += zc & 1;
-                    const int64_t items = tx * ty * ((L.nz + zc - 1) / zc);
-                    const int64_t cost = (((items + 7) / 8 + conc_ps - 1) / conc_ps) * (zc + 2);
-                    if (best_ps < 0 || cost < best_ps) {
-                        best_ps = cost;
-                        zc_ps = zc;
+                for (const bool f32 : {false, true}) {
+                    const void* fps = f32 ? reinterpret_cast<const void*>(&k_mg_prolong_smooth<true>)
+                                          : reinterpret_cast<const void*>(&k_mg_prolong_smooth<false>);
+                    const size_t lds = f32 ? kPSLds<true> : kPSLds<false>;
+                    QPAT_HIP(c, hipFuncSetAttribute(fps, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                    int occ_ps = 1;
+                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_ps, fps, kTT, lds) != hipSuccess) occ_ps = 1;
+                    const int64_t conc_ps = (int64_t)std::max(occ_ps, 1) * (cus / 8);
+                    int64_t best_ps = -1, zc_ps = L.nz + (L.nz & 1);
+                    for (int64_t nch = 1; nch <= L.nz; ++nch) {
+                        int64_t zc = (L.nz + nch - 1) / nch;
+                        zc += zc & 1;
+                        const int64_t items = tx * ty * ((L.nz + zc - 1) / zc);
+                        const int64_t cost = (((items + 7) / 8 + conc_ps - 1) / conc_ps) * (zc + 2);
+                        if (best_ps < 0 || cost < best_ps) {
+                            best_ps = cost;
+                            zc_ps = zc;
+                        }
                     }
+                    const int32_t items = static_cast<int32_t>(tx * ty * ((L.nz + zc_ps - 1) / zc_ps));
+                    const int32_t blocks = static_cast<int32_t>(8 * std::min<int64_t>(conc_ps, (items + 7) / 8));
+                    (f32 ? t.ps_zc32 : t.ps_zc) = static_cast<int32_t>(zc_ps);
+                    (f32 ? t.ps_items32 : t.ps_items) = items;
+                    (f32 ? t.ps_blocks32 : t.ps_blocks) = blocks;
                 }
-                t.ps_zc = static_cast<int32_t>(zc_ps);
-                t.ps_items = static_cast<int32_t>(tx * ty * ((L.nz + zc_ps - 1) / zc_ps));
-                t.ps_blocks = static_cast<int32_t>(8 * std::min<int64_t>(conc_ps, (t.ps_items + 7) / 8));
                 t.ps_on = true;
             }
         }
@@ -2762,9 +2826,10 @@ inline bool z32_path(const MgState& M, const TileGeo& tg) {
 // sweep each way the first sweep w D^{-1} r is never stored: the residual
 // kernel stages it and the prolongation recomputes it. Level 0 takes
 // 2 kMgNu - 1 ping-pong sweeps (an odd number), so z ends in level 0's t.
+// lo32 (mixed precision) stages the fused last sweep's x0 in FP32.
 template <int B>
 void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev = nullptr, const double* b0 = nullptr,
-            bool resid_done = false) {
+            bool resid_done = false, bool lo32 = false) {
     const int nl = static_cast<int>(M.lv.size());
     const bool fused0 = tg.on && kMgNu == 1;
     const double* r0 = b0 ? b0 : M.lv[0].b;   // level 0's right-hand side (the PCG residual)
@@ -2830,7 +2895,7 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         const double* bl = l == 0 ? r0 : L.b;
         if (l == 0 && z32_path<B>(M, tg)) {   // prolongation fused into the last sweep (z in FP32)
             if (ev) (void)hipEventRecord(ev[2], st);
-            launch_ps(M, tg, st, r0, xl[1], tl[0]);
+            launch_ps(M, tg, st, r0, xl[1], tl[0], lo32);
             if (ev) (void)hipEventRecord(ev[3], st);
             std::swap(xl[0], tl[0]);
             continue;
@@ -2940,7 +3005,7 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
     if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 1);
     region_solve<B>(M, a, st);
-    vcycle<B>(M, st, tg, ev ? ev + 4 : nullptr, a.r, fused_update(tg));
+    vcycle<B>(M, st, tg, ev ? ev + 4 : nullptr, a.r, fused_update(tg), p32);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 2);
 }
 
@@ -2990,7 +3055,7 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
         if (!any_active()) break;
         // first direction of a run: z = V(r) (+ Z y), p = z - c
         region_solve<B>(M, a, sm);
-        vcycle<B>(M, sm, tg);
+        vcycle<B>(M, sm, tg, nullptr, nullptr, false, a.p32 != 0 && z32_path<B>(M, tg));
         hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, sm, a, 3);
         QPAT_HIP(c, hipGetLastError());
         // Iterations run in chunks of even length between host checks. The
