@@ -1663,6 +1663,23 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                 for (int u = 0; u < NPF; ++u) dc[u] = bload<double>(bd, od[u]);
             }
             constexpr int NO = UPD ? (TX * TY * B + kTT - 1) / kTT : 1;   // output slots in use
+            // UPD: x and p of this plane's nodes, in flight during the stencil work
+            double xv[NO], pw[NO];
+            if constexpr (UPD) {
+                const auto bx = plane(g.x3, z, nxy * B, pv);
+#pragma unroll
+                for (int u = 0; u < NO; ++u) {
+                    const uint32_t o = act && tid + u * kTT < TX * TY * B ? oo[u] : kOut;
+                    xv[u] = bload_nt(bx, o);
+                    if constexpr (P32) {
+                        const auto bp = plane(reinterpret_cast<const float*>(g.p3), z, nxy * B, pv / 2);
+                        pw[u] = static_cast<double>(bload<float>(bp, o == kOut ? kOut : o / 2));
+                    } else {
+                        const auto bp = plane(g.p3, z, nxy * B, pv);
+                        pw[u] = bload_nt(bp, o);
+                    }
+                }
+            }
             // descriptors stay uniform over the wavefront (a per-lane size would
             // turn every access into a loop over the distinct values); the
             // stores of stopped right-hand sides are skipped by the branch
@@ -1747,21 +1764,10 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                 if constexpr (UPD) {   // x += alpha p on this plane's nodes, after the stencil work
                     __builtin_amdgcn_sched_barrier(0);
                     const auto bx = plane(g.x3, z, nxy * B, pv);
-                    if constexpr (P32) {
-                        const auto bp = plane(reinterpret_cast<const float*>(g.p3), z, nxy * B, pv / 2);
 #pragma unroll
-                        for (int u = 0; u < NO; ++u) {
-                            if (tid + u * kTT >= TX * TY * B) continue;
-                            const double pu = static_cast<double>(bload<float>(bp, oo[u] == kOut ? kOut : oo[u] / 2));
-                            bstore_nt(bx, oo[u], bload_nt(bx, oo[u]) + alpha * pu);
-                        }
-                    } else {
-                        const auto bp = plane(g.p3, z, nxy * B, pv);
-#pragma unroll
-                        for (int u = 0; u < NO; ++u) {
-                            if (tid + u * kTT >= TX * TY * B) continue;
-                            bstore_nt(bx, oo[u], bload_nt(bx, oo[u]) + alpha * bload_nt(bp, oo[u]));
-                        }
+                    for (int u = 0; u < NO; ++u) {
+                        if (tid + u * kTT >= TX * TY * B) continue;
+                        bstore_nt(bx, oo[u], xv[u] + alpha * pw[u]);
                     }
                 }
             }
