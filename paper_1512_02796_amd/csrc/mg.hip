@@ -279,8 +279,12 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             const int32_t lin = dx + L.nx * (dy + L.ny * dz);
             const bool up = inner || (ix + dx >= 0 && ix + dx < L.nx && iy + dy >= 0 && iy + dy < L.ny && iz + dz < L.nz);
             const bool lo = inner || (ix - dx >= 0 && ix - dx < L.nx && iy - dy >= 0 && iy - dy < L.ny && iz - dz >= 0);
-            if (up) s += U[(1 + j) * L.N + i] * vld<T>(x + (i + lin) * B);
-            if (lo) s += U[(14 + j) * L.N + i] * vld<T>(x + (i - lin) * B);
+            // loads from clamped indices and selected sums: no branch per
+            // neighbour, so all of a row's loads are in flight together
+            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + (lo ? i - lin : i) * B);
+            const double cu = U[(1 + j) * L.N + i], cl = U[(14 + j) * L.N + i];
+            s = up ? s + cu * xu : s;
+            s = lo ? s + cl * xl : s;
         }
         return s;
     } else if constexpr (KIND == 5) {   // the kind-3 rows in FP32 (a preconditioner's operator)
@@ -296,8 +300,9 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             const int32_t lin = dx + L.nx * (dy + L.ny * dz);
             const bool up = inner || (ix + dx < L.nx && iy + dy < L.ny && iz + dz < L.nz);
             const bool lo = inner || (ix - dx >= 0 && iy - dy >= 0 && iz - dz >= 0);
-            if (up) s += u[1 + j] * vld<T>(x + (i + lin) * B);
-            if (lo) s += u[8 + j] * vld<T>(x + (i - lin) * B);
+            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + (lo ? i - lin : i) * B);
+            s = up ? s + u[1 + j] * xu : s;
+            s = lo ? s + u[8 + j] * xl : s;
         }
         return s;
     } else if constexpr (KIND == 3) {
@@ -312,8 +317,9 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             const int32_t lin = dx + L.nx * (dy + L.ny * dz);
             const bool up = inner || (ix + dx < L.nx && iy + dy < L.ny && iz + dz < L.nz);
             const bool lo = inner || (ix - dx >= 0 && iy - dy >= 0 && iz - dz >= 0);
-            if (up) s += u[1 + j] * vld<T>(x + (i + lin) * B);
-            if (lo) s += u[8 + j] * vld<T>(x + (i - lin) * B);
+            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + (lo ? i - lin : i) * B);
+            s = up ? s + u[1 + j] * xu : s;
+            s = lo ? s + u[8 + j] * xl : s;
         }
         return s;
     } else {
@@ -338,8 +344,11 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             const int32_t lin = dx + L.nx * (dy + L.ny * dz);
             const bool up = inner || (ix + dx >= 0 && ix + dx < L.nx && iy + dy >= 0 && iy + dy < L.ny && iz + dz < L.nz);
             const bool lo = inner || (ix - dx >= 0 && ix - dx < L.nx && iy - dy >= 0 && iy - dy < L.ny && iz - dz >= 0);
-            if (up) s += u[j + 1] * vld<T>(x + (i + lin) * B);
-            if (lo) s += U[(i - lin) * M1 + j + 1] * vld<T>(x + (i - lin) * B);
+            const int32_t il = lo ? i - lin : i;
+            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + il * B);
+            const double cl = U[il * M1 + j + 1];
+            s = up ? s + u[j + 1] * xu : s;
+            s = lo ? s + cl * xl : s;
         }
         return s;
     }
@@ -802,9 +811,11 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
 #pragma unroll
                     for (int dx = 0; dx < 3; ++dx) {
                         double wgt = wyz * wx[dx];
-                        if constexpr (OPW)   // I is corner (d == 0 per axis) of fine node 2 I + d - 1
-                            if (wgt != 0.0)
-                                wgt = static_cast<double>(Ws[((dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)) * Nf + (row + fx[dx])]);
+                        if constexpr (OPW) {   // I is corner (d == 0 per axis) of fine node 2 I + d - 1
+                            // (the clamped index is always a lattice node: load, then select)
+                            const double wo = static_cast<double>(Ws[((dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)) * Nf + (row + fx[dx])]);
+                            wgt = wgt != 0.0 ? wo : 0.0;
+                        }
                         s += wgt * vld<T>(rs + (row + fx[dx]) * B);
                     }
                 }
@@ -1663,23 +1674,6 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                 for (int u = 0; u < NPF; ++u) dc[u] = bload<double>(bd, od[u]);
             }
             constexpr int NO = UPD ? (TX * TY * B + kTT - 1) / kTT : 1;   // output slots in use
-            // UPD: x and p of this plane's nodes, in flight during the stencil work
-            double xv[NO], pw[NO];
-            if constexpr (UPD) {
-                const auto bx = plane(g.x3, z, nxy * B, pv);
-#pragma unroll
-                for (int u = 0; u < NO; ++u) {
-                    const uint32_t o = act && tid + u * kTT < TX * TY * B ? oo[u] : kOut;
-                    xv[u] = bload_nt(bx, o);
-                    if constexpr (P32) {
-                        const auto bp = plane(reinterpret_cast<const float*>(g.p3), z, nxy * B, pv / 2);
-                        pw[u] = static_cast<double>(bload<float>(bp, o == kOut ? kOut : o / 2));
-                    } else {
-                        const auto bp = plane(g.p3, z, nxy * B, pv);
-                        pw[u] = bload_nt(bp, o);
-                    }
-                }
-            }
             // descriptors stay uniform over the wavefront (a per-lane size would
             // turn every access into a loop over the distinct values); the
             // stores of stopped right-hand sides are skipped by the branch
@@ -1764,10 +1758,21 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                 if constexpr (UPD) {   // x += alpha p on this plane's nodes, after the stencil work
                     __builtin_amdgcn_sched_barrier(0);
                     const auto bx = plane(g.x3, z, nxy * B, pv);
+                    if constexpr (P32) {
+                        const auto bp = plane(reinterpret_cast<const float*>(g.p3), z, nxy * B, pv / 2);
 #pragma unroll
-                    for (int u = 0; u < NO; ++u) {
-                        if (tid + u * kTT >= TX * TY * B) continue;
-                        bstore_nt(bx, oo[u], xv[u] + alpha * pw[u]);
+                        for (int u = 0; u < NO; ++u) {
+                            if (tid + u * kTT >= TX * TY * B) continue;
+                            const double pu = static_cast<double>(bload<float>(bp, oo[u] == kOut ? kOut : oo[u] / 2));
+                            bstore_nt(bx, oo[u], bload_nt(bx, oo[u]) + alpha * pu);
+                        }
+                    } else {
+                        const auto bp = plane(g.p3, z, nxy * B, pv);
+#pragma unroll
+                        for (int u = 0; u < NO; ++u) {
+                            if (tid + u * kTT >= TX * TY * B) continue;
+                            bstore_nt(bx, oo[u], bload_nt(bx, oo[u]) + alpha * bload_nt(bp, oo[u]));
+                        }
                     }
                 }
             }
