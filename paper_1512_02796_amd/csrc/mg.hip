@@ -811,11 +811,9 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
 #pragma unroll
                     for (int dx = 0; dx < 3; ++dx) {
                         double wgt = wyz * wx[dx];
-                        if constexpr (OPW) {   // I is corner (d == 0 per axis) of fine node 2 I + d - 1
-                            // (the clamped index is always a lattice node: load, then select)
-                            const double wo = static_cast<double>(Ws[((dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)) * Nf + (row + fx[dx])]);
-                            wgt = wgt != 0.0 ? wo : 0.0;
-                        }
+                        if constexpr (OPW)   // I is corner (d == 0 per axis) of fine node 2 I + d - 1
+                            if (wgt != 0.0)
+                                wgt = static_cast<double>(Ws[((dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)) * Nf + (row + fx[dx])]);
                         s += wgt * vld<T>(rs + (row + fx[dx]) * B);
                     }
                 }
