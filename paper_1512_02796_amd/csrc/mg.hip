@@ -801,6 +801,19 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
                 fy[d] = min(max(gy, 0), ny - 1);
                 fz[d] = min(max(gz, 0), nz - 1);
             }
+            // the 27 fine values first (clamped indices, all loads in flight
+            // together: the tiny levels are latency-bound), then the sum in
+            // the order dz, dy, dx
+            T fv[27];
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const int32_t row = nx * (fy[dy] + ny * fz[dz]);
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) fv[(dz * 3 + dy) * 3 + dx] = vld<T>(rs + (row + fx[dx]) * B);
+                }
+            if constexpr (!OPW) __builtin_amdgcn_sched_barrier(0);
             T s = 0.0;
 #pragma unroll
             for (int dz = 0; dz < 3; ++dz)
@@ -814,7 +827,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
                         if constexpr (OPW)   // I is corner (d == 0 per axis) of fine node 2 I + d - 1
                             if (wgt != 0.0)
                                 wgt = static_cast<double>(Ws[((dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)) * Nf + (row + fx[dx])]);
-                        s += wgt * vld<T>(rs + (row + fx[dx]) * B);
+                        s += wgt * fv[(dz * 3 + dy) * 3 + dx];
                     }
                 }
             vst<T>(bc + oc + I * B, s);
@@ -847,6 +860,9 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
             const int32_t jx[2] = {sx.j0, sx.j1}, jy[2] = {sy.j0, sy.j1}, jz[2] = {sz.j0, sz.j1};
             const double wx[2] = {sx.w0, sx.w1}, wy[2] = {sy.w0, sy.w1}, wz[2] = {sz.w0, sz.w1};
             T s = FIRST ? (w * dinv[i]) * vld<T>(bs + i * B) : vld<T>(xf + i * B);
+            // the 8 coarse values (and weights) first, all loads in flight together
+            T cv[8];
+            double wgt[8];
 #pragma unroll
             for (int c2 = 0; c2 < 2; ++c2)
 #pragma unroll
@@ -857,14 +873,17 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
                     for (int a2 = 0; a2 < 2; ++a2) {
                         // corner (a2, b2, c2) from J0 = (ix/2, iy/2, iz/2); Span
                         // clamps the index of a zero-weight corner
-                        double wgt;
+                        const int cn = a2 + 2 * b2 + 4 * c2;
                         if constexpr (OPW)
-                            wgt = static_cast<double>(Ws[(a2 + 2 * b2 + 4 * c2) * Nf + i]);
+                            wgt[cn] = static_cast<double>(Ws[cn * Nf + i]);
                         else
-                            wgt = wyz * wx[a2];
-                        s += wgt * vld<T>(xs + (row + jx[a2]) * B);
+                            wgt[cn] = wyz * wx[a2];
+                        cv[cn] = vld<T>(xs + (row + jx[a2]) * B);
                     }
                 }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int cn = 0; cn < 8; ++cn) s += wgt[cn] * cv[cn];
             vst<T>(xf + i * B, s);
         });
     }
@@ -1047,6 +1066,30 @@ __device__ double red(const double* parts, int nb, int lane, int slot, double* s
     return group_sum<1>(s, sm);
 }
 
+// the same sums of three slots of one lane in one pass (each in red's order)
+__device__ void red3(const double* parts, int nb, int lane, const int (&slot)[3], double* sm3, double (&out)[3]) {
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s[c] += parts[(lane * 4 + slot[c]) * kMgBlocks + b];
+    const int ln = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) s[c] += __shfl_xor(s[c], off);
+        if (ln == 0) sm3[wave * 3 + c] = s[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double t = 0.0;
+        if (threadIdx.x == 0)
+            for (int w = 0; w < kMgT / 64; ++w) t += sm3[w * 3 + c];
+        out[c] = t;
+    }
+    __syncthreads();
+}
+
 // one block per lane (blockIdx.y). phase 0: alpha = rz / pq; phase 1: rr,
 // convergence, iteration count; phase 2 (after the V-cycle): c, beta, rz;
 // phase 3: start of a run (after its first V-cycle): c, rz, beta = 0
@@ -1074,9 +1117,11 @@ __global__ __launch_bounds__(kMgT) void k_mgp_scalars(PcgMg a, int phase) {
             }
         }
     } else {
-        double rz = red(a.parts, a.nb, lane, 0, sm);
-        const double z1 = red(a.parts, a.nb, lane, 2, sm);
-        const double r1 = red(a.parts, a.nb, lane, 3, sm);
+        __shared__ double sm3[(kMgT / 64) * 3];
+        double v[3];
+        red3(a.parts, a.nb, lane, {0, 2, 3}, sm3, v);
+        double rz = v[0];
+        const double z1 = v[1], r1 = v[2];
         if (threadIdx.x == 0) {
             // z = V(r) + Z y; with deflation its mean is mean(V(r)) + ybar, and the
             // direction takes (V(r) - mean V(r)) + (Z y - ybar): the large, nearly
@@ -1107,11 +1152,21 @@ __global__ __launch_bounds__(kMgT) void k_reg_rsum(PcgMg a, double* __restrict__
         for (int j = 0; j < kRegMax; ++j) acc[j] = 0.0;
         const int32_t* rg = a.reg + sys * a.L.N;
         const double* r = a.r + sys * a.L.N;
-        QPAT_MG_ELEMS(i, a.L.N) {
-            const int32_t g = rg[i];
-            const double v = r[i];
+        // grid-stride order, four nodes' loads in flight per trip
+        const int64_t n = a.L.N, stride = (int64_t)gridDim.x * kMgT;
+        for (int64_t i0 = blockIdx.x * (int64_t)kMgT + threadIdx.x; i0 < n; i0 += 4 * stride) {
+            int32_t g[4];
+            double v[4];
 #pragma unroll
-            for (int j = 0; j < kRegMax; ++j) acc[j] += g == j ? v : 0.0;
+            for (int q = 0; q < 4; ++q) {
+                const int64_t i = i0 + q * stride;
+                g[q] = i < n ? rg[i] : -1;
+                v[q] = i < n ? r[i] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int j = 0; j < kRegMax; ++j) acc[j] += g[q] == j ? v[q] : 0.0;
         }
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -1138,18 +1193,35 @@ __global__ __launch_bounds__(kMgT) void k_reg_rsum(PcgMg a, double* __restrict__
 __global__ __launch_bounds__(kMgT) void k_reg_solve(PcgMg a, const double* __restrict__ rparts,
                                                     const double* __restrict__ einv, const double* __restrict__ rsize,
                                                     double* __restrict__ ry, double* __restrict__ rcorr) {
-    __shared__ double zr[kRegMax], yy[kRegMax], sm[kMgT / 64];
+    __shared__ double zr[kRegMax], yy[kRegMax];
     const int sys = blockIdx.y;
     if (!a.sc[sys].active) return;
     const int t = threadIdx.x;
-    for (int j = 0; j < a.kreg; ++j) {   // fixed-order block sums of the partials
-        double s = 0.0;
-        for (int b = t; b < a.nb; b += kMgT) s += rparts[(sys * kRegMax + j) * kMgBlocks + b];
-        s = group_sum<1>(s, sm);
-        if (t == 0) zr[j] = s;
+    {   // fixed-order block sums of the partials, every region in one pass
+        // (slots of regions past kreg hold zeros)
+        __shared__ double wsum[(kMgT / 64) * kRegMax];
+        double s[kRegMax];
+#pragma unroll
+        for (int j = 0; j < kRegMax; ++j) s[j] = 0.0;
+        for (int b = t; b < a.nb; b += kMgT)
+#pragma unroll
+            for (int j = 0; j < kRegMax; ++j) s[j] += rparts[(sys * kRegMax + j) * kMgBlocks + b];
+        const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+        for (int j = 0; j < kRegMax; ++j) {
+            double v = s[j];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) wsum[wave * kRegMax + j] = v;
+        }
+        __syncthreads();
+        if (t < kRegMax) {
+            double v = 0.0;
+            for (int w = 0; w < kMgT / 64; ++w) v += wsum[w * kRegMax + t];
+            zr[t] = t < a.kreg ? v : 0.0;
+        }
+        __syncthreads();
     }
-    if (t >= a.kreg && t < kRegMax) zr[t] = 0.0;
-    __syncthreads();
     if (t < kRegMax) {
         double y = 0.0;
         for (int b = 0; b < a.kreg; ++b) y += einv[(sys * kRegMax + t) * kRegMax + b] * zr[b];
