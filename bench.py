@@ -114,7 +114,8 @@ def mg_levels(nx, ny, nz, dense_max=1000, coarse_axis=5):
     return [int(np.prod(v)) for v in lv]
 
 
-def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled27_min=16384, p32=False):
+def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled27_min=16384, p32=False,
+                           voxel=True):
     """Algorithmic HBM bytes of one J s + J^T t pair on the multigrid path: every
     kernel's reads and writes counted once (FP64 vectors of N B values; in
     FP32 the finest level's residual for the restriction, the V-cycle's output
@@ -131,10 +132,14 @@ def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled2
     (the old p and the new p in the direction kernel, p in the update).
     Per solve: start 3 V_0, the first V-cycle's finest residual 1.5 V_0 + rows,
     one V-cycle more than iterations, the final true residual 3 V_0 + rows.
-    Jacobian kernels per block: J s -- dK(s) rows from the elements (tets 16 B,
-    class 1 B per element; 80 B a node), the stencil product 2 V_0 + rows, the
-    output 3 V_0; J^T t -- right-hand side 2 V_0, element sums 2 V_0 + 57 B a
-    tetrahedron, gather 2 V_0 + 56 B a tetrahedron, output 48 B a node.
+    Jacobian kernels per block: J s -- dK(s) rows (80 B a node: its two
+    coefficients read, 8 row entries written; the element form also reads 17 B
+    a tetrahedron of connectivity and geometry class), the stencil product
+    2 V_0 + rows, the output 3 V_0; J^T t -- right-hand side 2 V_0, then in the
+    voxel form (Kuhn lattice of equal voxels, N_v = E / 6) the voxel sums
+    2 V_0 + 128 B a voxel and the gather 128 B a voxel + 2 V_0, in the element
+    form element sums 2 V_0 + 57 B a tetrahedron and gather 2 V_0 + 56 B a
+    tetrahedron; output 48 B a node.
     Returns (total bytes, dict of the parts)."""
     vb = 8 * B
     V = [n * vb for n in levels]
@@ -155,8 +160,13 @@ def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled2
     def solve(it):
         return 3 * V[0] + 1.5 * V[0] + rows0 + d0 + (it + 1) * vc + it * pcg_it + 3 * V[0] + rows0
 
-    jv = blocks * (80 * N + 17 * E + 2 * V[0] + rows0 + 3 * V[0])
-    jt = blocks * (2 * V[0] + 2 * V[0] + 57 * E + 2 * V[0] + 56 * E) + 48 * N
+    if voxel:
+        nv = E // 6
+        jv = blocks * (80 * N + 2 * V[0] + rows0 + 3 * V[0])
+        jt = blocks * (2 * V[0] + 2 * V[0] + 128 * nv) + 128 * nv + 2 * V[0] + 48 * N
+    else:
+        jv = blocks * (80 * N + 17 * E + 2 * V[0] + rows0 + 3 * V[0])
+        jt = blocks * (2 * V[0] + 2 * V[0] + 57 * E + 2 * V[0] + 56 * E) + 48 * N
     parts = {"vcycle_per_iter": vc, "pcg_per_iter": pcg_it, "tangent_solves": blocks * solve(iters_tan),
              "adjoint_solves": blocks * solve(iters_adj), "jacobian_kernels": jv + jt}
     return parts["tangent_solves"] + parts["adjoint_solves"] + parts["jacobian_kernels"], parts

@@ -163,6 +163,21 @@ qpat_status lattice_setup(qpat_ctx* c, const double* coords) {
     QPAT_HIP(c, hipMemsetAsync(c->MU64, 0, 2 * U * sizeof(double), c->stream));
     lat.on = true;
     L = lat;
+    // the Kuhn pattern with equal voxels: spacings from nodes 0, 1, nx and nx ny
+    // (the voxel form of the Jacobian kernels is checked against the element
+    // form before its first use)
+    c->vox = -1;
+    if (lat.m == 7) {
+        double p[4][3];
+        const int64_t at[4] = {0, 1, nx, nxy};
+        for (int q = 0; q < 4; ++q)
+            QPAT_HIP(c, hipMemcpyAsync(p[q], coords + 3 * at[q], 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        QPAT_HIP(c, hipStreamSynchronize(c->stream));
+        c->vox_h[0] = p[1][0] - p[0][0];
+        c->vox_h[1] = p[2][1] - p[0][1];
+        c->vox_h[2] = p[3][2] - p[0][2];
+        if (c->vox_h[0] > 0.0 && c->vox_h[1] > 0.0 && c->vox_h[2] > 0.0) c->vox = 0;
+    }
     return QPAT_OK;
 }
 

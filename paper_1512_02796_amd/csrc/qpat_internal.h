@@ -219,6 +219,10 @@ struct qpat_ctx {
     double* dKc = nullptr;         // [N][2] its coefficients kappa s1, mu s2
     double* tq = nullptr;          // [E] per-tetrahedron sums of J^T t (stiffness part)
     double* tr = nullptr;          // [E][4] per-tetrahedron sums of J^T t (mass part)
+    // voxel form of the G kernels (Kuhn lattices of equal voxels): 0 not yet
+    // checked against the element form, 1 in use, -1 not applicable
+    int32_t vox = -1;
+    double vox_h[3] = {0.0, 0.0, 0.0};   // the lattice spacings along x, y, z
 
     // LSQR
     bool lsqr_ready = false;

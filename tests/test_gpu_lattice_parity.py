@@ -96,3 +96,32 @@ def test_slab_mixed_precision_parity(slab):
         assert_close(host(outT), lin.vjp(slab["t"]), 1e-10, "slab J^T t, mixed")
     finally:
         ctx.set_opts(precision=0)
+
+
+def test_graded_lattice_products():
+    """A lattice numbering with unequal voxels (x graded): the stencil form still
+    applies, the voxel form of the G kernels (equal voxels only) must be turned
+    down by its set-up comparison with the element form, and J s, J^T t match
+    the oracle at the FP64 tolerance through 16-right-hand-side blocks."""
+    from paper_1512_02796_amd import qpat
+    from qpat_inputs import make_problem, probe_vectors
+    from gpu_util import assert_close, dev, host, oracle_of
+    P = make_problem("T8", n_ill=16)
+    m = P.mesh
+    L = float(m.coords[:, 0].max())
+    m.coords[:, 0] = L * (m.coords[:, 0] / L) ** 1.25   # monotone: the numbering stays lexicographic
+    ctx = qpat.Context(dev(m.coords), dev(m.tets, torch.int32), dev(m.bfaces, torch.int32),
+                       opts=qpat.default_opts(max_rhs_block=16))
+    ctx.set_sources(dev(P.phi_src))
+    phi = torch.empty(P.n_ill * m.N, dtype=torch.float64, device="cuda")
+    h = torch.empty_like(phi)
+    ctx.forward(dev(P.kappa), dev(P.mu), phi, h)
+    g, lin = oracle_of(P)
+    assert_close(host(phi).reshape(P.n_ill, m.N), lin.phi, 1e-10, "phi graded")
+    s, t = probe_vectors(P.cfg["id"], P.n_ill, m.N)
+    out = torch.empty(P.n_ill * m.N, dtype=torch.float64, device="cuda")
+    ctx.jvp(dev(s), out)
+    assert_close(host(out).reshape(P.n_ill, m.N), lin.jvp(s), 1e-10, "J s graded lattice")
+    outT = torch.empty(2 * m.N, dtype=torch.float64, device="cuda")
+    ctx.vjp(dev(t), outT)
+    assert_close(host(outT), lin.vjp(t), 1e-10, "J^T t graded lattice")
