@@ -482,6 +482,11 @@ def main():
                         "bytes_per_iteration": round(parts["vcycle_per_iter"] + parts["pcg_per_iter"]),
                         "jacobian_kernels_bytes": round(parts["jacobian_kernels"])}
     log("pair roofline", roofline["pair"])
+    try:   # z-chunk lengths of the tiled kernels (autotuned or the cost model's)
+        roofline["tile_schedule"] = ctx.tile_schedule(16)
+        log("tile schedule", roofline["tile_schedule"])
+    except Exception as e:   # no 16-right-hand-side tiling on this mesh
+        log("tile schedule", str(e))
 
     # ---- M_delta^{-1}'s multigrid kernels (one right-hand side per system)
     if args.lsqr_steps > 0:

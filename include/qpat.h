@@ -96,6 +96,13 @@ typedef struct {
                                meshes with the stencil form; elsewhere Jacobi-PCG); 0 =
                                Jacobi-PCG. `precision` selects the arithmetic of either.
                                Same stopping rule either way.                                */
+    int32_t autotune;       /* 1 (default): the z-chunk length of the LDS-tiled finest-level
+                               kernels of the multigrid K solves (the PCG direction, update
+                               and residual tiles; the fused prolongation + last sweep) is
+                               chosen by timing the cost model's lowest-cost candidates on the
+                               device at the first solve of a lattice size and block width,
+                               and cached for the process. 0: the cost model's choice. The
+                               results agree up to the order of the partial sums.            */
 } qpat_opts;
 
 /* Solve report of a call (host struct). The first five fields are outputs.
@@ -120,7 +127,8 @@ typedef struct {
 
 /* Fill *opts with the defaults: FP64, block 16, rtol 1e-10, maxit 20000,
  * prior_rtol 1e-8, deflation on, reorthogonalisation on with 64 steps,
- * ru_delta 1e-3, graphs on, stencil form on lattice meshes, multigrid for M_delta. */
+ * ru_delta 1e-3, graphs on, stencil form on lattice meshes, multigrid for M_delta
+ * and K, autotuned tile schedules. */
 void qpat_default_opts(qpat_opts* opts);
 
 /* Create a context for a tetrahedral P1 mesh (Sec. 3: piecewise linear
@@ -330,6 +338,15 @@ qpat_status qpat_batch(qpat_ctx* const* ctxs, int32_t n, int32_t op, const doubl
  * out[4] = stored stencil arrays per operator (diagonal + upper offsets),
  * out[5] = padded sliced-ELL entries. out: 6 int64 (host). */
 qpat_status qpat_operator_layout(const qpat_ctx* ctx, int64_t out[6]);
+
+/* The tile schedule of the multigrid K solves for blocks of B right-hand sides
+ * (B = 8 or 16), set at the first solve with that B: out[0] = 1 if the finest
+ * level is tiled, out[1] / out[2] = the z-chunk length in use / the cost
+ * model's for the direction, update and residual tiles, out[3] / out[4] and
+ * out[5] / out[6] = the same for the fused prolongation + last sweep in FP64
+ * and FP32 staging (0: not in use), out[7] = 1 if the lengths in use were
+ * picked by timing (opts.autotune). QPAT_ERR_STATE before that solve. */
+qpat_status qpat_tile_schedule(const qpat_ctx* ctx, int32_t B, int32_t out[8]);
 
 /* ---- Learned initial guess of the forward solves (extension; needs a
  * structured node lattice: node (x, y, z) has index x + nx (y + ny z)).

@@ -67,6 +67,7 @@ qpat_status check_opts(qpat_ctx* c, const qpat_opts* o) {
         return fail(c, QPAT_ERR_ARG, "operator_format must be 0 or 1");
     if (o->prior_precond != 0 && o->prior_precond != 1) return fail(c, QPAT_ERR_ARG, "prior_precond must be 0 or 1");
     if (o->pcg_precond != 0 && o->pcg_precond != 1) return fail(c, QPAT_ERR_ARG, "pcg_precond must be 0 or 1");
+    if (o->autotune != 0 && o->autotune != 1) return fail(c, QPAT_ERR_ARG, "autotune must be 0 or 1");
     return QPAT_OK;
 }
 
@@ -187,6 +188,7 @@ void qpat_default_opts(qpat_opts* o) {
     o->operator_format = 1;
     o->prior_precond = 1;
     o->pcg_precond = 1;
+    o->autotune = 1;
 }
 
 const char* qpat_version(void) { return "qpat 0.1 (gfx950)"; }
@@ -742,6 +744,11 @@ qpat_status qpat_operator_layout(const qpat_ctx* c, int64_t out[6]) {
     out[4] = c->lat.on ? c->lat.m + 1 : 0;
     out[5] = c->sell.len;
     return QPAT_OK;
+}
+
+qpat_status qpat_tile_schedule(const qpat_ctx* c, int32_t B, int32_t out[8]) {
+    if (!c || !out || (B != 8 && B != 16)) return QPAT_ERR_ARG;
+    return mg_tile_schedule(c, B, out);
 }
 
 int32_t qpat_geometry_classes(const qpat_ctx* c) { return c ? c->geo_ncls : -1; }

@@ -26,6 +26,9 @@
 // residual at the end. Everything is FP64.
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 
 #include "qpat_internal.h"
@@ -74,6 +77,10 @@ struct TileGeo {
     bool ps_on = false;
     int32_t ps_zc = 0, ps_items = 0, ps_blocks = 0;
     int32_t ps_zc32 = 0, ps_items32 = 0, ps_blocks32 = 0;   // its FP32-staged form
+    // the cost model's z-chunk lengths (tiles, prolongation + sweep FP64, FP32) and whether
+    // the ones in use were picked by timing them (autotune)
+    int32_t zc_model = 0, ps_zc_model = 0, ps_zc32_model = 0;
+    bool tuned = false;
     // the tiled 27-point kernels of the coarse levels (16 right-hand sides)
     struct Lv27 {
         bool on = false;
@@ -2748,6 +2755,57 @@ void launch_restrict(const MgState& M, const TileGeo& t, int l, hipStream_t st, 
 // The finest-level tiling for block size B: on for the Kuhn stencil of one
 // system with B >= 8 whose plane offsets fit 32 bits; the z-chunk length
 // balances the work items over the blocks resident per XCD.
+// ---- autotuning of the tiled z-chunk length
+// The cost model ranks z-chunk lengths by (item waves per XCD) x (planes + 2).
+// With opts.autotune the lowest-cost candidates (at most kTuneCands distinct
+// lengths) are timed on the device, each by one untimed and kTuneReps timed
+// launches of the kernel on scratch vectors, and the fastest is kept. The
+// choice is cached per process by (kernel, lattice size, block), so a second
+// context on the same lattice reuses it; timings taken while other streams
+// load the GPU (concurrent batched instances) are noisier but only pick among
+// the model's own candidates.
+constexpr int kTuneCands = 4, kTuneReps = 3;
+using TuneKey = std::tuple<int, int, int, int, int>;   // kernel, nx, ny, nz, B
+std::mutex g_tune_mu;
+std::map<TuneKey, int32_t> g_tune;
+
+// the candidate chunk lengths (even: only even lengths), lowest model cost first
+inline std::vector<int64_t> chunk_candidates(int64_t nz, int64_t tiles, int64_t conc, bool even) {
+    std::vector<std::pair<int64_t, int64_t>> cz;   // (cost, zc)
+    for (int64_t nch = 1; nch <= nz; ++nch) {
+        int64_t zc = (nz + nch - 1) / nch;
+        if (even) zc += zc & 1;
+        const int64_t items = tiles * ((nz + zc - 1) / zc);
+        const int64_t cost = (((items + 7) / 8 + conc - 1) / conc) * (zc + 2);
+        bool seen = false;
+        for (auto& e : cz) seen = seen || e.second == zc;
+        if (!seen) cz.emplace_back(cost, zc);
+    }
+    std::stable_sort(cz.begin(), cz.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    std::vector<int64_t> out;
+    for (size_t i = 0; i < cz.size() && (int)i < kTuneCands; ++i) out.push_back(cz[i].second);
+    return out;
+}
+
+// mean time (ms) of kTuneReps launches after one untimed launch
+template <typename F>
+qpat_status time_launches(qpat_ctx* c, F&& launch, float* ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    QPAT_HIP(c, hipEventCreate(&e0));
+    QPAT_HIP(c, hipEventCreate(&e1));
+    launch();
+    QPAT_HIP(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < kTuneReps; ++r) launch();
+    QPAT_HIP(c, hipEventRecord(e1, c->stream));
+    QPAT_HIP(c, hipGetLastError());
+    QPAT_HIP(c, hipEventSynchronize(e1));
+    QPAT_HIP(c, hipEventElapsedTime(ms, e0, e1));
+    *ms /= kTuneReps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return QPAT_OK;
+}
+
 template <int B>
 qpat_status tile_setup(qpat_ctx* c, MgState& M) {
     TileGeo& t = M.tiles[B];
@@ -2788,10 +2846,87 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
         }
         t.tiles_x = static_cast<int32_t>(tx);
         t.tiles_y = static_cast<int32_t>(ty);
-        t.zc = static_cast<int32_t>(best_zc);
-        t.items = static_cast<int32_t>(tx * ty * ((L.nz + best_zc - 1) / best_zc));
-        t.blocks = static_cast<int32_t>(8 * std::min<int64_t>(conc, (t.items + 7) / 8));
+        auto set_zc = [&](int64_t zc) {
+            t.zc = static_cast<int32_t>(zc);
+            t.items = static_cast<int32_t>(tx * ty * ((L.nz + zc - 1) / zc));
+            t.blocks = static_cast<int32_t>(8 * std::min<int64_t>(conc, (t.items + 7) / 8));
+        };
+        set_zc(best_zc);
+        t.zc_model = t.zc;
         t.on = true;
+        if (c->opts.autotune) {
+            // time the two kernels of every PCG iteration that share this geometry, the
+            // direction + product and the fused update + first residual (FP64 forms), on
+            // the PCG's scratch vectors with every lane active
+            const TuneKey key{0, L.nx, L.ny, L.nz, B};
+            int32_t zc_t = 0;
+            {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                auto it = g_tune.find(key);
+                if (it != g_tune.end()) zc_t = it->second;
+            }
+            if (!zc_t) {
+                MgScal* sc_t = nullptr;
+                QPAT_TRY(dalloc(c, &sc_t, B));
+                std::vector<MgScal> hs(B);
+                for (auto& h : hs) {
+                    std::memset(&h, 0, sizeof h);
+                    h.active = 1;
+                    h.alpha = 0.5;
+                    h.beta = 0.5;   // nonzero: the direction kernel reads the old direction
+                }
+                QPAT_HIP(c, hipMemcpyAsync(sc_t, hs.data(), B * sizeof(MgScal), hipMemcpyHostToDevice, c->stream));
+                for (double* v : {M.pa, M.pb, M.pq, M.pr, M.pr2})
+                    QPAT_HIP(c, hipMemsetAsync(v, 0, L.N * B * sizeof(double), c->stream));
+                float best_ms = -1.f;
+                for (int64_t zc : chunk_candidates(L.nz, tx * ty, conc, false)) {
+                    set_zc(zc);
+                    TileArgs g{};
+                    g.nx = L.nx;
+                    g.ny = L.ny;
+                    g.nz = L.nz;
+                    g.tiles_x = t.tiles_x;
+                    g.tiles_y = t.tiles_y;
+                    g.zc = t.zc;
+                    g.items = t.items;
+                    g.ld = B;
+                    g.col = 0;
+                    g.U = L.U;
+                    g.dinv = L.dinv;
+                    g.w = M.w;
+                    g.parts = M.parts;
+                    g.sc = sc_t;
+                    TileArgs gd = g, gu = g;
+                    gd.in = M.pa;    // z
+                    gd.in2 = M.pb;   // old direction
+                    gd.out = M.pq;   // q
+                    gd.out2 = M.pr;  // new direction
+                    gu.in = M.pr;    // r
+                    gu.in2 = M.pq;   // q
+                    gu.out = M.lv[0].r;
+                    gu.out2 = M.pr2;
+                    gu.x3 = M.pa;
+                    gu.p3 = M.pb;
+                    const dim3 grid(t.blocks);
+                    float ms_d = 0.f, ms_u = 0.f;
+                    QPAT_TRY(time_launches(c, [&] {
+                        hipLaunchKernelGGL((k_mg_tile<kTDirSpmv, B>), grid, dim3(kTT), MgTile<B>::LDS, c->stream, gd);
+                    }, &ms_d));
+                    QPAT_TRY(time_launches(c, [&] {
+                        hipLaunchKernelGGL((k_mg_tile<kTUpdResid, B>), grid, dim3(kTT), MgTile<B>::LDS, c->stream, gu);
+                    }, &ms_u));
+                    if (best_ms < 0.f || ms_d + ms_u < best_ms) {
+                        best_ms = ms_d + ms_u;
+                        zc_t = t.zc;
+                    }
+                }
+                QPAT_TRY(dfree(c, sc_t));
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                g_tune.emplace(key, zc_t);
+            }
+            set_zc(zc_t);
+            t.tuned = true;
+        }
         // restrictions to levels 1, 2, ... (coarse level of at least kTile27Min nodes): the
         // same balance with (2 zc + 1) fine planes per item
         const MgLevel& C = M.lv[1];
@@ -2844,11 +2979,75 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
                             zc_ps = zc;
                         }
                     }
-                    const int32_t items = static_cast<int32_t>(tx * ty * ((L.nz + zc_ps - 1) / zc_ps));
-                    const int32_t blocks = static_cast<int32_t>(8 * std::min<int64_t>(conc_ps, (items + 7) / 8));
-                    (f32 ? t.ps_zc32 : t.ps_zc) = static_cast<int32_t>(zc_ps);
-                    (f32 ? t.ps_items32 : t.ps_items) = items;
-                    (f32 ? t.ps_blocks32 : t.ps_blocks) = blocks;
+                    auto set_ps = [&](int64_t zc) {
+                        const int32_t items = static_cast<int32_t>(tx * ty * ((L.nz + zc - 1) / zc));
+                        (f32 ? t.ps_zc32 : t.ps_zc) = static_cast<int32_t>(zc);
+                        (f32 ? t.ps_items32 : t.ps_items) = items;
+                        (f32 ? t.ps_blocks32 : t.ps_blocks) =
+                            static_cast<int32_t>(8 * std::min<int64_t>(conc_ps, (items + 7) / 8));
+                    };
+                    set_ps(zc_ps);
+                    (f32 ? t.ps_zc32_model : t.ps_zc_model) = static_cast<int32_t>(zc_ps);
+                    if (!c->opts.autotune) continue;
+                    const TuneKey key{f32 ? 2 : 1, L.nx, L.ny, L.nz, B};
+                    int32_t zc_t = 0;
+                    {
+                        std::lock_guard<std::mutex> lk(g_tune_mu);
+                        auto it = g_tune.find(key);
+                        if (it != g_tune.end()) zc_t = it->second;
+                    }
+                    if (!zc_t) {
+                        // scratch: r in pa, z in pq, lanes all active in a private scalar array
+                        MgScal* sc_t = nullptr;
+                        QPAT_TRY(dalloc(c, &sc_t, B));
+                        std::vector<MgScal> hs(B);
+                        for (auto& h : hs) {
+                            std::memset(&h, 0, sizeof h);
+                            h.active = 1;
+                        }
+                        QPAT_HIP(c, hipMemcpyAsync(sc_t, hs.data(), B * sizeof(MgScal), hipMemcpyHostToDevice, c->stream));
+                        QPAT_HIP(c, hipMemsetAsync(M.pa, 0, L.N * B * sizeof(double), c->stream));
+                        QPAT_HIP(c, hipMemsetAsync(C.x, 0, C.N * B * sizeof(double), c->stream));
+                        float best_ms = -1.f;
+                        for (int64_t zc : chunk_candidates(L.nz, tx * ty, conc_ps, true)) {
+                            set_ps(zc);
+                            PSArgs g;
+                            g.nx = L.nx;
+                            g.ny = L.ny;
+                            g.nz = L.nz;
+                            g.cx = C.nx;
+                            g.cy = C.ny;
+                            g.cz = C.nz;
+                            g.tiles_x = static_cast<int32_t>(tx);
+                            g.tiles_y = static_cast<int32_t>(ty);
+                            g.zc = static_cast<int32_t>(zc);
+                            g.items = f32 ? t.ps_items32 : t.ps_items;
+                            g.Uf = L.Ufk32;
+                            g.r = M.pa;
+                            g.xc = C.x;
+                            g.dinv = L.dinv;
+                            g.w = M.w;
+                            g.z = reinterpret_cast<float*>(M.pq);
+                            g.parts = M.parts;
+                            g.sc = sc_t;
+                            const dim3 grid(f32 ? t.ps_blocks32 : t.ps_blocks);
+                            float ms = 0.f;
+                            QPAT_TRY(time_launches(c, [&] {
+                                if (f32)
+                                    hipLaunchKernelGGL(k_mg_prolong_smooth<true>, grid, dim3(kTT), kPSLds<true>, c->stream, g);
+                                else
+                                    hipLaunchKernelGGL(k_mg_prolong_smooth<false>, grid, dim3(kTT), kPSLds<false>, c->stream, g);
+                            }, &ms));
+                            if (best_ms < 0.f || ms < best_ms) {
+                                best_ms = ms;
+                                zc_t = static_cast<int32_t>(zc);
+                            }
+                        }
+                        QPAT_TRY(dfree(c, sc_t));
+                        std::lock_guard<std::mutex> lk(g_tune_mu);
+                        g_tune.emplace(key, zc_t);
+                    }
+                    set_ps(zc_t);
                 }
                 t.ps_on = true;
             }
@@ -3686,6 +3885,23 @@ static qpat_status apply_B(qpat_ctx* c, const double* U, const double* in, int l
         QPAT_HIP(c, hipGetLastError());
         *done = true;
     }
+    return QPAT_OK;
+}
+
+qpat_status mg_tile_schedule(const qpat_ctx* c, int B, int32_t out[8]) {
+    const MgState* M = state_of(const_cast<qpat_ctx*>(c), Op::K);
+    if (!M) return QPAT_ERR_STATE;
+    const auto it = M->tiles.find(B);
+    if (it == M->tiles.end() || !it->second.ready) return QPAT_ERR_STATE;
+    const TileGeo& t = it->second;
+    out[0] = t.on ? 1 : 0;
+    out[1] = t.on ? t.zc : 0;
+    out[2] = t.on ? t.zc_model : 0;
+    out[3] = t.ps_on ? t.ps_zc : 0;
+    out[4] = t.ps_on ? t.ps_zc_model : 0;
+    out[5] = t.ps_on ? t.ps_zc32 : 0;
+    out[6] = t.ps_on ? t.ps_zc32_model : 0;
+    out[7] = t.tuned ? 1 : 0;
     return QPAT_OK;
 }
 

@@ -401,6 +401,8 @@ void mg_destroy(qpat_ctx* c);
 // out [N][B] = scale U in for a Kuhn stencil form U [N][8] and in [N][ld]
 // (columns col ... col + B - 1), LDS-tiled; *done = false when that path is
 // not available (no current K hierarchy, B < 8, offsets past 32 bits).
+// the tile schedule of the K hierarchy for blocks of B (qpat_tile_schedule)
+qpat_status mg_tile_schedule(const qpat_ctx* c, int B, int32_t out[8]);
 qpat_status mg_stencil_apply(qpat_ctx* c, int B, const double* U, const double* in, int ld, int col, double* out,
                              double scale, bool* done);
 

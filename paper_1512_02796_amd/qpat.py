@@ -33,7 +33,7 @@ class Opts(ctypes.Structure):
                 ("lsqr_reorth", ctypes.c_int32), ("lsqr_max_steps", ctypes.c_int32),
                 ("ru_delta", ctypes.c_double), ("use_graphs", ctypes.c_int32),
                 ("operator_format", ctypes.c_int32), ("prior_precond", ctypes.c_int32),
-                ("pcg_precond", ctypes.c_int32)]
+                ("pcg_precond", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -110,6 +110,7 @@ SIGNATURES = {
     "qpat_profile": (_S, [_P, _I32]),
     "qpat_profile_read": (_S, [_P, ctypes.POINTER(KStat)]),
     "qpat_operator_layout": (_S, [_P, ctypes.POINTER(_I64)]),
+    "qpat_tile_schedule": (_S, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "qpat_batch": (_S, [ctypes.POINTER(_P), _I32, _I32, ctypes.POINTER(_P), ctypes.POINTER(_P),
                         ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(Info)]),
     "qpat_forward_x0": (_S, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(Info)]),
@@ -422,6 +423,13 @@ class Context:
         self._check(_lib.qpat_operator_layout(self._h, arr))
         return {"lattice": bool(arr[0]), "nx": arr[1], "ny": arr[2], "nz": arr[3], "stencil_arrays": arr[4],
                 "sell_len": arr[5]}
+
+
+    def tile_schedule(self, B=16):
+        arr = (ctypes.c_int32 * 8)()
+        self._check(_lib.qpat_tile_schedule(self._h, B, arr))
+        return {"tiled": bool(arr[0]), "zc": arr[1], "zc_model": arr[2], "ps_zc": arr[3], "ps_zc_model": arr[4],
+                "ps_zc32": arr[5], "ps_zc32_model": arr[6], "tuned": bool(arr[7])}
 
 
 PRIOR_PM, PRIOR_TVQ = 0, 1   # QPAT_PRIOR_PM, QPAT_PRIOR_TVQ

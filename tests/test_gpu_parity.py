@@ -371,3 +371,21 @@ def test_geometry_classes_on_an_exact_lattice():
     assert_close(host(outT), lin.vjp(t), 1e-10, "J^T t")
     H = GpuProblem("T12", opts())
     assert H.ctx.geometry_classes() in (0, 6)
+
+
+def test_autotuned_tile_schedule():
+    """opts.autotune times the cost model's lowest-cost z-chunk lengths of the tiled
+    kernels at the first solve and keeps the fastest: the schedule reports a tuned
+    length among those candidates, and the forward fluence equals the untuned
+    context's up to the order of the partial sums."""
+    P = dict(n_ill=16)
+    G0 = GpuProblem("T12", opts(max_rhs_block=16, autotune=0), **P)
+    G1 = GpuProblem("T12", opts(max_rhs_block=16, autotune=1), **P)
+    phi0, _, _ = G0.forward()
+    phi1, _, _ = G1.forward()
+    s0, s1 = G0.ctx.tile_schedule(16), G1.ctx.tile_schedule(16)
+    assert s0["tiled"] and s1["tiled"] and not s0["tuned"] and s1["tuned"]
+    assert s0["zc"] == s0["zc_model"] and s1["zc_model"] == s0["zc_model"]
+    nz = G1.ctx.operator_layout()["nz"]
+    assert 1 <= s1["zc"] <= nz and s1["ps_zc"] % 2 == 0 and s1["ps_zc32"] % 2 == 0
+    assert_close(host(phi1), host(phi0), 1e-12, "phi tuned vs untuned")
