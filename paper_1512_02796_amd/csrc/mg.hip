@@ -54,6 +54,7 @@ struct MgLevel {
     double* Uf = nullptr;          // kind 3: [nsys][kFullRow][N] whole Kuhn rows, entry-major; K levels >= 1: [N][kRow27]
     float* Uf32 = nullptr;         // kind 5: the kind-3 rows in FP32 (M_delta's V-cycle)
     float* Ufk32 = nullptr;        // K level 0: the whole Kuhn rows [N][16] in FP32 (fused prolongation + last sweep)
+    float* Uf27p = nullptr;        // K tiled levels >= 1: the 27-point rows in FP32 as [N][16] pairs (entry k, entry k + 16)
     int32_t vkind = -1;            // row kind of the V-cycle's kernels on this level (-1: kind)
 };
 
@@ -2072,6 +2073,21 @@ __device__ __forceinline__ double row_bcast(double v) {
     return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + J, 0xF, 0xF, true);
 }
 
+// Two FP32 row entries as one 64-bit value, so that one 64-bit DPP row
+// broadcast delivers both: pair = (low: v of this lane, high: v of lane k + 8)
+// (row_pair), or two entries stored side by side and loaded as 8 bytes.
+__device__ __forceinline__ double row_pair(float v) {
+    const int hi = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128, 0xF, 0xF, true);   // row_ror:8
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                          static_cast<uint32_t>(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float pair_lo(double p) {
+    return __builtin_bit_cast(float, static_cast<uint32_t>(__builtin_bit_cast(uint64_t, p)));
+}
+__device__ __forceinline__ float pair_hi(double p) {
+    return __builtin_bit_cast(float, static_cast<uint32_t>(__builtin_bit_cast(uint64_t, p) >> 32));
+}
+
 // sum over the 13 offset pairs: entry 1 + j (upper) and 14 + j (lower) of
 // the row held as (ua: entries 0-15, ub: 16-31) times the LDS neighbours
 template <int J>
@@ -2097,10 +2113,51 @@ __device__ __forceinline__ double apply27(double ua, double ub, const double* rb
     return s;
 }
 
+// the same sum with the row in FP32 pairs: pair k = (entry k, entry k + 16),
+// 16 broadcasts for the 27 entries, the products in FP64
+template <int... K>
+__device__ __forceinline__ void bcast16(double pr, double (&bc)[16], std::integer_sequence<int, K...>) {
+    ((bc[K] = row_bcast<K>(pr)), ...);
+}
+template <int J>
+__device__ __forceinline__ double pair27p(double s, const double (&bc)[16], const double* rb, int sz, int sp, int sl) {
+    constexpr int code = 14 + J;
+    constexpr int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
+    constexpr int d = (dy * kTHX + dx) * 16;
+    const int up = dz ? sp : sz, lo = dz ? sl : sz;
+    const double cu = static_cast<double>(pair_lo(bc[1 + J]));
+    double cl;
+    if constexpr (14 + J < 16)
+        cl = static_cast<double>(pair_lo(bc[14 + J]));
+    else
+        cl = static_cast<double>(pair_hi(bc[J - 2]));
+    return fma(cl, rb[lo - d], fma(cu, rb[up + d], s));
+}
+template <int... J>
+__device__ __forceinline__ double apply27p(double pr, const double* rb, int sz, int sp, int sl,
+                                           std::integer_sequence<int, J...>) {
+    double bc[16];
+    bcast16(pr, bc, std::make_integer_sequence<int, 16>{});
+    double s = static_cast<double>(pair_lo(bc[0])) * rb[sz];
+    ((s = pair27p<J>(s, bc, rb, sz, sp, sl)), ...);
+    return s;
+}
+
+// [n][16][2] FP32 pairs (entry k, entry k + 16) from the [n][kRow27] FP64 rows
+__global__ void k_pairs27(int64_t n, const double* __restrict__ U, float* __restrict__ P) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * 16;
+         i += (int64_t)gridDim.x * blockDim.x) {   // (node, k)
+        const int64_t node = i / 16, k = i % 16;
+        P[2 * i] = static_cast<float>(U[node * kRow27 + k]);
+        P[2 * i + 1] = static_cast<float>(U[node * kRow27 + 16 + k]);
+    }
+}
+
 struct Tile27Args {
     int32_t nx, ny, nz;
     int32_t tiles_x, tiles_y, zc, items;
     const double* Uf;     // [N][kRow27]
+    const float* Uf27p;   // R32: the rows as [N][16] FP32 pairs
     const double* x;      // staged vector [N][16]
     const double* b;      // [N][16]
     const double* dinv;   // [N] (kT27Smooth)
@@ -2109,7 +2166,7 @@ struct Tile27Args {
     const MgScal* sc;     // [16]
 };
 
-template <int MODE>
+template <int MODE, bool R32 = false>
 __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
     constexpr int B = 16;
     constexpr int NPF = MgTile<B>::NPF, RS = NPF * kTT;
@@ -2175,13 +2232,23 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
         // the operator rows and b of plane z, loaded a plane ahead
         double ua[NO], ub[NO], bn[NO];
         auto load_node = [&](int z) {
-            const auto bu = plane(g.Uf, z, nxy * kRow27, pr);
             const auto bb = plane(g.b, z, nxy * B, pv);
+            if constexpr (R32) {   // the pair (entry k, entry k + 16) as 8 bytes: the layout of a [N][16] vector
+                const auto bq = plane(reinterpret_cast<const double*>(g.Uf27p), z, nxy * B, pv);
 #pragma unroll
-            for (int u = 0; u < NO; ++u) {
-                ua[u] = bload<double>(bu, ro[u]);
-                ub[u] = bload<double>(bu, ro[u] == kOut ? kOut : ro[u] + 16 * SZ);
-                bn[u] = bload<double>(bb, oo[u]);
+                for (int u = 0; u < NO; ++u) {
+                    ua[u] = bload<double>(bq, oo[u]);
+                    ub[u] = 0.0;
+                    bn[u] = bload<double>(bb, oo[u]);
+                }
+            } else {
+                const auto bu = plane(g.Uf, z, nxy * kRow27, pr);
+#pragma unroll
+                for (int u = 0; u < NO; ++u) {
+                    ua[u] = bload<double>(bu, ro[u]);
+                    ub[u] = bload<double>(bu, ro[u] == kOut ? kOut : ro[u] + 16 * SZ);
+                    bn[u] = bload<double>(bb, oo[u]);
+                }
             }
         };
         load_node(zb);
@@ -2208,8 +2275,11 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
             for (int u = 0; u < NO; ++u) {
                 if (tid + u * kTT >= TX * TY * B) continue;   // whole waves past the tile skip
                 const double* rb = ring + oc[u] * B + k;
-                const double ax = apply27(ca[u], cb[u], rb, sz * RS, sp * RS, sl * RS,
-                                          std::make_integer_sequence<int, 13>{});
+                double ax;
+                if constexpr (R32)
+                    ax = apply27p(ca[u], rb, sz * RS, sp * RS, sl * RS, std::make_integer_sequence<int, 13>{});
+                else
+                    ax = apply27(ca[u], cb[u], rb, sz * RS, sp * RS, sl * RS, std::make_integer_sequence<int, 13>{});
                 double o = bc[u] - ax;
                 if constexpr (MODE == kT27Smooth) o = rb[sz * RS] + w * dc[u] * o;
                 bstore<double>(bo, act ? oo[u] : kOut, o);
@@ -2277,21 +2347,11 @@ __device__ __forceinline__ double apply_kuhn16(double ua, const double* rb, int 
     return s;
 }
 
-// The FP32 form (mixed precision) stages x0 in FP32 and sums A x0 in FP32:
-// lane k of a node's 16 holds the row entries k and k + 8 as one 64-bit pair,
-// so 8 pair broadcasts deliver the diagonal, the 7 upper and the 7 lower
-// entries (pair i: entry i low, entry i + 8 high).
-__device__ __forceinline__ double row_pair(float v) {
-    const int hi = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128, 0xF, 0xF, true);   // row_ror:8
-    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
-                                          static_cast<uint32_t>(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ float pair_lo(double p) {
-    return __builtin_bit_cast(float, static_cast<uint32_t>(__builtin_bit_cast(uint64_t, p)));
-}
-__device__ __forceinline__ float pair_hi(double p) {
-    return __builtin_bit_cast(float, static_cast<uint32_t>(__builtin_bit_cast(uint64_t, p) >> 32));
-}
+// The FP32 form (mixed precision) of the fused prolongation + sweep stages x0
+// in FP32 and sums A x0 in FP32: lane k of a node's 16 holds the row entries k
+// and k + 8 as one 64-bit pair (row_pair), so 8 pair broadcasts deliver the
+// diagonal, the 7 upper and the 7 lower entries (pair i: entry i low, entry
+// i + 8 high).
 template <int... J>
 __device__ __forceinline__ float apply_kuhn16_f32(double pr, const float* rb, int sz, int sp, int sl,
                                                   std::integer_sequence<int, J...>) {
@@ -2680,14 +2740,18 @@ void launch_tile27(const MgState& M, const TileGeo& t, int l, hipStream_t st, co
     g.zc = q.zc;
     g.items = q.items;
     g.Uf = L.Uf;
+    g.Uf27p = L.Uf27p;
     g.x = x;
     g.b = b;
     g.dinv = L.dinv;
     g.w = M.w + l;   // system 0, level l
     g.out = out;
     g.sc = M.sc;
-    hipLaunchKernelGGL(k_mg_tile27<MODE>, dim3(q.blocks), dim3(kTT), (size_t)3 * MgTile<16>::NPF * kTT * sizeof(double),
-                       st, g);
+    const size_t lds = (size_t)3 * MgTile<16>::NPF * kTT * sizeof(double);
+    if (L.Uf27p)   // the rows in FP32 (the V-cycle's coarse operators)
+        hipLaunchKernelGGL((k_mg_tile27<MODE, true>), dim3(q.blocks), dim3(kTT), lds, st, g);
+    else
+        hipLaunchKernelGGL((k_mg_tile27<MODE, false>), dim3(q.blocks), dim3(kTT), lds, st, g);
 }
 inline bool tiled27(const TileGeo& t, int l) { return l >= 1 && l < kMgMaxLevels && t.t27[l].on; }
 
@@ -3053,8 +3117,10 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
             }
         }
         if constexpr (B == 16) {   // the coarse levels' 27-point kernels
-            const void* f27[2] = {reinterpret_cast<const void*>(&k_mg_tile27<kT27Resid>),
-                                  reinterpret_cast<const void*>(&k_mg_tile27<kT27Smooth>)};
+            const void* f27[4] = {reinterpret_cast<const void*>(&k_mg_tile27<kT27Resid>),
+                                  reinterpret_cast<const void*>(&k_mg_tile27<kT27Smooth>),
+                                  reinterpret_cast<const void*>(&k_mg_tile27<kT27Resid, true>),
+                                  reinterpret_cast<const void*>(&k_mg_tile27<kT27Smooth, true>)};
             constexpr size_t lds27 = (size_t)3 * MgTile<16>::NPF * kTT * sizeof(double);
             for (const void* f : f27)
                 QPAT_HIP(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds27));
@@ -3730,8 +3796,10 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
                 QPAT_TRY(dalloc(c, &L.Ufk32, nsys * L.N * kFullRow));
             }
             if (op == Op::K && l >= 1 && l < kMgMaxLevels && M.bmax == 16 && M.lv[0].kind == 1 &&
-                L.N >= kTile27Min && L.N * kRow27 * (int64_t)sizeof(double) < (int64_t(1) << 31))
+                L.N >= kTile27Min && L.N * kRow27 * (int64_t)sizeof(double) < (int64_t(1) << 31)) {
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kRow27));
+                QPAT_TRY(dalloc(c, &L.Uf27p, nsys * L.N * kRow27));
+            }
             if (op == Op::Prior && l >= 1 && l + 1 < nl && L.N >= kRow27Min)   // entry-major rows (kind 4)
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * 27));
         }
@@ -3786,10 +3854,13 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
                            lv_args(F), M.opdep ? F.W : nullptr, C.U, C.nx, C.ny, C.nz);
     }
     for (int l = 1; l < nl; ++l)
-        if (M.lv[l].Uf && op == Op::K)
+        if (M.lv[l].Uf && op == Op::K) {
             hipLaunchKernelGGL(k_mg_fullrows27<false>, dim3(grid_for(M.lv[l].N, kMgT, 4096), nsys), dim3(kMgT), 0,
                                c->stream, lv_args(M.lv[l]), M.lv[l].Uf);
-        else if (M.lv[l].Uf)
+            if (M.lv[l].Uf27p)
+                hipLaunchKernelGGL(k_pairs27, dim3(grid_for(nsys * M.lv[l].N * 16, kMgT, 4096)), dim3(kMgT), 0,
+                                   c->stream, nsys * M.lv[l].N, M.lv[l].Uf, M.lv[l].Uf27p);
+        } else if (M.lv[l].Uf)
             hipLaunchKernelGGL(k_mg_fullrows27<true>, dim3(grid_for(M.lv[l].N, kMgT, 4096), nsys), dim3(kMgT), 0,
                                c->stream, lv_args(M.lv[l]), M.lv[l].Uf);
     QPAT_HIP(c, hipMemsetAsync(M.gmax, 0, nsys * nl * sizeof(uint64_t), c->stream));

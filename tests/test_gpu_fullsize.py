@@ -52,6 +52,9 @@ def sample_rows(N, k=400, seed=0):
 def test_forward_true_residual_on_sampled_rows(big):
     P, ctx, phi, info = big
     assert info["relres_max"] <= 1e-10
+    # the V-cycle at full strength (tiled levels 1 and 2 included): 14 iterations
+    # at this size; a damaged coarse operator still converges, only slower
+    assert info["iters_max"] <= 15, info["iters_max"]
     rows = sample_rows(P.mesh.N)
     g, sel_f = local_geometry(P, rows)
     K = fem.system_matrix(g, P.kappa, P.mu)
