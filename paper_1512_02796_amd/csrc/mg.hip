@@ -52,7 +52,7 @@ struct MgLevel {
     float* W32 = nullptr;          // the same in FP32: the V-cycle's prolongation reads these (W holds the same
                                    // rounded values for the restriction and the Galerkin set-up: one P throughout)
     double* Uf = nullptr;          // kind 3: [nsys][kFullRow][N] whole Kuhn rows, entry-major; K levels >= 1: [N][kRow27]
-    float* Uf32 = nullptr;         // kind 5: the kind-3 rows in FP32 (M_delta's V-cycle)
+    float* Uf32 = nullptr;         // kind 5 / 6: the kind-3 / kind-4 rows in FP32 (M_delta's V-cycle)
     float* Ufk32 = nullptr;        // K level 0: the whole Kuhn rows [N][16] in FP32 (fused prolongation + last sweep)
     float* Uf27p = nullptr;        // K tiled levels >= 1: the 27-point rows in FP32 as [N][16] pairs (entry k, entry k + 16)
     int32_t vkind = -1;            // row kind of the V-cycle's kernels on this level (-1: kind)
@@ -255,6 +255,7 @@ template <int KIND>
 __device__ __forceinline__ const double* rows_of(const LvArgs& L, int sys) {
     if constexpr (KIND == 3) return L.Uf + (int64_t)sys * L.N * kFullRow;
     if constexpr (KIND == 4) return L.Uf + (int64_t)sys * L.N * 27;
+    if constexpr (KIND == 6) return reinterpret_cast<const double*>(L.Uf32 + (int64_t)sys * L.N * 27);
     if constexpr (KIND == 5) return reinterpret_cast<const double*>(L.Uf32 + (int64_t)sys * L.N * kFullRow);
     return L.U + (int64_t)sys * L.N * (L.m + 1);
 }
@@ -291,6 +292,23 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             // neighbour, so all of a row's loads are in flight together
             const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + (lo ? i - lin : i) * B);
             const double cu = U[(1 + j) * L.N + i], cl = U[(14 + j) * L.N + i];
+            s = up ? s + cu * xu : s;
+            s = lo ? s + cl * xl : s;
+        }
+        return s;
+    } else if constexpr (KIND == 6) {   // the kind-4 rows in FP32 (a preconditioner's coarse operator)
+        const float* Uw = reinterpret_cast<const float*>(U);
+        const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
+        T s = static_cast<double>(Uw[i]) * vld<T>(x + i * B);
+#pragma unroll
+        for (int j = 0; j < 13; ++j) {
+            const int code = 14 + j;
+            const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
+            const int32_t lin = dx + L.nx * (dy + L.ny * dz);
+            const bool up = inner || (ix + dx >= 0 && ix + dx < L.nx && iy + dy >= 0 && iy + dy < L.ny && iz + dz < L.nz);
+            const bool lo = inner || (ix - dx >= 0 && ix - dx < L.nx && iy - dy >= 0 && iy - dy < L.ny && iz - dz >= 0);
+            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + (lo ? i - lin : i) * B);
+            const double cu = static_cast<double>(Uw[(1 + j) * L.N + i]), cl = static_cast<double>(Uw[(14 + j) * L.N + i]);
             s = up ? s + cu * xu : s;
             s = lo ? s + cl * xl : s;
         }
@@ -2626,6 +2644,9 @@ inline dim3 vgrid(int64_t n, int cap = kMgGrid) { return dim3((grid_for(n, kMgT,
         case 5:                                                             \
             if constexpr (B == 1) hipLaunchKernelGGL((KERNEL<5, 1>), __VA_ARGS__); \
             break;                                                          \
+        case 6:                                                             \
+            if constexpr (B == 1) hipLaunchKernelGGL((KERNEL<6, 1>), __VA_ARGS__); \
+            break;                                                          \
         default: hipLaunchKernelGGL((KERNEL<0, B>), __VA_ARGS__); break;    \
     }
 
@@ -2681,6 +2702,9 @@ void launch_smooth(int kind, dim3 g, hipStream_t st, const SmArgs& a, const doub
             break;
         case 5:
             if constexpr (B == 1) hipLaunchKernelGGL((k_mg_smooth<5, 1, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts);
+            break;
+        case 6:
+            if constexpr (B == 1) hipLaunchKernelGGL((k_mg_smooth<6, 1, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts);
             break;
         default: hipLaunchKernelGGL((k_mg_smooth<0, B, DOTS>), g, dim3(kMgT), 0, st, a, b, x, y, parts); break;
     }
@@ -3800,8 +3824,10 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kRow27));
                 QPAT_TRY(dalloc(c, &L.Uf27p, nsys * L.N * kRow27));
             }
-            if (op == Op::Prior && l >= 1 && l + 1 < nl && L.N >= kRow27Min)   // entry-major rows (kind 4)
+            if (op == Op::Prior && l >= 1 && l + 1 < nl && L.N >= kRow27Min) {   // entry-major rows (kind 4)
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * 27));
+                QPAT_TRY(dalloc(c, &L.Uf32, nsys * L.N * 27));   // and in FP32 for the V-cycle (kind 6)
+            }
         }
         QPAT_TRY(dalloc(c, &M.w, nsys * nl));
         QPAT_TRY(dalloc(c, &M.gmax, nsys * nl));
@@ -3860,9 +3886,13 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             if (M.lv[l].Uf27p)
                 hipLaunchKernelGGL(k_pairs27, dim3(grid_for(nsys * M.lv[l].N * 16, kMgT, 4096)), dim3(kMgT), 0,
                                    c->stream, nsys * M.lv[l].N, M.lv[l].Uf, M.lv[l].Uf27p);
-        } else if (M.lv[l].Uf)
+        } else if (M.lv[l].Uf) {
             hipLaunchKernelGGL(k_mg_fullrows27<true>, dim3(grid_for(M.lv[l].N, kMgT, 4096), nsys), dim3(kMgT), 0,
                                c->stream, lv_args(M.lv[l]), M.lv[l].Uf);
+            if (M.lv[l].Uf32)
+                hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nsys * M.lv[l].N * 27, kMgT, 4096)), dim3(kMgT), 0,
+                                   c->stream, M.lv[l].Uf, M.lv[l].Uf32, nsys * M.lv[l].N * 27);
+        }
     QPAT_HIP(c, hipMemsetAsync(M.gmax, 0, nsys * nl * sizeof(uint64_t), c->stream));
     for (int l = 0; l < nl; ++l)
         hipLaunchKernelGGL(k_mg_diag, dim3(grid_for(M.lv[l].N, kMgT, kMgBlocks), nsys), dim3(kMgT), 0, c->stream,
@@ -3917,8 +3947,10 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     if (op == Op::Prior) QPAT_TRY(region_setup(c, M));
     if (M.lv[0].Uf && op == Op::Prior) M.lv[0].kind = 3;
     if (M.lv[0].Uf32 && op == Op::Prior) M.lv[0].vkind = 5;   // the V-cycle's sweeps and residuals on FP32 rows
-    for (int l = 1; op == Op::Prior && l < nl; ++l)
+    for (int l = 1; op == Op::Prior && l < nl; ++l) {
         if (M.lv[l].Uf) M.lv[l].kind = 4;
+        if (M.lv[l].Uf32) M.lv[l].vkind = 6;   // the V-cycle's sweeps and residuals on FP32 rows
+    }
     M.current = true;
     return QPAT_OK;
 }
