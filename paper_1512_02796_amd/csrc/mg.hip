@@ -930,6 +930,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_dense(int64_t Nc, int nsys, const d
     const int sys = blockIdx.z, v = blockIdx.y;
     if (!pair_active<B>(sc, sys, v)) return;   // uniform over the block
     const double* bs = b + sys * Nc * B + v * V;
+#pragma unroll 4
     for (int64_t J = threadIdx.x; J < Nc; J += kMgT) bl[J] = vld<T>(bs + J * B);
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -937,6 +938,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_dense(int64_t Nc, int nsys, const d
     if (I >= Nc) return;   // whole wavefronts, after the barrier
     const double* A = ainv + (sys * Nc + I) * Nc;
     T s = 0.0;
+#pragma unroll 4   // several rows' loads in flight (the coarsest solve is latency-bound)
     for (int64_t J = lane; J < Nc; J += 64) s += A[J] * bl[J];
     double out[V];
 #pragma unroll
