@@ -39,7 +39,8 @@ struct MgLevel {
     int32_t nx = 0, ny = 0, nz = 0;
     int64_t N = 0;
     int32_t m = 0;                 // stored upper offsets
-    int32_t kind = 0;              // row kernel: 0 generic table, 1 Kuhn offsets, 2 27-point, 3 whole Kuhn rows, 4 whole 27-point rows (Uf)
+    int32_t kind = 0;              // row kernel: 0 generic table, 1 Kuhn offsets, 2 27-point, 3 Kuhn upper rows
+                                   // entry-major (Uf), 4 whole 27-point rows (Uf)
     const int4* tab = nullptr;     // [m]: dx, dy, dz, dx + nx (dy + ny dz)
     int4* tab_own = nullptr;
     double* U = nullptr;           // [nsys][N][m+1] (level 0: the context's stencil arrays)
@@ -51,7 +52,8 @@ struct MgLevel {
     double* W = nullptr;           // [nsys][8][N] operator-dependent prolongation weights to the next level (corner-major)
     float* W32 = nullptr;          // the same in FP32: the V-cycle's prolongation reads these (W holds the same
                                    // rounded values for the restriction and the Galerkin set-up: one P throughout)
-    double* Uf = nullptr;          // kind 3: [nsys][kFullRow][N] whole Kuhn rows, entry-major; K levels >= 1: [N][kRow27]
+    double* Uf = nullptr;          // kind 3: [nsys][kUpRow][N] Kuhn diagonal + upper entries, entry-major;
+                                   // K level 0: [N][kFullRow] whole Kuhn rows; K levels >= 1: [N][kRow27]
     float* Uf32 = nullptr;         // kind 5 / 6: the kind-3 / kind-4 rows in FP32 (M_delta's V-cycle)
     float* Ufk32 = nullptr;        // K level 0: the whole Kuhn rows [N][16] in FP32 (fused prolongation + last sweep)
     float* Uf27p = nullptr;        // K tiled levels >= 1: the 27-point rows in FP32 as [N][16] pairs (entry k, entry k + 16)
@@ -239,24 +241,28 @@ struct LvArgs {
     const int4* tab;
     int32_t m, nx, ny, nz;
     int64_t N;
-    int32_t kind;         // row kernel: 0 generic table, 1 Kuhn offsets, 2 full 27-point, 3 Kuhn full rows
-    const double* Uf;     // kind 3: [nsys][kFullRow][N] whole rows of the Kuhn stencil
-    const float* Uf32;    // kind 5: the same in FP32
+    int32_t kind;         // row kernel: 0 generic table, 1 Kuhn offsets, 2 full 27-point, 3 Kuhn upper rows
+                          // entry-major, 4 27-point whole rows entry-major (5, 6: 3, 4 in FP32)
+    const double* Uf;     // kind 3: [nsys][kUpRow][N]; kind 4: [nsys][27][N]
+    const float* Uf32;    // kind 5 / 6: the same in FP32
 };
 
-// Kuhn rows stored whole for the one-right-hand-side kernels: diagonal, the 7
-// upper entries, the 7 lower ones (offset order), entry-major ([kFullRow][N]
-// per system) so that a wavefront's loads of one entry for consecutive nodes
-// are contiguous: no gather of the lower entries from 7 partner rows
+// Kuhn rows for the one-right-hand-side kernels: the diagonal and the 7 upper
+// entries, entry-major ([kUpRow][N] per system), so that a wavefront's loads of
+// one entry for consecutive nodes are contiguous, the lower entries included
+// (each is a partner row's upper entry at a shifted index)
+constexpr int kUpRow = 8;
+// whole Kuhn rows (diagonal, 7 upper, 7 lower entries, pad), node-major, for
+// the 16-lane fused prolongation + sweep
 constexpr int kFullRow = 16;
 
 // first stored row of system sys in the form the row kernel KIND reads
 template <int KIND>
 __device__ __forceinline__ const double* rows_of(const LvArgs& L, int sys) {
-    if constexpr (KIND == 3) return L.Uf + (int64_t)sys * L.N * kFullRow;
+    if constexpr (KIND == 3) return L.Uf + (int64_t)sys * L.N * kUpRow;
     if constexpr (KIND == 4) return L.Uf + (int64_t)sys * L.N * 27;
     if constexpr (KIND == 6) return reinterpret_cast<const double*>(L.Uf32 + (int64_t)sys * L.N * 27);
-    if constexpr (KIND == 5) return reinterpret_cast<const double*>(L.Uf32 + (int64_t)sys * L.N * kFullRow);
+    if constexpr (KIND == 5) return reinterpret_cast<const double*>(L.Uf32 + (int64_t)sys * L.N * kUpRow);
     return L.U + (int64_t)sys * L.N * (L.m + 1);
 }
 
@@ -313,11 +319,17 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             s = lo ? s + cl * xl : s;
         }
         return s;
-    } else if constexpr (KIND == 5) {   // the kind-3 rows in FP32 (a preconditioner's operator)
-        const float* Uw = reinterpret_cast<const float*>(U);
-        double u[15];
+    } else if constexpr (KIND == 3 || KIND == 5) {
+        // Kuhn rows' diagonal and upper entries, entry-major (3: FP64, 5: FP32).
+        // The lower entry of offset j of row i is the upper entry j of row
+        // i - u_j, read at the shifted index of the same entry array: the
+        // partner row's entries were read moments before in the sweep order,
+        // so the shifted reads come from L2 and each row crosses HBM once.
+        using W = std::conditional_t<KIND == 5, float, double>;
+        const W* Uw = reinterpret_cast<const W*>(U);
+        double u[8];
 #pragma unroll
-        for (int k = 0; k < 15; ++k) u[k] = static_cast<double>(Uw[k * L.N + i]);
+        for (int k = 0; k < 8; ++k) u[k] = static_cast<double>(Uw[k * L.N + i]);
         const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
         T s = u[0] * vld<T>(x + i * B);
 #pragma unroll
@@ -326,26 +338,11 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             const int32_t lin = dx + L.nx * (dy + L.ny * dz);
             const bool up = inner || (ix + dx < L.nx && iy + dy < L.ny && iz + dz < L.nz);
             const bool lo = inner || (ix - dx >= 0 && iy - dy >= 0 && iz - dz >= 0);
-            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + (lo ? i - lin : i) * B);
+            const int32_t il = lo ? i - lin : i;
+            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + il * B);
+            const double cl = static_cast<double>(Uw[(1 + j) * L.N + il]);
             s = up ? s + u[1 + j] * xu : s;
-            s = lo ? s + u[8 + j] * xl : s;
-        }
-        return s;
-    } else if constexpr (KIND == 3) {
-        double u[15];
-#pragma unroll
-        for (int k = 0; k < 15; ++k) u[k] = U[k * L.N + i];
-        const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
-        T s = u[0] * vld<T>(x + i * B);
-#pragma unroll
-        for (int j = 0; j < 7; ++j) {
-            const int dx = kKx[j], dy = kKy[j], dz = kKz[j];
-            const int32_t lin = dx + L.nx * (dy + L.ny * dz);
-            const bool up = inner || (ix + dx < L.nx && iy + dy < L.ny && iz + dz < L.nz);
-            const bool lo = inner || (ix - dx >= 0 && iy - dy >= 0 && iz - dz >= 0);
-            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + (lo ? i - lin : i) * B);
-            s = up ? s + u[1 + j] * xu : s;
-            s = lo ? s + u[8 + j] * xl : s;
+            s = lo ? s + cl * xl : s;
         }
         return s;
     } else {
@@ -466,15 +463,16 @@ __device__ __forceinline__ void put_sums(double* parts, int sys, int slot, TB<B>
     }
 }
 
-// whole Kuhn rows (diagonal, upper entries, lower entries gathered from the
-// partner rows, zero where the partner is off the lattice): entry-major for
-// the row kind 3 (ENTRY), node-major [N][kFullRow] for the 16-lane kernels
+// Kuhn rows from the stencil form (zero where the partner is off the lattice):
+// ENTRY, the row kind 3, the diagonal and upper entries entry-major
+// [kUpRow][N]; otherwise whole rows node-major [N][kFullRow] (the lower entries
+// gathered from the partner rows) for the 16-lane kernels
 template <bool ENTRY>
 __global__ __launch_bounds__(kMgT) void k_mg_fullrows(LvArgs L, double* __restrict__ Uf) {
     const int sys = blockIdx.y;
     constexpr int M1 = 8;
     const double* U = L.U + (int64_t)sys * L.N * M1;
-    double* F = Uf + (int64_t)sys * L.N * kFullRow;
+    double* F = Uf + (int64_t)sys * L.N * (ENTRY ? kUpRow : kFullRow);
     for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * kMgT) {
         int ix, iy, iz;
         coords(static_cast<int32_t>(i), L.nx, L.ny, ix, iy, iz);
@@ -490,12 +488,12 @@ __global__ __launch_bounds__(kMgT) void k_mg_fullrows(LvArgs L, double* __restri
             u[8 + j] = lo ? U[(i - lin) * M1 + 1 + j] : 0.0;
         }
         u[15] = 0.0;
+        if constexpr (ENTRY) {
 #pragma unroll
-        for (int k = 0; k < kFullRow; ++k) {
-            if constexpr (ENTRY)
-                F[k * L.N + i] = u[k];
-            else
-                F[i * kFullRow + k] = u[k];
+            for (int k = 0; k < kUpRow; ++k) F[k * L.N + i] = u[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < kFullRow; ++k) F[i * kFullRow + k] = u[k];
         }
     }
 }
@@ -1213,6 +1211,83 @@ __global__ __launch_bounds__(kMgT) void k_reg_rsum(PcgMg a, double* __restrict__
             for (int b = blockIdx.x + gridDim.x; b < kMgBlocks; b += gridDim.x) p[b] = 0.0;
         }
         __syncthreads();
+    }
+}
+
+// One right-hand side per system: the PCG update fused with the two passes
+// that read its new r next. x += alpha p, r -= alpha q (a system that
+// stopped keeps both) and the partial r.r; the V-cycle's first sweep on the
+// finest level, x0 = w D^{-1} r; and, with the region coarse space, the
+// partial sums of Z^T r. Four nodes' loads in flight per trip (buffer loads
+// with 32-bit offsets: N 8 < 2^31; past the end they read 0 and the stores
+// drop); few, full blocks (kMgGrid), so that each block's reduction of its
+// kRegMax region sums is spread over many nodes. Slots of blocks past the
+// grid read as zero.
+__global__ __launch_bounds__(kMgT, 4) void k_mgp_update_first(PcgMg a, SmArgs s, double* __restrict__ x0,
+                                                           double* __restrict__ rparts) {
+    __shared__ double sm[(kMgT / 64) * kRegMax];
+    const int64_t n = a.L.N, stride = (int64_t)gridDim.x * kMgT;
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        const MgScal& sc = a.sc[sys];
+        const bool regions = a.kreg > 0;
+        double rr = 0.0, acc[kRegMax];
+#pragma unroll
+        for (int j = 0; j < kRegMax; ++j) acc[j] = 0.0;
+        if (sc.active) {   // uniform over the grid
+            const double alpha = sc.alpha, w = s.w[sys * s.nlev];
+            const int64_t o = sys * n;
+            const uint32_t nb8 = static_cast<uint32_t>(n) * 8u;
+            const auto bp = rsrc(a.pn + o, nb8), bq = rsrc(a.q + o, nb8), bd = rsrc(s.dinv + o, nb8);
+            const auto bx = rsrc(a.x + o, nb8), br = rsrc(a.r + o, nb8), bs = rsrc(x0 + o, nb8);
+            const auto bg = rsrc(a.reg + (regions ? o : 0), regions ? nb8 / 2 : 0u);
+            for (int64_t i0 = blockIdx.x * (int64_t)kMgT + threadIdx.x; i0 < n; i0 += 4 * stride) {
+                double pv[4], qv[4], rv[4], xv[4], dv[4];
+                int32_t gv[4];
+                uint32_t off[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    off[u] = static_cast<uint32_t>(i0 + u * stride) * 8u;   // >= N 8 past the end
+                    pv[u] = bload<double>(bp, off[u]);
+                    qv[u] = bload<double>(bq, off[u]);
+                    rv[u] = bload<double>(br, off[u]);
+                    xv[u] = bload<double>(bx, off[u]);
+                    dv[u] = bload<double>(bd, off[u]);
+                    gv[u] = regions ? bload<int32_t>(bg, off[u] / 2) : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {   // nodes past the end: all zero, stores dropped
+                    const double rn = rv[u] - alpha * qv[u];
+                    bstore<double>(bx, off[u], xv[u] + alpha * pv[u]);
+                    bstore<double>(br, off[u], rn);
+                    bstore<double>(bs, off[u], w * dv[u] * rn);
+                    rr += rn * rn;
+                    if (regions)
+#pragma unroll
+                        for (int j = 0; j < kRegMax; ++j) acc[j] += gv[u] == j ? rn : 0.0;
+                }
+            }
+        }
+        const double t = group_sum<1>(rr, sm);
+        if (threadIdx.x == 0) put(a.parts, sys, 1, t);
+        if (regions) {   // fixed-order block sums of the region partials (as k_reg_rsum)
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+            for (int j = 0; j < kRegMax; ++j) {
+                double v = acc[j];
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+                if (lane == 0) sm[wave * kRegMax + j] = v;
+            }
+            __syncthreads();
+            if (threadIdx.x < kRegMax) {
+                double v = 0.0;
+                for (int wv = 0; wv < kMgT / 64; ++wv) v += sm[wv * kRegMax + threadIdx.x];
+                double* pp = rparts + (sys * kRegMax + threadIdx.x) * kMgBlocks;
+                pp[blockIdx.x] = v;
+                for (int b = blockIdx.x + gridDim.x; b < kMgBlocks; b += gridDim.x) pp[b] = 0.0;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -3199,9 +3274,24 @@ inline bool z32_path(const MgState& M, const TileGeo& tg) {
 // kernel stages it and the prolongation recomputes it. Level 0 takes
 // 2 kMgNu - 1 ping-pong sweeps (an odd number), so z ends in level 0's t.
 // lo32 (mixed precision) stages the fused last sweep's x0 in FP32.
+// the smoother arguments of level l
+inline SmArgs level_args(const MgState& M, int l) {
+    SmArgs a;
+    a.L = lv_args(M.lv[l]);
+    a.dinv = M.lv[l].dinv;
+    a.w = M.w;
+    a.nlev = static_cast<int>(M.lv.size());
+    a.lev = l;
+    a.nsys = M.nsys;
+    a.sc = M.sc;
+    return a;
+}
+
+// first_done: the PCG update already wrote the finest level's first sweep
+// (k_mgp_update_first)
 template <int B>
 void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev = nullptr, const double* b0 = nullptr,
-            bool resid_done = false, bool lo32 = false) {
+            bool resid_done = false, bool lo32 = false, bool first_done = false) {
     const int nl = static_cast<int>(M.lv.size());
     const bool fused0 = tg.on && kMgNu == 1;
     const double* r0 = b0 ? b0 : M.lv[0].b;   // level 0's right-hand side (the PCG residual)
@@ -3210,24 +3300,15 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         xl[l] = M.lv[l].x;
         tl[l] = M.lv[l].t;
     }
-    auto sm = [&](int l) {
-        SmArgs a;
-        a.L = lv_args(M.lv[l]);
-        a.dinv = M.lv[l].dinv;
-        a.w = M.w;
-        a.nlev = nl;
-        a.lev = l;
-        a.nsys = M.nsys;
-        a.sc = M.sc;
-        return a;
-    };
+    auto sm = [&](int l) { return level_args(M, l); };
     for (int l = 0; l < nl - 1; ++l) {
         const MgLevel& L = M.lv[l];
         const MgLevel& C = M.lv[l + 1];
         const SmArgs a = sm(l);
         const dim3 g = sgrid<B>(L.N);
         const double* bl = l == 0 ? r0 : L.b;
-        if (l == 0 && !fused0) hipLaunchKernelGGL(k_mg_first<B>, vgrid(L.N * B), dim3(kMgT), 0, st, a, r0, xl[0]);
+        if (l == 0 && !fused0 && !first_done)
+            hipLaunchKernelGGL(k_mg_first<B>, vgrid(L.N * B), dim3(kMgT), 0, st, a, r0, xl[0]);
         for (int k = 1; k < kMgNu; ++k) {
             launch_smooth<B, false>(vkind(L), g, st, a, bl, xl[l], tl[l], nullptr);
             std::swap(xl[l], tl[l]);
@@ -3331,11 +3412,12 @@ PcgMg pcg_args(qpat_ctx* c, Op op) {
 }
 
 // the region coarse-space part of the preconditioner for the current r
+// (sums_done: the PCG update already left the partial sums of Z^T r)
 template <int B>
-void region_solve(const MgState& M, const PcgMg& a, hipStream_t st) {
+void region_solve(const MgState& M, const PcgMg& a, hipStream_t st, bool sums_done = false) {
     if (a.kreg <= 0) return;
     // each block reduces kRegMax sums: fewer, fuller blocks than the walk kernels
-    hipLaunchKernelGGL(k_reg_rsum, vgrid(a.L.N, kMgGrid), dim3(kMgT), 0, st, a, M.rparts);
+    if (!sums_done) hipLaunchKernelGGL(k_reg_rsum, vgrid(a.L.N, kMgGrid), dim3(kMgT), 0, st, a, M.rparts);
     hipLaunchKernelGGL(k_reg_solve, dim3(1, a.nsys), dim3(kMgT), 0, st, a, M.rparts, M.einv, M.rsize, M.ry, M.rcorr);
 }
 
@@ -3363,6 +3445,7 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 0);
     if (ev) (void)hipEventRecord(ev[2], st);
+    const bool upd1 = B == 1 && !fused_update(tg) && M.lv.size() > 1 && a.L.N * 8 < (int64_t(1) << 31);
     if (fused_update(tg)) {   // r, x and the V-cycle's first sweep + residual in one pass; r alternates buffers
         double* r_old = par ? M.pr2 : M.pr;
         double* r_new = par ? M.pr : M.pr2;
@@ -3371,13 +3454,16 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
         else
             launch_tile<kTUpdResid, B>(M, tg, st, r_old, a.q, nullptr, M.lv[0].r, r_new, a.x, a.pn);
         a.r = r_new;
+    } else if (upd1) {   // one right-hand side: update, first sweep and region sums in one pass over r
+        hipLaunchKernelGGL(k_mgp_update_first, vgrid(a.L.N, kMgGrid), dim3(kMgT), 0, st, a, level_args(M, 0),
+                           M.lv[0].x, M.rparts);
     } else {
         hipLaunchKernelGGL(k_mgp_update<B>, g, dim3(kMgT), 0, st, a);
     }
     if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 1);
-    region_solve<B>(M, a, st);
-    vcycle<B>(M, st, tg, ev ? ev + 4 : nullptr, a.r, fused_update(tg), p32);
+    region_solve<B>(M, a, st, upd1);
+    vcycle<B>(M, st, tg, ev ? ev + 4 : nullptr, a.r, fused_update(tg), p32, upd1);
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 2);
 }
 
@@ -3812,9 +3898,9 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
                 QPAT_TRY(dalloc(c, &L.W, nsys * L.N * 8));
                 QPAT_TRY(dalloc(c, &L.W32, nsys * L.N * 8));
             }
-            if (op == Op::Prior && l == 0 && L.kind == 1) {
-                QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kFullRow));
-                QPAT_TRY(dalloc(c, &L.Uf32, nsys * L.N * kFullRow));
+            if (op == Op::Prior && l == 0 && L.kind == 1) {   // entry-major upper rows (kind 3) and in FP32 (kind 5)
+                QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kUpRow));
+                QPAT_TRY(dalloc(c, &L.Uf32, nsys * L.N * kUpRow));
             }
             if (op == Op::K && l == 0 && L.kind == 1 && M.bmax == 16 && nl > 1 &&
                 L.N * kFullRow * (int64_t)sizeof(double) < (int64_t(1) << 31)) {   // node-major, for k_mg_prolong_smooth
@@ -3849,7 +3935,7 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
     const int nl = static_cast<int>(M.lv.size());
     M.lv[0].U = op == Op::K ? c->KU64 : c->MU64;
     M.opdep = op == Op::Prior;
-    if (M.lv[0].Uf) {   // whole rows: M_delta's walk kernels, K's fused prolongation + sweep
+    if (M.lv[0].Uf) {   // M_delta's walk kernels (upper rows), K's fused prolongation + sweep (whole rows)
         M.lv[0].kind = 1;
         if (op == Op::K)
             hipLaunchKernelGGL(k_mg_fullrows<false>, dim3(grid_for(M.lv[0].N, kMgT, 4096), nsys), dim3(kMgT), 0,
@@ -3858,8 +3944,8 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             hipLaunchKernelGGL(k_mg_fullrows<true>, dim3(grid_for(M.lv[0].N, kMgT, 4096), nsys), dim3(kMgT), 0,
                                c->stream, lv_args(M.lv[0]), M.lv[0].Uf);
         if (M.lv[0].Uf32)
-            hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nsys * M.lv[0].N * kFullRow, kMgT, 4096)), dim3(kMgT), 0,
-                               c->stream, M.lv[0].Uf, M.lv[0].Uf32, nsys * M.lv[0].N * kFullRow);
+            hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nsys * M.lv[0].N * kUpRow, kMgT, 4096)), dim3(kMgT), 0,
+                               c->stream, M.lv[0].Uf, M.lv[0].Uf32, nsys * M.lv[0].N * kUpRow);
         if (M.lv[0].Ufk32)
             hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nsys * M.lv[0].N * kFullRow, kMgT, 4096)), dim3(kMgT), 0,
                                c->stream, M.lv[0].Uf, M.lv[0].Ufk32, nsys * M.lv[0].N * kFullRow);
