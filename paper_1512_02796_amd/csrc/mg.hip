@@ -5,7 +5,8 @@
 // each block of M_delta (Sec. 4 eqs. (4.5), (4.8)) are SPD FEM matrices on the
 // node lattice. Their solves are PCG preconditioned by one symmetric V-cycle:
 //   * levels: the lattice and its vertex-centred coarsenings, n -> n/2 + 1 per
-//     axis, down to at most kMgCoarse nodes per axis;
+//     axis, down to the first coarse level of at most kMgDenseK nodes (or at
+//     most kMgCoarse nodes per axis);
 //   * prolongation P: trilinear interpolation (weights 1, 1/2 per axis),
 //     restriction P^T;
 //   * coarse operators by Galerkin products A_c = P^T A P, stored like the fine
@@ -15,7 +16,8 @@
 //     bound: the first-degree Chebyshev weight for the interval [g/4, g] that
 //     the sweep has to damp; 19/(10 g) on the coarse levels (w lambda < 2
 //     keeps the cycle SPD);
-//   * coarsest level: the explicit inverse (dense, computed on the host).
+//   * coarsest level: the explicit inverse (dense; on the host up to order
+//     kMgHostDense, on the GPU above).
 // Vectors hold B right-hand sides interleaved ([sys][N][B]); every lane
 // (system, right-hand side) has its own PCG scalars and stops on its own.
 // With deflation (M_delta: the exact eigenpair (delta, 1) of each block) the
@@ -124,7 +126,7 @@ struct MgState {
 namespace {
 
 constexpr int kMgCoarse = 5;      // coarsest lattice: at most this many nodes per axis, or
-constexpr int64_t kMgDenseK = 1000;   // K: the first coarse level of at most this many nodes
+constexpr int64_t kMgDenseK = 1000;   // the first coarse level of at most this many nodes
 constexpr int64_t kMgHostDense = 256;   // coarsest inverses up to this order on the host, larger ones on the GPU
 constexpr int kMgNu = 1;          // Jacobi sweeps before and after the coarse correction
 constexpr int kMgBlocks = 2048;   // most blocks of a kernel that writes partial sums (8 per CU)
@@ -3850,10 +3852,10 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             kuhn = c->lat.dx[j] == kKx[j] && c->lat.dy[j] == kKy[j] && c->lat.dz[j] == kKz[j];
         L0.kind = kuhn ? 1 : 0;
         M.lv.push_back(L0);
-        // K stops at the first coarse level small enough for a dense inverse (the
-        // levels below it cost a launch each for almost no work); M_delta at kMgCoarse
+        // stop at the first coarse level small enough for a dense inverse (the
+        // levels below it cost a launch each for almost no work)
         while (std::max(M.lv.back().nx, std::max(M.lv.back().ny, M.lv.back().nz)) > kMgCoarse &&
-               !(op == Op::K && M.lv.size() >= 2 && M.lv.back().N <= kMgDenseK)) {
+               !(M.lv.size() >= 2 && M.lv.back().N <= kMgDenseK)) {
             const MgLevel& F = M.lv.back();
             MgLevel C;
             C.nx = F.nx > 2 ? F.nx / 2 + 1 : F.nx;
