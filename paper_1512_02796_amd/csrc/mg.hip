@@ -708,7 +708,7 @@ struct SmArgs {
 template <int B>
 __global__ __launch_bounds__(kMgT) void k_mg_first(SmArgs a, const double* __restrict__ b, double* __restrict__ x) {
     const int k = threadIdx.x % B;
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         if (!a.sc[sys * B + k].active) continue;
         const double w = a.w[sys * a.nlev + a.lev];
         const int64_t o = sys * a.L.N * B;
@@ -729,7 +729,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_smooth(SmArgs a, const double* __re
     __shared__ double sm[(kMgT / 64) * 16];
     const int v = threadIdx.x % Pk<B>::BV;
     const int32_t M1 = a.L.m + 1;
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         const double w = a.w[sys * a.nlev + a.lev];
         const double* U = rows_of<KIND>(a.L, sys);
         const double* dinv = a.dinv + sys * a.L.N;
@@ -767,7 +767,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_resid(SmArgs a, const double* __res
     constexpr int V = Pk<B>::V;
     const int v = threadIdx.x % Pk<B>::BV;
     const int32_t M1 = a.L.m + 1;
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         if (!pair_active<B>(a.sc, sys, v)) continue;
         const double* U = rows_of<KIND>(a.L, sys);
         const int64_t o = sys * a.L.N * B + v * V;
@@ -806,7 +806,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
     constexpr int V = Pk<B>::V;
     const int v = threadIdx.x % Pk<B>::BV;
     const int64_t Nf = (int64_t)nx * ny * nz, Nc = c.L.N;
-    for (int sys = 0; sys < c.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < c.nsys; sys += gridDim.y) {
         if (!pair_active<B>(c.sc, sys, v)) continue;
         const double w = c.w[sys * c.nlev + c.lev];
         const double* dinv = c.dinv + sys * Nc;
@@ -873,7 +873,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
     constexpr int V = Pk<B>::V;
     const int v = threadIdx.x % Pk<B>::BV;
     const int64_t Nf = f.L.N, Nc = (int64_t)cx * cy * cz;
-    for (int sys = 0; sys < f.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < f.nsys; sys += gridDim.y) {
         if (!pair_active<B>(f.sc, sys, v)) continue;
         const double w = f.w[sys * f.nlev + f.lev];
         const double* dinv = f.dinv + sys * Nf;
@@ -1017,7 +1017,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_dir(PcgMg a) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V, BV = Pk<B>::BV;
     const int v = threadIdx.x % BV;
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         const LaneScal<B> s(a.sc, sys, v);
         if (!s.on0 && !s.on1) continue;
         const int64_t o = sys * a.L.N * B + v * V;
@@ -1044,7 +1044,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_spmv(PcgMg a) {
     __shared__ double sm[(kMgT / 64) * 16];
     const int v = threadIdx.x % Pk<B>::BV;
     const int32_t M1 = a.L.m + 1;
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         const double* U = rows_of<KIND>(a.L, sys);
         const int64_t o = sys * a.L.N * B + v * V;
         const double* ps = a.pn + o;
@@ -1069,7 +1069,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_update(PcgMg a) {
     constexpr int V = Pk<B>::V, BV = Pk<B>::BV;
     __shared__ double sm[(kMgT / 64) * 16];
     const int v = threadIdx.x % BV;
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         const LaneScal<B> s(a.sc, sys, v);
         const int64_t o = sys * a.L.N * B + v * V;
         T rr = 0.0;
@@ -1173,7 +1173,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_scalars(PcgMg a, int phase) {
 // its nodes into kRegMax register accumulators, then fixed-order block sums.
 __global__ __launch_bounds__(kMgT) void k_reg_rsum(PcgMg a, double* __restrict__ rparts) {
     __shared__ double sm[(kMgT / 64) * kRegMax];
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         if (!a.sc[sys].active) continue;   // uniform over the block
         double acc[kRegMax];
 #pragma unroll
@@ -1229,7 +1229,7 @@ __global__ __launch_bounds__(kMgT, 4) void k_mgp_update_first(PcgMg a, SmArgs s,
                                                            double* __restrict__ rparts) {
     __shared__ double sm[(kMgT / 64) * kRegMax];
     const int64_t n = a.L.N, stride = (int64_t)gridDim.x * kMgT;
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         const MgScal& sc = a.sc[sys];
         const bool regions = a.kreg > 0;
         double rr = 0.0, acc[kRegMax];
@@ -1495,7 +1495,7 @@ __global__ __launch_bounds__(kMgT) void k_reg_e(LvArgs L, const int32_t* __restr
 template <int B>
 __global__ __launch_bounds__(kMgT) void k_mgp_bstats(PcgMg a, const double* __restrict__ b) {
     __shared__ double sm[(kMgT / 64) * 16];
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         const int64_t o = sys * a.L.N * B;
         double s1 = 0.0, s2 = 0.0;
         QPAT_MG_ELEMS(e, a.L.N * B) {
@@ -1536,7 +1536,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_init(PcgMg a, double inv_delta) {
 template <int B>
 __global__ __launch_bounds__(kMgT) void k_mgp_start0(PcgMg a, const double* __restrict__ b) {
     __shared__ double sm[(kMgT / 64) * 16];
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         const int64_t o = sys * a.L.N * B;
         double s1 = 0.0, s2 = 0.0;
         QPAT_MG_ELEMS(e, a.L.N * B) {
@@ -1559,7 +1559,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_start0(PcgMg a, const double* __re
 template <int B>
 __global__ __launch_bounds__(kMgT) void k_mgp_start(PcgMg a, double* __restrict__ b, int has_x0) {
     const int k = threadIdx.x % B;
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         const MgScal& s = a.sc[sys * B + k];
         const double m = s.c;
         const bool keep = has_x0 && s.active;
@@ -1581,7 +1581,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_true(PcgMg a, const double* __rest
     __shared__ double sm[(kMgT / 64) * 16];
     const int v = threadIdx.x % Pk<B>::BV;
     const int32_t M1 = a.L.m + 1;
-    for (int sys = 0; sys < a.nsys; ++sys) {
+    for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         const double* U = a.L.U + sys * a.L.N * M1;   // upper rows: the compensated sum walks the offset table
         const int64_t o = sys * a.L.N * B + v * V;
         const double* bs = b + o;
@@ -2789,11 +2789,16 @@ void launch_smooth(int kind, dim3 g, hipStream_t st, const SmArgs& a, const doub
     }
 }
 
+// one grid row per system (blockIdx.y) for one right-hand side per thread: the
+// systems' sweeps then run side by side instead of one after the other in
+// each block (the one-right-hand-side kernels are latency-bound)
+inline dim3 sys_rows(dim3 g, int B, int nsys) { return dim3(g.x, B == 1 ? nsys : 1); }
+
 // grid of the stencil and V-cycle kernels of a level with n nodes
 template <int B>
-dim3 sgrid(int64_t n) {
+dim3 sgrid(int64_t n, int nsys = 1) {
     // one right-hand side per thread (the M_delta solves) is latency-bound: more blocks
-    return vgrid(n * Pk<B>::BV, B == 1 ? kMgBlocks : kMgGrid);
+    return sys_rows(vgrid(n * Pk<B>::BV, B == 1 ? kMgBlocks : kMgGrid), B, nsys);
 }
 
 template <int MODE, int B, bool Z32 = false, bool P32 = false>
@@ -3307,10 +3312,10 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         const MgLevel& L = M.lv[l];
         const MgLevel& C = M.lv[l + 1];
         const SmArgs a = sm(l);
-        const dim3 g = sgrid<B>(L.N);
+        const dim3 g = sgrid<B>(L.N, M.nsys);
         const double* bl = l == 0 ? r0 : L.b;
         if (l == 0 && !fused0 && !first_done)
-            hipLaunchKernelGGL(k_mg_first<B>, vgrid(L.N * B), dim3(kMgT), 0, st, a, r0, xl[0]);
+            hipLaunchKernelGGL(k_mg_first<B>, sys_rows(vgrid(L.N * B), B, M.nsys), dim3(kMgT), 0, st, a, r0, xl[0]);
         for (int k = 1; k < kMgNu; ++k) {
             launch_smooth<B, false>(vkind(L), g, st, a, bl, xl[l], tl[l], nullptr);
             std::swap(xl[l], tl[l]);
@@ -3332,10 +3337,10 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         else if (M.opdep)
             // (the FP64 copy holds the same rounded values; the restriction measured
             // slower reading the FP32 copy: 135 against 71 us per V-cycle at 128^3)
-            hipLaunchKernelGGL((k_mg_restrict<B, true, double>), sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx,
+            hipLaunchKernelGGL((k_mg_restrict<B, true, double>), sgrid<B>(C.N, M.nsys), dim3(kMgT), 0, st, sm(l + 1), L.nx,
                                L.ny, L.nz, L.r, C.b, xl[l + 1], L.W);
         else
-            hipLaunchKernelGGL((k_mg_restrict<B, false>), sgrid<B>(C.N), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny,
+            hipLaunchKernelGGL((k_mg_restrict<B, false>), sgrid<B>(C.N, M.nsys), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny,
                                L.nz, L.r, C.b, xl[l + 1], static_cast<const double*>(nullptr));
     }
     const MgLevel& K = M.lv[nl - 1];
@@ -3346,7 +3351,7 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         const MgLevel& L = M.lv[l];
         const MgLevel& C = M.lv[l + 1];
         const SmArgs a = sm(l);
-        const dim3 g = sgrid<B>(L.N);
+        const dim3 g = sgrid<B>(L.N, M.nsys);
         const double* bl = l == 0 ? r0 : L.b;
         if (l == 0 && z32_path<B>(M, tg)) {   // prolongation fused into the last sweep (z in FP32)
             if (ev) (void)hipEventRecord(ev[2], st);
@@ -3419,7 +3424,8 @@ template <int B>
 void region_solve(const MgState& M, const PcgMg& a, hipStream_t st, bool sums_done = false) {
     if (a.kreg <= 0) return;
     // each block reduces kRegMax sums: fewer, fuller blocks than the walk kernels
-    if (!sums_done) hipLaunchKernelGGL(k_reg_rsum, vgrid(a.L.N, kMgGrid), dim3(kMgT), 0, st, a, M.rparts);
+    if (!sums_done)
+        hipLaunchKernelGGL(k_reg_rsum, sys_rows(vgrid(a.L.N, kMgGrid), B, a.nsys), dim3(kMgT), 0, st, a, M.rparts);
     hipLaunchKernelGGL(k_reg_solve, dim3(1, a.nsys), dim3(kMgT), 0, st, a, M.rparts, M.einv, M.rsize, M.ry, M.rcorr);
 }
 
@@ -3431,7 +3437,7 @@ void region_solve(const MgState& M, const PcgMg& a, hipStream_t st, bool sums_do
 template <int B>
 void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int par, hipEvent_t* ev = nullptr) {
     if (par) std::swap(a.po, a.pn);
-    const dim3 g = sgrid<B>(a.L.N), lanes(1, a.nsys * B);
+    const dim3 g = sgrid<B>(a.L.N, a.nsys), lanes(1, a.nsys * B);
     if (ev) (void)hipEventRecord(ev[0], st);
     const bool p32 = a.p32 && z32_path<B>(M, tg);   // mixed precision: the direction in FP32
     if (tg.on && p32) {
@@ -3457,7 +3463,8 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
             launch_tile<kTUpdResid, B>(M, tg, st, r_old, a.q, nullptr, M.lv[0].r, r_new, a.x, a.pn);
         a.r = r_new;
     } else if (upd1) {   // one right-hand side: update, first sweep and region sums in one pass over r
-        hipLaunchKernelGGL(k_mgp_update_first, vgrid(a.L.N, kMgGrid), dim3(kMgT), 0, st, a, level_args(M, 0),
+        hipLaunchKernelGGL(k_mgp_update_first, sys_rows(vgrid(a.L.N, kMgGrid), B, a.nsys), dim3(kMgT), 0, st, a,
+                           level_args(M, 0),
                            M.lv[0].x, M.rparts);
     } else {
         hipLaunchKernelGGL(k_mgp_update<B>, g, dim3(kMgT), 0, st, a);
@@ -3475,7 +3482,7 @@ void true_residual(const MgState& M, const PcgMg& a, const TileGeo& tg, const do
     if (tg.on)
         launch_tile<kTTrue, B>(M, tg, st, a.x, nullptr, b, a.r, nullptr);
     else
-        QPAT_MG_KIND(a.L.kind, B, k_mgp_true, sgrid<B>(a.L.N), dim3(kMgT), 0, st, a, b);
+        QPAT_MG_KIND(a.L.kind, B, k_mgp_true, sgrid<B>(a.L.N, a.nsys), dim3(kMgT), 0, st, a, b);
 }
 
 template <int B>
@@ -3483,7 +3490,7 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
     MgState& M = *state_of(c, op);
     hipStream_t sm = c->stream;
     const int S = M.nsys * B;
-    const dim3 g = sgrid<B>(c->N), lanes(1, S);
+    const dim3 g = sgrid<B>(c->N, M.nsys), lanes(1, S);
     const PcgMg a = pcg_args<B>(c, op);
     QPAT_TRY(tile_setup<B>(c, M));
     const TileGeo tg = M.tiles[B];
