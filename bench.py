@@ -68,12 +68,13 @@ MG_KERNELS = {
     "K_mg_smooth0": ("k_mg_tile<2,16>", 3, True, True),      # read x, r; write z
 }
 # on the tiled path counter 5 times the update fused with the finest-level
-# residual (counter 6 then stays empty): read r, q, x, p; write r', x, and
-# r' - A (w D^-1 r') in FP32 (half a vector),
+# residual (counter 6 then stays empty): read r, q; write r' and
+# r' - A (w D^-1 r') in FP32 (half a vector); x is not touched there (the
+# iterations keep their directions, and x is formed once per solve from them),
 # and counter 7 the prolongation fused with the last sweep: read r, level 1's x
 # (1/8 vector), the whole stencil rows (16 FP32 values a node: the bytes of the
 # stored form); write z in FP32 (half a vector)
-MG_FUSED_UPDATE = ("k_mg_tile<6,16>", 6.5, 1, True)
+MG_FUSED_UPDATE = ("k_mg_tile<6,16>", 3.5, 1, True)
 MG_FUSED_SMOOTH = ("k_mg_prolong_smooth<false>", 1.625, 1, True)
 
 
@@ -81,11 +82,11 @@ def mg_kernel(key, kst, p32=False):
     """(rocprofv3 name, vectors, stencil, 1/a_ii) of profile counter `key`; with
     p32 (mixed precision) the direction p is read and written in FP32: half a
     vector less in the direction kernel's read of the old p and its write of
-    p, and in the update's read of p."""
+    p."""
     fused = kst["K_mg_resid0"]["launches"] == 0
     if key == "K_mg_update" and fused:
         n, v, o, d = MG_FUSED_UPDATE
-        return ("k_mg_tile<6,16,false,true>", v - 0.5, o, d) if p32 else (n, v, o, d)
+        return ("k_mg_tile<6,16,false,true>", v, o, d) if p32 else (n, v, o, d)
     if key == "K_mg_smooth0" and fused:   # mixed precision stages its x0 in FP32 (same HBM bytes)
         n, v, o, d = MG_FUSED_SMOOTH
         return ("k_mg_prolong_smooth<true>", v, o, d) if p32 else (n, v, o, d)
@@ -122,16 +123,18 @@ def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled2
     z and the last sweep's whole rows), with the measured PCG iteration counts.
     Per multigrid-PCG iteration (levels N_0 > N_1 > ...):
       finest level: direction + product 3.5 V_0 + rows, update + first residual
-        6.5 V_0 + rows + 1/a_ii, restriction 0.5 V_0 + 2 V_1, prolongation +
+        3.5 V_0 + rows + 1/a_ii, restriction 0.5 V_0 + 2 V_1, prolongation +
         last sweep 1.5 V_0 + V_1 + whole FP32 rows (16 a node) + 1/a_ii;
       coarse level l: residual 3 V_l + rows, restriction V_l + 2 V_l+1,
         prolongation 2 V_l + V_l+1, sweep 3 V_l + rows (27-point rows: 32
         doubles a node on tiled levels, 27 elsewhere); coarsest: its dense
         inverse (N_c^2 doubles) and 2 V_c.
-    Mixed precision (p32): the direction in FP32 takes 1.5 V_0 off each iteration
-    (the old p and the new p in the direction kernel, p in the update).
+    Mixed precision (p32): the direction in FP32 takes V_0 off each iteration
+    (the old p and the new p in the direction kernel).
     Per solve: start 3 V_0, the first V-cycle's finest residual 1.5 V_0 + rows,
-    one V-cycle more than iterations, the final true residual 3 V_0 + rows.
+    one V-cycle more than iterations, x formed from the kept directions (each
+    read once, V_0 or in FP32 V_0 / 2, and x read and written), the final true
+    residual 3 V_0 + rows.
     Jacobian kernels per block: J s -- dK(s) rows (80 B a node: its two
     coefficients read, 8 row entries written; the element form also reads 17 B
     a tetrahedron of connectivity and geometry class), the stencil product
@@ -155,10 +158,11 @@ def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled2
         vc += 2 * V[l] + V[l + 1] + 3 * V[l] + coarse_rows(l) + 8 * levels[l]         # up
     vc += 8 * levels[-1] ** 2 + 2 * V[-1]
     vc += 1.5 * V[0] + V[1] + whole0 + d0                                             # prolongation + last sweep
-    pcg_it = 3.5 * V[0] + rows0 + 6.5 * V[0] + rows0 + d0 - (1.5 * V[0] if p32 else 0.0)
+    pcg_it = 3.5 * V[0] + rows0 + 3.5 * V[0] + rows0 + d0 - (1.0 * V[0] if p32 else 0.0)
 
     def solve(it):
-        return 3 * V[0] + 1.5 * V[0] + rows0 + d0 + (it + 1) * vc + it * pcg_it + 3 * V[0] + rows0
+        form_x = it * (0.5 if p32 else 1.0) * V[0] + 2 * V[0]
+        return 3 * V[0] + 1.5 * V[0] + rows0 + d0 + (it + 1) * vc + it * pcg_it + form_x + 3 * V[0] + rows0
 
     if voxel:
         nv = E // 6

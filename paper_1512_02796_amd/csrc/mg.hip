@@ -104,6 +104,9 @@ struct MgState {
     double* ainv = nullptr;        // [nsys][Nc][Nc]
     double *pr = nullptr, *pa = nullptr, *pb = nullptr, *pq = nullptr;  // PCG r, p (two), q: [nsys][N][bmax]
     double* pr2 = nullptr;         // the other residual buffer of the fused update (odd iterations write r here)
+    double* pring = nullptr;       // [kRing][N][bmax] directions of the tiled iterations (FP32 or FP64 elements)
+    double* ahist = nullptr;       // [kRing][lanes] their alphas (0: the lane did not iterate)
+    int32_t* pslot = nullptr;      // iterations of the current run so far (the ring slot of the next one)
     double* parts = nullptr;       // [lanes][4][kMgBlocks]
     uint64_t* gmax = nullptr;      // [nsys][levels] Gershgorin bounds (bit patterns)
     MgScal* sc = nullptr;          // [lanes], lane = sys B + k
@@ -134,6 +137,10 @@ constexpr int kMgGrid = 512;      // blocks of the vector kernels of several rig
 constexpr int kMgT = 256;
 constexpr int kMgLanes = 32;      // systems x right-hand sides
 constexpr int kMgChunk0 = 4;      // PCG iterations before the first host check of a run
+// The tiled K iterations keep their last kRing directions and alphas instead of
+// updating x each iteration; x is formed from them before it is read (the
+// true residual) or when the ring is full.
+constexpr int kRing = 16;
 // Region coarse space of M_delta: regions are the connected components of the
 // graph of strong couplings |a_ij| > kRegTheta sqrt(a_ii a_jj); the kRegMax
 // largest with at least kRegMin nodes get an indicator vector.
@@ -975,6 +982,9 @@ struct PcgMg {
     // region coarse space (one right-hand side per system), kreg = 0: off
     int32_t kreg;
     int32_t p32;          // 1: the direction in FP32 on the tiled 16-right-hand-side path (mixed precision)
+    int32_t ring;         // kRing: directions and alphas kept in the ring (x formed later), 0: x updated each iteration
+    int32_t* slot;        // the ring's iteration counter
+    double* ahist;        // [kRing][lanes]
     const int32_t* reg;   // [nsys][N]
     const double* ry;     // [nsys][kRegMax]
     const double* rcorr;  // [nsys][2]: r.(Z y), mean(Z y)
@@ -1124,13 +1134,22 @@ __device__ void red3(const double* parts, int nb, int lane, const int (&slot)[3]
 __global__ __launch_bounds__(kMgT) void k_mgp_scalars(PcgMg a, int phase) {
     __shared__ double sm[kMgT / 64];
     const int lane = blockIdx.y;
-    if (!a.sc[lane].active) return;
+    // the direction ring: each iteration's alpha per lane (0 where the lane did
+    // not iterate), and the iteration counter, advanced once at the end of an
+    // iteration (phase 2, lane 0's block)
+    const bool on = a.sc[lane].active != 0;
+    if (a.ring > 0 && threadIdx.x == 0) {
+        if (phase == 0 && !on) a.ahist[(*a.slot % a.ring) * gridDim.y + lane] = 0.0;
+        if (phase == 2 && lane == 0) *a.slot += 1;
+    }
+    if (!on) return;
     MgScal& s = a.sc[lane];
     if (phase == 0) {
         const double pq = red(a.parts, a.nb, lane, 0, sm);
         if (threadIdx.x == 0) {
             s.pq = pq;
             s.alpha = pq != 0.0 ? s.rz / pq : 0.0;
+            if (a.ring > 0) a.ahist[(*a.slot % a.ring) * gridDim.y + lane] = s.alpha;
         }
     } else if (phase == 1) {
         const double rr = red(a.parts, a.nb, lane, 1, sm);
@@ -1514,6 +1533,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_bstats(PcgMg a, const double* __re
 __global__ __launch_bounds__(kMgT) void k_mgp_init(PcgMg a, double inv_delta) {
     __shared__ double sm[kMgT / 64];
     const int lane = blockIdx.y;
+    if (a.ring > 0 && lane == 0 && threadIdx.x == 0) *a.slot = 0;   // a run's first iteration: slot 0
     const double s1 = red(a.parts, a.nb, lane, 2, sm);
     const double s2 = red(a.parts, a.nb, lane, 3, sm);
     if (threadIdx.x == 0) {
@@ -1619,6 +1639,31 @@ __global__ __launch_bounds__(kMgT) void k_mgp_true_fin(PcgMg a, int reopen) {
 }
 
 
+// x += alpha_j p_j over the ring slots of iterations f ... s - 1, in that order
+// (the fused multiply-adds the update would have made one iteration at a
+// time), for every element of the [N][B] iterate; lanes with alpha_j = 0 did
+// not iterate then and keep x (their slot holds no direction of theirs).
+template <typename PT>
+__global__ __launch_bounds__(kMgT) void k_mgp_ring_flush(int64_t n, int B, double* __restrict__ x,
+                                                         const char* __restrict__ ring, int64_t stride,
+                                                         const double* __restrict__ ahist, int lanes, int f, int s) {
+    for (int64_t e = blockIdx.x * (int64_t)kMgT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kMgT) {
+        const int lane = static_cast<int>(e % B);
+        double av[kRing], pv[kRing];   // every slot's load in flight before the sums
+#pragma unroll
+        for (int t = 0; t < kRing; ++t) {
+            const int sl = (f + t) % kRing;
+            const bool use = f + t < s;   // uniform
+            av[t] = use ? ahist[sl * lanes + lane] : 0.0;
+            pv[t] = use ? static_cast<double>(reinterpret_cast<const PT*>(ring + sl * stride)[e]) : 0.0;
+        }
+        double xv = x[e];
+#pragma unroll
+        for (int t = 0; t < kRing; ++t) xv = av[t] != 0.0 ? xv + av[t] * pv[t] : xv;
+        x[e] = xv;
+    }
+}
+
 // ------------------------------------------------ LDS-tiled finest-level kernels
 // On the finest level of a Kuhn lattice with B >= 8 right-hand sides (the
 // K solves) the stencil products run 2.5D-tiled: a work item is a tile of
@@ -1657,8 +1702,14 @@ struct TileArgs {
     double* out2;         // kTDirSpmv: the new direction
     double* parts;        // partial sums, [lanes][4][kMgBlocks]
     const MgScal* sc;     // [B]
-    double* x3;           // kTUpdResid: the iterate (updated in place)
+    double* x3;           // kTUpdResid: the iterate (updated in place; null: x is formed from the ring)
     const double* p3;     // kTUpdResid: the direction
+    // kTDirSpmv with ring_n > 0: the old and new directions are the ring slots
+    // of iterations slot - 1 and slot (ring_stride bytes apart)
+    const int32_t* slot;
+    const char* ring;
+    int64_t ring_stride;
+    int32_t ring_n;
 };
 
 // kTDirSpmv: the PCG direction and product, p = in - c + beta in2 (in = z,
@@ -1727,6 +1778,13 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
         const bool in = pl >= 0 && pl < nz;
         return rsrc(base + (in ? (int64_t)pl * stride : 0), in ? bytes : 0u);
     };
+    if constexpr (MODE == kTDirSpmv) {
+        if (g.ring_n > 0) {   // this iteration's slot and the one before (uniform)
+            const int32_t sl = *g.slot;
+            g.in2 = reinterpret_cast<const double*>(g.ring + ((sl + g.ring_n - 1) % g.ring_n) * g.ring_stride);
+            g.out2 = reinterpret_cast<double*>(const_cast<char*>(g.ring + (sl % g.ring_n) * g.ring_stride));
+        }
+    }
     static_assert(!Z32 || MODE == kTDirSpmv, "FP32 input only for the direction + product");
     static_assert(!P32 || MODE == kTDirSpmv || MODE == kTUpdResid, "FP32 direction: direction and update only");
     // LDS node of output slot u (slots past the tile point at an interior node)
@@ -1827,6 +1885,9 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
             }
 #pragma unroll
             for (int v = 0; v < NU; ++v) ust[sl * US + tid + v * kTT] = fu[v];
+            // w / a_ii of the same plane, with the plane's other staged values:
+            // slot sl is free only after the barrier that ends the step before
+            if (UPD && tid < kTHN) dring[sl * kTHN + tid] = w * dd;
         };
         // plane z with slots (z, z+1, z-1) = (SZ0, SP0, SL0)
         auto step = [&](int z, auto SZ0, auto SP0, auto SL0) {
@@ -1930,7 +1991,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                     else
                         bstore_nt(bo, oo[u], o);
                 }
-                if constexpr (UPD) {   // x += alpha p on this plane's nodes, after the stencil work
+                if (UPD && g.x3) {   // x += alpha p on this plane's nodes, after the stencil work
                     __builtin_amdgcn_sched_barrier(0);
                     const auto bx = plane(g.x3, z, nxy * B, pv);
                     if constexpr (P32) {
@@ -1951,23 +2012,13 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
                     }
                 }
             }
-            if (UPD && tid < kTHN && z + 1 < ze) dring[sl * kTHN + tid] = w * dd;   // plane z + 2 lives in slot sl
             __syncthreads();
         };
-        auto put_d = [&](int sl) {
-            if constexpr (UPD) {
-                if (tid < kTHN) dring[sl * kTHN + tid] = w * dd;
-                __syncthreads();
-            }
-        };
         fetch(zb - 1);
-        put_d(0);
         store(0);
         fetch(zb);
-        put_d(1);
         store(1);
         fetch(zb + 1);
-        put_d(2);
         using I0 = std::integral_constant<int, 0>;
         using I1 = std::integral_constant<int, 1>;
         using I2 = std::integral_constant<int, 2>;
@@ -2801,9 +2852,18 @@ dim3 sgrid(int64_t n, int nsys = 1) {
     return sys_rows(vgrid(n * Pk<B>::BV, B == 1 ? kMgBlocks : kMgGrid), B, nsys);
 }
 
+// the direction ring of the tiled iterations, as the direction kernel reads it
+struct RingArg {
+    const int32_t* slot = nullptr;
+    const char* base = nullptr;
+    int64_t stride = 0;
+    int32_t n = 0;
+};
+
 template <int MODE, int B, bool Z32 = false, bool P32 = false>
 void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const double* in, const double* in2,
-                 const double* b, double* out, double* out2, double* x3 = nullptr, const double* p3 = nullptr) {
+                 const double* b, double* out, double* out2, double* x3 = nullptr, const double* p3 = nullptr,
+                 RingArg ring = {}) {
     if constexpr (B >= 8) {   // tile_setup turns the tiling on only there
         const MgLevel& L = M.lv[0];
         TileArgs g;
@@ -2829,6 +2889,10 @@ void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const doubl
         g.sc = M.sc;
         g.x3 = x3;
         g.p3 = p3;
+        g.slot = ring.slot;
+        g.ring = ring.base;
+        g.ring_stride = ring.stride;
+        g.ring_n = ring.n;
         hipLaunchKernelGGL((k_mg_tile<MODE, B, Z32, P32>), dim3(t.blocks), dim3(kTT), MgTile<B>::LDS, st, g);
     }
 }
@@ -3415,6 +3479,9 @@ PcgMg pcg_args(qpat_ctx* c, Op op) {
     a.reg = M.reg;
     a.ry = M.ry;
     a.rcorr = M.rcorr;
+    a.ring = 0;   // solve_B turns the direction ring on for the tiled iterations
+    a.slot = M.pslot;
+    a.ahist = M.ahist;
     return a;
 }
 
@@ -3440,12 +3507,20 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
     const dim3 g = sgrid<B>(a.L.N, a.nsys), lanes(1, a.nsys * B);
     if (ev) (void)hipEventRecord(ev[0], st);
     const bool p32 = a.p32 && z32_path<B>(M, tg);   // mixed precision: the direction in FP32
+    RingArg ring;   // the direction ring: the slots of this iteration and the one before
+    if (a.ring > 0) {
+        ring.slot = a.slot;
+        ring.base = reinterpret_cast<const char*>(M.pring);
+        ring.stride = a.L.N * B * (p32 ? 4 : 8);
+        ring.n = a.ring;
+    }
+    double* const xu = a.ring > 0 ? nullptr : a.x;   // with the ring, x is formed later (k_mgp_ring_flush)
     if (tg.on && p32) {
-        launch_tile<kTDirSpmv, B, true, true>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn);
+        launch_tile<kTDirSpmv, B, true, true>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn, nullptr, nullptr, ring);
     } else if (tg.on && z32_path<B>(M, tg)) {   // z from the fused prolongation + last sweep, FP32
-        launch_tile<kTDirSpmv, B, true>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn);
+        launch_tile<kTDirSpmv, B, true>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn, nullptr, nullptr, ring);
     } else if (tg.on) {
-        launch_tile<kTDirSpmv, B>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn);
+        launch_tile<kTDirSpmv, B>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn, nullptr, nullptr, ring);
     } else {
         hipLaunchKernelGGL(k_mgp_dir<B>, g, dim3(kMgT), 0, st, a);
         QPAT_MG_KIND(a.L.kind, B, k_mgp_spmv, g, dim3(kMgT), 0, st, a);
@@ -3458,9 +3533,9 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
         double* r_old = par ? M.pr2 : M.pr;
         double* r_new = par ? M.pr : M.pr2;
         if (p32)
-            launch_tile<kTUpdResid, B, false, true>(M, tg, st, r_old, a.q, nullptr, M.lv[0].r, r_new, a.x, a.pn);
+            launch_tile<kTUpdResid, B, false, true>(M, tg, st, r_old, a.q, nullptr, M.lv[0].r, r_new, xu, a.pn);
         else
-            launch_tile<kTUpdResid, B>(M, tg, st, r_old, a.q, nullptr, M.lv[0].r, r_new, a.x, a.pn);
+            launch_tile<kTUpdResid, B>(M, tg, st, r_old, a.q, nullptr, M.lv[0].r, r_new, xu, a.pn);
         a.r = r_new;
     } else if (upd1) {   // one right-hand side: update, first sweep and region sums in one pass over r
         hipLaunchKernelGGL(k_mgp_update_first, sys_rows(vgrid(a.L.N, kMgGrid), B, a.nsys), dim3(kMgT), 0, st, a,
@@ -3491,9 +3566,42 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
     hipStream_t sm = c->stream;
     const int S = M.nsys * B;
     const dim3 g = sgrid<B>(c->N, M.nsys), lanes(1, S);
-    const PcgMg a = pcg_args<B>(c, op);
+    PcgMg a = pcg_args<B>(c, op);
     QPAT_TRY(tile_setup<B>(c, M));
     const TileGeo tg = M.tiles[B];
+    // The tiled iterations keep their directions and alphas in a ring and form
+    // x = x + sum alpha_j p_j (k_mgp_ring_flush) before x is read: the update
+    // then neither reads nor writes x nor reads p.
+    if (fused_update(tg)) {
+        if (!M.pring) {
+            const size_t n = (size_t)kRing * c->N * M.bmax;   // FP64-sized slots
+            QPAT_TRY(dalloc(c, &M.pring, n));
+            QPAT_TRY(dalloc(c, &M.ahist, (size_t)kRing * kMgLanes));
+            QPAT_TRY(dalloc(c, &M.pslot, 1));
+            // finite values in the slots of lanes that stopped (their alpha is 0)
+            QPAT_HIP(c, hipMemsetAsync(M.pring, 0, n * sizeof(double), sm));
+        }
+        a.ring = kRing;
+        a.slot = M.pslot;
+        a.ahist = M.ahist;
+    }
+    int ring_s = 0, ring_f = 0;   // iterations launched in this solve; those already added to x
+    auto ring_flush = [&]() -> qpat_status {
+        if (a.ring == 0 || ring_s == ring_f) return QPAT_OK;
+        const int64_t n = c->N * (int64_t)B;
+        const bool p32r = a.p32 && z32_path<B>(M, tg);
+        const int64_t stride = n * (p32r ? 4 : 8);
+        const char* base = reinterpret_cast<const char*>(M.pring);
+        if (p32r)
+            hipLaunchKernelGGL(k_mgp_ring_flush<float>, vgrid(n, kMgBlocks), dim3(kMgT), 0, sm, n, B, a.x, base, stride,
+                               M.ahist, S, ring_f, ring_s);
+        else
+            hipLaunchKernelGGL(k_mgp_ring_flush<double>, vgrid(n, kMgBlocks), dim3(kMgT), 0, sm, n, B, a.x, base, stride,
+                               M.ahist, S, ring_f, ring_s);
+        ring_f = ring_s;
+        QPAT_HIP(c, hipGetLastError());
+        return QPAT_OK;
+    };
     if (tg.on && !a.deflate && !has_x0) {   // one pass over b
         hipLaunchKernelGGL(k_mgp_start0<B>, g, dim3(kMgT), 0, sm, a, c->b64);
         hipLaunchKernelGGL(k_mgp_init, lanes, dim3(kMgT), 0, sm, a, c->delta > 0 ? 1.0 / c->delta : 0.0);
@@ -3556,6 +3664,9 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
                 iters_before[i] = M.sc_host[i].iters;
                 rr_before[i] = M.sc_host[i].rr;
             }
+            // the chunk writes ring slots ring_s ... ring_s + chunk - 1: those not yet in x must survive
+            if (a.ring > 0 && ring_s + chunk - ring_f > kRing) QPAT_TRY(ring_flush());
+            ring_s += chunk;
             const bool prof = c->prof_on;
             if (prof) {
                 if (M.ev.size() < (size_t)8 * chunk) {
@@ -3613,6 +3724,7 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
             QPAT_HIP(c, hipGetLastError());
         }
         // confirm on the true residual; a failed check restarts from the true residual
+        QPAT_TRY(ring_flush());
         true_residual<B>(M, a, tg, c->b64, sm);
         hipLaunchKernelGGL(k_mgp_true_fin, lanes, dim3(kMgT), 0, sm, a, restart < 3 ? 1 : 0);
         QPAT_HIP(c, hipGetLastError());

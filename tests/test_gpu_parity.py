@@ -52,6 +52,22 @@ def test_forward_parity(name, block, precision):
     assert info["n_solves"] >= G.n_ill
 
 
+def test_direction_ring_past_its_length():
+    """The tiled K iterations keep their directions and alphas (a ring of 16)
+    and form x from them before the true residual; a solve longer than the ring
+    forms x in the middle of the run as well. pcg_rtol 1e-14 takes T24 (blocks
+    of 8, tiled) past 16 iterations: the result matches the oracle, and the
+    same solve run again is bitwise the same."""
+    G = GpuProblem("T24", opts(max_rhs_block=8, pcg_rtol=1e-14))
+    phi, h, info = G.forward()
+    assert info["iters_max"] > 16, info["iters_max"]
+    assert info["relres_max"] <= 1e-14
+    g, lin = oracle_of(G.P)
+    assert_close(host(phi), lin.phi, 1e-10, "phi T24, rtol 1e-14")
+    phi2, _, _ = G.forward()
+    assert torch.equal(phi, phi2)
+
+
 @pytest.mark.parametrize("name,block,precision", [("T8", 4, 0), ("T12", 1, 0), ("T24", 8, 0),
                                                   ("T12", 4, 1), ("T24", 8, 1)])
 def test_jvp_vjp_parity(name, block, precision):
