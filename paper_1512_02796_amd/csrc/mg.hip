@@ -1642,25 +1642,49 @@ __global__ __launch_bounds__(kMgT) void k_mgp_true_fin(PcgMg a, int reopen) {
 // x += alpha_j p_j over the ring slots of iterations f ... s - 1, in that order
 // (the fused multiply-adds the update would have made one iteration at a
 // time), for every element of the [N][B] iterate; lanes with alpha_j = 0 did
-// not iterate then and keep x (their slot holds no direction of theirs).
+// not iterate then and keep x (their slot holds no direction of theirs). A
+// thread takes the V elements of one 16-byte load of a direction (4 in FP32,
+// 2 in FP64; B is a multiple of V), every slot's load in flight before the
+// sums; the alphas of all slots are staged in LDS.
 template <typename PT>
 __global__ __launch_bounds__(kMgT) void k_mgp_ring_flush(int64_t n, int B, double* __restrict__ x,
                                                          const char* __restrict__ ring, int64_t stride,
                                                          const double* __restrict__ ahist, int lanes, int f, int s) {
-    for (int64_t e = blockIdx.x * (int64_t)kMgT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kMgT) {
-        const int lane = static_cast<int>(e % B);
-        double av[kRing], pv[kRing];   // every slot's load in flight before the sums
+    constexpr int V = 16 / sizeof(PT);
+    typedef PT PV __attribute__((ext_vector_type(V)));
+    typedef double XV __attribute__((ext_vector_type(2)));
+    __shared__ double al[kRing * kMgLanes];
+    for (int i = threadIdx.x; i < kRing * lanes; i += kMgT) al[i] = ahist[i];
+    __syncthreads();
+    const int64_t nq = n / V;
+    for (int64_t q = blockIdx.x * (int64_t)kMgT + threadIdx.x; q < nq; q += (int64_t)gridDim.x * kMgT) {
+        const int64_t e0 = q * V;
+        const int lane0 = static_cast<int>(e0 % B);
+        PV pv[kRing];
 #pragma unroll
         for (int t = 0; t < kRing; ++t) {
             const int sl = (f + t) % kRing;
-            const bool use = f + t < s;   // uniform
-            av[t] = use ? ahist[sl * lanes + lane] : 0.0;
-            pv[t] = use ? static_cast<double>(reinterpret_cast<const PT*>(ring + sl * stride)[e]) : 0.0;
+            pv[t] = f + t < s ? *reinterpret_cast<const PV*>(ring + sl * stride + e0 * (int64_t)sizeof(PT)) : PV{};
         }
-        double xv = x[e];
+        double xv[V];
 #pragma unroll
-        for (int t = 0; t < kRing; ++t) xv = av[t] != 0.0 ? xv + av[t] * pv[t] : xv;
-        x[e] = xv;
+        for (int c = 0; c < V; c += 2) {
+            const XV t2 = *reinterpret_cast<const XV*>(x + e0 + c);
+            xv[c] = t2.x;
+            xv[c + 1] = t2.y;
+        }
+#pragma unroll
+        for (int t = 0; t < kRing; ++t) {
+            if (f + t >= s) break;   // uniform
+            const double* at = al + ((f + t) % kRing) * lanes + lane0;
+#pragma unroll
+            for (int c = 0; c < V; ++c) {
+                const double a = at[c];
+                xv[c] = a != 0.0 ? xv[c] + a * static_cast<double>(pv[t][c]) : xv[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < V; c += 2) *reinterpret_cast<XV*>(x + e0 + c) = XV{xv[c], xv[c + 1]};
     }
 }
 
@@ -3592,6 +3616,7 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
         const bool p32r = a.p32 && z32_path<B>(M, tg);
         const int64_t stride = n * (p32r ? 4 : 8);
         const char* base = reinterpret_cast<const char*>(M.pring);
+        if (B % (p32r ? 4 : 2) != 0) return fail(c, QPAT_ERR_STATE, "multigrid: direction ring with %d right-hand sides", B);
         if (p32r)
             hipLaunchKernelGGL(k_mgp_ring_flush<float>, vgrid(n, kMgBlocks), dim3(kMgT), 0, sm, n, B, a.x, base, stride,
                                M.ahist, S, ring_f, ring_s);
