@@ -423,6 +423,38 @@ __device__ double resid_comp(const LvArgs& L, const double* __restrict__ U, cons
     return r.value();
 }
 
+// The same for a stencil form of 7 offsets (the Kuhn lattice), all loads in
+// flight before the sums: indices clamped to the node itself and the terms of
+// neighbours off the lattice replaced by 0 * 0, which the compensated sum
+// takes exactly (so the value is bitwise that of resid_comp).
+template <int B>
+__device__ double resid_comp7(const LvArgs& L, const double* __restrict__ U, const double* __restrict__ x, double bi,
+                              int32_t ix, int32_t iy, int32_t iz, int32_t i) {
+    constexpr int32_t M1 = 8;
+    double cu[7], xu[7], cl[7], xl[7];
+    const double c0 = U[i * M1], x0 = x[i * B];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        const int4 t = L.tab[j];
+        const bool up = ix + t.x >= 0 && ix + t.x < L.nx && iy + t.y >= 0 && iy + t.y < L.ny && iz + t.z < L.nz;
+        const bool lo = ix - t.x >= 0 && ix - t.x < L.nx && iy - t.y >= 0 && iy - t.y < L.ny && iz - t.z >= 0;
+        const int32_t iu = up ? i + t.w : i, il = lo ? i - t.w : i;
+        const double a = U[i * M1 + j + 1], xa = x[iu * B], c = U[il * M1 + j + 1], xc = x[il * B];
+        cu[j] = up ? a : 0.0;
+        xu[j] = up ? xa : 0.0;
+        cl[j] = lo ? c : 0.0;
+        xl[j] = lo ? xc : 0.0;
+    }
+    CompSum r(bi);
+    r.sub(c0, x0);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        r.sub(cu[j], xu[j]);
+        r.sub(cl[j], xl[j]);
+    }
+    return r.value();
+}
+
 // plain grid-stride loop over n elements (one right-hand side each; the lane
 // of a thread is threadIdx.x mod B)
 #define QPAT_MG_ELEMS(e, n) \
@@ -1611,7 +1643,14 @@ __global__ __launch_bounds__(kMgT) void k_mgp_true(PcgMg a, const double* __rest
         walk<Pk<B>::BV>(a.L.nx, a.L.ny, a.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
             const T bi = vld<T>(bs + i * B);
             T ri;
-            if constexpr (V == 2) {
+            if (a.L.m == 7) {   // uniform: the loads of a row all in flight
+                if constexpr (V == 2) {
+                    ri.x = resid_comp7<B>(a.L, U, xs, bi.x, ix, iy, iz, i);
+                    ri.y = resid_comp7<B>(a.L, U, xs + 1, bi.y, ix, iy, iz, i);
+                } else {
+                    ri = resid_comp7<B>(a.L, U, xs, bi, ix, iy, iz, i);
+                }
+            } else if constexpr (V == 2) {
                 ri.x = resid_comp<B>(a.L, U, xs, bi.x, ix, iy, iz, i);
                 ri.y = resid_comp<B>(a.L, U, xs + 1, bi.y, ix, iy, iz, i);
             } else {
