@@ -80,17 +80,38 @@ __global__ __launch_bounds__(kThreads) void k_conv(Lat L, const uint16_t* __rest
         const int x = static_cast<int>(v % L.nx);
         const int y = static_cast<int>((v / L.nx) % L.ny);
         const int z = static_cast<int>(v / ((int64_t)L.nx * L.ny));
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int m = 0; m < NCH; ++m) {
+        // every tap's A fragment first, then the chain of MFMAs: the loads
+        // are in flight together instead of each waiting for the MFMA before
+        // it. Buffer loads with 32-bit offsets (V CIN 2 < 2^31 bytes, checked
+        // on the host); a tap outside the lattice reads 0 (offset kOut).
+        const auto bx = rsrc(X, static_cast<uint32_t>(L.V * CIN * 2));
+        auto tap = [&](int m) {
             const int t = CIN == 16 ? m : 4 * m + g;
             const int ci0 = CIN == 16 ? 4 * g : 0;
-            s4 a = {0, 0, 0, 0};
-            if (vok && t < 27) {
-                const int64_t nb = neighbour(L, x, y, z, t);
-                if (nb >= 0) a = *reinterpret_cast<const s4*>(X + nb * CIN + ci0);
+            const int64_t nb = vok && t < 27 ? neighbour(L, x, y, z, t) : -1;
+            const uint32_t off = nb >= 0 ? static_cast<uint32_t>(nb * CIN + ci0) * 2u : kOut;
+            return bload<s4>(bx, off);
+        };
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        // taps in groups of one z-plane (9), the loads of the next group issued
+        // before the MFMAs of this one (a two-group pipeline keeps the
+        // registers, and so the waves per SIMD, in bounds)
+        constexpr int G9 = NCH >= 9 ? 9 : NCH;
+        s4 cur[G9], nxt[G9];
+#pragma unroll
+        for (int m = 0; m < G9; ++m) cur[m] = tap(m);
+#pragma unroll
+        for (int g0 = 0; g0 < NCH; g0 += G9) {
+            __builtin_amdgcn_sched_barrier(0);
+            if (g0 + G9 < NCH) {
+#pragma unroll
+                for (int m = 0; m < G9; ++m) nxt[m] = g0 + G9 + m < NCH ? tap(g0 + G9 + m) : s4{0, 0, 0, 0};
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, wsh[m][lane], acc, 0, 0, 0);
+#pragma unroll
+            for (int m = 0; m < G9; ++m)
+                if (g0 + m < NCH) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(cur[m], wsh[g0 + m][lane], acc, 0, 0, 0);
+#pragma unroll
+            for (int m = 0; m < G9; ++m) cur[m] = nxt[m];
         }
         const int co = lane % 16;
 #pragma unroll
@@ -408,6 +429,8 @@ static qpat_status guess_backward(qpat_ctx* c) {
 
 qpat_status guess_setup(qpat_ctx* c, int nx, int ny, int nz) {
     if ((int64_t)nx * ny * nz != c->N) return fail(c, QPAT_ERR_ARG, "guess_setup: nx*ny*nz must equal N");
+    if (c->N * 16 * 2 >= (int64_t(1) << 31))   // the convolutions' 32-bit buffer offsets
+        return fail(c, QPAT_ERR_ARG, "guess_setup: lattice too large for the network (N = %lld)", (long long)c->N);
     if (!c->guess) c->guess = new GuessNet();
     GuessNet* G = c->guess;
     if (G->L.V == c->N && G->params) return QPAT_OK;
