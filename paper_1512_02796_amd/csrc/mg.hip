@@ -1585,6 +1585,8 @@ __global__ __launch_bounds__(kMgT) void k_mgp_init(PcgMg a, double inv_delta) {
 // The start of a run without deflation or initial guess in one pass: r = b,
 // x = 0 and the partial sums of b and b.b that k_mgp_init reduces. (The
 // first direction of the tiled path ignores the old direction, beta = 0.)
+// With the direction ring x is not written here: its first formation starts
+// from zero.
 template <int B>
 __global__ __launch_bounds__(kMgT) void k_mgp_start0(PcgMg a, const double* __restrict__ b) {
     __shared__ double sm[(kMgT / 64) * 16];
@@ -1594,7 +1596,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_start0(PcgMg a, const double* __re
         QPAT_MG_ELEMS(e, a.L.N * B) {
             const double v = b[o + e];
             a.r[o + e] = v;
-            a.x[o + e] = 0.0;
+            if (a.ring == 0) a.x[o + e] = 0.0;
             s1 += v;
             s2 += v * v;
         }
@@ -1688,7 +1690,8 @@ __global__ __launch_bounds__(kMgT) void k_mgp_true_fin(PcgMg a, int reopen) {
 template <typename PT>
 __global__ __launch_bounds__(kMgT) void k_mgp_ring_flush(int64_t n, int B, double* __restrict__ x,
                                                          const char* __restrict__ ring, int64_t stride,
-                                                         const double* __restrict__ ahist, int lanes, int f, int s) {
+                                                         const double* __restrict__ ahist, int lanes, int f, int s,
+                                                         int x_zero) {
     constexpr int V = 16 / sizeof(PT);
     typedef PT PV __attribute__((ext_vector_type(V)));
     typedef double XV __attribute__((ext_vector_type(2)));
@@ -1707,8 +1710,8 @@ __global__ __launch_bounds__(kMgT) void k_mgp_ring_flush(int64_t n, int B, doubl
         }
         double xv[V];
 #pragma unroll
-        for (int c = 0; c < V; c += 2) {
-            const XV t2 = *reinterpret_cast<const XV*>(x + e0 + c);
+        for (int c = 0; c < V; c += 2) {   // x_zero: the run started from x = 0, not yet stored
+            const XV t2 = x_zero ? XV{0.0, 0.0} : *reinterpret_cast<const XV*>(x + e0 + c);
             xv[c] = t2.x;
             xv[c + 1] = t2.y;
         }
@@ -3649,8 +3652,10 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
         a.ahist = M.ahist;
     }
     int ring_s = 0, ring_f = 0;   // iterations launched in this solve; those already added to x
+    // the one-pass start leaves x unwritten with the ring: the first formation starts from zero
+    bool x_zero = a.ring > 0 && tg.on && !a.deflate && !has_x0;
     auto ring_flush = [&]() -> qpat_status {
-        if (a.ring == 0 || ring_s == ring_f) return QPAT_OK;
+        if (a.ring == 0 || (ring_s == ring_f && !x_zero)) return QPAT_OK;
         const int64_t n = c->N * (int64_t)B;
         const bool p32r = a.p32 && z32_path<B>(M, tg);
         const int64_t stride = n * (p32r ? 4 : 8);
@@ -3658,11 +3663,12 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
         if (B % (p32r ? 4 : 2) != 0) return fail(c, QPAT_ERR_STATE, "multigrid: direction ring with %d right-hand sides", B);
         if (p32r)
             hipLaunchKernelGGL(k_mgp_ring_flush<float>, vgrid(n, kMgBlocks), dim3(kMgT), 0, sm, n, B, a.x, base, stride,
-                               M.ahist, S, ring_f, ring_s);
+                               M.ahist, S, ring_f, ring_s, x_zero ? 1 : 0);
         else
             hipLaunchKernelGGL(k_mgp_ring_flush<double>, vgrid(n, kMgBlocks), dim3(kMgT), 0, sm, n, B, a.x, base, stride,
-                               M.ahist, S, ring_f, ring_s);
+                               M.ahist, S, ring_f, ring_s, x_zero ? 1 : 0);
         ring_f = ring_s;
+        x_zero = false;
         QPAT_HIP(c, hipGetLastError());
         return QPAT_OK;
     };
@@ -3793,6 +3799,7 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
         hipLaunchKernelGGL(k_mgp_true_fin, lanes, dim3(kMgT), 0, sm, a, restart < 3 ? 1 : 0);
         QPAT_HIP(c, hipGetLastError());
     }
+    QPAT_TRY(ring_flush());   // a run that stopped before iterating still needs its x = 0
     QPAT_TRY(fetch());
     for (int i = 0; i < S; ++i) {
         const MgScal& s = M.sc_host[i];

@@ -68,6 +68,18 @@ def test_direction_ring_past_its_length():
     assert torch.equal(phi, phi2)
 
 
+def test_zero_direction_on_the_tiled_path():
+    """J 0 = 0 exactly on the tiled K path (T24, blocks of 8): every tangent
+    right-hand side is zero, so each lane stops before iterating and x is
+    formed from no directions at all."""
+    G = GpuProblem("T24", opts(max_rhs_block=8))
+    G.forward()
+    out = torch.full((G.n_ill * G.N,), 7.0, dtype=torch.float64, device="cuda")
+    info = G.ctx.jvp(torch.zeros(2 * G.N, dtype=torch.float64, device="cuda"), out)
+    assert torch.count_nonzero(out).item() == 0
+    assert info["iters_max"] == 0
+
+
 @pytest.mark.parametrize("name,block,precision", [("T8", 4, 0), ("T12", 1, 0), ("T24", 8, 0),
                                                   ("T12", 4, 1), ("T24", 8, 1)])
 def test_jvp_vjp_parity(name, block, precision):
