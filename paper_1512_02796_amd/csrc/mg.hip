@@ -213,6 +213,26 @@ template <typename T>
 __device__ __forceinline__ void vst(double* p, T v) {
     *reinterpret_cast<T*>(p) = v;
 }
+// the same from / to FP32 storage (a coarse level's vectors kept in FP32)
+template <typename T>
+__device__ __forceinline__ T vldf(const float* p) {
+    if constexpr (sizeof(T) == 8) {
+        return static_cast<double>(*p);
+    } else {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        const f2v t = *reinterpret_cast<const f2v*>(p);
+        return T{static_cast<double>(t.x), static_cast<double>(t.y)};
+    }
+}
+template <typename T>
+__device__ __forceinline__ void vstf(float* p, T v) {
+    if constexpr (sizeof(T) == 8) {
+        *p = static_cast<float>(v);
+    } else {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        *reinterpret_cast<f2v*>(p) = f2v{static_cast<float>(v.x), static_cast<float>(v.y)};
+    }
+}
 __device__ __forceinline__ double comp(double v, int) { return v; }
 __device__ __forceinline__ double comp(d2v v, int c) { return c ? v.y : v.x; }
 
@@ -904,7 +924,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
 // x = base + P xc on fine level f (coarse lattice cx, cy, cz). base = x, or
 // with FIRST the first sweep w D^{-1} b, which is then never stored. P:
 // trilinear, or the weights Wall ([nsys][8][Nf]).
-template <int B, bool FIRST, bool OPW, typename WT = double>
+template <int B, bool FIRST, bool OPW, typename WT = double, bool XF = false>
 __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32_t cy, int32_t cz,
                                                      const double* __restrict__ xc, const double* __restrict__ b,
                                                      double* __restrict__ x, const WT* __restrict__ Wall) {
@@ -919,12 +939,19 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
         const double* xs = xc + sys * Nc * B + v * V;
         const double* bs = b + sys * Nf * B + v * V;
         double* xf = x + sys * Nf * B + v * V;
+        float* xf32 = reinterpret_cast<float*>(x) + sys * Nf * B + v * V;   // XF: the fine x in FP32
         const WT* Ws = OPW ? Wall + sys * Nf * 8 : nullptr;
         walk<Pk<B>::BV>(f.L.nx, f.L.ny, f.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
             const Span sx(ix, cx), sy(iy, cy), sz(iz, cz);
             const int32_t jx[2] = {sx.j0, sx.j1}, jy[2] = {sy.j0, sy.j1}, jz[2] = {sz.j0, sz.j1};
             const double wx[2] = {sx.w0, sx.w1}, wy[2] = {sy.w0, sy.w1}, wz[2] = {sz.w0, sz.w1};
-            T s = FIRST ? (w * dinv[i]) * vld<T>(bs + i * B) : vld<T>(xf + i * B);
+            T s;
+            if constexpr (FIRST)
+                s = (w * dinv[i]) * vld<T>(bs + i * B);
+            else if constexpr (XF)
+                s = vldf<T>(xf32 + i * B);
+            else
+                s = vld<T>(xf + i * B);
             // the 8 coarse values (and weights) first, all loads in flight together
             T cv[8];
             double wgt[8];
@@ -949,7 +976,10 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int cn = 0; cn < 8; ++cn) s += wgt[cn] * cv[cn];
-            vst<T>(xf + i * B, s);
+            if constexpr (XF)
+                vstf<T>(xf32 + i * B, s);
+            else
+                vst<T>(xf + i * B, s);
         });
     }
 }
@@ -2147,7 +2177,7 @@ struct RstArgs {
     const MgScal* sc;        // [B]
 };
 
-template <int B, bool R32>
+template <int B, bool R32, bool O32 = false>
 __global__ __launch_bounds__(kTT) void k_mg_restrict_tile(RstArgs g) {
     using TR = MgRst<B>;
     constexpr int RY = TR::RY, FX = TR::FX, FY = TR::FY, NPF = TR::NPF, RS = NPF * kTT;
@@ -2224,8 +2254,13 @@ __global__ __launch_bounds__(kTT) void k_mg_restrict_tile(RstArgs g) {
                     const double v = acc + 0.5 * s;
                     if (own) {
                         const int64_t I = (int64_t)((p - 1) / 2) * cxy + (int64_t)Iy * g.cx + Ix;
-                        g.bc[I * B + k] = v;
-                        g.xc[I * B + k] = wc * g.dinv[I] * v;
+                        if constexpr (O32) {   // the coarse level's vectors in FP32
+                            reinterpret_cast<float*>(g.bc)[I * B + k] = static_cast<float>(v);
+                            reinterpret_cast<float*>(g.xc)[I * B + k] = static_cast<float>(wc * g.dinv[I] * v);
+                        } else {
+                            g.bc[I * B + k] = v;
+                            g.xc[I * B + k] = wc * g.dinv[I] * v;
+                        }
                     }
                 }
                 acc = 0.5 * s;
@@ -2380,7 +2415,7 @@ struct Tile27Args {
     const MgScal* sc;     // [16]
 };
 
-template <int MODE, bool R32 = false>
+template <int MODE, bool R32 = false, bool V32 = false>
 __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
     constexpr int B = 16;
     constexpr int NPF = MgTile<B>::NPF, RS = NPF * kTT;
@@ -2401,6 +2436,21 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
     auto plane = [&](const double* base, int pl, uint32_t stride, uint32_t bytes) {
         const bool in = pl >= 0 && pl < nz;
         return rsrc(base + (in ? (int64_t)pl * stride : 0), in ? bytes : 0u);
+    };
+    // x, b and out of the level: V32 keeps them in FP32 (offsets halve)
+    auto vplane = [&](const double* base, int pl) {
+        if constexpr (V32) {
+            const bool in = pl >= 0 && pl < nz;
+            return rsrc(reinterpret_cast<const float*>(base) + (in ? (int64_t)pl * nxy * B : 0), in ? pv / 2 : 0u);
+        } else {
+            return plane(base, pl, nxy * B, pv);
+        }
+    };
+    auto vload = [&](__amdgpu_buffer_rsrc_t br, uint32_t o) -> double {
+        if constexpr (V32)
+            return static_cast<double>(bload<float>(br, o == kOut ? kOut : o / 2));
+        else
+            return bload<double>(br, o);
     };
     int32_t oc[NO];
 #pragma unroll
@@ -2435,9 +2485,9 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
             ro[u] = oin ? (static_cast<uint32_t>(oy * nx + ox) * kRow27 + k) * SZ : kOut;
         }
         auto fetch = [&](int pl) {
-            const auto bx = plane(g.x, pl, nxy * B, pv);
+            const auto bx = vplane(g.x, pl);
 #pragma unroll
-            for (int u = 0; u < NPF; ++u) fr[u] = bload<double>(bx, fo[u]);
+            for (int u = 0; u < NPF; ++u) fr[u] = vload(bx, fo[u]);
         };
         auto store = [&](int sl) {
 #pragma unroll
@@ -2446,14 +2496,14 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
         // the operator rows and b of plane z, loaded a plane ahead
         double ua[NO], ub[NO], bn[NO];
         auto load_node = [&](int z) {
-            const auto bb = plane(g.b, z, nxy * B, pv);
+            const auto bb = vplane(g.b, z);
             if constexpr (R32) {   // the pair (entry k, entry k + 16) as 8 bytes: the layout of a [N][16] vector
                 const auto bq = plane(reinterpret_cast<const double*>(g.Uf27p), z, nxy * B, pv);
 #pragma unroll
                 for (int u = 0; u < NO; ++u) {
                     ua[u] = bload<double>(bq, oo[u]);
                     ub[u] = 0.0;
-                    bn[u] = bload<double>(bb, oo[u]);
+                    bn[u] = vload(bb, oo[u]);
                 }
             } else {
                 const auto bu = plane(g.Uf, z, nxy * kRow27, pr);
@@ -2461,7 +2511,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
                 for (int u = 0; u < NO; ++u) {
                     ua[u] = bload<double>(bu, ro[u]);
                     ub[u] = bload<double>(bu, ro[u] == kOut ? kOut : ro[u] + 16 * SZ);
-                    bn[u] = bload<double>(bb, oo[u]);
+                    bn[u] = vload(bb, oo[u]);
                 }
             }
         };
@@ -2484,7 +2534,7 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
 #pragma unroll
                 for (int u = 0; u < NO; ++u) dc[u] = bload<double>(bd, od[u]);
             }
-            const auto bo = plane(g.out, z, nxy * B, pv);   // uniform descriptor; stopped lanes store nowhere
+            const auto bo = vplane(g.out, z);   // uniform descriptor; stopped lanes store nowhere
 #pragma unroll
             for (int u = 0; u < NO; ++u) {
                 if (tid + u * kTT >= TX * TY * B) continue;   // whole waves past the tile skip
@@ -2496,7 +2546,10 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile27(Tile27Args g) {
                     ax = apply27(ca[u], cb[u], rb, sz * RS, sp * RS, sl * RS, std::make_integer_sequence<int, 13>{});
                 double o = bc[u] - ax;
                 if constexpr (MODE == kT27Smooth) o = rb[sz * RS] + w * dc[u] * o;
-                bstore<double>(bo, act ? oo[u] : kOut, o);
+                if constexpr (V32)
+                    bstore<float>(bo, act && oo[u] != kOut ? oo[u] / 2 : kOut, static_cast<float>(o));
+                else
+                    bstore<double>(bo, act ? oo[u] : kOut, o);
             }
             __syncthreads();
         };
@@ -2583,7 +2636,7 @@ __device__ __forceinline__ float apply_kuhn16_f32(double pr, const float* rb, in
     return s;
 }
 
-template <bool F32>
+template <bool F32, bool C32 = false>
 __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
     using RT = std::conditional_t<F32, float, double>;   // x0 as staged
     constexpr int B = 16;
@@ -2655,22 +2708,28 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_prolong_smooth(PSArgs g) {
             return e < kPCN && X >= 0 && X < g.cx && Y >= 0 && Y < g.cy
                        ? (static_cast<uint32_t>(Y * g.cx + X) * B + (e % B)) * SZ : kOut;
         };
+        // coarse plane Z of level 1's x (C32: stored in FP32)
+        auto load_coarse = [&](int Z) {
+            if constexpr (C32) {
+                const auto bc = plane(reinterpret_cast<const float*>(g.xc), Z, g.cz, cxy * B, pc / 2);
+#pragma unroll
+                for (int u = 0; u < NC; ++u) {
+                    const uint32_t o = coarse_off(u);
+                    cv[u] = static_cast<double>(bload<float>(bc, o == kOut ? kOut : o / 2));
+                }
+            } else {
+                const auto bc = plane(g.xc, Z, g.cz, cxy * B, pc);
+#pragma unroll
+                for (int u = 0; u < NC; ++u) cv[u] = bload<double>(bc, coarse_off(u));
+            }
+        };
         // fine plane p: r and 1/a_ii; odd p also the coarse plane (p + 1) / 2
         auto fetch = [&](int pl) {
             const auto br = plane(g.r, pl, nz, nxy * B, pv), bd = plane(g.dinv, pl, nz, nxy, pd);
 #pragma unroll
             for (int u = 0; u < NPF; ++u) fr[u] = bload<double>(br, fo[u]);
             dd = bload<double>(bd, dof);
-            if (pl & 1) {
-                const auto bc = plane(g.xc, (pl + 1) / 2, g.cz, cxy * B, pc);
-#pragma unroll
-                for (int u = 0; u < NC; ++u) cv[u] = bload<double>(bc, coarse_off(u));
-            }
-        };
-        auto load_coarse = [&](int Z) {
-            const auto bc = plane(g.xc, Z, g.cz, cxy * B, pc);
-#pragma unroll
-            for (int u = 0; u < NC; ++u) cv[u] = bload<double>(bc, coarse_off(u));
+            if (pl & 1) load_coarse((pl + 1) / 2);
         };
         auto put_coarse = [&](int Z) {   // coarse plane Z to its slot
 #pragma unroll
@@ -2966,7 +3025,7 @@ void launch_tile(const MgState& M, const TileGeo& t, hipStream_t st, const doubl
 // coarse level l: out = b - A x (kT27Resid) or x + w D^{-1} (b - A x) (kT27Smooth)
 template <int MODE>
 void launch_tile27(const MgState& M, const TileGeo& t, int l, hipStream_t st, const double* x, const double* b,
-                   double* out) {
+                   double* out, bool v32 = false) {
     const MgLevel& L = M.lv[l];
     const TileGeo::Lv27& q = t.t27[l];
     Tile27Args g;
@@ -2986,7 +3045,9 @@ void launch_tile27(const MgState& M, const TileGeo& t, int l, hipStream_t st, co
     g.out = out;
     g.sc = M.sc;
     const size_t lds = (size_t)3 * MgTile<16>::NPF * kTT * sizeof(double);
-    if (L.Uf27p)   // the rows in FP32 (the V-cycle's coarse operators)
+    if (L.Uf27p && v32)   // the rows and (v32) the level's vectors in FP32
+        hipLaunchKernelGGL((k_mg_tile27<MODE, true, true>), dim3(q.blocks), dim3(kTT), lds, st, g);
+    else if (L.Uf27p)   // the rows in FP32 (the V-cycle's coarse operators)
         hipLaunchKernelGGL((k_mg_tile27<MODE, true>), dim3(q.blocks), dim3(kTT), lds, st, g);
     else
         hipLaunchKernelGGL((k_mg_tile27<MODE, false>), dim3(q.blocks), dim3(kTT), lds, st, g);
@@ -2995,7 +3056,7 @@ inline bool tiled27(const TileGeo& t, int l) { return l >= 1 && l < kMgMaxLevels
 
 // level 0: z = x0 + w D^{-1} (r - A x0), x0 = w D^{-1} r + P x1 (fused, 16 right-hand sides)
 inline void launch_ps(const MgState& M, const TileGeo& t, hipStream_t st, const double* r, const double* x1, double* z,
-                      bool f32) {
+                      bool f32, bool c32 = false) {
     const MgLevel& L = M.lv[0];
     const MgLevel& C = M.lv[1];
     PSArgs g;
@@ -3017,15 +3078,19 @@ inline void launch_ps(const MgState& M, const TileGeo& t, hipStream_t st, const 
     g.z = reinterpret_cast<float*>(z);   // FP32 in the double buffer's first half
     g.parts = M.parts;
     g.sc = M.sc;
-    if (f32)
+    if (f32 && c32)   // c32: level 1's x in FP32
+        hipLaunchKernelGGL((k_mg_prolong_smooth<true, true>), dim3(t.ps_blocks32), dim3(kTT), kPSLds<true>, st, g);
+    else if (f32)
         hipLaunchKernelGGL(k_mg_prolong_smooth<true>, dim3(t.ps_blocks32), dim3(kTT), kPSLds<true>, st, g);
+    else if (c32)
+        hipLaunchKernelGGL((k_mg_prolong_smooth<false, true>), dim3(t.ps_blocks), dim3(kTT), kPSLds<false>, st, g);
     else
         hipLaunchKernelGGL(k_mg_prolong_smooth<false>, dim3(t.ps_blocks), dim3(kTT), kPSLds<false>, st, g);
 }
 
 // level l's residual to level l + 1's b and first sweep xc (tiled; trilinear)
 template <int B>
-void launch_restrict(const MgState& M, const TileGeo& t, int l, hipStream_t st, double* xc) {
+void launch_restrict(const MgState& M, const TileGeo& t, int l, hipStream_t st, double* xc, bool v1 = false) {
     if constexpr (B >= 8) {
         const MgLevel& L = M.lv[l];
         const MgLevel& C = M.lv[l + 1];
@@ -3047,7 +3112,12 @@ void launch_restrict(const MgState& M, const TileGeo& t, int l, hipStream_t st, 
         g.bc = C.b;
         g.xc = xc;
         g.sc = M.sc;
-        if (l == 0)   // the finest level's residual comes from the tiled kernels in FP32
+        // the finest level's residual comes from the tiled kernels in FP32; v1:
+        // level 1's vectors are FP32 too (written here from level 0, read here
+        // towards level 2)
+        if (l == 0 && v1)
+            hipLaunchKernelGGL((k_mg_restrict_tile<B, true, true>), dim3(q.blocks), dim3(kTT), MgRst<B>::LDS, st, g);
+        else if (l == 0 || (l == 1 && v1))
             hipLaunchKernelGGL((k_mg_restrict_tile<B, true>), dim3(q.blocks), dim3(kTT), MgRst<B>::LDS, st, g);
         else
             hipLaunchKernelGGL((k_mg_restrict_tile<B, false>), dim3(q.blocks), dim3(kTT), MgRst<B>::LDS, st, g);
@@ -3233,7 +3303,8 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
         // same balance with (2 zc + 1) fine planes per item
         const MgLevel& C = M.lv[1];
         const void* fr = reinterpret_cast<const void*>(&k_mg_restrict_tile<B, true>);
-        for (const void* f : {fr, reinterpret_cast<const void*>(&k_mg_restrict_tile<B, false>)})
+        for (const void* f : {fr, reinterpret_cast<const void*>(&k_mg_restrict_tile<B, false>),
+                              reinterpret_cast<const void*>(&k_mg_restrict_tile<B, true, true>)})
             QPAT_HIP(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MgRst<B>::LDS));
         int rocc = 1;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&rocc, fr, kTT, MgRst<B>::LDS) != hipSuccess) rocc = 1;
@@ -3267,6 +3338,9 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
                                           : reinterpret_cast<const void*>(&k_mg_prolong_smooth<false>);
                     const size_t lds = f32 ? kPSLds<true> : kPSLds<false>;
                     QPAT_HIP(c, hipFuncSetAttribute(fps, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                    const void* fps_c = f32 ? reinterpret_cast<const void*>(&k_mg_prolong_smooth<true, true>)
+                                            : reinterpret_cast<const void*>(&k_mg_prolong_smooth<false, true>);
+                    QPAT_HIP(c, hipFuncSetAttribute(fps_c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
                     int occ_ps = 1;
                     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_ps, fps, kTT, lds) != hipSuccess) occ_ps = 1;
                     const int64_t conc_ps = (int64_t)std::max(occ_ps, 1) * (cus / 8);
@@ -3355,10 +3429,12 @@ qpat_status tile_setup(qpat_ctx* c, MgState& M) {
             }
         }
         if constexpr (B == 16) {   // the coarse levels' 27-point kernels
-            const void* f27[4] = {reinterpret_cast<const void*>(&k_mg_tile27<kT27Resid>),
+            const void* f27[6] = {reinterpret_cast<const void*>(&k_mg_tile27<kT27Resid>),
                                   reinterpret_cast<const void*>(&k_mg_tile27<kT27Smooth>),
                                   reinterpret_cast<const void*>(&k_mg_tile27<kT27Resid, true>),
-                                  reinterpret_cast<const void*>(&k_mg_tile27<kT27Smooth, true>)};
+                                  reinterpret_cast<const void*>(&k_mg_tile27<kT27Smooth, true>),
+                                  reinterpret_cast<const void*>(&k_mg_tile27<kT27Resid, true, true>),
+                                  reinterpret_cast<const void*>(&k_mg_tile27<kT27Smooth, true, true>)};
             constexpr size_t lds27 = (size_t)3 * MgTile<16>::NPF * kTT * sizeof(double);
             for (const void* f : f27)
                 QPAT_HIP(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds27));
@@ -3405,6 +3481,17 @@ inline bool z32_path(const MgState& M, const TileGeo& tg) {
     return B == 16 && fused_update(tg) && tg.ps_on && !M.opdep;
 }
 
+// Level 1 keeps the V-cycle's vectors (x, its ping-pong partner, r, b) in FP32,
+// in the first half of their FP64 arrays, where every kernel that touches them
+// has that form: 16 right-hand sides, the tiled restrictions into and out of
+// level 1, its tiled 27-point residual and sweep, the prolongation into it and
+// the fused prolongation + last sweep above it (preconditioner work only).
+template <int B>
+inline bool v32_path(const MgState& M, const TileGeo& tg) {
+    return z32_path<B>(M, tg) && M.lv.size() > 2 && tiled27(tg, 1) && M.lv[1].Uf27p != nullptr && tg.rst[0].on &&
+           tg.rst[1].on;
+}
+
 // One V-cycle on every lane: z = V(r), r = level 0's b. The last sweep also
 // leaves the partial sums r.z, sum z, sum r. On a tiled finest level with one
 // sweep each way the first sweep w D^{-1} r is never stored: the residual
@@ -3431,6 +3518,7 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
             bool resid_done = false, bool lo32 = false, bool first_done = false) {
     const int nl = static_cast<int>(M.lv.size());
     const bool fused0 = tg.on && kMgNu == 1;
+    const bool v1 = v32_path<B>(M, tg);   // level 1's vectors in FP32
     const double* r0 = b0 ? b0 : M.lv[0].b;   // level 0's right-hand side (the PCG residual)
     std::vector<double*> xl(nl), tl(nl);
     for (int l = 0; l < nl; ++l) {
@@ -3458,12 +3546,12 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         else if (l == 0 && tg.on)
             launch_tile<kTResid, B>(M, tg, st, xl[0], nullptr, r0, L.r, nullptr);
         else if (B == 16 && tiled27(tg, l))
-            launch_tile27<kT27Resid>(M, tg, l, st, xl[l], L.b, L.r);
+            launch_tile27<kT27Resid>(M, tg, l, st, xl[l], L.b, L.r, v1 && l == 1);
         else
             QPAT_MG_KIND(vkind(L), B, k_mg_resid, g, dim3(kMgT), 0, st, a, bl, xl[l], L.r);
         if (l == 0 && ev) (void)hipEventRecord(ev[1], st);
         if (tg.on && l < kMgMaxLevels && tg.rst[l].on && !M.opdep)
-            launch_restrict<B>(M, tg, l, st, xl[l + 1]);
+            launch_restrict<B>(M, tg, l, st, xl[l + 1], v1);
         else if (M.opdep)
             // (the FP64 copy holds the same rounded values; the restriction measured
             // slower reading the FP32 copy: 135 against 71 us per V-cycle at 128^3)
@@ -3485,7 +3573,7 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         const double* bl = l == 0 ? r0 : L.b;
         if (l == 0 && z32_path<B>(M, tg)) {   // prolongation fused into the last sweep (z in FP32)
             if (ev) (void)hipEventRecord(ev[2], st);
-            launch_ps(M, tg, st, r0, xl[1], tl[0], lo32);
+            launch_ps(M, tg, st, r0, xl[1], tl[0], lo32, v1);
             if (ev) (void)hipEventRecord(ev[3], st);
             std::swap(xl[0], tl[0]);
             continue;
@@ -3499,6 +3587,9 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         else if (M.opdep)
             hipLaunchKernelGGL((k_mg_prolong<B, false, true, float>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz,
                                xl[l + 1], bl, xl[l], L.W32);
+        else if (l == 1 && v1)   // into level 1's FP32 x
+            hipLaunchKernelGGL((k_mg_prolong<B, false, false, double, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny,
+                               C.nz, xl[l + 1], bl, xl[l], static_cast<const double*>(nullptr));
         else
             hipLaunchKernelGGL((k_mg_prolong<B, false, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1],
                                bl, xl[l], static_cast<const double*>(nullptr));
@@ -3510,7 +3601,7 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
             else if (last)
                 launch_smooth<B, true>(vkind(L), g, st, a, bl, xl[l], tl[l], M.parts);
             else if (B == 16 && tiled27(tg, l))
-                launch_tile27<kT27Smooth>(M, tg, l, st, xl[l], L.b, tl[l]);
+                launch_tile27<kT27Smooth>(M, tg, l, st, xl[l], L.b, tl[l], v1 && l == 1);
             else
                 launch_smooth<B, false>(vkind(L), g, st, a, bl, xl[l], tl[l], nullptr);
             if (last && ev) (void)hipEventRecord(ev[3], st);
