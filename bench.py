@@ -72,10 +72,10 @@ MG_KERNELS = {
 # r' - A (w D^-1 r') in FP32 (half a vector); x is not touched there (the
 # iterations keep their directions, and x is formed once per solve from them),
 # and counter 7 the prolongation fused with the last sweep: read r, level 1's x
-# (1/8 vector), the whole stencil rows (16 FP32 values a node: the bytes of the
-# stored form); write z in FP32 (half a vector)
+# (1/8 of the nodes, in FP32: 1/16 vector), the whole stencil rows (16 FP32
+# values a node: the bytes of the stored form); write z in FP32 (half a vector)
 MG_FUSED_UPDATE = ("k_mg_tile<6,16>", 3.5, 1, True)
-MG_FUSED_SMOOTH = ("k_mg_prolong_smooth<false>", 1.625, 1, True)
+MG_FUSED_SMOOTH = ("k_mg_prolong_smooth<false,true>", 1.5625, 1, True)
 
 
 def mg_kernel(key, kst, p32=False):
@@ -89,7 +89,7 @@ def mg_kernel(key, kst, p32=False):
         return ("k_mg_tile<6,16,false,true>", v, o, d) if p32 else (n, v, o, d)
     if key == "K_mg_smooth0" and fused:   # mixed precision stages its x0 in FP32 (same HBM bytes)
         n, v, o, d = MG_FUSED_SMOOTH
-        return ("k_mg_prolong_smooth<true>", v, o, d) if p32 else (n, v, o, d)
+        return ("k_mg_prolong_smooth<true,true>", v, o, d) if p32 else (n, v, o, d)
     n, v, o, d = MG_KERNELS[key]
     if p32 and key == "K_mg_dir_spmv":
         return ("k_mg_tile<0,16,true,true>", v - 1.0, o, d)
@@ -130,7 +130,8 @@ def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled2
         doubles a node on tiled levels, 27 elsewhere); coarsest: its dense
         inverse (N_c^2 doubles) and 2 V_c.
     Mixed precision (p32): the direction in FP32 takes V_0 off each iteration
-    (the old p and the new p in the direction kernel).
+    (the old p and the new p in the direction kernel). With 16 right-hand sides
+    and a tiled level 1 its vectors are FP32: V_1 counts half.
     Per solve: start 3 V_0, the first V-cycle's finest residual 1.5 V_0 + rows,
     one V-cycle more than iterations, x formed from the kept directions (each
     read once, V_0 or in FP32 V_0 / 2, and x read and written), the final true
@@ -146,6 +147,8 @@ def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled2
     Returns (total bytes, dict of the parts)."""
     vb = 8 * B
     V = [n * vb for n in levels]
+    if B == 16 and len(levels) > 2 and levels[1] >= tiled27_min:
+        V[1] //= 2   # level 1's vectors in FP32
     rows0, whole0, d0 = 64 * N, 64 * N, 8 * N
     L = len(levels)
 
