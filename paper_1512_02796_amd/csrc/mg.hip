@@ -52,8 +52,9 @@ struct MgLevel {
     double* t = nullptr;           // ping-pong partner of x
     double* r = nullptr;           // residual before restriction
     double* W = nullptr;           // [nsys][8][N] operator-dependent prolongation weights to the next level (corner-major)
-    float* W32 = nullptr;          // the same in FP32: the V-cycle's prolongation reads these (W holds the same
-                                   // rounded values for the restriction and the Galerkin set-up: one P throughout)
+    float* Wc = nullptr;           // [nsys][WPack size] the nonzero ones of W in FP32, packed by corner: the V-cycle's
+                                   // transfers read these (W holds the same rounded values for the Galerkin set-up:
+                                   // one P throughout)
     double* Uf = nullptr;          // kind 3: [nsys][kUpRow][N] Kuhn diagonal + upper entries, entry-major;
                                    // K level 0: [N][kFullRow] whole Kuhn rows; K levels >= 1: [N][kRow27]
     float* Uf32 = nullptr;         // kind 5 / 6: the kind-3 / kind-4 rows in FP32 (M_delta's V-cycle)
@@ -559,16 +560,6 @@ __global__ __launch_bounds__(kMgT) void k_mg_fullrows(LvArgs L, double* __restri
     }
 }
 
-// b = a rounded to FP32, and a replaced by that rounded value (the FP64 users
-// then see exactly the FP32 numbers)
-__global__ __launch_bounds__(kMgT) void k_round_f32(double* __restrict__ a, float* __restrict__ b, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float v = static_cast<float>(a[i]);
-        b[i] = v;
-        a[i] = static_cast<double>(v);
-    }
-}
-
 __global__ __launch_bounds__(kMgT) void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kMgT)
         b[i] = static_cast<float>(a[i]);
@@ -617,6 +608,57 @@ __device__ __forceinline__ double pweight(const double* __restrict__ W, int64_t 
     const double wy = (fy & 1) ? 0.5 : (by ? 0.0 : 1.0);
     const double wz = (fz & 1) ? 0.5 : (bz ? 0.0 : 1.0);
     return wx * wy * wz;
+}
+
+// Packed prolongation weights. Fine node (ix, iy, iz) takes its value from the
+// corners J0 + (a, b, c) of the coarse cell J0 = (ix/2, iy/2, iz/2). Along an
+// axis where the node's coordinate is even it lies on a coarse plane, so a
+// corner one step up that axis has weight 0 (trilinear and operator-dependent
+// alike: the collapsed stencil has no extent along an even axis). Corner
+// cn = a + 2 b + 4 c is therefore kept only on the sub-lattice of nodes that are
+// odd along every axis of its set bits, indexed (a ? ix/2 : ix, b ? iy/2 : iy,
+// c ? iz/2 : iz); the eight sub-lattices follow one another in corner order,
+// 27/8 values per node instead of 8.
+struct WPack {
+    int32_t nx, ny, nz;
+    __host__ __device__ __forceinline__ int64_t size() const {
+        return (int64_t)(nx + (nx >> 1)) * (ny + (ny >> 1)) * (nz + (nz >> 1));
+    }
+    // (32-bit: the set-up keeps size() below 2^31)
+    __device__ __forceinline__ int32_t at(int cn, int32_t ix, int32_t iy, int32_t iz) const {
+        const int a = cn & 1, b = (cn >> 1) & 1, c = cn >> 2;
+        const int32_t sx = a ? nx >> 1 : nx, sy = b ? ny >> 1 : ny, sz = c ? nz >> 1 : nz;
+        const int32_t off = (c ? (nx + (nx >> 1)) * (ny + (ny >> 1)) * nz : 0) + (b ? (nx + (nx >> 1)) * ny * sz : 0) +
+                            (a ? nx * sy * sz : 0);
+        return off + (a ? ix >> 1 : ix) + sx * ((b ? iy >> 1 : iy) + sy * (c ? iz >> 1 : iz));
+    }
+    // at() for any node inside the lattice, clamped into the array: a load that
+    // is always in bounds, whose value is used only where held() is true
+    __device__ __forceinline__ int32_t atc(int cn, int32_t ix, int32_t iy, int32_t iz) const {
+        return min(at(cn, ix, iy, iz), static_cast<int32_t>(size() - 1));
+    }
+    // whether corner cn can carry a nonzero weight for node (ix, iy, iz)
+    __device__ __forceinline__ static bool held(int cn, int32_t ix, int32_t iy, int32_t iz) {
+        return !((cn & 1) && !(ix & 1)) && !((cn & 2) && !(iy & 1)) && !((cn & 4) && !(iz & 1));
+    }
+};
+
+// W rounded to FP32 in place (the Galerkin product then uses exactly the values
+// the transfers apply) and its nonzero entries packed into Wc
+__global__ __launch_bounds__(kMgT) void k_mg_wpack(LvArgs L, double* __restrict__ Wall, float* __restrict__ Wc) {
+    const int sys = blockIdx.y;
+    const WPack pk{L.nx, L.ny, L.nz};
+    double* W = Wall + (int64_t)sys * L.N * 8;
+    float* P = Wc + sys * pk.size();
+    for (int64_t i = blockIdx.x * (int64_t)kMgT + threadIdx.x; i < L.N; i += (int64_t)gridDim.x * kMgT) {
+        int ix, iy, iz;
+        coords(static_cast<int32_t>(i), L.nx, L.ny, ix, iy, iz);
+        for (int cn = 0; cn < 8; ++cn) {
+            const float v = static_cast<float>(W[cn * L.N + i]);
+            W[cn * L.N + i] = static_cast<double>(v);
+            if (WPack::held(cn, ix, iy, iz)) P[pk.at(cn, ix, iy, iz)] = v;
+        }
+    }
 }
 
 // Galerkin coarse operator A_c = P^T A P, diagonal and the 13 upper offsets
@@ -855,22 +897,23 @@ struct Span {
 
 // bc = P^T r on the coarse level c, and the first sweep there, xc = w D^{-1} bc.
 // Fine nodes 2 I + {-1, 0, 1} per axis, weights 1/2, 1, 1/2 (trilinear) or
-// from Wall ([nsys][8][Nf], operator-dependent); the ones past the lattice
-// get weight 0 (their loads are clamped inside it).
-template <int B, bool OPW, typename WT = double>
+// from Wc ([nsys][WPack size], operator-dependent, packed); the ones past the
+// lattice get weight 0 (their loads are clamped inside it).
+template <int B, bool OPW>
 __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int32_t ny, int32_t nz,
                                                       const double* __restrict__ r, double* __restrict__ bc,
-                                                      double* __restrict__ xc, const WT* __restrict__ Wall) {
+                                                      double* __restrict__ xc, const float* __restrict__ Wc) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V;
     const int v = threadIdx.x % Pk<B>::BV;
     const int64_t Nf = (int64_t)nx * ny * nz, Nc = c.L.N;
+    const WPack pk{nx, ny, nz};
     for (int sys = blockIdx.y; sys < c.nsys; sys += gridDim.y) {
         if (!pair_active<B>(c.sc, sys, v)) continue;
         const double w = c.w[sys * c.nlev + c.lev];
         const double* dinv = c.dinv + sys * Nc;
         const double* rs = r + sys * Nf * B + v * V;
-        const WT* Ws = OPW ? Wall + sys * Nf * 8 : nullptr;
+        const float* Ws = OPW ? Wc + sys * pk.size() : nullptr;
         const int64_t oc = sys * Nc * B + v * V;
         walk<Pk<B>::BV>(c.L.nx, c.L.ny, c.L.nz, [&](int32_t Ix, int32_t Iy, int32_t Iz, int32_t I, int32_t) {
             int32_t fx[3], fy[3], fz[3];
@@ -886,32 +929,40 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
                 fy[d] = min(max(gy, 0), ny - 1);
                 fz[d] = min(max(gz, 0), nz - 1);
             }
-            // the 27 fine values first (clamped indices, all loads in flight
-            // together: the tiny levels are latency-bound), then the sum in
-            // the order dz, dy, dx
+            // the 27 fine values (and weights) first (clamped indices, all loads
+            // in flight together: the tiny levels are latency-bound), then the
+            // sum in the order dz, dy, dx
             T fv[27];
+            float wv[OPW ? 27 : 1];
 #pragma unroll
             for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy) {
                     const int32_t row = nx * (fy[dy] + ny * fz[dz]);
 #pragma unroll
-                    for (int dx = 0; dx < 3; ++dx) fv[(dz * 3 + dy) * 3 + dx] = vld<T>(rs + (row + fx[dx]) * B);
+                    for (int dx = 0; dx < 3; ++dx) {
+                        const int k = (dz * 3 + dy) * 3 + dx;
+                        fv[k] = vld<T>(rs + (row + fx[dx]) * B);
+                        // I is corner (d == 0 per axis) of fine node 2 I + d - 1, which is
+                        // odd along each such axis: the packed entry exists where the
+                        // node is inside the lattice (elsewhere the weight is 0 and the
+                        // load, clamped, is not used)
+                        if constexpr (OPW)
+                            wv[k] = Ws[pk.atc((dx == 0) + 2 * (dy == 0) + 4 * (dz == 0), fx[dx], fy[dy], fz[dz])];
+                    }
                 }
-            if constexpr (!OPW) __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_sched_barrier(0);
             T s = 0.0;
 #pragma unroll
             for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy) {
-                    const int32_t row = nx * (fy[dy] + ny * fz[dz]);
                     const double wyz = wy[dy] * wz[dz];
 #pragma unroll
                     for (int dx = 0; dx < 3; ++dx) {
                         double wgt = wyz * wx[dx];
-                        if constexpr (OPW)   // I is corner (d == 0 per axis) of fine node 2 I + d - 1
-                            if (wgt != 0.0)
-                                wgt = static_cast<double>(Ws[((dx == 0) + 2 * (dy == 0) + 4 * (dz == 0)) * Nf + (row + fx[dx])]);
+                        if constexpr (OPW)
+                            if (wgt != 0.0) wgt = static_cast<double>(wv[(dz * 3 + dy) * 3 + dx]);
                         s += wgt * fv[(dz * 3 + dy) * 3 + dx];
                     }
                 }
@@ -923,11 +974,11 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
 
 // x = base + P xc on fine level f (coarse lattice cx, cy, cz). base = x, or
 // with FIRST the first sweep w D^{-1} b, which is then never stored. P:
-// trilinear, or the weights Wall ([nsys][8][Nf]).
-template <int B, bool FIRST, bool OPW, typename WT = double, bool XF = false>
+// trilinear, or the packed weights Wc ([nsys][WPack size]).
+template <int B, bool FIRST, bool OPW, bool XF = false>
 __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32_t cy, int32_t cz,
                                                      const double* __restrict__ xc, const double* __restrict__ b,
-                                                     double* __restrict__ x, const WT* __restrict__ Wall) {
+                                                     double* __restrict__ x, const float* __restrict__ Wc) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V;
     const int v = threadIdx.x % Pk<B>::BV;
@@ -940,7 +991,8 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
         const double* bs = b + sys * Nf * B + v * V;
         double* xf = x + sys * Nf * B + v * V;
         float* xf32 = reinterpret_cast<float*>(x) + sys * Nf * B + v * V;   // XF: the fine x in FP32
-        const WT* Ws = OPW ? Wall + sys * Nf * 8 : nullptr;
+        const WPack pk{f.L.nx, f.L.ny, f.L.nz};
+        const float* Ws = OPW ? Wc + sys * pk.size() : nullptr;
         walk<Pk<B>::BV>(f.L.nx, f.L.ny, f.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
             const Span sx(ix, cx), sy(iy, cy), sz(iz, cz);
             const int32_t jx[2] = {sx.j0, sx.j1}, jy[2] = {sy.j0, sy.j1}, jz[2] = {sz.j0, sz.j1};
@@ -967,13 +1019,17 @@ __global__ __launch_bounds__(kMgT) void k_mg_prolong(SmArgs f, int32_t cx, int32
                         // clamps the index of a zero-weight corner
                         const int cn = a2 + 2 * b2 + 4 * c2;
                         if constexpr (OPW)
-                            wgt[cn] = static_cast<double>(Ws[cn * Nf + i]);
+                            wgt[cn] = static_cast<double>(Ws[pk.atc(cn, ix, iy, iz)]);
                         else
                             wgt[cn] = wyz * wx[a2];
                         cv[cn] = vld<T>(xs + (row + jx[a2]) * B);
                     }
                 }
             __builtin_amdgcn_sched_barrier(0);
+            if constexpr (OPW)
+#pragma unroll
+                for (int cn = 0; cn < 8; ++cn)
+                    if (!WPack::held(cn, ix, iy, iz)) wgt[cn] = 0.0;
 #pragma unroll
             for (int cn = 0; cn < 8; ++cn) s += wgt[cn] * cv[cn];
             if constexpr (XF)
@@ -3553,13 +3609,11 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         if (tg.on && l < kMgMaxLevels && tg.rst[l].on && !M.opdep)
             launch_restrict<B>(M, tg, l, st, xl[l + 1], v1);
         else if (M.opdep)
-            // (the FP64 copy holds the same rounded values; the restriction measured
-            // slower reading the FP32 copy: 135 against 71 us per V-cycle at 128^3)
-            hipLaunchKernelGGL((k_mg_restrict<B, true, double>), sgrid<B>(C.N, M.nsys), dim3(kMgT), 0, st, sm(l + 1), L.nx,
-                               L.ny, L.nz, L.r, C.b, xl[l + 1], L.W);
+            hipLaunchKernelGGL((k_mg_restrict<B, true>), sgrid<B>(C.N, M.nsys), dim3(kMgT), 0, st, sm(l + 1), L.nx,
+                               L.ny, L.nz, L.r, C.b, xl[l + 1], L.Wc);
         else
             hipLaunchKernelGGL((k_mg_restrict<B, false>), sgrid<B>(C.N, M.nsys), dim3(kMgT), 0, st, sm(l + 1), L.nx, L.ny,
-                               L.nz, L.r, C.b, xl[l + 1], static_cast<const double*>(nullptr));
+                               L.nz, L.r, C.b, xl[l + 1], static_cast<const float*>(nullptr));
     }
     const MgLevel& K = M.lv[nl - 1];
     hipLaunchKernelGGL(k_mg_dense<B>,
@@ -3579,20 +3633,20 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
             continue;
         }
         if (l == 0 && fused0 && M.opdep)
-            hipLaunchKernelGGL((k_mg_prolong<B, true, true, float>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1],
-                               r0, xl[0], L.W32);
+            hipLaunchKernelGGL((k_mg_prolong<B, true, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1],
+                               r0, xl[0], L.Wc);
         else if (l == 0 && fused0)
             hipLaunchKernelGGL((k_mg_prolong<B, true, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], r0,
-                               xl[0], static_cast<const double*>(nullptr));
+                               xl[0], static_cast<const float*>(nullptr));
         else if (M.opdep)
-            hipLaunchKernelGGL((k_mg_prolong<B, false, true, float>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz,
-                               xl[l + 1], bl, xl[l], L.W32);
+            hipLaunchKernelGGL((k_mg_prolong<B, false, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz,
+                               xl[l + 1], bl, xl[l], L.Wc);
         else if (l == 1 && v1)   // into level 1's FP32 x
-            hipLaunchKernelGGL((k_mg_prolong<B, false, false, double, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny,
-                               C.nz, xl[l + 1], bl, xl[l], static_cast<const double*>(nullptr));
+            hipLaunchKernelGGL((k_mg_prolong<B, false, false, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny,
+                               C.nz, xl[l + 1], bl, xl[l], static_cast<const float*>(nullptr));
         else
             hipLaunchKernelGGL((k_mg_prolong<B, false, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[l + 1],
-                               bl, xl[l], static_cast<const double*>(nullptr));
+                               bl, xl[l], static_cast<const float*>(nullptr));
         for (int k = 0; k < kMgNu; ++k) {
             const bool last = l == 0 && k == kMgNu - 1;
             if (last && ev) (void)hipEventRecord(ev[2], st);
@@ -4178,8 +4232,11 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             QPAT_TRY(dalloc(c, &L.t, V * L.N));
             QPAT_TRY(dalloc(c, &L.r, V * L.N));
             if (op == Op::Prior && l + 1 < nl) {
+                if (WPack{L.nx, L.ny, L.nz}.size() >= (int64_t(1) << 31))
+                    return fail(c, QPAT_ERR_ARG, "multigrid: lattice %d x %d x %d too large for the prior's transfers",
+                                L.nx, L.ny, L.nz);
                 QPAT_TRY(dalloc(c, &L.W, nsys * L.N * 8));
-                QPAT_TRY(dalloc(c, &L.W32, nsys * L.N * 8));
+                QPAT_TRY(dalloc(c, &L.Wc, nsys * WPack{L.nx, L.ny, L.nz}.size()));
             }
             if (op == Op::Prior && l == 0 && L.kind == 1) {   // entry-major upper rows (kind 3) and in FP32 (kind 5)
                 QPAT_TRY(dalloc(c, &L.Uf, nsys * L.N * kUpRow));
@@ -4242,10 +4299,9 @@ qpat_status mg_setup(qpat_ctx* c, Op op) {
             hipLaunchKernelGGL(k_mg_pweights<1>, g, dim3(kMgT), 0, c->stream, lv_args(F), F.W);
             hipLaunchKernelGGL(k_mg_pweights<2>, g, dim3(kMgT), 0, c->stream, lv_args(F), F.W);
             hipLaunchKernelGGL(k_mg_pweights<3>, g, dim3(kMgT), 0, c->stream, lv_args(F), F.W);
-            // the transfers read the weights in FP32; the Galerkin product below uses
-            // the same rounded values, so A_c = P^T A P holds for the P applied
-            hipLaunchKernelGGL(k_round_f32, dim3(grid_for(nsys * F.N * 8, kMgT, 4096)), dim3(kMgT), 0, c->stream,
-                               F.W, F.W32, nsys * F.N * 8);
+            // the transfers read the weights in FP32, packed; the Galerkin product
+            // below uses the same rounded values, so A_c = P^T A P holds for the P applied
+            hipLaunchKernelGGL(k_mg_wpack, g, dim3(kMgT), 0, c->stream, lv_args(F), F.W, F.Wc);
         }
         hipLaunchKernelGGL(k_mg_rap, dim3((unsigned)((C.N + kMgT - 1) / kMgT), nsys), dim3(kMgT), 0, c->stream,
                            lv_args(F), M.opdep ? F.W : nullptr, C.U, C.nx, C.ny, C.nz);
