@@ -338,10 +338,16 @@ def main():
         torch.cuda.synchronize()
         lsqr_s = (time.perf_counter() - ls_t0) / args.lsqr_steps
         log(f"LSQR iteration: {lsqr_s * 1e3:.1f} ms, residuals {ls_hist}")
-        p_t0 = time.perf_counter()
-        pinfo = ctx.prior_solve(d(s_np), torch.empty(2 * N, dtype=torch.float64, device=dev))
+        # M_delta^{-1} of one right-hand side: one untimed call (it captures the
+        # graphs of the chunk lengths this right-hand side takes), then the mean of three
+        ps, py = d(s_np), torch.empty(2 * N, dtype=torch.float64, device=dev)
+        ctx.prior_solve(ps, py)
         torch.cuda.synchronize()
-        prior_s = time.perf_counter() - p_t0
+        p_t0 = time.perf_counter()
+        for _ in range(3):
+            pinfo = ctx.prior_solve(ps, py)
+        torch.cuda.synchronize()
+        prior_s = (time.perf_counter() - p_t0) / 3
         log(f"M_delta^-1: {prior_s * 1e3:.1f} ms", pinfo)
 
     # ---- the same pair one right-hand side at a time, and with the Jacobi preconditioner

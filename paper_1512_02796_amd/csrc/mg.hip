@@ -3850,10 +3850,15 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
         QPAT_HIP(c, hipGetLastError());
         // Iterations run in chunks of even length between host checks. The
         // first is kMgChunk0 long; later ones cover the iterations that the
-        // slowest lane still needs at its observed contraction rate (within
-        // [2, 16]), so few iterations run after convergence.
-        int chunk = kMgChunk0;
-        std::vector<int> iters_before(S, -1);
+        // slowest lane still needs at its contraction rate over the last
+        // chunk (within [2, 16]), so few iterations run after convergence. PCG
+        // converges superlinearly towards the end of a run, where that rate
+        // overestimates the need: a third or later chunk is therefore kept to
+        // half the iterations the run has done, which bounds the iterations
+        // launched after convergence (each still costs its launches) by that
+        // half, at the price of a host check more on runs that long.
+        int chunk = kMgChunk0, nchunk = 0;
+        std::vector<int> iters_before(S, -1), iters_start(S, 0);
         std::vector<double> rr_before(S, 0.0);
         for (;;) {
             QPAT_TRY(fetch());
@@ -3874,7 +3879,16 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
                 }
                 const int n = static_cast<int>(std::ceil(need));
                 chunk = std::min(16, std::max(2, n + (n & 1)));
+                if (nchunk >= 2) {
+                    int run_its = 0;
+                    for (int i = 0; i < S; ++i) run_its = std::max(run_its, M.sc_host[i].iters - iters_start[i]);
+                    const int half = run_its / 2;
+                    chunk = std::min(chunk, std::max(2, half + (half & 1)));
+                }
+            } else {
+                for (int i = 0; i < S; ++i) iters_start[i] = M.sc_host[i].iters;
             }
+            ++nchunk;
             for (int i = 0; i < S; ++i) {
                 iters_before[i] = M.sc_host[i].iters;
                 rr_before[i] = M.sc_host[i].rr;
