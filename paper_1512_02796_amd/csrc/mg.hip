@@ -3927,26 +3927,32 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
                 continue;
             }
             if (c->opts.use_graphs) {
-                // every by-value argument of the captured kernels that can change
-                // between runs: the region count is recomputed at each prior set-up
-                char key[128];
-                snprintf(key, sizeof key, "%d/%d/%.17g/%d/%d/%d/%d", B, chunk, a.rtol2, a.maxit, a.deflate, a.kreg,
-                         a.p32);
-                auto it = M.graphs.find(key);
-                hipGraphExec_t ex = nullptr;
-                if (it != M.graphs.end()) {
-                    ex = it->second;
-                } else {
-                    if (!M.cap) QPAT_HIP(c, hipStreamCreateWithFlags(&M.cap, hipStreamNonBlocking));
-                    hipGraph_t gr = nullptr;
-                    QPAT_HIP(c, hipStreamBeginCapture(M.cap, hipStreamCaptureModeThreadLocal));
-                    for (int i = 0; i < chunk; ++i) iteration<B>(M, a, tg, M.cap, i & 1);
-                    QPAT_HIP(c, hipStreamEndCapture(M.cap, &gr));
-                    QPAT_HIP(c, hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
-                    QPAT_HIP(c, hipGraphDestroy(gr));
-                    M.graphs[key] = ex;
+                // the chunk as graphs of 16, 8, 4 and 2 iterations (its binary
+                // digits; every chunk is even), so that a solver captures at most
+                // four graphs whatever chunk lengths its right-hand sides take
+                for (int len = 16; len >= 2; len /= 2) {
+                    if (!(chunk & len)) continue;
+                    // every by-value argument of the captured kernels that can change
+                    // between runs: the region count is recomputed at each prior set-up
+                    char key[128];
+                    snprintf(key, sizeof key, "%d/%d/%.17g/%d/%d/%d/%d", B, len, a.rtol2, a.maxit, a.deflate, a.kreg,
+                             a.p32);
+                    auto it = M.graphs.find(key);
+                    hipGraphExec_t ex = nullptr;
+                    if (it != M.graphs.end()) {
+                        ex = it->second;
+                    } else {
+                        if (!M.cap) QPAT_HIP(c, hipStreamCreateWithFlags(&M.cap, hipStreamNonBlocking));
+                        hipGraph_t gr = nullptr;
+                        QPAT_HIP(c, hipStreamBeginCapture(M.cap, hipStreamCaptureModeThreadLocal));
+                        for (int i = 0; i < len; ++i) iteration<B>(M, a, tg, M.cap, i & 1);
+                        QPAT_HIP(c, hipStreamEndCapture(M.cap, &gr));
+                        QPAT_HIP(c, hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+                        QPAT_HIP(c, hipGraphDestroy(gr));
+                        M.graphs[key] = ex;
+                    }
+                    QPAT_HIP(c, hipGraphLaunch(ex, sm));
                 }
-                QPAT_HIP(c, hipGraphLaunch(ex, sm));
             } else {
                 for (int i = 0; i < chunk; ++i) iteration<B>(M, a, tg, sm, i & 1);
             }
