@@ -180,16 +180,18 @@ def pair_algorithmic_bytes(N, E, levels, B, blocks, iters_tan, iters_adj, tiled2
 
 
 # M_delta's multigrid kernels (one right-hand side per system, two systems; profile
-# counters 8-11) and their algorithmic bytes per node: vectors of 2 N doubles
-# (16 B a node), the Kuhn rows' diagonal and 7 upper entries, entry-major (8
-# entries, each read once from HBM: FP64 for the PCG product, FP32 for the
-# V-cycle's finest sweeps), 1/a_ii (FP64) and the region map (int32). The
-# update also writes the V-cycle's first sweep and reads 1/a_ii and the map.
+# counters 8-11) and their algorithmic bytes per node: the PCG's vectors of 2 N
+# doubles (16 B a node), the V-cycle's finest-level vectors x0, its residual and
+# z in FP32 (8 B a node), the Kuhn rows' diagonal and 7 upper entries,
+# entry-major (8 entries, each read once from HBM: FP64 for the PCG product,
+# FP32 for the V-cycle's finest sweeps), 1/a_ii (FP64) and the region map
+# (int32). The update also writes the V-cycle's first sweep and reads 1/a_ii
+# and the map.
 PRIOR_MG_BYTES_PER_NODE = {
-    "prior_mg_dir_spmv": ("k_mgp_dir + k_mgp_spmv<3,1>", 5 * 16 + 2 * 8 * 8 + 2 * 4),
-    "prior_mg_update": ("k_mgp_update_first", 6 * 16 + 16 + 16 + 2 * 4),
-    "prior_mg_resid0": ("k_mg_resid<5,1>", 3 * 16 + 2 * 8 * 4),
-    "prior_mg_smooth0": ("k_mg_smooth<5,1,true>", 3 * 16 + 2 * 8 * 4 + 2 * 8),
+    "prior_mg_dir_spmv": ("k_mgp_dir<1,true> + k_mgp_spmv<3,1>", 8 + 4 * 16 + 2 * 8 * 8 + 2 * 4),
+    "prior_mg_update": ("k_mgp_update_first<float>", 6 * 16 + 8 + 16 + 2 * 4),
+    "prior_mg_resid0": ("k_mg_resid<5,1,float>", 16 + 2 * 8 + 2 * 8 * 4),
+    "prior_mg_smooth0": ("k_mg_smooth<5,1,true,float>", 16 + 2 * 8 + 2 * 8 * 4 + 2 * 8),
 }
 
 

@@ -234,6 +234,28 @@ __device__ __forceinline__ void vstf(float* p, T v) {
         *reinterpret_cast<f2v*>(p) = f2v{static_cast<float>(v.x), static_cast<float>(v.y)};
     }
 }
+// vectors kept in FP64 or in FP32, by the pointer's type
+template <typename T>
+__device__ __forceinline__ T vldx(const double* p) {
+    return vld<T>(p);
+}
+template <typename T>
+__device__ __forceinline__ T vldx(const float* p) {
+    return vldf<T>(p);
+}
+template <typename T>
+__device__ __forceinline__ void vstx(double* p, T v) {
+    vst<T>(p, v);
+}
+template <typename T>
+__device__ __forceinline__ void vstx(float* p, T v) {
+    vstf<T>(p, v);
+}
+// v as a vector of element type VT holds it (FP32: rounded)
+template <typename VT>
+__device__ __forceinline__ double held_as(double v) {
+    return static_cast<double>(static_cast<VT>(v));
+}
 __device__ __forceinline__ double comp(double v, int) { return v; }
 __device__ __forceinline__ double comp(d2v v, int c) { return c ? v.y : v.x; }
 
@@ -299,24 +321,24 @@ __device__ __forceinline__ const double* rows_of(const LvArgs& L, int sys) {
 // (A x)_i for the thread's V right-hand sides; x points at the thread's
 // first right-hand side of node 0 ([N][B] interleaved). Interior rows skip
 // the lattice-edge tests.
-template <int KIND, int B>
-__device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict__ U, const double* __restrict__ x,
+template <int KIND, int B, typename XT = double>
+__device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict__ U, const XT* __restrict__ x,
                                        int32_t ix, int32_t iy, int32_t iz, int32_t i) {
     using T = TB<B>;
     if constexpr (KIND == 0) {
         const int32_t M1 = L.m + 1;
-        T s = U[i * M1] * vld<T>(x + i * B);
+        T s = U[i * M1] * vldx<T>(x + i * B);
         for (int j = 0; j < L.m; ++j) {
             const int4 t = L.tab[j];
             if (ix + t.x >= 0 && ix + t.x < L.nx && iy + t.y >= 0 && iy + t.y < L.ny && iz + t.z < L.nz)
-                s += U[i * M1 + j + 1] * vld<T>(x + (i + t.w) * B);
+                s += U[i * M1 + j + 1] * vldx<T>(x + (i + t.w) * B);
             if (ix - t.x >= 0 && ix - t.x < L.nx && iy - t.y >= 0 && iy - t.y < L.ny && iz - t.z >= 0)
-                s += U[(i - t.w) * M1 + j + 1] * vld<T>(x + (i - t.w) * B);
+                s += U[(i - t.w) * M1 + j + 1] * vldx<T>(x + (i - t.w) * B);
         }
         return s;
     } else if constexpr (KIND == 4) {   // 27-point whole rows, entry-major ([27][N])
         const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
-        T s = U[i] * vld<T>(x + i * B);
+        T s = U[i] * vldx<T>(x + i * B);
 #pragma unroll
         for (int j = 0; j < 13; ++j) {
             const int code = 14 + j;
@@ -326,7 +348,7 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             const bool lo = inner || (ix - dx >= 0 && ix - dx < L.nx && iy - dy >= 0 && iy - dy < L.ny && iz - dz >= 0);
             // loads from clamped indices and selected sums: no branch per
             // neighbour, so all of a row's loads are in flight together
-            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + (lo ? i - lin : i) * B);
+            const T xu = vldx<T>(x + (up ? i + lin : i) * B), xl = vldx<T>(x + (lo ? i - lin : i) * B);
             const double cu = U[(1 + j) * L.N + i], cl = U[(14 + j) * L.N + i];
             s = up ? s + cu * xu : s;
             s = lo ? s + cl * xl : s;
@@ -335,7 +357,7 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
     } else if constexpr (KIND == 6) {   // the kind-4 rows in FP32 (a preconditioner's coarse operator)
         const float* Uw = reinterpret_cast<const float*>(U);
         const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
-        T s = static_cast<double>(Uw[i]) * vld<T>(x + i * B);
+        T s = static_cast<double>(Uw[i]) * vldx<T>(x + i * B);
 #pragma unroll
         for (int j = 0; j < 13; ++j) {
             const int code = 14 + j;
@@ -343,7 +365,7 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             const int32_t lin = dx + L.nx * (dy + L.ny * dz);
             const bool up = inner || (ix + dx >= 0 && ix + dx < L.nx && iy + dy >= 0 && iy + dy < L.ny && iz + dz < L.nz);
             const bool lo = inner || (ix - dx >= 0 && ix - dx < L.nx && iy - dy >= 0 && iy - dy < L.ny && iz - dz >= 0);
-            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + (lo ? i - lin : i) * B);
+            const T xu = vldx<T>(x + (up ? i + lin : i) * B), xl = vldx<T>(x + (lo ? i - lin : i) * B);
             const double cu = static_cast<double>(Uw[(1 + j) * L.N + i]), cl = static_cast<double>(Uw[(14 + j) * L.N + i]);
             s = up ? s + cu * xu : s;
             s = lo ? s + cl * xl : s;
@@ -361,7 +383,7 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
 #pragma unroll
         for (int k = 0; k < 8; ++k) u[k] = static_cast<double>(Uw[k * L.N + i]);
         const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
-        T s = u[0] * vld<T>(x + i * B);
+        T s = u[0] * vldx<T>(x + i * B);
 #pragma unroll
         for (int j = 0; j < 7; ++j) {
             const int dx = kKx[j], dy = kKy[j], dz = kKz[j];
@@ -369,7 +391,7 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             const bool up = inner || (ix + dx < L.nx && iy + dy < L.ny && iz + dz < L.nz);
             const bool lo = inner || (ix - dx >= 0 && iy - dy >= 0 && iz - dz >= 0);
             const int32_t il = lo ? i - lin : i;
-            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + il * B);
+            const T xu = vldx<T>(x + (up ? i + lin : i) * B), xl = vldx<T>(x + il * B);
             const double cl = static_cast<double>(Uw[(1 + j) * L.N + il]);
             s = up ? s + u[1 + j] * xu : s;
             s = lo ? s + cl * xl : s;
@@ -387,7 +409,7 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             u[2 * k + 1] = t.y;
         }
         const bool inner = ix > 0 && ix < L.nx - 1 && iy > 0 && iy < L.ny - 1 && iz > 0 && iz < L.nz - 1;
-        T s = u[0] * vld<T>(x + i * B);
+        T s = u[0] * vldx<T>(x + i * B);
 #pragma unroll
         for (int j = 0; j < MM; ++j) {
             const int code = 14 + j;
@@ -398,7 +420,7 @@ __device__ __forceinline__ TB<B> apply(const LvArgs& L, const double* __restrict
             const bool up = inner || (ix + dx >= 0 && ix + dx < L.nx && iy + dy >= 0 && iy + dy < L.ny && iz + dz < L.nz);
             const bool lo = inner || (ix - dx >= 0 && ix - dx < L.nx && iy - dy >= 0 && iy - dy < L.ny && iz - dz >= 0);
             const int32_t il = lo ? i - lin : i;
-            const T xu = vld<T>(x + (up ? i + lin : i) * B), xl = vld<T>(x + il * B);
+            const T xu = vldx<T>(x + (up ? i + lin : i) * B), xl = vldx<T>(x + il * B);
             const double cl = U[il * M1 + j + 1];
             s = up ? s + u[j + 1] * xu : s;
             s = lo ? s + cl * xl : s;
@@ -806,24 +828,25 @@ struct SmArgs {
 
 // x = w D^{-1} b (the first sweep from zero; on the finest level only at the
 // start of a run, elsewhere the kernel that writes b also writes x)
-template <int B>
-__global__ __launch_bounds__(kMgT) void k_mg_first(SmArgs a, const double* __restrict__ b, double* __restrict__ x) {
+template <int B, typename VT = double>
+__global__ __launch_bounds__(kMgT) void k_mg_first(SmArgs a, const double* __restrict__ b, VT* __restrict__ x) {
     const int k = threadIdx.x % B;
     for (int sys = blockIdx.y; sys < a.nsys; sys += gridDim.y) {
         if (!a.sc[sys * B + k].active) continue;
         const double w = a.w[sys * a.nlev + a.lev];
         const int64_t o = sys * a.L.N * B;
         const double* dinv = a.dinv + sys * a.L.N;
-        QPAT_MG_ELEMS(e, a.L.N * B) x[o + e] = w * dinv[e / B] * b[o + e];
+        QPAT_MG_ELEMS(e, a.L.N * B) x[o + e] = static_cast<VT>(w * dinv[e / B] * b[o + e]);
     }
 }
 
 // y = x + w D^{-1} (b - A x). The systems are swept one after the other by
 // the same blocks. DOTS (the last sweep on the finest level, where b = r and
-// y = z): also the partial sums r.z, sum z and sum r of every right-hand side.
-template <int KIND, int B, bool DOTS>
+// y = z): also the partial sums r.z, sum z and sum r of every right-hand side,
+// of y as stored. x and y in FP64 or FP32 (VT).
+template <int KIND, int B, bool DOTS, typename VT = double>
 __global__ __launch_bounds__(kMgT) void k_mg_smooth(SmArgs a, const double* __restrict__ b,
-                                                    const double* __restrict__ x, double* __restrict__ y,
+                                                    const VT* __restrict__ x, VT* __restrict__ y,
                                                     double* __restrict__ parts) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V;
@@ -836,15 +859,19 @@ __global__ __launch_bounds__(kMgT) void k_mg_smooth(SmArgs a, const double* __re
         const double* dinv = a.dinv + sys * a.L.N;
         const int64_t o = sys * a.L.N * B + v * V;
         const double* bs = b + o;
-        const double* xs = x + o;
-        double* ys = y + o;
+        const VT* xs = x + o;
+        VT* ys = y + o;
         T rz = 0.0, z1 = 0.0, r1 = 0.0;
         if (pair_active<B>(a.sc, sys, v)) {
             walk<Pk<B>::BV>(a.L.nx, a.L.ny, a.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
                 const T bi = vld<T>(bs + i * B);
-                const T ax = apply<KIND, B>(a.L, U, xs, ix, iy, iz, i);
-                const T yi = vld<T>(xs + i * B) + (w * dinv[i]) * (bi - ax);
-                vst<T>(ys + i * B, yi);
+                const T ax = apply<KIND, B, VT>(a.L, U, xs, ix, iy, iz, i);
+                T yi = vldx<T>(xs + i * B) + (w * dinv[i]) * (bi - ax);
+                if constexpr (sizeof(VT) == 4) {
+                    static_assert(B == 1, "FP32 sweep output: one right-hand side per thread");
+                    yi = held_as<float>(yi);
+                }
+                vstx<T>(ys + i * B, yi);
                 if constexpr (DOTS) {
                     rz += bi * yi;
                     z1 += yi;
@@ -860,10 +887,10 @@ __global__ __launch_bounds__(kMgT) void k_mg_smooth(SmArgs a, const double* __re
     }
 }
 
-// r = b - A x
-template <int KIND, int B>
+// r = b - A x (x and r in FP64 or FP32: VT)
+template <int KIND, int B, typename VT = double>
 __global__ __launch_bounds__(kMgT) void k_mg_resid(SmArgs a, const double* __restrict__ b,
-                                                   const double* __restrict__ x, double* __restrict__ r) {
+                                                   const VT* __restrict__ x, VT* __restrict__ r) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V;
     const int v = threadIdx.x % Pk<B>::BV;
@@ -873,10 +900,10 @@ __global__ __launch_bounds__(kMgT) void k_mg_resid(SmArgs a, const double* __res
         const double* U = rows_of<KIND>(a.L, sys);
         const int64_t o = sys * a.L.N * B + v * V;
         const double* bs = b + o;
-        const double* xs = x + o;
-        double* rs = r + o;
+        const VT* xs = x + o;
+        VT* rs = r + o;
         walk<Pk<B>::BV>(a.L.nx, a.L.ny, a.L.nz, [&](int32_t ix, int32_t iy, int32_t iz, int32_t i, int32_t) {
-            vst<T>(rs + i * B, vld<T>(bs + i * B) - apply<KIND, B>(a.L, U, xs, ix, iy, iz, i));
+            vstx<T>(rs + i * B, vld<T>(bs + i * B) - apply<KIND, B, VT>(a.L, U, xs, ix, iy, iz, i));
         });
     }
 }
@@ -895,13 +922,14 @@ struct Span {
     }
 };
 
-// bc = P^T r on the coarse level c, and the first sweep there, xc = w D^{-1} bc.
+// bc = P^T r on the coarse level c, and the first sweep there, xc = w D^{-1} bc
+// (r in FP64 or FP32: RT).
 // Fine nodes 2 I + {-1, 0, 1} per axis, weights 1/2, 1, 1/2 (trilinear) or
 // from Wc ([nsys][WPack size], operator-dependent, packed); the ones past the
 // lattice get weight 0 (their loads are clamped inside it).
-template <int B, bool OPW>
+template <int B, bool OPW, typename RT = double>
 __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int32_t ny, int32_t nz,
-                                                      const double* __restrict__ r, double* __restrict__ bc,
+                                                      const RT* __restrict__ r, double* __restrict__ bc,
                                                       double* __restrict__ xc, const float* __restrict__ Wc) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V;
@@ -912,7 +940,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
         if (!pair_active<B>(c.sc, sys, v)) continue;
         const double w = c.w[sys * c.nlev + c.lev];
         const double* dinv = c.dinv + sys * Nc;
-        const double* rs = r + sys * Nf * B + v * V;
+        const RT* rs = r + sys * Nf * B + v * V;
         const float* Ws = OPW ? Wc + sys * pk.size() : nullptr;
         const int64_t oc = sys * Nc * B + v * V;
         walk<Pk<B>::BV>(c.L.nx, c.L.ny, c.L.nz, [&](int32_t Ix, int32_t Iy, int32_t Iz, int32_t I, int32_t) {
@@ -942,7 +970,7 @@ __global__ __launch_bounds__(kMgT) void k_mg_restrict(SmArgs c, int32_t nx, int3
 #pragma unroll
                     for (int dx = 0; dx < 3; ++dx) {
                         const int k = (dz * 3 + dy) * 3 + dx;
-                        fv[k] = vld<T>(rs + (row + fx[dx]) * B);
+                        fv[k] = vldx<T>(rs + (row + fx[dx]) * B);
                         // I is corner (d == 0 per axis) of fine node 2 I + d - 1, which is
                         // odd along each such axis: the packed entry exists where the
                         // node is inside the lattice (elsewhere the weight is 0 and the
@@ -1139,8 +1167,8 @@ struct LaneScal {
     }
 };
 
-// pn = z - c + beta po (right-hand sides that stopped keep pn)
-template <int B>
+// pn = z - c + beta po (right-hand sides that stopped keep pn); ZF: z in FP32
+template <int B, bool ZF = false>
 __global__ __launch_bounds__(kMgT) void k_mgp_dir(PcgMg a) {
     using T = TB<B>;
     constexpr int V = Pk<B>::V, BV = Pk<B>::BV;
@@ -1151,7 +1179,7 @@ __global__ __launch_bounds__(kMgT) void k_mgp_dir(PcgMg a) {
         const int64_t o = sys * a.L.N * B + v * V;
         QPAT_MG_ELEMS(e, a.L.N * BV) {
             const int64_t at = o + (e / BV) * B;
-            T zc = vld<T>(a.z + at);
+            T zc = ZF ? vldf<T>(reinterpret_cast<const float*>(a.z) + at) : vld<T>(a.z + at);
             if constexpr (B == 1) {   // the region coarse-space part of z, y_reg(i) - ybar
                 if (a.kreg > 0) {
                     const int32_t rg = a.reg[sys * a.L.N + e];
@@ -1356,13 +1384,14 @@ __global__ __launch_bounds__(kMgT) void k_reg_rsum(PcgMg a, double* __restrict__
 // One right-hand side per system: the PCG update fused with the two passes
 // that read its new r next. x += alpha p, r -= alpha q (a system that
 // stopped keeps both) and the partial r.r; the V-cycle's first sweep on the
-// finest level, x0 = w D^{-1} r; and, with the region coarse space, the
-// partial sums of Z^T r. Four nodes' loads in flight per trip (buffer loads
+// finest level, x0 = w D^{-1} r (FP64 or FP32: XT); and, with the region
+// coarse space, the partial sums of Z^T r. Four nodes' loads in flight per trip (buffer loads
 // with 32-bit offsets: N 8 < 2^31; past the end they read 0 and the stores
 // drop); few, full blocks (kMgGrid), so that each block's reduction of its
 // kRegMax region sums is spread over many nodes. Slots of blocks past the
 // grid read as zero.
-__global__ __launch_bounds__(kMgT, 4) void k_mgp_update_first(PcgMg a, SmArgs s, double* __restrict__ x0,
+template <typename XT>
+__global__ __launch_bounds__(kMgT, 4) void k_mgp_update_first(PcgMg a, SmArgs s, XT* __restrict__ x0,
                                                            double* __restrict__ rparts) {
     __shared__ double sm[(kMgT / 64) * kRegMax];
     const int64_t n = a.L.N, stride = (int64_t)gridDim.x * kMgT;
@@ -1377,7 +1406,8 @@ __global__ __launch_bounds__(kMgT, 4) void k_mgp_update_first(PcgMg a, SmArgs s,
             const int64_t o = sys * n;
             const uint32_t nb8 = static_cast<uint32_t>(n) * 8u;
             const auto bp = rsrc(a.pn + o, nb8), bq = rsrc(a.q + o, nb8), bd = rsrc(s.dinv + o, nb8);
-            const auto bx = rsrc(a.x + o, nb8), br = rsrc(a.r + o, nb8), bs = rsrc(x0 + o, nb8);
+            const auto bx = rsrc(a.x + o, nb8), br = rsrc(a.r + o, nb8);
+            const auto bs = rsrc(x0 + o, static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(XT)));
             const auto bg = rsrc(a.reg + (regions ? o : 0), regions ? nb8 / 2 : 0u);
             for (int64_t i0 = blockIdx.x * (int64_t)kMgT + threadIdx.x; i0 < n; i0 += 4 * stride) {
                 double pv[4], qv[4], rv[4], xv[4], dv[4];
@@ -1398,7 +1428,7 @@ __global__ __launch_bounds__(kMgT, 4) void k_mgp_update_first(PcgMg a, SmArgs s,
                     const double rn = rv[u] - alpha * qv[u];
                     bstore<double>(bx, off[u], xv[u] + alpha * pv[u]);
                     bstore<double>(br, off[u], rn);
-                    bstore<double>(bs, off[u], w * dv[u] * rn);
+                    bstore<XT>(bs, off[u] / (8u / sizeof(XT)), static_cast<XT>(w * dv[u] * rn));
                     rr += rn * rn;
                     if (regions)
 #pragma unroll
@@ -3537,6 +3567,19 @@ inline bool z32_path(const MgState& M, const TileGeo& tg) {
     return B == 16 && fused_update(tg) && tg.ps_on && !M.opdep;
 }
 
+// One right-hand side per system (M_delta), walk kernels with the FP32 Kuhn
+// rows and one sweep each way: the finest level's V-cycle vectors (x0, its
+// residual, z) are FP32, in the first half of their FP64 arrays. Every kernel
+// that touches them has that form: the PCG update's first sweep (or the first
+// sweep from zero), the residual, the restriction, the prolongation into
+// level 0, the last sweep (whose dot products use z as stored) and the
+// direction. The PCG's own vectors (x, r, p, q) stay FP64.
+template <int B>
+inline bool f32v0_path(const MgState& M, const TileGeo& tg) {
+    return B == 1 && M.opdep && !tg.on && kMgNu == 1 && M.lv.size() > 1 && M.lv[0].vkind == 5 &&
+           M.lv[0].N * 8 < (int64_t(1) << 31);
+}
+
 // Level 1 keeps the V-cycle's vectors (x, its ping-pong partner, r, b) in FP32,
 // in the first half of their FP64 arrays, where every kernel that touches them
 // has that form: 16 right-hand sides, the tiled restrictions into and out of
@@ -3575,6 +3618,7 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
     const int nl = static_cast<int>(M.lv.size());
     const bool fused0 = tg.on && kMgNu == 1;
     const bool v1 = v32_path<B>(M, tg);   // level 1's vectors in FP32
+    const bool f0 = f32v0_path<B>(M, tg);  // level 0's vectors in FP32 (one right-hand side)
     const double* r0 = b0 ? b0 : M.lv[0].b;   // level 0's right-hand side (the PCG residual)
     std::vector<double*> xl(nl), tl(nl);
     for (int l = 0; l < nl; ++l) {
@@ -3588,7 +3632,10 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         const SmArgs a = sm(l);
         const dim3 g = sgrid<B>(L.N, M.nsys);
         const double* bl = l == 0 ? r0 : L.b;
-        if (l == 0 && !fused0 && !first_done)
+        if (l == 0 && !fused0 && !first_done && f0)
+            hipLaunchKernelGGL((k_mg_first<B, float>), sys_rows(vgrid(L.N * B), B, M.nsys), dim3(kMgT), 0, st, a, r0,
+                               reinterpret_cast<float*>(xl[0]));
+        else if (l == 0 && !fused0 && !first_done)
             hipLaunchKernelGGL(k_mg_first<B>, sys_rows(vgrid(L.N * B), B, M.nsys), dim3(kMgT), 0, st, a, r0, xl[0]);
         for (int k = 1; k < kMgNu; ++k) {
             launch_smooth<B, false>(vkind(L), g, st, a, bl, xl[l], tl[l], nullptr);
@@ -3603,11 +3650,18 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
             launch_tile<kTResid, B>(M, tg, st, xl[0], nullptr, r0, L.r, nullptr);
         else if (B == 16 && tiled27(tg, l))
             launch_tile27<kT27Resid>(M, tg, l, st, xl[l], L.b, L.r, v1 && l == 1);
-        else
+        else if (l == 0 && f0) {
+            if constexpr (B == 1)
+                hipLaunchKernelGGL((k_mg_resid<5, 1, float>), g, dim3(kMgT), 0, st, a, bl,
+                                   reinterpret_cast<const float*>(xl[0]), reinterpret_cast<float*>(L.r));
+        } else
             QPAT_MG_KIND(vkind(L), B, k_mg_resid, g, dim3(kMgT), 0, st, a, bl, xl[l], L.r);
         if (l == 0 && ev) (void)hipEventRecord(ev[1], st);
         if (tg.on && l < kMgMaxLevels && tg.rst[l].on && !M.opdep)
             launch_restrict<B>(M, tg, l, st, xl[l + 1], v1);
+        else if (M.opdep && l == 0 && f0)
+            hipLaunchKernelGGL((k_mg_restrict<B, true, float>), sgrid<B>(C.N, M.nsys), dim3(kMgT), 0, st, sm(l + 1),
+                               L.nx, L.ny, L.nz, reinterpret_cast<const float*>(L.r), C.b, xl[l + 1], L.Wc);
         else if (M.opdep)
             hipLaunchKernelGGL((k_mg_restrict<B, true>), sgrid<B>(C.N, M.nsys), dim3(kMgT), 0, st, sm(l + 1), L.nx,
                                L.ny, L.nz, L.r, C.b, xl[l + 1], L.Wc);
@@ -3638,6 +3692,9 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
         else if (l == 0 && fused0)
             hipLaunchKernelGGL((k_mg_prolong<B, true, false>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz, xl[1], r0,
                                xl[0], static_cast<const float*>(nullptr));
+        else if (M.opdep && l == 0 && f0)   // into level 0's FP32 x0
+            hipLaunchKernelGGL((k_mg_prolong<B, false, true, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz,
+                               xl[l + 1], bl, xl[l], L.Wc);
         else if (M.opdep)
             hipLaunchKernelGGL((k_mg_prolong<B, false, true>), g, dim3(kMgT), 0, st, a, C.nx, C.ny, C.nz,
                                xl[l + 1], bl, xl[l], L.Wc);
@@ -3652,7 +3709,12 @@ void vcycle(const MgState& M, hipStream_t st, const TileGeo& tg, hipEvent_t* ev 
             if (last && ev) (void)hipEventRecord(ev[2], st);
             if (last && tg.on)
                 launch_tile<kTSmoothDots, B>(M, tg, st, xl[0], nullptr, r0, tl[0], nullptr);
-            else if (last)
+            else if (last && f0) {
+                if constexpr (B == 1)
+                    hipLaunchKernelGGL((k_mg_smooth<5, 1, true, float>), g, dim3(kMgT), 0, st, a, bl,
+                                       reinterpret_cast<const float*>(xl[0]), reinterpret_cast<float*>(tl[0]),
+                                       M.parts);
+            } else if (last)
                 launch_smooth<B, true>(vkind(L), g, st, a, bl, xl[l], tl[l], M.parts);
             else if (B == 16 && tiled27(tg, l))
                 launch_tile27<kT27Smooth>(M, tg, l, st, xl[l], L.b, tl[l], v1 && l == 1);
@@ -3733,7 +3795,10 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
     } else if (tg.on) {
         launch_tile<kTDirSpmv, B>(M, tg, st, a.z, a.po, nullptr, a.q, a.pn, nullptr, nullptr, ring);
     } else {
-        hipLaunchKernelGGL(k_mgp_dir<B>, g, dim3(kMgT), 0, st, a);
+        if (f32v0_path<B>(M, tg))   // z in FP32
+            hipLaunchKernelGGL((k_mgp_dir<B, true>), g, dim3(kMgT), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_mgp_dir<B>, g, dim3(kMgT), 0, st, a);
         QPAT_MG_KIND(a.L.kind, B, k_mgp_spmv, g, dim3(kMgT), 0, st, a);
     }
     if (ev) (void)hipEventRecord(ev[1], st);
@@ -3748,10 +3813,12 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
         else
             launch_tile<kTUpdResid, B>(M, tg, st, r_old, a.q, nullptr, M.lv[0].r, r_new, xu, a.pn);
         a.r = r_new;
+    } else if (upd1 && f32v0_path<B>(M, tg)) {   // one right-hand side: update, first sweep (FP32), region sums
+        hipLaunchKernelGGL(k_mgp_update_first<float>, sys_rows(vgrid(a.L.N, kMgGrid), B, a.nsys), dim3(kMgT), 0, st,
+                           a, level_args(M, 0), reinterpret_cast<float*>(M.lv[0].x), M.rparts);
     } else if (upd1) {   // one right-hand side: update, first sweep and region sums in one pass over r
-        hipLaunchKernelGGL(k_mgp_update_first, sys_rows(vgrid(a.L.N, kMgGrid), B, a.nsys), dim3(kMgT), 0, st, a,
-                           level_args(M, 0),
-                           M.lv[0].x, M.rparts);
+        hipLaunchKernelGGL(k_mgp_update_first<double>, sys_rows(vgrid(a.L.N, kMgGrid), B, a.nsys), dim3(kMgT), 0, st,
+                           a, level_args(M, 0), M.lv[0].x, M.rparts);
     } else {
         hipLaunchKernelGGL(k_mgp_update<B>, g, dim3(kMgT), 0, st, a);
     }
