@@ -170,10 +170,12 @@ def test_prior_multigrid_matches_jacobi(deflate):
     assert infos[0]["iters_max"] * 4 < infos[1]["iters_max"], infos
 
 
-@pytest.mark.parametrize("dims", [(13, 7, 5), (30, 3, 9)])
+@pytest.mark.parametrize("dims", [(13, 7, 5), (30, 3, 9), (1, 40, 33), (26, 2, 37)])
 def test_prior_multigrid_on_boxes(dims):
-    """Ragged boxes (odd and even sides, a side of 4 nodes) against the oracle's
-    M_delta^{-1} (its delta-eigenvector taken exactly), element by element."""
+    """Ragged boxes (odd and even sides, sides of 2, 3 and 4 nodes, where the
+    packed transfer weights of a corner have one sub-lattice row or none)
+    against the oracle's M_delta^{-1} (its delta-eigenvector taken exactly),
+    element by element."""
     from oracle.prior import Prior
     coords, tets, bfaces, kappa, mu, src = box_problem(*dims, 1, seed=7 + sum(dims))
     rng = np.random.default_rng(sum(dims))
