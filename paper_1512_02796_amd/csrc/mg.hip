@@ -1822,7 +1822,10 @@ __global__ __launch_bounds__(kMgT) void k_mgp_ring_flush(int64_t n, int B, doubl
 #pragma unroll
         for (int t = 0; t < kRing; ++t) {
             const int sl = (f + t) % kRing;
-            pv[t] = f + t < s ? *reinterpret_cast<const PV*>(ring + sl * stride + e0 * (int64_t)sizeof(PT)) : PV{};
+            // each direction element is read once here: non-temporal
+            pv[t] = f + t < s ? __builtin_nontemporal_load(reinterpret_cast<const PV*>(ring + sl * stride +
+                                                                                        e0 * (int64_t)sizeof(PT)))
+                              : PV{};
         }
         double xv[V];
 #pragma unroll
