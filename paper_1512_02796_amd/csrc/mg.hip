@@ -1125,8 +1125,10 @@ struct PcgMg {
     double rtol2;
     int32_t maxit, deflate, nsys;
     int32_t nb;           // blocks of the kernels that write partials
-    // region coarse space (one right-hand side per system), kreg = 0: off
-    int32_t kreg;
+    // region coarse space (one right-hand side per system), kreg = 0: off;
+    // nbr: blocks of the kernels that write the region partials (the later
+    // slots hold zeros)
+    int32_t kreg, nbr;
     int32_t p32;          // 1: the direction in FP32 on the tiled 16-right-hand-side path (mixed precision)
     int32_t ring;         // kRing: directions and alphas kept in the ring (x formed later), 0: x updated each iteration
     int32_t* slot;        // the ring's iteration counter
@@ -1475,7 +1477,7 @@ __global__ __launch_bounds__(kMgT) void k_reg_solve(PcgMg a, const double* __res
         double s[kRegMax];
 #pragma unroll
         for (int j = 0; j < kRegMax; ++j) s[j] = 0.0;
-        for (int b = t; b < a.nb; b += kMgT)
+        for (int b = t; b < a.nbr; b += kMgT)
 #pragma unroll
             for (int j = 0; j < kRegMax; ++j) s[j] += rparts[(sys * kRegMax + j) * kMgBlocks + b];
         const int lane = t & 63, wave = t >> 6;
@@ -3764,6 +3766,7 @@ PcgMg pcg_args(qpat_ctx* c, Op op) {
     a.deflate = op == Op::Prior ? c->opts.prior_deflate : 0;
     a.nsys = M.nsys;
     a.nb = static_cast<int32_t>(sgrid<B>(c->N).x);
+    a.nbr = static_cast<int32_t>(vgrid(c->N, kMgGrid).x);   // k_reg_rsum, k_mgp_update_first
     a.kreg = B == 1 ? M.kreg : 0;
     a.p32 = op == Op::K && c->opts.precision == 1 ? 1 : 0;
     a.reg = M.reg;
