@@ -118,7 +118,8 @@ typedef struct {
     int32_t n_solves;       /* linear systems solved by the call                               */
     int32_t iters_max;      /* largest PCG iteration count among them                          */
     int64_t iters_sum;      /* total PCG iterations                                            */
-    int32_t updates;        /* FP64 true-residual recomputations                              */
+    int32_t updates;        /* FP64 true-residual recomputations (multigrid PCG: restarts     */
+                            /* after a failed true-residual check, summed over the systems) */
     double  relres_max;     /* largest final true relative residual                           */
     int32_t rhs_cap;        /* in: capacity of rhs_iters / rhs_relres                          */
     int32_t* rhs_iters;     /* in: host array [rhs_cap] or NULL                                */

@@ -1904,7 +1904,7 @@ struct TileArgs {
 // kTResidFirst: the V-cycle's first sweep and residual, x = w D^{-1} in
 //   (in = r) staged, out = b - A x with b = r.
 // kTResid: out = b - A in. kTTrue: the same for every right-hand side,
-//   partial out.out.
+//   partial out.out (out may be null: the partial only).
 // kTSmoothDots: out = in + w D^{-1} (b - A in), partial b.out, sum out,
 //   sum b (the last finest-level sweep of the V-cycle: b = r, out = z).
 // kTApply: out = scale A in for every right-hand side (any Kuhn stencil
@@ -2101,8 +2101,9 @@ __global__ __launch_bounds__(kTT, 4) void k_mg_tile(TileArgs g) {
             // turn every access into a loop over the distinct values); the
             // stores of stopped right-hand sides are skipped by the branch
             // RES32: float [N][B] planes
+            // kTTrue with out = null: only the partial out.out (every store dropped)
             const auto bo = RES32 ? rsrc(reinterpret_cast<const float*>(g.out) + (int64_t)z * nxy * B, pv / 2)
-                                  : plane(g.out, z, nxy * B, pv);
+                                  : plane(g.out, z, nxy * B, g.out ? pv : 0u);
             if (act) {
                 const auto bo2 = (MODE == kTDirSpmv && P32)
                                      ? plane(reinterpret_cast<const float*>(g.out2), z, nxy * B, pv / 2)
@@ -3849,11 +3850,13 @@ void iteration(const MgState& M, PcgMg a, const TileGeo& tg, hipStream_t st, int
     hipLaunchKernelGGL(k_mgp_scalars, lanes, dim3(kMgT), 0, st, a, 2);
 }
 
-// true residual r = b - A x of every lane, partial r.r
+// true residual r = b - A x of every lane, partial r.r (write_r false, tiled path:
+// the partial only)
 template <int B>
-void true_residual(const MgState& M, const PcgMg& a, const TileGeo& tg, const double* b, hipStream_t st) {
+void true_residual(const MgState& M, const PcgMg& a, const TileGeo& tg, const double* b, hipStream_t st,
+                   bool write_r = true) {
     if (tg.on)
-        launch_tile<kTTrue, B>(M, tg, st, a.x, nullptr, b, a.r, nullptr);
+        launch_tile<kTTrue, B>(M, tg, st, a.x, nullptr, b, write_r ? a.r : nullptr, nullptr);
     else
         QPAT_MG_KIND(a.L.kind, B, k_mgp_true, sgrid<B>(a.L.N, a.nsys), dim3(kMgT), 0, st, a, b);
 }
@@ -3927,9 +3930,15 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
             if (M.sc_host[i].active) return true;
         return false;
     };
+    std::vector<int> reopened(S, 0);   // per lane: restarts after a failed true-residual check
     for (int restart = 0; restart < 4; ++restart) {
         QPAT_TRY(fetch());
         if (!any_active()) break;
+        if (restart > 0)
+            for (int i = 0; i < S; ++i) reopened[i] += M.sc_host[i].active ? 1 : 0;
+        // the tiled check below stores no r (its lanes almost always stop there):
+        // a lane it reopened restarts from the true residual formed here
+        if (restart > 0 && tg.on) true_residual<B>(M, a, tg, c->b64, sm);
         // first direction of a run: z = V(r) (+ Z y), p = z - c
         region_solve<B>(M, a, sm);
         vcycle<B>(M, sm, tg, nullptr, nullptr, false, a.p32 != 0 && z32_path<B>(M, tg));
@@ -4047,7 +4056,7 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
         }
         // confirm on the true residual; a failed check restarts from the true residual
         QPAT_TRY(ring_flush());
-        true_residual<B>(M, a, tg, c->b64, sm);
+        true_residual<B>(M, a, tg, c->b64, sm, !tg.on);
         hipLaunchKernelGGL(k_mgp_true_fin, lanes, dim3(kMgT), 0, sm, a, restart < 3 ? 1 : 0);
         QPAT_HIP(c, hipGetLastError());
     }
@@ -4058,7 +4067,7 @@ qpat_status solve_B(qpat_ctx* c, Op op, SolveStats* st, bool has_x0) {
         if (op == Op::Prior)   // the output kernel of the prior solve adds mean(b)/delta
             QPAT_HIP(c, hipMemcpyAsync(&c->scal[i].mean, &M.sc[i].mean, sizeof(double), hipMemcpyDeviceToDevice, sm));
         const double rel = s.bnorm2 > 0 ? std::sqrt(s.rr / s.bnorm2) : 0.0;
-        st->add(s.iters, rel, 0, s.done != 0);
+        st->add(s.iters, rel, reopened[i], s.done != 0);
     }
     return QPAT_OK;
 }

@@ -68,6 +68,20 @@ def test_direction_ring_past_its_length():
     assert torch.equal(phi, phi2)
 
 
+def test_restart_from_the_true_residual():
+    """At pcg_rtol 5e-16, next to the attainable accuracy, the recursion's
+    residual passes the tolerance before the true residual does: the FP64
+    true-residual check reopens lanes, which restart from the true residual
+    (on the tiled path the check stores no r; it is formed again for the
+    restart). The solve still reaches the tolerance and matches the oracle."""
+    G = GpuProblem("T24", opts(max_rhs_block=8, pcg_rtol=5e-16))
+    phi, h, info = G.forward()
+    assert info["updates"] > 0, info
+    assert info["relres_max"] <= 5e-16, info
+    g, lin = oracle_of(G.P)
+    assert_close(host(phi), lin.phi, 1e-10, "phi T24, rtol 5e-16")
+
+
 def test_zero_direction_on_the_tiled_path():
     """J 0 = 0 exactly on the tiled K path (T24, blocks of 8): every tangent
     right-hand side is zero, so each lane stops before iterating and x is
