@@ -73,8 +73,11 @@ def test_restart_from_the_true_residual():
     residual passes the tolerance before the true residual does: the FP64
     true-residual check reopens lanes, which restart from the true residual
     (on the tiled path the check stores no r; it is formed again for the
-    restart). The solve still reaches the tolerance and matches the oracle."""
-    G = GpuProblem("T24", opts(max_rhs_block=8, pcg_rtol=5e-16))
+    restart). The solve still reaches the tolerance and matches the oracle.
+    The tile schedule is the cost model's (no timing), so the rounding that
+    decides the restarts does not depend on the box (every solve restarts once
+    from 3e-16 to 6e-16)."""
+    G = GpuProblem("T24", opts(max_rhs_block=8, pcg_rtol=5e-16, autotune=0))
     phi, h, info = G.forward()
     assert info["updates"] > 0, info
     assert info["relres_max"] <= 5e-16, info
